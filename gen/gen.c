@@ -1,0 +1,371 @@
+/*
+ * Seeded synthetic graph inputs.
+ *
+ * This module only makes inputs: edge samples, the CSR built from them (rows sorted,
+ * self-loops and duplicate edges removed), the symmetrized CSR, per-edge weights and
+ * source vertices.  It holds none of the traversal or cost-model arithmetic; both the
+ * CPU oracle and the GPU library consume what it writes.
+ *
+ *  - R-MAT (Chakrabarti, Zhan, Faloutsos, SDM 2004): each sample descends `scale`
+ *    levels of the adjacency matrix, choosing quadrant (0,0),(0,1),(1,0),(1,1) with
+ *    probabilities a, b, c, 1-a-b-c.  No per-level noise and no label permutation, so
+ *    vertex 0 is the largest hub.
+ *  - Erdos-Renyi G(n, m): m uniform directed (u, v) pairs.
+ *
+ * Randomness is SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014) used as a counter-based generator: draw i of the stream
+ * keyed by s is mix(s + (i + 1) * GOLDEN).  Any sample can therefore be regenerated
+ * from its index alone, which lets the CSR be built in two passes (count, then
+ * scatter) without ever storing the edge list.
+ *
+ * Weights are w(u, v) = 1 + (mix(wkey ^ (u << 32 | v)) mod maxw): a function of the
+ * edge, not of its position, so any relabelling or reordering keeps them.
+ */
+#define _GNU_SOURCE
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+#define GOLDEN 0x9E3779B97F4A7C15ULL
+
+static inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+/* draw i (0-based) of the SplitMix64 stream keyed by s */
+static inline uint64_t draw(uint64_t s, uint64_t i) { return mix64(s + (i + 1) * GOLDEN); }
+
+typedef struct gen_graph {
+    uint64_t n, m;
+    uint64_t *off; /* n + 1 */
+    uint32_t *col; /* m */
+} gen_graph;
+
+/* ------------------------------------------------------------------ threads */
+typedef void (*range_fn)(void *ctx, uint64_t lo, uint64_t hi, int tid);
+typedef struct {
+    range_fn fn;
+    void *ctx;
+    uint64_t total, chunk;
+    uint64_t next; /* atomic */
+    int tid;
+} par_job;
+
+static void *par_worker(void *p) {
+    par_job *j = (par_job *)p;
+    int tid = __atomic_fetch_add(&j->tid, 1, __ATOMIC_RELAXED);
+    for (;;) {
+        uint64_t lo = __atomic_fetch_add(&j->next, j->chunk, __ATOMIC_RELAXED);
+        if (lo >= j->total) break;
+        uint64_t hi = lo + j->chunk < j->total ? lo + j->chunk : j->total;
+        j->fn(j->ctx, lo, hi, tid);
+    }
+    return NULL;
+}
+
+static int g_threads = 0;
+static int nthreads_default(void) {
+    if (g_threads > 0) return g_threads;
+    long c = sysconf(_SC_NPROCESSORS_ONLN);
+    const char *e = getenv("OMP_NUM_THREADS");
+    if (e && atoi(e) > 0 && atoi(e) < c) c = atoi(e);
+    if (c < 1) c = 1;
+    if (c > 64) c = 64;
+    return (int)c;
+}
+void gen_set_threads(int t) { g_threads = t; }
+
+static void parallel_for(uint64_t total, uint64_t chunk, range_fn fn, void *ctx) {
+    if (total == 0) return;
+    par_job j = {fn, ctx, total, chunk ? chunk : 1, 0, 0};
+    int nt = nthreads_default();
+    if ((uint64_t)nt > (total + j.chunk - 1) / j.chunk) nt = (int)((total + j.chunk - 1) / j.chunk);
+    if (nt <= 1) {
+        par_worker(&j);
+        return;
+    }
+    pthread_t th[64];
+    for (int i = 0; i < nt; i++) pthread_create(&th[i], NULL, par_worker, &j);
+    for (int i = 0; i < nt; i++) pthread_join(th[i], NULL);
+}
+
+/* ------------------------------------------------------------ edge sources */
+typedef struct {
+    int kind; /* 0 rmat, 1 er, 2 explicit pairs, 3 symmetrize csr */
+    uint64_t n, nsamples, seed;
+    int scale;
+    uint32_t ta, tab, tabc; /* R-MAT quadrant thresholds on a 32-bit draw */
+    const uint32_t *ps, *pd; /* explicit pairs */
+    const gen_graph *g;      /* symmetrize */
+} edge_src;
+
+static inline void rmat_sample(const edge_src *s, uint64_t k, uint32_t *pu, uint32_t *pv) {
+    uint32_t u = 0, v = 0;
+    uint64_t r = 0;
+    for (int l = 0; l < s->scale; l++) {
+        if ((l & 1) == 0) r = draw(s->seed, k * 16 + (uint64_t)(l >> 1));
+        uint32_t x = (l & 1) ? (uint32_t)(r >> 32) : (uint32_t)r;
+        uint32_t bit = 1u << (s->scale - 1 - l);
+        if (x < s->ta) {
+        } else if (x < s->tab) {
+            v |= bit;
+        } else if (x < s->tabc) {
+            u |= bit;
+        } else {
+            u |= bit;
+            v |= bit;
+        }
+    }
+    *pu = u;
+    *pv = v;
+}
+static inline void er_sample(const edge_src *s, uint64_t k, uint32_t *pu, uint32_t *pv) {
+    uint64_t r0 = draw(s->seed, 2 * k), r1 = draw(s->seed, 2 * k + 1);
+    *pu = (uint32_t)(((unsigned __int128)r0 * s->n) >> 64);
+    *pv = (uint32_t)(((unsigned __int128)r1 * s->n) >> 64);
+}
+
+typedef struct {
+    const edge_src *s;
+    uint32_t *cnt;    /* n: pass 1 degree counts */
+    uint64_t *cur;    /* n: pass 2 write cursors */
+    uint32_t *rows;   /* scatter target */
+} build_ctx;
+
+static inline void emit(build_ctx *c, int pass, uint32_t u, uint32_t v) {
+    if (pass == 0)
+        __atomic_fetch_add(&c->cnt[u], 1u, __ATOMIC_RELAXED);
+    else {
+        uint64_t p = __atomic_fetch_add(&c->cur[u], 1ull, __ATOMIC_RELAXED);
+        c->rows[p] = v;
+    }
+}
+
+static void sample_range(build_ctx *c, uint64_t lo, uint64_t hi, int pass) {
+    const edge_src *s = c->s;
+    for (uint64_t k = lo; k < hi; k++) {
+        uint32_t u, v;
+        switch (s->kind) {
+        case 0: rmat_sample(s, k, &u, &v); emit(c, pass, u, v); break;
+        case 1: er_sample(s, k, &u, &v); emit(c, pass, u, v); break;
+        case 2: emit(c, pass, s->ps[k], s->pd[k]); break;
+        default: {
+            /* k indexes source vertices of the CSR being symmetrized */
+            const gen_graph *g = s->g;
+            for (uint64_t e = g->off[k]; e < g->off[k + 1]; e++) {
+                emit(c, pass, (uint32_t)k, g->col[e]);
+                emit(c, pass, g->col[e], (uint32_t)k);
+            }
+        }
+        }
+    }
+}
+static void pass0_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) { (void)tid; sample_range((build_ctx *)ctx, lo, hi, 0); }
+static void pass1_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) { (void)tid; sample_range((build_ctx *)ctx, lo, hi, 1); }
+
+static int cmp_u32(const void *a, const void *b) {
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return (x > y) - (x < y);
+}
+
+typedef struct {
+    uint64_t *rowbeg; /* n + 1 */
+    uint32_t *rows;
+    uint32_t *newdeg;
+} dedupe_ctx;
+
+/* sort each row, drop duplicates and self-loops; new length into newdeg */
+static void dedupe_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) {
+    (void)tid;
+    dedupe_ctx *c = (dedupe_ctx *)ctx;
+    for (uint64_t u = lo; u < hi; u++) {
+        uint32_t *r = c->rows + c->rowbeg[u];
+        uint64_t len = c->rowbeg[u + 1] - c->rowbeg[u];
+        if (len > 24) {
+            qsort(r, len, sizeof(uint32_t), cmp_u32);
+        } else {
+            for (uint64_t i = 1; i < len; i++) {
+                uint32_t x = r[i];
+                uint64_t j = i;
+                while (j > 0 && r[j - 1] > x) { r[j] = r[j - 1]; j--; }
+                r[j] = x;
+            }
+        }
+        uint64_t w = 0;
+        for (uint64_t i = 0; i < len; i++) {
+            if (r[i] == (uint32_t)u) continue;
+            if (w > 0 && r[w - 1] == r[i]) continue;
+            r[w++] = r[i];
+        }
+        c->newdeg[u] = (uint32_t)w;
+    }
+}
+
+typedef struct {
+    uint64_t *rowbeg, *off;
+    uint32_t *rows, *col;
+} compact_ctx;
+static void compact_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) {
+    (void)tid;
+    compact_ctx *c = (compact_ctx *)ctx;
+    for (uint64_t u = lo; u < hi; u++)
+        memcpy(c->col + c->off[u], c->rows + c->rowbeg[u], (c->off[u + 1] - c->off[u]) * sizeof(uint32_t));
+}
+
+static gen_graph *build_csr(const edge_src *s, uint64_t n, uint64_t nitems, uint64_t chunk) {
+    gen_graph *g = (gen_graph *)calloc(1, sizeof(gen_graph));
+    if (!g) return NULL;
+    g->n = n;
+    uint32_t *cnt = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+    uint64_t *rowbeg = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
+    if (!cnt || !rowbeg) goto fail_early;
+    build_ctx bc = {s, cnt, NULL, NULL};
+    parallel_for(nitems, chunk, pass0_fn, &bc);
+    rowbeg[0] = 0;
+    for (uint64_t u = 0; u < n; u++) rowbeg[u + 1] = rowbeg[u] + cnt[u];
+    uint64_t total = rowbeg[n];
+    free(cnt);
+    cnt = NULL;
+    uint32_t *rows = (uint32_t *)malloc((total ? total : 1) * sizeof(uint32_t));
+    uint64_t *cur = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+    if (!rows || !cur) { free(rows); free(cur); goto fail_early; }
+    memcpy(cur, rowbeg, n * sizeof(uint64_t));
+    bc.cur = cur;
+    bc.rows = rows;
+    parallel_for(nitems, chunk, pass1_fn, &bc);
+    free(cur);
+    /* newdeg reuses a fresh array */
+    uint32_t *newdeg = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    if (!newdeg) { free(rows); goto fail_early; }
+    dedupe_ctx dc = {rowbeg, rows, newdeg};
+    parallel_for(n, 2048, dedupe_fn, &dc);
+    g->off = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
+    if (!g->off) { free(rows); free(newdeg); goto fail_early; }
+    g->off[0] = 0;
+    for (uint64_t u = 0; u < n; u++) g->off[u + 1] = g->off[u] + newdeg[u];
+    free(newdeg);
+    g->m = g->off[n];
+    g->col = (uint32_t *)malloc((g->m ? g->m : 1) * sizeof(uint32_t));
+    if (!g->col) { free(rows); free(g->off); goto fail_early; }
+    compact_ctx cc = {rowbeg, g->off, rows, g->col};
+    parallel_for(n, 4096, compact_fn, &cc);
+    free(rows);
+    free(rowbeg);
+    return g;
+fail_early:
+    free(cnt);
+    free(rowbeg);
+    free(g);
+    return NULL;
+}
+
+/* ------------------------------------------------------------------ public */
+gen_graph *gen_rmat(int scale, uint64_t nsamples, double a, double b, double c, uint64_t seed) {
+    if (scale < 1 || scale > 31 || a < 0 || b < 0 || c < 0 || a + b + c > 1.0) return NULL;
+    edge_src s;
+    memset(&s, 0, sizeof(s));
+    s.kind = 0;
+    s.scale = scale;
+    s.n = 1ull << scale;
+    s.nsamples = nsamples;
+    s.seed = mix64(seed ^ 0x524D4154ULL); /* stream key for "RMAT" */
+    double two32 = 4294967296.0;
+    double ta = a * two32, tab = (a + b) * two32, tabc = (a + b + c) * two32;
+    s.ta = ta >= two32 ? 0xFFFFFFFFu : (uint32_t)ta;
+    s.tab = tab >= two32 ? 0xFFFFFFFFu : (uint32_t)tab;
+    s.tabc = tabc >= two32 ? 0xFFFFFFFFu : (uint32_t)tabc;
+    return build_csr(&s, s.n, nsamples, 1u << 16);
+}
+
+gen_graph *gen_er(uint64_t n, uint64_t nsamples, uint64_t seed) {
+    if (n == 0 || n > 0xFFFFFFFEull) return NULL;
+    edge_src s;
+    memset(&s, 0, sizeof(s));
+    s.kind = 1;
+    s.n = n;
+    s.nsamples = nsamples;
+    s.seed = mix64(seed ^ 0x4552ULL); /* "ER" */
+    return build_csr(&s, n, nsamples, 1u << 16);
+}
+
+/* explicit (src[i], dst[i]) pairs; every id must be < n */
+gen_graph *gen_from_pairs(uint64_t n, uint64_t npairs, const uint32_t *src, const uint32_t *dst) {
+    for (uint64_t i = 0; i < npairs; i++)
+        if (src[i] >= n || dst[i] >= n) return NULL;
+    edge_src s;
+    memset(&s, 0, sizeof(s));
+    s.kind = 2;
+    s.n = n;
+    s.ps = src;
+    s.pd = dst;
+    return build_csr(&s, n, npairs, 1u << 16);
+}
+
+/* CSR of E union E^T */
+gen_graph *gen_symmetrize(const gen_graph *g) {
+    edge_src s;
+    memset(&s, 0, sizeof(s));
+    s.kind = 3;
+    s.n = g->n;
+    s.g = g;
+    return build_csr(&s, g->n, g->n, 4096);
+}
+
+/* symmetrize a caller-held CSR */
+gen_graph *gen_symmetrize_csr(uint64_t n, const uint64_t *off, const uint32_t *col) {
+    gen_graph tmp = {n, off[n], (uint64_t *)off, (uint32_t *)col};
+    return gen_symmetrize(&tmp);
+}
+
+uint64_t gen_num_vertices(const gen_graph *g) { return g->n; }
+uint64_t gen_num_edges(const gen_graph *g) { return g->m; }
+void gen_copy_out(const gen_graph *g, uint64_t *off, uint32_t *col) {
+    memcpy(off, g->off, (g->n + 1) * sizeof(uint64_t));
+    memcpy(col, g->col, g->m * sizeof(uint32_t));
+}
+void gen_free(gen_graph *g) {
+    if (!g) return;
+    free(g->off);
+    free(g->col);
+    free(g);
+}
+
+typedef struct {
+    const uint64_t *off;
+    const uint32_t *col;
+    uint32_t *w;
+    uint64_t key;
+    uint32_t maxw;
+} wctx;
+static void weights_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) {
+    (void)tid;
+    wctx *c = (wctx *)ctx;
+    for (uint64_t u = lo; u < hi; u++)
+        for (uint64_t e = c->off[u]; e < c->off[u + 1]; e++)
+            c->w[e] = 1u + (uint32_t)(mix64(c->key ^ ((u << 32) | c->col[e])) % c->maxw);
+}
+/* w[e] = 1 + hash(u, v) mod maxw, in [1, maxw] */
+void gen_weights(uint64_t n, const uint64_t *off, const uint32_t *col, uint64_t seed, uint32_t maxw, uint32_t *w) {
+    wctx c = {off, col, w, mix64(seed ^ 0x57454947ULL), maxw ? maxw : 1};
+    parallel_for(n, 4096, weights_fn, &c);
+}
+
+/* k distinct sources, uniform over vertices with out-degree >= 1 (rejection on a
+   counter stream); returns the number written (fewer if not enough such vertices) */
+uint64_t gen_sources(uint64_t n, const uint64_t *off, uint64_t k, uint64_t seed, uint32_t *out) {
+    uint64_t have = 0, eligible = 0;
+    for (uint64_t u = 0; u < n; u++) eligible += off[u + 1] > off[u];
+    if (k > eligible) k = eligible;
+    uint64_t key = mix64(seed ^ 0x53524353ULL);
+    for (uint64_t i = 0; have < k; i++) {
+        uint32_t v = (uint32_t)(((unsigned __int128)draw(key, i) * n) >> 64);
+        if (off[v + 1] == off[v]) continue;
+        int dup = 0;
+        for (uint64_t j = 0; j < have; j++) dup |= out[j] == v;
+        if (!dup) out[have++] = v;
+    }
+    return have;
+}

@@ -1,0 +1,294 @@
+"""Pins for the CPU oracle's BFS, SSSP, CC and PageRank.
+
+Each check compares the oracle with something other than itself: brute force over every
+small digraph, closed forms, scipy's independent graph routines, certificates that
+characterise the unique answer, or exact rational matrix powers.
+"""
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+from hypothesis import given, settings, strategies as st
+
+import gen
+import oracle
+
+U = oracle.UNREACHED
+
+
+def csr_from_edges(n, edges):
+    src = np.array([e[0] for e in edges], dtype=np.uint32)
+    dst = np.array([e[1] for e in edges], dtype=np.uint32)
+    return gen.from_pairs(n, src, dst)
+
+
+def dense_reach_levels(n, adj, s):
+    """Hop levels by boolean matrix powers: level = least k with (A^k)[s, v]."""
+    lvl = [U] * n
+    frontier = np.zeros(n, dtype=bool)
+    frontier[s] = True
+    seen = frontier.copy()
+    k = 0
+    while frontier.any():
+        for v in np.nonzero(frontier)[0]:
+            lvl[v] = k
+        nxt = (adj[frontier].any(axis=0)) & ~seen
+        seen |= nxt
+        frontier = nxt
+        k += 1
+    return lvl
+
+
+# ------------------------------------------------------------------ BFS
+def test_bfs_every_digraph_up_to_4_vertices():
+    n = 4
+    pairs = [(u, v) for u in range(n) for v in range(n) if u != v]
+    for mask in range(1 << len(pairs)):
+        edges = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+        off, col = csr_from_edges(n, edges)
+        adj = np.zeros((n, n), dtype=bool)
+        for u, v in edges:
+            adj[u, v] = True
+        for s in range(n):
+            lvl, it = oracle.bfs(off, col, s)
+            want = dense_reach_levels(n, adj, s)
+            assert list(lvl) == want, (edges, s)
+            assert it == 1 + max(x for x in want if x != U)
+
+
+def test_bfs_closed_forms():
+    n = 50
+    off, col = csr_from_edges(n, [(i, i + 1) for i in range(n - 1)])  # path
+    lvl, it = oracle.bfs(off, col, 0)
+    assert list(lvl) == list(range(n)) and it == n
+    lvl, it = oracle.bfs(off, col, 10)
+    assert list(lvl[:10]) == [U] * 10 and list(lvl[10:]) == list(range(n - 10)) and it == n - 10
+    off, col = csr_from_edges(n, [(0, i) for i in range(1, n)])  # star
+    lvl, it = oracle.bfs(off, col, 0)
+    assert lvl[0] == 0 and (lvl[1:] == 1).all() and it == 2
+    n = 127  # complete binary tree in heap order: level = floor(log2(v + 1))
+    off, col = csr_from_edges(n, [(v, c) for v in range(n) for c in (2 * v + 1, 2 * v + 2) if c < n])
+    lvl, it = oracle.bfs(off, col, 0)
+    assert list(lvl) == [int(np.floor(np.log2(v + 1))) for v in range(n)] and it == 7
+    n = 9  # directed cycle
+    off, col = csr_from_edges(n, [(i, (i + 1) % n) for i in range(n)])
+    lvl, _ = oracle.bfs(off, col, 4)
+    assert list(lvl) == [(v - 4) % n for v in range(n)]
+
+
+def bfs_certificate(off, col, s, lvl):
+    n = len(off) - 1
+    deg = np.diff(off).astype(np.int64)
+    u = np.repeat(np.arange(n, dtype=np.int64), deg)
+    lu, lv = lvl[u].astype(np.int64), lvl[col].astype(np.int64)
+    reached_u = lvl[u] != U
+    assert lvl[s] == 0
+    # no edge from a reached vertex skips a level, and it never leaves a vertex unreached
+    assert (lv[reached_u] <= lu[reached_u] + 1).all()
+    assert (lvl[col[reached_u]] != U).all()
+    # every reached v != s has a parent one level up
+    has_parent = np.zeros(n, dtype=bool)
+    tight = reached_u & (lv == lu + 1)
+    has_parent[col[tight]] = True
+    reached = lvl != U
+    reached[s] = False
+    assert has_parent[reached].all()
+
+
+def test_bfs_rmat16_certificate_and_scipy():
+    off, col = gen.rmat(16, 16, seed=16)
+    lvl, it = oracle.bfs(off, col, 0)
+    bfs_certificate(off, col, 0, lvl)
+    assert it == 1 + int(lvl[lvl != U].max())
+    # scipy's unweighted shortest paths as an independent routine
+    n = len(off) - 1
+    A = sp.csr_matrix((np.ones(len(col)), col.astype(np.int64), off.astype(np.int64)), shape=(n, n))
+    d = csg.shortest_path(A, method="D", unweighted=True, indices=0)
+    want = np.where(np.isinf(d), U, d).astype(np.uint32)
+    np.testing.assert_array_equal(lvl, want)
+
+
+# ----------------------------------------------------------------- SSSP
+def floyd_warshall(n, wedges):
+    INF = float("inf")
+    D = [[0 if i == j else INF for j in range(n)] for i in range(n)]
+    for u, v, w in wedges:
+        D[u][v] = min(D[u][v], w)
+    for k in range(n):
+        for i in range(n):
+            for j in range(n):
+                if D[i][k] + D[k][j] < D[i][j]:
+                    D[i][j] = D[i][k] + D[k][j]
+    return D
+
+
+@settings(max_examples=150, deadline=None)
+@given(st.integers(1, 9).flatmap(lambda n: st.tuples(
+    st.just(n),
+    st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1), st.integers(1, 64)), max_size=30),
+    st.integers(0, n - 1))))
+def test_sssp_matches_floyd_warshall(case):
+    n, wedges, s = case
+    # the CSR keeps one copy of each (u, v); give it that pair's weight
+    wmap = {}
+    for u, v, w in wedges:
+        if u != v:
+            wmap.setdefault((u, v), w)
+    off, col = csr_from_edges(n, list(wmap))
+    deg = np.diff(off).astype(np.int64)
+    us = np.repeat(np.arange(n), deg)
+    w = np.array([wmap[(int(a), int(b))] for a, b in zip(us, col)], dtype=np.uint32)
+    dist = oracle.sssp(off, col, w, s)
+    D = floyd_warshall(n, [(a, b, c) for (a, b), c in wmap.items()])
+    want = [U if D[s][v] == float("inf") else D[s][v] for v in range(n)]
+    assert list(dist) == want
+
+
+def sssp_certificate(off, col, w, s, dist):
+    n = len(off) - 1
+    deg = np.diff(off).astype(np.int64)
+    u = np.repeat(np.arange(n, dtype=np.int64), deg)
+    du, dv = dist[u].astype(np.int64), dist[col].astype(np.int64)
+    ru = dist[u] != U
+    assert dist[s] == 0
+    assert (dist[col[ru]] != U).all()
+    assert (dv[ru] <= du[ru] + w[ru]).all()
+    tight = ru & (dv == du + w)
+    has_parent = np.zeros(n, dtype=bool)
+    has_parent[col[tight]] = True
+    reached = dist != U
+    reached[s] = False
+    assert has_parent[reached].all()
+
+
+def test_sssp_rmat16_certificate_scipy_and_unit_weights():
+    off, col = gen.rmat(16, 16, seed=16)
+    w = gen.weights(off, col, 1016)
+    dist = oracle.sssp(off, col, w, 0)
+    sssp_certificate(off, col, w, 0, dist)
+    n = len(off) - 1
+    A = sp.csr_matrix((w.astype(np.float64), col.astype(np.int64), off.astype(np.int64)), shape=(n, n))
+    d = csg.dijkstra(A, indices=0)
+    np.testing.assert_array_equal(dist, np.where(np.isinf(d), U, d).astype(np.uint32))
+    # unit weights reduce SSSP to BFS
+    lvl, _ = oracle.bfs(off, col, 0)
+    np.testing.assert_array_equal(oracle.sssp(off, col, np.ones_like(col), 0), lvl)
+
+
+def test_sssp_closed_form_and_overflow():
+    n = 20
+    off, col = csr_from_edges(n, [(i, i + 1) for i in range(n - 1)])
+    w = np.arange(1, n, dtype=np.uint32)
+    assert list(oracle.sssp(off, col, w, 0)) == [v * (v + 1) // 2 for v in range(n)]
+    off, col = csr_from_edges(3, [(0, 1), (1, 2)])
+    with pytest.raises(OverflowError):
+        oracle.sssp(off, col, np.array([2**31, 2**31], dtype=np.uint32), 0)
+    # 2^32 - 2 is the largest distance that fits
+    d = oracle.sssp(off, col, np.array([2**31, 2**31 - 2], dtype=np.uint32), 0)
+    assert int(d[2]) == 2**32 - 2
+
+
+def test_sync_rounds_bounds_and_closed_forms():
+    n = 30
+    off, col = csr_from_edges(n, [(i, i + 1) for i in range(n - 1)])
+    assert oracle.sync_rounds(off, col, np.ones(n - 1, np.uint32), "sssp", 0) == n
+    # a shortcut edge that is heavier than the path: synchronous rounds follow hop count
+    # first, then the cheaper long path keeps improving the far end
+    off, col = csr_from_edges(4, [(0, 1), (1, 2), (2, 3), (0, 3)])
+    w = np.array([1, 100, 1, 1], dtype=np.uint32)  # CSR rows: 0->1, 0->3, 1->2, 2->3
+    assert oracle.sync_rounds(off, col, w, "sssp", 0) == 4
+    # label propagation on an undirected path settles after n rounds (n-1 hops + 1 quiet)
+    off, col = gen.symmetrize(*csr_from_edges(n, [(i, i + 1) for i in range(n - 1)]))
+    assert oracle.sync_rounds(off, col, None, "cc") == n
+
+
+# ------------------------------------------------------------------- CC
+@settings(max_examples=120, deadline=None)
+@given(st.integers(1, 10).flatmap(lambda n: st.tuples(
+    st.just(n), st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=20))))
+def test_cc_matches_transitive_closure(case):
+    n, edges = case
+    off, col = gen.symmetrize(*csr_from_edges(n, [e for e in edges if e[0] != e[1]]))
+    lab, k = oracle.cc(off, col)
+    R = np.eye(n, dtype=bool)
+    for u, v in edges:
+        R[u, v] = R[v, u] = True
+    for m in range(n):  # Warshall
+        R |= R[:, [m]] & R[[m], :]
+    want = [int(np.nonzero(R[v])[0].min()) for v in range(n)]
+    assert list(lab) == want
+    assert k == len(set(want))
+
+
+def test_cc_rmat16_invariants_and_scipy():
+    off, col = gen.symmetrize(*gen.rmat(16, 16, seed=16))
+    lab, k = oracle.cc(off, col)
+    n = len(off) - 1
+    v = np.arange(n)
+    u = np.repeat(v, np.diff(off).astype(np.int64))
+    assert (lab[u] == lab[col]).all()
+    assert (lab <= v).all()
+    assert (lab[lab] == lab).all()
+    assert len(np.unique(lab)) == k
+    A = sp.csr_matrix((np.ones(len(col)), col.astype(np.int64), off.astype(np.int64)), shape=(n, n))
+    ncomp, comp = csg.connected_components(A, directed=False)
+    assert ncomp == k
+    # same partition: map scipy's component id to its min vertex
+    first = np.full(ncomp, n)
+    np.minimum.at(first, comp, v)
+    np.testing.assert_array_equal(lab, first[comp])
+    deg = np.diff(off)
+    assert (lab[deg == 0] == v[deg == 0]).all()  # isolated vertices label themselves
+
+
+# ------------------------------------------------------------ PageRank
+def exact_pagerank(n, edges, d, T):
+    """Exact rational power iteration, dangling mass leaks."""
+    out = {u: [] for u in range(n)}
+    for u, v in edges:
+        out[u].append(v)
+    x = [Fraction(1, n)] * n
+    for _ in range(T):
+        acc = [Fraction(0)] * n
+        for u in range(n):
+            for v in out[u]:
+                acc[v] += x[u] / len(out[u])
+        x = [(1 - d) / n + d * a for a in acc]
+    return x
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(1, 8).flatmap(lambda n: st.tuples(
+    st.just(n), st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=20),
+    st.integers(0, 12))))
+def test_pagerank_matches_exact_rationals(case):
+    n, edges, T = case
+    edges = sorted({e for e in edges if e[0] != e[1]})
+    off, col = csr_from_edges(n, edges)
+    x = oracle.pagerank(off, col, 0.85, T)
+    want = exact_pagerank(n, edges, Fraction(85, 100), T)
+    np.testing.assert_allclose(x, [float(f) for f in want], rtol=0, atol=1e-15)
+
+
+def test_pagerank_closed_forms_and_mass_invariant():
+    n = 11
+    off, col = csr_from_edges(n, [(i, (i + 1) % n) for i in range(n)])
+    np.testing.assert_allclose(oracle.pagerank(off, col, 0.85, 20), np.full(n, 1 / n), atol=1e-16)
+    off, col = gen.rmat(16, 16, seed=16)
+    n = len(off) - 1
+    d = 0.85
+    x19 = oracle.pagerank(off, col, d, 19)
+    x20 = oracle.pagerank(off, col, d, 20)
+    deg = np.diff(off)
+    indeg = np.bincount(col, minlength=n)
+    # no in-edges: only the teleport term
+    np.testing.assert_allclose(x20[indeg == 0], (1 - d) / n, rtol=1e-15)
+    # total mass after a step = (1-d) + d * mass held by vertices that have out-edges
+    assert abs(x20.sum() - ((1 - d) + d * x19[deg > 0].sum())) < 1e-12
+    # scipy sparse transpose product as an independent step
+    A = sp.csr_matrix((np.ones(len(col)), col.astype(np.int64), off.astype(np.int64)), shape=(n, n))
+    share = np.where(deg > 0, x19 / np.maximum(deg, 1), 0.0)
+    np.testing.assert_allclose(x20, (1 - d) / n + d * (A.T @ share), rtol=1e-12, atol=1e-18)
