@@ -1,0 +1,230 @@
+/*
+ * hytm.h -- C ABI of libhytm.so: hybrid transfer management for vertex-centric graph
+ * traversal on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: "HyTGraph: GPU-Accelerated Graph Processing with Hybrid Transfer Management"
+ * (Wang, Ai, Zhang, Chen, Yu; arXiv 2208.14935).
+ *
+ * Problem statement followed (Sec. 1, Sec. 2.1, Sec. 4): a CSR graph whose
+ * vertex-associated data (values, neighbour index, activity) lives in GPU memory while
+ * the edge-associated arrays (neighbours, weights) live in host memory; a push-style
+ * vertex-centric iteration processes the active vertices until none remain; each
+ * iteration a per-partition cost model (Sec. 5.1, Eq. 1-3) picks how a partition's
+ * active edges reach the GPU:
+ *   FILTER   -- explicit copy of the whole partition (Sec. 2.2 "ExpTM-filter");
+ *   COMPACT  -- host threads gather only the active neighbour lists, which are then
+ *               copied (Sec. 2.2 "ExpTM-compaction", Sec. 6.3);
+ *   ZEROCOPY -- kernels read the mapped pinned host arrays directly (Sec. 2.3).
+ * Consecutive FILTER partitions are combined into larger tasks (Sec. 5.2) and the
+ * engines run concurrently on several streams (Sec. 6.2).  A device-memory budget caps
+ * the bytes of edge data held on the GPU; partitions that fit inside it are kept
+ * resident (RESIDENT, no transfer), which is this library's addition to the method.
+ *
+ * Conventions for every call:
+ *  - Return value: hytm_status, HYTM_OK (0) on success.  On failure a thread-local
+ *    message is available from hytm_last_error() until the next call on that thread.
+ *  - On any error other than HYTM_E_DEVICE, caller-owned output buffers are untouched.
+ *  - Host pointers are plain CPU addresses; the library never keeps a caller pointer
+ *    past the call that received it.
+ *  - A graph handle is not reentrant: calls on one handle must not overlap.  Separate
+ *    handles may be used from separate threads.
+ */
+#ifndef HYTM_H
+#define HYTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hytm_graph hytm_graph; /* opaque, owned by the library */
+
+typedef enum {
+    HYTM_OK = 0,
+    HYTM_E_INVAL = 1,       /* null pointer, malformed CSR, missing weights, bad parameter */
+    HYTM_E_RANGE = 2,       /* n >= 2^32-1, source >= n, distance overflow */
+    HYTM_E_NOMEM = 3,       /* host or device allocation failed */
+    HYTM_E_BUDGET = 4,      /* a forced FILTER/COMPACT run whose staging does not fit the budget */
+    HYTM_E_DEVICE = 5,      /* a HIP runtime error; the message carries hipGetErrorString */
+    HYTM_E_STATE = 6,       /* call not valid in the handle's current state */
+    HYTM_E_UNSUPPORTED = 7  /* request this build does not implement */
+} hytm_status;
+
+/* Algorithms (Sec. 7.1).  Outputs are one 4-byte value per vertex:
+   BFS: uint32 hop level; SSSP: uint32 distance; CC: uint32 label = smallest vertex id
+   of the component; PAGERANK: float rank.  Unreached vertices hold 0xFFFFFFFF. */
+typedef enum { HYTM_BFS = 0, HYTM_SSSP = 1, HYTM_CC = 2, HYTM_PAGERANK = 3 } hytm_algo;
+
+/* Transfer policy for partitions that are not resident.  HYBRID applies the cost
+   model of Sec. 5.1; the others force one engine for every scheduled partition. */
+typedef enum {
+    HYTM_MODE_HYBRID = 0,
+    HYTM_MODE_FILTER = 1,
+    HYTM_MODE_COMPACT = 2,
+    HYTM_MODE_ZEROCOPY = 3
+} hytm_mode;
+
+/* Per-partition engine codes, as written to hytm_run_stats.mode_trace. */
+enum { HYTM_P_NONE = 0, HYTM_P_RESIDENT = 1, HYTM_P_FILTER = 2, HYTM_P_ZEROCOPY = 3, HYTM_P_COMPACT = 4 };
+
+/* hytm_graph_create flags */
+enum {
+    HYTM_GRAPH_SYMMETRIC = 1u << 1, /* caller asserts (u,v) in E implies (v,u) in E; needed by HYTM_CC */
+    HYTM_GRAPH_SKIP_COL_CHECK = 1u << 2 /* skip the O(m) check that every col[e] < n */
+};
+
+/* Tunables.  Defaults (hytm_default_params) are the constants the paper states:
+   m = 128-byte requests and MR = 256 outstanding requests per TLP window (Sec. 5.1,
+   Eq. 1), alpha = 0.8 and beta = 0.4 (Sec. 5.1 selection rule), gamma = 0.625 (the
+   zero-copy round-trip damping after Eq. 3), k = 4 partitions per combined filter task
+   (Sec. 5.2), index entries of 4 bytes (d2 of Eq. 2), and 32768 edges per partition. */
+typedef struct {
+    uint32_t struct_size;       /* sizeof(hytm_params) */
+    hytm_mode mode;             /* HYTM_MODE_HYBRID */
+    uint32_t partition_edges;   /* 32768: target edges per partition (Sec. 4 chunking) */
+    uint32_t combine_k;         /* 4: max partitions per filter task (Sec. 5.2) */
+    uint32_t alpha_num, alpha_den; /* 4, 5 */
+    uint32_t beta_num, beta_den;   /* 2, 5 */
+    uint32_t gamma_num, gamma_den; /* 5, 8 */
+    uint32_t line_bytes;        /* 128: m, a power of two >= 4 */
+    uint32_t max_outstanding;   /* 256: MR */
+    uint32_t index_bytes;       /* 4: d2 */
+    uint32_t pr_iterations;     /* 20 */
+    double pr_damping;          /* 0.85 */
+    uint32_t streams;           /* 4: staging slots of the filter pipeline (>= 2) */
+    uint32_t gather_threads;    /* 0 = automatic: host threads of the compaction engine */
+    uint64_t compact_chunk_edges; /* 0 = automatic: edges per compaction chunk */
+} hytm_params;
+
+/* Per-iteration record (optional, see hytm_run_stats.iters). */
+typedef struct {
+    uint32_t parts[5];          /* partitions per engine code */
+    uint32_t filter_tasks;      /* combined filter tasks issued */
+    uint64_t active_vertices;   /* active vertices with at least one out-edge */
+    uint64_t active_edges;      /* their out-edges (edges pushed) */
+    uint64_t bytes_filter;      /* host-to-device bytes moved by filter copies */
+    uint64_t bytes_compact;     /* host-to-device bytes moved by compaction copies */
+    uint64_t zc_lines;          /* 128-byte lines read by the zero-copy kernel, per edge array */
+    double ms;                  /* host wall time of the iteration */
+} hytm_iter_stats;
+
+/* Run statistics (optional).  Zero it, set struct_size, and optionally point iters /
+   mode_trace at caller buffers; the library fills the rest. */
+typedef struct {
+    uint32_t struct_size;       /* sizeof(hytm_run_stats) */
+    uint32_t iterations;
+    uint32_t npart;             /* partitions of the graph */
+    uint32_t nres;              /* resident partitions (a prefix 0..nres-1) */
+    uint64_t part_iters[5];     /* partition-iterations per engine code */
+    uint64_t active_vertices;   /* sum over iterations */
+    uint64_t active_edges;      /* sum over iterations: edges pushed */
+    uint64_t bytes_filter;      /* H2D bytes of filter copies */
+    uint64_t bytes_compact;     /* H2D bytes of compaction copies */
+    uint64_t zc_lines;          /* 128-byte lines read by the zero-copy kernel, per edge array */
+    uint64_t bytes_zerocopy;    /* zc_lines x 128 B x edge arrays */
+    uint64_t bytes_d2h;         /* device-to-host bytes of selections and active lists */
+    uint64_t bytes_resident_fill; /* H2D bytes copied into the resident cache this run */
+    uint64_t filter_tasks;
+    uint64_t compact_chunks;
+    double ms_total;            /* first kernel to values in the caller's buffer */
+    double ms_fill;             /* resident-cache fill inside ms_total */
+    double ms_select;           /* stats + selection + active lists + their D2H */
+    hytm_iter_stats *iters;     /* caller buffer of iters_cap records, or NULL */
+    uint32_t iters_cap;
+    uint32_t iters_written;
+    uint8_t *mode_trace;        /* caller buffer: iteration t's engine codes at t*npart, or NULL */
+    uint64_t mode_trace_cap;    /* bytes */
+} hytm_run_stats;
+
+/* Static facts about a graph handle. */
+typedef struct {
+    uint64_t n, m;
+    uint32_t npart;             /* partitions for the current partition_edges */
+    uint32_t max_partition_edges;
+    int hip_device;
+    uint32_t flags;
+} hytm_graph_info;
+
+/* Fill *p with the paper's defaults listed above. */
+void hytm_default_params(hytm_params *p);
+
+/* Create a graph from a CSR (Sec. 4 layout).
+   n, m      : vertex and edge counts; n < 2^32-1 (ids are uint32, 0xFFFFFFFF is reserved).
+   offsets   : host array of n+1 entries, each offset_bytes (4 or 8) wide, non-decreasing,
+               offsets[0] = 0 and offsets[n] = m.  Copied to the device (as uint64).
+   col       : host array of m neighbour ids (< n).  Copied into library-owned pinned,
+               device-mapped host memory (the edge data stays in host memory).
+   weights   : host array of m uint32 edge weights, or NULL.  Copied like col.
+   flags     : HYTM_GRAPH_* bits.
+   hip_device: HIP device ordinal the handle binds to.
+   out       : receives the handle.
+   Errors: E_INVAL (null pointers, malformed offsets, col >= n), E_RANGE (n too large),
+   E_NOMEM, E_DEVICE (no such device / HIP failure).  Partitioning uses the default
+   partition_edges until hytm_set_params changes it. */
+hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void *offsets, uint32_t offset_bytes,
+                              const uint32_t *col, const uint32_t *weights, uint32_t flags, int hip_device,
+                              hytm_graph **out);
+
+/* Device budget for edge-associated data: resident partitions + filter staging +
+   compaction buffers.  UINT64_MAX (the default) = uncapped: every partition resident.
+   Vertex arrays are outside the budget, as in the paper's placement (Sec. 1).  Takes
+   effect at the next run. */
+hytm_status hytm_set_device_budget(hytm_graph *g, uint64_t edge_bytes);
+
+/* Bytes of the budget that the engines' buffers take for `algo` under the current
+   parameters: filter = `streams` staging slots, each holding the largest combined task
+   (max(combine_k * partition_edges, largest partition) edges); compaction = two chunk
+   buffers of compact_chunk_edges edges (default max(slot, 2^22)); times 4 bytes per edge
+   array read (two arrays for SSSP).  Hybrid needs both; a forced mode needs its own;
+   zero-copy needs none.  The rest of the budget holds resident partitions.  In hybrid
+   mode an engine whose buffers do not fit is left out of the choice; a forced
+   FILTER/COMPACT run whose buffers do not fit fails with E_BUDGET. */
+hytm_status hytm_staging_bytes(const hytm_graph *g, hytm_algo algo, uint64_t *bytes);
+
+/* Replace the tunables (NULL = defaults).  E_INVAL on a bad field.  Re-partitions the
+   graph when partition_edges changes. */
+hytm_status hytm_set_params(hytm_graph *g, const hytm_params *p);
+hytm_status hytm_get_params(const hytm_graph *g, hytm_params *p);
+
+hytm_status hytm_graph_info_get(const hytm_graph *g, hytm_graph_info *info);
+
+/* Partition start vertices plus a final n: bounds[0..npart] (caller buffer of
+   info.npart + 1 entries). */
+hytm_status hytm_partition_bounds(const hytm_graph *g, uint64_t *bounds, uint64_t cap);
+
+/* Run one algorithm to convergence (PageRank: pr_iterations synchronous steps).
+   source     : start vertex for BFS/SSSP (ignored by CC and PageRank); E_RANGE if >= n.
+   values_out : host buffer of n 4-byte values (see hytm_algo).
+   iterations_out : number of non-empty frontiers processed (NULL ok).
+   stats      : NULL or a hytm_run_stats to fill.
+   hip_stream : hipStream_t to order the run after (NULL = the null stream); the call
+                returns only once values_out is written.
+   Errors: E_INVAL (SSSP without weights, CC without HYTM_GRAPH_SYMMETRIC), E_RANGE
+   (source, SSSP distance overflow), E_BUDGET, E_NOMEM, E_DEVICE. */
+hytm_status hytm_run(hytm_graph *g, hytm_algo algo, uint32_t source, void *values_out, uint32_t *iterations_out,
+                     hytm_run_stats *stats, void *hip_stream);
+
+/* Evaluate the engine selection of Sec. 5.1 (Eq. 1-3, alpha/beta rule) on the GPU for
+   caller-supplied per-partition statistics, with the handle's parameters.
+   npart      : partitions; E, nA, Ea, Rq: host arrays of npart uint64 (edges, active
+                vertices, active edges, zero-copy requests at m-byte lines);
+   nres       : partitions [0, nres) are resident;
+   edge_arrays: 1 (neighbours only) or 2 (neighbours and weights) -> d1 = 4 or 8;
+   p_out      : host array of npart engine codes (HYTM_P_*).  Used to test the device
+                selection against a reference on arbitrary inputs. */
+hytm_status hytm_select_engines(hytm_graph *g, uint64_t npart, const uint64_t *E, const uint64_t *nA,
+                                const uint64_t *Ea, const uint64_t *Rq, uint64_t nres, uint32_t edge_arrays,
+                                uint8_t *p_out);
+
+/* Free everything the handle owns.  NULL is accepted. */
+hytm_status hytm_graph_destroy(hytm_graph *g);
+
+/* Thread-local message for the last failed call on this thread ("" if none). */
+const char *hytm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYTM_H */

@@ -1,0 +1,295 @@
+"""Python binding of libhytm.so (hybrid transfer management graph traversal, MI355X).
+
+Argument marshalling only: every step of a run executes inside libhytm.so (HIP kernels
+for gfx950 plus its host runtime).  The C ABI is declared in include/hytm.h.  PyTorch,
+when present, only supplies the HIP stream a run is ordered after.
+
+Loading fails loudly when the library has not been built (``build()``); there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhytm.so")
+
+OK, E_INVAL, E_RANGE, E_NOMEM, E_BUDGET, E_DEVICE, E_STATE, E_UNSUPPORTED = range(8)
+STATUS_NAMES = ["OK", "E_INVAL", "E_RANGE", "E_NOMEM", "E_BUDGET", "E_DEVICE", "E_STATE", "E_UNSUPPORTED"]
+ALGOS = {"bfs": 0, "sssp": 1, "cc": 2, "pagerank": 3, "pr": 3}
+MODES = {"hybrid": 0, "filter": 1, "compact": 2, "zerocopy": 3}
+P_NONE, P_RESIDENT, P_FILTER, P_ZEROCOPY, P_COMPACT = range(5)
+ENGINE_NAMES = ["none", "resident", "filter", "zerocopy", "compact"]
+GRAPH_SYMMETRIC = 1 << 1
+GRAPH_SKIP_COL_CHECK = 1 << 2
+UNCAPPED = (1 << 64) - 1
+UNREACHED = 0xFFFFFFFF
+
+
+class HytmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {message}")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("mode", ctypes.c_int), ("partition_edges", ctypes.c_uint32),
+        ("combine_k", ctypes.c_uint32), ("alpha_num", ctypes.c_uint32), ("alpha_den", ctypes.c_uint32),
+        ("beta_num", ctypes.c_uint32), ("beta_den", ctypes.c_uint32), ("gamma_num", ctypes.c_uint32),
+        ("gamma_den", ctypes.c_uint32), ("line_bytes", ctypes.c_uint32), ("max_outstanding", ctypes.c_uint32),
+        ("index_bytes", ctypes.c_uint32), ("pr_iterations", ctypes.c_uint32), ("pr_damping", ctypes.c_double),
+        ("streams", ctypes.c_uint32), ("gather_threads", ctypes.c_uint32),
+        ("compact_chunk_edges", ctypes.c_uint64),
+    ]
+
+
+class IterStats(ctypes.Structure):
+    _fields_ = [
+        ("parts", ctypes.c_uint32 * 5), ("filter_tasks", ctypes.c_uint32), ("active_vertices", ctypes.c_uint64),
+        ("active_edges", ctypes.c_uint64), ("bytes_filter", ctypes.c_uint64), ("bytes_compact", ctypes.c_uint64),
+        ("zc_lines", ctypes.c_uint64), ("ms", ctypes.c_double),
+    ]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("iterations", ctypes.c_uint32), ("npart", ctypes.c_uint32),
+        ("nres", ctypes.c_uint32), ("part_iters", ctypes.c_uint64 * 5), ("active_vertices", ctypes.c_uint64),
+        ("active_edges", ctypes.c_uint64), ("bytes_filter", ctypes.c_uint64), ("bytes_compact", ctypes.c_uint64),
+        ("zc_lines", ctypes.c_uint64), ("bytes_zerocopy", ctypes.c_uint64), ("bytes_d2h", ctypes.c_uint64),
+        ("bytes_resident_fill", ctypes.c_uint64), ("filter_tasks", ctypes.c_uint64),
+        ("compact_chunks", ctypes.c_uint64), ("ms_total", ctypes.c_double), ("ms_fill", ctypes.c_double),
+        ("ms_select", ctypes.c_double), ("iters", ctypes.POINTER(IterStats)), ("iters_cap", ctypes.c_uint32),
+        ("iters_written", ctypes.c_uint32), ("mode_trace", ctypes.POINTER(ctypes.c_uint8)),
+        ("mode_trace_cap", ctypes.c_uint64),
+    ]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("m", ctypes.c_uint64), ("npart", ctypes.c_uint32),
+                ("max_partition_edges", ctypes.c_uint32), ("hip_device", ctypes.c_int), ("flags", ctypes.c_uint32)]
+
+
+# every exported entry point of include/hytm.h with its ctypes signature
+_SIGNATURES = {
+    "hytm_default_params": (None, [ctypes.POINTER(Params)]),
+    "hytm_graph_create": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "hytm_set_device_budget": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "hytm_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params)]),
+    "hytm_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params)]),
+    "hytm_graph_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GraphInfo)]),
+    "hytm_staging_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
+    "hytm_partition_bounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
+    "hytm_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(RunStats), ctypes.c_void_p]),
+    "hytm_select_engines": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                           ctypes.c_void_p]),
+    "hytm_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "hytm_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libhytm.so for gfx950 with hipcc (always recompiles)."""
+    from . import _build as _b
+    return _b.build(verbose=verbose)
+
+
+def load() -> ctypes.CDLL:
+    """Load the built library; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2208_14935_amd.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise HytmError(status, load().hytm_last_error().decode(errors="replace"))
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def default_params() -> Params:
+    p = Params()
+    load().hytm_default_params(ctypes.byref(p))
+    return p
+
+
+def _current_stream():
+    """HIP stream of PyTorch's current stream on the current device, or None."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+@dataclass
+class RunResult:
+    values: np.ndarray          # uint32 levels / distances / labels, or float32 ranks
+    iterations: int
+    stats: dict = field(default_factory=dict)
+    iters: list = field(default_factory=list)
+    mode_trace: np.ndarray | None = None  # iterations x npart engine codes
+
+
+class Graph:
+    """A CSR graph whose edge arrays live in pinned host memory (libhytm handle)."""
+
+    def __init__(self, off, col, weights=None, symmetric: bool = False, device: int = 0,
+                 check_col: bool = True):
+        lib = load()
+        off = np.ascontiguousarray(off)
+        if off.dtype not in (np.uint32, np.uint64):
+            off = off.astype(np.uint64)
+        col = np.ascontiguousarray(col, dtype=np.uint32)
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint32)
+        if w is not None and w.shape != col.shape:
+            raise ValueError("weights and col differ in length")
+        self.n = len(off) - 1
+        self.m = len(col)
+        flags = (GRAPH_SYMMETRIC if symmetric else 0) | (0 if check_col else GRAPH_SKIP_COL_CHECK)
+        h = ctypes.c_void_p()
+        self._keep = [np.zeros(1, np.uint32)]  # stand-in buffer for empty arrays
+        colp = _ptr(col) if self.m else _ptr(self._keep[0])
+        wp = None if w is None else (_ptr(w) if self.m else _ptr(self._keep[0]))
+        _check(lib.hytm_graph_create(self.n, self.m, _ptr(off), off.dtype.itemsize, colp, wp, flags, device,
+                                     ctypes.byref(h)))
+        self._h = h
+        self.weighted = w is not None
+        self.symmetric = symmetric
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().hytm_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_budget(self, edge_bytes):
+        """Device bytes for edge data (None = uncapped, every partition resident)."""
+        _check(load().hytm_set_device_budget(self._h, UNCAPPED if edge_bytes is None else int(edge_bytes)))
+
+    def params(self) -> Params:
+        p = Params()
+        _check(load().hytm_get_params(self._h, ctypes.byref(p)))
+        return p
+
+    def set_params(self, **kw):
+        """Update tunables by name (see hytm_params); mode may be given as a string."""
+        p = self.params()
+        for k, v in kw.items():
+            if k == "mode" and isinstance(v, str):
+                v = MODES[v]
+            if k in ("alpha", "beta", "gamma"):
+                setattr(p, k + "_num", int(v[0]))
+                setattr(p, k + "_den", int(v[1]))
+                continue
+            if not hasattr(p, k):
+                raise AttributeError(f"unknown parameter {k}")
+            setattr(p, k, v)
+        _check(load().hytm_set_params(self._h, ctypes.byref(p)))
+
+    def reset_params(self):
+        _check(load().hytm_set_params(self._h, None))
+
+    def info(self) -> dict:
+        i = GraphInfo()
+        _check(load().hytm_graph_info_get(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in GraphInfo._fields_}
+
+    def staging_bytes(self, algo: str) -> int:
+        b = ctypes.c_uint64(0)
+        _check(load().hytm_staging_bytes(self._h, ALGOS[algo], ctypes.byref(b)))
+        return int(b.value)
+
+    def set_resident_fraction(self, algo: str, frac: float):
+        """Budget = the engines' staging + `frac` of the edge bytes `algo` reads."""
+        arrays = 2 if ALGOS[algo] == 1 else 1
+        self.set_budget(self.staging_bytes(algo) + int(frac * 4 * arrays * self.m))
+
+    def partition_bounds(self) -> np.ndarray:
+        npart = self.info()["npart"]
+        b = np.empty(npart + 1, dtype=np.uint64)
+        _check(load().hytm_partition_bounds(self._h, _ptr(b), len(b)))
+        return b
+
+    def run(self, algo: str, source: int = 0, stats: bool = False, trace: bool = False, stream=None,
+            out: np.ndarray | None = None) -> RunResult:
+        lib = load()
+        a = ALGOS[algo]
+        dtype = np.float32 if a == 3 else np.uint32
+        vals = out if out is not None else np.empty(max(self.n, 1), dtype=dtype)[: self.n]
+        it = ctypes.c_uint32(0)
+        st = None
+        iters_buf = trace_buf = None
+        if stats or trace:
+            st = RunStats()
+            st.struct_size = ctypes.sizeof(RunStats)
+            cap = 4096
+            iters_buf = (IterStats * cap)()
+            st.iters = ctypes.cast(iters_buf, ctypes.POINTER(IterStats))
+            st.iters_cap = cap
+            if trace:
+                npart = self.info()["npart"]
+                trace_buf = np.zeros(npart * cap if npart * cap < (1 << 28) else npart * 64, dtype=np.uint8)
+                st.mode_trace = trace_buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+                st.mode_trace_cap = len(trace_buf)
+        s = stream if stream is not None else _current_stream()
+        _check(lib.hytm_run(self._h, a, int(source), _ptr(vals), ctypes.byref(it),
+                            ctypes.byref(st) if st is not None else None, s))
+        res = RunResult(vals, int(it.value))
+        if st is not None:
+            res.stats = {k: (list(getattr(st, k)) if k == "part_iters" else getattr(st, k))
+                         for k, _ in RunStats._fields_ if k not in ("iters", "mode_trace", "struct_size")}
+            for t in range(st.iters_written):
+                r = iters_buf[t]
+                res.iters.append({k: (list(getattr(r, k)) if k == "parts" else getattr(r, k))
+                                  for k, _ in IterStats._fields_})
+            if trace:
+                npart = st.npart
+                rows = min(res.iterations, len(trace_buf) // max(npart, 1))
+                res.mode_trace = trace_buf[: rows * npart].reshape(rows, npart).copy()
+        return res
+
+    def select_engines(self, E, nA, Ea, Rq, nres: int = 0, edge_arrays: int = 1) -> np.ndarray:
+        arrs = [np.ascontiguousarray(x, dtype=np.uint64) for x in (E, nA, Ea, Rq)]
+        npart = len(arrs[0])
+        p = np.zeros(max(npart, 1), dtype=np.uint8)
+        _check(load().hytm_select_engines(self._h, npart, *(_ptr(x) for x in arrs), int(nres), int(edge_arrays),
+                                          _ptr(p)))
+        return p[:npart]

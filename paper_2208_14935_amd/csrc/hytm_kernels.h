@@ -1,0 +1,101 @@
+// Device kernels of the hybrid-transfer traversal and their host-side launchers.
+// Every launcher is asynchronous on the given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hytm {
+
+// Engine codes per partition (same values as HYTM_P_* in hytm.h).
+enum : uint8_t { P_NONE = 0, P_RES = 1, P_FILTER = 2, P_ZC = 3, P_COMPACT = 4 };
+// Active lists are laid out in segments ordered RESIDENT, FILTER, ZEROCOPY, COMPACT
+// (segment index = engine code - 1); COMPACT is last so that the work prefix of its
+// final entry is the grand total.
+constexpr int NSEG = 4;
+constexpr int SEG_R = 0, SEG_F = 1, SEG_Z = 2, SEG_C = 3;
+
+enum Algo : int { ALGO_BFS = 0, ALGO_SSSP = 1, ALGO_CC = 2, ALGO_PR = 3 };
+
+// Zero-copy kernel line: 32 four-byte elements = 128 bytes.
+constexpr uint32_t ZC_LINE_SHIFT = 5;
+
+// Inputs of the engine selection (Sec. 5.1), all integers.
+struct SelParams {
+    uint64_t L;           // m * MR: bytes carried by one saturated TLP window
+    uint32_t MR;          // outstanding requests per window
+    uint32_t d1, d2;      // bytes per edge (over the arrays read), bytes per index entry
+    uint32_t an, ad;      // alpha = an / ad
+    uint32_t bn, bd;      // beta  = bn / bd
+    uint32_t gn, gd;      // gamma = gn / gd
+    uint32_t cost_shift;  // log2(m / 4): elements per m-byte request line
+    uint32_t arrays;      // edge arrays read per edge (1 or 2)
+    uint32_t force;       // 0: cost model; else the engine code for every scheduled partition
+    uint32_t nres;        // partitions [0, nres) are resident
+    uint32_t allow_filter, allow_compact; // engines whose staging fits the budget
+};
+
+// Written by the scan kernel, copied to the host every iteration.
+struct Header {
+    uint32_t seg_parts[NSEG];
+    uint32_t seg_list_start[NSEG];
+    uint32_t seg_list_count[NSEG];
+    uint64_t seg_work_start[NSEG];
+    uint64_t seg_work_total[NSEG];
+    uint64_t seg_edges[NSEG];
+    uint64_t seg_cost_lines[NSEG];
+    uint64_t total_active;   // list entries (active vertices with out-edges)
+    uint64_t frontier;       // all active vertices, including those without out-edges
+};
+
+// Vertex state an algorithm's push operator touches.
+struct AlgoState {
+    int algo;
+    uint32_t* val;        // BFS level / SSSP distance / CC label
+    uint32_t* visited;    // BFS: discovered-vertex bitmap
+    uint32_t* next;       // next-frontier bitmap
+    uint32_t* overflow;   // SSSP: set when a distance would reach 2^32-1
+    float* acc;           // PageRank accumulator
+    const float* contrib; // PageRank x[u] / D_o(u)
+    uint32_t level_next;  // BFS: level given to vertices discovered this iteration
+};
+
+hipError_t launch_init(const AlgoState& s, uint64_t n, uint32_t source, float pr_x0, float* pr_x, uint32_t* cur,
+                       uint32_t nwords, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t st);
+
+hipError_t launch_stats_select(uint32_t npart, const uint32_t* pv, const uint64_t* off, const uint32_t* cur,
+                               const SelParams& sp, uint8_t* mode, uint32_t* nA, uint32_t* nF, uint64_t* Ea,
+                               uint64_t* Rq, uint64_t* K, hipStream_t st);
+
+hipError_t launch_scan(uint32_t npart, const uint8_t* mode, const uint32_t* nA, const uint32_t* nF,
+                       const uint64_t* Ea, const uint64_t* Rq, const uint64_t* K, uint32_t* lbase, uint64_t* wbase,
+                       Header* hdr, uint64_t* wpre, hipStream_t st);
+
+hipError_t launch_build_lists(uint32_t npart, const uint32_t* pv, const uint64_t* off, const uint32_t* cur,
+                              const uint8_t* mode, const uint32_t* lbase, const uint64_t* wbase, uint32_t* list,
+                              uint64_t* wpre, hipStream_t st);
+
+// Push over edge items [item_lo, item_hi) of list entries [ja, jb).  Edge e of vertex
+// list[j] is read at col[off[v] - shift + (item - wpre[j])]; with compacted = true it
+// is read at col[item - shift] (the compaction buffer starts at item `shift`).
+hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uint64_t* wpre, uint32_t ja,
+                             uint32_t jb, uint64_t item_lo, uint64_t item_hi, const uint64_t* off,
+                             const uint32_t* col, const uint32_t* w, uint64_t shift, bool compacted,
+                             hipStream_t st);
+
+// Push over 128-byte line items [item_lo, item_hi) of list entries [ja, jb), reading
+// the mapped host arrays col / w at absolute edge indices.
+hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uint64_t* wpre, uint32_t ja,
+                             uint32_t jb, uint64_t item_lo, uint64_t item_hi, const uint64_t* off,
+                             const uint32_t* col, const uint32_t* w, hipStream_t st);
+
+hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
+                             hipStream_t st);
+hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, hipStream_t st);
+
+hipError_t launch_select_only(uint64_t npart, const uint64_t* E, const uint64_t* nA, const uint64_t* Ea,
+                              const uint64_t* Rq, const SelParams& sp, uint8_t* p, hipStream_t st);
+
+}  // namespace hytm

@@ -1,0 +1,699 @@
+// Device side of the hybrid-transfer traversal, written for gfx950 (wave64).
+//
+// Per iteration (Sec. 4 overview, Algorithm 1):
+//   k_stats_select  one workgroup per partition: active vertices, active edges and
+//                   request lines from the frontier bitmap, then the engine choice of
+//                   Sec. 5.1 (Eq. 1-3, alpha/beta rule) in exact integer arithmetic;
+//   k_scan          one workgroup: per-engine prefix sums over partitions, which place
+//                   every partition's active vertices in one list ordered by engine
+//                   segment and partition ("pre-combine" of Vc and Vz, Algorithm 1);
+//   k_build_lists   one workgroup per scheduled partition: ordered compaction of its
+//                   active vertices into the list plus the work prefix (edges, or
+//                   128-byte lines for zero-copy) used for load balancing;
+//   k_push_edges    edge-balanced push over a list slice reading device memory
+//                   (resident cache, filter staging, or compaction buffer);
+//   k_push_lines    line-balanced push reading mapped pinned host memory: each half
+//                   wave loads one whole 128-byte line (merged, aligned zero-copy
+//                   access, Sec. 2.3 / Sec. 3.2);
+// with push operators for BFS, SSSP (atomicMin), CC (atomicMin on labels) and
+// PageRank (FP32 atomic add), and a bitmap-directed next frontier (Sec. 6.3).
+#include <hip/hip_runtime.h>
+
+#include "hytm_kernels.h"
+
+namespace hytm {
+namespace {
+
+constexpr uint32_t UNREACHED = 0xFFFFFFFFu;
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ uint64_t lines_of(uint64_t s, uint64_t e, uint32_t sh) {
+    // lines of 2^sh four-byte elements touched by elements [s, e), e > s
+    return ((e - 1) >> sh) - (s >> sh) + 1;
+}
+
+// ------------------------------------------------------------ reductions / scans
+__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+// Block-wide exclusive prefix sum of x (blockDim.x = NT, a multiple of 64).
+// lds must hold NT/64 uint64.  Returns the exclusive prefix; *total gets the sum.
+template <int NT>
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t x, uint64_t* lds, uint64_t* total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t y = __shfl_up(v, d, 64);
+        if (lane >= d) v += y;
+    }
+    if (lane == 63) lds[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+        uint64_t u = lane < NT / 64 ? lds[lane] : 0;
+#pragma unroll
+        for (int d = 1; d < NT / 64; d <<= 1) {
+            uint64_t y = __shfl_up(u, d, 64);
+            if (lane >= d) u += y;
+        }
+        if (lane < NT / 64) lds[lane] = u;
+    }
+    __syncthreads();
+    const uint64_t base = wid ? lds[wid - 1] : 0;
+    *total = lds[NT / 64 - 1];
+    __syncthreads();
+    return base + v - x;
+}
+
+template <int NT>
+__device__ __forceinline__ uint64_t block_sum(uint64_t x, uint64_t* lds) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    x = wave_sum(x);
+    if (lane == 0) lds[wid] = x;
+    __syncthreads();
+    uint64_t t = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; i++) t += lds[i];
+    __syncthreads();
+    return t;
+}
+
+// Bits of word wi restricted to vertices [vb, ve).
+__device__ __forceinline__ uint32_t masked_word(const uint32_t* bm, uint32_t wi, uint32_t vb, uint32_t ve) {
+    uint32_t bits = bm[wi];
+    const uint32_t lo = wi << 5;
+    if (lo < vb) bits &= ~0u << (vb - lo);
+    if (ve - lo < 32) bits &= (1u << (ve - lo)) - 1u;
+    return bits;
+}
+
+// ------------------------------------------------------------- engine selection
+// Sec. 5.1 with RTT = 1 and every comparison cleared of denominators:
+//   Tef = ceil(E*d1 / L), Tec = ceil((Ea*d1 + nA*d2) / L), Q = ceil(Rq / MR),
+//   Tiz = Q * (gn*E + (gd-gn)*Ea) / (gd*E)
+//   compaction iff ad*Tec < an*Tef  and  bd*gd*E*Tec < bn*Q*(gn*E + (gd-gn)*Ea);
+//   else zero-copy iff Q*(gn*E + (gd-gn)*Ea) < gd*E*Tef; else filter.
+__device__ __forceinline__ uint8_t select_engine(uint64_t E, uint64_t nA, uint64_t Ea, uint64_t Rq,
+                                                 const SelParams& sp) {
+    const uint64_t tef = (E * sp.d1 + sp.L - 1) / sp.L;
+    const uint64_t tec = (Ea * sp.d1 + nA * sp.d2 + sp.L - 1) / sp.L;
+    const uint64_t q = (Rq + sp.MR - 1) / sp.MR;
+    const u128 zfac = (u128)sp.gn * E + (u128)(sp.gd - sp.gn) * Ea;
+    const bool c1 = (u128)sp.ad * tec < (u128)sp.an * tef;
+    const bool c2 = (u128)sp.bd * sp.gd * E * tec < (u128)sp.bn * q * zfac;
+    if (c1 && c2 && sp.allow_compact) return P_COMPACT;
+    if ((u128)q * zfac < (u128)sp.gd * E * tef) return P_ZC;
+    return sp.allow_filter ? P_FILTER : P_ZC;
+}
+
+// ------------------------------------------------------------------- stats
+__global__ __launch_bounds__(256) void k_stats_select(uint32_t npart, const uint32_t* __restrict__ pv,
+                                                      const uint64_t* __restrict__ off,
+                                                      const uint32_t* __restrict__ cur, SelParams sp,
+                                                      uint8_t* __restrict__ mode, uint32_t* __restrict__ nA,
+                                                      uint32_t* __restrict__ nF, uint64_t* __restrict__ Ea,
+                                                      uint64_t* __restrict__ Rq, uint64_t* __restrict__ K) {
+    __shared__ uint64_t red[4];
+    for (uint32_t i = blockIdx.x; i < npart; i += gridDim.x) {
+        const uint32_t vb = pv[i], ve = pv[i + 1];
+        const uint32_t wb = vb >> 5, we = (ve + 31) >> 5;
+        uint64_t c = 0, f = 0, ea = 0, rq = 0, kl = 0;
+        for (uint32_t wi = wb + threadIdx.x; wi < we; wi += blockDim.x) {
+            uint32_t bits = masked_word(cur, wi, vb, ve);
+            f += __popc(bits);
+            while (bits) {
+                const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
+                bits &= bits - 1;
+                const uint64_t s = off[v], e = off[v + 1];
+                if (e > s) {
+                    c += 1;
+                    ea += e - s;
+                    rq += lines_of(s, e, sp.cost_shift);
+                    kl += lines_of(s, e, ZC_LINE_SHIFT);
+                }
+            }
+        }
+        c = block_sum<256>(c, red);
+        f = block_sum<256>(f, red);
+        ea = block_sum<256>(ea, red);
+        rq = block_sum<256>(rq, red) * sp.arrays;
+        kl = block_sum<256>(kl, red);
+        if (threadIdx.x == 0) {
+            const uint64_t E = off[ve] - off[vb];
+            uint8_t p;
+            if (ea == 0)
+                p = P_NONE;
+            else if (i < sp.nres)
+                p = P_RES;
+            else if (sp.force)
+                p = (uint8_t)sp.force;
+            else
+                p = select_engine(E, c, ea, rq, sp);
+            mode[i] = p;
+            nA[i] = (uint32_t)c;
+            nF[i] = (uint32_t)f;
+            Ea[i] = ea;
+            Rq[i] = rq;
+            K[i] = kl;
+        }
+    }
+}
+
+__global__ void k_select_only(uint64_t npart, const uint64_t* __restrict__ E, const uint64_t* __restrict__ nA,
+                              const uint64_t* __restrict__ Ea, const uint64_t* __restrict__ Rq, SelParams sp,
+                              uint8_t* __restrict__ p) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < npart;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint8_t r;
+        if (Ea[i] == 0)
+            r = P_NONE;
+        else if (i < sp.nres)
+            r = P_RES;
+        else if (sp.force)
+            r = (uint8_t)sp.force;
+        else
+            r = select_engine(E[i], nA[i], Ea[i], Rq[i], sp);
+        p[i] = r;
+    }
+}
+
+// -------------------------------------------------------------------- scan
+__global__ __launch_bounds__(1024) void k_scan(uint32_t npart, const uint8_t* __restrict__ mode,
+                                               const uint32_t* __restrict__ nA, const uint32_t* __restrict__ nF,
+                                               const uint64_t* __restrict__ Ea, const uint64_t* __restrict__ Rq,
+                                               const uint64_t* __restrict__ K, uint32_t* __restrict__ lbase,
+                                               uint64_t* __restrict__ wbase, Header* __restrict__ hdr,
+                                               uint64_t* __restrict__ wpre) {
+    __shared__ uint64_t lds[16];
+    const uint32_t per = (npart + 1023) / 1024;
+    const uint32_t i0 = min(threadIdx.x * per, npart), i1 = min(i0 + per, npart);
+    uint64_t cnt[NSEG] = {0, 0, 0, 0}, work[NSEG] = {0, 0, 0, 0}, parts[NSEG] = {0, 0, 0, 0};
+    uint64_t edges[NSEG] = {0, 0, 0, 0}, cl[NSEG] = {0, 0, 0, 0}, fr = 0;
+    for (uint32_t i = i0; i < i1; i++) {
+        fr += nF[i];
+        const uint8_t m = mode[i];
+        if (m == P_NONE) continue;
+#pragma unroll
+        for (int s = 0; s < NSEG; s++) {
+            if (m != s + 1) continue;
+            parts[s] += 1;
+            cnt[s] += nA[i];
+            work[s] += (m == P_ZC) ? K[i] : Ea[i];
+            edges[s] += Ea[i];
+            cl[s] += Rq[i];
+        }
+    }
+    uint64_t ex_cnt[NSEG], ex_work[NSEG], tot_cnt[NSEG], tot_work[NSEG], tot_parts[NSEG], tot_edges[NSEG],
+        tot_cl[NSEG];
+#pragma unroll
+    for (int s = 0; s < NSEG; s++) {
+        ex_cnt[s] = block_exclusive_scan<1024>(cnt[s], lds, &tot_cnt[s]);
+        ex_work[s] = block_exclusive_scan<1024>(work[s], lds, &tot_work[s]);
+        tot_parts[s] = block_sum<1024>(parts[s], lds);
+        tot_edges[s] = block_sum<1024>(edges[s], lds);
+        tot_cl[s] = block_sum<1024>(cl[s], lds);
+    }
+    const uint64_t tot_fr = block_sum<1024>(fr, lds);
+    uint64_t lstart[NSEG], wstart[NSEG];
+    uint64_t la = 0, wa = 0;
+#pragma unroll
+    for (int s = 0; s < NSEG; s++) {
+        lstart[s] = la;
+        wstart[s] = wa;
+        la += tot_cnt[s];
+        wa += tot_work[s];
+    }
+    uint64_t runc[NSEG], runw[NSEG];
+#pragma unroll
+    for (int s = 0; s < NSEG; s++) {
+        runc[s] = lstart[s] + ex_cnt[s];
+        runw[s] = wstart[s] + ex_work[s];
+    }
+    for (uint32_t i = i0; i < i1; i++) {
+        const uint8_t m = mode[i];
+        uint32_t lb = 0xFFFFFFFFu;
+        uint64_t wb = ~0ull;
+#pragma unroll
+        for (int s = 0; s < NSEG; s++) {
+            if (m != s + 1) continue;
+            lb = (uint32_t)runc[s];
+            wb = runw[s];
+            runc[s] += nA[i];
+            runw[s] += (m == P_ZC) ? K[i] : Ea[i];
+        }
+        lbase[i] = lb;
+        wbase[i] = wb;
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s < NSEG; s++) {
+            hdr->seg_parts[s] = (uint32_t)tot_parts[s];
+            hdr->seg_list_start[s] = (uint32_t)lstart[s];
+            hdr->seg_list_count[s] = (uint32_t)tot_cnt[s];
+            hdr->seg_work_start[s] = wstart[s];
+            hdr->seg_work_total[s] = tot_work[s];
+            hdr->seg_edges[s] = tot_edges[s];
+            hdr->seg_cost_lines[s] = tot_cl[s];
+        }
+        hdr->total_active = la;
+        hdr->frontier = tot_fr;
+        wpre[la] = wa;
+    }
+}
+
+// ------------------------------------------------------------------ lists
+__global__ __launch_bounds__(256) void k_build_lists(uint32_t npart, const uint32_t* __restrict__ pv,
+                                                     const uint64_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ cur,
+                                                     const uint8_t* __restrict__ mode,
+                                                     const uint32_t* __restrict__ lbase,
+                                                     const uint64_t* __restrict__ wbase,
+                                                     uint32_t* __restrict__ list, uint64_t* __restrict__ wpre) {
+    __shared__ uint64_t lds[4];
+    for (uint32_t i = blockIdx.x; i < npart; i += gridDim.x) {
+        const uint8_t m = mode[i];
+        if (m == P_NONE) continue;
+        const bool by_lines = m == P_ZC;
+        const uint32_t vb = pv[i], ve = pv[i + 1];
+        const uint32_t wb = vb >> 5, we = (ve + 31) >> 5;
+        const uint32_t per = (we - wb + blockDim.x - 1) / blockDim.x;
+        const uint32_t w0 = min(wb + threadIdx.x * per, we), w1 = min(w0 + per, we);
+        uint64_t c = 0, wk = 0;
+        for (uint32_t wi = w0; wi < w1; wi++) {
+            uint32_t bits = masked_word(cur, wi, vb, ve);
+            while (bits) {
+                const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
+                bits &= bits - 1;
+                const uint64_t s = off[v], e = off[v + 1];
+                if (e > s) {
+                    c += 1;
+                    wk += by_lines ? lines_of(s, e, ZC_LINE_SHIFT) : e - s;
+                }
+            }
+        }
+        uint64_t tc, tw;
+        uint64_t pos = lbase[i] + block_exclusive_scan<256>(c, lds, &tc);
+        uint64_t wp = wbase[i] + block_exclusive_scan<256>(wk, lds, &tw);
+        for (uint32_t wi = w0; wi < w1; wi++) {
+            uint32_t bits = masked_word(cur, wi, vb, ve);
+            while (bits) {
+                const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
+                bits &= bits - 1;
+                const uint64_t s = off[v], e = off[v + 1];
+                if (e > s) {
+                    list[pos] = v;
+                    wpre[pos] = wp;
+                    pos++;
+                    wp += by_lines ? lines_of(s, e, ZC_LINE_SHIFT) : e - s;
+                }
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------- operators
+// src(u): the value u pushes (read when the workgroup stages its vertices; it may
+// already reflect updates made earlier in the same iteration, which only helps the
+// monotone operators).  push(value, v, w): relax edge (u, v) with weight w.
+struct OpBfs {
+    static constexpr bool weighted = false;
+    uint32_t* visited;
+    uint32_t* next;
+    uint32_t* lvl;
+    uint32_t level_next;
+    __device__ __forceinline__ uint32_t src(uint32_t) const { return 0; }
+    __device__ __forceinline__ void push(uint32_t, uint32_t v, uint32_t) const {
+        const uint32_t bit = 1u << (v & 31);
+        uint32_t* wp = visited + (v >> 5);
+        if (__builtin_nontemporal_load(wp) & bit) return;
+        const uint32_t old = atomicOr(wp, bit);
+        if (!(old & bit)) {  // exactly one thread discovers v
+            lvl[v] = level_next;
+            atomicOr(next + (v >> 5), bit);
+        }
+    }
+};
+
+struct OpSssp {
+    static constexpr bool weighted = true;
+    uint32_t* dist;
+    uint32_t* next;
+    uint32_t* overflow;
+    __device__ __forceinline__ uint32_t src(uint32_t u) const { return dist[u]; }
+    __device__ __forceinline__ void push(uint32_t du, uint32_t v, uint32_t w) const {
+        const uint64_t nd = (uint64_t)du + w;
+        if (nd >= UNREACHED) {
+            *overflow = 1u;
+            return;
+        }
+        if ((uint32_t)nd < dist[v]) {
+            const uint32_t old = atomicMin(dist + v, (uint32_t)nd);
+            if ((uint32_t)nd < old) atomicOr(next + (v >> 5), 1u << (v & 31));
+        }
+    }
+};
+
+struct OpCc {
+    static constexpr bool weighted = false;
+    uint32_t* lab;
+    uint32_t* next;
+    __device__ __forceinline__ uint32_t src(uint32_t u) const { return lab[u]; }
+    __device__ __forceinline__ void push(uint32_t lu, uint32_t v, uint32_t) const {
+        if (lu < lab[v]) {
+            const uint32_t old = atomicMin(lab + v, lu);
+            if (lu < old) atomicOr(next + (v >> 5), 1u << (v & 31));
+        }
+    }
+};
+
+struct OpPr {
+    static constexpr bool weighted = false;
+    float* acc;
+    const float* contrib;
+    __device__ __forceinline__ uint32_t src(uint32_t u) const { return __float_as_uint(contrib[u]); }
+    __device__ __forceinline__ void push(uint32_t c, uint32_t v, uint32_t) const {
+        unsafeAtomicAdd(acc + v, __uint_as_float(c));
+    }
+};
+
+// Largest j in [lo, hi) with a[j] <= x, given a[lo] <= x and a non-decreasing.
+__device__ __forceinline__ uint32_t search_le(const uint64_t* a, uint32_t lo, uint32_t hi, uint64_t x) {
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (a[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------- edge push
+constexpr int EDGE_THREADS = 256;
+constexpr int EDGE_IPB = 1024;  // edge items per workgroup pass
+
+template <class Op, bool COMPACTED>
+__global__ __launch_bounds__(EDGE_THREADS) void k_push_edges(const uint32_t* __restrict__ list,
+                                                             const uint64_t* __restrict__ wpre, uint32_t ja,
+                                                             uint32_t jb, uint64_t item_lo, uint64_t item_hi,
+                                                             const uint64_t* __restrict__ off,
+                                                             const uint32_t* __restrict__ col,
+                                                             const uint32_t* __restrict__ w, uint64_t shift,
+                                                             Op op) {
+    __shared__ uint64_t s_pre[EDGE_IPB];
+    __shared__ uint64_t s_st[EDGE_IPB];
+    __shared__ uint32_t s_val[EDGE_IPB];
+    __shared__ uint32_t s_j0, s_nv;
+    for (uint64_t blk = blockIdx.x;; blk += gridDim.x) {
+        const uint64_t i0 = item_lo + blk * EDGE_IPB;
+        if (i0 >= item_hi) break;
+        const uint64_t i1 = min(i0 + (uint64_t)EDGE_IPB, item_hi);
+        if (threadIdx.x == 0) {
+            const uint32_t j0 = search_le(wpre, ja, jb, i0);
+            const uint32_t j1 = search_le(wpre, j0, jb, i1 - 1);
+            s_j0 = j0;
+            s_nv = j1 - j0 + 1;
+        }
+        __syncthreads();
+        const uint32_t j0 = s_j0, nv = s_nv;
+        for (uint32_t k = threadIdx.x; k < nv; k += EDGE_THREADS) {
+            const uint32_t v = list[j0 + k];
+            const uint64_t pre = wpre[j0 + k];
+            s_pre[k] = pre;
+            s_st[k] = (COMPACTED ? pre : off[v]) - shift;
+            s_val[k] = op.src(v);
+        }
+        __syncthreads();
+        for (uint64_t i = i0 + threadIdx.x; i < i1; i += EDGE_THREADS) {
+            uint32_t lo = 0, hi = nv;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_pre[mid] <= i)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const uint64_t e = s_st[lo] + (i - s_pre[lo]);
+            const uint32_t v = col[e];
+            const uint32_t wt = Op::weighted ? w[e] : 0u;
+            op.push(s_val[lo], v, wt);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------- line push
+constexpr int LINE_THREADS = 256;
+constexpr int LINE_HALVES = LINE_THREADS / 32;  // half waves per workgroup
+constexpr int LINE_UNROLL = 8;                  // lines per half wave per pass
+constexpr int LINE_IPB = LINE_HALVES * LINE_UNROLL;
+
+template <class Op>
+__global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __restrict__ list,
+                                                             const uint64_t* __restrict__ wpre, uint32_t ja,
+                                                             uint32_t jb, uint64_t item_lo, uint64_t item_hi,
+                                                             const uint64_t* __restrict__ off,
+                                                             const uint32_t* __restrict__ col,
+                                                             const uint32_t* __restrict__ w, Op op) {
+    __shared__ uint64_t s_pre[LINE_IPB];
+    __shared__ uint64_t s_s[LINE_IPB];
+    __shared__ uint64_t s_e[LINE_IPB];
+    __shared__ uint32_t s_val[LINE_IPB];
+    __shared__ uint32_t s_j0, s_nv;
+    const uint32_t half = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    for (uint64_t blk = blockIdx.x;; blk += gridDim.x) {
+        const uint64_t i0 = item_lo + blk * LINE_IPB;
+        if (i0 >= item_hi) break;
+        const uint64_t i1 = min(i0 + (uint64_t)LINE_IPB, item_hi);
+        if (threadIdx.x == 0) {
+            const uint32_t j0 = search_le(wpre, ja, jb, i0);
+            const uint32_t j1 = search_le(wpre, j0, jb, i1 - 1);
+            s_j0 = j0;
+            s_nv = j1 - j0 + 1;
+        }
+        __syncthreads();
+        const uint32_t j0 = s_j0, nv = s_nv;
+        for (uint32_t k = threadIdx.x; k < nv; k += LINE_THREADS) {
+            const uint32_t v = list[j0 + k];
+            s_pre[k] = wpre[j0 + k];
+            s_s[k] = off[v];
+            s_e[k] = off[v + 1];
+            s_val[k] = op.src(v);
+        }
+        __syncthreads();
+        uint32_t cv[LINE_UNROLL], wv[LINE_UNROLL], kk[LINE_UNROLL];
+        bool ok[LINE_UNROLL];
+#pragma unroll
+        for (int r = 0; r < LINE_UNROLL; r++) {
+            const uint64_t i = i0 + half + (uint64_t)LINE_HALVES * r;
+            ok[r] = false;
+            kk[r] = 0;
+            cv[r] = 0;
+            wv[r] = 0;
+            if (i < i1) {
+                uint32_t lo = 0, hi = nv;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (s_pre[mid] <= i)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                const uint64_t s = s_s[lo];
+                const uint64_t e = ((s >> ZC_LINE_SHIFT) << ZC_LINE_SHIFT) + ((i - s_pre[lo]) << ZC_LINE_SHIFT) + lane;
+                if (e >= s && e < s_e[lo]) {
+                    ok[r] = true;
+                    kk[r] = lo;
+                    cv[r] = col[e];
+                    if (Op::weighted) wv[r] = w[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < LINE_UNROLL; r++)
+            if (ok[r]) op.push(s_val[kk[r]], cv[r], wv[r]);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------- init etc.
+__global__ void k_init(AlgoState s, uint64_t n, uint32_t source, float x0, float* __restrict__ x,
+                       uint32_t* __restrict__ cur, uint32_t nwords) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+        if (s.algo == ALGO_PR)
+            x[v] = x0;
+        else if (s.algo == ALGO_CC)
+            s.val[v] = (uint32_t)v;
+        else
+            s.val[v] = v == source ? 0u : UNREACHED;
+    }
+    for (uint64_t wi = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; wi < nwords; wi += stride) {
+        uint32_t c;
+        if (s.algo == ALGO_BFS || s.algo == ALGO_SSSP) {
+            c = (wi == (source >> 5)) ? (1u << (source & 31)) : 0u;
+        } else {
+            const uint64_t lo = wi << 5;
+            c = lo + 32 <= n ? ~0u : (lo < n ? (1u << (uint32_t)(n - lo)) - 1u : 0u);
+        }
+        cur[wi] = c;
+        if (s.next) s.next[wi] = 0;
+        if (s.visited) s.visited[wi] = s.algo == ALGO_BFS ? c : 0u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && s.overflow) *s.overflow = 0;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t value) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_pr_prepare(uint64_t n, const uint64_t* __restrict__ off, const float* __restrict__ x,
+                             float* __restrict__ contrib, float* __restrict__ acc) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t d = off[v + 1] - off[v];
+        contrib[v] = d ? x[v] / (float)d : 0.0f;
+        acc[v] = 0.0f;
+    }
+}
+
+__global__ void k_pr_apply(uint64_t n, float* __restrict__ x, const float* __restrict__ acc, float base,
+                           float damping) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * blockDim.x)
+        x[v] = base + damping * acc[v];
+}
+
+inline unsigned grid_for(uint64_t items, unsigned per_block, unsigned cap) {
+    uint64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return (unsigned)(g < cap ? g : cap);
+}
+
+constexpr unsigned GRID_CAP = 1u << 16;
+
+}  // namespace
+
+hipError_t launch_init(const AlgoState& s, uint64_t n, uint32_t source, float pr_x0, float* pr_x, uint32_t* cur,
+                       uint32_t nwords, hipStream_t st) {
+    k_init<<<grid_for(n > nwords ? n : nwords, 256, 8192), 256, 0, st>>>(s, n, source, pr_x0, pr_x, cur, nwords);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t st) {
+    if (!count) return hipSuccess;
+    k_fill_u32<<<grid_for(count, 256, 8192), 256, 0, st>>>(p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_select(uint32_t npart, const uint32_t* pv, const uint64_t* off, const uint32_t* cur,
+                               const SelParams& sp, uint8_t* mode, uint32_t* nA, uint32_t* nF, uint64_t* Ea,
+                               uint64_t* Rq, uint64_t* K, hipStream_t st) {
+    if (!npart) return hipSuccess;
+    k_stats_select<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, sp, mode, nA, nF, Ea,
+                                                                         Rq, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(uint32_t npart, const uint8_t* mode, const uint32_t* nA, const uint32_t* nF,
+                       const uint64_t* Ea, const uint64_t* Rq, const uint64_t* K, uint32_t* lbase, uint64_t* wbase,
+                       Header* hdr, uint64_t* wpre, hipStream_t st) {
+    k_scan<<<1, 1024, 0, st>>>(npart, mode, nA, nF, Ea, Rq, K, lbase, wbase, hdr, wpre);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_lists(uint32_t npart, const uint32_t* pv, const uint64_t* off, const uint32_t* cur,
+                              const uint8_t* mode, const uint32_t* lbase, const uint64_t* wbase, uint32_t* list,
+                              uint64_t* wpre, hipStream_t st) {
+    if (!npart) return hipSuccess;
+    k_build_lists<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, mode, lbase, wbase,
+                                                                        list, wpre);
+    return hipGetLastError();
+}
+
+template <class Op>
+static hipError_t push_edges_op(const Op& op, const uint32_t* list, const uint64_t* wpre, uint32_t ja, uint32_t jb,
+                                uint64_t lo, uint64_t hi, const uint64_t* off, const uint32_t* col,
+                                const uint32_t* w, uint64_t shift, bool compacted, hipStream_t st) {
+    const unsigned g = grid_for(hi - lo, EDGE_IPB, GRID_CAP);
+    if (compacted)
+        k_push_edges<Op, true><<<g, EDGE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, shift, op);
+    else
+        k_push_edges<Op, false><<<g, EDGE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, shift, op);
+    return hipGetLastError();
+}
+
+hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uint64_t* wpre, uint32_t ja,
+                             uint32_t jb, uint64_t item_lo, uint64_t item_hi, const uint64_t* off,
+                             const uint32_t* col, const uint32_t* w, uint64_t shift, bool compacted,
+                             hipStream_t st) {
+    if (item_hi <= item_lo || jb <= ja) return hipSuccess;
+    switch (s.algo) {
+    case ALGO_BFS:
+        return push_edges_op(OpBfs{s.visited, s.next, s.val, s.level_next}, list, wpre, ja, jb, item_lo, item_hi,
+                             off, col, w, shift, compacted, st);
+    case ALGO_SSSP:
+        return push_edges_op(OpSssp{s.val, s.next, s.overflow}, list, wpre, ja, jb, item_lo, item_hi, off, col, w,
+                             shift, compacted, st);
+    case ALGO_CC:
+        return push_edges_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
+                             compacted, st);
+    default:
+        return push_edges_op(OpPr{s.acc, s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
+                             compacted, st);
+    }
+}
+
+template <class Op>
+static hipError_t push_lines_op(const Op& op, const uint32_t* list, const uint64_t* wpre, uint32_t ja, uint32_t jb,
+                                uint64_t lo, uint64_t hi, const uint64_t* off, const uint32_t* col,
+                                const uint32_t* w, hipStream_t st) {
+    const unsigned g = grid_for(hi - lo, LINE_IPB, GRID_CAP);
+    k_push_lines<Op><<<g, LINE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, op);
+    return hipGetLastError();
+}
+
+hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uint64_t* wpre, uint32_t ja,
+                             uint32_t jb, uint64_t item_lo, uint64_t item_hi, const uint64_t* off,
+                             const uint32_t* col, const uint32_t* w, hipStream_t st) {
+    if (item_hi <= item_lo || jb <= ja) return hipSuccess;
+    switch (s.algo) {
+    case ALGO_BFS:
+        return push_lines_op(OpBfs{s.visited, s.next, s.val, s.level_next}, list, wpre, ja, jb, item_lo, item_hi,
+                             off, col, w, st);
+    case ALGO_SSSP:
+        return push_lines_op(OpSssp{s.val, s.next, s.overflow}, list, wpre, ja, jb, item_lo, item_hi, off, col, w,
+                             st);
+    case ALGO_CC:
+        return push_lines_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
+    default:
+        return push_lines_op(OpPr{s.acc, s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
+    }
+}
+
+hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
+                             hipStream_t st) {
+    if (!n) return hipSuccess;
+    k_pr_prepare<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, off, x, contrib, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, hipStream_t st) {
+    if (!n) return hipSuccess;
+    k_pr_apply<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, x, acc, base, damping);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_only(uint64_t npart, const uint64_t* E, const uint64_t* nA, const uint64_t* Ea,
+                              const uint64_t* Rq, const SelParams& sp, uint8_t* p, hipStream_t st) {
+    if (!npart) return hipSuccess;
+    k_select_only<<<grid_for(npart, 256, 4096), 256, 0, st>>>(npart, E, nA, Ea, Rq, sp, p);
+    return hipGetLastError();
+}
+
+}  // namespace hytm

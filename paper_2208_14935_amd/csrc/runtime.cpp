@@ -1,0 +1,1035 @@
+// Host runtime of libhytm.so: the C ABI declared in include/hytm.h.
+//
+// One handle = one CSR graph bound to one GPU.  Placement follows Sec. 1 / Sec. 4 of
+// the paper: offsets (the neighbour index), vertex values and frontiers live in device
+// memory; neighbour and weight arrays live in pinned host memory mapped into the GPU
+// address space.  Each iteration of hytm_run:
+//   1. the GPU computes per-partition statistics, selects an engine per partition
+//      (Sec. 5.1) and lays the active vertices out by engine (Algorithm 1);
+//   2. the host copies back the selection, combines consecutive filter partitions into
+//      tasks (Sec. 5.2) and issues, concurrently (Sec. 6.2):
+//        - resident partitions: push kernel on the main stream;
+//        - zero-copy: one push kernel over all zero-copy vertices (mapped host reads);
+//        - filter tasks: H2D copy into a ring of staging slots, then a push kernel;
+//        - compaction: a host thread pool gathers the active neighbour lists into
+//          pinned buffers in chunks, each copied and pushed while the next is
+//          gathered (Sec. 6.3);
+//   3. the main stream waits for every engine; the next frontier becomes current.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/hytm.h"
+#include "hytm_kernels.h"
+#include "pool.h"
+
+using namespace hytm;
+
+namespace {
+
+thread_local std::string g_err;
+
+hytm_status fail(hytm_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+struct HipError {
+    hytm_status status;
+};
+
+#define HIP_CHECK(expr)                                                                                   \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess) {                                                                           \
+            fail(e_ == hipErrorOutOfMemory ? HYTM_E_NOMEM : HYTM_E_DEVICE, "%s failed: %s (%s:%d)", #expr, \
+                 hipGetErrorString(e_), __FILE__, __LINE__);                                              \
+            throw HipError{e_ == hipErrorOutOfMemory ? HYTM_E_NOMEM : HYTM_E_DEVICE};                    \
+        }                                                                                                 \
+    } while (0)
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------ device buffer
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void ensure(size_t count) {
+        if (count <= n && p) return;
+        release();
+        HIP_CHECK(hipMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T)));
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+template <class T>
+struct HostBuf {  // pinned host memory
+    T* p = nullptr;
+    size_t n = 0;
+    void ensure(size_t count) {
+        if (count <= n && p) return;
+        release();
+        HIP_CHECK(hipHostMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+constexpr uint32_t kMaxSlots = 16;
+
+}  // namespace
+
+struct hytm_graph {
+    int device = 0;
+    uint64_t n = 0, m = 0;
+    uint32_t flags = 0;
+    hytm_params params{};
+    uint64_t budget = UINT64_MAX;
+
+    // host side
+    std::vector<uint64_t> h_off;      // n + 1
+    uint32_t* h_col = nullptr;        // pinned, device-mapped
+    uint32_t* h_w = nullptr;          // pinned, device-mapped, or null
+    uint32_t* d_col_map = nullptr;    // device addresses of the mapped arrays
+    uint32_t* d_w_map = nullptr;
+
+    // partitions
+    std::vector<uint32_t> pv;         // npart + 1 vertex bounds
+    std::vector<uint64_t> pE;         // edges per partition
+    uint32_t npart = 0;
+    uint64_t max_part_edges = 0;
+    DevBuf<uint32_t> d_pv;
+    DevBuf<uint64_t> d_off;
+
+    // per-vertex / per-partition device state
+    DevBuf<uint32_t> d_val, d_cur, d_next, d_visited, d_list, d_overflow;
+    DevBuf<float> d_x, d_contrib, d_acc;
+    DevBuf<uint64_t> d_wpre, d_Ea, d_Rq, d_K, d_wbase;
+    DevBuf<uint32_t> d_nA, d_nF, d_lbase;
+    DevBuf<uint8_t> d_mode;
+    DevBuf<Header> d_hdr;
+    DevBuf<uint64_t> d_sel_in;  // hytm_select_engines scratch
+    DevBuf<uint8_t> d_sel_out;
+
+    // host mirrors of the per-iteration selection
+    HostBuf<Header> h_hdr;
+    HostBuf<uint8_t> h_mode;
+    HostBuf<uint32_t> h_lbase;
+    HostBuf<uint64_t> h_wbase;
+    HostBuf<uint32_t> h_clist;
+    HostBuf<uint64_t> h_cwpre;
+
+    // edge-budget buffers
+    uint32_t res_parts = 0, res_arrays = 0;
+    uint64_t res_edges = 0;
+    bool res_valid = false;
+    DevBuf<uint32_t> d_res_col, d_res_w;
+    DevBuf<uint32_t> d_slot_col[kMaxSlots], d_slot_w[kMaxSlots];
+    DevBuf<uint32_t> d_cbuf_col[2], d_cbuf_w[2];
+    HostBuf<uint32_t> h_cbuf_col[2], h_cbuf_w[2];
+
+    // streams / events
+    hipStream_t s_main = nullptr, s_copy = nullptr, s_fk = nullptr, s_zc = nullptr, s_c = nullptr;
+    hipEvent_t ev_copied[kMaxSlots] = {}, ev_free[kMaxSlots] = {};
+    hipEvent_t ev_cdone[2] = {}, ev_join[4] = {}, ev_start = nullptr, ev_clist = nullptr;
+
+    Pool* pool = nullptr;
+};
+
+namespace {
+
+bool params_valid(const hytm_params& p, std::string* why) {
+    auto bad = [&](const char* s) {
+        *why = s;
+        return false;
+    };
+    if (p.mode < HYTM_MODE_HYBRID || p.mode > HYTM_MODE_ZEROCOPY) return bad("mode out of range");
+    if (p.partition_edges == 0) return bad("partition_edges must be > 0");
+    if (p.combine_k == 0) return bad("combine_k must be > 0");
+    auto frac_ok = [](uint32_t a, uint32_t b, bool le1) { return b > 0 && b <= 65536 && a <= 65536 && (!le1 || a <= b); };
+    if (!frac_ok(p.alpha_num, p.alpha_den, false)) return bad("alpha must be num/den with den in 1..65536");
+    if (!frac_ok(p.beta_num, p.beta_den, false)) return bad("beta must be num/den with den in 1..65536");
+    if (!frac_ok(p.gamma_num, p.gamma_den, true)) return bad("gamma must be in [0, 1] with den in 1..65536");
+    if (p.line_bytes < 4 || (p.line_bytes & (p.line_bytes - 1))) return bad("line_bytes must be a power of two >= 4");
+    if (p.max_outstanding == 0) return bad("max_outstanding must be > 0");
+    if (p.index_bytes > 64) return bad("index_bytes must be <= 64");
+    if (!(p.pr_damping >= 0.0 && p.pr_damping <= 1.0)) return bad("pr_damping must be in [0, 1]");
+    if (p.streams < 2 || p.streams > kMaxSlots) return bad("streams must be in 2..16");
+    if (p.gather_threads > 256) return bad("gather_threads must be <= 256");
+    return true;
+}
+
+// Greedy chunk partitioning (Sec. 4): walk vertices in order and close the current
+// partition before v when it already holds an edge and D_o(v) would take it past the
+// target; an oversize vertex therefore forms a partition of its own.
+void partition_graph(hytm_graph* g) {
+    const uint64_t target = g->params.partition_edges;
+    g->pv.clear();
+    g->pE.clear();
+    g->pv.push_back(0);
+    uint64_t edges = 0;
+    for (uint64_t v = 0; v < g->n; v++) {
+        const uint64_t d = g->h_off[v + 1] - g->h_off[v];
+        if (edges > 0 && edges + d > target) {
+            g->pv.push_back((uint32_t)v);
+            g->pE.push_back(edges);
+            edges = 0;
+        }
+        edges += d;
+    }
+    g->pv.push_back((uint32_t)g->n);
+    g->pE.push_back(edges);
+    g->npart = (uint32_t)g->pE.size();
+    g->max_part_edges = 0;
+    for (uint64_t e : g->pE) g->max_part_edges = std::max(g->max_part_edges, e);
+    g->d_pv.ensure(g->pv.size());
+    HIP_CHECK(hipMemcpy(g->d_pv.p, g->pv.data(), g->pv.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    g->res_valid = false;
+}
+
+SelParams make_sel(const hytm_graph* g, uint32_t arrays) {
+    const hytm_params& p = g->params;
+    SelParams sp{};
+    sp.L = (uint64_t)p.line_bytes * p.max_outstanding;
+    sp.MR = p.max_outstanding;
+    sp.d1 = 4 * arrays;
+    sp.d2 = p.index_bytes;
+    sp.an = p.alpha_num;
+    sp.ad = p.alpha_den;
+    sp.bn = p.beta_num;
+    sp.bd = p.beta_den;
+    sp.gn = p.gamma_num;
+    sp.gd = p.gamma_den;
+    uint32_t sh = 0;
+    while ((4u << sh) < p.line_bytes) sh++;
+    sp.cost_shift = sh;
+    sp.arrays = arrays;
+    sp.force = p.mode == HYTM_MODE_FILTER ? P_FILTER
+               : p.mode == HYTM_MODE_COMPACT ? P_COMPACT
+               : p.mode == HYTM_MODE_ZEROCOPY ? P_ZC
+                                              : 0;
+    sp.allow_filter = 1;
+    sp.allow_compact = 1;
+    return sp;
+}
+
+// Split of the edge budget (reading of the paper's placement: the budget covers only
+// edge-associated device memory).
+struct Plan {
+    uint32_t nres = 0;
+    uint64_t res_edges = 0;
+    uint64_t slot_edges = 0;
+    uint32_t nslots = 0;
+    uint64_t cchunk = 0;
+    bool allow_filter = false, allow_compact = false;
+};
+
+// Edge-budget bytes the engines' buffers take: filter = `streams` staging slots, each
+// holding the largest combined task; compaction = two chunk buffers.
+struct Staging {
+    uint64_t slot_edges, cchunk, f_bytes, c_bytes;
+};
+Staging staging_of(const hytm_graph* g, uint32_t arrays) {
+    const hytm_params& p = g->params;
+    const uint64_t d1 = 4ull * arrays;
+    Staging s;
+    s.slot_edges = std::max<uint64_t>((uint64_t)p.combine_k * p.partition_edges, g->max_part_edges);
+    s.cchunk = p.compact_chunk_edges ? p.compact_chunk_edges : std::max<uint64_t>(s.slot_edges, 1ull << 22);
+    s.f_bytes = s.slot_edges * p.streams * d1;
+    s.c_bytes = 2 * s.cchunk * d1;
+    return s;
+}
+
+hytm_status make_plan(const hytm_graph* g, uint32_t arrays, Plan* out) {
+    const hytm_params& p = g->params;
+    const uint64_t d1 = 4ull * arrays;
+    Plan pl;
+    if (g->budget == UINT64_MAX) {
+        pl.nres = g->npart;
+        pl.res_edges = g->m;
+        *out = pl;
+        return HYTM_OK;
+    }
+    const uint64_t B = g->budget;
+    const Staging sg = staging_of(g, arrays);
+    pl.slot_edges = sg.slot_edges;
+    pl.nslots = p.streams;
+    pl.cchunk = sg.cchunk;
+    uint64_t used = 0;
+    switch (p.mode) {
+    case HYTM_MODE_FILTER:
+        if (sg.f_bytes > B)
+            return fail(HYTM_E_BUDGET, "filter staging needs %llu bytes (%u slots x %llu edges), budget is %llu",
+                        (unsigned long long)sg.f_bytes, pl.nslots, (unsigned long long)pl.slot_edges,
+                        (unsigned long long)B);
+        pl.allow_filter = true;
+        used = sg.f_bytes;
+        break;
+    case HYTM_MODE_COMPACT:
+        if (sg.c_bytes > B)
+            return fail(HYTM_E_BUDGET, "compaction buffers need %llu bytes (2 x %llu edges), budget is %llu",
+                        (unsigned long long)sg.c_bytes, (unsigned long long)pl.cchunk, (unsigned long long)B);
+        pl.allow_compact = true;
+        used = sg.c_bytes;
+        break;
+    case HYTM_MODE_ZEROCOPY:
+        break;
+    default:  // hybrid: an engine whose staging does not fit is left out of the choice
+        if (sg.f_bytes + sg.c_bytes <= B) {
+            pl.allow_filter = pl.allow_compact = true;
+            used = sg.f_bytes + sg.c_bytes;
+        } else if (sg.f_bytes <= B) {
+            pl.allow_filter = true;
+            used = sg.f_bytes;
+        } else if (sg.c_bytes <= B) {
+            pl.allow_compact = true;
+            used = sg.c_bytes;
+        }
+    }
+    const uint64_t res_bytes = B - used;
+    uint32_t nres = 0;
+    uint64_t edges = 0;
+    while (nres < g->npart && (edges + g->pE[nres]) * d1 <= res_bytes) edges += g->pE[nres++];
+    pl.nres = nres;
+    pl.res_edges = edges;
+    *out = pl;
+    return HYTM_OK;
+}
+
+void ensure_streams(hytm_graph* g) {
+    if (g->s_copy) return;
+    HIP_CHECK(hipStreamCreateWithFlags(&g->s_main, hipStreamNonBlocking));
+    HIP_CHECK(hipStreamCreateWithFlags(&g->s_copy, hipStreamNonBlocking));
+    HIP_CHECK(hipStreamCreateWithFlags(&g->s_fk, hipStreamNonBlocking));
+    HIP_CHECK(hipStreamCreateWithFlags(&g->s_zc, hipStreamNonBlocking));
+    HIP_CHECK(hipStreamCreateWithFlags(&g->s_c, hipStreamNonBlocking));
+    for (uint32_t i = 0; i < kMaxSlots; i++) {
+        HIP_CHECK(hipEventCreateWithFlags(&g->ev_copied[i], hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&g->ev_free[i], hipEventDisableTiming));
+    }
+    for (auto& e : g->ev_cdone) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& e : g->ev_join) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&g->ev_start, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&g->ev_clist, hipEventDisableTiming));
+}
+
+void release_all(hytm_graph* g) {
+    if (g->s_copy) (void)hipDeviceSynchronize();
+    for (auto* b : {&g->d_val, &g->d_cur, &g->d_next, &g->d_visited, &g->d_list, &g->d_overflow, &g->d_nA, &g->d_nF,
+                    &g->d_lbase, &g->d_pv, &g->d_res_col, &g->d_res_w})
+        b->release();
+    for (auto* b : {&g->d_x, &g->d_contrib, &g->d_acc}) b->release();
+    for (auto* b : {&g->d_wpre, &g->d_Ea, &g->d_Rq, &g->d_K, &g->d_wbase, &g->d_off, &g->d_sel_in}) b->release();
+    g->d_mode.release();
+    g->d_sel_out.release();
+    g->d_hdr.release();
+    for (uint32_t i = 0; i < kMaxSlots; i++) {
+        g->d_slot_col[i].release();
+        g->d_slot_w[i].release();
+    }
+    for (int i = 0; i < 2; i++) {
+        g->d_cbuf_col[i].release();
+        g->d_cbuf_w[i].release();
+        g->h_cbuf_col[i].release();
+        g->h_cbuf_w[i].release();
+    }
+    g->h_hdr.release();
+    g->h_mode.release();
+    g->h_lbase.release();
+    g->h_wbase.release();
+    g->h_clist.release();
+    g->h_cwpre.release();
+    if (g->h_col) (void)hipHostFree(g->h_col);
+    if (g->h_w) (void)hipHostFree(g->h_w);
+    g->h_col = g->h_w = nullptr;
+    for (hipStream_t s : {g->s_main, g->s_copy, g->s_fk, g->s_zc, g->s_c})
+        if (s) (void)hipStreamDestroy(s);
+    for (uint32_t i = 0; i < kMaxSlots; i++) {
+        if (g->ev_copied[i]) (void)hipEventDestroy(g->ev_copied[i]);
+        if (g->ev_free[i]) (void)hipEventDestroy(g->ev_free[i]);
+    }
+    for (auto e : g->ev_cdone)
+        if (e) (void)hipEventDestroy(e);
+    for (auto e : g->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    if (g->ev_start) (void)hipEventDestroy(g->ev_start);
+    if (g->ev_clist) (void)hipEventDestroy(g->ev_clist);
+    delete g->pool;
+    g->pool = nullptr;
+}
+
+void parallel_copy(void* dst, const void* src, size_t bytes) {
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (bytes < (64u << 20) || nt == 1) {
+        memcpy(dst, src, bytes);
+        return;
+    }
+    std::vector<std::thread> th;
+    const size_t chunk = (bytes / nt + 4095) & ~size_t(4095);
+    for (unsigned i = 0; i < nt; i++) {
+        const size_t a = i * chunk;
+        if (a >= bytes) break;
+        const size_t b = std::min(bytes, a + chunk);
+        th.emplace_back([=] { memcpy((char*)dst + a, (const char*)src + a, b - a); });
+    }
+    for (auto& t : th) t.join();
+}
+
+// ------------------------------------------------------------------- run
+struct RunCtx {
+    hytm_graph* g;
+    int algo;
+    uint32_t arrays;
+    Plan plan;
+    SelParams sp;
+    AlgoState as;
+    hytm_run_stats* stats;
+};
+
+// Gather list entries' edges for items [x0, x1) of the compaction segment into
+// the pinned chunk buffer (Sec. 6.3 compaction engine).
+void gather_chunk(hytm_graph* g, uint32_t arrays, const uint32_t* clist, const uint64_t* cwpre, uint32_t count,
+                  uint64_t x0, uint64_t x1, uint32_t* out_col, uint32_t* out_w) {
+    const unsigned parts = std::max(1u, g->pool->size() * 2);
+    const uint64_t total = x1 - x0;
+    const uint64_t step = (total + parts - 1) / parts;
+    g->pool->run(parts, [&](unsigned t) {
+        const uint64_t y0 = x0 + std::min<uint64_t>(total, t * step);
+        const uint64_t y1 = x0 + std::min<uint64_t>(total, (uint64_t)(t + 1) * step);
+        if (y0 >= y1) return;
+        // last entry j with cwpre[j] <= y0
+        uint32_t j = (uint32_t)(std::upper_bound(cwpre, cwpre + count, y0) - cwpre) - 1;
+        uint64_t y = y0;
+        while (y < y1) {
+            const uint32_t v = clist[j];
+            const uint64_t pre = cwpre[j], end = cwpre[j + 1];
+            const uint64_t a = y, b = std::min(end, y1);
+            const uint64_t src = g->h_off[v] + (a - pre);
+            memcpy(out_col + (a - x0), g->h_col + src, (b - a) * sizeof(uint32_t));
+            if (arrays == 2) memcpy(out_w + (a - x0), g->h_w + src, (b - a) * sizeof(uint32_t));
+            y = b;
+            j++;
+        }
+    });
+}
+
+// The compaction engine for one iteration, run on its own host thread.
+void run_compaction(RunCtx* rc, uint32_t cs, uint32_t cc, uint64_t w0, uint64_t w1, uint64_t* chunks,
+                    uint64_t* bytes, uint64_t* d2h, hytm_status* st_out, std::string* msg) {
+    hytm_graph* g = rc->g;
+    try {
+        // active list and work prefix of the compaction segment (Vc and its offsets)
+        HIP_CHECK(hipMemcpyAsync(g->h_clist.p, g->d_list.p + cs, cc * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                 g->s_c));
+        HIP_CHECK(hipMemcpyAsync(g->h_cwpre.p, g->d_wpre.p + cs, (cc + 1) * sizeof(uint64_t),
+                                 hipMemcpyDeviceToHost, g->s_c));
+        HIP_CHECK(hipEventRecord(g->ev_clist, g->s_c));
+        HIP_CHECK(hipEventSynchronize(g->ev_clist));
+        *d2h += cc * (sizeof(uint32_t) + sizeof(uint64_t));
+        const uint64_t chunk = rc->plan.cchunk;
+        uint64_t x0 = w0;
+        uint32_t b = 0, issued = 0;
+        while (x0 < w1) {
+            const uint64_t x1 = std::min(w1, x0 + chunk);
+            if (issued >= 2) HIP_CHECK(hipEventSynchronize(g->ev_cdone[b]));
+            gather_chunk(g, rc->arrays, g->h_clist.p, g->h_cwpre.p, cc, x0, x1, g->h_cbuf_col[b].p,
+                         rc->arrays == 2 ? g->h_cbuf_w[b].p : nullptr);
+            HIP_CHECK(hipMemcpyAsync(g->d_cbuf_col[b].p, g->h_cbuf_col[b].p, (x1 - x0) * 4, hipMemcpyHostToDevice,
+                                     g->s_c));
+            if (rc->arrays == 2)
+                HIP_CHECK(hipMemcpyAsync(g->d_cbuf_w[b].p, g->h_cbuf_w[b].p, (x1 - x0) * 4, hipMemcpyHostToDevice,
+                                         g->s_c));
+            HIP_CHECK(launch_push_edges(rc->as, g->d_list.p, g->d_wpre.p, cs, cs + cc, x0, x1, g->d_off.p,
+                                        g->d_cbuf_col[b].p, g->d_cbuf_w[b].p, x0, true, g->s_c));
+            HIP_CHECK(hipEventRecord(g->ev_cdone[b], g->s_c));
+            *bytes += (x1 - x0) * 4 * rc->arrays;
+            *chunks += 1;
+            issued++;
+            b ^= 1;
+            x0 = x1;
+        }
+        *st_out = HYTM_OK;
+    } catch (const HipError& e) {
+        *st_out = e.status;
+    } catch (const std::bad_alloc&) {
+        *st_out = fail(HYTM_E_NOMEM, "host allocation failed in the compaction engine");
+    }
+    *msg = g_err;  // the message is thread-local: hand it back to the calling thread
+}
+
+hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* values_out, uint32_t* iterations_out,
+                     hytm_run_stats* stats, void* hip_stream) {
+    HIP_CHECK(hipSetDevice(g->device));
+    ensure_streams(g);
+    const double t_begin = now_ms();
+    const uint32_t arrays = algo == HYTM_SSSP ? 2 : 1;
+    RunCtx rc{};
+    rc.g = g;
+    rc.algo = algo;
+    rc.arrays = arrays;
+    rc.stats = stats;
+    hytm_status ps = make_plan(g, arrays, &rc.plan);
+    if (ps != HYTM_OK) return ps;
+    rc.sp = make_sel(g, arrays);
+    rc.sp.nres = rc.plan.nres;
+    rc.sp.allow_filter = rc.plan.allow_filter || g->budget == UINT64_MAX;
+    rc.sp.allow_compact = rc.plan.allow_compact || g->budget == UINT64_MAX;
+    hipStream_t main = hip_stream ? (hipStream_t)hip_stream : g->s_main;
+
+    const uint64_t n = g->n;
+    const uint32_t nwords = (uint32_t)((n + 31) / 32);
+    const uint32_t npart = g->npart;
+    // vertex-associated device state (outside the budget)
+    g->d_val.ensure(n);
+    g->d_cur.ensure(nwords);
+    g->d_next.ensure(nwords);
+    if (algo == HYTM_BFS) g->d_visited.ensure(nwords);
+    g->d_list.ensure(n);
+    g->d_wpre.ensure(n + 1);
+    g->d_overflow.ensure(1);
+    if (algo == HYTM_PAGERANK) {
+        g->d_x.ensure(n);
+        g->d_contrib.ensure(n);
+        g->d_acc.ensure(n);
+    }
+    g->d_mode.ensure(npart);
+    g->d_nA.ensure(npart);
+    g->d_nF.ensure(npart);
+    g->d_lbase.ensure(npart);
+    g->d_Ea.ensure(npart);
+    g->d_Rq.ensure(npart);
+    g->d_K.ensure(npart);
+    g->d_wbase.ensure(npart);
+    g->d_hdr.ensure(1);
+    g->h_hdr.ensure(1);
+    g->h_mode.ensure(npart);
+    g->h_lbase.ensure(npart);
+    g->h_wbase.ensure(npart);
+
+    // edge-budget buffers
+    const Plan& pl = rc.plan;
+    if (pl.allow_filter)
+        for (uint32_t s = 0; s < pl.nslots; s++) {
+            g->d_slot_col[s].ensure(pl.slot_edges);
+            if (arrays == 2) g->d_slot_w[s].ensure(pl.slot_edges);
+        }
+    if (pl.allow_compact) {
+        for (int b = 0; b < 2; b++) {
+            g->d_cbuf_col[b].ensure(pl.cchunk);
+            g->h_cbuf_col[b].ensure(pl.cchunk);
+            if (arrays == 2) {
+                g->d_cbuf_w[b].ensure(pl.cchunk);
+                g->h_cbuf_w[b].ensure(pl.cchunk);
+            }
+        }
+        g->h_clist.ensure(n);
+        g->h_cwpre.ensure(n + 1);
+        if (!g->pool) {
+            unsigned t = g->params.gather_threads;
+            if (!t) t = std::max(1u, std::min(16u, std::thread::hardware_concurrency() / 2));
+            g->pool = new Pool(t);
+        }
+    }
+    HIP_CHECK(hipEventRecord(g->ev_start, main));
+
+    // resident cache: partitions [0, nres) copied once and kept while nres/arrays hold
+    double fill_ms = 0;
+    uint64_t fill_bytes = 0;
+    if (pl.nres > 0 && !(g->res_valid && g->res_parts == pl.nres && g->res_arrays >= arrays)) {
+        const double t0 = now_ms();
+        g->d_res_col.ensure(pl.res_edges);
+        HIP_CHECK(hipMemcpyAsync(g->d_res_col.p, g->h_col, pl.res_edges * 4, hipMemcpyHostToDevice, main));
+        fill_bytes += pl.res_edges * 4;
+        if (arrays == 2) {
+            g->d_res_w.ensure(pl.res_edges);
+            HIP_CHECK(hipMemcpyAsync(g->d_res_w.p, g->h_w, pl.res_edges * 4, hipMemcpyHostToDevice, main));
+            fill_bytes += pl.res_edges * 4;
+        }
+        HIP_CHECK(hipStreamSynchronize(main));
+        g->res_parts = pl.nres;
+        g->res_edges = pl.res_edges;
+        g->res_arrays = arrays;
+        g->res_valid = true;
+        fill_ms = now_ms() - t0;
+    }
+
+    AlgoState& as = rc.as;
+    as.algo = algo;
+    as.val = g->d_val.p;
+    as.visited = algo == HYTM_BFS ? g->d_visited.p : nullptr;
+    as.next = algo == HYTM_PAGERANK ? nullptr : g->d_next.p;
+    as.overflow = g->d_overflow.p;
+    as.acc = g->d_acc.p;
+    as.contrib = g->d_contrib.p;
+    const float x0 = n ? (float)(1.0 / (double)n) : 0.f;
+    HIP_CHECK(launch_init(as, n, source, x0, g->d_x.p, g->d_cur.p, nwords, main));
+    uint32_t* cur = g->d_cur.p;
+    uint32_t* nxt = g->d_next.p;
+
+    const float pr_base = (float)((1.0 - g->params.pr_damping) / (double)n);
+    const float pr_d = (float)g->params.pr_damping;
+    const uint32_t T = g->params.pr_iterations;
+
+    uint32_t iters = 0;
+    double select_ms = 0;
+    uint64_t part_iters[5] = {0, 0, 0, 0, 0};
+    uint64_t tot_av = 0, tot_ae = 0, b_f = 0, b_c = 0, zcl = 0, d2h = 0, ftasks = 0, cchunks = 0;
+    const uint64_t d1b = 4ull * arrays;
+
+    for (uint32_t t = 0;; t++) {
+        if (algo == HYTM_PAGERANK && t >= T) break;
+        const double t_it = now_ms();
+        if (algo == HYTM_PAGERANK) HIP_CHECK(launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, main));
+        // 1. statistics, engine selection, active lists (Algorithm 1, GPU part)
+        HIP_CHECK(launch_stats_select(npart, g->d_pv.p, g->d_off.p, cur, rc.sp, g->d_mode.p, g->d_nA.p, g->d_nF.p,
+                                      g->d_Ea.p, g->d_Rq.p, g->d_K.p, main));
+        HIP_CHECK(launch_scan(npart, g->d_mode.p, g->d_nA.p, g->d_nF.p, g->d_Ea.p, g->d_Rq.p, g->d_K.p,
+                              g->d_lbase.p, g->d_wbase.p, g->d_hdr.p, g->d_wpre.p, main));
+        HIP_CHECK(launch_build_lists(npart, g->d_pv.p, g->d_off.p, cur, g->d_mode.p, g->d_lbase.p, g->d_wbase.p,
+                                     g->d_list.p, g->d_wpre.p, main));
+        // 2. selection back to the host (Algorithm 1: copy Vc, p and A to host)
+        HIP_CHECK(hipMemcpyAsync(g->h_hdr.p, g->d_hdr.p, sizeof(Header), hipMemcpyDeviceToHost, main));
+        HIP_CHECK(hipMemcpyAsync(g->h_mode.p, g->d_mode.p, npart, hipMemcpyDeviceToHost, main));
+        HIP_CHECK(hipMemcpyAsync(g->h_lbase.p, g->d_lbase.p, npart * sizeof(uint32_t), hipMemcpyDeviceToHost, main));
+        HIP_CHECK(hipMemcpyAsync(g->h_wbase.p, g->d_wbase.p, npart * sizeof(uint64_t), hipMemcpyDeviceToHost, main));
+        HIP_CHECK(hipStreamSynchronize(main));
+        d2h += sizeof(Header) + npart * (1 + 4 + 8);
+        const Header h = *g->h_hdr.p;
+        select_ms += now_ms() - t_it;
+        if (algo != HYTM_PAGERANK && h.frontier == 0) break;
+        iters++;
+
+        // per-iteration bookkeeping
+        hytm_iter_stats rec{};
+        rec.parts[0] = npart;
+        for (int s = 0; s < NSEG; s++) {
+            rec.parts[s + 1] = h.seg_parts[s];
+            rec.parts[0] -= h.seg_parts[s];
+        }
+        rec.active_vertices = h.total_active;
+        for (int s = 0; s < NSEG; s++) rec.active_edges += h.seg_edges[s];
+        if (stats && stats->mode_trace && (uint64_t)(t + 1) * npart <= stats->mode_trace_cap)
+            memcpy(stats->mode_trace + (uint64_t)t * npart, g->h_mode.p, npart);
+
+        as.level_next = t + 1;
+        // resident partitions: no transfer
+        if (h.seg_list_count[SEG_R])
+            HIP_CHECK(launch_push_edges(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_R],
+                                        h.seg_list_start[SEG_R] + h.seg_list_count[SEG_R], h.seg_work_start[SEG_R],
+                                        h.seg_work_start[SEG_R] + h.seg_work_total[SEG_R], g->d_off.p,
+                                        g->d_res_col.p, g->d_res_w.p, 0, false, main));
+        // zero-copy: one kernel over all zero-copy vertices (Vz)
+        if (h.seg_list_count[SEG_Z]) {
+            HIP_CHECK(launch_push_lines(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_Z],
+                                        h.seg_list_start[SEG_Z] + h.seg_list_count[SEG_Z], h.seg_work_start[SEG_Z],
+                                        h.seg_work_start[SEG_Z] + h.seg_work_total[SEG_Z], g->d_off.p,
+                                        g->d_col_map, g->d_w_map, g->s_zc));
+            rec.zc_lines = h.seg_work_total[SEG_Z];
+        }
+        // compaction: gathered by host threads, overlapping the filter tasks below
+        std::thread cthread;
+        hytm_status cst = HYTM_OK;
+        std::string cmsg;
+        uint64_t c_chunks = 0, c_bytes = 0, c_d2h = 0;
+        if (h.seg_list_count[SEG_C])
+            cthread = std::thread(run_compaction, &rc, h.seg_list_start[SEG_C], h.seg_list_count[SEG_C],
+                                  h.seg_work_start[SEG_C], h.seg_work_start[SEG_C] + h.seg_work_total[SEG_C],
+                                  &c_chunks, &c_bytes, &c_d2h, &cst, &cmsg);
+        // filter: combine runs of <= k consecutive partitions (Sec. 5.2), then copy+push
+        hytm_status fst = HYTM_OK;
+        try {
+            if (h.seg_list_count[SEG_F]) {
+                const uint32_t k = g->params.combine_k;
+                const uint64_t fend_list = h.seg_list_start[SEG_F] + h.seg_list_count[SEG_F];
+                const uint64_t fend_work = h.seg_work_start[SEG_F] + h.seg_work_total[SEG_F];
+                uint32_t gidx = 0;
+                uint32_t i = 0;
+                while (i < npart) {
+                    if (g->h_mode.p[i] != P_FILTER) {
+                        i++;
+                        continue;
+                    }
+                    // task = partitions [i, j): adjacent filter partitions, at most k, within one slot
+                    uint32_t j = i + 1;
+                    uint64_t edges = g->pE[i];
+                    while (j < npart && j - i < k && g->h_mode.p[j] == P_FILTER && edges + g->pE[j] <= pl.slot_edges) {
+                        edges += g->pE[j];
+                        j++;
+                    }
+                    // list / work range of the task: up to the next filter partition's start
+                    uint32_t nx = j;
+                    while (nx < npart && g->h_mode.p[nx] != P_FILTER) nx++;
+                    const uint32_t ja = g->h_lbase.p[i];
+                    const uint32_t jb = nx < npart ? g->h_lbase.p[nx] : (uint32_t)fend_list;
+                    const uint64_t wa = g->h_wbase.p[i];
+                    const uint64_t wb = nx < npart ? g->h_wbase.p[nx] : fend_work;
+                    const uint64_t ebeg = g->h_off[g->pv[i]];
+                    const uint32_t s = gidx % pl.nslots;
+                    if (gidx >= pl.nslots) HIP_CHECK(hipStreamWaitEvent(g->s_copy, g->ev_free[s], 0));
+                    HIP_CHECK(hipMemcpyAsync(g->d_slot_col[s].p, g->h_col + ebeg, edges * 4, hipMemcpyHostToDevice,
+                                             g->s_copy));
+                    if (arrays == 2)
+                        HIP_CHECK(hipMemcpyAsync(g->d_slot_w[s].p, g->h_w + ebeg, edges * 4, hipMemcpyHostToDevice,
+                                                 g->s_copy));
+                    HIP_CHECK(hipEventRecord(g->ev_copied[s], g->s_copy));
+                    HIP_CHECK(hipStreamWaitEvent(g->s_fk, g->ev_copied[s], 0));
+                    HIP_CHECK(launch_push_edges(as, g->d_list.p, g->d_wpre.p, ja, jb, wa, wb, g->d_off.p,
+                                                g->d_slot_col[s].p, g->d_slot_w[s].p, ebeg, false, g->s_fk));
+                    HIP_CHECK(hipEventRecord(g->ev_free[s], g->s_fk));
+                    rec.bytes_filter += edges * d1b;
+                    gidx++;
+                    i = j;
+                }
+                rec.filter_tasks = gidx;
+            }
+        } catch (const HipError& e) {
+            fst = e.status;
+        }
+        if (cthread.joinable()) cthread.join();
+        if (fst != HYTM_OK) return fst;
+        if (cst != HYTM_OK) {
+            g_err = cmsg;
+            return cst;
+        }
+        rec.bytes_compact = c_bytes;
+        d2h += c_d2h;
+        cchunks += c_chunks;
+        // 3. join every engine into the main stream
+        HIP_CHECK(hipEventRecord(g->ev_join[0], g->s_fk));
+        HIP_CHECK(hipEventRecord(g->ev_join[1], g->s_zc));
+        HIP_CHECK(hipEventRecord(g->ev_join[2], g->s_c));
+        for (int q = 0; q < 3; q++) HIP_CHECK(hipStreamWaitEvent(main, g->ev_join[q], 0));
+        if (algo == HYTM_PAGERANK) {
+            HIP_CHECK(launch_pr_apply(n, g->d_x.p, g->d_acc.p, pr_base, pr_d, main));
+        } else {
+            std::swap(cur, nxt);
+            as.next = nxt;
+            HIP_CHECK(launch_fill_u32(nxt, nwords, 0u, main));
+        }
+        for (int s = 0; s < 5; s++) part_iters[s] += rec.parts[s];
+        tot_av += rec.active_vertices;
+        tot_ae += rec.active_edges;
+        b_f += rec.bytes_filter;
+        b_c += rec.bytes_compact;
+        zcl += rec.zc_lines;
+        ftasks += rec.filter_tasks;
+        rec.ms = now_ms() - t_it;
+        if (stats && stats->iters && t < stats->iters_cap) {
+            stats->iters[t] = rec;
+            stats->iters_written = t + 1;
+        }
+    }
+    HIP_CHECK(hipStreamSynchronize(main));
+    if (algo == HYTM_SSSP) {
+        uint32_t of = 0;
+        HIP_CHECK(hipMemcpy(&of, g->d_overflow.p, sizeof(of), hipMemcpyDeviceToHost));
+        if (of) return fail(HYTM_E_RANGE, "an SSSP distance reaches 2^32-1 and does not fit in uint32");
+    }
+    const void* src = algo == HYTM_PAGERANK ? (const void*)g->d_x.p : (const void*)g->d_val.p;
+    HIP_CHECK(hipMemcpyAsync(values_out, src, n * 4, hipMemcpyDeviceToHost, main));
+    HIP_CHECK(hipStreamSynchronize(main));
+    const double t_end = now_ms();
+    if (iterations_out) *iterations_out = iters;
+    if (stats) {
+        stats->iterations = iters;
+        stats->npart = npart;
+        stats->nres = pl.nres;
+        for (int s = 0; s < 5; s++) stats->part_iters[s] = part_iters[s];
+        stats->active_vertices = tot_av;
+        stats->active_edges = tot_ae;
+        stats->bytes_filter = b_f;
+        stats->bytes_compact = b_c;
+        stats->zc_lines = zcl;
+        stats->bytes_zerocopy = zcl * 128 * arrays;
+        stats->bytes_d2h = d2h;
+        stats->bytes_resident_fill = fill_bytes;
+        stats->filter_tasks = ftasks;
+        stats->compact_chunks = cchunks;
+        stats->ms_total = t_end - t_begin;
+        stats->ms_fill = fill_ms;
+        stats->ms_select = select_ms;
+    }
+    return HYTM_OK;
+}
+
+template <class F>
+hytm_status guarded(F&& f) {
+    try {
+        return f();
+    } catch (const HipError& e) {
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        return fail(HYTM_E_NOMEM, "host allocation failed");
+    }
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+void hytm_default_params(hytm_params* p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(hytm_params);
+    p->mode = HYTM_MODE_HYBRID;
+    p->partition_edges = 32768;
+    p->combine_k = 4;
+    p->alpha_num = 4;
+    p->alpha_den = 5;
+    p->beta_num = 2;
+    p->beta_den = 5;
+    p->gamma_num = 5;
+    p->gamma_den = 8;
+    p->line_bytes = 128;
+    p->max_outstanding = 256;
+    p->index_bytes = 4;
+    p->pr_iterations = 20;
+    p->pr_damping = 0.85;
+    p->streams = 4;
+    p->gather_threads = 0;
+    p->compact_chunk_edges = 0;
+}
+
+const char* hytm_last_error(void) { return g_err.c_str(); }
+
+hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint32_t offset_bytes, const uint32_t* col,
+                              const uint32_t* weights, uint32_t flags, int hip_device, hytm_graph** out) {
+    g_err.clear();
+    if (!out) return fail(HYTM_E_INVAL, "out is NULL");
+    if (!offsets) return fail(HYTM_E_INVAL, "offsets is NULL");
+    if (m > 0 && !col) return fail(HYTM_E_INVAL, "col is NULL");
+    if (offset_bytes != 4 && offset_bytes != 8) return fail(HYTM_E_INVAL, "offset_bytes must be 4 or 8");
+    if (n == 0) return fail(HYTM_E_INVAL, "graph has no vertices");
+    if (n >= 0xFFFFFFFFull) return fail(HYTM_E_RANGE, "n = %llu: vertex ids must fit below 2^32-1", (unsigned long long)n);
+    if (offset_bytes == 4 && m > 0xFFFFFFFFull) return fail(HYTM_E_INVAL, "m does not fit 4-byte offsets");
+    if (flags & ~(uint32_t)(HYTM_GRAPH_SYMMETRIC | HYTM_GRAPH_SKIP_COL_CHECK))
+        return fail(HYTM_E_INVAL, "unknown flag bits 0x%x", flags);
+    hytm_graph* g = nullptr;
+    try {
+        g = new hytm_graph();
+        g->n = n;
+        g->m = m;
+        g->flags = flags;
+        g->device = hip_device;
+        hytm_default_params(&g->params);
+        g->h_off.resize(n + 1);
+        for (uint64_t v = 0; v <= n; v++)
+            g->h_off[v] = offset_bytes == 8 ? ((const uint64_t*)offsets)[v] : ((const uint32_t*)offsets)[v];
+        if (g->h_off[0] != 0) {
+            delete g;
+            return fail(HYTM_E_INVAL, "offsets[0] must be 0");
+        }
+        for (uint64_t v = 0; v < n; v++)
+            if (g->h_off[v + 1] < g->h_off[v]) {
+                delete g;
+                return fail(HYTM_E_INVAL, "offsets decrease at vertex %llu", (unsigned long long)v);
+            }
+        if (g->h_off[n] != m) {
+            delete g;
+            return fail(HYTM_E_INVAL, "offsets[n] = %llu but m = %llu", (unsigned long long)g->h_off[n],
+                        (unsigned long long)m);
+        }
+        if (!(flags & HYTM_GRAPH_SKIP_COL_CHECK)) {
+            for (uint64_t e = 0; e < m; e++)
+                if (col[e] >= n) {
+                    delete g;
+                    return fail(HYTM_E_INVAL, "col[%llu] = %u is not a vertex", (unsigned long long)e, col[e]);
+                }
+        }
+    } catch (const std::bad_alloc&) {
+        delete g;
+        return fail(HYTM_E_NOMEM, "host allocation failed");
+    }
+    hytm_status st = guarded([&]() -> hytm_status {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess || count == 0)
+            return fail(HYTM_E_DEVICE, "no HIP device available: %s", hipGetErrorString(e));
+        if (hip_device < 0 || hip_device >= count)
+            return fail(HYTM_E_DEVICE, "HIP device %d does not exist (%d visible)", hip_device, count);
+        HIP_CHECK(hipSetDevice(hip_device));
+        // edge arrays: pinned host memory mapped into the device address space
+        const size_t eb = std::max<uint64_t>(m, 1) * sizeof(uint32_t);
+        HIP_CHECK(hipHostMalloc((void**)&g->h_col, eb, hipHostMallocMapped));
+        if (m) parallel_copy(g->h_col, col, m * sizeof(uint32_t));
+        HIP_CHECK(hipHostGetDevicePointer((void**)&g->d_col_map, g->h_col, 0));
+        if (weights) {
+            HIP_CHECK(hipHostMalloc((void**)&g->h_w, eb, hipHostMallocMapped));
+            if (m) parallel_copy(g->h_w, weights, m * sizeof(uint32_t));
+            HIP_CHECK(hipHostGetDevicePointer((void**)&g->d_w_map, g->h_w, 0));
+        }
+        g->d_off.ensure(n + 1);
+        HIP_CHECK(hipMemcpy(g->d_off.p, g->h_off.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
+        partition_graph(g);
+        return HYTM_OK;
+    });
+    if (st != HYTM_OK) {
+        release_all(g);
+        delete g;
+        return st;
+    }
+    *out = g;
+    return HYTM_OK;
+}
+
+hytm_status hytm_set_device_budget(hytm_graph* g, uint64_t edge_bytes) {
+    g_err.clear();
+    if (!g) return fail(HYTM_E_INVAL, "graph is NULL");
+    if (edge_bytes != g->budget) g->res_valid = false;
+    g->budget = edge_bytes;
+    return HYTM_OK;
+}
+
+hytm_status hytm_set_params(hytm_graph* g, const hytm_params* p) {
+    g_err.clear();
+    if (!g) return fail(HYTM_E_INVAL, "graph is NULL");
+    hytm_params np;
+    if (p) {
+        if (p->struct_size != sizeof(hytm_params)) return fail(HYTM_E_INVAL, "params.struct_size mismatch");
+        np = *p;
+    } else {
+        hytm_default_params(&np);
+    }
+    std::string why;
+    if (!params_valid(np, &why)) return fail(HYTM_E_INVAL, "bad params: %s", why.c_str());
+    const bool repart = np.partition_edges != g->params.partition_edges;
+    g->params = np;
+    if (repart)
+        return guarded([&]() -> hytm_status {
+            HIP_CHECK(hipSetDevice(g->device));
+            partition_graph(g);
+            return HYTM_OK;
+        });
+    g->res_valid = false;
+    return HYTM_OK;
+}
+
+hytm_status hytm_get_params(const hytm_graph* g, hytm_params* p) {
+    g_err.clear();
+    if (!g || !p) return fail(HYTM_E_INVAL, "NULL argument");
+    *p = g->params;
+    return HYTM_OK;
+}
+
+hytm_status hytm_staging_bytes(const hytm_graph* g, hytm_algo algo, uint64_t* bytes) {
+    g_err.clear();
+    if (!g || !bytes) return fail(HYTM_E_INVAL, "NULL argument");
+    if (algo < HYTM_BFS || algo > HYTM_PAGERANK) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
+    const Staging s = staging_of(g, algo == HYTM_SSSP ? 2 : 1);
+    switch (g->params.mode) {
+    case HYTM_MODE_FILTER: *bytes = s.f_bytes; break;
+    case HYTM_MODE_COMPACT: *bytes = s.c_bytes; break;
+    case HYTM_MODE_ZEROCOPY: *bytes = 0; break;
+    default: *bytes = s.f_bytes + s.c_bytes;
+    }
+    return HYTM_OK;
+}
+
+hytm_status hytm_graph_info_get(const hytm_graph* g, hytm_graph_info* info) {
+    g_err.clear();
+    if (!g || !info) return fail(HYTM_E_INVAL, "NULL argument");
+    info->n = g->n;
+    info->m = g->m;
+    info->npart = g->npart;
+    info->max_partition_edges = (uint32_t)std::min<uint64_t>(g->max_part_edges, 0xFFFFFFFFull);
+    info->hip_device = g->device;
+    info->flags = g->flags;
+    return HYTM_OK;
+}
+
+hytm_status hytm_partition_bounds(const hytm_graph* g, uint64_t* bounds, uint64_t cap) {
+    g_err.clear();
+    if (!g || !bounds) return fail(HYTM_E_INVAL, "NULL argument");
+    if (cap < g->pv.size()) return fail(HYTM_E_INVAL, "bounds buffer holds %llu entries, needs %zu",
+                                        (unsigned long long)cap, g->pv.size());
+    for (size_t i = 0; i < g->pv.size(); i++) bounds[i] = g->pv[i];
+    return HYTM_OK;
+}
+
+hytm_status hytm_run(hytm_graph* g, hytm_algo algo, uint32_t source, void* values_out, uint32_t* iterations_out,
+                     hytm_run_stats* stats, void* hip_stream) {
+    g_err.clear();
+    if (!g) return fail(HYTM_E_INVAL, "graph is NULL");
+    if (!values_out) return fail(HYTM_E_INVAL, "values_out is NULL");
+    if (algo < HYTM_BFS || algo > HYTM_PAGERANK) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
+    if (stats && stats->struct_size != sizeof(hytm_run_stats))
+        return fail(HYTM_E_INVAL, "stats.struct_size mismatch");
+    if ((algo == HYTM_BFS || algo == HYTM_SSSP) && source >= g->n)
+        return fail(HYTM_E_RANGE, "source %u >= n = %llu", source, (unsigned long long)g->n);
+    if (algo == HYTM_SSSP && !g->h_w) return fail(HYTM_E_INVAL, "SSSP needs edge weights");
+    if (algo == HYTM_CC && !(g->flags & HYTM_GRAPH_SYMMETRIC))
+        return fail(HYTM_E_INVAL, "CC needs a graph created with HYTM_GRAPH_SYMMETRIC");
+    if (algo == HYTM_PAGERANK && g->params.pr_iterations == 0)
+        return fail(HYTM_E_INVAL, "pr_iterations must be > 0");
+    return guarded([&] { return run_impl(g, algo, source, values_out, iterations_out, stats, hip_stream); });
+}
+
+hytm_status hytm_select_engines(hytm_graph* g, uint64_t npart, const uint64_t* E, const uint64_t* nA,
+                                const uint64_t* Ea, const uint64_t* Rq, uint64_t nres, uint32_t edge_arrays,
+                                uint8_t* p_out) {
+    g_err.clear();
+    if (!g || (npart && (!E || !nA || !Ea || !Rq || !p_out))) return fail(HYTM_E_INVAL, "NULL argument");
+    if (edge_arrays != 1 && edge_arrays != 2) return fail(HYTM_E_INVAL, "edge_arrays must be 1 or 2");
+    for (uint64_t i = 0; i < npart; i++)
+        if (E[i] >= (1ull << 40) || Ea[i] > E[i] || nA[i] > Ea[i] || Rq[i] >= (1ull << 44) ||
+            (Ea[i] > 0 && nA[i] == 0))
+            return fail(HYTM_E_INVAL, "partition %llu: statistics out of range", (unsigned long long)i);
+    if (npart == 0) return HYTM_OK;
+    return guarded([&]() -> hytm_status {
+        HIP_CHECK(hipSetDevice(g->device));
+        ensure_streams(g);
+        SelParams sp = make_sel(g, edge_arrays);
+        sp.nres = (uint32_t)std::min<uint64_t>(nres, 0xFFFFFFFFull);
+        g->d_sel_in.ensure(4 * npart);
+        g->d_sel_out.ensure(npart);
+        const uint64_t* src[4] = {E, nA, Ea, Rq};
+        for (int a = 0; a < 4; a++)
+            HIP_CHECK(hipMemcpyAsync(g->d_sel_in.p + a * npart, src[a], npart * 8, hipMemcpyHostToDevice, g->s_main));
+        HIP_CHECK(launch_select_only(npart, g->d_sel_in.p, g->d_sel_in.p + npart, g->d_sel_in.p + 2 * npart,
+                                     g->d_sel_in.p + 3 * npart, sp, g->d_sel_out.p, g->s_main));
+        HIP_CHECK(hipMemcpyAsync(p_out, g->d_sel_out.p, npart, hipMemcpyDeviceToHost, g->s_main));
+        HIP_CHECK(hipStreamSynchronize(g->s_main));
+        return HYTM_OK;
+    });
+}
+
+hytm_status hytm_graph_destroy(hytm_graph* g) {
+    g_err.clear();
+    if (!g) return HYTM_OK;
+    (void)hipSetDevice(g->device);
+    release_all(g);
+    delete g;
+    return HYTM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,257 @@
+"""GPU parity: libhytm (through its C ABI) against the CPU oracle on the same seeded inputs.
+
+BFS levels, SSSP distances and CC labels must match bit for bit; PageRank must stay within
+1e-6 max-abs of the FP64 oracle.  Every transfer engine (forced filter / compaction /
+zero-copy, hybrid) and several device budgets must give the same values.
+"""
+import sys
+
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings, strategies as st
+
+import gen
+import oracle
+import paper_2208_14935_amd as hy
+
+pytestmark = pytest.mark.gpu
+PR_TOL = 1e-6
+MODES = ["hybrid", "filter", "compact", "zerocopy"]
+
+
+def note(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+class Case:
+    """A graph with its symmetrized twin, weights and oracle answers (computed lazily)."""
+
+    def __init__(self, off, col, seed=1):
+        self.off, self.col = off, col
+        self.w = gen.weights(off, col, seed)
+        self.soff, self.scol = gen.symmetrize(off, col)
+        self._cache = {}
+
+    def want(self, algo, source=0):
+        key = (algo, source)
+        if key not in self._cache:
+            if algo == "bfs":
+                self._cache[key] = oracle.bfs(self.off, self.col, source)
+            elif algo == "sssp":
+                self._cache[key] = (oracle.sssp(self.off, self.col, self.w, source), None)
+            elif algo == "cc":
+                self._cache[key] = (oracle.cc(self.soff, self.scol)[0], None)
+            else:
+                self._cache[key] = (oracle.pagerank(self.off, self.col, 0.85, 20), 20)
+        return self._cache[key]
+
+    def graph(self, algo):
+        if algo == "cc":
+            return hy.Graph(self.soff, self.scol, symmetric=True)
+        return hy.Graph(self.off, self.col, weights=self.w)
+
+
+def check(case, algo, res, source=0):
+    want, want_it = case.want(algo, source)
+    if algo == "pagerank":
+        err = np.abs(res.values.astype(np.float64) - want).max() if len(want) else 0.0
+        assert err <= PR_TOL, f"pagerank max-abs error {err}"
+        assert res.iterations == 20
+    else:
+        bad = np.nonzero(res.values != want)[0]
+        assert len(bad) == 0, f"{algo}: {len(bad)} mismatches, first at {bad[:5]}: got {res.values[bad[:5]]} want {want[bad[:5]]}"
+        if algo == "bfs":
+            assert res.iterations == want_it
+
+
+def sssp_iteration_bounds(case, source):
+    lvl, it_bfs = case.want("bfs", source)
+    upper = oracle.sync_rounds(case.off, case.col, case.w, "sssp", source)
+    return it_bfs, upper
+
+
+@pytest.fixture(scope="module")
+def rmat16():
+    off, col = gen.rmat(16, 16, seed=16)
+    return Case(off, col, seed=1016)
+
+
+@pytest.fixture(scope="module")
+def rmat12():
+    off, col = gen.rmat(12, 16, seed=12)
+    return Case(off, col, seed=1012)
+
+
+# ----------------------------------------------------------- resident path
+@pytest.mark.parametrize("algo", ["bfs", "sssp", "cc", "pagerank"])
+def test_rmat16_resident_matches_oracle(rmat16, algo):
+    note(f"rmat16 resident {algo}")
+    with rmat16.graph(algo) as g:
+        res = g.run(algo, 0, stats=True)
+        check(rmat16, algo, res)
+        assert res.stats["nres"] == res.stats["npart"]
+        if algo == "sssp":
+            lo, hi = sssp_iteration_bounds(rmat16, 0)
+            assert lo <= res.iterations <= hi
+        if algo == "cc":
+            assert 1 <= res.iterations <= oracle.sync_rounds(rmat16.soff, rmat16.scol, None, "cc")
+
+
+# ------------------------------------------- forced engines and budgets
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("algo", ["bfs", "sssp", "cc", "pagerank"])
+@pytest.mark.parametrize("resident", [0.25, 0.0])
+def test_engines_and_budgets_agree(rmat12, algo, mode, resident):
+    note(f"rmat12 {algo} mode={mode} resident={resident}")
+    with rmat12.graph(algo) as g:
+        # small partitions and chunks so that the 4K-vertex graph spans many of each
+        g.set_params(partition_edges=2048, mode=mode, compact_chunk_edges=4096)
+        if mode in ("filter", "compact"):
+            g.set_budget(g.staging_bytes(algo) - 1)
+            with pytest.raises(hy.HytmError) as ei:
+                g.run(algo, 0)
+            assert ei.value.status == hy.E_BUDGET
+        g.set_resident_fraction(algo, resident)
+        res = g.run(algo, 0, stats=True)
+        check(rmat12, algo, res)
+        s = res.stats
+        assert s["nres"] < s["npart"]
+        if mode != "hybrid":
+            used = {hy.ENGINE_NAMES[i] for i in range(2, 5) if s["part_iters"][i]}
+            assert used <= {mode}, used
+
+
+def test_hybrid_uses_several_engines_and_moves_fewer_bytes_than_filter(rmat16):
+    note("rmat16 hybrid vs filter bytes")
+    with rmat16.graph("bfs") as g:
+        g.set_params(partition_edges=4096)
+        g.set_resident_fraction("bfs", 0.25)
+        hyb = g.run("bfs", 0, stats=True)
+        check(rmat16, "bfs", hyb)
+        g.set_params(mode="filter")
+        g.set_resident_fraction("bfs", 0.25)
+        fil = g.run("bfs", 0, stats=True)
+        check(rmat16, "bfs", fil)
+    moved = lambda s: s["bytes_filter"] + s["bytes_compact"] + s["bytes_zerocopy"]
+    assert moved(hyb.stats) < moved(fil.stats)
+    assert sum(1 for i in (2, 3, 4) if hyb.stats["part_iters"][i]) >= 2
+
+
+# --------------------------------------------------- selection parity
+def test_bfs_engine_trace_matches_oracle_selection(rmat16):
+    """BFS frontiers are unique (level t), so the per-iteration engine vector is pinned."""
+    note("rmat16 bfs engine trace")
+    lvl, it = rmat16.want("bfs", 0)
+    with rmat16.graph("bfs") as g:
+        g.set_params(partition_edges=4096)
+        g.set_resident_fraction("bfs", 0.25)
+        res = g.run("bfs", 0, trace=True, stats=True)
+        check(rmat16, "bfs", res)
+        bounds = g.partition_bounds()
+        nres = res.stats["nres"]
+    np.testing.assert_array_equal(bounds, oracle.partition(rmat16.off, 4096))
+    E = np.diff(rmat16.off[bounds.astype(np.int64)])
+    assert res.mode_trace.shape == (it, len(E))
+    for t in range(it):
+        nA, Ea, Rq = oracle.partition_stats(bounds, rmat16.off, lvl == t, arrays=1)
+        want = oracle.select(E, nA, Ea, Rq, nres=nres)
+        np.testing.assert_array_equal(res.mode_trace[t], want, err_msg=f"iteration {t}")
+
+
+@settings(max_examples=30, deadline=None, suppress_health_check=list(HealthCheck))
+@given(st.integers(1, 3000), st.integers(0, 2**32 - 1))
+def test_select_engines_matches_oracle_on_random_stats(npart, seed):
+    rng = np.random.default_rng(seed)
+    E = rng.integers(1, 1 << 22, npart, dtype=np.uint64)
+    Ea = (E * rng.random(npart)).astype(np.uint64)
+    nA = np.minimum(Ea, rng.integers(1, 1 << 16, npart, dtype=np.uint64))
+    nA[Ea == 0] = 0
+    Rq = nA + (Ea // rng.integers(1, 64, npart, dtype=np.uint64))
+    for arrays in (1, 2):
+        nres = int(rng.integers(0, npart + 1))
+        g = _select_graph()
+        got = g.select_engines(E, nA, Ea, Rq, nres=nres, edge_arrays=arrays)
+        want = oracle.select(E, nA, Ea, Rq, nres=nres, params=oracle.CostParams(d1=4 * arrays))
+        np.testing.assert_array_equal(got, want)
+
+
+_SEL = []
+
+
+def _select_graph():
+    if not _SEL:
+        _SEL.append(hy.Graph(np.array([0, 1, 1], np.uint64), np.array([1], np.uint32)))
+    return _SEL[0]
+
+
+# -------------------------------------------------------- edge cases
+def test_tiny_and_degenerate_graphs():
+    note("degenerate graphs")
+    # single vertex, no edges
+    off, col = np.array([0, 0], np.uint64), np.zeros(0, np.uint32)
+    with hy.Graph(off, col, weights=np.zeros(0, np.uint32)) as g:
+        r = g.run("bfs", 0)
+        assert list(r.values) == [0] and r.iterations == 1
+        assert list(g.run("sssp", 0).values) == [0]
+        r = g.run("pagerank")
+        assert abs(float(r.values[0]) - 0.15) < 1e-7
+    # a source without out-edges, unreachable rest, uint32 offsets
+    off32 = np.array([0, 0, 1, 2], np.uint32)
+    col = np.array([2, 1], np.uint32)
+    with hy.Graph(off32, col, weights=np.array([3, 4], np.uint32)) as g:
+        r = g.run("bfs", 0)
+        assert list(r.values) == [0, hy.UNREACHED, hy.UNREACHED] and r.iterations == 1
+        assert list(g.run("sssp", 1).values) == [hy.UNREACHED, 0, 3]
+
+
+def test_sssp_overflow_is_reported():
+    off = np.array([0, 1, 2, 2], np.uint64)
+    col = np.array([1, 2], np.uint32)
+    with hy.Graph(off, col, weights=np.array([2**31, 2**31], np.uint32)) as g:
+        with pytest.raises(hy.HytmError) as ei:
+            g.run("sssp", 0)
+        assert ei.value.status == hy.E_RANGE
+
+
+def test_argument_errors():
+    off, col = gen.rmat(8, 4, seed=1)
+    with hy.Graph(off, col) as g:
+        with pytest.raises(hy.HytmError) as ei:
+            g.run("sssp", 0)
+        assert ei.value.status == hy.E_INVAL
+        with pytest.raises(hy.HytmError) as ei:
+            g.run("cc")
+        assert ei.value.status == hy.E_INVAL
+        with pytest.raises(hy.HytmError) as ei:
+            g.run("bfs", len(off) - 1)
+        assert ei.value.status == hy.E_RANGE
+        with pytest.raises(hy.HytmError):
+            g.set_params(combine_k=0)
+
+
+@settings(max_examples=40, deadline=None, suppress_health_check=list(HealthCheck))
+@given(st.integers(1, 40).flatmap(lambda n: st.tuples(
+    st.just(n), st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=160),
+    st.integers(0, n - 1), st.sampled_from(MODES), st.sampled_from([None, 0.5, 0.0]))))
+def test_random_small_graphs(case):
+    n, edges, s, mode, frac = case
+    src = np.array([e[0] for e in edges], np.uint32)
+    dst = np.array([e[1] for e in edges], np.uint32)
+    off, col = gen.from_pairs(n, src, dst)
+    c = Case(off, col, seed=7)
+    for algo in ("bfs", "sssp", "cc", "pagerank"):
+        with c.graph(algo) as g:
+            g.set_params(partition_edges=8, combine_k=2, compact_chunk_edges=16,
+                         mode=mode if frac is not None else "hybrid")
+            if frac is not None:
+                g.set_resident_fraction(algo, frac)
+            check(c, algo, g.run(algo, s), s)
+
+
+def test_repeat_runs_are_identical(rmat16):
+    with rmat16.graph("sssp") as g:
+        g.set_params(partition_edges=4096)
+        g.set_resident_fraction("sssp", 0.25)
+        a = g.run("sssp", 0).values.copy()
+        b = g.run("sssp", 0).values
+        np.testing.assert_array_equal(a, b)
