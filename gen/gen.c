@@ -108,16 +108,11 @@ static inline void rmat_sample(const edge_src *s, uint64_t k, uint32_t *pu, uint
     for (int l = 0; l < s->scale; l++) {
         if ((l & 1) == 0) r = draw(s->seed, k * 16 + (uint64_t)(l >> 1));
         uint32_t x = (l & 1) ? (uint32_t)(r >> 32) : (uint32_t)r;
-        uint32_t bit = 1u << (s->scale - 1 - l);
-        if (x < s->ta) {
-        } else if (x < s->tab) {
-            v |= bit;
-        } else if (x < s->tabc) {
-            u |= bit;
-        } else {
-            u |= bit;
-            v |= bit;
-        }
+        /* quadrants by x: [0,ta) -> (0,0), [ta,tab) -> (0,1), [tab,tabc) -> (1,0), rest -> (1,1) */
+        const uint32_t ge_a = x >= s->ta, ge_ab = x >= s->tab, ge_abc = x >= s->tabc;
+        const uint32_t sh = (uint32_t)(s->scale - 1 - l);
+        u |= ge_ab << sh;
+        v |= ((ge_a ^ ge_ab) | ge_abc) << sh;
     }
     *pu = u;
     *pv = v;
@@ -128,136 +123,178 @@ static inline void er_sample(const edge_src *s, uint64_t k, uint32_t *pu, uint32
     *pv = (uint32_t)(((unsigned __int128)r1 * s->n) >> 64);
 }
 
+/* ------------------------------------------------------------- CSR build */
+/* Edges are routed to 2^bbits buckets by the top bits of u.  Pass A counts edges per
+   (item block, bucket) over a fixed split of the items into blocks; pass B regenerates
+   the same items and scatters (u << 32 | v) keys into their (bucket, block) slots;
+   pass C sorts every bucket (LSD radix over the bits that vary inside it), drops
+   duplicates and self-loops and counts each row; pass D copies the kept keys into the
+   final CSR.  No atomics: every slot and every row has exactly one writer. */
 typedef struct {
     const edge_src *s;
-    uint32_t *cnt;    /* n: pass 1 degree counts */
-    uint64_t *cur;    /* n: pass 2 write cursors */
-    uint32_t *rows;   /* scatter target */
-} build_ctx;
+    uint64_t nitems;
+    uint32_t nblk;     /* item blocks of the fixed split */
+    uint32_t nb;       /* buckets */
+    uint32_t shift;    /* bucket = u >> shift */
+    uint32_t vbits;    /* bits of a vertex id */
+    uint64_t *slot;    /* nblk x nb: counts, then write cursors */
+    uint64_t *keys;
+    uint64_t *bstart;  /* nb + 1 */
+    uint64_t *bkept;   /* nb */
+    uint32_t *deg;     /* n */
+    uint64_t *off;
+    uint32_t *col;
+    int pass;
+    int oom;
+} bctx;
 
-static inline void emit(build_ctx *c, int pass, uint32_t u, uint32_t v) {
-    if (pass == 0)
-        __atomic_fetch_add(&c->cnt[u], 1u, __ATOMIC_RELAXED);
-    else {
-        uint64_t p = __atomic_fetch_add(&c->cur[u], 1ull, __ATOMIC_RELAXED);
-        c->rows[p] = v;
-    }
+static inline void route(bctx *c, uint64_t blk, uint32_t u, uint32_t v) {
+    uint64_t *sl = &c->slot[blk * c->nb + (u >> c->shift)];
+    if (c->pass == 0)
+        (*sl)++;
+    else
+        c->keys[(*sl)++] = ((uint64_t)u << 32) | v;
 }
 
-static void sample_range(build_ctx *c, uint64_t lo, uint64_t hi, int pass) {
-    const edge_src *s = c->s;
-    for (uint64_t k = lo; k < hi; k++) {
-        uint32_t u, v;
-        switch (s->kind) {
-        case 0: rmat_sample(s, k, &u, &v); emit(c, pass, u, v); break;
-        case 1: er_sample(s, k, &u, &v); emit(c, pass, u, v); break;
-        case 2: emit(c, pass, s->ps[k], s->pd[k]); break;
-        default: {
-            /* k indexes source vertices of the CSR being symmetrized */
-            const gen_graph *g = s->g;
-            for (uint64_t e = g->off[k]; e < g->off[k + 1]; e++) {
-                emit(c, pass, (uint32_t)k, g->col[e]);
-                emit(c, pass, g->col[e], (uint32_t)k);
-            }
-        }
-        }
-    }
-}
-static void pass0_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) { (void)tid; sample_range((build_ctx *)ctx, lo, hi, 0); }
-static void pass1_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) { (void)tid; sample_range((build_ctx *)ctx, lo, hi, 1); }
-
-static int cmp_u32(const void *a, const void *b) {
-    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
-    return (x > y) - (x < y);
-}
-
-typedef struct {
-    uint64_t *rowbeg; /* n + 1 */
-    uint32_t *rows;
-    uint32_t *newdeg;
-} dedupe_ctx;
-
-/* sort each row, drop duplicates and self-loops; new length into newdeg */
-static void dedupe_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) {
+static void items_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) {
     (void)tid;
-    dedupe_ctx *c = (dedupe_ctx *)ctx;
-    for (uint64_t u = lo; u < hi; u++) {
-        uint32_t *r = c->rows + c->rowbeg[u];
-        uint64_t len = c->rowbeg[u + 1] - c->rowbeg[u];
-        if (len > 24) {
-            qsort(r, len, sizeof(uint32_t), cmp_u32);
-        } else {
-            for (uint64_t i = 1; i < len; i++) {
-                uint32_t x = r[i];
-                uint64_t j = i;
-                while (j > 0 && r[j - 1] > x) { r[j] = r[j - 1]; j--; }
-                r[j] = x;
+    bctx *c = (bctx *)ctx;
+    const edge_src *s = c->s;
+    for (uint64_t blk = lo; blk < hi; blk++) {
+        const uint64_t k0 = c->nitems * blk / c->nblk, k1 = c->nitems * (blk + 1) / c->nblk;
+        for (uint64_t k = k0; k < k1; k++) {
+            uint32_t u, v;
+            switch (s->kind) {
+            case 0: rmat_sample(s, k, &u, &v); route(c, blk, u, v); break;
+            case 1: er_sample(s, k, &u, &v); route(c, blk, u, v); break;
+            case 2: route(c, blk, s->ps[k], s->pd[k]); break;
+            default: {
+                /* k indexes source vertices of the CSR being symmetrized */
+                const gen_graph *g = s->g;
+                for (uint64_t e = g->off[k]; e < g->off[k + 1]; e++) {
+                    route(c, blk, (uint32_t)k, g->col[e]);
+                    route(c, blk, g->col[e], (uint32_t)k);
+                }
             }
+            }
+        }
+    }
+}
+
+#define RADIX_BITS 11
+static void sort_bucket_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) {
+    (void)tid;
+    bctx *c = (bctx *)ctx;
+    const uint64_t vmask = (c->vbits >= 32) ? 0xFFFFFFFFull : ((1ull << c->vbits) - 1);
+    const uint64_t umask = (1ull << c->shift) - 1;
+    const uint32_t nbits = c->shift + c->vbits;
+    for (uint64_t b = lo; b < hi; b++) {
+        uint64_t *k = c->keys + c->bstart[b];
+        const uint64_t len = c->bstart[b + 1] - c->bstart[b];
+        if (len <= 32) {
+            for (uint64_t i = 1; i < len; i++) {
+                uint64_t x = k[i], j = i;
+                while (j > 0 && k[j - 1] > x) { k[j] = k[j - 1]; j--; }
+                k[j] = x;
+            }
+        } else {
+            uint64_t *tmp = (uint64_t *)malloc(len * sizeof(uint64_t));
+            if (!tmp) { c->oom = 1; return; }
+            uint64_t *src = k, *dst = tmp;
+            static __thread uint64_t hist[1u << RADIX_BITS];
+            for (uint32_t sh = 0; sh < nbits; sh += RADIX_BITS) {
+                memset(hist, 0, sizeof(hist));
+                for (uint64_t i = 0; i < len; i++) {
+                    uint64_t ck = (((src[i] >> 32) & umask) << c->vbits) | (src[i] & vmask);
+                    hist[(ck >> sh) & ((1u << RADIX_BITS) - 1)]++;
+                }
+                uint64_t run = 0;
+                for (uint32_t d = 0; d < (1u << RADIX_BITS); d++) { uint64_t h = hist[d]; hist[d] = run; run += h; }
+                for (uint64_t i = 0; i < len; i++) {
+                    uint64_t ck = (((src[i] >> 32) & umask) << c->vbits) | (src[i] & vmask);
+                    dst[hist[(ck >> sh) & ((1u << RADIX_BITS) - 1)]++] = src[i];
+                }
+                uint64_t *t = src; src = dst; dst = t;
+            }
+            if (src != k) memcpy(k, src, len * sizeof(uint64_t));
+            free(tmp);
         }
         uint64_t w = 0;
         for (uint64_t i = 0; i < len; i++) {
-            if (r[i] == (uint32_t)u) continue;
-            if (w > 0 && r[w - 1] == r[i]) continue;
-            r[w++] = r[i];
+            const uint32_t u = (uint32_t)(k[i] >> 32), v = (uint32_t)k[i];
+            if (u == v) continue;
+            if (w > 0 && k[w - 1] == k[i]) continue;
+            k[w++] = k[i];
+            c->deg[u]++;
         }
-        c->newdeg[u] = (uint32_t)w;
+        c->bkept[b] = w;
     }
 }
 
-typedef struct {
-    uint64_t *rowbeg, *off;
-    uint32_t *rows, *col;
-} compact_ctx;
-static void compact_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) {
+static void write_rows_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) {
     (void)tid;
-    compact_ctx *c = (compact_ctx *)ctx;
-    for (uint64_t u = lo; u < hi; u++)
-        memcpy(c->col + c->off[u], c->rows + c->rowbeg[u], (c->off[u + 1] - c->off[u]) * sizeof(uint32_t));
+    bctx *c = (bctx *)ctx;
+    for (uint64_t b = lo; b < hi; b++) {
+        const uint64_t *k = c->keys + c->bstart[b];
+        uint32_t *out = c->col + c->off[b << c->shift];
+        for (uint64_t i = 0; i < c->bkept[b]; i++) out[i] = (uint32_t)k[i];
+    }
 }
 
-static gen_graph *build_csr(const edge_src *s, uint64_t n, uint64_t nitems, uint64_t chunk) {
+static gen_graph *build_csr(const edge_src *s, uint64_t n, uint64_t nitems) {
     gen_graph *g = (gen_graph *)calloc(1, sizeof(gen_graph));
     if (!g) return NULL;
     g->n = n;
-    uint32_t *cnt = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
-    uint64_t *rowbeg = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
-    if (!cnt || !rowbeg) goto fail_early;
-    build_ctx bc = {s, cnt, NULL, NULL};
-    parallel_for(nitems, chunk, pass0_fn, &bc);
-    rowbeg[0] = 0;
-    for (uint64_t u = 0; u < n; u++) rowbeg[u + 1] = rowbeg[u] + cnt[u];
-    uint64_t total = rowbeg[n];
-    free(cnt);
-    cnt = NULL;
-    uint32_t *rows = (uint32_t *)malloc((total ? total : 1) * sizeof(uint32_t));
-    uint64_t *cur = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
-    if (!rows || !cur) { free(rows); free(cur); goto fail_early; }
-    memcpy(cur, rowbeg, n * sizeof(uint64_t));
-    bc.cur = cur;
-    bc.rows = rows;
-    parallel_for(nitems, chunk, pass1_fn, &bc);
-    free(cur);
-    /* newdeg reuses a fresh array */
-    uint32_t *newdeg = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
-    if (!newdeg) { free(rows); goto fail_early; }
-    dedupe_ctx dc = {rowbeg, rows, newdeg};
-    parallel_for(n, 2048, dedupe_fn, &dc);
+    bctx c;
+    memset(&c, 0, sizeof(c));
+    c.s = s;
+    c.nitems = nitems;
+    c.vbits = 1;
+    while (c.vbits < 32 && (1ull << c.vbits) < n) c.vbits++;
+    const uint32_t bbits = c.vbits < 12 ? c.vbits : 12;
+    c.shift = c.vbits - bbits;
+    c.nb = 1u << bbits;
+    c.nblk = (uint32_t)(nitems < 4096 ? (nitems ? nitems : 1) : 4096);
+    c.slot = (uint64_t *)calloc((uint64_t)c.nblk * c.nb, sizeof(uint64_t));
+    c.bstart = (uint64_t *)malloc((c.nb + 1) * sizeof(uint64_t));
+    c.bkept = (uint64_t *)calloc(c.nb, sizeof(uint64_t));
+    c.deg = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
     g->off = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
-    if (!g->off) { free(rows); free(newdeg); goto fail_early; }
+    if (!c.slot || !c.bstart || !c.bkept || !c.deg || !g->off) goto fail;
+    c.pass = 0;
+    parallel_for(c.nblk, 1, items_fn, &c);
+    /* bucket-major, block-minor prefix: slot becomes each (block, bucket) cursor */
+    uint64_t run = 0;
+    for (uint32_t b = 0; b < c.nb; b++) {
+        c.bstart[b] = run;
+        for (uint32_t blk = 0; blk < c.nblk; blk++) {
+            uint64_t *sl = &c.slot[(uint64_t)blk * c.nb + b];
+            uint64_t h = *sl;
+            *sl = run;
+            run += h;
+        }
+    }
+    c.bstart[c.nb] = run;
+    c.keys = (uint64_t *)malloc((run ? run : 1) * sizeof(uint64_t));
+    if (!c.keys) goto fail;
+    c.pass = 1;
+    parallel_for(c.nblk, 1, items_fn, &c);
+    parallel_for(c.nb, 1, sort_bucket_fn, &c);
+    if (c.oom) goto fail;
     g->off[0] = 0;
-    for (uint64_t u = 0; u < n; u++) g->off[u + 1] = g->off[u] + newdeg[u];
-    free(newdeg);
+    for (uint64_t u = 0; u < n; u++) g->off[u + 1] = g->off[u] + c.deg[u];
     g->m = g->off[n];
     g->col = (uint32_t *)malloc((g->m ? g->m : 1) * sizeof(uint32_t));
-    if (!g->col) { free(rows); free(g->off); goto fail_early; }
-    compact_ctx cc = {rowbeg, g->off, rows, g->col};
-    parallel_for(n, 4096, compact_fn, &cc);
-    free(rows);
-    free(rowbeg);
+    if (!g->col) goto fail;
+    c.off = g->off;
+    c.col = g->col;
+    parallel_for(c.nb, 1, write_rows_fn, &c);
+    free(c.slot); free(c.bstart); free(c.bkept); free(c.deg); free(c.keys);
     return g;
-fail_early:
-    free(cnt);
-    free(rowbeg);
+fail:
+    free(c.slot); free(c.bstart); free(c.bkept); free(c.deg); free(c.keys);
+    free(g->off);
+    free(g->col);
     free(g);
     return NULL;
 }
@@ -277,7 +314,7 @@ gen_graph *gen_rmat(int scale, uint64_t nsamples, double a, double b, double c, 
     s.ta = ta >= two32 ? 0xFFFFFFFFu : (uint32_t)ta;
     s.tab = tab >= two32 ? 0xFFFFFFFFu : (uint32_t)tab;
     s.tabc = tabc >= two32 ? 0xFFFFFFFFu : (uint32_t)tabc;
-    return build_csr(&s, s.n, nsamples, 1u << 16);
+    return build_csr(&s, s.n, nsamples);
 }
 
 gen_graph *gen_er(uint64_t n, uint64_t nsamples, uint64_t seed) {
@@ -288,7 +325,7 @@ gen_graph *gen_er(uint64_t n, uint64_t nsamples, uint64_t seed) {
     s.n = n;
     s.nsamples = nsamples;
     s.seed = mix64(seed ^ 0x4552ULL); /* "ER" */
-    return build_csr(&s, n, nsamples, 1u << 16);
+    return build_csr(&s, n, nsamples);
 }
 
 /* explicit (src[i], dst[i]) pairs; every id must be < n */
@@ -301,7 +338,7 @@ gen_graph *gen_from_pairs(uint64_t n, uint64_t npairs, const uint32_t *src, cons
     s.n = n;
     s.ps = src;
     s.pd = dst;
-    return build_csr(&s, n, npairs, 1u << 16);
+    return build_csr(&s, n, npairs);
 }
 
 /* CSR of E union E^T */
@@ -311,7 +348,7 @@ gen_graph *gen_symmetrize(const gen_graph *g) {
     s.kind = 3;
     s.n = g->n;
     s.g = g;
-    return build_csr(&s, g->n, g->n, 4096);
+    return build_csr(&s, g->n, g->n);
 }
 
 /* symmetrize a caller-held CSR */
