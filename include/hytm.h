@@ -136,7 +136,41 @@ typedef struct {
     uint32_t iters_written;
     uint8_t *mode_trace;        /* caller buffer: iteration t's engine codes at t*npart, or NULL */
     uint64_t mode_trace_cap;    /* bytes */
+    /* Per-kernel timing.  Input: set time_kernels = 1 to bracket every launch with HIP
+       events on the stream it runs on (adds a little host work per launch).  Output,
+       indexed by HYTM_K_*: summed event time, launches, and items processed (edges for
+       the edge kernels, 128-byte lines for the zero-copy kernel, vertices otherwise). */
+    uint32_t time_kernels;
+    uint32_t reserved0;
+    double kernel_ms[8];
+    uint64_t kernel_launches[8];
+    uint64_t kernel_items[8];
 } hytm_run_stats;
+
+/* Kernel classes of hytm_run_stats.kernel_* */
+enum {
+    HYTM_K_STATS = 0,    /* per-partition statistics + engine selection */
+    HYTM_K_SCAN = 1,     /* per-engine prefix sums over partitions */
+    HYTM_K_LISTS = 2,    /* active-list compaction */
+    HYTM_K_PUSH_RES = 3, /* push over resident partitions */
+    HYTM_K_PUSH_F = 4,   /* push over a filter task's staging slot */
+    HYTM_K_PUSH_ZC = 5,  /* zero-copy push (mapped host reads) */
+    HYTM_K_PUSH_C = 6,   /* push over a compaction chunk */
+    HYTM_K_OTHER = 7     /* init, frontier clear, PageRank prepare/apply */
+};
+
+/* Host-link and HBM probe (calibration of the cost constants, Sec. 3.2 / Sec. 5.1). */
+typedef struct {
+    double h2d_copy_gbps;       /* hipMemcpyAsync pinned host -> device, best of 3 */
+    double d2h_copy_gbps;       /* device -> pinned host, best of 3 */
+    double zc_read_gbps[4];     /* kernel reads of mapped pinned memory, useful bytes/s, when each
+                                   128-byte line contributes 32, 64, 128 bytes, or whole 256-byte runs */
+    double hbm_copy_gbps;       /* device-to-device copy kernel, (read + write) bytes / s */
+} hytm_link_probe_result;
+
+/* Measure the host link and HBM on `hip_device` with `bytes` per transfer (>= 1 MiB).
+   Allocates and frees its own pinned and device buffers. */
+hytm_status hytm_link_probe(int hip_device, uint64_t bytes, hytm_link_probe_result *out);
 
 /* Static facts about a graph handle. */
 typedef struct {

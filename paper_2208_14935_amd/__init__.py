@@ -67,8 +67,19 @@ class RunStats(ctypes.Structure):
         ("compact_chunks", ctypes.c_uint64), ("ms_total", ctypes.c_double), ("ms_fill", ctypes.c_double),
         ("ms_select", ctypes.c_double), ("iters", ctypes.POINTER(IterStats)), ("iters_cap", ctypes.c_uint32),
         ("iters_written", ctypes.c_uint32), ("mode_trace", ctypes.POINTER(ctypes.c_uint8)),
-        ("mode_trace_cap", ctypes.c_uint64),
+        ("mode_trace_cap", ctypes.c_uint64), ("time_kernels", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+        ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_uint64 * 8),
+        ("kernel_items", ctypes.c_uint64 * 8),
     ]
+
+
+KERNEL_CLASSES = ["stats", "scan", "lists", "push_resident", "push_filter", "push_zerocopy", "push_compact",
+                  "other"]
+
+
+class LinkProbe(ctypes.Structure):
+    _fields_ = [("h2d_copy_gbps", ctypes.c_double), ("d2h_copy_gbps", ctypes.c_double),
+                ("zc_read_gbps", ctypes.c_double * 4), ("hbm_copy_gbps", ctypes.c_double)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -95,7 +106,19 @@ _SIGNATURES = {
                                            ctypes.c_void_p]),
     "hytm_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "hytm_last_error": (ctypes.c_char_p, []),
+    "hytm_link_probe": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(LinkProbe)]),
 }
+
+
+def link_probe(bytes_: int = 1 << 30, device: int = 0) -> dict:
+    """Pinned H2D/D2H copy, zero-copy read (32/64/128 B of every line, and streaming) and
+    HBM copy throughput in GB/s."""
+    r = LinkProbe()
+    _check(load().hytm_link_probe(device, int(bytes_), ctypes.byref(r)))
+    return {"h2d_copy_gbps": r.h2d_copy_gbps, "d2h_copy_gbps": r.d2h_copy_gbps,
+            "zc_read_gbps": {"32B": r.zc_read_gbps[0], "64B": r.zc_read_gbps[1], "128B": r.zc_read_gbps[2],
+                             "stream": r.zc_read_gbps[3]},
+            "hbm_copy_gbps": r.hbm_copy_gbps}
 
 _lib = None
 
@@ -249,7 +272,7 @@ class Graph:
         return b
 
     def run(self, algo: str, source: int = 0, stats: bool = False, trace: bool = False, stream=None,
-            out: np.ndarray | None = None) -> RunResult:
+            out: np.ndarray | None = None, time_kernels: bool = False) -> RunResult:
         lib = load()
         a = ALGOS[algo]
         dtype = np.float32 if a == 3 else np.uint32
@@ -257,9 +280,10 @@ class Graph:
         it = ctypes.c_uint32(0)
         st = None
         iters_buf = trace_buf = None
-        if stats or trace:
+        if stats or trace or time_kernels:
             st = RunStats()
             st.struct_size = ctypes.sizeof(RunStats)
+            st.time_kernels = 1 if time_kernels else 0
             cap = 4096
             iters_buf = (IterStats * cap)()
             st.iters = ctypes.cast(iters_buf, ctypes.POINTER(IterStats))
@@ -274,8 +298,10 @@ class Graph:
                             ctypes.byref(st) if st is not None else None, s))
         res = RunResult(vals, int(it.value))
         if st is not None:
-            res.stats = {k: (list(getattr(st, k)) if k == "part_iters" else getattr(st, k))
-                         for k, _ in RunStats._fields_ if k not in ("iters", "mode_trace", "struct_size")}
+            arrays = ("part_iters", "kernel_ms", "kernel_launches", "kernel_items")
+            res.stats = {k: (list(getattr(st, k)) if k in arrays else getattr(st, k))
+                         for k, _ in RunStats._fields_
+                         if k not in ("iters", "mode_trace", "struct_size", "reserved0", "time_kernels")}
             for t in range(st.iters_written):
                 r = iters_buf[t]
                 res.iters.append({k: (list(getattr(r, k)) if k == "parts" else getattr(r, k))

@@ -95,6 +95,13 @@ hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, fl
                              hipStream_t st);
 hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, hipStream_t st);
 
+// Probes of the host link and HBM.  words_per_line in {8, 16, 32}: each 128-byte line
+// of the mapped buffer contributes that many leading 4-byte words; 0 = stream the whole
+// buffer with 16-byte loads.
+hipError_t launch_zc_probe(const uint32_t* src, uint64_t bytes, uint32_t words_per_line, uint32_t* sink,
+                           hipStream_t st);
+hipError_t launch_copy_probe(void* dst, const void* src, uint64_t bytes, hipStream_t st);
+
 hipError_t launch_select_only(uint64_t npart, const uint64_t* E, const uint64_t* nA, const uint64_t* Ea,
                               const uint64_t* Rq, const SelParams& sp, uint8_t* p, hipStream_t st);
 

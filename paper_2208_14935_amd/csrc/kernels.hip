@@ -569,6 +569,36 @@ __global__ void k_pr_apply(uint64_t n, float* __restrict__ x, const float* __res
         x[v] = base + damping * acc[v];
 }
 
+// ------------------------------------------------------------------ probes
+__global__ __launch_bounds__(256) void k_zc_probe_lines(const uint32_t* __restrict__ src, uint64_t nlines,
+                                                        uint32_t wpl, uint32_t* __restrict__ sink) {
+    const uint32_t lane = threadIdx.x & 31;
+    const uint64_t half = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 5;
+    const uint64_t halves = ((uint64_t)gridDim.x * blockDim.x) >> 5;
+    uint32_t acc = 0;
+    for (uint64_t line = half; line < nlines; line += halves)
+        if (lane < wpl) acc += src[(line << 5) + lane];
+    if (acc == 0x9E3779B9u) sink[0] = acc;  // keeps the loads; practically never true
+}
+
+__global__ __launch_bounds__(256) void k_zc_probe_stream(const uint4* __restrict__ src, uint64_t n16,
+                                                         uint32_t* __restrict__ sink) {
+    uint32_t acc = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n16;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint4 v = src[i];
+        acc += v.x ^ v.y ^ v.z ^ v.w;
+    }
+    if (acc == 0x9E3779B9u) sink[0] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_copy_probe(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                    uint64_t n16) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n16;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 inline unsigned grid_for(uint64_t items, unsigned per_block, unsigned cap) {
     uint64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -686,6 +716,20 @@ hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, fl
 hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, hipStream_t st) {
     if (!n) return hipSuccess;
     k_pr_apply<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, x, acc, base, damping);
+    return hipGetLastError();
+}
+
+hipError_t launch_zc_probe(const uint32_t* src, uint64_t bytes, uint32_t words_per_line, uint32_t* sink,
+                           hipStream_t st) {
+    if (words_per_line == 0)
+        k_zc_probe_stream<<<4096, 256, 0, st>>>((const uint4*)src, bytes / 16, sink);
+    else
+        k_zc_probe_lines<<<4096, 256, 0, st>>>(src, bytes / 128, words_per_line, sink);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(void* dst, const void* src, uint64_t bytes, hipStream_t st) {
+    k_copy_probe<<<8192, 256, 0, st>>>((uint4*)dst, (const uint4*)src, bytes / 16);
     return hipGetLastError();
 }
 

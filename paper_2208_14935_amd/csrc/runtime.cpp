@@ -105,6 +105,62 @@ struct HostBuf {  // pinned host memory
 };
 
 constexpr uint32_t kMaxSlots = 16;
+constexpr int kClasses = 8;
+
+// Optional per-launch HIP-event timing, by kernel class (HYTM_K_*).  Launches may come
+// from the main thread and the compaction thread, hence the lock.
+struct KTimer {
+    bool on = false;
+    std::mutex mu;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+        uint64_t items;
+    };
+    std::vector<Rec> recs;
+
+    template <class F>
+    hipError_t run(int cls, uint64_t items, hipStream_t st, F&& launch) {
+        if (!on) return launch();
+        std::lock_guard<std::mutex> lk(mu);
+        hipEvent_t a = take(), b = take();
+        hipError_t e = hipEventRecord(a, st);
+        if (e != hipSuccess) return e;
+        e = launch();
+        if (e != hipSuccess) return e;
+        e = hipEventRecord(b, st);
+        if (e == hipSuccess) recs.push_back({cls, a, b, items});
+        return e;
+    }
+    hipEvent_t take() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            HIP_CHECK(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    // after every recorded launch has completed
+    void collect(double* ms, uint64_t* launches, uint64_t* items) {
+        for (const Rec& r : recs) {
+            float t = 0;
+            HIP_CHECK(hipEventElapsedTime(&t, r.a, r.b));
+            ms[r.cls] += t;
+            launches[r.cls] += 1;
+            items[r.cls] += r.items;
+        }
+        recs.clear();
+        used = 0;
+    }
+    void destroy() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+        recs.clear();
+        used = 0;
+    }
+};
 
 }  // namespace
 
@@ -163,6 +219,7 @@ struct hytm_graph {
     hipEvent_t ev_cdone[2] = {}, ev_join[4] = {}, ev_start = nullptr, ev_clist = nullptr;
 
     Pool* pool = nullptr;
+    KTimer timer;
 };
 
 namespace {
@@ -385,6 +442,7 @@ void release_all(hytm_graph* g) {
     if (g->ev_clist) (void)hipEventDestroy(g->ev_clist);
     delete g->pool;
     g->pool = nullptr;
+    g->timer.destroy();
 }
 
 void parallel_copy(void* dst, const void* src, size_t bytes) {
@@ -468,8 +526,10 @@ void run_compaction(RunCtx* rc, uint32_t cs, uint32_t cc, uint64_t w0, uint64_t 
             if (rc->arrays == 2)
                 HIP_CHECK(hipMemcpyAsync(g->d_cbuf_w[b].p, g->h_cbuf_w[b].p, (x1 - x0) * 4, hipMemcpyHostToDevice,
                                          g->s_c));
-            HIP_CHECK(launch_push_edges(rc->as, g->d_list.p, g->d_wpre.p, cs, cs + cc, x0, x1, g->d_off.p,
-                                        g->d_cbuf_col[b].p, g->d_cbuf_w[b].p, x0, true, g->s_c));
+            HIP_CHECK(g->timer.run(HYTM_K_PUSH_C, x1 - x0, g->s_c, [&] {
+                return launch_push_edges(rc->as, g->d_list.p, g->d_wpre.p, cs, cs + cc, x0, x1, g->d_off.p,
+                                         g->d_cbuf_col[b].p, g->d_cbuf_w[b].p, x0, true, g->s_c);
+            }));
             HIP_CHECK(hipEventRecord(g->ev_cdone[b], g->s_c));
             *bytes += (x1 - x0) * 4 * rc->arrays;
             *chunks += 1;
@@ -504,6 +564,10 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
     rc.sp.allow_filter = rc.plan.allow_filter || g->budget == UINT64_MAX;
     rc.sp.allow_compact = rc.plan.allow_compact || g->budget == UINT64_MAX;
     hipStream_t main = hip_stream ? (hipStream_t)hip_stream : g->s_main;
+    KTimer& kt = g->timer;
+    kt.on = stats && stats->time_kernels;
+    kt.recs.clear();
+    kt.used = 0;
 
     const uint64_t n = g->n;
     const uint32_t nwords = (uint32_t)((n + 31) / 32);
@@ -591,7 +655,8 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
     as.acc = g->d_acc.p;
     as.contrib = g->d_contrib.p;
     const float x0 = n ? (float)(1.0 / (double)n) : 0.f;
-    HIP_CHECK(launch_init(as, n, source, x0, g->d_x.p, g->d_cur.p, nwords, main));
+    HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
+                     [&] { return launch_init(as, n, source, x0, g->d_x.p, g->d_cur.p, nwords, main); }));
     uint32_t* cur = g->d_cur.p;
     uint32_t* nxt = g->d_next.p;
 
@@ -608,14 +673,23 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
     for (uint32_t t = 0;; t++) {
         if (algo == HYTM_PAGERANK && t >= T) break;
         const double t_it = now_ms();
-        if (algo == HYTM_PAGERANK) HIP_CHECK(launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, main));
+        if (algo == HYTM_PAGERANK)
+            HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
+                return launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, main);
+            }));
         // 1. statistics, engine selection, active lists (Algorithm 1, GPU part)
-        HIP_CHECK(launch_stats_select(npart, g->d_pv.p, g->d_off.p, cur, rc.sp, g->d_mode.p, g->d_nA.p, g->d_nF.p,
-                                      g->d_Ea.p, g->d_Rq.p, g->d_K.p, main));
-        HIP_CHECK(launch_scan(npart, g->d_mode.p, g->d_nA.p, g->d_nF.p, g->d_Ea.p, g->d_Rq.p, g->d_K.p,
-                              g->d_lbase.p, g->d_wbase.p, g->d_hdr.p, g->d_wpre.p, main));
-        HIP_CHECK(launch_build_lists(npart, g->d_pv.p, g->d_off.p, cur, g->d_mode.p, g->d_lbase.p, g->d_wbase.p,
-                                     g->d_list.p, g->d_wpre.p, main));
+        HIP_CHECK(kt.run(HYTM_K_STATS, npart, main, [&] {
+            return launch_stats_select(npart, g->d_pv.p, g->d_off.p, cur, rc.sp, g->d_mode.p, g->d_nA.p, g->d_nF.p,
+                                       g->d_Ea.p, g->d_Rq.p, g->d_K.p, main);
+        }));
+        HIP_CHECK(kt.run(HYTM_K_SCAN, npart, main, [&] {
+            return launch_scan(npart, g->d_mode.p, g->d_nA.p, g->d_nF.p, g->d_Ea.p, g->d_Rq.p, g->d_K.p,
+                               g->d_lbase.p, g->d_wbase.p, g->d_hdr.p, g->d_wpre.p, main);
+        }));
+        HIP_CHECK(kt.run(HYTM_K_LISTS, npart, main, [&] {
+            return launch_build_lists(npart, g->d_pv.p, g->d_off.p, cur, g->d_mode.p, g->d_lbase.p, g->d_wbase.p,
+                                      g->d_list.p, g->d_wpre.p, main);
+        }));
         // 2. selection back to the host (Algorithm 1: copy Vc, p and A to host)
         HIP_CHECK(hipMemcpyAsync(g->h_hdr.p, g->d_hdr.p, sizeof(Header), hipMemcpyDeviceToHost, main));
         HIP_CHECK(hipMemcpyAsync(g->h_mode.p, g->d_mode.p, npart, hipMemcpyDeviceToHost, main));
@@ -643,16 +717,20 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
         as.level_next = t + 1;
         // resident partitions: no transfer
         if (h.seg_list_count[SEG_R])
-            HIP_CHECK(launch_push_edges(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_R],
-                                        h.seg_list_start[SEG_R] + h.seg_list_count[SEG_R], h.seg_work_start[SEG_R],
-                                        h.seg_work_start[SEG_R] + h.seg_work_total[SEG_R], g->d_off.p,
-                                        g->d_res_col.p, g->d_res_w.p, 0, false, main));
+            HIP_CHECK(kt.run(HYTM_K_PUSH_RES, h.seg_work_total[SEG_R], main, [&] {
+                return launch_push_edges(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_R],
+                                         h.seg_list_start[SEG_R] + h.seg_list_count[SEG_R], h.seg_work_start[SEG_R],
+                                         h.seg_work_start[SEG_R] + h.seg_work_total[SEG_R], g->d_off.p,
+                                         g->d_res_col.p, g->d_res_w.p, 0, false, main);
+            }));
         // zero-copy: one kernel over all zero-copy vertices (Vz)
         if (h.seg_list_count[SEG_Z]) {
-            HIP_CHECK(launch_push_lines(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_Z],
-                                        h.seg_list_start[SEG_Z] + h.seg_list_count[SEG_Z], h.seg_work_start[SEG_Z],
-                                        h.seg_work_start[SEG_Z] + h.seg_work_total[SEG_Z], g->d_off.p,
-                                        g->d_col_map, g->d_w_map, g->s_zc));
+            HIP_CHECK(kt.run(HYTM_K_PUSH_ZC, h.seg_work_total[SEG_Z], g->s_zc, [&] {
+                return launch_push_lines(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_Z],
+                                         h.seg_list_start[SEG_Z] + h.seg_list_count[SEG_Z], h.seg_work_start[SEG_Z],
+                                         h.seg_work_start[SEG_Z] + h.seg_work_total[SEG_Z], g->d_off.p,
+                                         g->d_col_map, g->d_w_map, g->s_zc);
+            }));
             rec.zc_lines = h.seg_work_total[SEG_Z];
         }
         // compaction: gathered by host threads, overlapping the filter tasks below
@@ -702,8 +780,10 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
                                                  g->s_copy));
                     HIP_CHECK(hipEventRecord(g->ev_copied[s], g->s_copy));
                     HIP_CHECK(hipStreamWaitEvent(g->s_fk, g->ev_copied[s], 0));
-                    HIP_CHECK(launch_push_edges(as, g->d_list.p, g->d_wpre.p, ja, jb, wa, wb, g->d_off.p,
-                                                g->d_slot_col[s].p, g->d_slot_w[s].p, ebeg, false, g->s_fk));
+                    HIP_CHECK(kt.run(HYTM_K_PUSH_F, wb - wa, g->s_fk, [&] {
+                        return launch_push_edges(as, g->d_list.p, g->d_wpre.p, ja, jb, wa, wb, g->d_off.p,
+                                                 g->d_slot_col[s].p, g->d_slot_w[s].p, ebeg, false, g->s_fk);
+                    }));
                     HIP_CHECK(hipEventRecord(g->ev_free[s], g->s_fk));
                     rec.bytes_filter += edges * d1b;
                     gidx++;
@@ -729,11 +809,12 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
         HIP_CHECK(hipEventRecord(g->ev_join[2], g->s_c));
         for (int q = 0; q < 3; q++) HIP_CHECK(hipStreamWaitEvent(main, g->ev_join[q], 0));
         if (algo == HYTM_PAGERANK) {
-            HIP_CHECK(launch_pr_apply(n, g->d_x.p, g->d_acc.p, pr_base, pr_d, main));
+            HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
+                             [&] { return launch_pr_apply(n, g->d_x.p, g->d_acc.p, pr_base, pr_d, main); }));
         } else {
             std::swap(cur, nxt);
             as.next = nxt;
-            HIP_CHECK(launch_fill_u32(nxt, nwords, 0u, main));
+            HIP_CHECK(kt.run(HYTM_K_OTHER, nwords, main, [&] { return launch_fill_u32(nxt, nwords, 0u, main); }));
         }
         for (int s = 0; s < 5; s++) part_iters[s] += rec.parts[s];
         tot_av += rec.active_vertices;
@@ -760,6 +841,16 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
     const double t_end = now_ms();
     if (iterations_out) *iterations_out = iters;
     if (stats) {
+        if (kt.on) {
+            // every engine joined the main stream before it was synchronised above
+            for (int c = 0; c < kClasses; c++) {
+                stats->kernel_ms[c] = 0;
+                stats->kernel_launches[c] = 0;
+                stats->kernel_items[c] = 0;
+            }
+            kt.collect(stats->kernel_ms, stats->kernel_launches, stats->kernel_items);
+            kt.on = false;
+        }
         stats->iterations = iters;
         stats->npart = npart;
         stats->nres = pl.nres;
@@ -1021,6 +1112,65 @@ hytm_status hytm_select_engines(hytm_graph* g, uint64_t npart, const uint64_t* E
         HIP_CHECK(hipStreamSynchronize(g->s_main));
         return HYTM_OK;
     });
+}
+
+hytm_status hytm_link_probe(int hip_device, uint64_t bytes, hytm_link_probe_result* out) {
+    g_err.clear();
+    if (!out) return fail(HYTM_E_INVAL, "out is NULL");
+    if (bytes < (1u << 20)) return fail(HYTM_E_INVAL, "probe size must be at least 1 MiB");
+    bytes &= ~uint64_t(255);
+    uint32_t* host = nullptr;
+    void *dev = nullptr, *dev2 = nullptr;
+    uint32_t* sink = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    hytm_status status = guarded([&]() -> hytm_status {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count)
+            return fail(HYTM_E_DEVICE, "HIP device %d is not available", hip_device);
+        HIP_CHECK(hipSetDevice(hip_device));
+        HIP_CHECK(hipHostMalloc((void**)&host, bytes, hipHostMallocMapped));
+        memset(host, 1, bytes);
+        uint32_t* dmap = nullptr;
+        HIP_CHECK(hipHostGetDevicePointer((void**)&dmap, host, 0));
+        HIP_CHECK(hipMalloc(&dev, bytes));
+        HIP_CHECK(hipMalloc(&dev2, bytes));
+        HIP_CHECK(hipMalloc((void**)&sink, 64));
+        HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreate(&a));
+        HIP_CHECK(hipEventCreate(&b));
+        auto best_of = [&](auto&& op) {
+            float best = 1e30f;
+            for (int r = 0; r < 4; r++) {  // the first repetition warms up
+                HIP_CHECK(hipEventRecord(a, st));
+                HIP_CHECK(op());
+                HIP_CHECK(hipEventRecord(b, st));
+                HIP_CHECK(hipEventSynchronize(b));
+                float ms = 0;
+                HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+                if (r > 0) best = std::min(best, ms);
+            }
+            return (double)best;
+        };
+        const double gb = (double)bytes / 1e9;
+        out->h2d_copy_gbps = gb / (best_of([&] { return hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, st); }) / 1e3);
+        out->d2h_copy_gbps = gb / (best_of([&] { return hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st); }) / 1e3);
+        const uint32_t wpl[4] = {8, 16, 32, 0};
+        for (int i = 0; i < 4; i++) {
+            const double useful = wpl[i] ? gb * wpl[i] * 4 / 128.0 : gb;
+            out->zc_read_gbps[i] = useful / (best_of([&] { return launch_zc_probe(dmap, bytes, wpl[i], sink, st); }) / 1e3);
+        }
+        out->hbm_copy_gbps = 2 * gb / (best_of([&] { return launch_copy_probe(dev2, dev, bytes, st); }) / 1e3);
+        return HYTM_OK;
+    });
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (st) (void)hipStreamDestroy(st);
+    if (sink) (void)hipFree(sink);
+    if (dev) (void)hipFree(dev);
+    if (dev2) (void)hipFree(dev2);
+    if (host) (void)hipHostFree(host);
+    return status;
 }
 
 hytm_status hytm_graph_destroy(hytm_graph* g) {
