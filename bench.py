@@ -54,6 +54,10 @@ def main():
     ap.add_argument("--mode", default="hybrid", choices=list(hy.MODES))
     ap.add_argument("--partition-edges", type=int, default=32768)
     ap.add_argument("--combine-k", type=int, default=4)
+    ap.add_argument("--filter-engine", default="stream", choices=list(hy.FILTER_ENGINES))
+    ap.add_argument("--gamma", default="probe",
+                    help="zero-copy damping: 'probe' (from the measured partial-line cost), "
+                         "'paper' (5/8) or num/den")
     ap.add_argument("--algos", default="bfs,sssp,cc,pagerank")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -83,9 +87,12 @@ def main():
     g = hy.Graph(off, col, weights=w, check_col=False)
     gs = hy.Graph(soff, scol, symmetric=True, check_col=False) if scol is not None else None
     log(f"pinned graph copies {time.time() - t0:.1f}s")
+    gamma = gamma_from(args.gamma, probe)
+    log(f"gamma = {gamma[0]}/{gamma[1]}")
     for h in (g, gs):
         if h is not None:
-            h.set_params(mode=args.mode, partition_edges=args.partition_edges, combine_k=args.combine_k)
+            h.set_params(mode=args.mode, partition_edges=args.partition_edges, combine_k=args.combine_k,
+                         filter_engine=args.filter_engine, gamma=gamma)
 
     def budget(h, arrays):
         h.set_budget(int(args.budget_frac * 4 * arrays * h.m))
@@ -214,7 +221,7 @@ def main():
                    "n": n, "m": m, "m_sym": int(gs.m) if gs is not None else None,
                    "sources": [int(s) for s in srcs], "budget_frac_of_edge_bytes": args.budget_frac,
                    "partition_edges": args.partition_edges, "combine_k": args.combine_k, "mode": args.mode,
-                   "algos": algos},
+                   "filter_engine": args.filter_engine, "gamma": list(gamma), "algos": algos},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "host_link": host_link,
@@ -223,6 +230,25 @@ def main():
         "probe": probe,
     }
     print(json.dumps(out), flush=True)
+
+
+def gamma_from(spec, probe):
+    """RTTzc = gamma*RTT + (1-gamma)*ratio*RTT prices a zero-copy request as a fixed part
+    plus a part proportional to its payload.  From the probe, a line read for a fraction f
+    of its bytes takes time proportional to f*U(1)/U(f) (U = useful GB/s); solving
+    gamma + (1-gamma)*f = f*U(1)/U(f) at f = 1/4 and 1/2 and averaging gives gamma."""
+    if spec == "paper":
+        return (5, 8)
+    if spec != "probe":
+        a, b = spec.split("/")
+        return (int(a), int(b))
+    u = probe["zc_read_gbps"]
+    est = []
+    for f, key in ((0.25, "32B"), (0.5, "64B")):
+        t = f * u["128B"] / u[key]
+        est.append((t - f) / (1 - f))
+    gam = min(1.0, max(0.0, sum(est) / len(est)))
+    return (int(round(gam * 64)), 64)
 
 
 def cpu_baseline(off, col, w, soff, scol, srcs, algos):

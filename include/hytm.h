@@ -96,7 +96,18 @@ typedef struct {
     uint32_t streams;           /* 4: staging slots of the filter pipeline (>= 2) */
     uint32_t gather_threads;    /* 0 = automatic: host threads of the compaction engine */
     uint64_t compact_chunk_edges; /* 0 = automatic: edges per compaction chunk */
+    uint32_t filter_engine;     /* HYTM_FILTER_STREAM (default) or HYTM_FILTER_COPY, see below */
+    uint32_t reserved0;
 } hytm_params;
+
+/* How a FILTER task moves its whole partition range to the GPU.  Both transfer every
+   byte of the task's partitions, which is what Eq. 1 prices.
+   STREAM: one kernel per iteration reads every 128-byte line of every filter task from
+           the mapped pinned arrays, in order, and pushes the edges of active vertices;
+           no staging memory, no per-task host calls.
+   COPY:   per task, hipMemcpyAsync into a ring of `streams` device staging slots, then
+           a push kernel over the slot (the explicit-copy form of Sec. 2.2). */
+enum { HYTM_FILTER_STREAM = 0, HYTM_FILTER_COPY = 1 };
 
 /* Per-iteration record (optional, see hytm_run_stats.iters). */
 typedef struct {

@@ -45,8 +45,12 @@ class Params(ctypes.Structure):
         ("gamma_den", ctypes.c_uint32), ("line_bytes", ctypes.c_uint32), ("max_outstanding", ctypes.c_uint32),
         ("index_bytes", ctypes.c_uint32), ("pr_iterations", ctypes.c_uint32), ("pr_damping", ctypes.c_double),
         ("streams", ctypes.c_uint32), ("gather_threads", ctypes.c_uint32),
-        ("compact_chunk_edges", ctypes.c_uint64),
+        ("compact_chunk_edges", ctypes.c_uint64), ("filter_engine", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
     ]
+
+
+FILTER_ENGINES = {"stream": 0, "copy": 1}
 
 
 class IterStats(ctypes.Structure):
@@ -238,6 +242,8 @@ class Graph:
         for k, v in kw.items():
             if k == "mode" and isinstance(v, str):
                 v = MODES[v]
+            if k == "filter_engine" and isinstance(v, str):
+                v = FILTER_ENGINES[v]
             if k in ("alpha", "beta", "gamma"):
                 setattr(p, k + "_num", int(v[0]))
                 setattr(p, k + "_den", int(v[1]))

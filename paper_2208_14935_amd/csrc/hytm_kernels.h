@@ -91,6 +91,34 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
                              uint32_t jb, uint64_t item_lo, uint64_t item_hi, const uint64_t* off,
                              const uint32_t* col, const uint32_t* w, hipStream_t st);
 
+// A filter task streamed from the mapped host arrays: edges [e0, e1) of a run of
+// consecutive filter partitions whose active vertices are list entries [ja, jb).
+// chunk0 = chunks of all earlier tasks (a chunk is FSTREAM_LINES 128-byte lines).
+struct FTask {
+    uint64_t e0, e1;
+    uint32_t ja, jb;
+    uint64_t chunk0;
+};
+constexpr uint32_t FSTREAM_LINES = 64;
+inline uint64_t fstream_chunks(uint64_t e0, uint64_t e1) {
+    const uint64_t lines = ((e1 - 1) >> ZC_LINE_SHIFT) - (e0 >> ZC_LINE_SHIFT) + 1;
+    return (lines + FSTREAM_LINES - 1) / FSTREAM_LINES;
+}
+
+// Filter engine, streaming form: every line of every task is read once from host
+// memory (the whole partition is transferred); edges of active vertices are pushed.
+hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t ntasks, uint64_t total_chunks,
+                               const uint32_t* list, const uint64_t* off, const uint32_t* col, const uint32_t* w,
+                               hipStream_t st);
+
+// PageRank accumulator slot of vertex v: the low 12 bits are XORed with a hash of the
+// high bits (a bijection on each 4096-aligned block) so that the R-MAT hubs, whose ids
+// share many zero bits, spread over the L2 channels instead of piling onto one.
+__host__ __device__ inline uint32_t acc_slot(uint32_t v) {
+    return v ^ (((v >> 12) * 0x9E3779B1u) >> 20);
+}
+__host__ __device__ inline uint64_t acc_slots(uint64_t n) { return (n + 4095) & ~uint64_t(4095); }
+
 hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
                              hipStream_t st);
 hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, hipStream_t st);

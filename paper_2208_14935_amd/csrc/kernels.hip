@@ -375,7 +375,7 @@ struct OpPr {
     const float* contrib;
     __device__ __forceinline__ uint32_t src(uint32_t u) const { return __float_as_uint(contrib[u]); }
     __device__ __forceinline__ void push(uint32_t c, uint32_t v, uint32_t) const {
-        unsafeAtomicAdd(acc + v, __uint_as_float(c));
+        unsafeAtomicAdd(acc + acc_slot(v), __uint_as_float(c));
     }
 };
 
@@ -554,10 +554,13 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t va
 
 __global__ void k_pr_prepare(uint64_t n, const uint64_t* __restrict__ off, const float* __restrict__ x,
                              float* __restrict__ contrib, float* __restrict__ acc) {
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+    const uint64_t slots = acc_slots(n);
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < slots;
          v += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t d = off[v + 1] - off[v];
-        contrib[v] = d ? x[v] / (float)d : 0.0f;
+        if (v < n) {
+            const uint64_t d = off[v + 1] - off[v];
+            contrib[v] = d ? x[v] / (float)d : 0.0f;
+        }
         acc[v] = 0.0f;
     }
 }
@@ -566,7 +569,105 @@ __global__ void k_pr_apply(uint64_t n, float* __restrict__ x, const float* __res
                            float damping) {
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
          v += (uint64_t)gridDim.x * blockDim.x)
-        x[v] = base + damping * acc[v];
+        x[v] = base + damping * acc[acc_slot((uint32_t)v)];
+}
+
+// ---------------------------------------------------------- filter stream
+// One workgroup pass = one chunk of FSTREAM_LINES lines of one task.  All lines of the
+// chunk are loaded (the filter engine transfers whole partitions); an edge is pushed
+// when it lies in the out-edge range of one of the task's active vertices.
+template <class Op>
+__global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __restrict__ tasks, uint32_t ntasks,
+                                                               uint64_t total_chunks,
+                                                               const uint32_t* __restrict__ list,
+                                                               const uint64_t* __restrict__ off,
+                                                               const uint32_t* __restrict__ col,
+                                                               const uint32_t* __restrict__ w, Op op) {
+    constexpr uint32_t MAXV = FSTREAM_LINES * 32;
+    constexpr int UNROLL = FSTREAM_LINES / LINE_HALVES;
+    __shared__ uint64_t s_s[MAXV];
+    __shared__ uint64_t s_e[MAXV];
+    __shared__ uint32_t s_val[MAXV];
+    __shared__ uint32_t s_t, s_j0, s_nv;
+    const uint32_t half = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    for (uint64_t c = blockIdx.x; c < total_chunks; c += gridDim.x) {
+        if (threadIdx.x == 0) {
+            // task of chunk c: last t with tasks[t].chunk0 <= c
+            uint32_t lo = 0, hi = ntasks;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (tasks[mid].chunk0 <= c)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            s_t = lo;
+        }
+        __syncthreads();
+        const FTask t = tasks[s_t];
+        const uint64_t line0 = (t.e0 >> ZC_LINE_SHIFT) + (c - t.chunk0) * FSTREAM_LINES;
+        const uint64_t ce0 = max(t.e0, line0 << ZC_LINE_SHIFT);
+        const uint64_t ce1 = min(t.e1, (line0 + FSTREAM_LINES) << ZC_LINE_SHIFT);
+        if (threadIdx.x == 0) {
+            // active vertices whose ranges meet [ce0, ce1): j in [jlo, jhi)
+            uint32_t lo = t.ja, hi = t.jb;  // first j with off[list[j] + 1] > ce0
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (off[list[mid] + 1] > ce0)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            const uint32_t jlo = lo;
+            hi = t.jb;  // first j with off[list[j]] >= ce1
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (off[list[mid]] >= ce1)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            s_j0 = jlo;
+            s_nv = lo - jlo;
+        }
+        __syncthreads();
+        const uint32_t j0 = s_j0, nv = s_nv;
+        for (uint32_t k = threadIdx.x; k < nv; k += LINE_THREADS) {
+            const uint32_t v = list[j0 + k];
+            s_s[k] = off[v];
+            s_e[k] = off[v + 1];
+            s_val[k] = op.src(v);
+        }
+        __syncthreads();
+        uint32_t cv[UNROLL], wv[UNROLL];
+#pragma unroll
+        for (int r = 0; r < UNROLL; r++) {
+            const uint64_t e = ((line0 + half + (uint64_t)LINE_HALVES * r) << ZC_LINE_SHIFT) + lane;
+            cv[r] = 0;
+            wv[r] = 0;
+            if (e >= ce0 && e < ce1) {
+                cv[r] = col[e];
+                if (Op::weighted) wv[r] = w[e];
+            }
+        }
+        if (nv > 0) {
+#pragma unroll
+            for (int r = 0; r < UNROLL; r++) {
+                const uint64_t e = ((line0 + half + (uint64_t)LINE_HALVES * r) << ZC_LINE_SHIFT) + lane;
+                if (e < ce0 || e >= ce1 || e < s_s[0]) continue;
+                uint32_t lo = 0, hi = nv;  // last k with s_s[k] <= e
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (s_s[mid] <= e)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                if (e < s_e[lo]) op.push(s_val[lo], cv[r], wv[r]);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------ probes
@@ -709,8 +810,34 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
 hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
                              hipStream_t st) {
     if (!n) return hipSuccess;
-    k_pr_prepare<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, off, x, contrib, acc);
+    k_pr_prepare<<<grid_for(acc_slots(n), 256, 8192), 256, 0, st>>>(n, off, x, contrib, acc);
     return hipGetLastError();
+}
+
+template <class Op>
+static hipError_t push_fstream_op(const Op& op, const FTask* tasks, uint32_t ntasks, uint64_t chunks,
+                                  const uint32_t* list, const uint64_t* off, const uint32_t* col, const uint32_t* w,
+                                  hipStream_t st) {
+    const unsigned g = (unsigned)(chunks < GRID_CAP ? chunks : GRID_CAP);
+    k_push_fstream<Op><<<g, LINE_THREADS, 0, st>>>(tasks, ntasks, chunks, list, off, col, w, op);
+    return hipGetLastError();
+}
+
+hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t ntasks, uint64_t total_chunks,
+                               const uint32_t* list, const uint64_t* off, const uint32_t* col, const uint32_t* w,
+                               hipStream_t st) {
+    if (!ntasks || !total_chunks) return hipSuccess;
+    switch (s.algo) {
+    case ALGO_BFS:
+        return push_fstream_op(OpBfs{s.visited, s.next, s.val, s.level_next}, tasks, ntasks, total_chunks, list,
+                               off, col, w, st);
+    case ALGO_SSSP:
+        return push_fstream_op(OpSssp{s.val, s.next, s.overflow}, tasks, ntasks, total_chunks, list, off, col, w, st);
+    case ALGO_CC:
+        return push_fstream_op(OpCc{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, st);
+    default:
+        return push_fstream_op(OpPr{s.acc, s.contrib}, tasks, ntasks, total_chunks, list, off, col, w, st);
+    }
 }
 
 hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, hipStream_t st) {

@@ -195,6 +195,8 @@ struct hytm_graph {
     DevBuf<Header> d_hdr;
     DevBuf<uint64_t> d_sel_in;  // hytm_select_engines scratch
     DevBuf<uint8_t> d_sel_out;
+    DevBuf<FTask> d_tasks;        // streaming filter tasks of the current iteration
+    HostBuf<FTask> h_tasks;
 
     // host mirrors of the per-iteration selection
     HostBuf<Header> h_hdr;
@@ -242,6 +244,8 @@ bool params_valid(const hytm_params& p, std::string* why) {
     if (!(p.pr_damping >= 0.0 && p.pr_damping <= 1.0)) return bad("pr_damping must be in [0, 1]");
     if (p.streams < 2 || p.streams > kMaxSlots) return bad("streams must be in 2..16");
     if (p.gather_threads > 256) return bad("gather_threads must be <= 256");
+    if (p.filter_engine != HYTM_FILTER_STREAM && p.filter_engine != HYTM_FILTER_COPY)
+        return bad("filter_engine must be HYTM_FILTER_STREAM or HYTM_FILTER_COPY");
     return true;
 }
 
@@ -321,7 +325,8 @@ Staging staging_of(const hytm_graph* g, uint32_t arrays) {
     Staging s;
     s.slot_edges = std::max<uint64_t>((uint64_t)p.combine_k * p.partition_edges, g->max_part_edges);
     s.cchunk = p.compact_chunk_edges ? p.compact_chunk_edges : std::max<uint64_t>(s.slot_edges, 1ull << 22);
-    s.f_bytes = s.slot_edges * p.streams * d1;
+    // the streaming filter engine reads host memory directly and stages nothing
+    s.f_bytes = p.filter_engine == HYTM_FILTER_COPY ? s.slot_edges * p.streams * d1 : 0;
     s.c_bytes = 2 * s.cchunk * d1;
     return s;
 }
@@ -408,6 +413,8 @@ void release_all(hytm_graph* g) {
     for (auto* b : {&g->d_wpre, &g->d_Ea, &g->d_Rq, &g->d_K, &g->d_wbase, &g->d_off, &g->d_sel_in}) b->release();
     g->d_mode.release();
     g->d_sel_out.release();
+    g->d_tasks.release();
+    g->h_tasks.release();
     g->d_hdr.release();
     for (uint32_t i = 0; i < kMaxSlots; i++) {
         g->d_slot_col[i].release();
@@ -583,7 +590,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
     if (algo == HYTM_PAGERANK) {
         g->d_x.ensure(n);
         g->d_contrib.ensure(n);
-        g->d_acc.ensure(n);
+        g->d_acc.ensure(acc_slots(n));
     }
     g->d_mode.ensure(npart);
     g->d_nA.ensure(npart);
@@ -601,11 +608,16 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
 
     // edge-budget buffers
     const Plan& pl = rc.plan;
-    if (pl.allow_filter)
+    const bool fstream = g->params.filter_engine == HYTM_FILTER_STREAM;
+    if (pl.allow_filter && !fstream)
         for (uint32_t s = 0; s < pl.nslots; s++) {
             g->d_slot_col[s].ensure(pl.slot_edges);
             if (arrays == 2) g->d_slot_w[s].ensure(pl.slot_edges);
         }
+    if (pl.allow_filter && fstream) {
+        g->d_tasks.ensure(npart);
+        g->h_tasks.ensure(npart);
+    }
     if (pl.allow_compact) {
         for (int b = 0; b < 2; b++) {
             g->d_cbuf_col[b].ensure(pl.cchunk);
@@ -749,17 +761,20 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
                 const uint32_t k = g->params.combine_k;
                 const uint64_t fend_list = h.seg_list_start[SEG_F] + h.seg_list_count[SEG_F];
                 const uint64_t fend_work = h.seg_work_start[SEG_F] + h.seg_work_total[SEG_F];
+                // the copy form keeps every task within one staging slot
+                const uint64_t cap = fstream ? UINT64_MAX : pl.slot_edges;
                 uint32_t gidx = 0;
                 uint32_t i = 0;
+                uint64_t chunks = 0;
                 while (i < npart) {
                     if (g->h_mode.p[i] != P_FILTER) {
                         i++;
                         continue;
                     }
-                    // task = partitions [i, j): adjacent filter partitions, at most k, within one slot
+                    // task = partitions [i, j): adjacent filter partitions, at most k
                     uint32_t j = i + 1;
                     uint64_t edges = g->pE[i];
-                    while (j < npart && j - i < k && g->h_mode.p[j] == P_FILTER && edges + g->pE[j] <= pl.slot_edges) {
+                    while (j < npart && j - i < k && g->h_mode.p[j] == P_FILTER && edges + g->pE[j] <= cap) {
                         edges += g->pE[j];
                         j++;
                     }
@@ -771,6 +786,18 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
                     const uint64_t wa = g->h_wbase.p[i];
                     const uint64_t wb = nx < npart ? g->h_wbase.p[nx] : fend_work;
                     const uint64_t ebeg = g->h_off[g->pv[i]];
+                    rec.bytes_filter += edges * d1b;
+                    if (fstream) {
+                        FTask& ft = g->h_tasks.p[gidx++];
+                        ft.e0 = ebeg;
+                        ft.e1 = ebeg + edges;
+                        ft.ja = ja;
+                        ft.jb = jb;
+                        ft.chunk0 = chunks;
+                        chunks += fstream_chunks(ft.e0, ft.e1);
+                        i = j;
+                        continue;
+                    }
                     const uint32_t s = gidx % pl.nslots;
                     if (gidx >= pl.nslots) HIP_CHECK(hipStreamWaitEvent(g->s_copy, g->ev_free[s], 0));
                     HIP_CHECK(hipMemcpyAsync(g->d_slot_col[s].p, g->h_col + ebeg, edges * 4, hipMemcpyHostToDevice,
@@ -785,9 +812,17 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
                                                  g->d_slot_col[s].p, g->d_slot_w[s].p, ebeg, false, g->s_fk);
                     }));
                     HIP_CHECK(hipEventRecord(g->ev_free[s], g->s_fk));
-                    rec.bytes_filter += edges * d1b;
                     gidx++;
                     i = j;
+                }
+                if (fstream && gidx) {
+                    // one launch streams every filter task of the iteration
+                    HIP_CHECK(hipMemcpyAsync(g->d_tasks.p, g->h_tasks.p, gidx * sizeof(FTask), hipMemcpyHostToDevice,
+                                             g->s_fk));
+                    HIP_CHECK(kt.run(HYTM_K_PUSH_F, rec.bytes_filter / d1b, g->s_fk, [&] {
+                        return launch_push_fstream(as, g->d_tasks.p, gidx, chunks, g->d_list.p, g->d_off.p,
+                                                   g->d_col_map, g->d_w_map, g->s_fk);
+                    }));
                 }
                 rec.filter_tasks = gidx;
             }

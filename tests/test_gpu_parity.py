@@ -98,16 +98,21 @@ def test_rmat16_resident_matches_oracle(rmat16, algo):
 
 
 # ------------------------------------------- forced engines and budgets
-@pytest.mark.parametrize("mode", MODES)
+ENGINE_CASES = [("hybrid", "stream"), ("hybrid", "copy"), ("filter", "stream"), ("filter", "copy"),
+                ("compact", "stream"), ("zerocopy", "stream")]
+
+
+@pytest.mark.parametrize("mode,fe", ENGINE_CASES)
 @pytest.mark.parametrize("algo", ["bfs", "sssp", "cc", "pagerank"])
 @pytest.mark.parametrize("resident", [0.25, 0.0])
-def test_engines_and_budgets_agree(rmat12, algo, mode, resident):
-    note(f"rmat12 {algo} mode={mode} resident={resident}")
+def test_engines_and_budgets_agree(rmat12, algo, mode, fe, resident):
+    note(f"rmat12 {algo} mode={mode} filter_engine={fe} resident={resident}")
     with rmat12.graph(algo) as g:
         # small partitions and chunks so that the 4K-vertex graph spans many of each
-        g.set_params(partition_edges=2048, mode=mode, compact_chunk_edges=4096)
-        if mode in ("filter", "compact"):
-            g.set_budget(g.staging_bytes(algo) - 1)
+        g.set_params(partition_edges=2048, mode=mode, compact_chunk_edges=4096, filter_engine=fe)
+        staging = g.staging_bytes(algo)
+        if mode in ("filter", "compact") and staging > 0:
+            g.set_budget(staging - 1)
             with pytest.raises(hy.HytmError) as ei:
                 g.run(algo, 0)
             assert ei.value.status == hy.E_BUDGET
@@ -232,16 +237,17 @@ def test_argument_errors():
 @settings(max_examples=40, deadline=None, suppress_health_check=list(HealthCheck))
 @given(st.integers(1, 40).flatmap(lambda n: st.tuples(
     st.just(n), st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=160),
-    st.integers(0, n - 1), st.sampled_from(MODES), st.sampled_from([None, 0.5, 0.0]))))
+    st.integers(0, n - 1), st.sampled_from(MODES), st.sampled_from([None, 0.5, 0.0]),
+    st.sampled_from(["stream", "copy"]))))
 def test_random_small_graphs(case):
-    n, edges, s, mode, frac = case
+    n, edges, s, mode, frac, fe = case
     src = np.array([e[0] for e in edges], np.uint32)
     dst = np.array([e[1] for e in edges], np.uint32)
     off, col = gen.from_pairs(n, src, dst)
     c = Case(off, col, seed=7)
     for algo in ("bfs", "sssp", "cc", "pagerank"):
         with c.graph(algo) as g:
-            g.set_params(partition_edges=8, combine_k=2, compact_chunk_edges=16,
+            g.set_params(partition_edges=8, combine_k=2, compact_chunk_edges=16, filter_engine=fe,
                          mode=mode if frac is not None else "hybrid")
             if frac is not None:
                 g.set_resident_fraction(algo, frac)
