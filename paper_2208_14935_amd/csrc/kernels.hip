@@ -379,16 +379,59 @@ struct OpPr {
     }
 };
 
-// Largest j in [lo, hi) with a[j] <= x, given a[lo] <= x and a non-decreasing.
-__device__ __forceinline__ uint32_t search_le(const uint64_t* a, uint32_t lo, uint32_t hi, uint64_t x) {
+// Largest j in [lo, hi) with pred(j) true, for a predicate that is true on a prefix of
+// [lo, hi) and true at lo.  The whole workgroup searches together: each round every
+// thread probes one of blockDim.x evenly spaced positions, so a range of N entries takes
+// about log(N)/log(blockDim.x) rounds of independent loads instead of log2(N) dependent
+// ones.  Every thread of the block must call it with the same arguments.
+template <class Pred>
+__device__ __forceinline__ uint32_t block_search_last(uint32_t lo, uint32_t hi, Pred pred, uint32_t* s_tmp) {
     while (hi - lo > 1) {
-        const uint32_t mid = lo + (hi - lo) / 2;
-        if (a[mid] <= x)
-            lo = mid;
-        else
-            hi = mid;
+        const uint32_t step = (hi - lo + blockDim.x - 1) / blockDim.x;
+        const uint32_t p = lo + threadIdx.x * step;
+        const bool ok = p < hi && (threadIdx.x == 0 || pred(p));
+        if (threadIdx.x == 0) *s_tmp = 0;
+        __syncthreads();
+        if (ok && threadIdx.x) atomicMax(s_tmp, threadIdx.x);
+        __syncthreads();
+        const uint32_t t = *s_tmp;
+        __syncthreads();
+        lo = lo + t * step;
+        hi = min(lo + step, hi);
     }
     return lo;
+}
+
+// Inclusive prefix maximum of a[0 .. count) in LDS, count <= 4 * blockDim.x, blockDim.x a
+// multiple of 64 and at most 1024.  s_wave holds blockDim.x / 64 entries.
+__device__ __forceinline__ void block_prefix_max_u16(uint16_t* a, uint32_t count, uint32_t* s_wave) {
+    const uint32_t t = threadIdx.x, lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
+    uint32_t v[4], m = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint32_t i = 4 * t + q;
+        v[q] = i < count ? a[i] : 0u;
+        m = max(m, v[q]);
+        v[q] = m;
+    }
+    uint32_t x = m;  // inclusive scan of thread maxima across the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (uint32_t)d) x = max(x, y);
+    }
+    if (lane == 63) s_wave[wid] = x;
+    __syncthreads();
+    uint32_t before = __shfl_up(x, 1, 64);
+    if (lane == 0) before = 0;
+    for (uint32_t w = 0; w < wid; w++) before = max(before, s_wave[w]);
+    (void)nw;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint32_t i = 4 * t + q;
+        if (i < count) a[i] = (uint16_t)max(v[q], before);
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------- edge push
@@ -406,40 +449,37 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_push_edges(const uint32_t* __r
     __shared__ uint64_t s_pre[EDGE_IPB];
     __shared__ uint64_t s_st[EDGE_IPB];
     __shared__ uint32_t s_val[EDGE_IPB];
-    __shared__ uint32_t s_j0, s_nv;
+    __shared__ uint16_t s_owner[EDGE_IPB];  // item -> staged vertex
+    __shared__ uint32_t s_tmp, s_wave[EDGE_THREADS / 64];
     for (uint64_t blk = blockIdx.x;; blk += gridDim.x) {
         const uint64_t i0 = item_lo + blk * EDGE_IPB;
         if (i0 >= item_hi) break;
         const uint64_t i1 = min(i0 + (uint64_t)EDGE_IPB, item_hi);
-        if (threadIdx.x == 0) {
-            const uint32_t j0 = search_le(wpre, ja, jb, i0);
-            const uint32_t j1 = search_le(wpre, j0, jb, i1 - 1);
-            s_j0 = j0;
-            s_nv = j1 - j0 + 1;
-        }
+        // list entries whose items meet [i0, i1): every one has at least one item there,
+        // so there are at most EDGE_IPB of them
+        const uint32_t j0 = block_search_last(ja, jb, [&](uint32_t j) { return wpre[j] <= i0; }, &s_tmp);
+        const uint32_t j1 = block_search_last(j0, jb, [&](uint32_t j) { return wpre[j] < i1; }, &s_tmp);
+        const uint32_t nv = j1 - j0 + 1;
+        const uint32_t cnt = (uint32_t)(i1 - i0);
+        for (uint32_t q = threadIdx.x; q < cnt; q += EDGE_THREADS) s_owner[q] = 0;
         __syncthreads();
-        const uint32_t j0 = s_j0, nv = s_nv;
         for (uint32_t k = threadIdx.x; k < nv; k += EDGE_THREADS) {
             const uint32_t v = list[j0 + k];
             const uint64_t pre = wpre[j0 + k];
             s_pre[k] = pre;
             s_st[k] = (COMPACTED ? pre : off[v]) - shift;
             s_val[k] = op.src(v);
+            if (k) s_owner[pre - i0] = (uint16_t)k;  // first item of every later vertex
         }
         __syncthreads();
-        for (uint64_t i = i0 + threadIdx.x; i < i1; i += EDGE_THREADS) {
-            uint32_t lo = 0, hi = nv;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (s_pre[mid] <= i)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            const uint64_t e = s_st[lo] + (i - s_pre[lo]);
+        block_prefix_max_u16(s_owner, cnt, s_wave);
+        for (uint32_t q = threadIdx.x; q < cnt; q += EDGE_THREADS) {
+            const uint32_t k = s_owner[q];
+            const uint64_t i = i0 + q;
+            const uint64_t e = s_st[k] + (i - s_pre[k]);
             const uint32_t v = col[e];
             const uint32_t wt = Op::weighted ? w[e] : 0u;
-            op.push(s_val[lo], v, wt);
+            op.push(s_val[k], v, wt);
         }
         __syncthreads();
     }
@@ -462,20 +502,15 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
     __shared__ uint64_t s_s[LINE_IPB];
     __shared__ uint64_t s_e[LINE_IPB];
     __shared__ uint32_t s_val[LINE_IPB];
-    __shared__ uint32_t s_j0, s_nv;
+    __shared__ uint32_t s_tmp;
     const uint32_t half = threadIdx.x >> 5, lane = threadIdx.x & 31;
     for (uint64_t blk = blockIdx.x;; blk += gridDim.x) {
         const uint64_t i0 = item_lo + blk * LINE_IPB;
         if (i0 >= item_hi) break;
         const uint64_t i1 = min(i0 + (uint64_t)LINE_IPB, item_hi);
-        if (threadIdx.x == 0) {
-            const uint32_t j0 = search_le(wpre, ja, jb, i0);
-            const uint32_t j1 = search_le(wpre, j0, jb, i1 - 1);
-            s_j0 = j0;
-            s_nv = j1 - j0 + 1;
-        }
-        __syncthreads();
-        const uint32_t j0 = s_j0, nv = s_nv;
+        const uint32_t j0 = block_search_last(ja, jb, [&](uint32_t j) { return wpre[j] <= i0; }, &s_tmp);
+        const uint32_t j1 = block_search_last(j0, jb, [&](uint32_t j) { return wpre[j] < i1; }, &s_tmp);
+        const uint32_t nv = j1 - j0 + 1;
         for (uint32_t k = threadIdx.x; k < nv; k += LINE_THREADS) {
             const uint32_t v = list[j0 + k];
             s_pre[k] = wpre[j0 + k];
@@ -588,50 +623,22 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
     __shared__ uint64_t s_s[MAXV];
     __shared__ uint64_t s_e[MAXV];
     __shared__ uint32_t s_val[MAXV];
-    __shared__ uint32_t s_t, s_j0, s_nv;
+    __shared__ uint32_t s_tmp;
     const uint32_t half = threadIdx.x >> 5, lane = threadIdx.x & 31;
     for (uint64_t c = blockIdx.x; c < total_chunks; c += gridDim.x) {
-        if (threadIdx.x == 0) {
-            // task of chunk c: last t with tasks[t].chunk0 <= c
-            uint32_t lo = 0, hi = ntasks;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (tasks[mid].chunk0 <= c)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            s_t = lo;
-        }
-        __syncthreads();
-        const FTask t = tasks[s_t];
+        // task of chunk c: last t with tasks[t].chunk0 <= c (tasks[0].chunk0 = 0)
+        const uint32_t ti = block_search_last(0, ntasks, [&](uint32_t j) { return tasks[j].chunk0 <= c; }, &s_tmp);
+        const FTask t = tasks[ti];
         const uint64_t line0 = (t.e0 >> ZC_LINE_SHIFT) + (c - t.chunk0) * FSTREAM_LINES;
         const uint64_t ce0 = max(t.e0, line0 << ZC_LINE_SHIFT);
         const uint64_t ce1 = min(t.e1, (line0 + FSTREAM_LINES) << ZC_LINE_SHIFT);
-        if (threadIdx.x == 0) {
-            // active vertices whose ranges meet [ce0, ce1): j in [jlo, jhi)
-            uint32_t lo = t.ja, hi = t.jb;  // first j with off[list[j] + 1] > ce0
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (off[list[mid] + 1] > ce0)
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            const uint32_t jlo = lo;
-            hi = t.jb;  // first j with off[list[j]] >= ce1
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (off[list[mid]] >= ce1)
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            s_j0 = jlo;
-            s_nv = lo - jlo;
-        }
-        __syncthreads();
-        const uint32_t j0 = s_j0, nv = s_nv;
+        // active vertices whose out-edge ranges meet [ce0, ce1): list entries [j0, j0 + nv)
+        // (the list is in vertex order, so both range ends increase with j)
+        uint32_t j0 = t.ja, nv = 0;
+        if (t.ja < t.jb && off[list[t.ja] + 1] <= ce0)
+            j0 = block_search_last(t.ja, t.jb, [&](uint32_t j) { return off[list[j] + 1] <= ce0; }, &s_tmp) + 1;
+        if (j0 < t.jb && off[list[j0]] < ce1)
+            nv = block_search_last(j0, t.jb, [&](uint32_t j) { return off[list[j]] < ce1; }, &s_tmp) + 1 - j0;
         for (uint32_t k = threadIdx.x; k < nv; k += LINE_THREADS) {
             const uint32_t v = list[j0 + k];
             s_s[k] = off[v];

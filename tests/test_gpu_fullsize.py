@@ -1,0 +1,114 @@
+"""GPU parity at the benchmark's full size and launch configuration (R-MAT scale 24,
+edge budget 25% of the bytes each algorithm reads, 32768-edge partitions, hybrid engines).
+
+BFS and CC are compared with the oracle element by element; SSSP by its certificate
+(distance 0 at the source, no edge can still relax, every reached vertex has a tight parent
+edge, reachability equal to BFS's), which pins the unique distances; PageRank by the
+recurrence it must satisfy, checked on sampled vertices from the GPU's own previous step,
+plus the exact mass identity.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_2208_14935_amd as hy
+
+pytestmark = pytest.mark.gpu
+SCALE = int(os.environ.get("HYTM_FULLSIZE_SCALE", "24"))
+
+
+def note(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+@pytest.fixture(scope="module")
+def big():
+    gen.set_threads(min(16, os.cpu_count() or 1))
+    off, col = gen.rmat(SCALE, 16, seed=SCALE)
+    w = gen.weights(off, col, 1000 + SCALE)
+    srcs = gen.sources(off, 8, 2000 + SCALE)
+    g = hy.Graph(off, col, weights=w, check_col=False)
+    note(f"rmat{SCALE}: n={g.n} m={g.m}")
+    yield off, col, w, srcs, g
+    g.close()
+
+
+def budget(g, arrays):
+    g.set_budget(int(0.25 * 4 * arrays * g.m))
+
+
+def test_bfs_fullsize_exact(big):
+    off, col, w, srcs, g = big
+    budget(g, 1)
+    for s in srcs[:2]:
+        note(f"bfs from {s}")
+        r = g.run("bfs", int(s), stats=True)
+        want, it = oracle.bfs(off, col, int(s))
+        np.testing.assert_array_equal(r.values, want)
+        assert r.iterations == it
+        assert r.stats["nres"] < r.stats["npart"]  # oversubscribed
+
+
+def test_sssp_fullsize_certificate(big):
+    off, col, w, srcs, g = big
+    budget(g, 2)
+    s = int(srcs[0])
+    r = g.run("sssp", s)
+    dist = r.values
+    lvl, it_bfs = oracle.bfs(off, col, s)
+    n = len(off) - 1
+    assert dist[s] == 0
+    assert ((dist != hy.UNREACHED) == (lvl != hy.UNREACHED)).all()
+    u = np.repeat(np.arange(n, dtype=np.uint32), np.diff(off).astype(np.int64))
+    du = dist[u].astype(np.int64)
+    dv = dist[col].astype(np.int64)
+    reached = dist[u] != hy.UNREACHED
+    del u
+    assert (dv[reached] <= du[reached] + w[reached]).all()
+    tight = reached & (dv == du + w.astype(np.int64))
+    has_parent = np.zeros(n, dtype=bool)
+    has_parent[col[tight]] = True
+    need = dist != hy.UNREACHED
+    need[s] = False
+    assert has_parent[need].all()
+    assert r.iterations >= it_bfs
+
+
+def test_cc_fullsize_exact():
+    off, col = gen.rmat(SCALE, 16, seed=SCALE)
+    soff, scol = gen.symmetrize(off, col)
+    del off, col
+    with hy.Graph(soff, scol, symmetric=True, check_col=False) as g:
+        budget(g, 1)
+        r = g.run("cc")
+    want, _ = oracle.cc(soff, scol)
+    np.testing.assert_array_equal(r.values, want)
+
+
+def test_pagerank_fullsize_recurrence(big):
+    off, col, w, srcs, g = big
+    budget(g, 1)
+    d = 0.85
+    n = len(off) - 1
+    g.set_params(pr_iterations=19)
+    x19 = g.run("pagerank").values.astype(np.float64)
+    g.set_params(pr_iterations=20)
+    x20 = g.run("pagerank").values.astype(np.float64)
+    deg = np.diff(off).astype(np.int64)
+    # mass identity: sum x_{t+1} = (1-d) + d * sum over vertices with out-edges of x_t
+    assert abs(x20.sum() - ((1 - d) + d * x19[deg > 0].sum())) < 1e-4
+    # one step of the recurrence on sampled vertices, from the GPU's own x_19
+    rng = np.random.default_rng(5)
+    sample = np.unique(np.concatenate([np.arange(64), rng.choice(n, 512, replace=False)]))
+    share = np.where(deg > 0, x19 / np.maximum(deg, 1), 0.0)
+    mask = np.isin(col, sample)
+    u = np.repeat(np.arange(n), deg)[mask]
+    want = np.full(len(sample), (1 - d) / n)
+    idx = np.searchsorted(sample, col[mask])
+    np.add.at(want, idx, d * share[u])
+    err = np.abs(x20[sample] - want).max()
+    assert err < 1e-6, err

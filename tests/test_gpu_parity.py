@@ -126,6 +126,28 @@ def test_engines_and_budgets_agree(rmat12, algo, mode, fe, resident):
             assert used <= {mode}, used
 
 
+@pytest.fixture(scope="module")
+def rmat20():
+    off, col = gen.rmat(20, 16, seed=20)
+    return Case(off, col, seed=1020)
+
+
+@pytest.mark.parametrize("mode,fe", [("hybrid", "stream"), ("hybrid", "copy"), ("zerocopy", "stream"),
+                                     ("compact", "stream"), ("filter", "stream")])
+@pytest.mark.parametrize("algo", ["bfs", "sssp", "cc", "pagerank"])
+def test_rmat20_quarter_budget_matches_oracle(rmat20, algo, mode, fe):
+    """The benchmark's configuration (32768-edge partitions, budget = 25% of the edge bytes
+    read, staging included) on a graph the oracle finishes in about a second."""
+    note(f"rmat20 {algo} {mode} {fe}")
+    with rmat20.graph(algo) as g:
+        g.set_params(mode=mode, filter_engine=fe, gamma=(1, 1) if mode == "hybrid" else (5, 8))
+        arrays = 2 if algo == "sssp" else 1
+        g.set_budget(max(int(0.25 * 4 * arrays * g.m), g.staging_bytes(algo)))
+        res = g.run(algo, 3, stats=True)
+        check(rmat20, algo, res, 3)
+        assert res.stats["nres"] < res.stats["npart"]
+
+
 def test_hybrid_uses_several_engines_and_moves_fewer_bytes_than_filter(rmat16):
     note("rmat16 hybrid vs filter bytes")
     with rmat16.graph("bfs") as g:
