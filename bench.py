@@ -99,13 +99,21 @@ def main():
 
     kt = not args.no_kernel_timing
 
+    # algorithmic edges of BFS and SSSP from s: out-edges of the vertices reachable from s
+    # (SSSP reaches exactly the vertices BFS reaches), counted outside the timed region
+    reach_edges = {}
+    budget(g, 1)
+    for s in srcs:
+        lv = g.run("bfs", int(s)).values
+        reach_edges[int(s)] = int(deg[lv != hy.UNREACHED].sum())
+
     def step(record):
         runs = []
         if "bfs" in algos:
             budget(g, 1)
             for s in srcs:
                 r = g.run("bfs", int(s), stats=True, time_kernels=kt and record)
-                runs.append(("bfs", r, int(deg[r.values != hy.UNREACHED].sum())))
+                runs.append(("bfs", r, reach_edges[int(s)]))
         if "pagerank" in algos:
             budget(g, 1)
             r = g.run("pagerank", stats=True, time_kernels=kt and record)
@@ -114,7 +122,7 @@ def main():
             budget(g, 2)
             for s in srcs:
                 r = g.run("sssp", int(s), stats=True, time_kernels=kt and record)
-                runs.append(("sssp", r, int(deg[r.values != hy.UNREACHED].sum())))
+                runs.append(("sssp", r, reach_edges[int(s)]))
         if "cc" in algos:
             budget(gs, 1)
             r = gs.run("cc", stats=True, time_kernels=kt and record)
@@ -183,22 +191,29 @@ def main():
                            "items": int(items[c]) // args.steps}
         dom = int(np.argmax(ms))
         avg_ms = ms[dom] / max(launches[dom], 1)
-        # algorithmic bytes per item: edge kernels read 4 B per edge array and touch one
-        # 4-byte vertex value per edge; the zero-copy kernel reads 128-byte lines of each
-        # array over the host link and touches up to 32 vertex values per line
-        if hy.KERNEL_CLASSES[dom] == "push_zerocopy":
+        name = hy.KERNEL_CLASSES[dom]
+        # algorithmic bytes per launch.  Kernels reading the mapped host arrays are priced
+        # against the host link: the zero-copy kernel moves 128 B per line item per edge
+        # array, the streaming filter kernel 4 B per edge of its tasks per edge array.
+        # Kernels reading device memory are priced against HBM: 4 B per edge per array
+        # plus one 4-byte vertex value touched per edge.
+        if name == "push_zerocopy":
             per_launch = arrays_items[dom] * 128 / max(launches[dom], 1)
             bound, peak = "pcie", PCIE_GEN5_X16_GBPS
-        elif hy.KERNEL_CLASSES[dom].startswith("push"):
+        elif name == "push_filter" and args.filter_engine == "stream":
+            per_launch = arrays_items[dom] * 4 / max(launches[dom], 1)
+            bound, peak = "pcie", PCIE_GEN5_X16_GBPS
+        elif name.startswith("push"):
             per_launch = (arrays_items[dom] * 4 + items[dom] * 4) / max(launches[dom], 1)
             bound, peak = "hbm", HBM_PEAK_GBPS
         else:
             per_launch = items[dom] * 16 / max(launches[dom], 1)
             bound, peak = "hbm", HBM_PEAK_GBPS
         achieved = per_launch / (avg_ms / 1e3) / 1e9
-        roofline = {"kernel": hy.KERNEL_CLASSES[dom], "bound": bound, "achieved": achieved, "peak": peak,
+        roofline = {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak,
                     "unit": "GB/s", "frac": achieved / peak, "traffic": None,
-                    "avg_launch_ms": avg_ms, "launches_per_step": int(launches[dom]) // args.steps}
+                    "avg_launch_ms": avg_ms, "launches_per_step": int(launches[dom]) // args.steps,
+                    "measured_link_peak_gbps": probe["h2d_copy_gbps"]}
 
     cpu = None
     if not args.no_cpu_baseline:

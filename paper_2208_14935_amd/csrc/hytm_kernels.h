@@ -56,10 +56,14 @@ struct AlgoState {
     uint32_t* visited;    // BFS: discovered-vertex bitmap
     uint32_t* next;       // next-frontier bitmap
     uint32_t* overflow;   // SSSP: set when a distance would reach 2^32-1
-    float* acc;           // PageRank accumulator
+    float* acc;           // PageRank accumulators: ACC_COPIES x acc_slots(n) floats
     const float* contrib; // PageRank x[u] / D_o(u)
     uint32_t level_next;  // BFS: level given to vertices discovered this iteration
+    uint64_t n;           // vertices
 };
+
+// PageRank keeps one accumulator copy per XCD; the apply step sums them.
+constexpr uint32_t ACC_COPIES = 8;
 
 hipError_t launch_init(const AlgoState& s, uint64_t n, uint32_t source, float pr_x0, float* pr_x, uint32_t* cur,
                        uint32_t nwords, hipStream_t st);

@@ -369,13 +369,24 @@ struct OpCc {
     }
 };
 
+// Accumulator copy of the XCD (accelerator complex die) the wave runs on.  Any value in
+// [0, ACC_COPIES) would be correct -- the adds are device-scope atomics and the copies are
+// summed afterwards -- the die id just keeps each copy's lines in one die's L2 and splits
+// the adds aimed at one hub vertex eight ways.
+__device__ __forceinline__ uint32_t acc_copy() {
+    uint32_t x;
+    asm("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(x));
+    return x & (ACC_COPIES - 1);
+}
+
 struct OpPr {
     static constexpr bool weighted = false;
     float* acc;
+    uint64_t stride;  // floats per accumulator copy
     const float* contrib;
     __device__ __forceinline__ uint32_t src(uint32_t u) const { return __float_as_uint(contrib[u]); }
     __device__ __forceinline__ void push(uint32_t c, uint32_t v, uint32_t) const {
-        unsafeAtomicAdd(acc + acc_slot(v), __uint_as_float(c));
+        unsafeAtomicAdd(acc + acc_copy() * stride + acc_slot(v), __uint_as_float(c));
     }
 };
 
@@ -596,15 +607,22 @@ __global__ void k_pr_prepare(uint64_t n, const uint64_t* __restrict__ off, const
             const uint64_t d = off[v + 1] - off[v];
             contrib[v] = d ? x[v] / (float)d : 0.0f;
         }
-        acc[v] = 0.0f;
+#pragma unroll
+        for (uint32_t c = 0; c < ACC_COPIES; c++) acc[c * slots + v] = 0.0f;
     }
 }
 
 __global__ void k_pr_apply(uint64_t n, float* __restrict__ x, const float* __restrict__ acc, float base,
                            float damping) {
+    const uint64_t slots = acc_slots(n);
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
-         v += (uint64_t)gridDim.x * blockDim.x)
-        x[v] = base + damping * acc[acc_slot((uint32_t)v)];
+         v += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = acc_slot((uint32_t)v);
+        float sum = 0.0f;
+#pragma unroll
+        for (uint32_t c = 0; c < ACC_COPIES; c++) sum += acc[c * slots + s];
+        x[v] = base + damping * sum;
+    }
 }
 
 // ---------------------------------------------------------- filter stream
@@ -782,7 +800,7 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
         return push_edges_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
                              compacted, st);
     default:
-        return push_edges_op(OpPr{s.acc, s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
+        return push_edges_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
                              compacted, st);
     }
 }
@@ -810,7 +828,7 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
     case ALGO_CC:
         return push_lines_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
     default:
-        return push_lines_op(OpPr{s.acc, s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
+        return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
     }
 }
 
@@ -843,7 +861,7 @@ hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t 
     case ALGO_CC:
         return push_fstream_op(OpCc{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, st);
     default:
-        return push_fstream_op(OpPr{s.acc, s.contrib}, tasks, ntasks, total_chunks, list, off, col, w, st);
+        return push_fstream_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, tasks, ntasks, total_chunks, list, off, col, w, st);
     }
 }
 

@@ -590,7 +590,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
     if (algo == HYTM_PAGERANK) {
         g->d_x.ensure(n);
         g->d_contrib.ensure(n);
-        g->d_acc.ensure(acc_slots(n));
+        g->d_acc.ensure(ACC_COPIES * acc_slots(n));
     }
     g->d_mode.ensure(npart);
     g->d_nA.ensure(npart);
@@ -666,6 +666,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
     as.overflow = g->d_overflow.p;
     as.acc = g->d_acc.p;
     as.contrib = g->d_contrib.p;
+    as.n = n;
     const float x0 = n ? (float)(1.0 / (double)n) : 0.f;
     HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
                      [&] { return launch_init(as, n, source, x0, g->d_x.p, g->d_cur.p, nwords, main); }));
