@@ -251,6 +251,20 @@ hytm_status hytm_partition_bounds(const hytm_graph *g, uint64_t *bounds, uint64_
 hytm_status hytm_run(hytm_graph *g, hytm_algo algo, uint32_t source, void *values_out, uint32_t *iterations_out,
                      hytm_run_stats *stats, void *hip_stream);
 
+/* Batched BFS or SSSP from up to 64 sources in one traversal.  Each vertex carries a
+   64-bit mask of the sources (lanes) active at it and one uint32 value per lane; a vertex
+   is active when any lane is, so the cost model (Sec. 5.1) runs on the union frontier and
+   every edge moved over the host link serves all lanes at once.  Lane l's values equal
+   those of hytm_run from sources[l].
+   sources        : host array of nsources vertex ids (1..64 entries; repeats allowed).
+   values_out     : host buffer of nsources x n uint32, row l = results of sources[l].
+   iterations_out : NULL or nsources counts: the non-empty frontiers of each lane.
+   Errors as hytm_run; E_INVAL also for CC/PageRank or nsources outside 1..64.  Device
+   memory for the lanes (n x 64 x 4 bytes of values + three n x 8-byte masks) is vertex
+   data, outside the edge budget. */
+hytm_status hytm_run_batch(hytm_graph *g, hytm_algo algo, const uint32_t *sources, uint32_t nsources,
+                           void *values_out, uint32_t *iterations_out, hytm_run_stats *stats, void *hip_stream);
+
 /* Evaluate the engine selection of Sec. 5.1 (Eq. 1-3, alpha/beta rule) on the GPU for
    caller-supplied per-partition statistics, with the handle's parameters.
    npart      : partitions; E, nA, Ea, Rq: host arrays of npart uint64 (edges, active

@@ -105,6 +105,8 @@ _SIGNATURES = {
     "hytm_partition_bounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
     "hytm_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p,
                                 ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(RunStats), ctypes.c_void_p]),
+    "hytm_run_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(RunStats), ctypes.c_void_p]),
     "hytm_select_engines": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
                                            ctypes.c_void_p]),
@@ -317,6 +319,27 @@ class Graph:
                 rows = min(res.iterations, len(trace_buf) // max(npart, 1))
                 res.mode_trace = trace_buf[: rows * npart].reshape(rows, npart).copy()
         return res
+
+    def run_batch(self, algo: str, sources, stats: bool = False, stream=None, time_kernels: bool = False):
+        """Batched BFS/SSSP from up to 64 sources in one traversal.  Returns
+        (values[nsources, n] uint32, iterations[nsources], stats dict)."""
+        srcs = np.ascontiguousarray(sources, dtype=np.uint32)
+        vals = np.empty((max(len(srcs), 1), max(self.n, 1)), dtype=np.uint32)[: len(srcs), : self.n]
+        its = np.zeros(max(len(srcs), 1), dtype=np.uint32)
+        st = None
+        if stats or time_kernels:
+            st = RunStats()
+            st.struct_size = ctypes.sizeof(RunStats)
+            st.time_kernels = 1 if time_kernels else 0
+        s = stream if stream is not None else _current_stream()
+        _check(load().hytm_run_batch(self._h, ALGOS[algo], _ptr(srcs), len(srcs), _ptr(vals), _ptr(its),
+                                     ctypes.byref(st) if st is not None else None, s))
+        sd = {}
+        if st is not None:
+            arrays = ("part_iters", "kernel_ms", "kernel_launches", "kernel_items")
+            sd = {k: (list(getattr(st, k)) if k in arrays else getattr(st, k)) for k, _ in RunStats._fields_
+                  if k not in ("iters", "mode_trace", "struct_size", "reserved0", "time_kernels")}
+        return vals, its[: len(srcs)], sd
 
     def select_engines(self, E, nA, Ea, Rq, nres: int = 0, edge_arrays: int = 1) -> np.ndarray:
         arrs = [np.ascontiguousarray(x, dtype=np.uint64) for x in (E, nA, Ea, Rq)]

@@ -16,7 +16,15 @@ enum : uint8_t { P_NONE = 0, P_RES = 1, P_FILTER = 2, P_ZC = 3, P_COMPACT = 4 };
 constexpr int NSEG = 4;
 constexpr int SEG_R = 0, SEG_F = 1, SEG_Z = 2, SEG_C = 3;
 
-enum Algo : int { ALGO_BFS = 0, ALGO_SSSP = 1, ALGO_CC = 2, ALGO_PR = 3 };
+// ALGO_MBFS / ALGO_MSSSP: up to 64 sources at once, one bit / value lane per source.
+enum Algo : int { ALGO_BFS = 0, ALGO_SSSP = 1, ALGO_CC = 2, ALGO_PR = 3, ALGO_MBFS = 4, ALGO_MSSSP = 5 };
+constexpr uint32_t MAX_LANES = 64;
+
+// Sources of a batched run, passed by value to the init kernel.
+struct LaneSources {
+    uint32_t src[MAX_LANES];
+    uint32_t count;
+};
 
 // Zero-copy kernel line: 32 four-byte elements = 128 bytes.
 constexpr uint32_t ZC_LINE_SHIFT = 5;
@@ -60,6 +68,11 @@ struct AlgoState {
     const float* contrib; // PageRank x[u] / D_o(u)
     uint32_t level_next;  // BFS: level given to vertices discovered this iteration
     uint64_t n;           // vertices
+    // batched runs: per-vertex lane masks and per (vertex, lane) values in rows of 64
+    const uint64_t* mcur; // lanes active at each vertex this iteration
+    uint64_t* mnext;      // lanes improved this iteration
+    uint64_t* mvisited;   // BFS: lanes that have reached each vertex
+    uint32_t* lval;       // n x 64: level or distance of each lane
 };
 
 // PageRank keeps one accumulator copy per XCD; the apply step sums them.
@@ -72,6 +85,14 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStrea
 hipError_t launch_stats_select(uint32_t npart, const uint32_t* pv, const uint64_t* off, const uint32_t* cur,
                                const SelParams& sp, uint8_t* mode, uint32_t* nA, uint32_t* nF, uint64_t* Ea,
                                uint64_t* Rq, uint64_t* K, hipStream_t st);
+
+// Batched runs: initialise lane masks, lane values and the union frontier.
+hipError_t launch_init_lanes(const AlgoState& s, const LaneSources& src, uint32_t* cur_union, uint32_t nwords,
+                             hipStream_t st);
+// OR of the lane masks of all vertices into *lanes (one uint64, zeroed by the caller).
+hipError_t launch_lane_union(const uint64_t* mask, uint64_t n, unsigned long long* lanes, hipStream_t st);
+// Copy lane `lane` of the n x 64 value rows into out[0..n).
+hipError_t launch_extract_lane(const uint32_t* lval, uint64_t n, uint32_t lane, uint32_t* out, hipStream_t st);
 
 hipError_t launch_scan(uint32_t npart, const uint8_t* mode, const uint32_t* nA, const uint32_t* nF,
                        const uint64_t* Ea, const uint64_t* Rq, const uint64_t* K, uint32_t* lbase, uint64_t* wbase,

@@ -390,6 +390,66 @@ struct OpPr {
     }
 };
 
+// Batched BFS: lanes of u's mask that have not reached v yet reach it now (one 64-bit
+// atomicOr decides, per lane, which edge discovers v first).  The staged value is u.
+struct OpMBfs {
+    static constexpr bool weighted = false;
+    const uint64_t* mcur;
+    uint64_t* mnext;
+    uint64_t* mvisited;
+    uint32_t* lvl;   // n x 64
+    uint32_t* next;  // union of the next frontier
+    uint32_t level_next;
+    __device__ __forceinline__ uint32_t src(uint32_t u) const { return u; }
+    __device__ __forceinline__ void push(uint32_t u, uint32_t v, uint32_t) const {
+        const uint64_t want = mcur[u] & ~mvisited[v];
+        if (!want) return;
+        const uint64_t old = atomicOr((unsigned long long*)(mvisited + v), (unsigned long long)want);
+        uint64_t gained = want & ~old;
+        if (!gained) return;
+        atomicOr((unsigned long long*)(mnext + v), (unsigned long long)gained);
+        atomicOr(next + (v >> 5), 1u << (v & 31));
+        uint32_t* row = lvl + (uint64_t)v * MAX_LANES;
+        while (gained) {
+            row[__ffsll((unsigned long long)gained) - 1] = level_next;
+            gained &= gained - 1;
+        }
+    }
+};
+
+// Batched SSSP: every lane active at u relaxes (u, v) in its own distance row.
+struct OpMSssp {
+    static constexpr bool weighted = true;
+    const uint64_t* mcur;
+    uint64_t* mnext;
+    uint32_t* dist;  // n x 64
+    uint32_t* next;  // union of the next frontier
+    uint32_t* overflow;
+    __device__ __forceinline__ uint32_t src(uint32_t u) const { return u; }
+    __device__ __forceinline__ void push(uint32_t u, uint32_t v, uint32_t w) const {
+        uint64_t m = mcur[u], gained = 0;
+        const uint32_t* du = dist + (uint64_t)u * MAX_LANES;
+        uint32_t* dv = dist + (uint64_t)v * MAX_LANES;
+        while (m) {
+            const uint32_t l = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const uint64_t nd = (uint64_t)du[l] + w;
+            if (nd >= UNREACHED) {
+                *overflow = 1u;
+                continue;
+            }
+            if ((uint32_t)nd < dv[l]) {
+                const uint32_t old = atomicMin(dv + l, (uint32_t)nd);
+                if ((uint32_t)nd < old) gained |= 1ull << l;
+            }
+        }
+        if (gained) {
+            atomicOr((unsigned long long*)(mnext + v), (unsigned long long)gained);
+            atomicOr(next + (v >> 5), 1u << (v & 31));
+        }
+    }
+};
+
 // Largest j in [lo, hi) with pred(j) true, for a predicate that is true on a prefix of
 // [lo, hi) and true at lo.  The whole workgroup searches together: each round every
 // thread probes one of blockDim.x evenly spaced positions, so a range of N entries takes
@@ -413,14 +473,15 @@ __device__ __forceinline__ uint32_t block_search_last(uint32_t lo, uint32_t hi, 
     return lo;
 }
 
-// Inclusive prefix maximum of a[0 .. count) in LDS, count <= 4 * blockDim.x, blockDim.x a
-// multiple of 64 and at most 1024.  s_wave holds blockDim.x / 64 entries.
+// Inclusive prefix maximum of a[0 .. count) in LDS, count <= PER * blockDim.x, blockDim.x
+// a multiple of 64 and at most 1024.  s_wave holds blockDim.x / 64 entries.
+template <int PER = 4>
 __device__ __forceinline__ void block_prefix_max_u16(uint16_t* a, uint32_t count, uint32_t* s_wave) {
     const uint32_t t = threadIdx.x, lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
-    uint32_t v[4], m = 0;
+    uint32_t v[PER], m = 0;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const uint32_t i = 4 * t + q;
+    for (int q = 0; q < PER; q++) {
+        const uint32_t i = PER * t + q;
         v[q] = i < count ? a[i] : 0u;
         m = max(m, v[q]);
         v[q] = m;
@@ -438,8 +499,8 @@ __device__ __forceinline__ void block_prefix_max_u16(uint16_t* a, uint32_t count
     for (uint32_t w = 0; w < wid; w++) before = max(before, s_wave[w]);
     (void)nw;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const uint32_t i = 4 * t + q;
+    for (int q = 0; q < PER; q++) {
+        const uint32_t i = PER * t + q;
         if (i < count) a[i] = (uint16_t)max(v[q], before);
     }
     __syncthreads();
@@ -592,6 +653,49 @@ __global__ void k_init(AlgoState s, uint64_t n, uint32_t source, float x0, float
     if (blockIdx.x == 0 && threadIdx.x == 0 && s.overflow) *s.overflow = 0;
 }
 
+// Batched runs: value rows to UNREACHED except each lane's own source, lane masks with
+// each lane's bit at its source, the union frontier holding every source.
+__global__ void k_init_lanes(AlgoState s, LaneSources src, uint32_t* __restrict__ cur, uint32_t nwords) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t cells = s.n * MAX_LANES;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cells; i += stride) {
+        const uint32_t v = (uint32_t)(i / MAX_LANES), l = (uint32_t)(i % MAX_LANES);
+        s.lval[i] = (l < src.count && src.src[l] == v) ? 0u : UNREACHED;
+    }
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < s.n; v += stride) {
+        uint64_t m = 0;
+        for (uint32_t l = 0; l < src.count; l++)
+            if (src.src[l] == v) m |= 1ull << l;
+        ((uint64_t*)s.mcur)[v] = m;
+        s.mnext[v] = 0;
+        if (s.mvisited) s.mvisited[v] = m;
+    }
+    for (uint64_t wi = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; wi < nwords; wi += stride) {
+        uint32_t c = 0;
+        for (uint32_t l = 0; l < src.count; l++)
+            if ((src.src[l] >> 5) == wi) c |= 1u << (src.src[l] & 31);
+        cur[wi] = c;
+        s.next[wi] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && s.overflow) *s.overflow = 0;
+}
+
+__global__ __launch_bounds__(256) void k_lane_union(const uint64_t* __restrict__ mask, uint64_t n,
+                                                    unsigned long long* __restrict__ lanes) {
+    uint64_t m = 0;
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+        m |= mask[v];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m |= __shfl_xor(m, d, 64);
+    if ((threadIdx.x & 63) == 0 && m) atomicOr(lanes, (unsigned long long)m);
+}
+
+__global__ void k_extract_lane(const uint32_t* __restrict__ lval, uint64_t n, uint32_t lane,
+                               uint32_t* __restrict__ out) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+        out[v] = lval[v * MAX_LANES + lane];
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t value) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -629,6 +733,10 @@ __global__ void k_pr_apply(uint64_t n, float* __restrict__ x, const float* __res
 // One workgroup pass = one chunk of FSTREAM_LINES lines of one task.  All lines of the
 // chunk are loaded (the filter engine transfers whole partitions); an edge is pushed
 // when it lies in the out-edge range of one of the task's active vertices.
+// The chunk's host loads are issued as soon as the chunk is located, so the search for
+// its active vertices and their staging overlap the link latency.  Staged ranges are
+// chunk-relative 16-bit offsets, and each edge finds its vertex through an owner map
+// (the index of the last active vertex starting at or before it, by prefix maximum).
 template <class Op>
 __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __restrict__ tasks, uint32_t ntasks,
                                                                uint64_t total_chunks,
@@ -636,12 +744,14 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
                                                                const uint64_t* __restrict__ off,
                                                                const uint32_t* __restrict__ col,
                                                                const uint32_t* __restrict__ w, Op op) {
-    constexpr uint32_t MAXV = FSTREAM_LINES * 32;
+    constexpr uint32_t MAXE = FSTREAM_LINES * 32;  // edges per chunk (2048)
     constexpr int UNROLL = FSTREAM_LINES / LINE_HALVES;
-    __shared__ uint64_t s_s[MAXV];
-    __shared__ uint64_t s_e[MAXV];
-    __shared__ uint32_t s_val[MAXV];
-    __shared__ uint32_t s_tmp;
+    static_assert(MAXE <= 8 * LINE_THREADS, "owner map prefix covers 8 entries per thread");
+    __shared__ uint16_t s_owner[MAXE];  // chunk position -> staged vertex
+    __shared__ uint16_t s_s[MAXE];      // staged vertex range, relative to the chunk start
+    __shared__ uint16_t s_e[MAXE];
+    __shared__ uint32_t s_val[MAXE];
+    __shared__ uint32_t s_tmp, s_wave[LINE_THREADS / 64];
     const uint32_t half = threadIdx.x >> 5, lane = threadIdx.x & 31;
     for (uint64_t c = blockIdx.x; c < total_chunks; c += gridDim.x) {
         // task of chunk c: last t with tasks[t].chunk0 <= c (tasks[0].chunk0 = 0)
@@ -650,20 +760,8 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
         const uint64_t line0 = (t.e0 >> ZC_LINE_SHIFT) + (c - t.chunk0) * FSTREAM_LINES;
         const uint64_t ce0 = max(t.e0, line0 << ZC_LINE_SHIFT);
         const uint64_t ce1 = min(t.e1, (line0 + FSTREAM_LINES) << ZC_LINE_SHIFT);
-        // active vertices whose out-edge ranges meet [ce0, ce1): list entries [j0, j0 + nv)
-        // (the list is in vertex order, so both range ends increase with j)
-        uint32_t j0 = t.ja, nv = 0;
-        if (t.ja < t.jb && off[list[t.ja] + 1] <= ce0)
-            j0 = block_search_last(t.ja, t.jb, [&](uint32_t j) { return off[list[j] + 1] <= ce0; }, &s_tmp) + 1;
-        if (j0 < t.jb && off[list[j0]] < ce1)
-            nv = block_search_last(j0, t.jb, [&](uint32_t j) { return off[list[j]] < ce1; }, &s_tmp) + 1 - j0;
-        for (uint32_t k = threadIdx.x; k < nv; k += LINE_THREADS) {
-            const uint32_t v = list[j0 + k];
-            s_s[k] = off[v];
-            s_e[k] = off[v + 1];
-            s_val[k] = op.src(v);
-        }
-        __syncthreads();
+        const uint32_t cnt = (uint32_t)(ce1 - ce0);  // edges of the chunk, <= MAXE
+        // the transfer: every line of the chunk, loads in flight from here on
         uint32_t cv[UNROLL], wv[UNROLL];
 #pragma unroll
         for (int r = 0; r < UNROLL; r++) {
@@ -675,20 +773,34 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
                 if (Op::weighted) wv[r] = w[e];
             }
         }
-        if (nv > 0) {
+        // active vertices whose out-edge ranges meet [ce0, ce1): list entries [j0, j0 + nv)
+        // (the list is in vertex order, so both range ends increase with j)
+        uint32_t j0 = t.ja, nv = 0;
+        if (t.ja < t.jb && off[list[t.ja] + 1] <= ce0)
+            j0 = block_search_last(t.ja, t.jb, [&](uint32_t j) { return off[list[j] + 1] <= ce0; }, &s_tmp) + 1;
+        if (j0 < t.jb && off[list[j0]] < ce1)
+            nv = block_search_last(j0, t.jb, [&](uint32_t j) { return off[list[j]] < ce1; }, &s_tmp) + 1 - j0;
+        if (nv > 0) {  // uniform across the workgroup
+            for (uint32_t q = threadIdx.x; q < cnt; q += LINE_THREADS) s_owner[q] = 0;
+            __syncthreads();
+            for (uint32_t k = threadIdx.x; k < nv; k += LINE_THREADS) {
+                const uint32_t v = list[j0 + k];
+                const uint64_t vs = off[v], ve = off[v + 1];
+                const uint32_t rs = vs > ce0 ? (uint32_t)(vs - ce0) : 0u;
+                s_s[k] = (uint16_t)rs;
+                s_e[k] = (uint16_t)((ve < ce1 ? ve : ce1) - ce0);
+                s_val[k] = op.src(v);
+                if (k) s_owner[rs] = (uint16_t)k;  // later vertices start inside the chunk
+            }
+            __syncthreads();
+            block_prefix_max_u16<8>(s_owner, cnt, s_wave);
 #pragma unroll
             for (int r = 0; r < UNROLL; r++) {
                 const uint64_t e = ((line0 + half + (uint64_t)LINE_HALVES * r) << ZC_LINE_SHIFT) + lane;
-                if (e < ce0 || e >= ce1 || e < s_s[0]) continue;
-                uint32_t lo = 0, hi = nv;  // last k with s_s[k] <= e
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (s_s[mid] <= e)
-                        lo = mid;
-                    else
-                        hi = mid;
-                }
-                if (e < s_e[lo]) op.push(s_val[lo], cv[r], wv[r]);
+                if (e < ce0 || e >= ce1) continue;
+                const uint32_t q = (uint32_t)(e - ce0);
+                const uint32_t k = s_owner[q];
+                if (q >= s_s[k] && q < s_e[k]) op.push(s_val[k], cv[r], wv[r]);
             }
         }
         __syncthreads();
@@ -738,6 +850,22 @@ constexpr unsigned GRID_CAP = 1u << 16;
 hipError_t launch_init(const AlgoState& s, uint64_t n, uint32_t source, float pr_x0, float* pr_x, uint32_t* cur,
                        uint32_t nwords, hipStream_t st) {
     k_init<<<grid_for(n > nwords ? n : nwords, 256, 8192), 256, 0, st>>>(s, n, source, pr_x0, pr_x, cur, nwords);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_lanes(const AlgoState& s, const LaneSources& src, uint32_t* cur_union, uint32_t nwords,
+                             hipStream_t st) {
+    k_init_lanes<<<grid_for(s.n * MAX_LANES, 256, 16384), 256, 0, st>>>(s, src, cur_union, nwords);
+    return hipGetLastError();
+}
+
+hipError_t launch_lane_union(const uint64_t* mask, uint64_t n, unsigned long long* lanes, hipStream_t st) {
+    k_lane_union<<<grid_for(n, 256, 2048), 256, 0, st>>>(mask, n, lanes);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_lane(const uint32_t* lval, uint64_t n, uint32_t lane, uint32_t* out, hipStream_t st) {
+    k_extract_lane<<<grid_for(n, 256, 8192), 256, 0, st>>>(lval, n, lane, out);
     return hipGetLastError();
 }
 
@@ -799,6 +927,12 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
     case ALGO_CC:
         return push_edges_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
                              compacted, st);
+    case ALGO_MBFS:
+        return push_edges_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next}, list, wpre, ja, jb,
+                             item_lo, item_hi, off, col, w, shift, compacted, st);
+    case ALGO_MSSSP:
+        return push_edges_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow}, list, wpre, ja, jb, item_lo,
+                             item_hi, off, col, w, shift, compacted, st);
     default:
         return push_edges_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
                              compacted, st);
@@ -827,6 +961,12 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
                              st);
     case ALGO_CC:
         return push_lines_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
+    case ALGO_MBFS:
+        return push_lines_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next}, list, wpre, ja, jb,
+                             item_lo, item_hi, off, col, w, st);
+    case ALGO_MSSSP:
+        return push_lines_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow}, list, wpre, ja, jb, item_lo,
+                             item_hi, off, col, w, st);
     default:
         return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
     }
@@ -860,6 +1000,12 @@ hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t 
         return push_fstream_op(OpSssp{s.val, s.next, s.overflow}, tasks, ntasks, total_chunks, list, off, col, w, st);
     case ALGO_CC:
         return push_fstream_op(OpCc{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, st);
+    case ALGO_MBFS:
+        return push_fstream_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next}, tasks, ntasks,
+                               total_chunks, list, off, col, w, st);
+    case ALGO_MSSSP:
+        return push_fstream_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow}, tasks, ntasks, total_chunks,
+                               list, off, col, w, st);
     default:
         return push_fstream_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, tasks, ntasks, total_chunks, list, off, col, w, st);
     }

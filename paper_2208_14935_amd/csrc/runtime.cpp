@@ -31,7 +31,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/hytm.h"
+#include "hytm.h"
 #include "hytm_kernels.h"
 #include "pool.h"
 
@@ -197,6 +197,10 @@ struct hytm_graph {
     DevBuf<uint8_t> d_sel_out;
     DevBuf<FTask> d_tasks;        // streaming filter tasks of the current iteration
     HostBuf<FTask> h_tasks;
+    // batched runs (up to 64 lanes): lane masks, lane values, lanes active this iteration
+    DevBuf<uint64_t> d_mcur, d_mnext, d_mvis, d_lanes;
+    DevBuf<uint32_t> d_lval;
+    HostBuf<uint64_t> h_lanes;
 
     // host mirrors of the per-iteration selection
     HostBuf<Header> h_hdr;
@@ -415,6 +419,9 @@ void release_all(hytm_graph* g) {
     g->d_sel_out.release();
     g->d_tasks.release();
     g->h_tasks.release();
+    for (auto* b : {&g->d_mcur, &g->d_mnext, &g->d_mvis, &g->d_lanes}) b->release();
+    g->d_lval.release();
+    g->h_lanes.release();
     g->d_hdr.release();
     for (uint32_t i = 0; i < kMaxSlots; i++) {
         g->d_slot_col[i].release();
@@ -553,12 +560,18 @@ void run_compaction(RunCtx* rc, uint32_t cs, uint32_t cc, uint64_t w0, uint64_t 
     *msg = g_err;  // the message is thread-local: hand it back to the calling thread
 }
 
-hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* values_out, uint32_t* iterations_out,
-                     hytm_run_stats* stats, void* hip_stream) {
+// One run.  lanes == 0: single source `sources[0]` (BFS/SSSP) or none (CC/PR), values_out
+// holds n values, iterations_out one count.  lanes in 1..64: batched BFS/SSSP from
+// sources[0..lanes), values_out holds lanes rows of n values, iterations_out one count per
+// lane (the non-empty frontiers of that lane).
+hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uint32_t lanes, void* values_out,
+                     uint32_t* iterations_out, hytm_run_stats* stats, void* hip_stream) {
     HIP_CHECK(hipSetDevice(g->device));
     ensure_streams(g);
     const double t_begin = now_ms();
     const uint32_t arrays = algo == HYTM_SSSP ? 2 : 1;
+    const bool batched = lanes > 0;
+    const uint32_t source = sources ? sources[0] : 0;
     RunCtx rc{};
     rc.g = g;
     rc.algo = algo;
@@ -591,6 +604,14 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
         g->d_x.ensure(n);
         g->d_contrib.ensure(n);
         g->d_acc.ensure(ACC_COPIES * acc_slots(n));
+    }
+    if (batched) {
+        g->d_mcur.ensure(n);
+        g->d_mnext.ensure(n);
+        if (algo == HYTM_BFS) g->d_mvis.ensure(n);
+        g->d_lval.ensure(n * MAX_LANES);
+        g->d_lanes.ensure(1);
+        g->h_lanes.ensure(1);
     }
     g->d_mode.ensure(npart);
     g->d_nA.ensure(npart);
@@ -659,19 +680,33 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
     }
 
     AlgoState& as = rc.as;
-    as.algo = algo;
+    as.algo = batched ? (algo == HYTM_BFS ? ALGO_MBFS : ALGO_MSSSP) : (int)algo;
     as.val = g->d_val.p;
-    as.visited = algo == HYTM_BFS ? g->d_visited.p : nullptr;
+    as.visited = (algo == HYTM_BFS && !batched) ? g->d_visited.p : nullptr;
     as.next = algo == HYTM_PAGERANK ? nullptr : g->d_next.p;
     as.overflow = g->d_overflow.p;
     as.acc = g->d_acc.p;
     as.contrib = g->d_contrib.p;
     as.n = n;
+    uint64_t* mcur = batched ? g->d_mcur.p : nullptr;
+    uint64_t* mnxt = batched ? g->d_mnext.p : nullptr;
+    as.mcur = mcur;
+    as.mnext = mnxt;
+    as.mvisited = (batched && algo == HYTM_BFS) ? g->d_mvis.p : nullptr;
+    as.lval = batched ? g->d_lval.p : nullptr;
     const float x0 = n ? (float)(1.0 / (double)n) : 0.f;
-    HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
-                     [&] { return launch_init(as, n, source, x0, g->d_x.p, g->d_cur.p, nwords, main); }));
+    if (batched) {
+        LaneSources ls{};
+        ls.count = lanes;
+        for (uint32_t l = 0; l < lanes; l++) ls.src[l] = sources[l];
+        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_init_lanes(as, ls, g->d_cur.p, nwords, main); }));
+    } else {
+        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
+                         [&] { return launch_init(as, n, source, x0, g->d_x.p, g->d_cur.p, nwords, main); }));
+    }
     uint32_t* cur = g->d_cur.p;
     uint32_t* nxt = g->d_next.p;
+    uint32_t lane_iters[MAX_LANES] = {};
 
     const float pr_base = (float)((1.0 - g->params.pr_damping) / (double)n);
     const float pr_d = (float)g->params.pr_damping;
@@ -708,12 +743,20 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
         HIP_CHECK(hipMemcpyAsync(g->h_mode.p, g->d_mode.p, npart, hipMemcpyDeviceToHost, main));
         HIP_CHECK(hipMemcpyAsync(g->h_lbase.p, g->d_lbase.p, npart * sizeof(uint32_t), hipMemcpyDeviceToHost, main));
         HIP_CHECK(hipMemcpyAsync(g->h_wbase.p, g->d_wbase.p, npart * sizeof(uint64_t), hipMemcpyDeviceToHost, main));
+        if (batched) {
+            // which lanes have a non-empty frontier this iteration
+            HIP_CHECK(launch_fill_u32((uint32_t*)g->d_lanes.p, 2, 0u, main));
+            HIP_CHECK(launch_lane_union(mcur, n, (unsigned long long*)g->d_lanes.p, main));
+            HIP_CHECK(hipMemcpyAsync(g->h_lanes.p, g->d_lanes.p, sizeof(uint64_t), hipMemcpyDeviceToHost, main));
+        }
         HIP_CHECK(hipStreamSynchronize(main));
         d2h += sizeof(Header) + npart * (1 + 4 + 8);
         const Header h = *g->h_hdr.p;
         select_ms += now_ms() - t_it;
         if (algo != HYTM_PAGERANK && h.frontier == 0) break;
         iters++;
+        if (batched)
+            for (uint32_t l = 0; l < lanes; l++) lane_iters[l] += (uint32_t)((*g->h_lanes.p >> l) & 1);
 
         // per-iteration bookkeeping
         hytm_iter_stats rec{};
@@ -851,6 +894,13 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
             std::swap(cur, nxt);
             as.next = nxt;
             HIP_CHECK(kt.run(HYTM_K_OTHER, nwords, main, [&] { return launch_fill_u32(nxt, nwords, 0u, main); }));
+            if (batched) {
+                std::swap(mcur, mnxt);
+                as.mcur = mcur;
+                as.mnext = mnxt;
+                HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
+                                 [&] { return launch_fill_u32((uint32_t*)mnxt, 2 * n, 0u, main); }));
+            }
         }
         for (int s = 0; s < 5; s++) part_iters[s] += rec.parts[s];
         tot_av += rec.active_vertices;
@@ -871,11 +921,25 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
         HIP_CHECK(hipMemcpy(&of, g->d_overflow.p, sizeof(of), hipMemcpyDeviceToHost));
         if (of) return fail(HYTM_E_RANGE, "an SSSP distance reaches 2^32-1 and does not fit in uint32");
     }
-    const void* src = algo == HYTM_PAGERANK ? (const void*)g->d_x.p : (const void*)g->d_val.p;
-    HIP_CHECK(hipMemcpyAsync(values_out, src, n * 4, hipMemcpyDeviceToHost, main));
+    if (batched) {
+        // lane l of the value rows -> row l of the caller's buffer
+        for (uint32_t l = 0; l < lanes; l++) {
+            HIP_CHECK(launch_extract_lane(g->d_lval.p, n, l, g->d_val.p, main));
+            HIP_CHECK(hipMemcpyAsync((uint32_t*)values_out + (uint64_t)l * n, g->d_val.p, n * 4,
+                                     hipMemcpyDeviceToHost, main));
+        }
+    } else {
+        const void* src = algo == HYTM_PAGERANK ? (const void*)g->d_x.p : (const void*)g->d_val.p;
+        HIP_CHECK(hipMemcpyAsync(values_out, src, n * 4, hipMemcpyDeviceToHost, main));
+    }
     HIP_CHECK(hipStreamSynchronize(main));
     const double t_end = now_ms();
-    if (iterations_out) *iterations_out = iters;
+    if (iterations_out) {
+        if (batched)
+            for (uint32_t l = 0; l < lanes; l++) iterations_out[l] = lane_iters[l];
+        else
+            *iterations_out = iters;
+    }
     if (stats) {
         if (kt.on) {
             // every engine joined the main stream before it was synchronised above
@@ -1118,7 +1182,24 @@ hytm_status hytm_run(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
         return fail(HYTM_E_INVAL, "CC needs a graph created with HYTM_GRAPH_SYMMETRIC");
     if (algo == HYTM_PAGERANK && g->params.pr_iterations == 0)
         return fail(HYTM_E_INVAL, "pr_iterations must be > 0");
-    return guarded([&] { return run_impl(g, algo, source, values_out, iterations_out, stats, hip_stream); });
+    return guarded([&] { return run_impl(g, algo, &source, 0, values_out, iterations_out, stats, hip_stream); });
+}
+
+hytm_status hytm_run_batch(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uint32_t nsources,
+                           void* values_out, uint32_t* iterations_out, hytm_run_stats* stats, void* hip_stream) {
+    g_err.clear();
+    if (!g) return fail(HYTM_E_INVAL, "graph is NULL");
+    if (!values_out || !sources) return fail(HYTM_E_INVAL, "NULL argument");
+    if (algo != HYTM_BFS && algo != HYTM_SSSP) return fail(HYTM_E_INVAL, "batched runs support BFS and SSSP");
+    if (nsources == 0 || nsources > MAX_LANES) return fail(HYTM_E_INVAL, "nsources must be in 1..64");
+    if (stats && stats->struct_size != sizeof(hytm_run_stats))
+        return fail(HYTM_E_INVAL, "stats.struct_size mismatch");
+    for (uint32_t l = 0; l < nsources; l++)
+        if (sources[l] >= g->n)
+            return fail(HYTM_E_RANGE, "sources[%u] = %u >= n = %llu", l, sources[l], (unsigned long long)g->n);
+    if (algo == HYTM_SSSP && !g->h_w) return fail(HYTM_E_INVAL, "SSSP needs edge weights");
+    return guarded(
+        [&] { return run_impl(g, algo, sources, nsources, values_out, iterations_out, stats, hip_stream); });
 }
 
 hytm_status hytm_select_engines(hytm_graph* g, uint64_t npart, const uint64_t* E, const uint64_t* nA,
