@@ -69,6 +69,7 @@ def _load():
         "orc_sync_rounds": (u32, [u64, vp, vp, vp, i32, u32]),
         "orc_cc": (u64, [u64, vp, vp, vp]),
         "orc_pagerank": (None, [u64, vp, vp, dbl, u32, vp]),
+        "orc_ppr": (None, [u64, vp, vp, u32, dbl, u32, vp]),
         "orc_partition": (u64, [u64, vp, u64, vp]),
         "orc_partition_stats": (None, [u64, vp, vp, vp, u32, u32, vp, vp, vp]),
         "orc_select": (None, [u64, vp, vp, vp, vp, u64, ctypes.POINTER(_CostParams), i32, vp]),
@@ -135,6 +136,17 @@ def pagerank(off, col, d: float = 0.85, T: int = 20):
     off, col, n = _csr(off, col)
     x = np.empty(max(n, 1), dtype=np.float64)[:n]
     _load().orc_pagerank(n, _p(off), _p(col), float(d), int(T), _p(x))
+    return x
+
+
+def ppr(off, col, source: int, d: float = 0.85, T: int = 10):
+    """FP64 personalized PageRank x_T from `source` (x_0 = e_s, restart 1 - d at s,
+    dangling mass leaks)."""
+    off, col, n = _csr(off, col)
+    if not 0 <= source < n:
+        raise ValueError("source out of range")
+    x = np.empty(max(n, 1), dtype=np.float64)[:n]
+    _load().orc_ppr(n, _p(off), _p(col), int(source), float(d), int(T), _p(x))
     return x
 
 

@@ -21,6 +21,9 @@
  *  - orc_cc       : union-find (union by size, path halving), label = min vertex id
  *                   in the component (Sec. 7.1 "connected component").
  *  - orc_pagerank : FP64 power iteration, T synchronous steps (Sec. 3, Sec. 7.1).
+ *  - orc_ppr      : personalized PageRank: the same iteration with the restart mass
+ *                   on one source vertex instead of spread over all of them, x_0 = e_s
+ *                   (the query served alongside BFS and SSSP).  FP64.
  *  - orc_partition: chunk-based edge-balanced partitioning into consecutive vertex
  *                   ranges (Sec. 4).
  *  - orc_partition_stats / orc_select : the per-partition cost model, Eq. 1-3 with the
@@ -242,6 +245,27 @@ void orc_pagerank(uint64_t n, const uint64_t *off, const uint32_t *col, double d
             for (uint64_t e = off[u]; e < off[u + 1]; e++) acc[col[e]] += share;
         }
         for (uint64_t v = 0; v < n; v++) x[v] = (1.0 - d) / (double)n + d * acc[v];
+    }
+    free(acc);
+}
+
+/* Personalized PageRank from `source`: x_0 = e_s and
+       x_{t+1}(v) = (1 - d) [v == s] + d * sum over edges (u, v) of x_t(u) / D_o(u),
+   T steps; a vertex without out-edges passes nothing on (its mass leaks), as in
+   orc_pagerank. */
+void orc_ppr(uint64_t n, const uint64_t *off, const uint32_t *col, uint32_t source, double d, uint32_t T,
+             double *x) {
+    double *acc = (double *)malloc((n ? n : 1) * sizeof(double));
+    for (uint64_t v = 0; v < n; v++) x[v] = v == source ? 1.0 : 0.0;
+    for (uint32_t t = 0; t < T; t++) {
+        for (uint64_t v = 0; v < n; v++) acc[v] = 0.0;
+        for (uint64_t u = 0; u < n; u++) {
+            uint64_t deg = off[u + 1] - off[u];
+            if (deg == 0 || x[u] == 0.0) continue;
+            double share = x[u] / (double)deg;
+            for (uint64_t e = off[u]; e < off[u + 1]; e++) acc[col[e]] += share;
+        }
+        for (uint64_t v = 0; v < n; v++) x[v] = (v == source ? 1.0 - d : 0.0) + d * acc[v];
     }
     free(acc);
 }

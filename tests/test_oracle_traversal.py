@@ -292,3 +292,92 @@ def test_pagerank_closed_forms_and_mass_invariant():
     A = sp.csr_matrix((np.ones(len(col)), col.astype(np.int64), off.astype(np.int64)), shape=(n, n))
     share = np.where(deg > 0, x19 / np.maximum(deg, 1), 0.0)
     np.testing.assert_allclose(x20, (1 - d) / n + d * (A.T @ share), rtol=1e-12, atol=1e-18)
+
+
+# ------------------------------------------------- personalized PageRank
+def test_ppr_closed_form_on_a_path():
+    # path 0 -> 1 -> ... -> 14: the walk moves one hop per step, so after T steps
+    # vertex j < T holds the restart mass that survived j hops and vertex T the
+    # initial unit that survived T hops; the end of the path leaks.
+    n, d = 15, 0.85
+    off, col = csr_from_edges(n, [(i, i + 1) for i in range(n - 1)])
+    for T in (0, 1, 2, 5, 10, 14):
+        want = np.zeros(n)
+        want[:T] = (1 - d) * d ** np.arange(T)
+        want[T] = d ** T
+        np.testing.assert_allclose(oracle.ppr(off, col, 0, d, T), want, rtol=1e-14, atol=1e-300)
+    # started mid-path, nothing flows backwards
+    x = oracle.ppr(off, col, 9, d, 10)
+    assert (x[:9] == 0).all()
+    # the sink keeps receiving restart mass that made 5 hops (it passes nothing on)
+    np.testing.assert_allclose(x[9:], (1 - d) * d ** np.arange(6), rtol=1e-14)
+
+
+def test_ppr_averages_to_pagerank():
+    # uniform start and uniform restart are the average of the point ones, and the
+    # iteration is linear: PageRank = mean over sources of the personalized vectors
+    off, col = gen.rmat(7, 6, seed=5)
+    n = len(off) - 1
+    for T in (1, 4, 10):
+        mean = np.mean([oracle.ppr(off, col, s, 0.85, T) for s in range(n)], axis=0)
+        np.testing.assert_allclose(mean, oracle.pagerank(off, col, 0.85, T), rtol=1e-12, atol=1e-17)
+
+
+def test_ppr_converges_to_the_linear_solve():
+    # x* = (1-d) (I - d P)^-1 e_s with P the column-substochastic transition matrix;
+    # the step is a d-contraction in L1, so |x_T - x*|_1 <= d^T |x_0 - x*|_1 <= 2 d^T
+    import scipy.sparse.linalg as spla
+    off, col = gen.rmat(10, 8, seed=10)
+    n, d = len(off) - 1, 0.85
+    deg = np.diff(off).astype(np.float64)
+    src = np.repeat(np.arange(n), np.diff(off).astype(np.int64))
+    P = sp.csr_matrix((1.0 / deg[src], (col.astype(np.int64), src)), shape=(n, n))
+    for s in (0, 3, 77):
+        e = np.zeros(n)
+        e[s] = 1.0
+        xs = spla.spsolve((sp.identity(n) - d * P).tocsc(), (1 - d) * e)
+        for T in (10, 60, 200):
+            err = np.abs(oracle.ppr(off, col, s, d, T) - xs).sum()
+            assert err <= 2 * d ** T + 1e-12, (s, T, err)
+
+
+def test_ppr_mass_and_support():
+    # on a graph without sinks the mass stays 1; the support after T steps is the set
+    # of vertices within T hops of the source
+    off, col = gen.symmetrize(*gen.rmat(9, 8, seed=3))
+    deg = np.diff(off)
+    s = int(np.nonzero(deg)[0][0])
+    lvl, _ = oracle.bfs(off, col, s)
+    comp = lvl != U
+    assert (deg[comp] > 0).all()
+    for T in (0, 1, 2, 3, 10):
+        x = oracle.ppr(off, col, s, 0.85, T)
+        assert abs(x.sum() - 1.0) < 1e-12
+        np.testing.assert_array_equal(x > 0, lvl <= T)
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(1, 7).flatmap(lambda n: st.tuples(
+    st.just(n), st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=16),
+    st.integers(0, n - 1), st.integers(0, 10))))
+def test_ppr_matches_matrix_powers(case):
+    # x_T = d^T P^T e_s + (1-d) sum_{j<T} d^j P^j e_s, by exact dense rational powers
+    n, edges, s, T = case
+    edges = sorted({e for e in edges if e[0] != e[1]})
+    off, col = csr_from_edges(n, edges)
+    deg = [sum(1 for u, _ in edges if u == a) for a in range(n)]
+    P = [[Fraction(0)] * n for _ in range(n)]
+    for u, v in edges:
+        P[v][u] += Fraction(1, deg[u])
+    d = Fraction(85, 100)
+
+    def mul(vec):
+        return [sum(P[i][j] * vec[j] for j in range(n)) for i in range(n)]
+
+    p = [Fraction(int(i == s)) for i in range(n)]
+    want = [Fraction(0)] * n
+    for j in range(T):
+        want = [w + (1 - d) * d ** j * a for w, a in zip(want, p)]
+        p = mul(p)
+    want = [w + d ** T * a for w, a in zip(want, p)]
+    np.testing.assert_allclose(oracle.ppr(off, col, s, 0.85, T), [float(f) for f in want], rtol=0, atol=1e-15)
