@@ -62,10 +62,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--probe-bytes", type=int, default=1 << 30)
-    ap.add_argument("--workload", default="quarter-budget", choices=["quarter-budget", "batch"],
+    ap.add_argument("--workload", default="quarter-budget", choices=["quarter-budget", "batch", "serve", "modes"],
                     help="quarter-budget: the headline step; batch: 64-source BFS/SSSP in one traversal "
-                         "against 64 sequential single-source runs")
+                         "against 64 sequential single-source runs; serve: Poisson arrivals of a BFS/SSSP/PPR "
+                         "mix through the query server against one query at a time")
     ap.add_argument("--lanes", type=int, default=64)
+    ap.add_argument("--qps", type=float, default=50.0, help="serve: mean arrival rate")
+    ap.add_argument("--graph", default="rmat", choices=["rmat", "er"],
+                    help="rmat: R-MAT at --scale; er: uniform G(n, m) with --er-vertices and --er-degree")
+    ap.add_argument("--er-vertices", type=int, default=200_000_000)
+    ap.add_argument("--er-degree", type=float, default=20.0)
+    ap.add_argument("--budget-bytes", type=float, default=0,
+                    help="modes: absolute device budget for edge data (0 = --budget-frac of each algorithm's bytes)")
+    ap.add_argument("--modes", default="filter,compact,zerocopy,hybrid", help="modes: transfer modes to compare")
+    ap.add_argument("--queries", type=int, default=200, help="serve: queries in the arrival trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -75,14 +85,18 @@ def main():
 
     t0 = time.time()
     gen.set_threads(min(16, os.cpu_count() or 1))
-    off, col = gen.rmat(args.scale, args.edge_factor, seed=args.scale)
+    if args.graph == "er":
+        off, col = gen.er(args.er_vertices, int(args.er_vertices * args.er_degree), seed=7)
+    else:
+        off, col = gen.rmat(args.scale, args.edge_factor, seed=args.scale)
     n, m = len(off) - 1, len(col)
     w = gen.weights(off, col, 1000 + args.scale)
     srcs = gen.sources(off, args.sources, 2000 + args.scale)
-    need_sym = "cc" in algos and args.workload != "batch"
+    need_sym = "cc" in algos and args.workload in ("quarter-budget", "modes")
     soff, scol = gen.symmetrize(off, col) if need_sym else (None, None)
     deg = np.diff(off).astype(np.int64)
-    log(f"graph: rmat{args.scale} n={n} m={m} m_sym={len(scol) if scol is not None else 0} "
+    gname = f"er{n}-d{args.er_degree:g}" if args.graph == "er" else f"rmat{args.scale}"
+    log(f"graph: {gname} n={n} m={m} m_sym={len(scol) if scol is not None else 0} "
         f"max_deg={deg.max()} gen {time.time() - t0:.1f}s")
 
     probe = hy.link_probe(args.probe_bytes)
@@ -100,6 +114,10 @@ def main():
                          filter_engine=args.filter_engine, gamma=gamma)
     if args.workload == "batch":
         return batch_workload(args, g, off, col, deg, gamma, probe)
+    if args.workload == "serve":
+        return serve_workload(args, g, off, gamma, probe)
+    if args.workload == "modes":
+        return modes_workload(args, gname, g, gs, deg, srcs[:1], algos, gamma, probe)
 
     def budget(h, arrays):
         h.set_budget(int(args.budget_frac * 4 * arrays * h.m))
@@ -114,25 +132,29 @@ def main():
         lv = g.run("bfs", int(s)).values
         reach_edges[int(s)] = int(deg[lv != hy.UNREACHED].sum())
 
+    # results land in pinned host buffers (direct DMA); each run overwrites the previous one
+    out_u32 = hy.pinned_empty(max(g.n, gs.n) if gs is not None else g.n, np.uint32)
+    out_f32 = hy.pinned_empty(g.n, np.float32)
+
     def step(record):
         runs = []
         if "bfs" in algos:
             budget(g, 1)
             for s in srcs:
-                r = g.run("bfs", int(s), stats=True, time_kernels=kt and record)
+                r = g.run("bfs", int(s), stats=True, time_kernels=kt and record, out=out_u32[: g.n])
                 runs.append(("bfs", r, reach_edges[int(s)]))
         if "pagerank" in algos:
             budget(g, 1)
-            r = g.run("pagerank", stats=True, time_kernels=kt and record)
+            r = g.run("pagerank", stats=True, time_kernels=kt and record, out=out_f32)
             runs.append(("pagerank", r, 20 * m))
         if "sssp" in algos:
             budget(g, 2)
             for s in srcs:
-                r = g.run("sssp", int(s), stats=True, time_kernels=kt and record)
+                r = g.run("sssp", int(s), stats=True, time_kernels=kt and record, out=out_u32[: g.n])
                 runs.append(("sssp", r, reach_edges[int(s)]))
         if "cc" in algos:
             budget(gs, 1)
-            r = gs.run("cc", stats=True, time_kernels=kt and record)
+            r = gs.run("cc", stats=True, time_kernels=kt and record, out=out_u32[: gs.n])
             runs.append(("cc", r, gs.m))
         return runs
 
@@ -267,21 +289,23 @@ def batch_workload(args, g, off, col, deg, gamma, probe):
         reach.append(int(deg[lv != hy.UNREACHED].sum()))
     edges = sum(reach)
     res = {}
+    out_b = hy.pinned_empty((len(srcs), g.n), np.uint32)
+    out_1 = hy.pinned_empty(g.n, np.uint32)
     for algo, arrays in (("bfs", 1), ("sssp", 2)):
         g.set_budget(int(args.budget_frac * 4 * arrays * g.m))
-        g.run_batch(algo, srcs)  # warm-up
+        g.run_batch(algo, srcs, out=out_b)  # warm-up
         times = []
         for _ in range(args.steps):
             sync()
             t = time.perf_counter()
-            vals, its, st = g.run_batch(algo, srcs, stats=True)
+            vals, its, st = g.run_batch(algo, srcs, stats=True, out=out_b)
             sync()
             times.append(time.perf_counter() - t)
         tb = min(times)
         sync()
         t = time.perf_counter()
         for s in srcs:
-            g.run(algo, int(s))
+            g.run(algo, int(s), out=out_1)
         sync()
         ts = time.perf_counter() - t
         res[algo] = {"batched_ms": tb * 1e3, "sequential_ms": ts * 1e3, "speedup": ts / tb,
@@ -298,6 +322,139 @@ def batch_workload(args, g, off, col, deg, gamma, probe):
         "config": {"workload": f"rmat{args.scale}-batch{len(srcs)}-budget{args.budget_frac:g}", "n": n, "m": m,
                    "lanes": len(srcs), "mode": args.mode, "filter_engine": args.filter_engine, "gamma": list(gamma)},
         "batch": res, "probe": probe,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def modes_workload(args, gname, g, gs, deg, srcs, algos, gamma, probe):
+    """Every algorithm once under each transfer mode at one device budget (absolute
+    --budget-bytes, else --budget-frac of the algorithm's edge bytes): GTEPS and the host
+    link's achieved GB/s (explicit + zero-copy + resident-fill bytes over run time) against
+    the measured pinned-copy peak."""
+    s = int(srcs[0])
+    lv = g.run("bfs", s).values  # reach of the source, outside the timed runs
+    reach = int(deg[lv != hy.UNREACHED].sum())
+    work = {"bfs": reach, "sssp": reach, "cc": gs.m if gs is not None else 0, "pagerank": 20 * g.m}
+    table = {}
+    for mode in args.modes.split(","):
+        for a in algos:
+            h = gs if a == "cc" else g
+            arrays = 2 if a == "sssp" else 1
+            h.set_params(mode=mode)
+            h.set_budget(int(args.budget_bytes) if args.budget_bytes else int(args.budget_frac * 4 * arrays * h.m))
+            try:
+                r = h.run(a, s, stats=True)
+            except hy.HytmError as e:  # a forced engine whose staging does not fit
+                table[f"{mode}/{a}"] = {"error": str(e)}
+                log(f"{mode:9s} {a:9s} {e}")
+                continue
+            st = r.stats
+            sec = st["ms_total"] / 1e3
+            moved = st["bytes_filter"] + st["bytes_compact"] + st["bytes_zerocopy"] + st["bytes_resident_fill"]
+            row = {"ms": st["ms_total"], "gteps": work[a] / sec / 1e9, "iterations": r.iterations,
+                   "link_gbps": moved / sec / 1e9, "link_frac": moved / sec / 1e9 / probe["h2d_copy_gbps"],
+                   "bytes_filter": st["bytes_filter"], "bytes_compact": st["bytes_compact"],
+                   "bytes_zerocopy": st["bytes_zerocopy"], "bytes_resident_fill": st["bytes_resident_fill"],
+                   "nres": st["nres"], "npart": st["npart"],
+                   "engine_partition_iters": dict(zip(hy.ENGINE_NAMES, st["part_iters"]))}
+            table[f"{mode}/{a}"] = row
+            log(f"{mode:9s} {a:9s} {row['ms']:9.1f} ms  {row['gteps']:6.2f} GTEPS  link {row['link_gbps']:5.1f} GB/s "
+                f"({row['link_frac'] * 100:4.1f}%)  iters {r.iterations}")
+    hyb = [v for k, v in table.items() if k.startswith("hybrid/") and "ms" in v]
+    tot_ms = sum(v["ms"] for v in hyb)
+    value = sum(work[k.split("/")[1]] for k, v in table.items() if k.startswith("hybrid/") and "ms" in v) / (tot_ms / 1e3) / 1e9 if hyb else None
+    out = {
+        "metric": "GTEPS for BFS/SSSP/CC/PR at capped HBM budget; host-link GB/s vs peak",
+        "value": value, "unit": "GTEPS", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": tot_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 (BFS/SSSP/CC), f32 (PageRank)", "data": "synthetic, seeded",
+        "config": {"workload": f"{gname}-budget{args.budget_bytes / 1e9:g}GB-modes" if args.budget_bytes
+                   else f"{gname}-budget{args.budget_frac:g}-modes", "n": int(g.n), "m": int(g.m),
+                   "m_sym": int(gs.m) if gs is not None else None, "source": s, "gamma": list(gamma)},
+        "modes": table, "probe": probe,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_workload(args, g, off, gamma, probe):
+    """A seeded trace of Poisson arrivals (mean rate --qps) carrying 50% BFS, 30% SSSP and
+    20% personalized PageRank (10 steps, restart 0.15) queries.  The server run submits
+    each query at its arrival time and measures submit-to-result latency inside the
+    library.  The one-at-a-time reference runs the same queries back to back through
+    hytm_run and replays the trace through a single FIFO server with those service times.
+    --budget-frac < 0 keeps the graph device-resident."""
+    n = len(off) - 1
+    rng = np.random.default_rng(6000 + args.scale)
+    kinds = rng.choice(["bfs", "sssp", "ppr"], size=args.queries, p=[0.5, 0.3, 0.2])
+    srcs = gen.sources(off, args.queries, 6100 + args.scale)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.qps, size=args.queries))
+    if args.budget_frac >= 0:
+        g.set_budget(int(args.budget_frac * 8 * g.m))  # planned for the weighted arrays
+    outs = {k: hy.pinned_empty(n, np.float32 if k == "ppr" else np.uint32) for k in ("bfs", "sssp", "ppr")}
+    for k in ("bfs", "sssp", "ppr"):
+        g.run(k, int(srcs[0]), out=outs[k])  # warm-up: buffers and resident cache
+    service = []
+    for k, s in zip(kinds, srcs):
+        t = time.perf_counter()
+        g.run(str(k), int(s), out=outs[str(k)])
+        service.append(time.perf_counter() - t)
+    finish, seq_lat = 0.0, []
+    for a, sv in zip(arrivals, service):
+        finish = max(finish, a) + sv
+        seq_lat.append(finish - a)
+    seq_span = finish - arrivals[0]
+    log(f"one at a time: service p50 {np.percentile(service, 50) * 1e3:.1f} ms, busy {sum(service):.2f}s "
+        f"for a {arrivals[-1]:.2f}s trace")
+
+    lanes = min(64, args.lanes)
+    # result buffers per kind: enough for every query of the kind in flight or queued, up to
+    # 2 x lanes; latency counts from the scheduled arrival, so a submit held back by a
+    # missing buffer is charged to the server
+    bufs = {k: [hy.pinned_empty(n, np.float32 if k == "ppr" else np.uint32)
+                for _ in range(min(2 * lanes, int((kinds == k).sum()) or 1))] for k in ("bfs", "sssp", "ppr")}
+    with hy.Server(g, bfs=lanes, sssp=lanes, ppr=lanes) as srv:
+        warm = [srv.submit(k, int(srcs[0])) for k in ("bfs", "sssp", "ppr")]
+        for q in warm:
+            srv.wait(q)
+        subs = []
+        free = {k: list(range(lanes)) for k in bufs}
+        t0 = time.perf_counter()
+        pending = []
+        for i, (k, s) in enumerate(zip(kinds, srcs)):
+            k = str(k)
+            while time.perf_counter() - t0 < arrivals[i] - arrivals[0]:
+                time.sleep(0.0002)
+            if not free[k]:  # every buffer of this kind is busy: wait for the oldest query of the kind
+                j = next(x for x in range(len(pending)) if pending[x][1] == k)
+                q, _, b, lag = pending.pop(j)
+                srv.wait(q)
+                subs.append((q.result, lag))
+                free[k].append(b)
+            b = free[k].pop()
+            lag = (time.perf_counter() - t0 - (arrivals[i] - arrivals[0])) * 1e3
+            pending.append((srv.submit(k, int(s), out=bufs[k][b]), k, b, lag))
+        for q, k, b, lag in pending:
+            srv.wait(q)
+            subs.append((q.result, lag))
+        span = time.perf_counter() - t0
+    lat = np.array([r["total_ms"] + lag for r, lag in subs])
+    subs = [r for r, _ in subs]
+    seq = np.array(seq_lat) * 1e3
+    res = {
+        "server": {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "qps": args.queries / span, "queue_p99_ms": float(np.percentile([r["queue_ms"] for r in subs], 99))},
+        "one_at_a_time": {"p50_ms": float(np.percentile(seq, 50)), "p99_ms": float(np.percentile(seq, 99)),
+                          "qps": args.queries / seq_span, "service_p50_ms": float(np.percentile(service, 50)) * 1e3},
+    }
+    log(json.dumps(res))
+    out = {
+        "metric": f"serving p99 latency, Poisson arrivals at {args.qps:g} QPS, 50/30/20 BFS/SSSP/PPR",
+        "value": res["server"]["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.queries, "warmup": 3,
+        "ms_per_step": span * 1e3 / args.queries, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32+f32", "data": "synthetic R-MAT, seeded arrivals",
+        "config": {"workload": f"rmat{args.scale}-serve-{args.qps:g}qps", "n": n, "m": int(g.m), "lanes": lanes,
+                   "budget_frac": args.budget_frac, "gamma": list(gamma)},
+        "serve": res, "probe": probe,
     }
     print(json.dumps(out), flush=True)
 

@@ -54,8 +54,11 @@ typedef enum {
 
 /* Algorithms (Sec. 7.1).  Outputs are one 4-byte value per vertex:
    BFS: uint32 hop level; SSSP: uint32 distance; CC: uint32 label = smallest vertex id
-   of the component; PAGERANK: float rank.  Unreached vertices hold 0xFFFFFFFF. */
-typedef enum { HYTM_BFS = 0, HYTM_SSSP = 1, HYTM_CC = 2, HYTM_PAGERANK = 3 } hytm_algo;
+   of the component; PAGERANK: float rank.  Unreached vertices hold 0xFFFFFFFF.
+   PPR: personalized PageRank from a source s, float: the PageRank step with all of the
+   restart mass (1 - pr_damping) at s, from x_0 = e_s, ppr_iterations synchronous steps;
+   mass that reaches a vertex without out-edges leaks, as in PAGERANK. */
+typedef enum { HYTM_BFS = 0, HYTM_SSSP = 1, HYTM_CC = 2, HYTM_PAGERANK = 3, HYTM_PPR = 4 } hytm_algo;
 
 /* Transfer policy for partitions that are not resident.  HYBRID applies the cost
    model of Sec. 5.1; the others force one engine for every scheduled partition. */
@@ -97,7 +100,7 @@ typedef struct {
     uint32_t gather_threads;    /* 0 = automatic: host threads of the compaction engine */
     uint64_t compact_chunk_edges; /* 0 = automatic: edges per compaction chunk */
     uint32_t filter_engine;     /* HYTM_FILTER_STREAM (default) or HYTM_FILTER_COPY, see below */
-    uint32_t reserved0;
+    uint32_t ppr_iterations;    /* 10: steps of HYTM_PPR (restart mass 1 - pr_damping) */
 } hytm_params;
 
 /* How a FILTER task moves its whole partition range to the GPU.  Both transfer every
@@ -251,7 +254,7 @@ hytm_status hytm_partition_bounds(const hytm_graph *g, uint64_t *bounds, uint64_
 hytm_status hytm_run(hytm_graph *g, hytm_algo algo, uint32_t source, void *values_out, uint32_t *iterations_out,
                      hytm_run_stats *stats, void *hip_stream);
 
-/* Batched BFS or SSSP from up to 64 sources in one traversal.  Each vertex carries a
+/* Batched BFS, SSSP or PPR from up to 64 sources in one traversal.  Each vertex carries a
    64-bit mask of the sources (lanes) active at it and one uint32 value per lane; a vertex
    is active when any lane is, so the cost model (Sec. 5.1) runs on the union frontier and
    every edge moved over the host link serves all lanes at once.  Lane l's values equal
@@ -259,9 +262,10 @@ hytm_status hytm_run(hytm_graph *g, hytm_algo algo, uint32_t source, void *value
    sources        : host array of nsources vertex ids (1..64 entries; repeats allowed).
    values_out     : host buffer of nsources x n uint32, row l = results of sources[l].
    iterations_out : NULL or nsources counts: the non-empty frontiers of each lane.
+   values_out is float for PPR (row l = x from sources[l]).
    Errors as hytm_run; E_INVAL also for CC/PageRank or nsources outside 1..64.  Device
-   memory for the lanes (n x 64 x 4 bytes of values + three n x 8-byte masks) is vertex
-   data, outside the edge budget. */
+   memory for the lanes (n x L x 4 bytes of values, twice for PPR, with L the power of two
+   >= nsources, plus three n x 8-byte masks) is vertex data, outside the edge budget. */
 hytm_status hytm_run_batch(hytm_graph *g, hytm_algo algo, const uint32_t *sources, uint32_t nsources,
                            void *values_out, uint32_t *iterations_out, hytm_run_stats *stats, void *hip_stream);
 
@@ -277,7 +281,68 @@ hytm_status hytm_select_engines(hytm_graph *g, uint64_t npart, const uint64_t *E
                                 const uint64_t *Ea, const uint64_t *Rq, uint64_t nres, uint32_t edge_arrays,
                                 uint8_t *p_out);
 
-/* Free everything the handle owns.  NULL is accepted. */
+/* Pinned host memory for result buffers: a values_out buffer from here is written by DMA
+   directly, without the staging copy an ordinary (pageable) buffer needs.  hip_device
+   selects the device the allocation is registered with.  hytm_host_free(NULL) is a no-op. */
+hytm_status hytm_host_alloc(int hip_device, uint64_t bytes, void **out);
+hytm_status hytm_host_free(void *p);
+
+/* ---------------------------------------------------------------- serving
+   A query server over one graph: BFS, SSSP and PPR queries submitted from any thread
+   join free lanes of a per-algorithm lane group between iterations (continuous
+   batching) and leave it as soon as their own traversal ends, so a query never waits
+   for the rest of its batch.  One worker thread steps every group that holds queries,
+   one iteration at a time, through the same engines as hytm_run_batch: the cost model
+   runs on each group's union frontier, so an edge moved over the host link serves every
+   query in the group.  Results equal those of hytm_run for the same query.
+   Lane state lives in device memory outside the edge budget; the lanes of each group
+   are fixed when the server opens, and the server refuses (E_BUDGET) a configuration
+   whose lane state exceeds state_budget.  A query waits in the queue until a lane of its
+   group is free.  While a server is open, every other call on its graph except
+   hytm_graph_info_get and hytm_get_params returns E_STATE. */
+typedef struct hytm_server hytm_server;
+
+typedef struct {
+    uint32_t struct_size;      /* sizeof(hytm_server_config) */
+    uint32_t lanes[3];         /* lanes of the BFS, SSSP and PPR groups: 0 (no group) or 1..64 */
+    uint64_t state_budget;     /* device bytes for lane state; 0 = no limit */
+    uint64_t max_pending;      /* queue bound; submit returns E_STATE when full (0 = no bound) */
+} hytm_server_config;
+
+typedef struct {
+    hytm_status status;        /* HYTM_OK, or E_RANGE (SSSP overflow), E_DEVICE ... */
+    uint32_t iterations;       /* non-empty frontiers of this query (PPR: ppr_iterations) */
+    double queue_ms;           /* submit -> admitted into a lane */
+    double run_ms;             /* admitted -> values written */
+    double total_ms;           /* submit -> values written */
+} hytm_query_result;
+
+/* Device bytes of lane state for `lanes` lanes of `algo` (BFS/SSSP/PPR) on graph g. */
+hytm_status hytm_server_state_bytes(const hytm_graph *g, hytm_algo algo, uint32_t lanes, uint64_t *bytes);
+
+/* Open a server on g (the graph's parameters and budget apply; set them before).
+   The edge budget is planned once for the weighted arrays when an SSSP group exists. */
+hytm_status hytm_server_open(hytm_graph *g, const hytm_server_config *cfg, hytm_server **out);
+
+/* Queue a query.  values_out: caller buffer of n 4-byte values (float for PPR) that must
+   stay valid until hytm_server_wait returns for the ticket; a pinned buffer
+   (hytm_host_alloc) is written by DMA directly.  E_INVAL if the algorithm has no group
+   or no weights (SSSP); E_RANGE if source >= n. */
+hytm_status hytm_server_submit(hytm_server *s, hytm_algo algo, uint32_t source, void *values_out,
+                               uint64_t *ticket);
+
+/* Block until the query is done (timeout_ms < 0: no limit); then fill *result (NULL ok)
+   and return its status.  E_STATE if the ticket is unknown or already waited for, or the
+   timeout passed (the ticket stays valid). */
+hytm_status hytm_server_wait(hytm_server *s, uint64_t ticket, double timeout_ms, hytm_query_result *result);
+
+/* Finish every queued query, stop the worker, free the lane state and release the graph.
+   Tickets not waited for are dropped.  Returns the error that stopped the worker, if a
+   step failed (every query then failed with it).  NULL is accepted. */
+hytm_status hytm_server_close(hytm_server *s);
+
+/* Free everything the handle owns.  NULL is accepted; E_STATE while a query server is
+   open on the graph. */
 hytm_status hytm_graph_destroy(hytm_graph *g);
 
 /* Thread-local message for the last failed call on this thread ("" if none). */

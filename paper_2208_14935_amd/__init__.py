@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libhytm.so")
 
 OK, E_INVAL, E_RANGE, E_NOMEM, E_BUDGET, E_DEVICE, E_STATE, E_UNSUPPORTED = range(8)
 STATUS_NAMES = ["OK", "E_INVAL", "E_RANGE", "E_NOMEM", "E_BUDGET", "E_DEVICE", "E_STATE", "E_UNSUPPORTED"]
-ALGOS = {"bfs": 0, "sssp": 1, "cc": 2, "pagerank": 3, "pr": 3}
+ALGOS = {"bfs": 0, "sssp": 1, "cc": 2, "pagerank": 3, "pr": 3, "ppr": 4}
+FLOAT_ALGOS = (3, 4)
 MODES = {"hybrid": 0, "filter": 1, "compact": 2, "zerocopy": 3}
 P_NONE, P_RESIDENT, P_FILTER, P_ZEROCOPY, P_COMPACT = range(5)
 ENGINE_NAMES = ["none", "resident", "filter", "zerocopy", "compact"]
@@ -46,7 +47,7 @@ class Params(ctypes.Structure):
         ("index_bytes", ctypes.c_uint32), ("pr_iterations", ctypes.c_uint32), ("pr_damping", ctypes.c_double),
         ("streams", ctypes.c_uint32), ("gather_threads", ctypes.c_uint32),
         ("compact_chunk_edges", ctypes.c_uint64), ("filter_engine", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32),
+        ("ppr_iterations", ctypes.c_uint32),
     ]
 
 
@@ -86,6 +87,16 @@ class LinkProbe(ctypes.Structure):
                 ("zc_read_gbps", ctypes.c_double * 4), ("hbm_copy_gbps", ctypes.c_double)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("lanes", ctypes.c_uint32 * 3), ("state_budget", ctypes.c_uint64),
+                ("max_pending", ctypes.c_uint64)]
+
+
+class QueryResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_uint32), ("queue_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("m", ctypes.c_uint64), ("npart", ctypes.c_uint32),
                 ("max_partition_edges", ctypes.c_uint32), ("hip_device", ctypes.c_int), ("flags", ctypes.c_uint32)]
@@ -113,7 +124,45 @@ _SIGNATURES = {
     "hytm_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "hytm_last_error": (ctypes.c_char_p, []),
     "hytm_link_probe": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(LinkProbe)]),
+    "hytm_host_alloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]),
+    "hytm_host_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "hytm_server_state_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32,
+                                               ctypes.POINTER(ctypes.c_uint64)]),
+    "hytm_server_open": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerConfig),
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "hytm_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "hytm_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double,
+                                        ctypes.POINTER(QueryResult)]),
+    "hytm_server_close": (ctypes.c_int, [ctypes.c_void_p]),
 }
+
+
+class _PinnedBlock:
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        try:
+            load().hytm_host_free(self.ptr)
+        except Exception:
+            pass
+
+
+def pinned_empty(shape, dtype=np.uint32, device: int = 0) -> np.ndarray:
+    """numpy array over pinned host memory (freed with the array); pass it as `out=` so a
+    run's results arrive by direct DMA."""
+    dtype = np.dtype(dtype)
+    count = int(np.prod(shape)) if np.ndim(shape) else int(shape)
+    p = ctypes.c_void_p()
+    _check(load().hytm_host_alloc(device, max(count * dtype.itemsize, 1), ctypes.byref(p)))
+    block = _PinnedBlock(p)
+    buf = (ctypes.c_char * max(count * dtype.itemsize, 1)).from_address(p.value)
+    arr = np.frombuffer(buf, dtype=dtype, count=count).reshape(shape)
+    arr.flags.writeable = True
+    # keep the allocation alive as long as the array (numpy keeps `buf` via .base)
+    buf._hytm_block = block
+    return arr
 
 
 def link_probe(bytes_: int = 1 << 30, device: int = 0) -> dict:
@@ -213,6 +262,9 @@ class Graph:
         self.symmetric = symmetric
 
     def close(self):
+        srv = getattr(self, "_server", None)
+        if srv is not None:
+            srv.close()
         if getattr(self, "_h", None):
             load().hytm_graph_destroy(self._h)
             self._h = None
@@ -283,8 +335,13 @@ class Graph:
             out: np.ndarray | None = None, time_kernels: bool = False) -> RunResult:
         lib = load()
         a = ALGOS[algo]
-        dtype = np.float32 if a == 3 else np.uint32
-        vals = out if out is not None else np.empty(max(self.n, 1), dtype=dtype)[: self.n]
+        dtype = np.float32 if a in FLOAT_ALGOS else np.uint32
+        if out is not None:
+            if out.dtype != dtype or not out.flags.c_contiguous or out.size < self.n:
+                raise ValueError(f"out must be a C-contiguous {np.dtype(dtype).name} array of n elements")
+            vals = out.reshape(-1)[: self.n]
+        else:
+            vals = np.empty(max(self.n, 1), dtype=dtype)[: self.n]
         it = ctypes.c_uint32(0)
         st = None
         iters_buf = trace_buf = None
@@ -320,11 +377,20 @@ class Graph:
                 res.mode_trace = trace_buf[: rows * npart].reshape(rows, npart).copy()
         return res
 
-    def run_batch(self, algo: str, sources, stats: bool = False, stream=None, time_kernels: bool = False):
-        """Batched BFS/SSSP from up to 64 sources in one traversal.  Returns
-        (values[nsources, n] uint32, iterations[nsources], stats dict)."""
+    def run_batch(self, algo: str, sources, stats: bool = False, stream=None, time_kernels: bool = False,
+                  out: np.ndarray | None = None):
+        """Batched BFS/SSSP/PPR from up to 64 sources in one traversal.  Returns
+        (values[nsources, n] uint32 (float32 for PPR), iterations[nsources], stats dict).
+        `out`, if given, is a C-contiguous array of that dtype with at least nsources*n
+        elements (e.g. from pinned_empty)."""
         srcs = np.ascontiguousarray(sources, dtype=np.uint32)
-        vals = np.empty((max(len(srcs), 1), max(self.n, 1)), dtype=np.uint32)[: len(srcs), : self.n]
+        dtype = np.float32 if ALGOS[algo] in FLOAT_ALGOS else np.uint32
+        if out is not None:
+            if out.dtype != dtype or not out.flags.c_contiguous or out.size < len(srcs) * self.n:
+                raise ValueError(f"out must be a C-contiguous {np.dtype(dtype).name} array of nsources*n elements")
+            vals = out.reshape(-1)[: len(srcs) * self.n].reshape(len(srcs), self.n)
+        else:
+            vals = np.empty((max(len(srcs), 1), max(self.n, 1)), dtype=dtype)[: len(srcs), : self.n]
         its = np.zeros(max(len(srcs), 1), dtype=np.uint32)
         st = None
         if stats or time_kernels:
@@ -348,3 +414,83 @@ class Graph:
         _check(load().hytm_select_engines(self._h, npart, *(_ptr(x) for x in arrs), int(nres), int(edge_arrays),
                                           _ptr(p)))
         return p[:npart]
+
+
+@dataclass
+class Query:
+    ticket: int
+    algo: str
+    source: int
+    values: np.ndarray
+    result: dict | None = None
+
+
+class Server:
+    """Query server over a Graph (hytm_server_*): BFS, SSSP and PPR queries join free lanes
+    of their algorithm's lane group between iterations and leave when their traversal
+    ends.  submit() returns a Query whose `values` array is filled once wait() returns."""
+
+    def __init__(self, graph: Graph, bfs: int = 64, sssp: int = 64, ppr: int = 64, state_budget: int = 0,
+                 max_pending: int = 0, pinned: bool = True):
+        cfg = ServerConfig()
+        cfg.struct_size = ctypes.sizeof(ServerConfig)
+        cfg.lanes[0], cfg.lanes[1], cfg.lanes[2] = int(bfs), int(sssp), int(ppr)
+        cfg.state_budget = int(state_budget)
+        cfg.max_pending = int(max_pending)
+        h = ctypes.c_void_p()
+        _check(load().hytm_server_open(graph._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.graph = graph
+        self.pinned = pinned
+        self._live = {}
+        graph._server = self
+
+    @staticmethod
+    def state_bytes(graph: Graph, algo: str, lanes: int) -> int:
+        b = ctypes.c_uint64(0)
+        _check(load().hytm_server_state_bytes(graph._h, ALGOS[algo], int(lanes), ctypes.byref(b)))
+        return int(b.value)
+
+    def submit(self, algo: str, source: int, out: np.ndarray | None = None) -> Query:
+        n = self.graph.n
+        dtype = np.float32 if ALGOS[algo] in FLOAT_ALGOS else np.uint32
+        if out is None:
+            out = pinned_empty(max(n, 1), dtype)[:n] if self.pinned else np.empty(max(n, 1), dtype)[:n]
+        elif out.dtype != dtype or not out.flags.c_contiguous or out.size < n:
+            raise ValueError(f"out must be a C-contiguous {np.dtype(dtype).name} array of n elements")
+        t = ctypes.c_uint64(0)
+        _check(load().hytm_server_submit(self._h, ALGOS[algo], int(source), _ptr(out), ctypes.byref(t)))
+        q = Query(int(t.value), algo, int(source), out.reshape(-1)[:n])
+        self._live[q.ticket] = q  # the buffer must outlive the query
+        return q
+
+    def wait(self, q: Query, timeout_ms: float = -1.0) -> Query:
+        r = QueryResult()
+        st = load().hytm_server_wait(self._h, q.ticket, float(timeout_ms), ctypes.byref(r))
+        if st == E_STATE and q.ticket in self._live and timeout_ms >= 0:
+            _check(st)  # timed out: the ticket stays live
+        self._live.pop(q.ticket, None)
+        q.result = {"status": r.status, "iterations": r.iterations, "queue_ms": r.queue_ms, "run_ms": r.run_ms,
+                    "total_ms": r.total_ms}
+        _check(st)
+        return q
+
+    def close(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            st = load().hytm_server_close(h)
+            self.graph._server = None
+            self._live.clear()
+            _check(st)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

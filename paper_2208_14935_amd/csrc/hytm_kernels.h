@@ -17,13 +17,20 @@ constexpr int NSEG = 4;
 constexpr int SEG_R = 0, SEG_F = 1, SEG_Z = 2, SEG_C = 3;
 
 // ALGO_MBFS / ALGO_MSSSP: up to 64 sources at once, one bit / value lane per source.
-enum Algo : int { ALGO_BFS = 0, ALGO_SSSP = 1, ALGO_CC = 2, ALGO_PR = 3, ALGO_MBFS = 4, ALGO_MSSSP = 5 };
+// ALGO_MPPR: personalized PageRank, one value lane per source.
+enum Algo : int { ALGO_BFS = 0, ALGO_SSSP = 1, ALGO_CC = 2, ALGO_PR = 3, ALGO_MBFS = 4, ALGO_MSSSP = 5, ALGO_MPPR = 6 };
 constexpr uint32_t MAX_LANES = 64;
 
 // Sources of a batched run, passed by value to the init kernel.
 struct LaneSources {
     uint32_t src[MAX_LANES];
     uint32_t count;
+};
+// A set of lanes with one source and one level base each (lane admission / extraction).
+struct LaneSet {
+    uint64_t mask;              // lanes taking part
+    uint32_t src[MAX_LANES];    // source vertex of each lane in mask
+    uint32_t base[MAX_LANES];   // BFS: iteration at which the lane joined (level offset)
 };
 
 // Zero-copy kernel line: 32 four-byte elements = 128 bytes.
@@ -68,11 +75,15 @@ struct AlgoState {
     const float* contrib; // PageRank x[u] / D_o(u)
     uint32_t level_next;  // BFS: level given to vertices discovered this iteration
     uint64_t n;           // vertices
-    // batched runs: per-vertex lane masks and per (vertex, lane) values in rows of 64
+    // batched runs: per-vertex lane masks and per (vertex, lane) values in rows of
+    // 2^lshift lanes (lshift <= 6)
     const uint64_t* mcur; // lanes active at each vertex this iteration
     uint64_t* mnext;      // lanes improved this iteration
     uint64_t* mvisited;   // BFS: lanes that have reached each vertex
-    uint32_t* lval;       // n x 64: level or distance of each lane
+    uint32_t* lval;       // BFS: level (plus the lane's join iteration); SSSP: distance
+    float* lx;            // PPR: x of each lane; scaled to x / D_o in place before a push
+    float* lacc;          // PPR: per-lane accumulators, zero between iterations
+    uint32_t lshift;
 };
 
 // PageRank keeps one accumulator copy per XCD; the apply step sums them.
@@ -91,8 +102,25 @@ hipError_t launch_init_lanes(const AlgoState& s, const LaneSources& src, uint32_
                              hipStream_t st);
 // OR of the lane masks of all vertices into *lanes (one uint64, zeroed by the caller).
 hipError_t launch_lane_union(const uint64_t* mask, uint64_t n, unsigned long long* lanes, hipStream_t st);
-// Copy lane `lane` of the n x 64 value rows into out[0..n).
-hipError_t launch_extract_lane(const uint32_t* lval, uint64_t n, uint32_t lane, uint32_t* out, hipStream_t st);
+// Rows k = 0.. of out (n values each) <- the lanes of `set` in increasing lane order,
+// from n rows of 2^lshift 32-bit values; with sub_base, a value other than UNREACHED has
+// the lane's base subtracted (BFS levels of lanes that joined late).
+hipError_t launch_extract_lanes(const uint32_t* vals, uint64_t n, uint32_t lshift, const LaneSet& set, bool sub_base,
+                                uint32_t* out, hipStream_t st);
+// Start the lanes of `set` at their sources (their columns must hold the reset values):
+// BFS level = base, SSSP distance = 0, PPR x = 1; lane bits at the source in mcur (and
+// mvisited), source bits in the union frontier `cur`.
+hipError_t launch_admit_lanes(const AlgoState& s, const LaneSet& set, uint32_t* cur, hipStream_t st);
+// Return the lanes in `mask` to the reset state: values UNREACHED (BFS/SSSP) or 0 (PPR x
+// and accumulators), their bits cleared from mcur, mnext, mvisited and the two
+// overflow words.
+hipError_t launch_reset_lanes(const AlgoState& s, uint64_t mask, hipStream_t st);
+// PPR step around the push: prepare scales each active (vertex, lane) x by 1 / D_o;
+// apply sets x = damping * acc for every lane in mcur | mnext and clears acc; restart
+// adds 1 - damping at each lane's source and marks it active for the next step.
+hipError_t launch_ppr_prepare(const AlgoState& s, const uint64_t* off, hipStream_t st);
+hipError_t launch_ppr_apply(const AlgoState& s, float damping, hipStream_t st);
+hipError_t launch_ppr_restart(const AlgoState& s, const LaneSet& set, float restart, hipStream_t st);
 
 hipError_t launch_scan(uint32_t npart, const uint8_t* mode, const uint32_t* nA, const uint32_t* nF,
                        const uint64_t* Ea, const uint64_t* Rq, const uint64_t* K, uint32_t* lbase, uint64_t* wbase,

@@ -319,6 +319,7 @@ __global__ __launch_bounds__(256) void k_build_lists(uint32_t npart, const uint3
 // already reflect updates made earlier in the same iteration, which only helps the
 // monotone operators).  push(value, v, w): relax edge (u, v) with weight w.
 struct OpBfs {
+    static constexpr bool wave = false;
     static constexpr bool weighted = false;
     uint32_t* visited;
     uint32_t* next;
@@ -338,6 +339,7 @@ struct OpBfs {
 };
 
 struct OpSssp {
+    static constexpr bool wave = false;
     static constexpr bool weighted = true;
     uint32_t* dist;
     uint32_t* next;
@@ -357,6 +359,7 @@ struct OpSssp {
 };
 
 struct OpCc {
+    static constexpr bool wave = false;
     static constexpr bool weighted = false;
     uint32_t* lab;
     uint32_t* next;
@@ -380,6 +383,7 @@ __device__ __forceinline__ uint32_t acc_copy() {
 }
 
 struct OpPr {
+    static constexpr bool wave = false;
     static constexpr bool weighted = false;
     float* acc;
     uint64_t stride;  // floats per accumulator copy
@@ -393,13 +397,15 @@ struct OpPr {
 // Batched BFS: lanes of u's mask that have not reached v yet reach it now (one 64-bit
 // atomicOr decides, per lane, which edge discovers v first).  The staged value is u.
 struct OpMBfs {
+    static constexpr bool wave = false;
     static constexpr bool weighted = false;
     const uint64_t* mcur;
     uint64_t* mnext;
     uint64_t* mvisited;
-    uint32_t* lvl;   // n x 64
+    uint32_t* lvl;   // n rows of 2^lshift lanes
     uint32_t* next;  // union of the next frontier
     uint32_t level_next;
+    uint32_t lshift;
     __device__ __forceinline__ uint32_t src(uint32_t u) const { return u; }
     __device__ __forceinline__ void push(uint32_t u, uint32_t v, uint32_t) const {
         const uint64_t want = mcur[u] & ~mvisited[v];
@@ -409,7 +415,7 @@ struct OpMBfs {
         if (!gained) return;
         atomicOr((unsigned long long*)(mnext + v), (unsigned long long)gained);
         atomicOr(next + (v >> 5), 1u << (v & 31));
-        uint32_t* row = lvl + (uint64_t)v * MAX_LANES;
+        uint32_t* row = lvl + ((uint64_t)v << lshift);
         while (gained) {
             row[__ffsll((unsigned long long)gained) - 1] = level_next;
             gained &= gained - 1;
@@ -419,23 +425,25 @@ struct OpMBfs {
 
 // Batched SSSP: every lane active at u relaxes (u, v) in its own distance row.
 struct OpMSssp {
+    static constexpr bool wave = false;
     static constexpr bool weighted = true;
     const uint64_t* mcur;
     uint64_t* mnext;
-    uint32_t* dist;  // n x 64
-    uint32_t* next;  // union of the next frontier
-    uint32_t* overflow;
+    uint32_t* dist;      // n rows of 2^lshift lanes
+    uint32_t* next;      // union of the next frontier
+    uint32_t* overflow;  // two words of lane bits: lanes whose distance would overflow
+    uint32_t lshift;
     __device__ __forceinline__ uint32_t src(uint32_t u) const { return u; }
     __device__ __forceinline__ void push(uint32_t u, uint32_t v, uint32_t w) const {
         uint64_t m = mcur[u], gained = 0;
-        const uint32_t* du = dist + (uint64_t)u * MAX_LANES;
-        uint32_t* dv = dist + (uint64_t)v * MAX_LANES;
+        const uint32_t* du = dist + ((uint64_t)u << lshift);
+        uint32_t* dv = dist + ((uint64_t)v << lshift);
         while (m) {
             const uint32_t l = __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
             const uint64_t nd = (uint64_t)du[l] + w;
             if (nd >= UNREACHED) {
-                *overflow = 1u;
+                atomicOr(overflow + (l >> 5), 1u << (l & 31));
                 continue;
             }
             if ((uint32_t)nd < dv[l]) {
@@ -449,6 +457,75 @@ struct OpMSssp {
         }
     }
 };
+
+// Batched personalized PageRank: every lane active at u adds its share x_u / D_o(u)
+// (prepared in place in u's row) into v's accumulator row.
+struct OpMPpr {
+    static constexpr bool wave = true;
+    static constexpr bool weighted = false;
+    const uint64_t* mcur;
+    uint64_t* mnext;
+    const float* share;  // n rows of 2^lshift lanes
+    float* acc;          // n rows of 2^lshift lanes
+    uint32_t* next;      // union of the next frontier
+    uint32_t lshift;
+    __device__ __forceinline__ uint32_t src(uint32_t u) const { return u; }
+    __device__ __forceinline__ void push(uint32_t u, uint32_t v, uint32_t) const {
+        const uint64_t m = mcur[u];
+        if (!m) return;
+        const float* su = share + ((uint64_t)u << lshift);
+        float* av = acc + ((uint64_t)v << lshift);
+        uint64_t b = m;
+        while (b) {
+            const uint32_t l = __ffsll((unsigned long long)b) - 1;
+            b &= b - 1;
+            unsafeAtomicAdd(av + l, su[l]);
+        }
+        mark(m, v);
+    }
+    __device__ __forceinline__ void mark(uint64_t m, uint32_t v) const {
+        if ((__builtin_nontemporal_load(mnext + v) & m) != m) atomicOr((unsigned long long*)(mnext + v), (unsigned long long)m);
+        const uint32_t bit = 1u << (v & 31);
+        if (!(__builtin_nontemporal_load(next + (v >> 5)) & bit)) atomicOr(next + (v >> 5), bit);
+    }
+    // The wave's edges (threads with ok) spread over the wave: each pass gives 64 >> lshift
+    // edges one thread per lane, so the adds of one edge are one instruction over a
+    // contiguous accumulator row instead of one instruction per lane.  Called by every
+    // thread of the wave.
+    __device__ __forceinline__ void push_wave(bool ok, uint32_t u, uint32_t v) const {
+        if (lshift < 3) {  // rows of 1..4 lanes: one thread per edge
+            if (ok) push(u, v, 0);
+            return;
+        }
+        const uint32_t me = __lane_id();
+        const uint32_t slot = me >> lshift, ln = me & ((1u << lshift) - 1);
+        const uint32_t per = 64u >> lshift;
+        uint64_t act = __ballot(ok);
+        while (act) {
+            uint64_t a = act;
+            for (uint32_t k = 0; k < slot; k++) a &= a - 1;
+            const int from = a ? (int)__ffsll((unsigned long long)a) - 1 : 0;
+            const uint32_t uu = __shfl(u, from, 64), vv = __shfl(v, from, 64);
+            if (a && ((mcur[uu] >> ln) & 1))
+                unsafeAtomicAdd(acc + ((uint64_t)vv << lshift) + ln, share[((uint64_t)uu << lshift) + ln]);
+            for (uint32_t k = 0; k < per && act; k++) act &= act - 1;
+        }
+        if (ok) {
+            const uint64_t m = mcur[u];
+            if (m) mark(m, v);
+        }
+    }
+};
+
+// push(val, v, w) where ok holds, called by every thread of the wave together: operators
+// with a wave form (Op::wave) share the work across the wave.
+template <class Op>
+__device__ __forceinline__ void push_if(const Op& op, bool ok, uint32_t val, uint32_t v, uint32_t w) {
+    if constexpr (Op::wave)
+        op.push_wave(ok, val, v);
+    else if (ok)
+        op.push(val, v, w);
+}
 
 // Largest j in [lo, hi) with pred(j) true, for a predicate that is true on a prefix of
 // [lo, hi) and true at lo.  The whole workgroup searches together: each round every
@@ -545,13 +622,18 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_push_edges(const uint32_t* __r
         }
         __syncthreads();
         block_prefix_max_u16(s_owner, cnt, s_wave);
-        for (uint32_t q = threadIdx.x; q < cnt; q += EDGE_THREADS) {
-            const uint32_t k = s_owner[q];
-            const uint64_t i = i0 + q;
-            const uint64_t e = s_st[k] + (i - s_pre[k]);
-            const uint32_t v = col[e];
-            const uint32_t wt = Op::weighted ? w[e] : 0u;
-            op.push(s_val[k], v, wt);
+        for (uint32_t q0 = 0; q0 < cnt; q0 += EDGE_THREADS) {  // whole waves stay together
+            const uint32_t q = q0 + threadIdx.x;
+            const bool ok = q < cnt;
+            uint32_t val = 0, v = 0, wt = 0;
+            if (ok) {
+                const uint32_t k = s_owner[q];
+                const uint64_t e = s_st[k] + (i0 + q - s_pre[k]);
+                v = col[e];
+                if (Op::weighted) wt = w[e];
+                val = s_val[k];
+            }
+            push_if(op, ok, val, v, wt);
         }
         __syncthreads();
     }
@@ -620,8 +702,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
             }
         }
 #pragma unroll
-        for (int r = 0; r < LINE_UNROLL; r++)
-            if (ok[r]) op.push(s_val[kk[r]], cv[r], wv[r]);
+        for (int r = 0; r < LINE_UNROLL; r++) push_if(op, ok[r], s_val[kk[r]], cv[r], wv[r]);
         __syncthreads();
     }
 }
@@ -657,10 +738,17 @@ __global__ void k_init(AlgoState s, uint64_t n, uint32_t source, float x0, float
 // each lane's bit at its source, the union frontier holding every source.
 __global__ void k_init_lanes(AlgoState s, LaneSources src, uint32_t* __restrict__ cur, uint32_t nwords) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t cells = s.n * MAX_LANES;
+    const uint64_t cells = s.n << s.lshift;
+    const uint32_t lmask = (1u << s.lshift) - 1;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cells; i += stride) {
-        const uint32_t v = (uint32_t)(i / MAX_LANES), l = (uint32_t)(i % MAX_LANES);
-        s.lval[i] = (l < src.count && src.src[l] == v) ? 0u : UNREACHED;
+        const uint32_t v = (uint32_t)(i >> s.lshift), l = (uint32_t)i & lmask;
+        const bool at_src = l < src.count && src.src[l] == v;
+        if (s.algo == ALGO_MPPR) {
+            s.lx[i] = at_src ? 1.0f : 0.0f;
+            s.lacc[i] = 0.0f;
+        } else {
+            s.lval[i] = at_src ? 0u : UNREACHED;
+        }
     }
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < s.n; v += stride) {
         uint64_t m = 0;
@@ -677,7 +765,7 @@ __global__ void k_init_lanes(AlgoState s, LaneSources src, uint32_t* __restrict_
         cur[wi] = c;
         s.next[wi] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && s.overflow) *s.overflow = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && s.overflow) s.overflow[0] = s.overflow[1] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_lane_union(const uint64_t* __restrict__ mask, uint64_t n,
@@ -690,10 +778,119 @@ __global__ __launch_bounds__(256) void k_lane_union(const uint64_t* __restrict__
     if ((threadIdx.x & 63) == 0 && m) atomicOr(lanes, (unsigned long long)m);
 }
 
-__global__ void k_extract_lane(const uint32_t* __restrict__ lval, uint64_t n, uint32_t lane,
-                               uint32_t* __restrict__ out) {
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
-        out[v] = lval[v * MAX_LANES + lane];
+// Lane extraction through LDS: a workgroup loads the rows of EX_V vertices with
+// coalesced reads (row pitch padded by one word against bank conflicts), then writes
+// each requested lane as a contiguous run of EX_V values.
+constexpr uint32_t EX_V = 64;
+__global__ __launch_bounds__(256) void k_extract_lanes(const uint32_t* __restrict__ vals, uint64_t n,
+                                                       uint32_t lshift, LaneSet set, uint32_t nsel, bool sub_base,
+                                                       uint32_t* __restrict__ out) {
+    __shared__ uint32_t tile[EX_V * (MAX_LANES + 1)];
+    __shared__ uint8_t s_lane[MAX_LANES];
+    __shared__ uint32_t s_base[MAX_LANES];
+    const uint32_t S = 1u << lshift, pitch = S + 1;
+    if (threadIdx.x < MAX_LANES) {
+        // k-th set lane of the mask, k = threadIdx.x
+        uint64_t m = set.mask;
+        for (uint32_t k = 0; k < threadIdx.x && m; k++) m &= m - 1;
+        if (m) {
+            const uint32_t l = __ffsll((unsigned long long)m) - 1;
+            s_lane[threadIdx.x] = (uint8_t)l;
+            s_base[threadIdx.x] = set.base[l];
+        }
+    }
+    for (uint64_t v0 = (uint64_t)blockIdx.x * EX_V; v0 < n; v0 += (uint64_t)gridDim.x * EX_V) {
+        const uint32_t nv = (uint32_t)(n - v0 < EX_V ? n - v0 : EX_V);
+        __syncthreads();
+        const uint32_t cells = nv << lshift;
+        const uint32_t* src = vals + (v0 << lshift);
+        for (uint32_t c = threadIdx.x; c < cells; c += blockDim.x) tile[(c >> lshift) * pitch + (c & (S - 1))] = src[c];
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < nsel * EX_V; q += blockDim.x) {
+            const uint32_t k = q / EX_V, i = q % EX_V;
+            if (i >= nv) continue;
+            uint32_t x = tile[i * pitch + s_lane[k]];
+            if (sub_base && x != UNREACHED) x -= s_base[k];
+            out[(uint64_t)k * n + v0 + i] = x;
+        }
+    }
+}
+
+__global__ void k_admit_lanes(AlgoState s, LaneSet set, uint32_t* __restrict__ cur) {
+    const uint32_t l = threadIdx.x;
+    if (l >= MAX_LANES || !((set.mask >> l) & 1)) return;
+    const uint32_t v = set.src[l];
+    const uint64_t cell = ((uint64_t)v << s.lshift) + l;
+    if (s.algo == ALGO_MPPR)
+        s.lx[cell] = 1.0f;
+    else
+        s.lval[cell] = s.algo == ALGO_MBFS ? set.base[l] : 0u;
+    atomicOr((unsigned long long*)(s.mcur + v), 1ull << l);
+    if (s.mvisited) atomicOr((unsigned long long*)(s.mvisited + v), 1ull << l);
+    atomicOr(cur + (v >> 5), 1u << (v & 31));
+}
+
+__global__ void k_reset_lanes(AlgoState s, uint64_t mask) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t lmask = (1u << s.lshift) - 1;
+    const uint64_t cells = s.n << s.lshift;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cells; i += stride) {
+        if (!((mask >> ((uint32_t)i & lmask)) & 1)) continue;
+        if (s.algo == ALGO_MPPR) {
+            s.lx[i] = 0.0f;
+            s.lacc[i] = 0.0f;
+        } else {
+            s.lval[i] = UNREACHED;
+        }
+    }
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < s.n; v += stride) {
+        ((uint64_t*)s.mcur)[v] &= ~mask;
+        s.mnext[v] &= ~mask;
+        if (s.mvisited) s.mvisited[v] &= ~mask;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && s.overflow) {
+        s.overflow[0] &= ~(uint32_t)mask;
+        s.overflow[1] &= ~(uint32_t)(mask >> 32);
+    }
+}
+
+__global__ void k_ppr_prepare(AlgoState s, const uint64_t* __restrict__ off) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < s.n; v += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t m = s.mcur[v];
+        const uint64_t d = off[v + 1] - off[v];
+        if (!m || !d) continue;
+        float* row = s.lx + (v << s.lshift);
+        const float fd = (float)d;
+        while (m) {
+            const uint32_t l = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            row[l] = row[l] / fd;
+        }
+    }
+}
+
+__global__ void k_ppr_apply(AlgoState s, float damping) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < s.n; v += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t m = s.mcur[v] | s.mnext[v];
+        if (!m) continue;
+        float* x = s.lx + (v << s.lshift);
+        float* a = s.lacc + (v << s.lshift);
+        while (m) {
+            const uint32_t l = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            x[l] = damping * a[l];
+            a[l] = 0.0f;
+        }
+    }
+}
+
+__global__ void k_ppr_restart(AlgoState s, LaneSet set, float restart) {
+    const uint32_t l = threadIdx.x;
+    if (l >= MAX_LANES || !((set.mask >> l) & 1)) return;
+    const uint32_t v = set.src[l];
+    s.lx[((uint64_t)v << s.lshift) + l] += restart;
+    atomicOr((unsigned long long*)(s.mnext + v), 1ull << l);
+    atomicOr(s.next + (v >> 5), 1u << (v & 31));
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t value) {
@@ -797,10 +994,15 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
 #pragma unroll
             for (int r = 0; r < UNROLL; r++) {
                 const uint64_t e = ((line0 + half + (uint64_t)LINE_HALVES * r) << ZC_LINE_SHIFT) + lane;
-                if (e < ce0 || e >= ce1) continue;
-                const uint32_t q = (uint32_t)(e - ce0);
-                const uint32_t k = s_owner[q];
-                if (q >= s_s[k] && q < s_e[k]) op.push(s_val[k], cv[r], wv[r]);
+                bool ok = false;
+                uint32_t val = 0;
+                if (e >= ce0 && e < ce1) {
+                    const uint32_t q = (uint32_t)(e - ce0);
+                    const uint32_t k = s_owner[q];
+                    ok = q >= s_s[k] && q < s_e[k];
+                    val = s_val[k];
+                }
+                push_if(op, ok, val, cv[r], wv[r]);
             }
         }
         __syncthreads();
@@ -855,7 +1057,7 @@ hipError_t launch_init(const AlgoState& s, uint64_t n, uint32_t source, float pr
 
 hipError_t launch_init_lanes(const AlgoState& s, const LaneSources& src, uint32_t* cur_union, uint32_t nwords,
                              hipStream_t st) {
-    k_init_lanes<<<grid_for(s.n * MAX_LANES, 256, 16384), 256, 0, st>>>(s, src, cur_union, nwords);
+    k_init_lanes<<<grid_for(s.n << s.lshift, 256, 16384), 256, 0, st>>>(s, src, cur_union, nwords);
     return hipGetLastError();
 }
 
@@ -864,8 +1066,41 @@ hipError_t launch_lane_union(const uint64_t* mask, uint64_t n, unsigned long lon
     return hipGetLastError();
 }
 
-hipError_t launch_extract_lane(const uint32_t* lval, uint64_t n, uint32_t lane, uint32_t* out, hipStream_t st) {
-    k_extract_lane<<<grid_for(n, 256, 8192), 256, 0, st>>>(lval, n, lane, out);
+hipError_t launch_extract_lanes(const uint32_t* vals, uint64_t n, uint32_t lshift, const LaneSet& set, bool sub_base,
+                                uint32_t* out, hipStream_t st) {
+    const uint32_t nsel = (uint32_t)__builtin_popcountll(set.mask);
+    if (!n || !nsel || lshift > 6 || (set.mask >> 1 >> ((1u << lshift) - 1))) return n && nsel ? hipErrorInvalidValue : hipSuccess;
+    k_extract_lanes<<<grid_for(n, EX_V, 16384), 256, 0, st>>>(vals, n, lshift, set, nsel, sub_base, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_admit_lanes(const AlgoState& s, const LaneSet& set, uint32_t* cur, hipStream_t st) {
+    if (!set.mask) return hipSuccess;
+    k_admit_lanes<<<1, MAX_LANES, 0, st>>>(s, set, cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_lanes(const AlgoState& s, uint64_t mask, hipStream_t st) {
+    if (!mask || !s.n) return hipSuccess;
+    k_reset_lanes<<<grid_for(s.n << s.lshift, 256, 16384), 256, 0, st>>>(s, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_ppr_prepare(const AlgoState& s, const uint64_t* off, hipStream_t st) {
+    if (!s.n) return hipSuccess;
+    k_ppr_prepare<<<grid_for(s.n, 256, 8192), 256, 0, st>>>(s, off);
+    return hipGetLastError();
+}
+
+hipError_t launch_ppr_apply(const AlgoState& s, float damping, hipStream_t st) {
+    if (!s.n) return hipSuccess;
+    k_ppr_apply<<<grid_for(s.n, 256, 8192), 256, 0, st>>>(s, damping);
+    return hipGetLastError();
+}
+
+hipError_t launch_ppr_restart(const AlgoState& s, const LaneSet& set, float restart, hipStream_t st) {
+    if (!set.mask) return hipSuccess;
+    k_ppr_restart<<<1, MAX_LANES, 0, st>>>(s, set, restart);
     return hipGetLastError();
 }
 
@@ -928,10 +1163,13 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
         return push_edges_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
                              compacted, st);
     case ALGO_MBFS:
-        return push_edges_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next}, list, wpre, ja, jb,
+        return push_edges_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next, s.lshift}, list, wpre, ja, jb,
                              item_lo, item_hi, off, col, w, shift, compacted, st);
     case ALGO_MSSSP:
-        return push_edges_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow}, list, wpre, ja, jb, item_lo,
+        return push_edges_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow, s.lshift}, list, wpre, ja, jb, item_lo,
+                             item_hi, off, col, w, shift, compacted, st);
+    case ALGO_MPPR:
+        return push_edges_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
                              item_hi, off, col, w, shift, compacted, st);
     default:
         return push_edges_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
@@ -962,10 +1200,13 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
     case ALGO_CC:
         return push_lines_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
     case ALGO_MBFS:
-        return push_lines_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next}, list, wpre, ja, jb,
+        return push_lines_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next, s.lshift}, list, wpre, ja, jb,
                              item_lo, item_hi, off, col, w, st);
     case ALGO_MSSSP:
-        return push_lines_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow}, list, wpre, ja, jb, item_lo,
+        return push_lines_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow, s.lshift}, list, wpre, ja, jb, item_lo,
+                             item_hi, off, col, w, st);
+    case ALGO_MPPR:
+        return push_lines_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
                              item_hi, off, col, w, st);
     default:
         return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
@@ -1001,10 +1242,13 @@ hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t 
     case ALGO_CC:
         return push_fstream_op(OpCc{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, st);
     case ALGO_MBFS:
-        return push_fstream_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next}, tasks, ntasks,
+        return push_fstream_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next, s.lshift}, tasks, ntasks,
                                total_chunks, list, off, col, w, st);
     case ALGO_MSSSP:
-        return push_fstream_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow}, tasks, ntasks, total_chunks,
+        return push_fstream_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow, s.lshift}, tasks, ntasks, total_chunks,
+                               list, off, col, w, st);
+    case ALGO_MPPR:
+        return push_fstream_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, tasks, ntasks, total_chunks,
                                list, off, col, w, st);
     default:
         return push_fstream_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, tasks, ntasks, total_chunks, list, off, col, w, st);

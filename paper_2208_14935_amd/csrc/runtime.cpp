@@ -21,6 +21,8 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <deque>
+#include <memory>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -29,6 +31,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "hytm.h"
@@ -200,6 +203,8 @@ struct hytm_graph {
     // batched runs (up to 64 lanes): lane masks, lane values, lanes active this iteration
     DevBuf<uint64_t> d_mcur, d_mnext, d_mvis, d_lanes;
     DevBuf<uint32_t> d_lval;
+    DevBuf<float> d_lx, d_lacc;   // batched PPR: x and accumulator rows
+    DevBuf<uint32_t> d_xout;      // lanes extracted for the copy back
     HostBuf<uint64_t> h_lanes;
 
     // host mirrors of the per-iteration selection
@@ -226,6 +231,7 @@ struct hytm_graph {
 
     Pool* pool = nullptr;
     KTimer timer;
+    hytm_server* server = nullptr;  // open query server (owns the graph while set)
 };
 
 namespace {
@@ -421,6 +427,9 @@ void release_all(hytm_graph* g) {
     g->h_tasks.release();
     for (auto* b : {&g->d_mcur, &g->d_mnext, &g->d_mvis, &g->d_lanes}) b->release();
     g->d_lval.release();
+    g->d_lx.release();
+    g->d_lacc.release();
+    g->d_xout.release();
     g->h_lanes.release();
     g->d_hdr.release();
     for (uint32_t i = 0; i < kMaxSlots; i++) {
@@ -477,14 +486,33 @@ void parallel_copy(void* dst, const void* src, size_t bytes) {
 }
 
 // ------------------------------------------------------------------- run
+// Totals of one traversal, summed over its iterations.
+struct Totals {
+    uint32_t iters = 0;
+    double select_ms = 0, fill_ms = 0;
+    uint64_t fill_bytes = 0;
+    uint64_t part_iters[5] = {0, 0, 0, 0, 0};
+    uint64_t av = 0, ae = 0, bf = 0, bc = 0, zcl = 0, d2h = 0, ftasks = 0, cchunks = 0;
+};
+
+// One traversal: a single-source or whole-graph run, or one group of lanes (a batched
+// run or a lane group of the query server).  The per-graph scratch it steps through
+// (lists, selection, staging) is shared; the frontier and value state is its own.
 struct RunCtx {
-    hytm_graph* g;
-    int algo;
-    uint32_t arrays;
+    hytm_graph* g = nullptr;
+    int algo = 0;         // hytm_algo
+    uint32_t arrays = 1;  // edge arrays read per edge (SSSP: neighbours and weights)
+    bool batched = false;
     Plan plan;
-    SelParams sp;
-    AlgoState as;
-    hytm_run_stats* stats;
+    SelParams sp{};
+    AlgoState as{};
+    hytm_run_stats* stats = nullptr;
+    uint32_t nwords = 0;
+    uint32_t *cur = nullptr, *nxt = nullptr;   // frontier bitmaps (union over lanes)
+    uint64_t *mcur = nullptr, *mnxt = nullptr; // lane masks
+    LaneSet ppr{};                             // PPR lanes stepping, restarted at their sources
+    uint32_t t = 0;                            // iterations taken
+    Totals tot;
 };
 
 // Gather list entries' edges for items [x0, x1) of the compaction segment into
@@ -560,59 +588,19 @@ void run_compaction(RunCtx* rc, uint32_t cs, uint32_t cc, uint64_t w0, uint64_t 
     *msg = g_err;  // the message is thread-local: hand it back to the calling thread
 }
 
-// One run.  lanes == 0: single source `sources[0]` (BFS/SSSP) or none (CC/PR), values_out
-// holds n values, iterations_out one count.  lanes in 1..64: batched BFS/SSSP from
-// sources[0..lanes), values_out holds lanes rows of n values, iterations_out one count per
-// lane (the non-empty frontiers of that lane).
-hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uint32_t lanes, void* values_out,
-                     uint32_t* iterations_out, hytm_run_stats* stats, void* hip_stream) {
-    HIP_CHECK(hipSetDevice(g->device));
-    ensure_streams(g);
-    const double t_begin = now_ms();
-    const uint32_t arrays = algo == HYTM_SSSP ? 2 : 1;
-    const bool batched = lanes > 0;
-    const uint32_t source = sources ? sources[0] : 0;
-    RunCtx rc{};
-    rc.g = g;
-    rc.algo = algo;
-    rc.arrays = arrays;
-    rc.stats = stats;
-    hytm_status ps = make_plan(g, arrays, &rc.plan);
+// Plan the edge budget for `plan_arrays` edge arrays and put the per-graph scratch, the
+// engines' buffers and the resident cache in place.
+hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main, Plan* plan, Totals* tot) {
+    hytm_status ps = make_plan(g, plan_arrays, plan);
     if (ps != HYTM_OK) return ps;
-    rc.sp = make_sel(g, arrays);
-    rc.sp.nres = rc.plan.nres;
-    rc.sp.allow_filter = rc.plan.allow_filter || g->budget == UINT64_MAX;
-    rc.sp.allow_compact = rc.plan.allow_compact || g->budget == UINT64_MAX;
-    hipStream_t main = hip_stream ? (hipStream_t)hip_stream : g->s_main;
-    KTimer& kt = g->timer;
-    kt.on = stats && stats->time_kernels;
-    kt.recs.clear();
-    kt.used = 0;
-
+    const Plan& pl = *plan;
     const uint64_t n = g->n;
-    const uint32_t nwords = (uint32_t)((n + 31) / 32);
     const uint32_t npart = g->npart;
-    // vertex-associated device state (outside the budget)
-    g->d_val.ensure(n);
-    g->d_cur.ensure(nwords);
-    g->d_next.ensure(nwords);
-    if (algo == HYTM_BFS) g->d_visited.ensure(nwords);
     g->d_list.ensure(n);
     g->d_wpre.ensure(n + 1);
-    g->d_overflow.ensure(1);
-    if (algo == HYTM_PAGERANK) {
-        g->d_x.ensure(n);
-        g->d_contrib.ensure(n);
-        g->d_acc.ensure(ACC_COPIES * acc_slots(n));
-    }
-    if (batched) {
-        g->d_mcur.ensure(n);
-        g->d_mnext.ensure(n);
-        if (algo == HYTM_BFS) g->d_mvis.ensure(n);
-        g->d_lval.ensure(n * MAX_LANES);
-        g->d_lanes.ensure(1);
-        g->h_lanes.ensure(1);
-    }
+    g->d_overflow.ensure(2);
+    g->d_lanes.ensure(1);
+    g->h_lanes.ensure(1);
     g->d_mode.ensure(npart);
     g->d_nA.ensure(npart);
     g->d_nF.ensure(npart);
@@ -628,12 +616,11 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     g->h_wbase.ensure(npart);
 
     // edge-budget buffers
-    const Plan& pl = rc.plan;
     const bool fstream = g->params.filter_engine == HYTM_FILTER_STREAM;
     if (pl.allow_filter && !fstream)
         for (uint32_t s = 0; s < pl.nslots; s++) {
             g->d_slot_col[s].ensure(pl.slot_edges);
-            if (arrays == 2) g->d_slot_w[s].ensure(pl.slot_edges);
+            if (plan_arrays == 2) g->d_slot_w[s].ensure(pl.slot_edges);
         }
     if (pl.allow_filter && fstream) {
         g->d_tasks.ensure(npart);
@@ -643,7 +630,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         for (int b = 0; b < 2; b++) {
             g->d_cbuf_col[b].ensure(pl.cchunk);
             g->h_cbuf_col[b].ensure(pl.cchunk);
-            if (arrays == 2) {
+            if (plan_arrays == 2) {
                 g->d_cbuf_w[b].ensure(pl.cchunk);
                 g->h_cbuf_w[b].ensure(pl.cchunk);
             }
@@ -656,278 +643,413 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
             g->pool = new Pool(t);
         }
     }
-    HIP_CHECK(hipEventRecord(g->ev_start, main));
 
     // resident cache: partitions [0, nres) copied once and kept while nres/arrays hold
-    double fill_ms = 0;
-    uint64_t fill_bytes = 0;
-    if (pl.nres > 0 && !(g->res_valid && g->res_parts == pl.nres && g->res_arrays >= arrays)) {
+    if (pl.nres > 0 && !(g->res_valid && g->res_parts == pl.nres && g->res_arrays >= plan_arrays)) {
         const double t0 = now_ms();
         g->d_res_col.ensure(pl.res_edges);
         HIP_CHECK(hipMemcpyAsync(g->d_res_col.p, g->h_col, pl.res_edges * 4, hipMemcpyHostToDevice, main));
-        fill_bytes += pl.res_edges * 4;
-        if (arrays == 2) {
+        tot->fill_bytes += pl.res_edges * 4;
+        if (plan_arrays == 2) {
             g->d_res_w.ensure(pl.res_edges);
             HIP_CHECK(hipMemcpyAsync(g->d_res_w.p, g->h_w, pl.res_edges * 4, hipMemcpyHostToDevice, main));
-            fill_bytes += pl.res_edges * 4;
+            tot->fill_bytes += pl.res_edges * 4;
         }
         HIP_CHECK(hipStreamSynchronize(main));
         g->res_parts = pl.nres;
         g->res_edges = pl.res_edges;
-        g->res_arrays = arrays;
+        g->res_arrays = plan_arrays;
         g->res_valid = true;
-        fill_ms = now_ms() - t0;
+        tot->fill_ms += now_ms() - t0;
+    }
+    return HYTM_OK;
+}
+
+// Engine choice inputs of a traversal under a plan made by prepare_graph.
+void init_ctx(RunCtx& rc, hytm_graph* g, int algo, bool batched, const Plan& pl, hytm_run_stats* stats) {
+    rc.g = g;
+    rc.algo = algo;
+    rc.arrays = algo == HYTM_SSSP ? 2 : 1;
+    rc.batched = batched;
+    rc.plan = pl;
+    rc.stats = stats;
+    rc.sp = make_sel(g, rc.arrays);
+    rc.sp.nres = pl.nres;
+    rc.sp.allow_filter = pl.allow_filter || g->budget == UINT64_MAX;
+    rc.sp.allow_compact = pl.allow_compact || g->budget == UINT64_MAX;
+    rc.nwords = (uint32_t)((g->n + 31) / 32);
+    rc.as.n = g->n;
+    rc.as.overflow = g->d_overflow.p;
+}
+
+// One iteration of a traversal (Algorithm 1 plus the engines of Sec. 6.2).  *lanes_out:
+// batched runs: the lanes with a non-empty frontier at the start of the iteration.
+// *empty_out: BFS/SSSP/CC only: the frontier was empty, nothing was pushed and the
+// traversal is over.
+hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* empty_out) {
+    hytm_graph* g = rc.g;
+    KTimer& kt = g->timer;
+    AlgoState& as = rc.as;
+    const uint64_t n = g->n;
+    const uint32_t npart = g->npart;
+    const Plan& pl = rc.plan;
+    const bool fstream = g->params.filter_engine == HYTM_FILTER_STREAM;
+    const uint64_t d1b = 4ull * rc.arrays;
+    const uint32_t t = rc.t;
+    const bool fixed_steps = rc.algo == HYTM_PAGERANK || rc.algo == HYTM_PPR;
+    const double t_it = now_ms();
+    if (rc.algo == HYTM_PAGERANK)
+        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
+            return launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, main);
+        }));
+    if (rc.algo == HYTM_PPR)
+        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_ppr_prepare(as, g->d_off.p, main); }));
+    // 1. statistics, engine selection, active lists (Algorithm 1, GPU part)
+    HIP_CHECK(kt.run(HYTM_K_STATS, npart, main, [&] {
+        return launch_stats_select(npart, g->d_pv.p, g->d_off.p, rc.cur, rc.sp, g->d_mode.p, g->d_nA.p, g->d_nF.p,
+                                   g->d_Ea.p, g->d_Rq.p, g->d_K.p, main);
+    }));
+    HIP_CHECK(kt.run(HYTM_K_SCAN, npart, main, [&] {
+        return launch_scan(npart, g->d_mode.p, g->d_nA.p, g->d_nF.p, g->d_Ea.p, g->d_Rq.p, g->d_K.p, g->d_lbase.p,
+                           g->d_wbase.p, g->d_hdr.p, g->d_wpre.p, main);
+    }));
+    HIP_CHECK(kt.run(HYTM_K_LISTS, npart, main, [&] {
+        return launch_build_lists(npart, g->d_pv.p, g->d_off.p, rc.cur, g->d_mode.p, g->d_lbase.p, g->d_wbase.p,
+                                  g->d_list.p, g->d_wpre.p, main);
+    }));
+    // 2. selection back to the host (Algorithm 1: copy Vc, p and A to host)
+    HIP_CHECK(hipMemcpyAsync(g->h_hdr.p, g->d_hdr.p, sizeof(Header), hipMemcpyDeviceToHost, main));
+    HIP_CHECK(hipMemcpyAsync(g->h_mode.p, g->d_mode.p, npart, hipMemcpyDeviceToHost, main));
+    HIP_CHECK(hipMemcpyAsync(g->h_lbase.p, g->d_lbase.p, npart * sizeof(uint32_t), hipMemcpyDeviceToHost, main));
+    HIP_CHECK(hipMemcpyAsync(g->h_wbase.p, g->d_wbase.p, npart * sizeof(uint64_t), hipMemcpyDeviceToHost, main));
+    if (rc.batched) {
+        // which lanes have a non-empty frontier this iteration
+        HIP_CHECK(launch_fill_u32((uint32_t*)g->d_lanes.p, 2, 0u, main));
+        HIP_CHECK(launch_lane_union(rc.mcur, n, (unsigned long long*)g->d_lanes.p, main));
+        HIP_CHECK(hipMemcpyAsync(g->h_lanes.p, g->d_lanes.p, sizeof(uint64_t), hipMemcpyDeviceToHost, main));
+    }
+    HIP_CHECK(hipStreamSynchronize(main));
+    Totals& tt = rc.tot;
+    tt.d2h += sizeof(Header) + npart * (1 + 4 + 8);
+    const Header h = *g->h_hdr.p;
+    tt.select_ms += now_ms() - t_it;
+    *lanes_out = rc.batched ? *g->h_lanes.p : 0;
+    *empty_out = false;
+    if (!fixed_steps && h.frontier == 0) {
+        *empty_out = true;
+        return HYTM_OK;
+    }
+    tt.iters++;
+
+    // per-iteration bookkeeping
+    hytm_iter_stats rec{};
+    rec.parts[0] = npart;
+    for (int s = 0; s < NSEG; s++) {
+        rec.parts[s + 1] = h.seg_parts[s];
+        rec.parts[0] -= h.seg_parts[s];
+    }
+    rec.active_vertices = h.total_active;
+    for (int s = 0; s < NSEG; s++) rec.active_edges += h.seg_edges[s];
+    hytm_run_stats* stats = rc.stats;
+    if (stats && stats->mode_trace && (uint64_t)(t + 1) * npart <= stats->mode_trace_cap)
+        memcpy(stats->mode_trace + (uint64_t)t * npart, g->h_mode.p, npart);
+
+    as.level_next = t + 1;
+    // resident partitions: no transfer
+    if (h.seg_list_count[SEG_R])
+        HIP_CHECK(kt.run(HYTM_K_PUSH_RES, h.seg_work_total[SEG_R], main, [&] {
+            return launch_push_edges(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_R],
+                                     h.seg_list_start[SEG_R] + h.seg_list_count[SEG_R], h.seg_work_start[SEG_R],
+                                     h.seg_work_start[SEG_R] + h.seg_work_total[SEG_R], g->d_off.p, g->d_res_col.p,
+                                     g->d_res_w.p, 0, false, main);
+        }));
+    // zero-copy: one kernel over all zero-copy vertices (Vz)
+    if (h.seg_list_count[SEG_Z]) {
+        HIP_CHECK(kt.run(HYTM_K_PUSH_ZC, h.seg_work_total[SEG_Z], g->s_zc, [&] {
+            return launch_push_lines(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_Z],
+                                     h.seg_list_start[SEG_Z] + h.seg_list_count[SEG_Z], h.seg_work_start[SEG_Z],
+                                     h.seg_work_start[SEG_Z] + h.seg_work_total[SEG_Z], g->d_off.p, g->d_col_map,
+                                     g->d_w_map, g->s_zc);
+        }));
+        rec.zc_lines = h.seg_work_total[SEG_Z];
+    }
+    // compaction: gathered by host threads, overlapping the filter tasks below
+    std::thread cthread;
+    hytm_status cst = HYTM_OK;
+    std::string cmsg;
+    uint64_t c_chunks = 0, c_bytes = 0, c_d2h = 0;
+    if (h.seg_list_count[SEG_C])
+        cthread = std::thread(run_compaction, &rc, h.seg_list_start[SEG_C], h.seg_list_count[SEG_C],
+                              h.seg_work_start[SEG_C], h.seg_work_start[SEG_C] + h.seg_work_total[SEG_C], &c_chunks,
+                              &c_bytes, &c_d2h, &cst, &cmsg);
+    // filter: combine runs of <= k consecutive partitions (Sec. 5.2), then copy+push
+    hytm_status fst = HYTM_OK;
+    try {
+        if (h.seg_list_count[SEG_F]) {
+            const uint32_t k = g->params.combine_k;
+            const uint64_t fend_list = h.seg_list_start[SEG_F] + h.seg_list_count[SEG_F];
+            const uint64_t fend_work = h.seg_work_start[SEG_F] + h.seg_work_total[SEG_F];
+            // the copy form keeps every task within one staging slot
+            const uint64_t cap = fstream ? UINT64_MAX : pl.slot_edges;
+            uint32_t gidx = 0;
+            uint32_t i = 0;
+            uint64_t chunks = 0;
+            while (i < npart) {
+                if (g->h_mode.p[i] != P_FILTER) {
+                    i++;
+                    continue;
+                }
+                // task = partitions [i, j): adjacent filter partitions, at most k
+                uint32_t j = i + 1;
+                uint64_t edges = g->pE[i];
+                while (j < npart && j - i < k && g->h_mode.p[j] == P_FILTER && edges + g->pE[j] <= cap) {
+                    edges += g->pE[j];
+                    j++;
+                }
+                // list / work range of the task: up to the next filter partition's start
+                uint32_t nx = j;
+                while (nx < npart && g->h_mode.p[nx] != P_FILTER) nx++;
+                const uint32_t ja = g->h_lbase.p[i];
+                const uint32_t jb = nx < npart ? g->h_lbase.p[nx] : (uint32_t)fend_list;
+                const uint64_t wa = g->h_wbase.p[i];
+                const uint64_t wb = nx < npart ? g->h_wbase.p[nx] : fend_work;
+                const uint64_t ebeg = g->h_off[g->pv[i]];
+                rec.bytes_filter += edges * d1b;
+                if (fstream) {
+                    FTask& ft = g->h_tasks.p[gidx++];
+                    ft.e0 = ebeg;
+                    ft.e1 = ebeg + edges;
+                    ft.ja = ja;
+                    ft.jb = jb;
+                    ft.chunk0 = chunks;
+                    chunks += fstream_chunks(ft.e0, ft.e1);
+                    i = j;
+                    continue;
+                }
+                const uint32_t s = gidx % pl.nslots;
+                if (gidx >= pl.nslots) HIP_CHECK(hipStreamWaitEvent(g->s_copy, g->ev_free[s], 0));
+                HIP_CHECK(hipMemcpyAsync(g->d_slot_col[s].p, g->h_col + ebeg, edges * 4, hipMemcpyHostToDevice,
+                                         g->s_copy));
+                if (rc.arrays == 2)
+                    HIP_CHECK(hipMemcpyAsync(g->d_slot_w[s].p, g->h_w + ebeg, edges * 4, hipMemcpyHostToDevice,
+                                             g->s_copy));
+                HIP_CHECK(hipEventRecord(g->ev_copied[s], g->s_copy));
+                HIP_CHECK(hipStreamWaitEvent(g->s_fk, g->ev_copied[s], 0));
+                HIP_CHECK(kt.run(HYTM_K_PUSH_F, wb - wa, g->s_fk, [&] {
+                    return launch_push_edges(as, g->d_list.p, g->d_wpre.p, ja, jb, wa, wb, g->d_off.p,
+                                             g->d_slot_col[s].p, g->d_slot_w[s].p, ebeg, false, g->s_fk);
+                }));
+                HIP_CHECK(hipEventRecord(g->ev_free[s], g->s_fk));
+                gidx++;
+                i = j;
+            }
+            if (fstream && gidx) {
+                // one launch streams every filter task of the iteration
+                HIP_CHECK(hipMemcpyAsync(g->d_tasks.p, g->h_tasks.p, gidx * sizeof(FTask), hipMemcpyHostToDevice,
+                                         g->s_fk));
+                HIP_CHECK(kt.run(HYTM_K_PUSH_F, rec.bytes_filter / d1b, g->s_fk, [&] {
+                    return launch_push_fstream(as, g->d_tasks.p, gidx, chunks, g->d_list.p, g->d_off.p,
+                                               g->d_col_map, g->d_w_map, g->s_fk);
+                }));
+            }
+            rec.filter_tasks = gidx;
+        }
+    } catch (const HipError& e) {
+        fst = e.status;
+    }
+    if (cthread.joinable()) cthread.join();
+    if (fst != HYTM_OK) return fst;
+    if (cst != HYTM_OK) {
+        g_err = cmsg;
+        return cst;
+    }
+    rec.bytes_compact = c_bytes;
+    tt.d2h += c_d2h;
+    tt.cchunks += c_chunks;
+    // 3. join every engine into the main stream
+    HIP_CHECK(hipEventRecord(g->ev_join[0], g->s_fk));
+    HIP_CHECK(hipEventRecord(g->ev_join[1], g->s_zc));
+    HIP_CHECK(hipEventRecord(g->ev_join[2], g->s_c));
+    for (int q = 0; q < 3; q++) HIP_CHECK(hipStreamWaitEvent(main, g->ev_join[q], 0));
+    if (rc.algo == HYTM_PAGERANK) {
+        const float base = (float)((1.0 - g->params.pr_damping) / (double)n);
+        const float d = (float)g->params.pr_damping;
+        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
+                         [&] { return launch_pr_apply(n, g->d_x.p, g->d_acc.p, base, d, main); }));
+    } else {
+        if (rc.algo == HYTM_PPR) {
+            const float d = (float)g->params.pr_damping;
+            const float restart = (float)(1.0 - g->params.pr_damping);
+            HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_ppr_apply(as, d, main); }));
+            HIP_CHECK(kt.run(HYTM_K_OTHER, 1, main, [&] { return launch_ppr_restart(as, rc.ppr, restart, main); }));
+        }
+        std::swap(rc.cur, rc.nxt);
+        as.next = rc.nxt;
+        HIP_CHECK(kt.run(HYTM_K_OTHER, rc.nwords, main, [&] { return launch_fill_u32(rc.nxt, rc.nwords, 0u, main); }));
+        if (rc.batched) {
+            std::swap(rc.mcur, rc.mnxt);
+            as.mcur = rc.mcur;
+            as.mnext = rc.mnxt;
+            HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
+                             [&] { return launch_fill_u32((uint32_t*)rc.mnxt, 2 * n, 0u, main); }));
+        }
+    }
+    for (int s = 0; s < 5; s++) tt.part_iters[s] += rec.parts[s];
+    tt.av += rec.active_vertices;
+    tt.ae += rec.active_edges;
+    tt.bf += rec.bytes_filter;
+    tt.bc += rec.bytes_compact;
+    tt.zcl += rec.zc_lines;
+    tt.ftasks += rec.filter_tasks;
+    rec.ms = now_ms() - t_it;
+    if (stats && stats->iters && t < stats->iters_cap) {
+        stats->iters[t] = rec;
+        stats->iters_written = t + 1;
+    }
+    rc.t++;
+    return HYTM_OK;
+}
+
+// Lane rows of a batched traversal: the power of two >= lanes.
+uint32_t lane_shift(uint32_t lanes) {
+    uint32_t sh = 0;
+    while ((1u << sh) < lanes) sh++;
+    return sh;
+}
+
+// Copy the lanes of `set` (values of n vertices each, in rows of 2^lshift) into
+// consecutive n-value rows of the host buffer `out`, EXTRACT_LANES lanes per device pass.
+constexpr uint32_t EXTRACT_LANES = 8;
+void copy_lanes_out(hytm_graph* g, const uint32_t* vals, uint32_t lshift, const LaneSet& set, bool sub_base,
+                    void* const* outs, hipStream_t main) {
+    const uint64_t n = g->n;
+    g->d_xout.ensure(n * EXTRACT_LANES);
+    uint64_t rest = set.mask;
+    uint32_t k = 0;
+    while (rest) {
+        LaneSet part = set;
+        part.mask = 0;
+        for (uint32_t c = 0; c < EXTRACT_LANES && rest; c++) {
+            part.mask |= rest & (~rest + 1);
+            rest &= rest - 1;
+        }
+        HIP_CHECK(launch_extract_lanes(vals, n, lshift, part, sub_base, g->d_xout.p, main));
+        const uint32_t cnt = (uint32_t)__builtin_popcountll(part.mask);
+        for (uint32_t c = 0; c < cnt; c++)
+            HIP_CHECK(hipMemcpyAsync(outs[k + c], g->d_xout.p + (uint64_t)c * n, n * 4, hipMemcpyDeviceToHost, main));
+        // the staging rows are reused by the next pass
+        HIP_CHECK(hipStreamSynchronize(main));
+        k += cnt;
+    }
+}
+
+// One run.  lanes == 0: single source `sources[0]` (BFS/SSSP) or none (CC/PR), values_out
+// holds n values, iterations_out one count.  lanes in 1..64: batched BFS/SSSP/PPR from
+// sources[0..lanes), values_out holds lanes rows of n values, iterations_out one count per
+// lane (the non-empty frontiers of that lane; PPR: its steps).
+hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uint32_t lanes, void* values_out,
+                     uint32_t* iterations_out, hytm_run_stats* stats, void* hip_stream) {
+    HIP_CHECK(hipSetDevice(g->device));
+    ensure_streams(g);
+    const double t_begin = now_ms();
+    const uint32_t arrays = algo == HYTM_SSSP ? 2 : 1;
+    const bool batched = lanes > 0;
+    const uint32_t source = sources ? sources[0] : 0;
+    hipStream_t main = hip_stream ? (hipStream_t)hip_stream : g->s_main;
+    KTimer& kt = g->timer;
+    kt.on = stats && stats->time_kernels;
+    kt.recs.clear();
+    kt.used = 0;
+
+    RunCtx rc;
+    Plan pl;
+    hytm_status ps = prepare_graph(g, arrays, main, &pl, &rc.tot);
+    if (ps != HYTM_OK) return ps;
+    HIP_CHECK(hipEventRecord(g->ev_start, main));
+    init_ctx(rc, g, algo, batched, pl, stats);
+
+    const uint64_t n = g->n;
+    const uint32_t nwords = rc.nwords;
+    const uint32_t lsh = batched ? lane_shift(lanes) : 0;
+    // vertex-associated device state (outside the budget)
+    g->d_cur.ensure(nwords);
+    g->d_next.ensure(nwords);
+    if (!batched) g->d_val.ensure(n);
+    if (algo == HYTM_BFS && !batched) g->d_visited.ensure(nwords);
+    if (algo == HYTM_PAGERANK) {
+        g->d_x.ensure(n);
+        g->d_contrib.ensure(n);
+        g->d_acc.ensure(ACC_COPIES * acc_slots(n));
+    }
+    if (batched) {
+        g->d_mcur.ensure(n);
+        g->d_mnext.ensure(n);
+        if (algo == HYTM_BFS) g->d_mvis.ensure(n);
+        if (algo == HYTM_PPR) {
+            g->d_lx.ensure(n << lsh);
+            g->d_lacc.ensure(n << lsh);
+        } else {
+            g->d_lval.ensure(n << lsh);
+        }
     }
 
     AlgoState& as = rc.as;
-    as.algo = batched ? (algo == HYTM_BFS ? ALGO_MBFS : ALGO_MSSSP) : (int)algo;
+    as.algo = batched ? (algo == HYTM_BFS ? ALGO_MBFS : algo == HYTM_SSSP ? ALGO_MSSSP : ALGO_MPPR) : (int)algo;
     as.val = g->d_val.p;
     as.visited = (algo == HYTM_BFS && !batched) ? g->d_visited.p : nullptr;
     as.next = algo == HYTM_PAGERANK ? nullptr : g->d_next.p;
-    as.overflow = g->d_overflow.p;
     as.acc = g->d_acc.p;
     as.contrib = g->d_contrib.p;
-    as.n = n;
-    uint64_t* mcur = batched ? g->d_mcur.p : nullptr;
-    uint64_t* mnxt = batched ? g->d_mnext.p : nullptr;
-    as.mcur = mcur;
-    as.mnext = mnxt;
-    as.mvisited = (batched && algo == HYTM_BFS) ? g->d_mvis.p : nullptr;
-    as.lval = batched ? g->d_lval.p : nullptr;
-    const float x0 = n ? (float)(1.0 / (double)n) : 0.f;
+    rc.cur = g->d_cur.p;
+    rc.nxt = g->d_next.p;
     if (batched) {
+        rc.mcur = g->d_mcur.p;
+        rc.mnxt = g->d_mnext.p;
+        as.mcur = rc.mcur;
+        as.mnext = rc.mnxt;
+        as.mvisited = algo == HYTM_BFS ? g->d_mvis.p : nullptr;
+        as.lval = algo == HYTM_PPR ? nullptr : g->d_lval.p;
+        as.lx = algo == HYTM_PPR ? g->d_lx.p : nullptr;
+        as.lacc = algo == HYTM_PPR ? g->d_lacc.p : nullptr;
+        as.lshift = lsh;
         LaneSources ls{};
         ls.count = lanes;
         for (uint32_t l = 0; l < lanes; l++) ls.src[l] = sources[l];
-        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_init_lanes(as, ls, g->d_cur.p, nwords, main); }));
+        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_init_lanes(as, ls, rc.cur, nwords, main); }));
+        rc.ppr.mask = lanes == 64 ? ~0ull : (1ull << lanes) - 1;
+        for (uint32_t l = 0; l < lanes; l++) rc.ppr.src[l] = sources[l];
     } else {
+        const float x0 = n ? (float)(1.0 / (double)n) : 0.f;
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
-                         [&] { return launch_init(as, n, source, x0, g->d_x.p, g->d_cur.p, nwords, main); }));
+                         [&] { return launch_init(as, n, source, x0, g->d_x.p, rc.cur, nwords, main); }));
     }
-    uint32_t* cur = g->d_cur.p;
-    uint32_t* nxt = g->d_next.p;
     uint32_t lane_iters[MAX_LANES] = {};
-
-    const float pr_base = (float)((1.0 - g->params.pr_damping) / (double)n);
-    const float pr_d = (float)g->params.pr_damping;
-    const uint32_t T = g->params.pr_iterations;
-
-    uint32_t iters = 0;
-    double select_ms = 0;
-    uint64_t part_iters[5] = {0, 0, 0, 0, 0};
-    uint64_t tot_av = 0, tot_ae = 0, b_f = 0, b_c = 0, zcl = 0, d2h = 0, ftasks = 0, cchunks = 0;
-    const uint64_t d1b = 4ull * arrays;
-
-    for (uint32_t t = 0;; t++) {
-        if (algo == HYTM_PAGERANK && t >= T) break;
-        const double t_it = now_ms();
-        if (algo == HYTM_PAGERANK)
-            HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
-                return launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, main);
-            }));
-        // 1. statistics, engine selection, active lists (Algorithm 1, GPU part)
-        HIP_CHECK(kt.run(HYTM_K_STATS, npart, main, [&] {
-            return launch_stats_select(npart, g->d_pv.p, g->d_off.p, cur, rc.sp, g->d_mode.p, g->d_nA.p, g->d_nF.p,
-                                       g->d_Ea.p, g->d_Rq.p, g->d_K.p, main);
-        }));
-        HIP_CHECK(kt.run(HYTM_K_SCAN, npart, main, [&] {
-            return launch_scan(npart, g->d_mode.p, g->d_nA.p, g->d_nF.p, g->d_Ea.p, g->d_Rq.p, g->d_K.p,
-                               g->d_lbase.p, g->d_wbase.p, g->d_hdr.p, g->d_wpre.p, main);
-        }));
-        HIP_CHECK(kt.run(HYTM_K_LISTS, npart, main, [&] {
-            return launch_build_lists(npart, g->d_pv.p, g->d_off.p, cur, g->d_mode.p, g->d_lbase.p, g->d_wbase.p,
-                                      g->d_list.p, g->d_wpre.p, main);
-        }));
-        // 2. selection back to the host (Algorithm 1: copy Vc, p and A to host)
-        HIP_CHECK(hipMemcpyAsync(g->h_hdr.p, g->d_hdr.p, sizeof(Header), hipMemcpyDeviceToHost, main));
-        HIP_CHECK(hipMemcpyAsync(g->h_mode.p, g->d_mode.p, npart, hipMemcpyDeviceToHost, main));
-        HIP_CHECK(hipMemcpyAsync(g->h_lbase.p, g->d_lbase.p, npart * sizeof(uint32_t), hipMemcpyDeviceToHost, main));
-        HIP_CHECK(hipMemcpyAsync(g->h_wbase.p, g->d_wbase.p, npart * sizeof(uint64_t), hipMemcpyDeviceToHost, main));
-        if (batched) {
-            // which lanes have a non-empty frontier this iteration
-            HIP_CHECK(launch_fill_u32((uint32_t*)g->d_lanes.p, 2, 0u, main));
-            HIP_CHECK(launch_lane_union(mcur, n, (unsigned long long*)g->d_lanes.p, main));
-            HIP_CHECK(hipMemcpyAsync(g->h_lanes.p, g->d_lanes.p, sizeof(uint64_t), hipMemcpyDeviceToHost, main));
-        }
-        HIP_CHECK(hipStreamSynchronize(main));
-        d2h += sizeof(Header) + npart * (1 + 4 + 8);
-        const Header h = *g->h_hdr.p;
-        select_ms += now_ms() - t_it;
-        if (algo != HYTM_PAGERANK && h.frontier == 0) break;
-        iters++;
-        if (batched)
-            for (uint32_t l = 0; l < lanes; l++) lane_iters[l] += (uint32_t)((*g->h_lanes.p >> l) & 1);
-
-        // per-iteration bookkeeping
-        hytm_iter_stats rec{};
-        rec.parts[0] = npart;
-        for (int s = 0; s < NSEG; s++) {
-            rec.parts[s + 1] = h.seg_parts[s];
-            rec.parts[0] -= h.seg_parts[s];
-        }
-        rec.active_vertices = h.total_active;
-        for (int s = 0; s < NSEG; s++) rec.active_edges += h.seg_edges[s];
-        if (stats && stats->mode_trace && (uint64_t)(t + 1) * npart <= stats->mode_trace_cap)
-            memcpy(stats->mode_trace + (uint64_t)t * npart, g->h_mode.p, npart);
-
-        as.level_next = t + 1;
-        // resident partitions: no transfer
-        if (h.seg_list_count[SEG_R])
-            HIP_CHECK(kt.run(HYTM_K_PUSH_RES, h.seg_work_total[SEG_R], main, [&] {
-                return launch_push_edges(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_R],
-                                         h.seg_list_start[SEG_R] + h.seg_list_count[SEG_R], h.seg_work_start[SEG_R],
-                                         h.seg_work_start[SEG_R] + h.seg_work_total[SEG_R], g->d_off.p,
-                                         g->d_res_col.p, g->d_res_w.p, 0, false, main);
-            }));
-        // zero-copy: one kernel over all zero-copy vertices (Vz)
-        if (h.seg_list_count[SEG_Z]) {
-            HIP_CHECK(kt.run(HYTM_K_PUSH_ZC, h.seg_work_total[SEG_Z], g->s_zc, [&] {
-                return launch_push_lines(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_Z],
-                                         h.seg_list_start[SEG_Z] + h.seg_list_count[SEG_Z], h.seg_work_start[SEG_Z],
-                                         h.seg_work_start[SEG_Z] + h.seg_work_total[SEG_Z], g->d_off.p,
-                                         g->d_col_map, g->d_w_map, g->s_zc);
-            }));
-            rec.zc_lines = h.seg_work_total[SEG_Z];
-        }
-        // compaction: gathered by host threads, overlapping the filter tasks below
-        std::thread cthread;
-        hytm_status cst = HYTM_OK;
-        std::string cmsg;
-        uint64_t c_chunks = 0, c_bytes = 0, c_d2h = 0;
-        if (h.seg_list_count[SEG_C])
-            cthread = std::thread(run_compaction, &rc, h.seg_list_start[SEG_C], h.seg_list_count[SEG_C],
-                                  h.seg_work_start[SEG_C], h.seg_work_start[SEG_C] + h.seg_work_total[SEG_C],
-                                  &c_chunks, &c_bytes, &c_d2h, &cst, &cmsg);
-        // filter: combine runs of <= k consecutive partitions (Sec. 5.2), then copy+push
-        hytm_status fst = HYTM_OK;
-        try {
-            if (h.seg_list_count[SEG_F]) {
-                const uint32_t k = g->params.combine_k;
-                const uint64_t fend_list = h.seg_list_start[SEG_F] + h.seg_list_count[SEG_F];
-                const uint64_t fend_work = h.seg_work_start[SEG_F] + h.seg_work_total[SEG_F];
-                // the copy form keeps every task within one staging slot
-                const uint64_t cap = fstream ? UINT64_MAX : pl.slot_edges;
-                uint32_t gidx = 0;
-                uint32_t i = 0;
-                uint64_t chunks = 0;
-                while (i < npart) {
-                    if (g->h_mode.p[i] != P_FILTER) {
-                        i++;
-                        continue;
-                    }
-                    // task = partitions [i, j): adjacent filter partitions, at most k
-                    uint32_t j = i + 1;
-                    uint64_t edges = g->pE[i];
-                    while (j < npart && j - i < k && g->h_mode.p[j] == P_FILTER && edges + g->pE[j] <= cap) {
-                        edges += g->pE[j];
-                        j++;
-                    }
-                    // list / work range of the task: up to the next filter partition's start
-                    uint32_t nx = j;
-                    while (nx < npart && g->h_mode.p[nx] != P_FILTER) nx++;
-                    const uint32_t ja = g->h_lbase.p[i];
-                    const uint32_t jb = nx < npart ? g->h_lbase.p[nx] : (uint32_t)fend_list;
-                    const uint64_t wa = g->h_wbase.p[i];
-                    const uint64_t wb = nx < npart ? g->h_wbase.p[nx] : fend_work;
-                    const uint64_t ebeg = g->h_off[g->pv[i]];
-                    rec.bytes_filter += edges * d1b;
-                    if (fstream) {
-                        FTask& ft = g->h_tasks.p[gidx++];
-                        ft.e0 = ebeg;
-                        ft.e1 = ebeg + edges;
-                        ft.ja = ja;
-                        ft.jb = jb;
-                        ft.chunk0 = chunks;
-                        chunks += fstream_chunks(ft.e0, ft.e1);
-                        i = j;
-                        continue;
-                    }
-                    const uint32_t s = gidx % pl.nslots;
-                    if (gidx >= pl.nslots) HIP_CHECK(hipStreamWaitEvent(g->s_copy, g->ev_free[s], 0));
-                    HIP_CHECK(hipMemcpyAsync(g->d_slot_col[s].p, g->h_col + ebeg, edges * 4, hipMemcpyHostToDevice,
-                                             g->s_copy));
-                    if (arrays == 2)
-                        HIP_CHECK(hipMemcpyAsync(g->d_slot_w[s].p, g->h_w + ebeg, edges * 4, hipMemcpyHostToDevice,
-                                                 g->s_copy));
-                    HIP_CHECK(hipEventRecord(g->ev_copied[s], g->s_copy));
-                    HIP_CHECK(hipStreamWaitEvent(g->s_fk, g->ev_copied[s], 0));
-                    HIP_CHECK(kt.run(HYTM_K_PUSH_F, wb - wa, g->s_fk, [&] {
-                        return launch_push_edges(as, g->d_list.p, g->d_wpre.p, ja, jb, wa, wb, g->d_off.p,
-                                                 g->d_slot_col[s].p, g->d_slot_w[s].p, ebeg, false, g->s_fk);
-                    }));
-                    HIP_CHECK(hipEventRecord(g->ev_free[s], g->s_fk));
-                    gidx++;
-                    i = j;
-                }
-                if (fstream && gidx) {
-                    // one launch streams every filter task of the iteration
-                    HIP_CHECK(hipMemcpyAsync(g->d_tasks.p, g->h_tasks.p, gidx * sizeof(FTask), hipMemcpyHostToDevice,
-                                             g->s_fk));
-                    HIP_CHECK(kt.run(HYTM_K_PUSH_F, rec.bytes_filter / d1b, g->s_fk, [&] {
-                        return launch_push_fstream(as, g->d_tasks.p, gidx, chunks, g->d_list.p, g->d_off.p,
-                                                   g->d_col_map, g->d_w_map, g->s_fk);
-                    }));
-                }
-                rec.filter_tasks = gidx;
-            }
-        } catch (const HipError& e) {
-            fst = e.status;
-        }
-        if (cthread.joinable()) cthread.join();
-        if (fst != HYTM_OK) return fst;
-        if (cst != HYTM_OK) {
-            g_err = cmsg;
-            return cst;
-        }
-        rec.bytes_compact = c_bytes;
-        d2h += c_d2h;
-        cchunks += c_chunks;
-        // 3. join every engine into the main stream
-        HIP_CHECK(hipEventRecord(g->ev_join[0], g->s_fk));
-        HIP_CHECK(hipEventRecord(g->ev_join[1], g->s_zc));
-        HIP_CHECK(hipEventRecord(g->ev_join[2], g->s_c));
-        for (int q = 0; q < 3; q++) HIP_CHECK(hipStreamWaitEvent(main, g->ev_join[q], 0));
-        if (algo == HYTM_PAGERANK) {
-            HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
-                             [&] { return launch_pr_apply(n, g->d_x.p, g->d_acc.p, pr_base, pr_d, main); }));
-        } else {
-            std::swap(cur, nxt);
-            as.next = nxt;
-            HIP_CHECK(kt.run(HYTM_K_OTHER, nwords, main, [&] { return launch_fill_u32(nxt, nwords, 0u, main); }));
-            if (batched) {
-                std::swap(mcur, mnxt);
-                as.mcur = mcur;
-                as.mnext = mnxt;
-                HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
-                                 [&] { return launch_fill_u32((uint32_t*)mnxt, 2 * n, 0u, main); }));
-            }
-        }
-        for (int s = 0; s < 5; s++) part_iters[s] += rec.parts[s];
-        tot_av += rec.active_vertices;
-        tot_ae += rec.active_edges;
-        b_f += rec.bytes_filter;
-        b_c += rec.bytes_compact;
-        zcl += rec.zc_lines;
-        ftasks += rec.filter_tasks;
-        rec.ms = now_ms() - t_it;
-        if (stats && stats->iters && t < stats->iters_cap) {
-            stats->iters[t] = rec;
-            stats->iters_written = t + 1;
-        }
+    const uint32_t T = algo == HYTM_PAGERANK ? g->params.pr_iterations
+                       : algo == HYTM_PPR    ? g->params.ppr_iterations
+                                             : UINT32_MAX;
+    while (rc.t < T) {
+        uint64_t active = 0;
+        bool empty = false;
+        hytm_status st = step_once(rc, main, &active, &empty);
+        if (st != HYTM_OK) return st;
+        if (empty) break;
+        for (uint32_t l = 0; l < lanes; l++) lane_iters[l] += (uint32_t)((active >> l) & 1);
     }
     HIP_CHECK(hipStreamSynchronize(main));
     if (algo == HYTM_SSSP) {
-        uint32_t of = 0;
-        HIP_CHECK(hipMemcpy(&of, g->d_overflow.p, sizeof(of), hipMemcpyDeviceToHost));
-        if (of) return fail(HYTM_E_RANGE, "an SSSP distance reaches 2^32-1 and does not fit in uint32");
+        uint32_t of[2] = {0, 0};
+        HIP_CHECK(hipMemcpy(of, g->d_overflow.p, sizeof(of), hipMemcpyDeviceToHost));
+        if (of[0] | (batched ? of[1] : 0u))
+            return fail(HYTM_E_RANGE, "an SSSP distance reaches 2^32-1 and does not fit in uint32");
     }
     if (batched) {
         // lane l of the value rows -> row l of the caller's buffer
-        for (uint32_t l = 0; l < lanes; l++) {
-            HIP_CHECK(launch_extract_lane(g->d_lval.p, n, l, g->d_val.p, main));
-            HIP_CHECK(hipMemcpyAsync((uint32_t*)values_out + (uint64_t)l * n, g->d_val.p, n * 4,
-                                     hipMemcpyDeviceToHost, main));
-        }
+        LaneSet all{};
+        all.mask = rc.ppr.mask;
+        std::vector<void*> outs(lanes);
+        for (uint32_t l = 0; l < lanes; l++) outs[l] = (uint32_t*)values_out + (uint64_t)l * n;
+        const uint32_t* vals = algo == HYTM_PPR ? (const uint32_t*)g->d_lx.p : g->d_lval.p;
+        copy_lanes_out(g, vals, lsh, all, false, outs.data(), main);
     } else {
         const void* src = algo == HYTM_PAGERANK ? (const void*)g->d_x.p : (const void*)g->d_val.p;
         HIP_CHECK(hipMemcpyAsync(values_out, src, n * 4, hipMemcpyDeviceToHost, main));
@@ -938,7 +1060,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         if (batched)
             for (uint32_t l = 0; l < lanes; l++) iterations_out[l] = lane_iters[l];
         else
-            *iterations_out = iters;
+            *iterations_out = rc.tot.iters;
     }
     if (stats) {
         if (kt.on) {
@@ -951,23 +1073,24 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
             kt.collect(stats->kernel_ms, stats->kernel_launches, stats->kernel_items);
             kt.on = false;
         }
-        stats->iterations = iters;
-        stats->npart = npart;
+        const Totals& tt = rc.tot;
+        stats->iterations = tt.iters;
+        stats->npart = g->npart;
         stats->nres = pl.nres;
-        for (int s = 0; s < 5; s++) stats->part_iters[s] = part_iters[s];
-        stats->active_vertices = tot_av;
-        stats->active_edges = tot_ae;
-        stats->bytes_filter = b_f;
-        stats->bytes_compact = b_c;
-        stats->zc_lines = zcl;
-        stats->bytes_zerocopy = zcl * 128 * arrays;
-        stats->bytes_d2h = d2h;
-        stats->bytes_resident_fill = fill_bytes;
-        stats->filter_tasks = ftasks;
-        stats->compact_chunks = cchunks;
+        for (int s = 0; s < 5; s++) stats->part_iters[s] = tt.part_iters[s];
+        stats->active_vertices = tt.av;
+        stats->active_edges = tt.ae;
+        stats->bytes_filter = tt.bf;
+        stats->bytes_compact = tt.bc;
+        stats->zc_lines = tt.zcl;
+        stats->bytes_zerocopy = tt.zcl * 128 * arrays;
+        stats->bytes_d2h = tt.d2h;
+        stats->bytes_resident_fill = tt.fill_bytes;
+        stats->filter_tasks = tt.ftasks;
+        stats->compact_chunks = tt.cchunks;
         stats->ms_total = t_end - t_begin;
-        stats->ms_fill = fill_ms;
-        stats->ms_select = select_ms;
+        stats->ms_fill = tt.fill_ms;
+        stats->ms_select = tt.select_ms;
     }
     return HYTM_OK;
 }
@@ -981,6 +1104,277 @@ hytm_status guarded(F&& f) {
     } catch (const std::bad_alloc&) {
         return fail(HYTM_E_NOMEM, "host allocation failed");
     }
+}
+
+}  // namespace
+
+// ============================================================== query server
+namespace {
+
+struct Query {
+    int algo = 0;
+    uint32_t source = 0;
+    void* out = nullptr;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    uint32_t iterations = 0;
+    hytm_status status = HYTM_OK;
+    std::string msg;
+    bool done = false;
+};
+
+// The lanes of one algorithm: own frontier bitmaps, lane masks and value rows; the
+// graph's scratch and engines are shared with the other groups.
+struct LaneGroup {
+    int algo = -1;  // hytm_algo; -1 = no group
+    uint32_t lanes = 0, lshift = 0;
+    RunCtx rc;
+    DevBuf<uint32_t> cur, nxt, lval;
+    DevBuf<uint64_t> mcur, mnxt, mvis;
+    DevBuf<float> lx, lacc;
+    uint64_t occupied = 0;  // lanes holding a query (changed by the worker only, under the lock)
+    uint64_t fresh = 0;     // lanes admitted since the last step
+    std::shared_ptr<Query> q[MAX_LANES];
+    uint32_t src[MAX_LANES] = {}, base[MAX_LANES] = {}, iters[MAX_LANES] = {}, left[MAX_LANES] = {};
+
+    uint64_t all() const { return lanes == 64 ? ~0ull : (1ull << lanes) - 1; }
+    void release() {
+        for (auto* b : {&cur, &nxt, &lval}) b->release();
+        for (auto* b : {&mcur, &mnxt, &mvis}) b->release();
+        lx.release();
+        lacc.release();
+    }
+};
+
+int group_index(int algo) { return algo == HYTM_BFS ? 0 : algo == HYTM_SSSP ? 1 : algo == HYTM_PPR ? 2 : -1; }
+
+uint64_t group_state_bytes(uint64_t n, int algo, uint32_t lanes) {
+    const uint64_t rows = n << lane_shift(lanes);
+    uint64_t b = 2 * ((n + 31) / 32) * 4 + 2 * n * 8;  // union bitmaps, lane masks
+    if (algo == HYTM_BFS) b += n * 8;                   // lanes that reached each vertex
+    return b + rows * 4 * (algo == HYTM_PPR ? 2 : 1);
+}
+
+}  // namespace
+
+struct hytm_server {
+    hytm_graph* g = nullptr;
+    hytm_server_config cfg{};
+    LaneGroup grp[3];  // BFS, SSSP, PPR
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Query>> pending;
+    std::unordered_map<uint64_t, std::shared_ptr<Query>> tickets;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    hytm_status fatal = HYTM_OK;
+    std::string fatal_msg;
+    std::thread worker;
+};
+
+namespace {
+
+// Hand the values of the lanes in `mask` to their queries and free the lanes.
+void retire_lanes(hytm_server* s, LaneGroup& gr, uint64_t mask, hipStream_t main) {
+    hytm_graph* g = s->g;
+    uint64_t over = 0;
+    if (gr.algo == HYTM_SSSP) {
+        HIP_CHECK(hipStreamSynchronize(main));
+        uint32_t of[2] = {0, 0};
+        HIP_CHECK(hipMemcpy(of, g->d_overflow.p, sizeof(of), hipMemcpyDeviceToHost));
+        over = ((uint64_t)of[0] | ((uint64_t)of[1] << 32)) & mask;
+    }
+    LaneSet set{};
+    set.mask = mask & ~over;
+    void* outs[MAX_LANES];
+    uint32_t k = 0;
+    for (uint64_t m = set.mask; m; m &= m - 1) {
+        const uint32_t l = (uint32_t)__builtin_ctzll(m);
+        set.base[l] = gr.base[l];
+        outs[k++] = gr.q[l]->out;
+    }
+    if (set.mask) {
+        const uint32_t* vals = gr.algo == HYTM_PPR ? (const uint32_t*)gr.lx.p : gr.lval.p;
+        copy_lanes_out(g, vals, gr.lshift, set, gr.algo == HYTM_BFS, outs, main);
+    }
+    HIP_CHECK(launch_reset_lanes(gr.rc.as, mask, main));
+    const double now = now_ms();
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (uint64_t m = mask; m; m &= m - 1) {
+        const uint32_t l = (uint32_t)__builtin_ctzll(m);
+        Query& q = *gr.q[l];
+        q.iterations = gr.iters[l];
+        if ((over >> l) & 1) {
+            q.status = HYTM_E_RANGE;
+            q.msg = "an SSSP distance reaches 2^32-1 and does not fit in uint32";
+        }
+        q.t_done = now;
+        q.done = true;
+        gr.q[l].reset();
+    }
+    gr.occupied &= ~mask;
+    s->cv_done.notify_all();
+}
+
+// The worker: admit queued queries into free lanes, step every group that holds
+// queries by one iteration, retire the lanes whose traversal ended.
+void serve_loop(hytm_server* s) {
+    hytm_graph* g = s->g;
+    hipStream_t main = g->s_main;
+    hytm_status st = HYTM_OK;
+    try {
+        HIP_CHECK(hipSetDevice(g->device));
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(s->mu);
+                auto busy = [&] { return (s->grp[0].occupied | s->grp[1].occupied | s->grp[2].occupied) != 0; };
+                s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty() || busy(); });
+                if (s->pending.empty() && !busy()) break;  // stopped and drained
+                // oldest first, each into the lowest free lane of its group
+                const double now = now_ms();
+                for (auto it = s->pending.begin(); it != s->pending.end();) {
+                    LaneGroup& gr = s->grp[group_index((*it)->algo)];
+                    const uint64_t free_lanes = gr.all() & ~gr.occupied;
+                    if (!free_lanes) {
+                        ++it;
+                        continue;
+                    }
+                    const uint32_t l = (uint32_t)__builtin_ctzll(free_lanes);
+                    gr.occupied |= 1ull << l;
+                    gr.fresh |= 1ull << l;
+                    gr.q[l] = *it;
+                    gr.src[l] = (*it)->source;
+                    gr.base[l] = gr.rc.t;
+                    gr.iters[l] = 0;
+                    gr.left[l] = g->params.ppr_iterations;
+                    (*it)->t_admit = now;
+                    it = s->pending.erase(it);
+                }
+            }
+            for (LaneGroup& gr : s->grp) {
+                if (!gr.occupied) continue;
+                if (gr.fresh) {
+                    LaneSet set{};
+                    set.mask = gr.fresh;
+                    for (uint64_t m = gr.fresh; m; m &= m - 1) {
+                        const uint32_t l = (uint32_t)__builtin_ctzll(m);
+                        set.src[l] = gr.src[l];
+                        set.base[l] = gr.base[l];
+                    }
+                    HIP_CHECK(launch_admit_lanes(gr.rc.as, set, gr.rc.cur, main));
+                    gr.fresh = 0;
+                }
+                if (gr.algo == HYTM_PPR) {
+                    uint64_t due = 0;  // nothing left to step (ppr_iterations = 0)
+                    for (uint64_t m = gr.occupied; m; m &= m - 1)
+                        if (!gr.left[__builtin_ctzll(m)]) due |= m & (~m + 1);
+                    if (due) retire_lanes(s, gr, due, main);
+                    if (!gr.occupied) continue;
+                    gr.rc.ppr.mask = gr.occupied;
+                    for (uint64_t m = gr.occupied; m; m &= m - 1) gr.rc.ppr.src[__builtin_ctzll(m)] = gr.src[__builtin_ctzll(m)];
+                }
+                uint64_t active = 0;
+                bool empty = false;
+                st = step_once(gr.rc, main, &active, &empty);
+                if (st != HYTM_OK) throw HipError{st};
+                uint64_t done = 0;
+                if (gr.algo == HYTM_PPR) {
+                    for (uint64_t m = gr.occupied; m; m &= m - 1) {
+                        const uint32_t l = (uint32_t)__builtin_ctzll(m);
+                        gr.iters[l]++;
+                        if (--gr.left[l] == 0) done |= 1ull << l;
+                    }
+                } else {
+                    for (uint64_t m = gr.occupied & active; m; m &= m - 1) gr.iters[__builtin_ctzll(m)]++;
+                    done = gr.occupied & ~active;
+                }
+                if (done) retire_lanes(s, gr, done, main);
+            }
+        }
+        return;
+    } catch (const HipError& e) {
+        st = e.status;
+    } catch (const std::bad_alloc&) {
+        st = fail(HYTM_E_NOMEM, "host allocation failed in the query server");
+    }
+    // a failed step leaves the lane state undefined: fail every query, accept no more
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->fatal = st;
+    s->fatal_msg = g_err;
+    auto fail_query = [&](Query& q) {
+        q.status = st;
+        q.msg = s->fatal_msg;
+        q.t_done = now_ms();
+        q.done = true;
+    };
+    for (auto& q : s->pending) fail_query(*q);
+    s->pending.clear();
+    for (LaneGroup& gr : s->grp)
+        for (uint32_t l = 0; l < MAX_LANES; l++)
+            if (gr.q[l]) {
+                fail_query(*gr.q[l]);
+                gr.q[l].reset();
+            }
+    for (LaneGroup& gr : s->grp) gr.occupied = 0;
+    s->cv_done.notify_all();
+}
+
+hytm_status server_setup(hytm_server* s) {
+    hytm_graph* g = s->g;
+    HIP_CHECK(hipSetDevice(g->device));
+    ensure_streams(g);
+    hipStream_t main = g->s_main;
+    g->timer.on = false;
+    const uint64_t n = g->n;
+    const uint32_t nwords = (uint32_t)((n + 31) / 32);
+    Plan pl;
+    Totals tot;
+    const uint32_t plan_arrays = s->cfg.lanes[1] ? 2 : 1;
+    hytm_status ps = prepare_graph(g, plan_arrays, main, &pl, &tot);
+    if (ps != HYTM_OK) return ps;
+    static const int algos[3] = {HYTM_BFS, HYTM_SSSP, HYTM_PPR};
+    for (int k = 0; k < 3; k++) {
+        LaneGroup& gr = s->grp[k];
+        if (!s->cfg.lanes[k]) continue;
+        gr.algo = algos[k];
+        gr.lanes = s->cfg.lanes[k];
+        gr.lshift = lane_shift(gr.lanes);
+        gr.cur.ensure(nwords);
+        gr.nxt.ensure(nwords);
+        gr.mcur.ensure(n);
+        gr.mnxt.ensure(n);
+        if (gr.algo == HYTM_BFS) gr.mvis.ensure(n);
+        if (gr.algo == HYTM_PPR) {
+            gr.lx.ensure(n << gr.lshift);
+            gr.lacc.ensure(n << gr.lshift);
+        } else {
+            gr.lval.ensure(n << gr.lshift);
+        }
+        init_ctx(gr.rc, g, gr.algo, true, pl, nullptr);
+        AlgoState& as = gr.rc.as;
+        as.algo = gr.algo == HYTM_BFS ? ALGO_MBFS : gr.algo == HYTM_SSSP ? ALGO_MSSSP : ALGO_MPPR;
+        as.next = gr.nxt.p;
+        as.mcur = gr.mcur.p;
+        as.mnext = gr.mnxt.p;
+        as.mvisited = gr.mvis.p;
+        as.lval = gr.lval.p;
+        as.lx = gr.lx.p;
+        as.lacc = gr.lacc.p;
+        as.lshift = gr.lshift;
+        gr.rc.cur = gr.cur.p;
+        gr.rc.nxt = gr.nxt.p;
+        gr.rc.mcur = gr.mcur.p;
+        gr.rc.mnxt = gr.mnxt.p;
+        HIP_CHECK(launch_fill_u32(gr.cur.p, nwords, 0u, main));
+        HIP_CHECK(launch_fill_u32(gr.nxt.p, nwords, 0u, main));
+        HIP_CHECK(launch_fill_u32((uint32_t*)gr.mcur.p, 2 * n, 0u, main));
+        HIP_CHECK(launch_fill_u32((uint32_t*)gr.mnxt.p, 2 * n, 0u, main));
+        if (gr.mvis.p) HIP_CHECK(launch_fill_u32((uint32_t*)gr.mvis.p, 2 * n, 0u, main));
+        HIP_CHECK(launch_reset_lanes(as, gr.all(), main));
+    }
+    HIP_CHECK(launch_fill_u32(g->d_overflow.p, 2, 0u, main));
+    g->d_xout.ensure(n * EXTRACT_LANES);
+    HIP_CHECK(hipStreamSynchronize(main));
+    return HYTM_OK;
 }
 
 }  // namespace
@@ -1006,6 +1400,7 @@ void hytm_default_params(hytm_params* p) {
     p->index_bytes = 4;
     p->pr_iterations = 20;
     p->pr_damping = 0.85;
+    p->ppr_iterations = 10;
     p->streams = 4;
     p->gather_threads = 0;
     p->compact_chunk_edges = 0;
@@ -1096,6 +1491,7 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
 hytm_status hytm_set_device_budget(hytm_graph* g, uint64_t edge_bytes) {
     g_err.clear();
     if (!g) return fail(HYTM_E_INVAL, "graph is NULL");
+    if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
     if (edge_bytes != g->budget) g->res_valid = false;
     g->budget = edge_bytes;
     return HYTM_OK;
@@ -1104,6 +1500,7 @@ hytm_status hytm_set_device_budget(hytm_graph* g, uint64_t edge_bytes) {
 hytm_status hytm_set_params(hytm_graph* g, const hytm_params* p) {
     g_err.clear();
     if (!g) return fail(HYTM_E_INVAL, "graph is NULL");
+    if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
     hytm_params np;
     if (p) {
         if (p->struct_size != sizeof(hytm_params)) return fail(HYTM_E_INVAL, "params.struct_size mismatch");
@@ -1135,7 +1532,8 @@ hytm_status hytm_get_params(const hytm_graph* g, hytm_params* p) {
 hytm_status hytm_staging_bytes(const hytm_graph* g, hytm_algo algo, uint64_t* bytes) {
     g_err.clear();
     if (!g || !bytes) return fail(HYTM_E_INVAL, "NULL argument");
-    if (algo < HYTM_BFS || algo > HYTM_PAGERANK) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
+    if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
+    if (algo < HYTM_BFS || algo > HYTM_PPR) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
     const Staging s = staging_of(g, algo == HYTM_SSSP ? 2 : 1);
     switch (g->params.mode) {
     case HYTM_MODE_FILTER: *bytes = s.f_bytes; break;
@@ -1161,6 +1559,7 @@ hytm_status hytm_graph_info_get(const hytm_graph* g, hytm_graph_info* info) {
 hytm_status hytm_partition_bounds(const hytm_graph* g, uint64_t* bounds, uint64_t cap) {
     g_err.clear();
     if (!g || !bounds) return fail(HYTM_E_INVAL, "NULL argument");
+    if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
     if (cap < g->pv.size()) return fail(HYTM_E_INVAL, "bounds buffer holds %llu entries, needs %zu",
                                         (unsigned long long)cap, g->pv.size());
     for (size_t i = 0; i < g->pv.size(); i++) bounds[i] = g->pv[i];
@@ -1171,26 +1570,31 @@ hytm_status hytm_run(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
                      hytm_run_stats* stats, void* hip_stream) {
     g_err.clear();
     if (!g) return fail(HYTM_E_INVAL, "graph is NULL");
+    if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
     if (!values_out) return fail(HYTM_E_INVAL, "values_out is NULL");
-    if (algo < HYTM_BFS || algo > HYTM_PAGERANK) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
+    if (algo < HYTM_BFS || algo > HYTM_PPR) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
     if (stats && stats->struct_size != sizeof(hytm_run_stats))
         return fail(HYTM_E_INVAL, "stats.struct_size mismatch");
-    if ((algo == HYTM_BFS || algo == HYTM_SSSP) && source >= g->n)
+    if ((algo == HYTM_BFS || algo == HYTM_SSSP || algo == HYTM_PPR) && source >= g->n)
         return fail(HYTM_E_RANGE, "source %u >= n = %llu", source, (unsigned long long)g->n);
     if (algo == HYTM_SSSP && !g->h_w) return fail(HYTM_E_INVAL, "SSSP needs edge weights");
     if (algo == HYTM_CC && !(g->flags & HYTM_GRAPH_SYMMETRIC))
         return fail(HYTM_E_INVAL, "CC needs a graph created with HYTM_GRAPH_SYMMETRIC");
     if (algo == HYTM_PAGERANK && g->params.pr_iterations == 0)
         return fail(HYTM_E_INVAL, "pr_iterations must be > 0");
-    return guarded([&] { return run_impl(g, algo, &source, 0, values_out, iterations_out, stats, hip_stream); });
+    // personalized PageRank runs as one lane of the batched form
+    const uint32_t lanes = algo == HYTM_PPR ? 1 : 0;
+    return guarded([&] { return run_impl(g, algo, &source, lanes, values_out, iterations_out, stats, hip_stream); });
 }
 
 hytm_status hytm_run_batch(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uint32_t nsources,
                            void* values_out, uint32_t* iterations_out, hytm_run_stats* stats, void* hip_stream) {
     g_err.clear();
     if (!g) return fail(HYTM_E_INVAL, "graph is NULL");
+    if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
     if (!values_out || !sources) return fail(HYTM_E_INVAL, "NULL argument");
-    if (algo != HYTM_BFS && algo != HYTM_SSSP) return fail(HYTM_E_INVAL, "batched runs support BFS and SSSP");
+    if (algo != HYTM_BFS && algo != HYTM_SSSP && algo != HYTM_PPR)
+        return fail(HYTM_E_INVAL, "batched runs support BFS, SSSP and PPR");
     if (nsources == 0 || nsources > MAX_LANES) return fail(HYTM_E_INVAL, "nsources must be in 1..64");
     if (stats && stats->struct_size != sizeof(hytm_run_stats))
         return fail(HYTM_E_INVAL, "stats.struct_size mismatch");
@@ -1207,6 +1611,7 @@ hytm_status hytm_select_engines(hytm_graph* g, uint64_t npart, const uint64_t* E
                                 uint8_t* p_out) {
     g_err.clear();
     if (!g || (npart && (!E || !nA || !Ea || !Rq || !p_out))) return fail(HYTM_E_INVAL, "NULL argument");
+    if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
     if (edge_arrays != 1 && edge_arrays != 2) return fail(HYTM_E_INVAL, "edge_arrays must be 1 or 2");
     for (uint64_t i = 0; i < npart; i++)
         if (E[i] >= (1ull << 40) || Ea[i] > E[i] || nA[i] > Ea[i] || Rq[i] >= (1ull << 44) ||
@@ -1290,9 +1695,150 @@ hytm_status hytm_link_probe(int hip_device, uint64_t bytes, hytm_link_probe_resu
     return status;
 }
 
+hytm_status hytm_host_alloc(int hip_device, uint64_t bytes, void** out) {
+    g_err.clear();
+    if (!out) return fail(HYTM_E_INVAL, "out is NULL");
+    return guarded([&]() -> hytm_status {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count)
+            return fail(HYTM_E_DEVICE, "HIP device %d is not available", hip_device);
+        HIP_CHECK(hipSetDevice(hip_device));
+        HIP_CHECK(hipHostMalloc(out, bytes ? bytes : 1, hipHostMallocDefault));
+        return HYTM_OK;
+    });
+}
+
+hytm_status hytm_host_free(void* p) {
+    g_err.clear();
+    if (!p) return HYTM_OK;
+    hipError_t e = hipHostFree(p);
+    if (e != hipSuccess) return fail(HYTM_E_DEVICE, "hipHostFree failed: %s", hipGetErrorString(e));
+    return HYTM_OK;
+}
+
+hytm_status hytm_server_state_bytes(const hytm_graph* g, hytm_algo algo, uint32_t lanes, uint64_t* bytes) {
+    g_err.clear();
+    if (!g || !bytes) return fail(HYTM_E_INVAL, "NULL argument");
+    if (group_index(algo) < 0) return fail(HYTM_E_INVAL, "the server runs BFS, SSSP and PPR");
+    if (lanes == 0 || lanes > MAX_LANES) return fail(HYTM_E_INVAL, "lanes must be in 1..64");
+    *bytes = group_state_bytes(g->n, algo, lanes);
+    return HYTM_OK;
+}
+
+hytm_status hytm_server_open(hytm_graph* g, const hytm_server_config* cfg, hytm_server** out) {
+    g_err.clear();
+    if (!g || !cfg || !out) return fail(HYTM_E_INVAL, "NULL argument");
+    *out = nullptr;
+    if (cfg->struct_size != sizeof(hytm_server_config)) return fail(HYTM_E_INVAL, "config.struct_size mismatch");
+    if (g->server) return fail(HYTM_E_STATE, "a query server is already open on this graph");
+    static const hytm_algo algos[3] = {HYTM_BFS, HYTM_SSSP, HYTM_PPR};
+    uint64_t need = g->n * EXTRACT_LANES * 4;  // extraction staging
+    uint32_t groups = 0;
+    for (int k = 0; k < 3; k++) {
+        if (cfg->lanes[k] > MAX_LANES) return fail(HYTM_E_INVAL, "lanes[%d] = %u exceeds 64", k, cfg->lanes[k]);
+        if (!cfg->lanes[k]) continue;
+        groups++;
+        need += group_state_bytes(g->n, algos[k], cfg->lanes[k]);
+    }
+    if (!groups) return fail(HYTM_E_INVAL, "no lane group: every lanes[] entry is 0");
+    if (cfg->lanes[1] && !g->h_w) return fail(HYTM_E_INVAL, "an SSSP group needs edge weights");
+    if (cfg->state_budget && need > cfg->state_budget)
+        return fail(HYTM_E_BUDGET, "lane state needs %llu bytes, state_budget is %llu", (unsigned long long)need,
+                    (unsigned long long)cfg->state_budget);
+    std::unique_ptr<hytm_server> s(new (std::nothrow) hytm_server);
+    if (!s) return fail(HYTM_E_NOMEM, "host allocation failed");
+    s->g = g;
+    s->cfg = *cfg;
+    hytm_status st = guarded([&] { return server_setup(s.get()); });
+    if (st != HYTM_OK) {
+        for (LaneGroup& gr : s->grp) gr.release();
+        return st;
+    }
+    g->server = s.get();
+    s->worker = std::thread(serve_loop, s.get());
+    *out = s.release();
+    return HYTM_OK;
+}
+
+hytm_status hytm_server_submit(hytm_server* s, hytm_algo algo, uint32_t source, void* values_out,
+                               uint64_t* ticket) {
+    g_err.clear();
+    if (!s || !values_out || !ticket) return fail(HYTM_E_INVAL, "NULL argument");
+    const int k = group_index(algo);
+    if (k < 0 || !s->cfg.lanes[k]) return fail(HYTM_E_INVAL, "the server has no lane group for algorithm %d", (int)algo);
+    if (source >= s->g->n) return fail(HYTM_E_RANGE, "source %u >= n = %llu", source, (unsigned long long)s->g->n);
+    std::shared_ptr<Query> q;
+    try {
+        q = std::make_shared<Query>();
+    } catch (const std::bad_alloc&) {
+        return fail(HYTM_E_NOMEM, "host allocation failed");
+    }
+    q->algo = algo;
+    q->source = source;
+    q->out = values_out;
+    q->t_submit = now_ms();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->fatal != HYTM_OK) {
+        g_err = s->fatal_msg;
+        return s->fatal;
+    }
+    if (s->stop) return fail(HYTM_E_STATE, "the server is closing");
+    if (s->cfg.max_pending && s->pending.size() >= s->cfg.max_pending)
+        return fail(HYTM_E_STATE, "the queue holds max_pending = %llu queries", (unsigned long long)s->cfg.max_pending);
+    *ticket = s->next_ticket++;
+    s->tickets[*ticket] = q;
+    s->pending.push_back(q);
+    s->cv_work.notify_one();
+    return HYTM_OK;
+}
+
+hytm_status hytm_server_wait(hytm_server* s, uint64_t ticket, double timeout_ms, hytm_query_result* result) {
+    g_err.clear();
+    if (!s) return fail(HYTM_E_INVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return fail(HYTM_E_STATE, "unknown ticket %llu", (unsigned long long)ticket);
+    std::shared_ptr<Query> q = it->second;
+    auto ready = [&] { return q->done; };
+    if (timeout_ms < 0)
+        s->cv_done.wait(lk, ready);
+    else if (!s->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), ready))
+        return fail(HYTM_E_STATE, "query %llu not done within %.1f ms", (unsigned long long)ticket, timeout_ms);
+    s->tickets.erase(ticket);
+    if (result) {
+        result->status = q->status;
+        result->iterations = q->iterations;
+        result->queue_ms = q->t_admit ? q->t_admit - q->t_submit : 0.0;
+        result->run_ms = q->t_admit ? q->t_done - q->t_admit : 0.0;
+        result->total_ms = q->t_done - q->t_submit;
+    }
+    if (q->status != HYTM_OK) g_err = q->msg;
+    return q->status;
+}
+
+hytm_status hytm_server_close(hytm_server* s) {
+    g_err.clear();
+    if (!s) return HYTM_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    const hytm_status fatal = s->fatal;
+    if (fatal != HYTM_OK) g_err = s->fatal_msg;
+    (void)hipSetDevice(s->g->device);
+    (void)hipDeviceSynchronize();
+    for (LaneGroup& gr : s->grp) gr.release();
+    s->g->server = nullptr;
+    delete s;
+    return fatal;
+}
+
 hytm_status hytm_graph_destroy(hytm_graph* g) {
     g_err.clear();
     if (!g) return HYTM_OK;
+    if (g->server) return fail(HYTM_E_STATE, "close the query server on this graph first");
     (void)hipSetDevice(g->device);
     release_all(g);
     delete g;

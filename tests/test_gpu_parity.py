@@ -283,3 +283,28 @@ def test_repeat_runs_are_identical(rmat16):
         a = g.run("sssp", 0).values.copy()
         b = g.run("sssp", 0).values
         np.testing.assert_array_equal(a, b)
+
+
+def test_pinned_output_buffers_match_pageable(rmat16):
+    """Results written into pinned host buffers (direct DMA) equal the pageable-buffer path,
+    for single runs and for a batched run into a buffer larger than needed."""
+    n = len(rmat16.off) - 1
+    with rmat16.graph("sssp") as g:
+        g.set_params(partition_edges=4096)
+        g.set_resident_fraction("sssp", 0.25)
+        pin = hy.pinned_empty(n + 7, np.uint32)
+        pin[:] = 0xDEADBEEF
+        r = g.run("sssp", 0, out=pin[:n])
+        check(rmat16, "sssp", r, 0)
+        assert np.all(pin[n:] == 0xDEADBEEF)
+        pf = hy.pinned_empty(n, np.float32)
+        g.set_resident_fraction("pagerank", 0.25)
+        check(rmat16, "pagerank", g.run("pagerank", out=pf))
+        srcs = np.array([0, 5, 9], dtype=np.uint32)
+        g.set_resident_fraction("bfs", 0.25)
+        pb = hy.pinned_empty((4, n), np.uint32)
+        vals, its, _ = g.run_batch("bfs", srcs, out=pb)
+        for i, s in enumerate(srcs):
+            np.testing.assert_array_equal(vals[i], rmat16.want("bfs", int(s))[0])
+        with pytest.raises(ValueError):
+            g.run("bfs", 0, out=np.zeros(n, dtype=np.float32))
