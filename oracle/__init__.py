@@ -70,6 +70,7 @@ def _load():
         "orc_cc": (u64, [u64, vp, vp, vp]),
         "orc_pagerank": (None, [u64, vp, vp, dbl, u32, vp]),
         "orc_ppr": (None, [u64, vp, vp, u32, dbl, u32, vp]),
+        "orc_hub_order": (u64, [u64, vp, vp, u32, u32, vp]),
         "orc_partition": (u64, [u64, vp, u64, vp]),
         "orc_partition_stats": (None, [u64, vp, vp, vp, u32, u32, vp, vp, vp]),
         "orc_select": (None, [u64, vp, vp, vp, vp, u64, ctypes.POINTER(_CostParams), i32, vp]),
@@ -148,6 +149,15 @@ def ppr(off, col, source: int, d: float = 0.85, T: int = 10):
     x = np.empty(max(n, 1), dtype=np.float64)[:n]
     _load().orc_ppr(n, _p(off), _p(col), int(source), float(d), int(T), _p(x))
     return x
+
+
+def hub_order(off, col, num: int = 8, den: int = 100):
+    """Hub sorting's new vertex order: (order, k) with order[i] = original id of new vertex
+    i and the first k entries the hubs."""
+    off, col, n = _csr(off, col)
+    order = np.empty(max(n, 1), dtype=np.uint32)[:n]
+    k = _load().orc_hub_order(n, _p(off), _p(col), int(num), int(den), _p(order))
+    return order, int(k)
 
 
 def partition(off, target_edges: int):

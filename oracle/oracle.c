@@ -24,6 +24,9 @@
  *  - orc_ppr      : personalized PageRank: the same iteration with the restart mass
  *                   on one source vertex instead of spread over all of them, x_0 = e_s
  *                   (the query served alongside BFS and SSSP).  FP64.
+ *  - orc_hub_order: hub sorting (Sec. 6.1): the top 8% of vertices by
+ *                   H(v) = D_o(v) D_i(v) / (D_omax D_imax), highest first, ahead of the
+ *                   other vertices in their natural order.
  *  - orc_partition: chunk-based edge-balanced partitioning into consecutive vertex
  *                   ranges (Sec. 4).
  *  - orc_partition_stats / orc_select : the per-partition cost model, Eq. 1-3 with the
@@ -268,6 +271,55 @@ void orc_ppr(uint64_t n, const uint64_t *off, const uint32_t *col, uint32_t sour
         for (uint64_t v = 0; v < n; v++) x[v] = (v == source ? 1.0 - d : 0.0) + d * acc[v];
     }
     free(acc);
+}
+
+/* ----------------------------------------------------------- hub sorting */
+/* New vertex order of hub sorting (Sec. 6.1).  H(v) is proportional to D_o(v) * D_i(v)
+   (the maxima in its denominator are the same for every v), so ranking by the integer
+   product ranks by H.  Readings: the hubs are the floor(n * num / den) highest-ranked
+   vertices among those with H > 0 (num/den = 8/100), ties to the smaller id; hubs come
+   first in decreasing H, then every other vertex in increasing id.  order[i] = the
+   original id of new vertex i.  Returns the number of hubs. */
+typedef struct {
+    unsigned __int128 score;
+    uint32_t v;
+} orc_scored;
+
+static int orc_by_score(const void *a, const void *b) {
+    const orc_scored *x = (const orc_scored *)a, *y = (const orc_scored *)b;
+    if (x->score != y->score) return x->score > y->score ? -1 : 1;
+    return x->v < y->v ? -1 : (x->v > y->v ? 1 : 0);
+}
+
+uint64_t orc_hub_order(uint64_t n, const uint64_t *off, const uint32_t *col, uint32_t num, uint32_t den,
+                       uint32_t *order) {
+    uint64_t *din = (uint64_t *)calloc(n ? n : 1, sizeof(uint64_t));
+    for (uint64_t e = 0; e < off[n]; e++) din[col[e]]++;
+    orc_scored *sc = (orc_scored *)malloc((n ? n : 1) * sizeof(orc_scored));
+    uint64_t pos = 0;
+    for (uint64_t v = 0; v < n; v++) {
+        unsigned __int128 h = (unsigned __int128)(off[v + 1] - off[v]) * din[v];
+        if (h) {
+            sc[pos].score = h;
+            sc[pos].v = (uint32_t)v;
+            pos++;
+        }
+    }
+    qsort(sc, pos, sizeof(orc_scored), orc_by_score);
+    uint64_t k = (uint64_t)(((unsigned __int128)n * num) / den);
+    if (k > pos) k = pos;
+    uint8_t *hub = (uint8_t *)calloc(n ? n : 1, 1);
+    for (uint64_t i = 0; i < k; i++) {
+        order[i] = sc[i].v;
+        hub[sc[i].v] = 1;
+    }
+    uint64_t i = k;
+    for (uint64_t v = 0; v < n; v++)
+        if (!hub[v]) order[i++] = (uint32_t)v;
+    free(hub);
+    free(sc);
+    free(din);
+    return k;
 }
 
 /* ----------------------------------------------------------- partitions */
