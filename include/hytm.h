@@ -75,7 +75,13 @@ enum { HYTM_P_NONE = 0, HYTM_P_RESIDENT = 1, HYTM_P_FILTER = 2, HYTM_P_ZEROCOPY 
 /* hytm_graph_create flags */
 enum {
     HYTM_GRAPH_SYMMETRIC = 1u << 1, /* caller asserts (u,v) in E implies (v,u) in E; needed by HYTM_CC */
-    HYTM_GRAPH_SKIP_COL_CHECK = 1u << 2 /* skip the O(m) check that every col[e] < n */
+    HYTM_GRAPH_SKIP_COL_CHECK = 1u << 2, /* skip the O(m) check that every col[e] < n */
+    /* hub sorting (Sec. 6.1): relabel the graph once at creation so that its hubs -- the
+       top 8% of vertices by H(v) = D_o(v) D_i(v) / (D_omax D_imax) -- come first, highest
+       first, the other vertices keeping their natural order.  Sources and results stay in
+       the caller's ids; partitions, hytm_partition_bounds and mode traces refer to the
+       relabelled order.  Implies the col check. */
+    HYTM_GRAPH_HUB_SORT = 1u << 3
 };
 
 /* Tunables.  Defaults (hytm_default_params) are the constants the paper states:
@@ -193,6 +199,7 @@ typedef struct {
     uint32_t max_partition_edges;
     int hip_device;
     uint32_t flags;
+    uint64_t hubs;              /* vertices moved to the front by HYTM_GRAPH_HUB_SORT (else 0) */
 } hytm_graph_info;
 
 /* Fill *p with the paper's defaults listed above. */
@@ -214,6 +221,14 @@ void hytm_default_params(hytm_params *p);
 hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void *offsets, uint32_t offset_bytes,
                               const uint32_t *col, const uint32_t *weights, uint32_t flags, int hip_device,
                               hytm_graph **out);
+
+/* The new vertex order hub sorting gives a CSR (host computation, no device needed):
+   order_out[i] = original id of new vertex i (n entries), *hubs_out = the number of hubs,
+   which come first.  Ranking by D_o(v) D_i(v) is ranking by H(v); the hubs are the
+   floor(0.08 n) highest-ranked vertices with H(v) > 0, ties to the smaller id.  Errors:
+   E_INVAL (null pointers, malformed offsets, col >= n), E_RANGE (n too large). */
+hytm_status hytm_hub_order(uint64_t n, uint64_t m, const void *offsets, uint32_t offset_bytes, const uint32_t *col,
+                           uint32_t *order_out, uint64_t *hubs_out);
 
 /* Device budget for edge-associated data: resident partitions + filter staging +
    compaction buffers.  UINT64_MAX (the default) = uncapped: every partition resident.

@@ -27,6 +27,7 @@ P_NONE, P_RESIDENT, P_FILTER, P_ZEROCOPY, P_COMPACT = range(5)
 ENGINE_NAMES = ["none", "resident", "filter", "zerocopy", "compact"]
 GRAPH_SYMMETRIC = 1 << 1
 GRAPH_SKIP_COL_CHECK = 1 << 2
+GRAPH_HUB_SORT = 1 << 3
 UNCAPPED = (1 << 64) - 1
 UNREACHED = 0xFFFFFFFF
 
@@ -99,7 +100,8 @@ class QueryResult(ctypes.Structure):
 
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("m", ctypes.c_uint64), ("npart", ctypes.c_uint32),
-                ("max_partition_edges", ctypes.c_uint32), ("hip_device", ctypes.c_int), ("flags", ctypes.c_uint32)]
+                ("max_partition_edges", ctypes.c_uint32), ("hip_device", ctypes.c_int), ("flags", ctypes.c_uint32),
+                ("hubs", ctypes.c_uint64)]
 
 
 # every exported entry point of include/hytm.h with its ctypes signature
@@ -109,6 +111,8 @@ _SIGNATURES = {
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "hytm_set_device_budget": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "hytm_hub_order": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "hytm_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params)]),
     "hytm_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params)]),
     "hytm_graph_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GraphInfo)]),
@@ -209,6 +213,21 @@ def _ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
 
 
+def hub_order(off, col):
+    """Hub sorting's vertex order as the library computes it on the host: (order, hubs)
+    with order[i] = original id of new vertex i and the first `hubs` entries the hubs."""
+    off = np.ascontiguousarray(off)
+    if off.dtype not in (np.uint32, np.uint64):
+        off = off.astype(np.uint64)
+    col = np.ascontiguousarray(col, dtype=np.uint32)
+    n = len(off) - 1
+    order = np.empty(max(n, 1), dtype=np.uint32)
+    k = ctypes.c_uint64(0)
+    _check(load().hytm_hub_order(n, len(col), _ptr(off), off.dtype.itemsize, _ptr(col) if len(col) else None,
+                                 _ptr(order), ctypes.byref(k)))
+    return order[:n], int(k.value)
+
+
 def default_params() -> Params:
     p = Params()
     load().hytm_default_params(ctypes.byref(p))
@@ -239,7 +258,7 @@ class Graph:
     """A CSR graph whose edge arrays live in pinned host memory (libhytm handle)."""
 
     def __init__(self, off, col, weights=None, symmetric: bool = False, device: int = 0,
-                 check_col: bool = True):
+                 check_col: bool = True, hub_sort: bool = False):
         lib = load()
         off = np.ascontiguousarray(off)
         if off.dtype not in (np.uint32, np.uint64):
@@ -250,7 +269,8 @@ class Graph:
             raise ValueError("weights and col differ in length")
         self.n = len(off) - 1
         self.m = len(col)
-        flags = (GRAPH_SYMMETRIC if symmetric else 0) | (0 if check_col else GRAPH_SKIP_COL_CHECK)
+        flags = ((GRAPH_SYMMETRIC if symmetric else 0) | (0 if check_col else GRAPH_SKIP_COL_CHECK)
+                 | (GRAPH_HUB_SORT if hub_sort else 0))
         h = ctypes.c_void_p()
         self._keep = [np.zeros(1, np.uint32)]  # stand-in buffer for empty arrays
         colp = _ptr(col) if self.m else _ptr(self._keep[0])

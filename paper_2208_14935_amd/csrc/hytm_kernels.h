@@ -104,9 +104,17 @@ hipError_t launch_init_lanes(const AlgoState& s, const LaneSources& src, uint32_
 hipError_t launch_lane_union(const uint64_t* mask, uint64_t n, unsigned long long* lanes, hipStream_t st);
 // Rows k = 0.. of out (n values each) <- the lanes of `set` in increasing lane order,
 // from n rows of 2^lshift 32-bit values; with sub_base, a value other than UNREACHED has
-// the lane's base subtracted (BFS levels of lanes that joined late).
+// the lane's base subtracted (BFS levels of lanes that joined late).  order (or null):
+// vertex v's value goes to position order[v] of its row (back to the caller's ids).
 hipError_t launch_extract_lanes(const uint32_t* vals, uint64_t n, uint32_t lshift, const LaneSet& set, bool sub_base,
-                                uint32_t* out, hipStream_t st);
+                                const uint32_t* order, uint32_t* out, hipStream_t st);
+// Back to the caller's ids after hub sorting: dst[v] = src[rank[v]] for v < n.
+hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* rank, uint64_t n, uint32_t* dst, hipStream_t st);
+// CC labels back to the caller's ids: every component's label becomes its smallest
+// original id.  lab: labels in the relabelled order; order / rank: new -> original and
+// original -> new ids; minold: n words of scratch.
+hipError_t launch_cc_relabel(const uint32_t* lab, const uint32_t* order, const uint32_t* rank, uint64_t n,
+                             uint32_t* minold, uint32_t* dst, hipStream_t st);
 // Start the lanes of `set` at their sources (their columns must hold the reset values):
 // BFS level = base, SSSP distance = 0, PPR x = 1; lane bits at the source in mcur (and
 // mvisited), source bits in the union frontier `cur`.

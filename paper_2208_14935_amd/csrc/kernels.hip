@@ -784,6 +784,7 @@ __global__ __launch_bounds__(256) void k_lane_union(const uint64_t* __restrict__
 constexpr uint32_t EX_V = 64;
 __global__ __launch_bounds__(256) void k_extract_lanes(const uint32_t* __restrict__ vals, uint64_t n,
                                                        uint32_t lshift, LaneSet set, uint32_t nsel, bool sub_base,
+                                                       const uint32_t* __restrict__ order,
                                                        uint32_t* __restrict__ out) {
     __shared__ uint32_t tile[EX_V * (MAX_LANES + 1)];
     __shared__ uint8_t s_lane[MAX_LANES];
@@ -811,9 +812,27 @@ __global__ __launch_bounds__(256) void k_extract_lanes(const uint32_t* __restric
             if (i >= nv) continue;
             uint32_t x = tile[i * pitch + s_lane[k]];
             if (sub_base && x != UNREACHED) x -= s_base[k];
-            out[(uint64_t)k * n + v0 + i] = x;
+            out[(uint64_t)k * n + (order ? order[v0 + i] : v0 + i)] = x;
         }
     }
+}
+
+__global__ void k_gather_u32(const uint32_t* __restrict__ src, const uint32_t* __restrict__ rank, uint64_t n,
+                             uint32_t* __restrict__ dst) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+        dst[v] = src[rank[v]];
+}
+
+__global__ void k_cc_min_old(const uint32_t* __restrict__ lab, const uint32_t* __restrict__ order, uint64_t n,
+                             uint32_t* __restrict__ minold) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+        atomicMin(minold + lab[v], order[v]);
+}
+
+__global__ void k_cc_canon(const uint32_t* __restrict__ lab, const uint32_t* __restrict__ minold,
+                           const uint32_t* __restrict__ rank, uint64_t n, uint32_t* __restrict__ dst) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+        dst[v] = minold[lab[rank[v]]];
 }
 
 __global__ void k_admit_lanes(AlgoState s, LaneSet set, uint32_t* __restrict__ cur) {
@@ -1067,10 +1086,26 @@ hipError_t launch_lane_union(const uint64_t* mask, uint64_t n, unsigned long lon
 }
 
 hipError_t launch_extract_lanes(const uint32_t* vals, uint64_t n, uint32_t lshift, const LaneSet& set, bool sub_base,
-                                uint32_t* out, hipStream_t st) {
+                                const uint32_t* order, uint32_t* out, hipStream_t st) {
     const uint32_t nsel = (uint32_t)__builtin_popcountll(set.mask);
     if (!n || !nsel || lshift > 6 || (set.mask >> 1 >> ((1u << lshift) - 1))) return n && nsel ? hipErrorInvalidValue : hipSuccess;
-    k_extract_lanes<<<grid_for(n, EX_V, 16384), 256, 0, st>>>(vals, n, lshift, set, nsel, sub_base, out);
+    k_extract_lanes<<<grid_for(n, EX_V, 16384), 256, 0, st>>>(vals, n, lshift, set, nsel, sub_base, order, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* rank, uint64_t n, uint32_t* dst, hipStream_t st) {
+    if (!n) return hipSuccess;
+    k_gather_u32<<<grid_for(n, 256, 8192), 256, 0, st>>>(src, rank, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_cc_relabel(const uint32_t* lab, const uint32_t* order, const uint32_t* rank, uint64_t n,
+                             uint32_t* minold, uint32_t* dst, hipStream_t st) {
+    if (!n) return hipSuccess;
+    hipError_t e = launch_fill_u32(minold, n, UNREACHED, st);
+    if (e != hipSuccess) return e;
+    k_cc_min_old<<<grid_for(n, 256, 8192), 256, 0, st>>>(lab, order, n, minold);
+    k_cc_canon<<<grid_for(n, 256, 8192), 256, 0, st>>>(lab, minold, rank, n, dst);
     return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "hytm.h"
+#include "hubsort.h"
 #include "hytm_kernels.h"
 #include "pool.h"
 
@@ -232,6 +233,14 @@ struct hytm_graph {
     Pool* pool = nullptr;
     KTimer timer;
     hytm_server* server = nullptr;  // open query server (owns the graph while set)
+
+    // hub sorting: the graph is held relabelled; callers' ids map through these
+    uint64_t hubs = 0;
+    std::vector<uint32_t> h_rank;        // caller id -> internal id
+    DevBuf<uint32_t> d_rank, d_order;    // caller -> internal, internal -> caller
+    DevBuf<uint32_t> d_minold;           // CC label canonicalization scratch
+    bool hub_sorted() const { return !h_rank.empty(); }
+    uint32_t inner(uint32_t v) const { return h_rank.empty() ? v : h_rank[v]; }
 };
 
 namespace {
@@ -430,6 +439,9 @@ void release_all(hytm_graph* g) {
     g->d_lx.release();
     g->d_lacc.release();
     g->d_xout.release();
+    g->d_rank.release();
+    g->d_order.release();
+    g->d_minold.release();
     g->h_lanes.release();
     g->d_hdr.release();
     for (uint32_t i = 0; i < kMaxSlots; i++) {
@@ -933,7 +945,8 @@ void copy_lanes_out(hytm_graph* g, const uint32_t* vals, uint32_t lshift, const 
             part.mask |= rest & (~rest + 1);
             rest &= rest - 1;
         }
-        HIP_CHECK(launch_extract_lanes(vals, n, lshift, part, sub_base, g->d_xout.p, main));
+        HIP_CHECK(launch_extract_lanes(vals, n, lshift, part, sub_base, g->hub_sorted() ? g->d_order.p : nullptr,
+                                       g->d_xout.p, main));
         const uint32_t cnt = (uint32_t)__builtin_popcountll(part.mask);
         for (uint32_t c = 0; c < cnt; c++)
             HIP_CHECK(hipMemcpyAsync(outs[k + c], g->d_xout.p + (uint64_t)c * n, n * 4, hipMemcpyDeviceToHost, main));
@@ -954,7 +967,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     const double t_begin = now_ms();
     const uint32_t arrays = algo == HYTM_SSSP ? 2 : 1;
     const bool batched = lanes > 0;
-    const uint32_t source = sources ? sources[0] : 0;
+    const uint32_t source = sources ? g->inner(sources[0]) : 0;
     hipStream_t main = hip_stream ? (hipStream_t)hip_stream : g->s_main;
     KTimer& kt = g->timer;
     kt.on = stats && stats->time_kernels;
@@ -1014,10 +1027,10 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         as.lshift = lsh;
         LaneSources ls{};
         ls.count = lanes;
-        for (uint32_t l = 0; l < lanes; l++) ls.src[l] = sources[l];
+        for (uint32_t l = 0; l < lanes; l++) ls.src[l] = g->inner(sources[l]);
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_init_lanes(as, ls, rc.cur, nwords, main); }));
         rc.ppr.mask = lanes == 64 ? ~0ull : (1ull << lanes) - 1;
-        for (uint32_t l = 0; l < lanes; l++) rc.ppr.src[l] = sources[l];
+        for (uint32_t l = 0; l < lanes; l++) rc.ppr.src[l] = ls.src[l];
     } else {
         const float x0 = n ? (float)(1.0 / (double)n) : 0.f;
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
@@ -1051,7 +1064,18 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         const uint32_t* vals = algo == HYTM_PPR ? (const uint32_t*)g->d_lx.p : g->d_lval.p;
         copy_lanes_out(g, vals, lsh, all, false, outs.data(), main);
     } else {
-        const void* src = algo == HYTM_PAGERANK ? (const void*)g->d_x.p : (const void*)g->d_val.p;
+        const uint32_t* src = algo == HYTM_PAGERANK ? (const uint32_t*)g->d_x.p : g->d_val.p;
+        if (g->hub_sorted()) {
+            // back to the caller's ids (CC: labels become the smallest original id)
+            g->d_xout.ensure(n);
+            if (algo == HYTM_CC) {
+                g->d_minold.ensure(n);
+                HIP_CHECK(launch_cc_relabel(src, g->d_order.p, g->d_rank.p, n, g->d_minold.p, g->d_xout.p, main));
+            } else {
+                HIP_CHECK(launch_gather_u32(src, g->d_rank.p, n, g->d_xout.p, main));
+            }
+            src = g->d_xout.p;
+        }
         HIP_CHECK(hipMemcpyAsync(values_out, src, n * 4, hipMemcpyDeviceToHost, main));
     }
     HIP_CHECK(hipStreamSynchronize(main));
@@ -1418,8 +1442,9 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
     if (n == 0) return fail(HYTM_E_INVAL, "graph has no vertices");
     if (n >= 0xFFFFFFFFull) return fail(HYTM_E_RANGE, "n = %llu: vertex ids must fit below 2^32-1", (unsigned long long)n);
     if (offset_bytes == 4 && m > 0xFFFFFFFFull) return fail(HYTM_E_INVAL, "m does not fit 4-byte offsets");
-    if (flags & ~(uint32_t)(HYTM_GRAPH_SYMMETRIC | HYTM_GRAPH_SKIP_COL_CHECK))
+    if (flags & ~(uint32_t)(HYTM_GRAPH_SYMMETRIC | HYTM_GRAPH_SKIP_COL_CHECK | HYTM_GRAPH_HUB_SORT))
         return fail(HYTM_E_INVAL, "unknown flag bits 0x%x", flags);
+    const bool hub_sort = flags & HYTM_GRAPH_HUB_SORT;
     hytm_graph* g = nullptr;
     try {
         g = new hytm_graph();
@@ -1445,7 +1470,7 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
             return fail(HYTM_E_INVAL, "offsets[n] = %llu but m = %llu", (unsigned long long)g->h_off[n],
                         (unsigned long long)m);
         }
-        if (!(flags & HYTM_GRAPH_SKIP_COL_CHECK)) {
+        if (!(flags & HYTM_GRAPH_SKIP_COL_CHECK) || hub_sort) {
             for (uint64_t e = 0; e < m; e++)
                 if (col[e] >= n) {
                     delete g;
@@ -1467,12 +1492,28 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
         // edge arrays: pinned host memory mapped into the device address space
         const size_t eb = std::max<uint64_t>(m, 1) * sizeof(uint32_t);
         HIP_CHECK(hipHostMalloc((void**)&g->h_col, eb, hipHostMallocMapped));
-        if (m) parallel_copy(g->h_col, col, m * sizeof(uint32_t));
         HIP_CHECK(hipHostGetDevicePointer((void**)&g->d_col_map, g->h_col, 0));
         if (weights) {
             HIP_CHECK(hipHostMalloc((void**)&g->h_w, eb, hipHostMallocMapped));
-            if (m) parallel_copy(g->h_w, weights, m * sizeof(uint32_t));
             HIP_CHECK(hipHostGetDevicePointer((void**)&g->d_w_map, g->h_w, 0));
+        }
+        if (hub_sort) {
+            // relabel once, straight into the pinned arrays (Sec. 6.1)
+            const unsigned threads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+            std::vector<uint32_t> order(n);
+            g->h_rank.resize(n);
+            g->hubs = hub_order(n, g->h_off.data(), col, 8, 100, threads, order.data(), g->h_rank.data());
+            std::vector<uint64_t> off2(n + 1);
+            hub_relabel(n, g->h_off.data(), col, weights, order.data(), g->h_rank.data(), threads, off2.data(),
+                        g->h_col, g->h_w);
+            g->h_off.swap(off2);
+            g->d_rank.ensure(n);
+            g->d_order.ensure(n);
+            HIP_CHECK(hipMemcpy(g->d_rank.p, g->h_rank.data(), n * 4, hipMemcpyHostToDevice));
+            HIP_CHECK(hipMemcpy(g->d_order.p, order.data(), n * 4, hipMemcpyHostToDevice));
+        } else if (m) {
+            parallel_copy(g->h_col, col, m * sizeof(uint32_t));
+            if (weights) parallel_copy(g->h_w, weights, m * sizeof(uint32_t));
         }
         g->d_off.ensure(n + 1);
         HIP_CHECK(hipMemcpy(g->d_off.p, g->h_off.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
@@ -1485,6 +1526,30 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
         return st;
     }
     *out = g;
+    return HYTM_OK;
+}
+
+hytm_status hytm_hub_order(uint64_t n, uint64_t m, const void* offsets, uint32_t offset_bytes, const uint32_t* col,
+                           uint32_t* order_out, uint64_t* hubs_out) {
+    g_err.clear();
+    if (!offsets || !order_out || !hubs_out || (m && !col)) return fail(HYTM_E_INVAL, "NULL argument");
+    if (offset_bytes != 4 && offset_bytes != 8) return fail(HYTM_E_INVAL, "offset_bytes must be 4 or 8");
+    if (n >= 0xFFFFFFFFull) return fail(HYTM_E_RANGE, "n = %llu: vertex ids must fit below 2^32-1", (unsigned long long)n);
+    try {
+        std::vector<uint64_t> off(n + 1);
+        for (uint64_t v = 0; v <= n; v++)
+            off[v] = offset_bytes == 8 ? ((const uint64_t*)offsets)[v] : ((const uint32_t*)offsets)[v];
+        if (off[0] != 0 || off[n] != m) return fail(HYTM_E_INVAL, "offsets must start at 0 and end at m");
+        for (uint64_t v = 0; v < n; v++)
+            if (off[v + 1] < off[v]) return fail(HYTM_E_INVAL, "offsets decrease at vertex %llu", (unsigned long long)v);
+        for (uint64_t e = 0; e < m; e++)
+            if (col[e] >= n) return fail(HYTM_E_INVAL, "col[%llu] = %u is not a vertex", (unsigned long long)e, col[e]);
+        std::vector<uint32_t> rank(n);
+        const unsigned threads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        *hubs_out = hub_order(n, off.data(), col, 8, 100, threads, order_out, rank.data());
+    } catch (const std::bad_alloc&) {
+        return fail(HYTM_E_NOMEM, "host allocation failed");
+    }
     return HYTM_OK;
 }
 
@@ -1553,6 +1618,7 @@ hytm_status hytm_graph_info_get(const hytm_graph* g, hytm_graph_info* info) {
     info->max_partition_edges = (uint32_t)std::min<uint64_t>(g->max_part_edges, 0xFFFFFFFFull);
     info->hip_device = g->device;
     info->flags = g->flags;
+    info->hubs = g->hubs;
     return HYTM_OK;
 }
 
@@ -1774,7 +1840,7 @@ hytm_status hytm_server_submit(hytm_server* s, hytm_algo algo, uint32_t source, 
         return fail(HYTM_E_NOMEM, "host allocation failed");
     }
     q->algo = algo;
-    q->source = source;
+    q->source = s->g->inner(source);
     q->out = values_out;
     q->t_submit = now_ms();
     std::lock_guard<std::mutex> lk(s->mu);

@@ -89,3 +89,17 @@ def test_binding_validates_before_calling():
     assert lib.hytm_set_device_budget(None, 0) == hy.E_INVAL
     assert lib.hytm_run(None, 0, 0, None, None, None, None) == hy.E_INVAL
     assert lib.hytm_set_params(None, None) == hy.E_INVAL
+
+
+def test_library_hub_order_matches_the_oracle():
+    """The library's host hub sorting (no device needed) against the oracle's."""
+    import gen
+    import oracle
+    for off, col in (gen.rmat(12, 16, seed=3), gen.er(3000, 20000, seed=4),
+                     gen.from_pairs(5, np.array([0, 1, 2], np.uint32), np.array([1, 2, 0], np.uint32))):
+        order, k = hy.hub_order(off, col)
+        want, wk = oracle.hub_order(off, col)
+        assert k == wk
+        np.testing.assert_array_equal(order, want)
+    with pytest.raises(hy.HytmError):
+        hy.hub_order(np.array([0, 1], np.uint64), np.array([5], np.uint32))  # col >= n
