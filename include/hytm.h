@@ -57,8 +57,19 @@ typedef enum {
    of the component; PAGERANK: float rank.  Unreached vertices hold 0xFFFFFFFF.
    PPR: personalized PageRank from a source s, float: the PageRank step with all of the
    restart mass (1 - pr_damping) at s, from x_0 = e_s, ppr_iterations synchronous steps;
-   mass that reaches a vertex without out-edges leaks, as in PAGERANK. */
-typedef enum { HYTM_BFS = 0, HYTM_SSSP = 1, HYTM_CC = 2, HYTM_PAGERANK = 3, HYTM_PPR = 4 } hytm_algo;
+   mass that reaches a vertex without out-edges leaks, as in PAGERANK.
+   PAGERANK_DELTA: PageRank to convergence by delta accumulation with delta-driven
+   partition priority (Sec. 6.1), float: x = 0 and delta = (1 - d) / n at the start; each
+   iteration folds the pushed deltas in, schedules the partitions whose delta sum is at
+   least the mean over partitions, moves every scheduled vertex's delta into x and pushes
+   d * delta / D_o(v) along its out-edges; with `reprocess`, the scheduled partitions get a
+   second such pass in the same iteration.  It stops when the total pending delta is at
+   most dpr_epsilon (or after dpr_max_iterations) and returns x + delta, within
+   d / (1 - d) * (final total delta) in L1 of the fixed point that PAGERANK's iteration
+   approaches; hytm_run_stats.residual reports that total. */
+typedef enum {
+    HYTM_BFS = 0, HYTM_SSSP = 1, HYTM_CC = 2, HYTM_PAGERANK = 3, HYTM_PPR = 4, HYTM_PAGERANK_DELTA = 5
+} hytm_algo;
 
 /* Transfer policy for partitions that are not resident.  HYBRID applies the cost
    model of Sec. 5.1; the others force one engine for every scheduled partition. */
@@ -107,6 +118,13 @@ typedef struct {
     uint64_t compact_chunk_edges; /* 0 = automatic: edges per compaction chunk */
     uint32_t filter_engine;     /* HYTM_FILTER_STREAM (default) or HYTM_FILTER_COPY, see below */
     uint32_t ppr_iterations;    /* 10: steps of HYTM_PPR (restart mass 1 - pr_damping) */
+    uint32_t reprocess;         /* 0: off.  1: every iteration makes a second pass over the partitions
+                                   it loaded, from the vertices the first pass improved (Sec. 6.1);
+                                   BFS, SSSP, CC and PAGERANK_DELTA, single-source runs only.  The
+                                   results are unchanged (BFS relaxes levels instead of marking
+                                   first visits); iteration counts drop. */
+    uint32_t dpr_max_iterations; /* 10000: cap on PAGERANK_DELTA iterations */
+    double dpr_epsilon;         /* 1e-7: PAGERANK_DELTA stops when the pending delta sums to this */
 } hytm_params;
 
 /* How a FILTER task moves its whole partition range to the GPU.  Both transfer every
@@ -165,6 +183,7 @@ typedef struct {
     double kernel_ms[8];
     uint64_t kernel_launches[8];
     uint64_t kernel_items[8];
+    double residual;            /* PAGERANK_DELTA: total pending delta at the end (else 0) */
 } hytm_run_stats;
 
 /* Kernel classes of hytm_run_stats.kernel_* */

@@ -20,8 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libhytm.so")
 
 OK, E_INVAL, E_RANGE, E_NOMEM, E_BUDGET, E_DEVICE, E_STATE, E_UNSUPPORTED = range(8)
 STATUS_NAMES = ["OK", "E_INVAL", "E_RANGE", "E_NOMEM", "E_BUDGET", "E_DEVICE", "E_STATE", "E_UNSUPPORTED"]
-ALGOS = {"bfs": 0, "sssp": 1, "cc": 2, "pagerank": 3, "pr": 3, "ppr": 4}
-FLOAT_ALGOS = (3, 4)
+ALGOS = {"bfs": 0, "sssp": 1, "cc": 2, "pagerank": 3, "pr": 3, "ppr": 4, "pagerank_delta": 5, "dpr": 5}
+FLOAT_ALGOS = (3, 4, 5)
 MODES = {"hybrid": 0, "filter": 1, "compact": 2, "zerocopy": 3}
 P_NONE, P_RESIDENT, P_FILTER, P_ZEROCOPY, P_COMPACT = range(5)
 ENGINE_NAMES = ["none", "resident", "filter", "zerocopy", "compact"]
@@ -48,7 +48,8 @@ class Params(ctypes.Structure):
         ("index_bytes", ctypes.c_uint32), ("pr_iterations", ctypes.c_uint32), ("pr_damping", ctypes.c_double),
         ("streams", ctypes.c_uint32), ("gather_threads", ctypes.c_uint32),
         ("compact_chunk_edges", ctypes.c_uint64), ("filter_engine", ctypes.c_uint32),
-        ("ppr_iterations", ctypes.c_uint32),
+        ("ppr_iterations", ctypes.c_uint32), ("reprocess", ctypes.c_uint32),
+        ("dpr_max_iterations", ctypes.c_uint32), ("dpr_epsilon", ctypes.c_double),
     ]
 
 
@@ -75,7 +76,7 @@ class RunStats(ctypes.Structure):
         ("iters_written", ctypes.c_uint32), ("mode_trace", ctypes.POINTER(ctypes.c_uint8)),
         ("mode_trace_cap", ctypes.c_uint64), ("time_kernels", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
         ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_uint64 * 8),
-        ("kernel_items", ctypes.c_uint64 * 8),
+        ("kernel_items", ctypes.c_uint64 * 8), ("residual", ctypes.c_double),
     ]
 
 

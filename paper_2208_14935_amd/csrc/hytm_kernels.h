@@ -18,7 +18,12 @@ constexpr int SEG_R = 0, SEG_F = 1, SEG_Z = 2, SEG_C = 3;
 
 // ALGO_MBFS / ALGO_MSSSP: up to 64 sources at once, one bit / value lane per source.
 // ALGO_MPPR: personalized PageRank, one value lane per source.
-enum Algo : int { ALGO_BFS = 0, ALGO_SSSP = 1, ALGO_CC = 2, ALGO_PR = 3, ALGO_MBFS = 4, ALGO_MSSSP = 5, ALGO_MPPR = 6 };
+// ALGO_BFS_RELAX: BFS by level relaxation (lvl[v] = min(lvl[v], lvl[u] + 1)), exact under
+// the asynchronous reprocessing that first-visit marking would get wrong.
+enum Algo : int {
+    ALGO_BFS = 0, ALGO_SSSP = 1, ALGO_CC = 2, ALGO_PR = 3, ALGO_MBFS = 4, ALGO_MSSSP = 5, ALGO_MPPR = 6,
+    ALGO_BFS_RELAX = 7
+};
 constexpr uint32_t MAX_LANES = 64;
 
 // Sources of a batched run, passed by value to the init kernel.
@@ -183,6 +188,22 @@ __host__ __device__ inline uint64_t acc_slots(uint64_t n) { return (n + 4095) & 
 hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
                              hipStream_t st);
 hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, hipStream_t st);
+
+// Reprocessing (Sec. 6.1): cur2 <- the vertices of next that lie in partitions whose mode
+// is not NONE (the partitions loaded by the pass that just ran).  Clears cur2 first.
+hipError_t launch_loaded_frontier(uint32_t npart, const uint32_t* pv, const uint8_t* mode, const uint32_t* next,
+                                  uint32_t* cur2, uint32_t nwords, hipStream_t st);
+// Delta-based PageRank.  fold: delta[v] += the accumulator copies of v (then zeroed) and
+// psum[p] = the partition's delta sum (FP64).  activate: in every partition with
+// sched[p] != 0, each vertex with delta > 0 moves delta into x, shares damping * delta /
+// D_o(v) as its contribution and joins the frontier cur (cleared first).
+hipError_t launch_dpr_fold(uint32_t npart, const uint32_t* pv, uint64_t n, float* acc, float* delta, double* psum,
+                           hipStream_t st);
+hipError_t launch_dpr_activate(uint32_t npart, const uint32_t* pv, const uint64_t* off, const uint8_t* sched,
+                               float* delta, float* x, float* contrib, uint32_t* cur, uint32_t nwords, float damping,
+                               hipStream_t st);
+// x[v] += delta[v] for every v (the pending mass, after a final fold).
+hipError_t launch_dpr_finish(uint64_t n, float* x, const float* delta, hipStream_t st);
 
 // Probes of the host link and HBM.  words_per_line in {8, 16, 32}: each 128-byte line
 // of the mapped buffer contributes that many leading 4-byte words; 0 = stream the whole

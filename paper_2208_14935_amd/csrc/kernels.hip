@@ -358,6 +358,21 @@ struct OpSssp {
     }
 };
 
+struct OpBfsRelax {
+    static constexpr bool wave = false;
+    static constexpr bool weighted = false;
+    uint32_t* lvl;
+    uint32_t* next;
+    __device__ __forceinline__ uint32_t src(uint32_t u) const { return lvl[u]; }
+    __device__ __forceinline__ void push(uint32_t lu, uint32_t v, uint32_t) const {
+        const uint32_t nl = lu + 1;
+        if (nl < lvl[v]) {
+            const uint32_t old = atomicMin(lvl + v, nl);
+            if (nl < old) atomicOr(next + (v >> 5), 1u << (v & 31));
+        }
+    }
+};
+
 struct OpCc {
     static constexpr bool wave = false;
     static constexpr bool weighted = false;
@@ -721,7 +736,7 @@ __global__ void k_init(AlgoState s, uint64_t n, uint32_t source, float x0, float
     }
     for (uint64_t wi = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; wi < nwords; wi += stride) {
         uint32_t c;
-        if (s.algo == ALGO_BFS || s.algo == ALGO_SSSP) {
+        if (s.algo == ALGO_BFS || s.algo == ALGO_SSSP || s.algo == ALGO_BFS_RELAX) {
             c = (wi == (source >> 5)) ? (1u << (source & 31)) : 0u;
         } else {
             const uint64_t lo = wi << 5;
@@ -815,6 +830,69 @@ __global__ __launch_bounds__(256) void k_extract_lanes(const uint32_t* __restric
             out[(uint64_t)k * n + (order ? order[v0 + i] : v0 + i)] = x;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_loaded_frontier(uint32_t npart, const uint32_t* __restrict__ pv,
+                                                         const uint8_t* __restrict__ mode,
+                                                         const uint32_t* __restrict__ next, uint32_t* __restrict__ cur2) {
+    for (uint32_t p = blockIdx.x; p < npart; p += gridDim.x) {
+        if (mode[p] == P_NONE) continue;  // uniform across the workgroup
+        for (uint32_t v = pv[p] + threadIdx.x; v < pv[p + 1]; v += blockDim.x)
+            if ((next[v >> 5] >> (v & 31)) & 1) atomicOr(cur2 + (v >> 5), 1u << (v & 31));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dpr_fold(uint32_t npart, const uint32_t* __restrict__ pv, uint64_t n,
+                                                  float* __restrict__ acc, float* __restrict__ delta,
+                                                  double* __restrict__ psum) {
+    __shared__ double s_w[4];
+    const uint64_t slots = acc_slots(n);
+    for (uint32_t p = blockIdx.x; p < npart; p += gridDim.x) {
+        double sum = 0.0;
+        for (uint32_t v = pv[p] + threadIdx.x; v < pv[p + 1]; v += blockDim.x) {
+            const uint32_t sl = acc_slot(v);
+            float d = delta[v];
+#pragma unroll
+            for (uint32_t c = 0; c < ACC_COPIES; c++) {
+                d += acc[c * slots + sl];
+                acc[c * slots + sl] = 0.0f;
+            }
+            delta[v] = d;
+            sum += (double)d;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = sum;
+        __syncthreads();
+        if (threadIdx.x == 0) psum[p] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dpr_activate(uint32_t npart, const uint32_t* __restrict__ pv,
+                                                      const uint64_t* __restrict__ off,
+                                                      const uint8_t* __restrict__ sched, float* __restrict__ delta,
+                                                      float* __restrict__ x, float* __restrict__ contrib,
+                                                      uint32_t* __restrict__ cur, float damping) {
+    for (uint32_t p = blockIdx.x; p < npart; p += gridDim.x) {
+        if (!sched[p]) continue;  // uniform across the workgroup
+        for (uint32_t v = pv[p] + threadIdx.x; v < pv[p + 1]; v += blockDim.x) {
+            const float d = delta[v];
+            if (!(d > 0.0f)) continue;
+            x[v] += d;
+            delta[v] = 0.0f;
+            const uint64_t deg = off[v + 1] - off[v];
+            if (deg) {
+                contrib[v] = damping * d / (float)deg;
+                atomicOr(cur + (v >> 5), 1u << (v & 31));
+            }
+        }
+    }
+}
+
+__global__ void k_dpr_finish(uint64_t n, float* __restrict__ x, const float* __restrict__ delta) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+        x[v] += delta[v];
 }
 
 __global__ void k_gather_u32(const uint32_t* __restrict__ src, const uint32_t* __restrict__ rank, uint64_t n,
@@ -1093,6 +1171,37 @@ hipError_t launch_extract_lanes(const uint32_t* vals, uint64_t n, uint32_t lshif
     return hipGetLastError();
 }
 
+hipError_t launch_loaded_frontier(uint32_t npart, const uint32_t* pv, const uint8_t* mode, const uint32_t* next,
+                                  uint32_t* cur2, uint32_t nwords, hipStream_t st) {
+    hipError_t e = launch_fill_u32(cur2, nwords, 0u, st);
+    if (e != hipSuccess || !npart) return e;
+    k_loaded_frontier<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, mode, next, cur2);
+    return hipGetLastError();
+}
+
+hipError_t launch_dpr_fold(uint32_t npart, const uint32_t* pv, uint64_t n, float* acc, float* delta, double* psum,
+                           hipStream_t st) {
+    if (!npart) return hipSuccess;
+    k_dpr_fold<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, n, acc, delta, psum);
+    return hipGetLastError();
+}
+
+hipError_t launch_dpr_activate(uint32_t npart, const uint32_t* pv, const uint64_t* off, const uint8_t* sched,
+                               float* delta, float* x, float* contrib, uint32_t* cur, uint32_t nwords, float damping,
+                               hipStream_t st) {
+    hipError_t e = launch_fill_u32(cur, nwords, 0u, st);
+    if (e != hipSuccess || !npart) return e;
+    k_dpr_activate<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, off, sched, delta, x, contrib,
+                                                                         cur, damping);
+    return hipGetLastError();
+}
+
+hipError_t launch_dpr_finish(uint64_t n, float* x, const float* delta, hipStream_t st) {
+    if (!n) return hipSuccess;
+    k_dpr_finish<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, x, delta);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* rank, uint64_t n, uint32_t* dst, hipStream_t st) {
     if (!n) return hipSuccess;
     k_gather_u32<<<grid_for(n, 256, 8192), 256, 0, st>>>(src, rank, n, dst);
@@ -1197,6 +1306,9 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
     case ALGO_CC:
         return push_edges_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
                              compacted, st);
+    case ALGO_BFS_RELAX:
+        return push_edges_op(OpBfsRelax{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
+                             compacted, st);
     case ALGO_MBFS:
         return push_edges_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next, s.lshift}, list, wpre, ja, jb,
                              item_lo, item_hi, off, col, w, shift, compacted, st);
@@ -1234,6 +1346,8 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
                              st);
     case ALGO_CC:
         return push_lines_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
+    case ALGO_BFS_RELAX:
+        return push_lines_op(OpBfsRelax{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
     case ALGO_MBFS:
         return push_lines_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next, s.lshift}, list, wpre, ja, jb,
                              item_lo, item_hi, off, col, w, st);
@@ -1276,6 +1390,8 @@ hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t 
         return push_fstream_op(OpSssp{s.val, s.next, s.overflow}, tasks, ntasks, total_chunks, list, off, col, w, st);
     case ALGO_CC:
         return push_fstream_op(OpCc{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, st);
+    case ALGO_BFS_RELAX:
+        return push_fstream_op(OpBfsRelax{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, st);
     case ALGO_MBFS:
         return push_fstream_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next, s.lshift}, tasks, ntasks,
                                total_chunks, list, off, col, w, st);

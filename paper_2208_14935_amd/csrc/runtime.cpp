@@ -206,6 +206,12 @@ struct hytm_graph {
     DevBuf<uint32_t> d_lval;
     DevBuf<float> d_lx, d_lacc;   // batched PPR: x and accumulator rows
     DevBuf<uint32_t> d_xout;      // lanes extracted for the copy back
+    DevBuf<uint32_t> d_cur2;      // frontier of the reprocessing pass
+    DevBuf<float> d_delta;        // delta-based PageRank: pending delta per vertex
+    DevBuf<double> d_psum;        // ... and per partition
+    HostBuf<double> h_psum;
+    DevBuf<uint8_t> d_sched;      // ... partitions scheduled this iteration
+    HostBuf<uint8_t> h_sched;
     HostBuf<uint64_t> h_lanes;
 
     // host mirrors of the per-iteration selection
@@ -261,6 +267,8 @@ bool params_valid(const hytm_params& p, std::string* why) {
     if (p.max_outstanding == 0) return bad("max_outstanding must be > 0");
     if (p.index_bytes > 64) return bad("index_bytes must be <= 64");
     if (!(p.pr_damping >= 0.0 && p.pr_damping <= 1.0)) return bad("pr_damping must be in [0, 1]");
+    if (p.reprocess > 1) return bad("reprocess must be 0 or 1");
+    if (!(p.dpr_epsilon >= 0.0)) return bad("dpr_epsilon must be >= 0");
     if (p.streams < 2 || p.streams > kMaxSlots) return bad("streams must be in 2..16");
     if (p.gather_threads > 256) return bad("gather_threads must be <= 256");
     if (p.filter_engine != HYTM_FILTER_STREAM && p.filter_engine != HYTM_FILTER_COPY)
@@ -439,6 +447,12 @@ void release_all(hytm_graph* g) {
     g->d_lx.release();
     g->d_lacc.release();
     g->d_xout.release();
+    g->d_cur2.release();
+    g->d_delta.release();
+    g->d_psum.release();
+    g->h_psum.release();
+    g->d_sched.release();
+    g->h_sched.release();
     g->d_rank.release();
     g->d_order.release();
     g->d_minold.release();
@@ -523,6 +537,7 @@ struct RunCtx {
     uint32_t *cur = nullptr, *nxt = nullptr;   // frontier bitmaps (union over lanes)
     uint64_t *mcur = nullptr, *mnxt = nullptr; // lane masks
     LaneSet ppr{};                             // PPR lanes stepping, restarted at their sources
+    bool reprocess = false;                    // second pass over loaded partitions (Sec. 6.1)
     uint32_t t = 0;                            // iterations taken
     Totals tot;
 };
@@ -694,11 +709,13 @@ void init_ctx(RunCtx& rc, hytm_graph* g, int algo, bool batched, const Plan& pl,
     rc.as.overflow = g->d_overflow.p;
 }
 
-// One iteration of a traversal (Algorithm 1 plus the engines of Sec. 6.2).  *lanes_out:
-// batched runs: the lanes with a non-empty frontier at the start of the iteration.
-// *empty_out: BFS/SSSP/CC only: the frontier was empty, nothing was pushed and the
-// traversal is over.
-hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* empty_out) {
+// One engine pass over the frontier `cur` (Algorithm 1 plus the engines of Sec. 6.2),
+// joined into `main`.  *hout: the pass's selection header.  With lanes != null, *lanes =
+// the union of the lane masks rc.mcur.  With stop_if_empty and an empty frontier, nothing
+// is pushed.  Transfer and activity counts are added to *rec; trace_t >= 0 records the
+// engine choice in the caller's mode trace.
+hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Header* hout, uint64_t* lanes,
+                        bool stop_if_empty, hytm_iter_stats* rec, int64_t trace_t) {
     hytm_graph* g = rc.g;
     KTimer& kt = g->timer;
     AlgoState& as = rc.as;
@@ -707,18 +724,10 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
     const Plan& pl = rc.plan;
     const bool fstream = g->params.filter_engine == HYTM_FILTER_STREAM;
     const uint64_t d1b = 4ull * rc.arrays;
-    const uint32_t t = rc.t;
-    const bool fixed_steps = rc.algo == HYTM_PAGERANK || rc.algo == HYTM_PPR;
-    const double t_it = now_ms();
-    if (rc.algo == HYTM_PAGERANK)
-        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
-            return launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, main);
-        }));
-    if (rc.algo == HYTM_PPR)
-        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_ppr_prepare(as, g->d_off.p, main); }));
+    const double t_sel = now_ms();
     // 1. statistics, engine selection, active lists (Algorithm 1, GPU part)
     HIP_CHECK(kt.run(HYTM_K_STATS, npart, main, [&] {
-        return launch_stats_select(npart, g->d_pv.p, g->d_off.p, rc.cur, rc.sp, g->d_mode.p, g->d_nA.p, g->d_nF.p,
+        return launch_stats_select(npart, g->d_pv.p, g->d_off.p, cur, rc.sp, g->d_mode.p, g->d_nA.p, g->d_nF.p,
                                    g->d_Ea.p, g->d_Rq.p, g->d_K.p, main);
     }));
     HIP_CHECK(kt.run(HYTM_K_SCAN, npart, main, [&] {
@@ -726,7 +735,7 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
                            g->d_wbase.p, g->d_hdr.p, g->d_wpre.p, main);
     }));
     HIP_CHECK(kt.run(HYTM_K_LISTS, npart, main, [&] {
-        return launch_build_lists(npart, g->d_pv.p, g->d_off.p, rc.cur, g->d_mode.p, g->d_lbase.p, g->d_wbase.p,
+        return launch_build_lists(npart, g->d_pv.p, g->d_off.p, cur, g->d_mode.p, g->d_lbase.p, g->d_wbase.p,
                                   g->d_list.p, g->d_wpre.p, main);
     }));
     // 2. selection back to the host (Algorithm 1: copy Vc, p and A to host)
@@ -734,7 +743,7 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
     HIP_CHECK(hipMemcpyAsync(g->h_mode.p, g->d_mode.p, npart, hipMemcpyDeviceToHost, main));
     HIP_CHECK(hipMemcpyAsync(g->h_lbase.p, g->d_lbase.p, npart * sizeof(uint32_t), hipMemcpyDeviceToHost, main));
     HIP_CHECK(hipMemcpyAsync(g->h_wbase.p, g->d_wbase.p, npart * sizeof(uint64_t), hipMemcpyDeviceToHost, main));
-    if (rc.batched) {
+    if (lanes) {
         // which lanes have a non-empty frontier this iteration
         HIP_CHECK(launch_fill_u32((uint32_t*)g->d_lanes.p, 2, 0u, main));
         HIP_CHECK(launch_lane_union(rc.mcur, n, (unsigned long long*)g->d_lanes.p, main));
@@ -744,29 +753,24 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
     Totals& tt = rc.tot;
     tt.d2h += sizeof(Header) + npart * (1 + 4 + 8);
     const Header h = *g->h_hdr.p;
-    tt.select_ms += now_ms() - t_it;
-    *lanes_out = rc.batched ? *g->h_lanes.p : 0;
-    *empty_out = false;
-    if (!fixed_steps && h.frontier == 0) {
-        *empty_out = true;
-        return HYTM_OK;
-    }
-    tt.iters++;
+    *hout = h;
+    tt.select_ms += now_ms() - t_sel;
+    if (lanes) *lanes = *g->h_lanes.p;
+    if (stop_if_empty && h.frontier == 0) return HYTM_OK;
 
-    // per-iteration bookkeeping
-    hytm_iter_stats rec{};
-    rec.parts[0] = npart;
+    // bookkeeping of the pass
+    uint32_t scheduled = 0;
     for (int s = 0; s < NSEG; s++) {
-        rec.parts[s + 1] = h.seg_parts[s];
-        rec.parts[0] -= h.seg_parts[s];
+        rec->parts[s + 1] += h.seg_parts[s];
+        scheduled += h.seg_parts[s];
     }
-    rec.active_vertices = h.total_active;
-    for (int s = 0; s < NSEG; s++) rec.active_edges += h.seg_edges[s];
+    rec->parts[0] += npart - scheduled;
+    rec->active_vertices += h.total_active;
+    for (int s = 0; s < NSEG; s++) rec->active_edges += h.seg_edges[s];
     hytm_run_stats* stats = rc.stats;
-    if (stats && stats->mode_trace && (uint64_t)(t + 1) * npart <= stats->mode_trace_cap)
-        memcpy(stats->mode_trace + (uint64_t)t * npart, g->h_mode.p, npart);
+    if (trace_t >= 0 && stats && stats->mode_trace && (uint64_t)(trace_t + 1) * npart <= stats->mode_trace_cap)
+        memcpy(stats->mode_trace + (uint64_t)trace_t * npart, g->h_mode.p, npart);
 
-    as.level_next = t + 1;
     // resident partitions: no transfer
     if (h.seg_list_count[SEG_R])
         HIP_CHECK(kt.run(HYTM_K_PUSH_RES, h.seg_work_total[SEG_R], main, [&] {
@@ -783,7 +787,7 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
                                      h.seg_work_start[SEG_Z] + h.seg_work_total[SEG_Z], g->d_off.p, g->d_col_map,
                                      g->d_w_map, g->s_zc);
         }));
-        rec.zc_lines = h.seg_work_total[SEG_Z];
+        rec->zc_lines += h.seg_work_total[SEG_Z];
     }
     // compaction: gathered by host threads, overlapping the filter tasks below
     std::thread cthread;
@@ -796,6 +800,7 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
                               &c_bytes, &c_d2h, &cst, &cmsg);
     // filter: combine runs of <= k consecutive partitions (Sec. 5.2), then copy+push
     hytm_status fst = HYTM_OK;
+    uint64_t f_bytes = 0;
     try {
         if (h.seg_list_count[SEG_F]) {
             const uint32_t k = g->params.combine_k;
@@ -826,7 +831,7 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
                 const uint64_t wa = g->h_wbase.p[i];
                 const uint64_t wb = nx < npart ? g->h_wbase.p[nx] : fend_work;
                 const uint64_t ebeg = g->h_off[g->pv[i]];
-                rec.bytes_filter += edges * d1b;
+                f_bytes += edges * d1b;
                 if (fstream) {
                     FTask& ft = g->h_tasks.p[gidx++];
                     ft.e0 = ebeg;
@@ -856,15 +861,15 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
                 i = j;
             }
             if (fstream && gidx) {
-                // one launch streams every filter task of the iteration
+                // one launch streams every filter task of the pass
                 HIP_CHECK(hipMemcpyAsync(g->d_tasks.p, g->h_tasks.p, gidx * sizeof(FTask), hipMemcpyHostToDevice,
                                          g->s_fk));
-                HIP_CHECK(kt.run(HYTM_K_PUSH_F, rec.bytes_filter / d1b, g->s_fk, [&] {
+                HIP_CHECK(kt.run(HYTM_K_PUSH_F, f_bytes / d1b, g->s_fk, [&] {
                     return launch_push_fstream(as, g->d_tasks.p, gidx, chunks, g->d_list.p, g->d_off.p,
                                                g->d_col_map, g->d_w_map, g->s_fk);
                 }));
             }
-            rec.filter_tasks = gidx;
+            rec->filter_tasks += gidx;
         }
     } catch (const HipError& e) {
         fst = e.status;
@@ -875,7 +880,8 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
         g_err = cmsg;
         return cst;
     }
-    rec.bytes_compact = c_bytes;
+    rec->bytes_filter += f_bytes;
+    rec->bytes_compact += c_bytes;
     tt.d2h += c_d2h;
     tt.cchunks += c_chunks;
     // 3. join every engine into the main stream
@@ -883,6 +889,66 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
     HIP_CHECK(hipEventRecord(g->ev_join[1], g->s_zc));
     HIP_CHECK(hipEventRecord(g->ev_join[2], g->s_c));
     for (int q = 0; q < 3; q++) HIP_CHECK(hipStreamWaitEvent(main, g->ev_join[q], 0));
+    return HYTM_OK;
+}
+
+// Fold one iteration's record into the traversal's totals and the caller's stats.
+void record_iteration(RunCtx& rc, hytm_iter_stats& rec, uint32_t t, double t_it) {
+    Totals& tt = rc.tot;
+    for (int s = 0; s < 5; s++) tt.part_iters[s] += rec.parts[s];
+    tt.av += rec.active_vertices;
+    tt.ae += rec.active_edges;
+    tt.bf += rec.bytes_filter;
+    tt.bc += rec.bytes_compact;
+    tt.zcl += rec.zc_lines;
+    tt.ftasks += rec.filter_tasks;
+    rec.ms = now_ms() - t_it;
+    hytm_run_stats* stats = rc.stats;
+    if (stats && stats->iters && t < stats->iters_cap) {
+        stats->iters[t] = rec;
+        stats->iters_written = t + 1;
+    }
+}
+
+// One iteration of a traversal.  *lanes_out: batched runs: the lanes with a non-empty
+// frontier at the start of the iteration.  *empty_out: BFS/SSSP/CC only: the frontier was
+// empty, nothing was pushed and the traversal is over.
+hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* empty_out) {
+    hytm_graph* g = rc.g;
+    KTimer& kt = g->timer;
+    AlgoState& as = rc.as;
+    const uint64_t n = g->n;
+    const uint32_t t = rc.t;
+    const bool fixed_steps = rc.algo == HYTM_PAGERANK || rc.algo == HYTM_PPR;
+    const double t_it = now_ms();
+    if (rc.algo == HYTM_PAGERANK)
+        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
+            return launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, main);
+        }));
+    if (rc.algo == HYTM_PPR)
+        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_ppr_prepare(as, g->d_off.p, main); }));
+    as.level_next = t + 1;
+    hytm_iter_stats rec{};
+    Header h;
+    *lanes_out = 0;
+    *empty_out = false;
+    hytm_status st = engine_pass(rc, rc.cur, main, &h, rc.batched ? lanes_out : nullptr, !fixed_steps, &rec, t);
+    if (st != HYTM_OK) return st;
+    if (!fixed_steps && h.frontier == 0) {
+        *empty_out = true;
+        return HYTM_OK;
+    }
+    rc.tot.iters++;
+    if (rc.reprocess) {
+        // Sec. 6.1: the partitions just loaded are processed once more, from the vertices
+        // the first pass improved; those stay in the next frontier
+        HIP_CHECK(kt.run(HYTM_K_OTHER, g->npart, main, [&] {
+            return launch_loaded_frontier(g->npart, g->d_pv.p, g->d_mode.p, rc.nxt, g->d_cur2.p, rc.nwords, main);
+        }));
+        Header h2;
+        st = engine_pass(rc, g->d_cur2.p, main, &h2, nullptr, true, &rec, -1);
+        if (st != HYTM_OK) return st;
+    }
     if (rc.algo == HYTM_PAGERANK) {
         const float base = (float)((1.0 - g->params.pr_damping) / (double)n);
         const float d = (float)g->params.pr_damping;
@@ -906,19 +972,58 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
                              [&] { return launch_fill_u32((uint32_t*)rc.mnxt, 2 * n, 0u, main); }));
         }
     }
-    for (int s = 0; s < 5; s++) tt.part_iters[s] += rec.parts[s];
-    tt.av += rec.active_vertices;
-    tt.ae += rec.active_edges;
-    tt.bf += rec.bytes_filter;
-    tt.bc += rec.bytes_compact;
-    tt.zcl += rec.zc_lines;
-    tt.ftasks += rec.filter_tasks;
-    rec.ms = now_ms() - t_it;
-    if (stats && stats->iters && t < stats->iters_cap) {
-        stats->iters[t] = rec;
-        stats->iters_written = t + 1;
-    }
+    record_iteration(rc, rec, t, t_it);
     rc.t++;
+    return HYTM_OK;
+}
+
+// Delta-based PageRank to convergence (Sec. 6.1, delta-driven priority): one iteration
+// folds the pushed deltas in, reads the per-partition delta sums, schedules the partitions
+// at or above the mean and pushes their vertices' deltas (twice with reprocessing).
+// Returns the final total delta in *residual; x holds x + delta on return.
+hytm_status run_delta_pagerank(RunCtx& rc, hipStream_t main, double* residual) {
+    hytm_graph* g = rc.g;
+    KTimer& kt = g->timer;
+    const uint64_t n = g->n;
+    const uint32_t npart = g->npart;
+    const float d = (float)g->params.pr_damping;
+    const uint32_t passes = rc.reprocess ? 2 : 1;
+    double total = 0;
+    for (;;) {
+        const double t_it = now_ms();
+        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
+            return launch_dpr_fold(npart, g->d_pv.p, n, g->d_acc.p, g->d_delta.p, g->d_psum.p, main);
+        }));
+        HIP_CHECK(hipMemcpyAsync(g->h_psum.p, g->d_psum.p, npart * sizeof(double), hipMemcpyDeviceToHost, main));
+        HIP_CHECK(hipStreamSynchronize(main));
+        rc.tot.d2h += npart * sizeof(double);
+        total = 0;
+        for (uint32_t p = 0; p < npart; p++) total += g->h_psum.p[p];
+        if (!(total > g->params.dpr_epsilon) || rc.t >= g->params.dpr_max_iterations) break;
+        // delta-driven priority: the partitions holding at least the mean pending delta
+        const double mean = total / npart;
+        for (uint32_t p = 0; p < npart; p++) g->h_sched.p[p] = g->h_psum.p[p] > 0 && g->h_psum.p[p] >= mean;
+        HIP_CHECK(hipMemcpyAsync(g->d_sched.p, g->h_sched.p, npart, hipMemcpyHostToDevice, main));
+        hytm_iter_stats rec{};
+        for (uint32_t pass = 0; pass < passes; pass++) {
+            if (pass)
+                HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
+                    return launch_dpr_fold(npart, g->d_pv.p, n, g->d_acc.p, g->d_delta.p, g->d_psum.p, main);
+                }));
+            HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
+                return launch_dpr_activate(npart, g->d_pv.p, g->d_off.p, g->d_sched.p, g->d_delta.p, g->d_x.p,
+                                           g->d_contrib.p, rc.cur, rc.nwords, d, main);
+            }));
+            Header h;
+            hytm_status st = engine_pass(rc, rc.cur, main, &h, nullptr, true, &rec, pass ? -1 : (int64_t)rc.t);
+            if (st != HYTM_OK) return st;
+        }
+        rc.tot.iters++;
+        record_iteration(rc, rec, rc.t, t_it);
+        rc.t++;
+    }
+    HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_dpr_finish(n, g->d_x.p, g->d_delta.p, main); }));
+    *residual = total;
     return HYTM_OK;
 }
 
@@ -987,13 +1092,24 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     // vertex-associated device state (outside the budget)
     g->d_cur.ensure(nwords);
     g->d_next.ensure(nwords);
+    rc.reprocess = g->params.reprocess && !batched &&
+                   (algo == HYTM_BFS || algo == HYTM_SSSP || algo == HYTM_CC || algo == HYTM_PAGERANK_DELTA);
+    const bool pr_like = algo == HYTM_PAGERANK || algo == HYTM_PAGERANK_DELTA;
     if (!batched) g->d_val.ensure(n);
-    if (algo == HYTM_BFS && !batched) g->d_visited.ensure(nwords);
-    if (algo == HYTM_PAGERANK) {
+    if (algo == HYTM_BFS && !batched && !rc.reprocess) g->d_visited.ensure(nwords);
+    if (pr_like) {
         g->d_x.ensure(n);
         g->d_contrib.ensure(n);
         g->d_acc.ensure(ACC_COPIES * acc_slots(n));
     }
+    if (algo == HYTM_PAGERANK_DELTA) {
+        g->d_delta.ensure(n);
+        g->d_psum.ensure(g->npart);
+        g->h_psum.ensure(g->npart);
+        g->d_sched.ensure(g->npart);
+        g->h_sched.ensure(g->npart);
+    }
+    if (rc.reprocess) g->d_cur2.ensure(nwords);
     if (batched) {
         g->d_mcur.ensure(n);
         g->d_mnext.ensure(n);
@@ -1007,10 +1123,13 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     }
 
     AlgoState& as = rc.as;
-    as.algo = batched ? (algo == HYTM_BFS ? ALGO_MBFS : algo == HYTM_SSSP ? ALGO_MSSSP : ALGO_MPPR) : (int)algo;
+    as.algo = batched                                   ? (algo == HYTM_BFS ? ALGO_MBFS : algo == HYTM_SSSP ? ALGO_MSSSP : ALGO_MPPR)
+              : algo == HYTM_PAGERANK_DELTA              ? ALGO_PR
+              : (algo == HYTM_BFS && rc.reprocess)       ? ALGO_BFS_RELAX
+                                                         : (int)algo;
     as.val = g->d_val.p;
-    as.visited = (algo == HYTM_BFS && !batched) ? g->d_visited.p : nullptr;
-    as.next = algo == HYTM_PAGERANK ? nullptr : g->d_next.p;
+    as.visited = (algo == HYTM_BFS && !batched && !rc.reprocess) ? g->d_visited.p : nullptr;
+    as.next = pr_like ? nullptr : g->d_next.p;
     as.acc = g->d_acc.p;
     as.contrib = g->d_contrib.p;
     rc.cur = g->d_cur.p;
@@ -1031,6 +1150,14 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_init_lanes(as, ls, rc.cur, nwords, main); }));
         rc.ppr.mask = lanes == 64 ? ~0ull : (1ull << lanes) - 1;
         for (uint32_t l = 0; l < lanes; l++) rc.ppr.src[l] = ls.src[l];
+    } else if (algo == HYTM_PAGERANK_DELTA) {
+        // x = 0, every vertex holds delta = (1 - d) / n, nothing pushed yet
+        const float d0 = (float)((1.0 - g->params.pr_damping) / (double)n);
+        uint32_t d0_bits;
+        memcpy(&d0_bits, &d0, 4);
+        HIP_CHECK(launch_fill_u32((uint32_t*)g->d_x.p, n, 0u, main));
+        HIP_CHECK(launch_fill_u32((uint32_t*)g->d_delta.p, n, d0_bits, main));
+        HIP_CHECK(launch_fill_u32((uint32_t*)g->d_acc.p, ACC_COPIES * acc_slots(n), 0u, main));
     } else {
         const float x0 = n ? (float)(1.0 / (double)n) : 0.f;
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
@@ -1040,7 +1167,12 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     const uint32_t T = algo == HYTM_PAGERANK ? g->params.pr_iterations
                        : algo == HYTM_PPR    ? g->params.ppr_iterations
                                              : UINT32_MAX;
-    while (rc.t < T) {
+    double residual = 0;
+    if (algo == HYTM_PAGERANK_DELTA) {
+        hytm_status st = run_delta_pagerank(rc, main, &residual);
+        if (st != HYTM_OK) return st;
+    }
+    while (algo != HYTM_PAGERANK_DELTA && rc.t < T) {
         uint64_t active = 0;
         bool empty = false;
         hytm_status st = step_once(rc, main, &active, &empty);
@@ -1064,7 +1196,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         const uint32_t* vals = algo == HYTM_PPR ? (const uint32_t*)g->d_lx.p : g->d_lval.p;
         copy_lanes_out(g, vals, lsh, all, false, outs.data(), main);
     } else {
-        const uint32_t* src = algo == HYTM_PAGERANK ? (const uint32_t*)g->d_x.p : g->d_val.p;
+        const uint32_t* src = pr_like ? (const uint32_t*)g->d_x.p : g->d_val.p;
         if (g->hub_sorted()) {
             // back to the caller's ids (CC: labels become the smallest original id)
             g->d_xout.ensure(n);
@@ -1115,6 +1247,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         stats->ms_total = t_end - t_begin;
         stats->ms_fill = tt.fill_ms;
         stats->ms_select = tt.select_ms;
+        stats->residual = residual;
     }
     return HYTM_OK;
 }
@@ -1425,6 +1558,9 @@ void hytm_default_params(hytm_params* p) {
     p->pr_iterations = 20;
     p->pr_damping = 0.85;
     p->ppr_iterations = 10;
+    p->reprocess = 0;
+    p->dpr_max_iterations = 10000;
+    p->dpr_epsilon = 1e-7;
     p->streams = 4;
     p->gather_threads = 0;
     p->compact_chunk_edges = 0;
@@ -1598,7 +1734,7 @@ hytm_status hytm_staging_bytes(const hytm_graph* g, hytm_algo algo, uint64_t* by
     g_err.clear();
     if (!g || !bytes) return fail(HYTM_E_INVAL, "NULL argument");
     if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
-    if (algo < HYTM_BFS || algo > HYTM_PPR) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
+    if (algo < HYTM_BFS || algo > HYTM_PAGERANK_DELTA) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
     const Staging s = staging_of(g, algo == HYTM_SSSP ? 2 : 1);
     switch (g->params.mode) {
     case HYTM_MODE_FILTER: *bytes = s.f_bytes; break;
@@ -1638,7 +1774,7 @@ hytm_status hytm_run(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
     if (!g) return fail(HYTM_E_INVAL, "graph is NULL");
     if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
     if (!values_out) return fail(HYTM_E_INVAL, "values_out is NULL");
-    if (algo < HYTM_BFS || algo > HYTM_PPR) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
+    if (algo < HYTM_BFS || algo > HYTM_PAGERANK_DELTA) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
     if (stats && stats->struct_size != sizeof(hytm_run_stats))
         return fail(HYTM_E_INVAL, "stats.struct_size mismatch");
     if ((algo == HYTM_BFS || algo == HYTM_SSSP || algo == HYTM_PPR) && source >= g->n)

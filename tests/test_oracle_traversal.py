@@ -381,3 +381,16 @@ def test_ppr_matches_matrix_powers(case):
         p = mul(p)
     want = [w + d ** T * a for w, a in zip(want, p)]
     np.testing.assert_allclose(oracle.ppr(off, col, s, 0.85, T), [float(f) for f in want], rtol=0, atol=1e-15)
+
+
+def test_pagerank_long_run_is_the_linear_solve_fixed_point():
+    # x* = (1-d)/n (I - d P)^-1 1 with P column-substochastic (sinks leak); the step is a
+    # d-contraction in L1, so T = 300 steps are within 2 d^T of it
+    import scipy.sparse.linalg as spla
+    for off, col in (gen.rmat(11, 8, seed=11), gen.er(1500, 6000, seed=2)):
+        n, d = len(off) - 1, 0.85
+        deg = np.diff(off).astype(np.float64)
+        src = np.repeat(np.arange(n), np.diff(off).astype(np.int64))
+        P = sp.csr_matrix((1.0 / deg[src], (col.astype(np.int64), src)), shape=(n, n))
+        xs = spla.spsolve((sp.identity(n) - d * P).tocsc(), np.full(n, (1 - d) / n))
+        assert np.abs(oracle.pagerank(off, col, d, 300) - xs).sum() <= 2 * d ** 300 + 1e-13
