@@ -62,7 +62,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--probe-bytes", type=int, default=1 << 30)
-    ap.add_argument("--workload", default="quarter-budget", choices=["quarter-budget", "batch", "serve", "modes"],
+    ap.add_argument("--workload", default="quarter-budget", choices=["quarter-budget", "batch", "serve", "modes", "multigraph"],
                     help="quarter-budget: the headline step; batch: 64-source BFS/SSSP in one traversal "
                          "against 64 sequential single-source runs; serve: Poisson arrivals of a BFS/SSSP/PPR "
                          "mix through the query server against one query at a time")
@@ -76,6 +76,7 @@ def main():
                     help="modes: absolute device budget for edge data (0 = --budget-frac of each algorithm's bytes)")
     ap.add_argument("--modes", default="filter,compact,zerocopy,hybrid", help="modes: transfer modes to compare")
     ap.add_argument("--queries", type=int, default=200, help="serve: queries in the arrival trace")
+    ap.add_argument("--graphs", type=int, default=32, help="multigraph: R-MAT graphs of scales 16..22")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -83,8 +84,10 @@ def main():
         sys.exit(2)
     algos = args.algos.split(",")
 
-    t0 = time.time()
     gen.set_threads(min(16, os.cpu_count() or 1))
+    if args.workload == "multigraph":
+        return multigraph_workload(args)
+    t0 = time.time()
     if args.graph == "er":
         off, col = gen.er(args.er_vertices, int(args.er_vertices * args.er_degree), seed=7)
     else:
@@ -372,6 +375,65 @@ def modes_workload(args, gname, g, gs, deg, srcs, algos, gamma, probe):
                    else f"{gname}-budget{args.budget_frac:g}-modes", "n": int(g.n), "m": int(g.m),
                    "m_sym": int(gs.m) if gs is not None else None, "source": s, "gamma": list(gamma)},
         "modes": table, "probe": probe,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def multigraph_workload(args):
+    """--graphs seeded R-MAT graphs of uneven size (scales 16..22), device-resident: CC on
+    their symmetrized forms and 20-step PageRank, once as one traversal over the disjoint
+    union (hytm_graph_set_parts) and once graph by graph.  GTEPS counts m_sym per CC run
+    and 20 m per PageRank run."""
+    rng = np.random.default_rng(3200)
+    scales = sorted(int(x) for x in rng.integers(16, 23, size=args.graphs))
+    t0 = time.time()
+    directed = [gen.rmat(s, args.edge_factor, seed=3300 + i) for i, s in enumerate(scales)]
+    sym = [gen.symmetrize(o, c) for o, c in directed]
+    off, col, _, b = gen.disjoint_union(directed)
+    soff, scol, _, sb = gen.disjoint_union(sym)
+    log(f"{args.graphs} graphs, scales {scales}, union n={len(off) - 1} m={len(col)} m_sym={len(scol)}, "
+        f"gen {time.time() - t0:.1f}s")
+    work = 20 * len(col) + len(scol)
+    u = hy.Graph(off, col, check_col=False)
+    us = hy.Graph(soff, scol, symmetric=True, check_col=False)
+    u.set_parts(b)
+    us.set_parts(sb)
+    singles = [(hy.Graph(o, c, check_col=False), hy.Graph(so, sc, symmetric=True, check_col=False))
+               for (o, c), (so, sc) in zip(directed, sym)]
+    u_out = hy.pinned_empty(len(off) - 1, np.float32)
+    us_out = hy.pinned_empty(len(soff) - 1, np.uint32)
+    big = max(len(o) - 1 for o, _ in directed)
+    s_pr, s_cc = hy.pinned_empty(big, np.float32), hy.pinned_empty(big, np.uint32)
+
+    def union_step():
+        u.run("pagerank", out=u_out)
+        us.run("cc", out=us_out)
+
+    def single_step():
+        for gd, gsym in singles:
+            gd.run("pagerank", out=s_pr[: gd.n])
+            gsym.run("cc", out=s_cc[: gsym.n])
+
+    res = {}
+    for name, fn in (("union", union_step), ("one_by_one", single_step)):
+        for _ in range(args.warmup):
+            fn()
+        sync()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        sync()
+        sec = (time.perf_counter() - t) / args.steps
+        res[name] = {"ms": sec * 1e3, "gteps": work / sec / 1e9}
+        log(f"{name}: {sec * 1e3:.1f} ms per CC+PR pass over all graphs")
+    out = {
+        "metric": f"GTEPS of CC + PageRank over {args.graphs} uneven R-MAT graphs in one traversal vs one by one",
+        "value": res["union"]["gteps"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["union"]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 (CC), f32 (PageRank)", "data": "synthetic R-MAT, seeded",
+        "config": {"workload": f"multigraph-{args.graphs}-rmat16to22-resident", "scales": scales,
+                   "n": len(off) - 1, "m": len(col), "m_sym": len(scol)},
+        "multigraph": res, "speedup": res["one_by_one"]["ms"] / res["union"]["ms"],
     }
     print(json.dumps(out), flush=True)
 

@@ -131,6 +131,27 @@ def weights(off: np.ndarray, col: np.ndarray, seed: int, maxw: int = 64) -> np.n
     return w[: len(col)]
 
 
+def disjoint_union(graphs):
+    """One CSR holding graphs [(off, col[, w]), ...] side by side: graph i's vertex v
+    becomes bounds[i] + v.  Returns (off, col, w or None, bounds)."""
+    ns = [len(g[0]) - 1 for g in graphs]
+    bounds = np.concatenate([[0], np.cumsum(ns)]).astype(np.uint64)
+    ms = [len(g[1]) for g in graphs]
+    ebase = np.concatenate([[0], np.cumsum(ms)]).astype(np.uint64)
+    off = np.empty(int(bounds[-1]) + 1, dtype=np.uint64)
+    col = np.empty(int(ebase[-1]), dtype=np.uint32)
+    have_w = all(len(g) > 2 and g[2] is not None for g in graphs)
+    w = np.empty(int(ebase[-1]), dtype=np.uint32) if have_w else None
+    for i, g in enumerate(graphs):
+        b, e = int(bounds[i]), int(ebase[i])
+        off[b:b + ns[i]] = np.asarray(g[0][:-1], dtype=np.uint64) + e
+        col[e:e + ms[i]] = np.asarray(g[1], dtype=np.uint32) + np.uint32(b)
+        if have_w:
+            w[e:e + ms[i]] = g[2]
+    off[-1] = ebase[-1]
+    return off, col, w, bounds
+
+
 def sources(off: np.ndarray, k: int, seed: int) -> np.ndarray:
     """k distinct vertices with out-degree >= 1, uniform, from a seeded counter stream."""
     off = np.ascontiguousarray(off, dtype=np.uint64)

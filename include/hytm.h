@@ -249,6 +249,16 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void *offsets, uint3
 hytm_status hytm_hub_order(uint64_t n, uint64_t m, const void *offsets, uint32_t offset_bytes, const uint32_t *col,
                            uint32_t *order_out, uint64_t *hubs_out);
 
+/* Declare g a disjoint union of `count` graphs, graph i holding vertices
+   [vertex_bounds[i], vertex_bounds[i+1]) (caller ids; count + 1 entries from 0 to n), so
+   that one traversal serves them all: every iteration's kernels balance edges across the
+   graphs, and a graph that has converged simply has no active vertices.  PageRank (and
+   PAGERANK_DELTA) then normalize by each graph's own vertex count, giving every graph
+   the values it would get alone; BFS/SSSP/CC need nothing more (CC labels are the
+   smallest vertex id in the component, in union ids).  count = 0 undoes it.  Errors:
+   E_INVAL (bounds not increasing from 0 to n, an edge leaving its graph). */
+hytm_status hytm_graph_set_parts(hytm_graph *g, uint32_t count, const uint64_t *vertex_bounds);
+
 /* Device budget for edge-associated data: resident partitions + filter staging +
    compaction buffers.  UINT64_MAX (the default) = uncapped: every partition resident.
    Vertex arrays are outside the budget, as in the paper's placement (Sec. 1).  Takes

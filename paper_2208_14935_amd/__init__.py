@@ -112,6 +112,7 @@ _SIGNATURES = {
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "hytm_set_device_budget": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "hytm_graph_set_parts": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]),
     "hytm_hub_order": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "hytm_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params)]),
@@ -301,6 +302,15 @@ class Graph:
 
     def __exit__(self, *exc):
         self.close()
+
+    def set_parts(self, vertex_bounds):
+        """Declare the graph a disjoint union of graphs with these vertex bounds (count + 1
+        entries, 0 .. n); PageRank then normalizes per graph.  None undoes it."""
+        if vertex_bounds is None:
+            _check(load().hytm_graph_set_parts(self._h, 0, None))
+            return
+        b = np.ascontiguousarray(vertex_bounds, dtype=np.uint64)
+        _check(load().hytm_graph_set_parts(self._h, len(b) - 1, _ptr(b)))
 
     def set_budget(self, edge_bytes):
         """Device bytes for edge data (None = uncapped, every partition resident)."""

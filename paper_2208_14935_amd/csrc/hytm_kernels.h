@@ -89,6 +89,7 @@ struct AlgoState {
     float* lx;            // PPR: x of each lane; scaled to x / D_o in place before a push
     float* lacc;          // PPR: per-lane accumulators, zero between iterations
     uint32_t lshift;
+    const float* inv_n;   // PageRank over a union of graphs: 1 / (vertices of v's graph), else null
 };
 
 // PageRank keeps one accumulator copy per XCD; the apply step sums them.
@@ -187,7 +188,12 @@ __host__ __device__ inline uint64_t acc_slots(uint64_t n) { return (n + 4095) & 
 
 hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
                              hipStream_t st);
-hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, hipStream_t st);
+// x = base + damping * (sum of the accumulator copies); with inv_n, the base of v is
+// restart * inv_n[v] (graph-wise normalization of a union of graphs).
+hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, const float* inv_n,
+                           float restart, hipStream_t st);
+// delta[v] = restart * (inv_n ? inv_n[v] : 1 / n): the initial pending mass of delta PageRank.
+hipError_t launch_dpr_init(uint64_t n, float* delta, const float* inv_n, float restart, hipStream_t st);
 
 // Reprocessing (Sec. 6.1): cur2 <- the vertices of next that lie in partitions whose mode
 // is not NONE (the partitions loaded by the pass that just ran).  Clears cur2 first.

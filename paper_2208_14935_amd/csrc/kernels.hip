@@ -728,7 +728,7 @@ __global__ void k_init(AlgoState s, uint64_t n, uint32_t source, float x0, float
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
         if (s.algo == ALGO_PR)
-            x[v] = x0;
+            x[v] = s.inv_n ? s.inv_n[v] : x0;
         else if (s.algo == ALGO_CC)
             s.val[v] = (uint32_t)v;
         else
@@ -890,6 +890,12 @@ __global__ __launch_bounds__(256) void k_dpr_activate(uint32_t npart, const uint
     }
 }
 
+__global__ void k_dpr_init(uint64_t n, float* __restrict__ delta, const float* __restrict__ inv_n, float restart,
+                           float uniform) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+        delta[v] = inv_n ? restart * inv_n[v] : uniform;
+}
+
 __global__ void k_dpr_finish(uint64_t n, float* __restrict__ x, const float* __restrict__ delta) {
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
         x[v] += delta[v];
@@ -1011,7 +1017,7 @@ __global__ void k_pr_prepare(uint64_t n, const uint64_t* __restrict__ off, const
 }
 
 __global__ void k_pr_apply(uint64_t n, float* __restrict__ x, const float* __restrict__ acc, float base,
-                           float damping) {
+                           float damping, const float* __restrict__ inv_n, float restart) {
     const uint64_t slots = acc_slots(n);
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
          v += (uint64_t)gridDim.x * blockDim.x) {
@@ -1019,7 +1025,7 @@ __global__ void k_pr_apply(uint64_t n, float* __restrict__ x, const float* __res
         float sum = 0.0f;
 #pragma unroll
         for (uint32_t c = 0; c < ACC_COPIES; c++) sum += acc[c * slots + s];
-        x[v] = base + damping * sum;
+        x[v] = (inv_n ? restart * inv_n[v] : base) + damping * sum;
     }
 }
 
@@ -1406,9 +1412,16 @@ hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t 
     }
 }
 
-hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, hipStream_t st) {
+hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, const float* inv_n,
+                           float restart, hipStream_t st) {
     if (!n) return hipSuccess;
-    k_pr_apply<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, x, acc, base, damping);
+    k_pr_apply<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, x, acc, base, damping, inv_n, restart);
+    return hipGetLastError();
+}
+
+hipError_t launch_dpr_init(uint64_t n, float* delta, const float* inv_n, float restart, hipStream_t st) {
+    if (!n) return hipSuccess;
+    k_dpr_init<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, delta, inv_n, restart, (float)((double)restart / (double)n));
     return hipGetLastError();
 }
 

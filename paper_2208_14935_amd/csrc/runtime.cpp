@@ -245,6 +245,10 @@ struct hytm_graph {
     std::vector<uint32_t> h_rank;        // caller id -> internal id
     DevBuf<uint32_t> d_rank, d_order;    // caller -> internal, internal -> caller
     DevBuf<uint32_t> d_minold;           // CC label canonicalization scratch
+
+    // a disjoint union of graphs (hytm_graph_set_parts): PageRank per graph
+    std::vector<uint64_t> parts;         // vertex bounds in caller ids, or empty
+    DevBuf<float> d_inv_n;               // per internal vertex: 1 / (vertices of its graph)
     bool hub_sorted() const { return !h_rank.empty(); }
     uint32_t inner(uint32_t v) const { return h_rank.empty() ? v : h_rank[v]; }
 };
@@ -456,6 +460,7 @@ void release_all(hytm_graph* g) {
     g->d_rank.release();
     g->d_order.release();
     g->d_minold.release();
+    g->d_inv_n.release();
     g->h_lanes.release();
     g->d_hdr.release();
     for (uint32_t i = 0; i < kMaxSlots; i++) {
@@ -952,8 +957,10 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
     if (rc.algo == HYTM_PAGERANK) {
         const float base = (float)((1.0 - g->params.pr_damping) / (double)n);
         const float d = (float)g->params.pr_damping;
-        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
-                         [&] { return launch_pr_apply(n, g->d_x.p, g->d_acc.p, base, d, main); }));
+        const float restart = (float)(1.0 - g->params.pr_damping);
+        HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
+            return launch_pr_apply(n, g->d_x.p, g->d_acc.p, base, d, as.inv_n, restart, main);
+        }));
     } else {
         if (rc.algo == HYTM_PPR) {
             const float d = (float)g->params.pr_damping;
@@ -1132,6 +1139,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     as.next = pr_like ? nullptr : g->d_next.p;
     as.acc = g->d_acc.p;
     as.contrib = g->d_contrib.p;
+    as.inv_n = g->d_inv_n.p;  // null unless the graph is a union of graphs
     rc.cur = g->d_cur.p;
     rc.nxt = g->d_next.p;
     if (batched) {
@@ -1151,12 +1159,9 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         rc.ppr.mask = lanes == 64 ? ~0ull : (1ull << lanes) - 1;
         for (uint32_t l = 0; l < lanes; l++) rc.ppr.src[l] = ls.src[l];
     } else if (algo == HYTM_PAGERANK_DELTA) {
-        // x = 0, every vertex holds delta = (1 - d) / n, nothing pushed yet
-        const float d0 = (float)((1.0 - g->params.pr_damping) / (double)n);
-        uint32_t d0_bits;
-        memcpy(&d0_bits, &d0, 4);
+        // x = 0, every vertex holds delta = (1 - d) / n (n of its own graph), nothing pushed yet
         HIP_CHECK(launch_fill_u32((uint32_t*)g->d_x.p, n, 0u, main));
-        HIP_CHECK(launch_fill_u32((uint32_t*)g->d_delta.p, n, d0_bits, main));
+        HIP_CHECK(launch_dpr_init(n, g->d_delta.p, as.inv_n, (float)(1.0 - g->params.pr_damping), main));
         HIP_CHECK(launch_fill_u32((uint32_t*)g->d_acc.p, ACC_COPIES * acc_slots(n), 0u, main));
     } else {
         const float x0 = n ? (float)(1.0 / (double)n) : 0.f;
@@ -1687,6 +1692,51 @@ hytm_status hytm_hub_order(uint64_t n, uint64_t m, const void* offsets, uint32_t
         return fail(HYTM_E_NOMEM, "host allocation failed");
     }
     return HYTM_OK;
+}
+
+hytm_status hytm_graph_set_parts(hytm_graph* g, uint32_t count, const uint64_t* vertex_bounds) {
+    g_err.clear();
+    if (!g) return fail(HYTM_E_INVAL, "graph is NULL");
+    if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
+    if (count == 0) {
+        g->parts.clear();
+        g->d_inv_n.release();
+        return HYTM_OK;
+    }
+    if (!vertex_bounds) return fail(HYTM_E_INVAL, "vertex_bounds is NULL");
+    if (vertex_bounds[0] != 0 || vertex_bounds[count] != g->n)
+        return fail(HYTM_E_INVAL, "vertex_bounds must run from 0 to n = %llu", (unsigned long long)g->n);
+    for (uint32_t i = 0; i < count; i++)
+        if (vertex_bounds[i + 1] <= vertex_bounds[i]) return fail(HYTM_E_INVAL, "graph %u has no vertices", i);
+    return guarded([&]() -> hytm_status {
+        // every edge must stay inside its graph (checked in the held order, mapped back)
+        std::vector<uint32_t> order;
+        if (g->hub_sorted()) {
+            order.resize(g->n);
+            for (uint64_t v = 0; v < g->n; v++) order[g->h_rank[v]] = (uint32_t)v;
+        }
+        auto caller = [&](uint64_t v) -> uint64_t { return order.empty() ? v : order[v]; };
+        auto graph_of = [&](uint64_t v) -> uint32_t {
+            return (uint32_t)(std::upper_bound(vertex_bounds, vertex_bounds + count + 1, v) - vertex_bounds - 1);
+        };
+        std::vector<float> inv(g->n);
+        for (uint64_t v = 0; v < g->n; v++) {
+            const uint64_t cv = caller(v);
+            const uint32_t gi = graph_of(cv);
+            inv[v] = (float)(1.0 / (double)(vertex_bounds[gi + 1] - vertex_bounds[gi]));
+            for (uint64_t e = g->h_off[v]; e < g->h_off[v + 1]; e++) {
+                const uint64_t cu = caller(g->h_col[e]);
+                if (cu < vertex_bounds[gi] || cu >= vertex_bounds[gi + 1])
+                    return fail(HYTM_E_INVAL, "edge %llu -> %llu leaves graph %u", (unsigned long long)cv,
+                                (unsigned long long)cu, gi);
+            }
+        }
+        HIP_CHECK(hipSetDevice(g->device));
+        g->d_inv_n.ensure(g->n);
+        HIP_CHECK(hipMemcpy(g->d_inv_n.p, inv.data(), g->n * sizeof(float), hipMemcpyHostToDevice));
+        g->parts.assign(vertex_bounds, vertex_bounds + count + 1);
+        return HYTM_OK;
+    });
 }
 
 hytm_status hytm_set_device_budget(hytm_graph* g, uint64_t edge_bytes) {

@@ -68,3 +68,16 @@ def test_sources():
     assert len(s) == 8 and len(set(s.tolist())) == 8
     assert (np.diff(off)[s] > 0).all()
     np.testing.assert_array_equal(s, gen.sources(off, 8, 2024))
+
+
+def test_disjoint_union_layout():
+    a = gen.rmat(6, 4, seed=1)
+    b = gen.from_pairs(3, np.array([0, 2], np.uint32), np.array([1, 0], np.uint32))
+    off, col, w, bounds = gen.disjoint_union([a, b])
+    na = len(a[0]) - 1
+    np.testing.assert_array_equal(bounds, [0, na, na + 3])
+    np.testing.assert_array_equal(off[: na + 1], a[0])
+    np.testing.assert_array_equal(col[: len(a[1])], a[1])
+    np.testing.assert_array_equal(off[na:] - off[na], b[0])
+    np.testing.assert_array_equal(col[len(a[1]):], b[1] + na)
+    assert w is None
