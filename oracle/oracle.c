@@ -391,6 +391,7 @@ typedef struct {
     uint32_t alpha_num, alpha_den;  /* 4/5 */
     uint32_t beta_num, beta_den;    /* 2/5 */
     uint32_t gamma_num, gamma_den;  /* 5/8 */
+    uint32_t gather_num, gather_den; /* 0/1: link rate / host gather rate (extension, see below) */
 } orc_cost_params;
 
 /* Engine selection for every partition (Sec. 5.1, Algorithm 1 cost analysis), with
@@ -404,7 +405,12 @@ typedef struct {
    states (the listing's branch order would give zero-copy); a partition with no active
    edge is not scheduled (NONE); the first nres partitions are device-resident and
    need no transfer (RESIDENT).  force: 0 = cost model, else every scheduled partition
-   gets that engine code. */
+   gets that engine code.
+   Extension beyond the paper (its Eq. 2 compute term, which it leaves to future work):
+   with gather = link rate / host gather rate > 0, the host gather of the active edges is
+   priced in the same units, Tgc = ceil(Ea_i * d1 * gather / m / MR), and since gathering
+   and copying run as a pipeline, compaction costs max(Tec, Tgc).  gather = 0 is the
+   paper's rule. */
 void orc_select(uint64_t npart, const uint64_t *E, const uint64_t *nA, const uint64_t *Ea, const uint64_t *Rq,
                 uint64_t nres, const orc_cost_params *cp, int force, unsigned char *p) {
     const u128 L = (u128)cp->line_bytes * cp->max_outstanding;
@@ -418,6 +424,10 @@ void orc_select(uint64_t npart, const uint64_t *E, const uint64_t *nA, const uin
         if (force) { p[i] = (unsigned char)force; continue; }
         rat Tef = rat_make(ceil_div((u128)E[i] * cp->d1, L), 1);
         rat Tec = rat_make(ceil_div((u128)Ea[i] * cp->d1 + (u128)nA[i] * cp->d2, L), 1);
+        if (cp->gather_num) {
+            rat Tgc = rat_make(ceil_div((u128)Ea[i] * cp->d1 * cp->gather_num, L * cp->gather_den), 1);
+            if (rat_lt(Tec, Tgc)) Tec = Tgc;
+        }
         rat RTTzc = rat_add(gamma, rat_mul(one_minus_gamma, rat_make(Ea[i], E[i])));
         rat Tiz = rat_mul(rat_make(ceil_div(Rq[i], cp->max_outstanding), 1), RTTzc);
         if (rat_lt(Tec, rat_mul(alpha, Tef)) && rat_lt(Tec, rat_mul(beta, Tiz)))

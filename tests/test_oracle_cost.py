@@ -202,3 +202,36 @@ def test_gather_matches_slicing():
     np.testing.assert_array_equal(packed, want)
     np.testing.assert_array_equal(np.diff(newoff), np.diff(off)[vc])
     assert newoff[0] == 0
+
+
+def test_select_gather_term_hand_case():
+    # the w3 partition: Ea = 16384 edges, d1 = 4 -> 65536 gathered bytes.  Tec = 3, Tef = 4,
+    # Tiz = 13.  gather = 1 (host gathers as fast as the link): Tgc = ceil(65536/32768) = 2
+    # -> max(3, 2) = 3, still compaction.  gather = 2: Tgc = 4 -> not < 0.8*4 -> the rule
+    # falls through to Tiz < Tef? 13 >= 4 -> filter.
+    E, nA, Ea, Rq = one_partition([4] * 8192, [1] * 4096 + [0] * 4096)
+    base = oracle.CostParams()
+    assert oracle.select(E, nA, Ea, Rq, params=oracle.CostParams(gather=(1, 1)))[0] == COMPACT
+    assert oracle.select(E, nA, Ea, Rq, params=oracle.CostParams(gather=(2, 1)))[0] == FILTER
+    assert oracle.select(E, nA, Ea, Rq, params=oracle.CostParams(gather=(0, 1)))[0] == \
+        oracle.select(E, nA, Ea, Rq, params=base)[0] == COMPACT
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(1, 64), st.integers(1, 16), st.integers(0, 2 ** 32 - 1))
+def test_select_gather_term_only_moves_partitions_off_compaction(gn, gd, seed):
+    # a costlier gather can only turn compaction into filter or zero-copy, never the reverse,
+    # and it never touches a partition that was not compaction
+    rng = np.random.default_rng(seed)
+    npart = 200
+    E = rng.integers(1, 1 << 18, size=npart).astype(np.uint64)
+    Ea = (E * rng.random(npart)).astype(np.uint64)
+    nA = np.minimum(Ea, rng.integers(1, 1 << 12, size=npart)).astype(np.uint64)
+    nA[Ea == 0] = 0
+    Rq = (nA + Ea // 32 + rng.integers(0, 64, size=npart)).astype(np.uint64)
+    a = oracle.select(E, nA, Ea, Rq)
+    b = oracle.select(E, nA, Ea, Rq, params=oracle.CostParams(gather=(gn, gd)))
+    changed = a != b
+    assert (a[changed] == COMPACT).all()
+    assert (b != COMPACT)[changed].all()
+    assert not ((b == COMPACT) & (a != COMPACT)).any()
