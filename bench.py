@@ -77,6 +77,12 @@ def main():
     ap.add_argument("--modes", default="filter,compact,zerocopy,hybrid", help="modes: transfer modes to compare")
     ap.add_argument("--queries", type=int, default=200, help="serve: queries in the arrival trace")
     ap.add_argument("--graphs", type=int, default=32, help="multigraph: R-MAT graphs of scales 16..22")
+    ap.add_argument("--reprocess", action="store_true",
+                    help="second pass over each iteration's loaded partitions (the paper's asynchronous scheduling)")
+    ap.add_argument("--hub-sort", action="store_true", help="relabel hubs to the front when the graphs are loaded")
+    ap.add_argument("--compact-gather", default="off",
+                    help="host-gather term of the compaction cost: 'off' (the paper's rule), 'probe' (link rate / "
+                         "measured gather rate) or num/den")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -106,15 +112,24 @@ def main():
     log(f"probe: {json.dumps(probe)}")
 
     t0 = time.time()
-    g = hy.Graph(off, col, weights=w, check_col=False)
-    gs = hy.Graph(soff, scol, symmetric=True, check_col=False) if scol is not None else None
+    g = hy.Graph(off, col, weights=w, check_col=False, hub_sort=args.hub_sort)
+    gs = hy.Graph(soff, scol, symmetric=True, check_col=False, hub_sort=args.hub_sort) if scol is not None else None
     log(f"pinned graph copies {time.time() - t0:.1f}s")
     gamma = gamma_from(args.gamma, probe)
     log(f"gamma = {gamma[0]}/{gamma[1]}")
+    if args.compact_gather == "off":
+        cgather = (0, 1)
+    elif args.compact_gather == "probe":
+        cgather = (max(1, int(round(64 * probe["h2d_copy_gbps"] / probe["host_gather_gbps"]))), 64)
+    else:
+        a, b_ = args.compact_gather.split("/")
+        cgather = (int(a), int(b_))
+    log(f"compaction gather cost = {cgather[0]}/{cgather[1]}")
     for h in (g, gs):
         if h is not None:
             h.set_params(mode=args.mode, partition_edges=args.partition_edges, combine_k=args.combine_k,
-                         filter_engine=args.filter_engine, gamma=gamma)
+                         filter_engine=args.filter_engine, gamma=gamma, reprocess=int(args.reprocess),
+                         compact_gather=cgather)
     if args.workload == "batch":
         return batch_workload(args, g, off, col, deg, gamma, probe)
     if args.workload == "serve":
@@ -264,11 +279,14 @@ def main():
         "vs_baseline": None,
         "dtype": "u32 (BFS/SSSP/CC), f32 (PageRank)",
         "data": "synthetic R-MAT, seeded",
-        "config": {"workload": f"rmat{args.scale}-ef{args.edge_factor:g}-budget{args.budget_frac:g}-{args.mode}",
+        "config": {"workload": f"rmat{args.scale}-ef{args.edge_factor:g}-budget{args.budget_frac:g}-{args.mode}"
+                               + ("-reprocess" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
+                               + ("" if cgather[0] == 0 else "-gathercost"),
                    "n": n, "m": m, "m_sym": int(gs.m) if gs is not None else None,
                    "sources": [int(s) for s in srcs], "budget_frac_of_edge_bytes": args.budget_frac,
                    "partition_edges": args.partition_edges, "combine_k": args.combine_k, "mode": args.mode,
-                   "filter_engine": args.filter_engine, "gamma": list(gamma), "algos": algos},
+                   "filter_engine": args.filter_engine, "gamma": list(gamma), "algos": algos,
+                   "compact_gather": list(cgather)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "host_link": host_link,

@@ -125,6 +125,11 @@ typedef struct {
                                    first visits); iteration counts drop. */
     uint32_t dpr_max_iterations; /* 10000: cap on PAGERANK_DELTA iterations */
     double dpr_epsilon;         /* 1e-7: PAGERANK_DELTA stops when the pending delta sums to this */
+    uint32_t compact_gather_num, compact_gather_den; /* 0/1: off.  Otherwise the ratio of the
+                                   host link's rate to the host gather's rate: compaction is then
+                                   priced max(Tec, ceil(Ea * d1 * ratio / (m * MR))), the gather of
+                                   Eq. 2 that the paper leaves out (an extension; hytm_link_probe
+                                   measures both rates). */
 } hytm_params;
 
 /* How a FILTER task moves its whole partition range to the GPU.  Both transfer every
@@ -205,6 +210,9 @@ typedef struct {
     double zc_read_gbps[4];     /* kernel reads of mapped pinned memory, useful bytes/s, when each
                                    128-byte line contributes 32, 64, 128 bytes, or whole 256-byte runs */
     double hbm_copy_gbps;       /* device-to-device copy kernel, (read + write) bytes / s */
+    double host_gather_gbps;    /* host threads (as many as the compaction engine uses by default)
+                                   gathering 64-byte runs from random places of pinned memory
+                                   into a pinned buffer: bytes gathered / s */
 } hytm_link_probe_result;
 
 /* Measure the host link and HBM on `hip_device` with `bytes` per transfer (>= 1 MiB).

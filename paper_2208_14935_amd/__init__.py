@@ -50,6 +50,7 @@ class Params(ctypes.Structure):
         ("compact_chunk_edges", ctypes.c_uint64), ("filter_engine", ctypes.c_uint32),
         ("ppr_iterations", ctypes.c_uint32), ("reprocess", ctypes.c_uint32),
         ("dpr_max_iterations", ctypes.c_uint32), ("dpr_epsilon", ctypes.c_double),
+        ("compact_gather_num", ctypes.c_uint32), ("compact_gather_den", ctypes.c_uint32),
     ]
 
 
@@ -86,7 +87,8 @@ KERNEL_CLASSES = ["stats", "scan", "lists", "push_resident", "push_filter", "pus
 
 class LinkProbe(ctypes.Structure):
     _fields_ = [("h2d_copy_gbps", ctypes.c_double), ("d2h_copy_gbps", ctypes.c_double),
-                ("zc_read_gbps", ctypes.c_double * 4), ("hbm_copy_gbps", ctypes.c_double)]
+                ("zc_read_gbps", ctypes.c_double * 4), ("hbm_copy_gbps", ctypes.c_double),
+                ("host_gather_gbps", ctypes.c_double)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -179,7 +181,7 @@ def link_probe(bytes_: int = 1 << 30, device: int = 0) -> dict:
     return {"h2d_copy_gbps": r.h2d_copy_gbps, "d2h_copy_gbps": r.d2h_copy_gbps,
             "zc_read_gbps": {"32B": r.zc_read_gbps[0], "64B": r.zc_read_gbps[1], "128B": r.zc_read_gbps[2],
                              "stream": r.zc_read_gbps[3]},
-            "hbm_copy_gbps": r.hbm_copy_gbps}
+            "hbm_copy_gbps": r.hbm_copy_gbps, "host_gather_gbps": r.host_gather_gbps}
 
 _lib = None
 
@@ -329,6 +331,9 @@ class Graph:
                 v = MODES[v]
             if k == "filter_engine" and isinstance(v, str):
                 v = FILTER_ENGINES[v]
+            if k == "compact_gather":
+                p.compact_gather_num, p.compact_gather_den = int(v[0]), int(v[1])
+                continue
             if k in ("alpha", "beta", "gamma"):
                 setattr(p, k + "_num", int(v[0]))
                 setattr(p, k + "_den", int(v[1]))

@@ -54,6 +54,7 @@ struct SelParams {
     uint32_t force;       // 0: cost model; else the engine code for every scheduled partition
     uint32_t nres;        // partitions [0, nres) are resident
     uint32_t allow_filter, allow_compact; // engines whose staging fits the budget
+    uint32_t gn_c, gd_c;  // host gather cost: link rate / gather rate = gn_c / gd_c (0 = off)
 };
 
 // Written by the scan kernel, copied to the host every iteration.

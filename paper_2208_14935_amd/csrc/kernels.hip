@@ -99,7 +99,13 @@ __device__ __forceinline__ uint32_t masked_word(const uint32_t* bm, uint32_t wi,
 __device__ __forceinline__ uint8_t select_engine(uint64_t E, uint64_t nA, uint64_t Ea, uint64_t Rq,
                                                  const SelParams& sp) {
     const uint64_t tef = (E * sp.d1 + sp.L - 1) / sp.L;
-    const uint64_t tec = (Ea * sp.d1 + nA * sp.d2 + sp.L - 1) / sp.L;
+    uint64_t tec = (Ea * sp.d1 + nA * sp.d2 + sp.L - 1) / sp.L;
+    if (sp.gn_c) {
+        // the host gather runs as a pipeline with the copy: the slower of the two counts
+        const u128 den = (u128)sp.L * sp.gd_c;
+        const uint64_t tgc = (uint64_t)(((u128)Ea * sp.d1 * sp.gn_c + den - 1) / den);
+        if (tgc > tec) tec = tgc;
+    }
     const uint64_t q = (Rq + sp.MR - 1) / sp.MR;
     const u128 zfac = (u128)sp.gn * E + (u128)(sp.gd - sp.gn) * Ea;
     const bool c1 = (u128)sp.ad * tec < (u128)sp.an * tef;

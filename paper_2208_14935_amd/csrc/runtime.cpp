@@ -272,6 +272,8 @@ bool params_valid(const hytm_params& p, std::string* why) {
     if (p.index_bytes > 64) return bad("index_bytes must be <= 64");
     if (!(p.pr_damping >= 0.0 && p.pr_damping <= 1.0)) return bad("pr_damping must be in [0, 1]");
     if (p.reprocess > 1) return bad("reprocess must be 0 or 1");
+    if (!frac_ok(p.compact_gather_num, p.compact_gather_den, false))
+        return bad("compact_gather must be num/den with den in 1..65536");
     if (!(p.dpr_epsilon >= 0.0)) return bad("dpr_epsilon must be >= 0");
     if (p.streams < 2 || p.streams > kMaxSlots) return bad("streams must be in 2..16");
     if (p.gather_threads > 256) return bad("gather_threads must be <= 256");
@@ -331,6 +333,8 @@ SelParams make_sel(const hytm_graph* g, uint32_t arrays) {
                                               : 0;
     sp.allow_filter = 1;
     sp.allow_compact = 1;
+    sp.gn_c = p.compact_gather_num;
+    sp.gd_c = p.compact_gather_den;
     return sp;
 }
 
@@ -1566,6 +1570,8 @@ void hytm_default_params(hytm_params* p) {
     p->reprocess = 0;
     p->dpr_max_iterations = 10000;
     p->dpr_epsilon = 1e-7;
+    p->compact_gather_num = 0;
+    p->compact_gather_den = 1;
     p->streams = 4;
     p->gather_threads = 0;
     p->compact_chunk_edges = 0;
@@ -1935,6 +1941,32 @@ hytm_status hytm_link_probe(int hip_device, uint64_t bytes, hytm_link_probe_resu
             out->zc_read_gbps[i] = useful / (best_of([&] { return launch_zc_probe(dmap, bytes, wpl[i], sink, st); }) / 1e3);
         }
         out->hbm_copy_gbps = 2 * gb / (best_of([&] { return launch_copy_probe(dev2, dev, bytes, st); }) / 1e3);
+        // host gather: the compaction engine's work, 16-word runs from random places
+        {
+            const uint64_t words = bytes / 4, runs = words / 2 / 16;
+            std::vector<uint64_t> from(runs);
+            uint64_t x = 0x9E3779B97F4A7C15ull;
+            for (uint64_t r = 0; r < runs; r++) {
+                x = x * 6364136223846793005ull + 1442695040888963407ull;
+                from[r] = ((x >> 17) % (words / 16)) * 16;
+            }
+            uint32_t* dst = nullptr;
+            HIP_CHECK(hipHostMalloc((void**)&dst, runs * 64, hipHostMallocDefault));
+            const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency() / 2));
+            Pool pool(nt);
+            double best = 1e30;
+            for (int rep = 0; rep < 3; rep++) {
+                const double t0 = now_ms();
+                const uint64_t step = (runs + nt * 4 - 1) / (nt * 4);
+                pool.run(nt * 4, [&](unsigned t) {
+                    const uint64_t r0 = std::min<uint64_t>(runs, t * step), r1 = std::min<uint64_t>(runs, r0 + step);
+                    for (uint64_t r = r0; r < r1; r++) memcpy(dst + r * 16, host + from[r], 64);
+                });
+                best = std::min(best, now_ms() - t0);
+            }
+            (void)hipHostFree(dst);
+            out->host_gather_gbps = (double)runs * 64 / 1e9 / (best / 1e3);
+        }
         return HYTM_OK;
     });
     if (a) (void)hipEventDestroy(a);

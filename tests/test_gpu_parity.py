@@ -202,6 +202,24 @@ def test_select_engines_matches_oracle_on_random_stats(npart, seed):
         np.testing.assert_array_equal(got, want)
 
 
+@pytest.mark.parametrize("gather", [(1, 1), (3, 2), (64, 17)])
+def test_select_engines_with_the_gather_term_matches_oracle(gather):
+    rng = np.random.default_rng(sum(gather))
+    npart = 3000
+    E = rng.integers(1, 1 << 22, npart, dtype=np.uint64)
+    Ea = (E * rng.random(npart)).astype(np.uint64)
+    nA = np.minimum(Ea, rng.integers(1, 1 << 16, npart, dtype=np.uint64))
+    nA[Ea == 0] = 0
+    Rq = nA + (Ea // rng.integers(1, 64, npart, dtype=np.uint64))
+    g = hy.Graph(np.array([0, 1, 1], np.uint64), np.array([1], np.uint32))
+    g.set_params(compact_gather=gather)
+    for arrays in (1, 2):
+        got = g.select_engines(E, nA, Ea, Rq, nres=0, edge_arrays=arrays)
+        want = oracle.select(E, nA, Ea, Rq, params=oracle.CostParams(d1=4 * arrays, gather=gather))
+        np.testing.assert_array_equal(got, want)
+    g.close()
+
+
 _SEL = []
 
 
