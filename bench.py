@@ -12,6 +12,7 @@ dominant kernel's roofline from live HIP-event timings, and the single-threaded 
 oracle's rate on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,14 @@ import gen  # noqa: E402
 import paper_2208_14935_amd as hy  # noqa: E402
 
 HBM_PEAK_GBPS = 8000.0
+# HBM traffic of the dominant kernel, from two rocprofv3 PMC passes over this benchmark
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the factors read off the probe's device copy of
+# known size), mean per launch of the timed step.  It holds only for the kernel source and
+# workload it was measured on; otherwise the roofline reports traffic null.
+PMC_TRAFFIC = {"kernel": "push_filter", "workload": "rmat24-ef16-budget0.25-hybrid",
+               "kernels_sha256": "25cc50230ef3d240e97667df86712d988b8577d02ff0f10a8036adfc93de8fbf",
+               "bytes_per_launch": (2 * 1167379 + 1201606) * 1024.0,
+               "summary": "profiles/pmc_traffic_rmat24_budget25_hybrid.md"}
 PCIE_GEN5_X16_GBPS = 63.0
 
 
@@ -219,6 +228,10 @@ def main():
                                        for _, r, _ in all_runs),
                  "zerocopy_bytes": sum(r.stats["bytes_zerocopy"] for _, r, _ in all_runs)}
 
+    workload = (gname + (f"-ef{args.edge_factor:g}" if args.graph == "rmat" else "")
+                + f"-budget{args.budget_frac:g}-{args.mode}"
+                + ("-reprocess" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
+                + ("" if cgather[0] == 0 else "-gathercost"))
     roofline = None
     kernels = {}
     if kt:
@@ -257,8 +270,16 @@ def main():
             per_launch = items[dom] * 16 / max(launches[dom], 1)
             bound, peak = "hbm", HBM_PEAK_GBPS
         achieved = per_launch / (avg_ms / 1e3) / 1e9
+        traffic = None
+        src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2208_14935_amd", "csrc", "kernels.hip")
+        with open(src, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+        if (name == PMC_TRAFFIC["kernel"] and sha == PMC_TRAFFIC["kernels_sha256"]
+                and workload == PMC_TRAFFIC["workload"]):
+            traffic = PMC_TRAFFIC["bytes_per_launch"]
         roofline = {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak,
-                    "unit": "GB/s", "frac": achieved / peak, "traffic": None,
+                    "unit": "GB/s", "frac": achieved / peak, "traffic": traffic,
+                    "traffic_unit": "bytes per launch (HBM, PMC)", "algorithmic_bytes_per_launch": per_launch,
                     "avg_launch_ms": avg_ms, "launches_per_step": int(launches[dom]) // args.steps,
                     "measured_link_peak_gbps": probe["h2d_copy_gbps"]}
 
@@ -279,9 +300,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32 (BFS/SSSP/CC), f32 (PageRank)",
         "data": "synthetic R-MAT, seeded",
-        "config": {"workload": f"rmat{args.scale}-ef{args.edge_factor:g}-budget{args.budget_frac:g}-{args.mode}"
-                               + ("-reprocess" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
-                               + ("" if cgather[0] == 0 else "-gathercost"),
+        "config": {"workload": workload,
                    "n": n, "m": m, "m_sym": int(gs.m) if gs is not None else None,
                    "sources": [int(s) for s in srcs], "budget_frac_of_edge_bytes": args.budget_frac,
                    "partition_edges": args.partition_edges, "combine_k": args.combine_k, "mode": args.mode,
@@ -497,7 +516,7 @@ def serve_workload(args, g, off, gamma, probe):
         for q in warm:
             srv.wait(q)
         subs = []
-        free = {k: list(range(lanes)) for k in bufs}
+        free = {k: list(range(len(bufs[k]))) for k in bufs}
         t0 = time.perf_counter()
         pending = []
         for i, (k, s) in enumerate(zip(kinds, srcs)):
