@@ -74,6 +74,7 @@ def _load():
         "orc_hub_order": (u64, [u64, vp, vp, u32, u32, vp]),
         "orc_partition": (u64, [u64, vp, u64, vp]),
         "orc_partition_stats": (None, [u64, vp, vp, vp, u32, u32, vp, vp, vp]),
+        "orc_partition_lines_distinct": (None, [u64, vp, vp, vp, u32, u32, vp]),
         "orc_select": (None, [u64, vp, vp, vp, vp, u64, ctypes.POINTER(_CostParams), i32, vp]),
         "orc_combine": (u64, [u64, vp, vp, u32, u64, vp, vp]),
         "orc_gather": (None, [u64, vp, vp, vp, vp, vp]),
@@ -170,8 +171,9 @@ def partition(off, target_edges: int):
     return bounds[: k + 1] if n else np.zeros(1, dtype=np.uint64)
 
 
-def partition_stats(bounds, off, active, arrays: int = 1, line_bytes: int = 128):
-    """(nA, Ea, Rq) per partition for the boolean frontier `active`."""
+def partition_stats(bounds, off, active, arrays: int = 1, line_bytes: int = 128, distinct: bool = False):
+    """(nA, Ea, Rq) per partition for the boolean frontier `active`; with distinct, Rq counts
+    the different lines the active lists touch instead of Eq. 3's per-vertex requests."""
     bounds = np.ascontiguousarray(bounds, dtype=np.uint64)
     off = np.ascontiguousarray(off, dtype=np.uint64)
     act = np.ascontiguousarray(active, dtype=np.uint8)
@@ -179,6 +181,9 @@ def partition_stats(bounds, off, active, arrays: int = 1, line_bytes: int = 128)
     nA, Ea, Rq = (np.zeros(max(npart, 1), dtype=np.uint64)[:npart] for _ in range(3))
     _load().orc_partition_stats(npart, _p(bounds), _p(off), _p(act), int(arrays), int(line_bytes),
                                 _p(nA), _p(Ea), _p(Rq))
+    if distinct:
+        _load().orc_partition_lines_distinct(npart, _p(bounds), _p(off), _p(act), int(arrays), int(line_bytes),
+                                             _p(Rq))
     return nA, Ea, Rq
 
 

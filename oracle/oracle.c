@@ -373,6 +373,26 @@ void orc_partition_stats(uint64_t npart, const uint64_t *bounds, const uint64_t 
     }
 }
 
+/* Zero-copy requests counted as distinct lines (a reading for kernels that read a line
+   shared by two consecutive active lists once): Rq[i] = arrays x the number of different
+   m-byte lines that the lists of A_i touch.  The lists lie in vertex order, so a line
+   repeats only as the previous list's last line. */
+void orc_partition_lines_distinct(uint64_t npart, const uint64_t *bounds, const uint64_t *off,
+                                  const unsigned char *active, uint32_t arrays, uint32_t line_bytes, uint64_t *Rq) {
+    for (uint64_t i = 0; i < npart; i++) {
+        uint64_t count = 0, last = UINT64_MAX;
+        for (uint64_t v = bounds[i]; v < bounds[i + 1]; v++) {
+            if (!active[v] || off[v + 1] == off[v]) continue;
+            for (uint64_t line = off[v] * 4 / line_bytes; line <= (off[v + 1] * 4 - 1) / line_bytes; line++)
+                if (line != last) {
+                    count++;
+                    last = line;
+                }
+        }
+        Rq[i] = (uint64_t)arrays * count;
+    }
+}
+
 /* Exact non-negative rational p/q (q > 0). */
 typedef struct {
     u128 p, q;

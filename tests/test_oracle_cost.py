@@ -235,3 +235,22 @@ def test_select_gather_term_only_moves_partitions_off_compaction(gn, gd, seed):
     assert (a[changed] == COMPACT).all()
     assert (b != COMPACT)[changed].all()
     assert not ((b == COMPACT) & (a != COMPACT)).any()
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.lists(st.integers(0, 70), min_size=1, max_size=60), st.integers(1, 300), st.data())
+def test_distinct_lines_match_a_set_of_touched_lines(deg, target, data):
+    off = np.concatenate([[0], np.cumsum(deg)]).astype(np.uint64)
+    n = len(deg)
+    active = np.array(data.draw(st.lists(st.booleans(), min_size=n, max_size=n)))
+    bounds = oracle.partition(off, target)
+    for arrays in (1, 2):
+        _, _, rq = oracle.partition_stats(bounds, off, active, arrays=arrays, distinct=True)
+        _, _, rq_pv = oracle.partition_stats(bounds, off, active, arrays=arrays)
+        for i in range(len(bounds) - 1):
+            lines = set()
+            for v in range(int(bounds[i]), int(bounds[i + 1])):
+                if active[v] and deg[v]:
+                    lines.update(range(int(off[v]) * 4 // 128, (int(off[v + 1]) * 4 - 1) // 128 + 1))
+            assert rq[i] == arrays * len(lines)
+            assert rq[i] <= rq_pv[i]  # never more than one request per vertex line
