@@ -89,6 +89,10 @@ def main():
     ap.add_argument("--reprocess", action="store_true",
                     help="second pass over each iteration's loaded partitions (the paper's asynchronous scheduling)")
     ap.add_argument("--hub-sort", action="store_true", help="relabel hubs to the front when the graphs are loaded")
+    ap.add_argument("--rq-per-vertex", dest="rq_distinct", action="store_false",
+                    help="zero-copy requests of the cost model as Eq. 3's per-vertex lines (default: the distinct "
+                         "lines the zero-copy kernel actually reads)")
+    ap.add_argument("--rq-distinct", dest="rq_distinct", action="store_true")
     ap.add_argument("--compact-gather", default="off",
                     help="host-gather term of the compaction cost: 'off' (the paper's rule), 'probe' (link rate / "
                          "measured gather rate) or num/den")
@@ -108,7 +112,9 @@ def main():
     else:
         off, col = gen.rmat(args.scale, args.edge_factor, seed=args.scale)
     n, m = len(off) - 1, len(col)
+    log(f"generated n={n} m={m} in {time.time() - t0:.1f}s")
     w = gen.weights(off, col, 1000 + args.scale)
+    log(f"weights done {time.time() - t0:.1f}s")
     srcs = gen.sources(off, args.sources, 2000 + args.scale)
     need_sym = "cc" in algos and args.workload in ("quarter-budget", "modes")
     soff, scol = gen.symmetrize(off, col) if need_sym else (None, None)
@@ -122,7 +128,10 @@ def main():
 
     t0 = time.time()
     g = hy.Graph(off, col, weights=w, check_col=False, hub_sort=args.hub_sort)
-    gs = hy.Graph(soff, scol, symmetric=True, check_col=False, hub_sort=args.hub_sort) if scol is not None else None
+    # the per-mode workload loads the symmetrized graph only after the directed one is
+    # closed, so that the two never hold pinned host memory at once
+    gs = (hy.Graph(soff, scol, symmetric=True, check_col=False, hub_sort=args.hub_sort)
+          if scol is not None and args.workload != "modes" else None)
     log(f"pinned graph copies {time.time() - t0:.1f}s")
     gamma = gamma_from(args.gamma, probe)
     log(f"gamma = {gamma[0]}/{gamma[1]}")
@@ -138,13 +147,13 @@ def main():
         if h is not None:
             h.set_params(mode=args.mode, partition_edges=args.partition_edges, combine_k=args.combine_k,
                          filter_engine=args.filter_engine, gamma=gamma, reprocess=int(args.reprocess),
-                         compact_gather=cgather)
+                         compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct))
     if args.workload == "batch":
         return batch_workload(args, g, off, col, deg, gamma, probe)
     if args.workload == "serve":
         return serve_workload(args, g, off, gamma, probe)
     if args.workload == "modes":
-        return modes_workload(args, gname, g, gs, deg, srcs[:1], algos, gamma, probe)
+        return modes_workload(args, gname, g, (soff, scol), deg, srcs[:1], algos, gamma, probe, cgather)
 
     def budget(h, arrays):
         h.set_budget(int(args.budget_frac * 4 * arrays * h.m))
@@ -231,7 +240,7 @@ def main():
     workload = (gname + (f"-ef{args.edge_factor:g}" if args.graph == "rmat" else "")
                 + f"-budget{args.budget_frac:g}-{args.mode}"
                 + ("-reprocess" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
-                + ("" if cgather[0] == 0 else "-gathercost"))
+                + ("" if cgather[0] == 0 else "-gathercost") + ("-rqdistinct" if args.rq_distinct else ""))
     roofline = None
     kernels = {}
     if kt:
@@ -366,23 +375,34 @@ def batch_workload(args, g, off, col, deg, gamma, probe):
     print(json.dumps(out), flush=True)
 
 
-def modes_workload(args, gname, g, gs, deg, srcs, algos, gamma, probe):
-    """Every algorithm once under each transfer mode at one device budget (absolute
+def modes_workload(args, gname, g, sym, deg, srcs, algos, gamma, probe, cgather):
+    """Every algorithm under each transfer mode at one device budget (one warm-up run, then
+    one timed run that reuses the resident prefix; absolute
     --budget-bytes, else --budget-frac of the algorithm's edge bytes): GTEPS and the host
     link's achieved GB/s (explicit + zero-copy + resident-fill bytes over run time) against
     the measured pinned-copy peak."""
     s = int(srcs[0])
     lv = g.run("bfs", s).values  # reach of the source, outside the timed runs
     reach = int(deg[lv != hy.UNREACHED].sum())
-    work = {"bfs": reach, "sssp": reach, "cc": gs.m if gs is not None else 0, "pagerank": 20 * g.m}
+    m_directed, m_sym = int(g.m), (len(sym[1]) if sym[1] is not None else 0)
+    work = {"bfs": reach, "sssp": reach, "cc": m_sym, "pagerank": 20 * g.m}
     table = {}
-    for mode in args.modes.split(","):
-        for a in algos:
+    order = [a for a in algos if a != "cc"] + (["cc"] if "cc" in algos else [])
+    gs = None
+    for a in order:
+        if a == "cc" and gs is None:
+            g.close()
+            gs = hy.Graph(sym[0], sym[1], symmetric=True, check_col=False, hub_sort=args.hub_sort)
+            gs.set_params(partition_edges=args.partition_edges, combine_k=args.combine_k,
+                          filter_engine=args.filter_engine, gamma=gamma, reprocess=int(args.reprocess),
+                          compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct))
+        for mode in args.modes.split(","):
             h = gs if a == "cc" else g
             arrays = 2 if a == "sssp" else 1
             h.set_params(mode=mode)
             h.set_budget(int(args.budget_bytes) if args.budget_bytes else int(args.budget_frac * 4 * arrays * h.m))
             try:
+                h.run(a, s)  # warm-up: staging buffers and the resident prefix of this plan
                 r = h.run(a, s, stats=True)
             except hy.HytmError as e:  # a forced engine whose staging does not fit
                 table[f"{mode}/{a}"] = {"error": str(e)}
@@ -408,9 +428,10 @@ def modes_workload(args, gname, g, gs, deg, srcs, algos, gamma, probe):
         "value": value, "unit": "GTEPS", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": tot_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32 (BFS/SSSP/CC), f32 (PageRank)", "data": "synthetic, seeded",
-        "config": {"workload": f"{gname}-budget{args.budget_bytes / 1e9:g}GB-modes" if args.budget_bytes
-                   else f"{gname}-budget{args.budget_frac:g}-modes", "n": int(g.n), "m": int(g.m),
-                   "m_sym": int(gs.m) if gs is not None else None, "source": s, "gamma": list(gamma)},
+        "config": {"workload": (f"{gname}-budget{args.budget_bytes / 1e9:g}GB-modes" if args.budget_bytes
+                                else f"{gname}-budget{args.budget_frac:g}-modes")
+                               + ("-rqdistinct" if args.rq_distinct else ""), "n": len(deg), "m": m_directed,
+                   "m_sym": m_sym, "source": s, "gamma": list(gamma)},
         "modes": table, "probe": probe,
     }
     print(json.dumps(out), flush=True)

@@ -130,6 +130,10 @@ typedef struct {
                                    priced max(Tec, ceil(Ea * d1 * ratio / (m * MR))), the gather of
                                    Eq. 2 that the paper leaves out (an extension; hytm_link_probe
                                    measures both rates). */
+    uint32_t rq_distinct_lines; /* 0: Rq of Eq. 3 counts each active list's lines (its footnote's
+                                   per-vertex requests).  1: Rq counts the different m-byte lines the
+                                   active lists of a partition touch -- what the zero-copy kernel
+                                   reads, since it loads a line two consecutive lists share once. */
 } hytm_params;
 
 /* How a FILTER task moves its whole partition range to the GPU.  Both transfer every
@@ -165,8 +169,9 @@ typedef struct {
     uint64_t active_edges;      /* sum over iterations: edges pushed */
     uint64_t bytes_filter;      /* H2D bytes of filter copies */
     uint64_t bytes_compact;     /* H2D bytes of compaction copies */
-    uint64_t zc_lines;          /* 128-byte lines read by the zero-copy kernel, per edge array */
-    uint64_t bytes_zerocopy;    /* zc_lines x 128 B x edge arrays */
+    uint64_t zc_lines;          /* 128-byte line requests of the zero-copy kernel (one per line of each
+                                   active vertex's list), per edge array: Rq of Eq. 3 at m = 128 */
+    uint64_t bytes_zerocopy;    /* zc_lines_distinct x 128 B x edge arrays: lines moved over the link */
     uint64_t bytes_d2h;         /* device-to-host bytes of selections and active lists */
     uint64_t bytes_resident_fill; /* H2D bytes copied into the resident cache this run */
     uint64_t filter_tasks;
@@ -189,6 +194,8 @@ typedef struct {
     uint64_t kernel_launches[8];
     uint64_t kernel_items[8];
     double residual;            /* PAGERANK_DELTA: total pending delta at the end (else 0) */
+    uint64_t zc_lines_distinct; /* different lines among zc_lines: a line shared by two consecutive
+                                   active vertices counts once */
 } hytm_run_stats;
 
 /* Kernel classes of hytm_run_stats.kernel_* */

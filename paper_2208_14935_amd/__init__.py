@@ -51,6 +51,7 @@ class Params(ctypes.Structure):
         ("ppr_iterations", ctypes.c_uint32), ("reprocess", ctypes.c_uint32),
         ("dpr_max_iterations", ctypes.c_uint32), ("dpr_epsilon", ctypes.c_double),
         ("compact_gather_num", ctypes.c_uint32), ("compact_gather_den", ctypes.c_uint32),
+        ("rq_distinct_lines", ctypes.c_uint32),
     ]
 
 
@@ -78,6 +79,7 @@ class RunStats(ctypes.Structure):
         ("mode_trace_cap", ctypes.c_uint64), ("time_kernels", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
         ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_uint64 * 8),
         ("kernel_items", ctypes.c_uint64 * 8), ("residual", ctypes.c_double),
+        ("zc_lines_distinct", ctypes.c_uint64),
     ]
 
 

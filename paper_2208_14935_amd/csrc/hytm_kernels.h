@@ -55,6 +55,7 @@ struct SelParams {
     uint32_t nres;        // partitions [0, nres) are resident
     uint32_t allow_filter, allow_compact; // engines whose staging fits the budget
     uint32_t gn_c, gd_c;  // host gather cost: link rate / gather rate = gn_c / gd_c (0 = off)
+    uint32_t rq_distinct; // zero-copy requests: 0 = per vertex (Eq. 3), 1 = distinct lines touched
 };
 
 // Written by the scan kernel, copied to the host every iteration.
@@ -154,10 +155,12 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
                              hipStream_t st);
 
 // Push over 128-byte line items [item_lo, item_hi) of list entries [ja, jb), reading
-// the mapped host arrays col / w at absolute edge indices.
+// the mapped host arrays col / w at absolute edge indices.  distinct (or null) gains the
+// number of different lines read: an item that is its vertex's first line and the
+// previous list entry's last line counts once.
 hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uint64_t* wpre, uint32_t ja,
                              uint32_t jb, uint64_t item_lo, uint64_t item_hi, const uint64_t* off,
-                             const uint32_t* col, const uint32_t* w, hipStream_t st);
+                             const uint32_t* col, const uint32_t* w, unsigned long long* distinct, hipStream_t st);
 
 // A filter task streamed from the mapped host arrays: edges [e0, e1) of a run of
 // consecutive filter partitions whose active vertices are list entries [ja, jb).

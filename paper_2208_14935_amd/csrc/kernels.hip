@@ -68,6 +68,33 @@ __device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t x, uint64_t* l
     return base + v - x;
 }
 
+// Block-wide exclusive prefix maximum of x (0 for thread 0); *total gets the maximum over
+// the block.  lds must hold NT/64 uint64.
+template <int NT>
+__device__ __forceinline__ uint64_t block_exclusive_max(uint64_t x, uint64_t* lds, uint64_t* total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(v, d, 64);
+        if (lane >= d) v = v > y ? v : y;
+    }
+    if (lane == 63) lds[wid] = v;
+    __syncthreads();
+    uint64_t base = 0, t = 0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; k++) {
+        const uint64_t w = lds[k];
+        if (k < wid) base = base > w ? base : w;
+        t = t > w ? t : w;
+    }
+    *total = t;
+    uint64_t ex = __shfl_up(v, 1, 64);
+    if (lane == 0) ex = 0;
+    __syncthreads();
+    return base > ex ? base : ex;
+}
+
 template <int NT>
 __device__ __forceinline__ uint64_t block_sum(uint64_t x, uint64_t* lds) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -122,30 +149,50 @@ __global__ __launch_bounds__(256) void k_stats_select(uint32_t npart, const uint
                                                       uint8_t* __restrict__ mode, uint32_t* __restrict__ nA,
                                                       uint32_t* __restrict__ nF, uint64_t* __restrict__ Ea,
                                                       uint64_t* __restrict__ Rq, uint64_t* __restrict__ K) {
-    __shared__ uint64_t red[4];
+    __shared__ uint64_t red[4], red2[4];
+    const uint32_t sh = sp.cost_shift;
     for (uint32_t i = blockIdx.x; i < npart; i += gridDim.x) {
         const uint32_t vb = pv[i], ve = pv[i + 1];
         const uint32_t wb = vb >> 5, we = (ve + 31) >> 5;
-        uint64_t c = 0, f = 0, ea = 0, rq = 0, kl = 0;
-        for (uint32_t wi = wb + threadIdx.x; wi < we; wi += blockDim.x) {
-            uint32_t bits = masked_word(cur, wi, vb, ve);
-            f += __popc(bits);
-            while (bits) {
-                const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
-                bits &= bits - 1;
-                const uint64_t s = off[v], e = off[v + 1];
-                if (e > s) {
-                    c += 1;
-                    ea += e - s;
-                    rq += lines_of(s, e, sp.cost_shift);
-                    kl += lines_of(s, e, ZC_LINE_SHIFT);
+        uint64_t c = 0, f = 0, ea = 0, rq = 0, kl = 0, rqd = 0;
+        // distinct lines: (line + 1) of the last list before the current 256 words, 0 = none
+        uint64_t carry = 0;
+        for (uint32_t base = wb; base < we; base += blockDim.x) {  // uniform across the block
+            const uint32_t wi = base + threadIdx.x;
+            uint64_t first1 = 0, last1 = 0, dl = 0;  // (line + 1) of the word's first / last list
+            if (wi < we) {
+                uint32_t bits = masked_word(cur, wi, vb, ve);
+                f += __popc(bits);
+                while (bits) {
+                    const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
+                    bits &= bits - 1;
+                    const uint64_t s = off[v], e = off[v + 1];
+                    if (e > s) {
+                        c += 1;
+                        ea += e - s;
+                        rq += lines_of(s, e, sh);
+                        kl += lines_of(s, e, ZC_LINE_SHIFT);
+                        const uint64_t fl = (s >> sh) + 1, ll = ((e - 1) >> sh) + 1;
+                        dl += ll - fl + 1 - (last1 == fl ? 1 : 0);
+                        if (!first1) first1 = fl;
+                        last1 = ll;
+                    }
                 }
+            }
+            if (sp.rq_distinct) {
+                // a word's first line repeats the last line of the latest earlier list
+                uint64_t tot;
+                const uint64_t ex = block_exclusive_max<256>(last1, red2, &tot);
+                const uint64_t prev = carry > ex ? carry : ex;
+                if (first1 && prev == first1) dl -= 1;
+                rqd += dl;
+                carry = carry > tot ? carry : tot;
             }
         }
         c = block_sum<256>(c, red);
         f = block_sum<256>(f, red);
         ea = block_sum<256>(ea, red);
-        rq = block_sum<256>(rq, red) * sp.arrays;
+        rq = block_sum<256>(sp.rq_distinct ? rqd : rq, red) * sp.arrays;
         kl = block_sum<256>(kl, red);
         if (threadIdx.x == 0) {
             const uint64_t E = off[ve] - off[vb];
@@ -672,12 +719,16 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
                                                              uint32_t jb, uint64_t item_lo, uint64_t item_hi,
                                                              const uint64_t* __restrict__ off,
                                                              const uint32_t* __restrict__ col,
-                                                             const uint32_t* __restrict__ w, Op op) {
+                                                             const uint32_t* __restrict__ w, Op op,
+                                                             unsigned long long* __restrict__ distinct) {
     __shared__ uint64_t s_pre[LINE_IPB];
     __shared__ uint64_t s_s[LINE_IPB];
     __shared__ uint64_t s_e[LINE_IPB];
     __shared__ uint32_t s_val[LINE_IPB];
     __shared__ uint32_t s_tmp;
+    __shared__ uint64_t s_prev_end;  // end offset of the list entry before the staged ones
+    __shared__ uint32_t s_cnt;
+    uint32_t my_lines = 0;  // distinct lines of the items this half wave loaded
     const uint32_t half = threadIdx.x >> 5, lane = threadIdx.x & 31;
     for (uint64_t blk = blockIdx.x;; blk += gridDim.x) {
         const uint64_t i0 = item_lo + blk * LINE_IPB;
@@ -693,6 +744,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
             s_e[k] = off[v + 1];
             s_val[k] = op.src(v);
         }
+        if (distinct && threadIdx.x == 0) s_prev_end = j0 > ja ? off[list[j0 - 1] + 1] : UINT64_MAX;
         __syncthreads();
         uint32_t cv[LINE_UNROLL], wv[LINE_UNROLL], kk[LINE_UNROLL];
         bool ok[LINE_UNROLL];
@@ -714,6 +766,14 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
                 }
                 const uint64_t s = s_s[lo];
                 const uint64_t e = ((s >> ZC_LINE_SHIFT) << ZC_LINE_SHIFT) + ((i - s_pre[lo]) << ZC_LINE_SHIFT) + lane;
+                if (distinct && lane == 0) {
+                    // the first line of a vertex repeats when the previous active vertex
+                    // (list order is CSR order) ends in it: count each line once
+                    const uint64_t pe = lo ? s_e[lo - 1] : s_prev_end;
+                    const bool dup = i == s_pre[lo] && pe != UINT64_MAX && pe > 0 &&
+                                     ((pe - 1) >> ZC_LINE_SHIFT) == (s >> ZC_LINE_SHIFT);
+                    my_lines += dup ? 0u : 1u;
+                }
                 if (e >= s && e < s_e[lo]) {
                     ok[r] = true;
                     kk[r] = lo;
@@ -725,6 +785,13 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
 #pragma unroll
         for (int r = 0; r < LINE_UNROLL; r++) push_if(op, ok[r], s_val[kk[r]], cv[r], wv[r]);
         __syncthreads();
+    }
+    if (distinct) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        if (lane == 0 && my_lines) atomicAdd(&s_cnt, my_lines);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_cnt) atomicAdd(distinct, (unsigned long long)s_cnt);
     }
 }
 
@@ -1339,38 +1406,37 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
 template <class Op>
 static hipError_t push_lines_op(const Op& op, const uint32_t* list, const uint64_t* wpre, uint32_t ja, uint32_t jb,
                                 uint64_t lo, uint64_t hi, const uint64_t* off, const uint32_t* col,
-                                const uint32_t* w, hipStream_t st) {
+                                const uint32_t* w, unsigned long long* distinct, hipStream_t st) {
     const unsigned g = grid_for(hi - lo, LINE_IPB, GRID_CAP);
-    k_push_lines<Op><<<g, LINE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, op);
+    k_push_lines<Op><<<g, LINE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, op, distinct);
     return hipGetLastError();
 }
 
 hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uint64_t* wpre, uint32_t ja,
                              uint32_t jb, uint64_t item_lo, uint64_t item_hi, const uint64_t* off,
-                             const uint32_t* col, const uint32_t* w, hipStream_t st) {
+                             const uint32_t* col, const uint32_t* w, unsigned long long* distinct, hipStream_t st) {
     if (item_hi <= item_lo || jb <= ja) return hipSuccess;
     switch (s.algo) {
     case ALGO_BFS:
         return push_lines_op(OpBfs{s.visited, s.next, s.val, s.level_next}, list, wpre, ja, jb, item_lo, item_hi,
-                             off, col, w, st);
+                             off, col, w, distinct, st);
     case ALGO_SSSP:
-        return push_lines_op(OpSssp{s.val, s.next, s.overflow}, list, wpre, ja, jb, item_lo, item_hi, off, col, w,
-                             st);
+        return push_lines_op(OpSssp{s.val, s.next, s.overflow}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, st);
     case ALGO_CC:
-        return push_lines_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
+        return push_lines_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, st);
     case ALGO_BFS_RELAX:
-        return push_lines_op(OpBfsRelax{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
+        return push_lines_op(OpBfsRelax{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, st);
     case ALGO_MBFS:
         return push_lines_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next, s.lshift}, list, wpre, ja, jb,
-                             item_lo, item_hi, off, col, w, st);
+                             item_lo, item_hi, off, col, w, distinct, st);
     case ALGO_MSSSP:
         return push_lines_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow, s.lshift}, list, wpre, ja, jb, item_lo,
-                             item_hi, off, col, w, st);
+                             item_hi, off, col, w, distinct, st);
     case ALGO_MPPR:
         return push_lines_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
-                             item_hi, off, col, w, st);
+                             item_hi, off, col, w, distinct, st);
     default:
-        return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, st);
+        return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, st);
     }
 }
 

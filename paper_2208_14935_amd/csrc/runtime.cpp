@@ -63,6 +63,7 @@ struct HipError {
     do {                                                                                                  \
         hipError_t e_ = (expr);                                                                           \
         if (e_ != hipSuccess) {                                                                           \
+            (void)hipGetLastError(); /* clear it, or the next launch check would report it again */        \
             fail(e_ == hipErrorOutOfMemory ? HYTM_E_NOMEM : HYTM_E_DEVICE, "%s failed: %s (%s:%d)", #expr, \
                  hipGetErrorString(e_), __FILE__, __LINE__);                                              \
             throw HipError{e_ == hipErrorOutOfMemory ? HYTM_E_NOMEM : HYTM_E_DEVICE};                    \
@@ -207,6 +208,7 @@ struct hytm_graph {
     DevBuf<float> d_lx, d_lacc;   // batched PPR: x and accumulator rows
     DevBuf<uint32_t> d_xout;      // lanes extracted for the copy back
     DevBuf<uint32_t> d_cur2;      // frontier of the reprocessing pass
+    DevBuf<uint64_t> d_zcl;       // distinct 128-byte lines read by the zero-copy kernel this run
     DevBuf<float> d_delta;        // delta-based PageRank: pending delta per vertex
     DevBuf<double> d_psum;        // ... and per partition
     HostBuf<double> h_psum;
@@ -272,6 +274,7 @@ bool params_valid(const hytm_params& p, std::string* why) {
     if (p.index_bytes > 64) return bad("index_bytes must be <= 64");
     if (!(p.pr_damping >= 0.0 && p.pr_damping <= 1.0)) return bad("pr_damping must be in [0, 1]");
     if (p.reprocess > 1) return bad("reprocess must be 0 or 1");
+    if (p.rq_distinct_lines > 1) return bad("rq_distinct_lines must be 0 or 1");
     if (!frac_ok(p.compact_gather_num, p.compact_gather_den, false))
         return bad("compact_gather must be num/den with den in 1..65536");
     if (!(p.dpr_epsilon >= 0.0)) return bad("dpr_epsilon must be >= 0");
@@ -335,6 +338,7 @@ SelParams make_sel(const hytm_graph* g, uint32_t arrays) {
     sp.allow_compact = 1;
     sp.gn_c = p.compact_gather_num;
     sp.gd_c = p.compact_gather_den;
+    sp.rq_distinct = p.rq_distinct_lines;
     return sp;
 }
 
@@ -456,6 +460,7 @@ void release_all(hytm_graph* g) {
     g->d_lacc.release();
     g->d_xout.release();
     g->d_cur2.release();
+    g->d_zcl.release();
     g->d_delta.release();
     g->d_psum.release();
     g->h_psum.release();
@@ -635,6 +640,7 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
     g->d_list.ensure(n);
     g->d_wpre.ensure(n + 1);
     g->d_overflow.ensure(2);
+    g->d_zcl.ensure(1);
     g->d_lanes.ensure(1);
     g->h_lanes.ensure(1);
     g->d_mode.ensure(npart);
@@ -794,7 +800,7 @@ hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Heade
             return launch_push_lines(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_Z],
                                      h.seg_list_start[SEG_Z] + h.seg_list_count[SEG_Z], h.seg_work_start[SEG_Z],
                                      h.seg_work_start[SEG_Z] + h.seg_work_total[SEG_Z], g->d_off.p, g->d_col_map,
-                                     g->d_w_map, g->s_zc);
+                                     g->d_w_map, (unsigned long long*)g->d_zcl.p, g->s_zc);
         }));
         rec->zc_lines += h.seg_work_total[SEG_Z];
     }
@@ -1095,6 +1101,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     hytm_status ps = prepare_graph(g, arrays, main, &pl, &rc.tot);
     if (ps != HYTM_OK) return ps;
     HIP_CHECK(hipEventRecord(g->ev_start, main));
+    HIP_CHECK(launch_fill_u32((uint32_t*)g->d_zcl.p, 2, 0u, main));
     init_ctx(rc, g, algo, batched, pl, stats);
 
     const uint64_t n = g->n;
@@ -1247,8 +1254,11 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         stats->active_edges = tt.ae;
         stats->bytes_filter = tt.bf;
         stats->bytes_compact = tt.bc;
+        uint64_t zcd = 0;
+        HIP_CHECK(hipMemcpy(&zcd, g->d_zcl.p, sizeof(zcd), hipMemcpyDeviceToHost));
         stats->zc_lines = tt.zcl;
-        stats->bytes_zerocopy = tt.zcl * 128 * arrays;
+        stats->zc_lines_distinct = zcd;
+        stats->bytes_zerocopy = zcd * 128 * arrays;
         stats->bytes_d2h = tt.d2h;
         stats->bytes_resident_fill = tt.fill_bytes;
         stats->filter_tasks = tt.ftasks;
@@ -1572,6 +1582,7 @@ void hytm_default_params(hytm_params* p) {
     p->dpr_epsilon = 1e-7;
     p->compact_gather_num = 0;
     p->compact_gather_den = 1;
+    p->rq_distinct_lines = 0;
     p->streams = 4;
     p->gather_threads = 0;
     p->compact_chunk_edges = 0;
@@ -1775,7 +1786,8 @@ hytm_status hytm_set_params(hytm_graph* g, const hytm_params* p) {
             partition_graph(g);
             return HYTM_OK;
         });
-    g->res_valid = false;
+    // the resident cache stays valid: a run refills it only if its partition count or
+    // edge arrays change under the new parameters
     return HYTM_OK;
 }
 

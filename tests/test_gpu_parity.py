@@ -165,23 +165,27 @@ def test_hybrid_uses_several_engines_and_moves_fewer_bytes_than_filter(rmat16):
 
 
 # --------------------------------------------------- selection parity
-def test_bfs_engine_trace_matches_oracle_selection(rmat16):
-    """BFS frontiers are unique (level t), so the per-iteration engine vector is pinned."""
-    note("rmat16 bfs engine trace")
+@pytest.mark.parametrize("pe,distinct,gamma", [(4096, False, (5, 8)), (4096, True, (5, 8)),
+                                              (1 << 18, True, (1, 1)), (1 << 18, False, (1, 1))])
+def test_bfs_engine_trace_matches_oracle_selection(rmat16, pe, distinct, gamma):
+    """BFS frontiers are unique (level t), so the per-iteration engine vector is pinned --
+    with Eq. 3's per-vertex requests or with distinct lines (partitions of 2^18 edges span
+    more than one 256-word pass of the statistics kernel)."""
+    note(f"rmat16 bfs engine trace pe={pe} distinct={distinct}")
     lvl, it = rmat16.want("bfs", 0)
     with rmat16.graph("bfs") as g:
-        g.set_params(partition_edges=4096)
+        g.set_params(partition_edges=pe, rq_distinct_lines=int(distinct), gamma=gamma)
         g.set_resident_fraction("bfs", 0.25)
         res = g.run("bfs", 0, trace=True, stats=True)
         check(rmat16, "bfs", res)
         bounds = g.partition_bounds()
         nres = res.stats["nres"]
-    np.testing.assert_array_equal(bounds, oracle.partition(rmat16.off, 4096))
+    np.testing.assert_array_equal(bounds, oracle.partition(rmat16.off, pe))
     E = np.diff(rmat16.off[bounds.astype(np.int64)])
     assert res.mode_trace.shape == (it, len(E))
     for t in range(it):
-        nA, Ea, Rq = oracle.partition_stats(bounds, rmat16.off, lvl == t, arrays=1)
-        want = oracle.select(E, nA, Ea, Rq, nres=nres)
+        nA, Ea, Rq = oracle.partition_stats(bounds, rmat16.off, lvl == t, arrays=1, distinct=distinct)
+        want = oracle.select(E, nA, Ea, Rq, nres=nres, params=oracle.CostParams(gamma=gamma))
         np.testing.assert_array_equal(res.mode_trace[t], want, err_msg=f"iteration {t}")
 
 
@@ -326,3 +330,26 @@ def test_pinned_output_buffers_match_pageable(rmat16):
             np.testing.assert_array_equal(vals[i], rmat16.want("bfs", int(s))[0])
         with pytest.raises(ValueError):
             g.run("bfs", 0, out=np.zeros(n, dtype=np.float32))
+
+
+def test_zero_copy_counts_each_line_once(rmat16):
+    """With every partition on zero-copy, a BFS iteration's zero-copy vertices are one level
+    of the BFS tree, so the lines moved are the distinct 128-byte lines of their lists."""
+    off, col = rmat16.off, rmat16.col
+    with rmat16.graph("sssp") as g:
+        g.set_params(mode="zerocopy", partition_edges=4096)
+        g.set_resident_fraction("bfs", 0.0)
+        r = g.run("bfs", 0, stats=True)
+    lvl, its = oracle.bfs(off, col, 0)
+    want = 0
+    for t in range(its):
+        lines = set()
+        for v in np.nonzero(lvl == t)[0]:
+            s, e = int(off[v]), int(off[v + 1])
+            if e > s:
+                lines.update(range(s >> 5, ((e - 1) >> 5) + 1))
+        want += len(lines)
+    st = r.stats
+    assert st["zc_lines_distinct"] == want
+    assert st["zc_lines_distinct"] <= st["zc_lines"]
+    assert st["bytes_zerocopy"] == want * 128
