@@ -86,8 +86,9 @@ def main():
     ap.add_argument("--modes", default="filter,compact,zerocopy,hybrid", help="modes: transfer modes to compare")
     ap.add_argument("--queries", type=int, default=200, help="serve: queries in the arrival trace")
     ap.add_argument("--graphs", type=int, default=32, help="multigraph: R-MAT graphs of scales 16..22")
-    ap.add_argument("--reprocess", action="store_true",
-                    help="second pass over each iteration's loaded partitions (the paper's asynchronous scheduling)")
+    ap.add_argument("--reprocess", type=int, nargs="?", const=1, default=0,
+                    help="second pass over each iteration's loaded partitions (the paper's asynchronous "
+                         "scheduling); 2 = only resident and zero-copy partitions")
     ap.add_argument("--hub-sort", action="store_true", help="relabel hubs to the front when the graphs are loaded")
     ap.add_argument("--rq-per-vertex", dest="rq_distinct", action="store_false",
                     help="zero-copy requests of the cost model as Eq. 3's per-vertex lines (default: the distinct "
@@ -239,7 +240,7 @@ def main():
 
     workload = (gname + (f"-ef{args.edge_factor:g}" if args.graph == "rmat" else "")
                 + f"-budget{args.budget_frac:g}-{args.mode}"
-                + ("-reprocess" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
+                + (f"-reprocess{args.reprocess}" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
                 + ("" if cgather[0] == 0 else "-gathercost") + ("-rqdistinct" if args.rq_distinct else ""))
     roofline = None
     kernels = {}

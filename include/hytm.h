@@ -122,7 +122,9 @@ typedef struct {
                                    it loaded, from the vertices the first pass improved (Sec. 6.1);
                                    BFS, SSSP, CC and PAGERANK_DELTA, single-source runs only.  The
                                    results are unchanged (BFS relaxes levels instead of marking
-                                   first visits); iteration counts drop. */
+                                   first visits); iteration counts drop.  2: the second pass covers
+                                   only resident and zero-copy partitions, whose lists cost no host
+                                   transfer or only the improved lists' lines (BFS/SSSP/CC). */
     uint32_t dpr_max_iterations; /* 10000: cap on PAGERANK_DELTA iterations */
     double dpr_epsilon;         /* 1e-7: PAGERANK_DELTA stops when the pending delta sums to this */
     uint32_t compact_gather_num, compact_gather_den; /* 0/1: off.  Otherwise the ratio of the

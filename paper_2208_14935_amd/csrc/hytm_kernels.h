@@ -200,9 +200,9 @@ hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, f
 hipError_t launch_dpr_init(uint64_t n, float* delta, const float* inv_n, float restart, hipStream_t st);
 
 // Reprocessing (Sec. 6.1): cur2 <- the vertices of next that lie in partitions whose mode
-// is not NONE (the partitions loaded by the pass that just ran).  Clears cur2 first.
-hipError_t launch_loaded_frontier(uint32_t npart, const uint32_t* pv, const uint8_t* mode, const uint32_t* next,
-                                  uint32_t* cur2, uint32_t nwords, hipStream_t st);
+// m has bit m set in mode_mask (engine codes of the pass that just ran).  Clears cur2 first.
+hipError_t launch_loaded_frontier(uint32_t npart, const uint32_t* pv, const uint8_t* mode, uint32_t mode_mask,
+                                  const uint32_t* next, uint32_t* cur2, uint32_t nwords, hipStream_t st);
 // Delta-based PageRank.  fold: delta[v] += the accumulator copies of v (then zeroed) and
 // psum[p] = the partition's delta sum (FP64).  activate: in every partition with
 // sched[p] != 0, each vertex with delta > 0 moves delta into x, shares damping * delta /

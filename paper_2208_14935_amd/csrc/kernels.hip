@@ -906,10 +906,10 @@ __global__ __launch_bounds__(256) void k_extract_lanes(const uint32_t* __restric
 }
 
 __global__ __launch_bounds__(256) void k_loaded_frontier(uint32_t npart, const uint32_t* __restrict__ pv,
-                                                         const uint8_t* __restrict__ mode,
+                                                         const uint8_t* __restrict__ mode, uint32_t mode_mask,
                                                          const uint32_t* __restrict__ next, uint32_t* __restrict__ cur2) {
     for (uint32_t p = blockIdx.x; p < npart; p += gridDim.x) {
-        if (mode[p] == P_NONE) continue;  // uniform across the workgroup
+        if (!((mode_mask >> mode[p]) & 1)) continue;  // uniform across the workgroup
         for (uint32_t v = pv[p] + threadIdx.x; v < pv[p + 1]; v += blockDim.x)
             if ((next[v >> 5] >> (v & 31)) & 1) atomicOr(cur2 + (v >> 5), 1u << (v & 31));
     }
@@ -1250,11 +1250,11 @@ hipError_t launch_extract_lanes(const uint32_t* vals, uint64_t n, uint32_t lshif
     return hipGetLastError();
 }
 
-hipError_t launch_loaded_frontier(uint32_t npart, const uint32_t* pv, const uint8_t* mode, const uint32_t* next,
-                                  uint32_t* cur2, uint32_t nwords, hipStream_t st) {
+hipError_t launch_loaded_frontier(uint32_t npart, const uint32_t* pv, const uint8_t* mode, uint32_t mode_mask,
+                                  const uint32_t* next, uint32_t* cur2, uint32_t nwords, hipStream_t st) {
     hipError_t e = launch_fill_u32(cur2, nwords, 0u, st);
     if (e != hipSuccess || !npart) return e;
-    k_loaded_frontier<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, mode, next, cur2);
+    k_loaded_frontier<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, mode, mode_mask, next, cur2);
     return hipGetLastError();
 }
 

@@ -273,7 +273,7 @@ bool params_valid(const hytm_params& p, std::string* why) {
     if (p.max_outstanding == 0) return bad("max_outstanding must be > 0");
     if (p.index_bytes > 64) return bad("index_bytes must be <= 64");
     if (!(p.pr_damping >= 0.0 && p.pr_damping <= 1.0)) return bad("pr_damping must be in [0, 1]");
-    if (p.reprocess > 1) return bad("reprocess must be 0 or 1");
+    if (p.reprocess > 2) return bad("reprocess must be 0, 1 or 2");
     if (p.rq_distinct_lines > 1) return bad("rq_distinct_lines must be 0 or 1");
     if (!frac_ok(p.compact_gather_num, p.compact_gather_den, false))
         return bad("compact_gather must be num/den with den in 1..65536");
@@ -958,7 +958,13 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
         // Sec. 6.1: the partitions just loaded are processed once more, from the vertices
         // the first pass improved; those stay in the next frontier
         HIP_CHECK(kt.run(HYTM_K_OTHER, g->npart, main, [&] {
-            return launch_loaded_frontier(g->npart, g->d_pv.p, g->d_mode.p, rc.nxt, g->d_cur2.p, rc.nwords, main);
+            // reprocess 1: every loaded partition; 2: only those whose lists cost no host
+            // transfer or only their own lines again (resident, zero-copy)
+            const uint32_t mask = g->params.reprocess == 2
+                                      ? (1u << P_RES) | (1u << P_ZC)
+                                      : (1u << P_RES) | (1u << P_FILTER) | (1u << P_ZC) | (1u << P_COMPACT);
+            return launch_loaded_frontier(g->npart, g->d_pv.p, g->d_mode.p, mask, rc.nxt, g->d_cur2.p, rc.nwords,
+                                          main);
         }));
         Header h2;
         st = engine_pass(rc, g->d_cur2.p, main, &h2, nullptr, true, &rec, -1);

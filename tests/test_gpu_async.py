@@ -98,3 +98,17 @@ def test_delta_pagerank_epsilon_and_cap(case, fixed_point):
         g.set_params(dpr_epsilon=1e-7, dpr_max_iterations=3)
         capped = g.run("pagerank_delta", stats=True)
         assert capped.iterations == 3 and capped.stats["residual"] > 1e-7
+
+
+@pytest.mark.parametrize("algo", ["bfs", "sssp", "cc"])
+def test_reprocessing_resident_and_zero_copy_only(case, algo):
+    off, col, w, soff, scol = case
+    s = int(gen.sources(off, 1, 9)[0])
+    g = hy.Graph(soff, scol, symmetric=True) if algo == "cc" else hy.Graph(off, col, weights=w)
+    with g:
+        g.set_params(partition_edges=4096, reprocess=2)
+        g.set_resident_fraction(algo, 0.25)
+        r = g.run(algo, s)
+    want = (oracle.bfs(off, col, s)[0] if algo == "bfs" else oracle.sssp(off, col, w, s) if algo == "sssp"
+            else oracle.cc(soff, scol)[0])
+    np.testing.assert_array_equal(r.values, want)
