@@ -90,6 +90,8 @@ def main():
                     help="second pass over each iteration's loaded partitions (the paper's asynchronous "
                          "scheduling); 2 = only resident and zero-copy partitions")
     ap.add_argument("--hub-sort", action="store_true", help="relabel hubs to the front when the graphs are loaded")
+    ap.add_argument("--no-pack", action="store_true",
+                    help="keep SSSP weights in their own array instead of packing them into the neighbour words")
     ap.add_argument("--rq-per-vertex", dest="rq_distinct", action="store_false",
                     help="zero-copy requests of the cost model as Eq. 3's per-vertex lines (default: the distinct "
                          "lines the zero-copy kernel actually reads)")
@@ -128,7 +130,7 @@ def main():
     log(f"probe: {json.dumps(probe)}")
 
     t0 = time.time()
-    g = hy.Graph(off, col, weights=w, check_col=False, hub_sort=args.hub_sort)
+    g = hy.Graph(off, col, weights=w, check_col=False, hub_sort=args.hub_sort, pack=not args.no_pack)
     # the per-mode workload loads the symmetrized graph only after the directed one is
     # closed, so that the two never hold pinned host memory at once
     gs = (hy.Graph(soff, scol, symmetric=True, check_col=False, hub_sort=args.hub_sort)
@@ -156,15 +158,17 @@ def main():
     if args.workload == "modes":
         return modes_workload(args, gname, g, (soff, scol), deg, srcs[:1], algos, gamma, probe, cgather)
 
-    def budget(h, arrays):
-        h.set_budget(int(args.budget_frac * 4 * arrays * h.m))
+    def budget(h, algo):
+        # a fraction of the edge bytes the graph holds for the algorithm (SSSP: neighbours and
+        # weights, or one packed word per edge)
+        h.set_budget(int(args.budget_frac * 4 * h.edge_arrays(algo) * h.m))
 
     kt = not args.no_kernel_timing
 
     # algorithmic edges of BFS and SSSP from s: out-edges of the vertices reachable from s
     # (SSSP reaches exactly the vertices BFS reaches), counted outside the timed region
     reach_edges = {}
-    budget(g, 1)
+    budget(g, "bfs")
     for s in srcs:
         lv = g.run("bfs", int(s)).values
         reach_edges[int(s)] = int(deg[lv != hy.UNREACHED].sum())
@@ -176,21 +180,21 @@ def main():
     def step(record):
         runs = []
         if "bfs" in algos:
-            budget(g, 1)
+            budget(g, "bfs")
             for s in srcs:
                 r = g.run("bfs", int(s), stats=True, time_kernels=kt and record, out=out_u32[: g.n])
                 runs.append(("bfs", r, reach_edges[int(s)]))
         if "pagerank" in algos:
-            budget(g, 1)
+            budget(g, "pagerank")
             r = g.run("pagerank", stats=True, time_kernels=kt and record, out=out_f32)
             runs.append(("pagerank", r, 20 * m))
         if "sssp" in algos:
-            budget(g, 2)
+            budget(g, "sssp")
             for s in srcs:
                 r = g.run("sssp", int(s), stats=True, time_kernels=kt and record, out=out_u32[: g.n])
                 runs.append(("sssp", r, reach_edges[int(s)]))
         if "cc" in algos:
-            budget(gs, 1)
+            budget(gs, "cc")
             r = gs.run("cc", stats=True, time_kernels=kt and record, out=out_u32[: gs.n])
             runs.append(("cc", r, gs.m))
         return runs
@@ -241,6 +245,7 @@ def main():
     workload = (gname + (f"-ef{args.edge_factor:g}" if args.graph == "rmat" else "")
                 + f"-budget{args.budget_frac:g}-{args.mode}"
                 + (f"-reprocess{args.reprocess}" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
+                + ("" if g.info()["packed_weights"] else "-unpacked")
                 + ("" if cgather[0] == 0 else "-gathercost") + ("-rqdistinct" if args.rq_distinct else ""))
     roofline = None
     kernels = {}
@@ -250,7 +255,7 @@ def main():
         items = np.zeros(8, dtype=np.int64)
         arrays_items = np.zeros(8)  # items weighted by edge arrays read
         for name, r, _ in all_runs:
-            a = 2 if name == "sssp" else 1
+            a = (gs if name == "cc" else g).edge_arrays(name)
             ms += np.array(r.stats["kernel_ms"])
             launches += np.array(r.stats["kernel_launches"], dtype=np.int64)
             it = np.array(r.stats["kernel_items"], dtype=np.int64)
@@ -342,7 +347,7 @@ def batch_workload(args, g, off, col, deg, gamma, probe):
     out_b = hy.pinned_empty((len(srcs), g.n), np.uint32)
     out_1 = hy.pinned_empty(g.n, np.uint32)
     for algo, arrays in (("bfs", 1), ("sssp", 2)):
-        g.set_budget(int(args.budget_frac * 4 * arrays * g.m))
+        g.set_budget(int(args.budget_frac * 4 * g.edge_arrays(algo) * g.m))
         g.run_batch(algo, srcs, out=out_b)  # warm-up
         times = []
         for _ in range(args.steps):
@@ -399,7 +404,7 @@ def modes_workload(args, gname, g, sym, deg, srcs, algos, gamma, probe, cgather)
                           compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct))
         for mode in args.modes.split(","):
             h = gs if a == "cc" else g
-            arrays = 2 if a == "sssp" else 1
+            arrays = h.edge_arrays(a)
             h.set_params(mode=mode)
             h.set_budget(int(args.budget_bytes) if args.budget_bytes else int(args.budget_frac * 4 * arrays * h.m))
             try:
@@ -510,7 +515,7 @@ def serve_workload(args, g, off, gamma, probe):
     srcs = gen.sources(off, args.queries, 6100 + args.scale)
     arrivals = np.cumsum(rng.exponential(1.0 / args.qps, size=args.queries))
     if args.budget_frac >= 0:
-        g.set_budget(int(args.budget_frac * 8 * g.m))  # planned for the weighted arrays
+        g.set_budget(int(args.budget_frac * 4 * g.edge_arrays("sssp") * g.m))  # planned for SSSP's edge words
     outs = {k: hy.pinned_empty(n, np.float32 if k == "ppr" else np.uint32) for k in ("bfs", "sssp", "ppr")}
     for k in ("bfs", "sssp", "ppr"):
         g.run(k, int(srcs[0]), out=outs[k])  # warm-up: buffers and resident cache

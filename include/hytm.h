@@ -92,7 +92,12 @@ enum {
        first, the other vertices keeping their natural order.  Sources and results stay in
        the caller's ids; partitions, hytm_partition_bounds and mode traces refer to the
        relabelled order.  Implies the col check. */
-    HYTM_GRAPH_HUB_SORT = 1u << 3
+    HYTM_GRAPH_HUB_SORT = 1u << 3,
+    /* keep weights in their own array.  By default, when ceil(log2 n) bits of neighbour id
+       and the bits of (max weight - min weight) fit one 32-bit word, the library stores
+       each edge as one word (neighbour low, weight - min above), so SSSP moves 4 bytes per
+       edge instead of 8; results are the same either way. */
+    HYTM_GRAPH_NO_PACK = 1u << 4
 };
 
 /* Tunables.  Defaults (hytm_default_params) are the constants the paper states:
@@ -236,6 +241,8 @@ typedef struct {
     int hip_device;
     uint32_t flags;
     uint64_t hubs;              /* vertices moved to the front by HYTM_GRAPH_HUB_SORT (else 0) */
+    uint32_t packed_weights;    /* 1 when weights share the neighbour words (see HYTM_GRAPH_NO_PACK) */
+    uint32_t reserved0;
 } hytm_graph_info;
 
 /* Fill *p with the paper's defaults listed above. */

@@ -28,6 +28,7 @@ ENGINE_NAMES = ["none", "resident", "filter", "zerocopy", "compact"]
 GRAPH_SYMMETRIC = 1 << 1
 GRAPH_SKIP_COL_CHECK = 1 << 2
 GRAPH_HUB_SORT = 1 << 3
+GRAPH_NO_PACK = 1 << 4
 UNCAPPED = (1 << 64) - 1
 UNREACHED = 0xFFFFFFFF
 
@@ -106,7 +107,7 @@ class QueryResult(ctypes.Structure):
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("m", ctypes.c_uint64), ("npart", ctypes.c_uint32),
                 ("max_partition_edges", ctypes.c_uint32), ("hip_device", ctypes.c_int), ("flags", ctypes.c_uint32),
-                ("hubs", ctypes.c_uint64)]
+                ("hubs", ctypes.c_uint64), ("packed_weights", ctypes.c_uint32), ("reserved0", ctypes.c_uint32)]
 
 
 # every exported entry point of include/hytm.h with its ctypes signature
@@ -264,7 +265,7 @@ class Graph:
     """A CSR graph whose edge arrays live in pinned host memory (libhytm handle)."""
 
     def __init__(self, off, col, weights=None, symmetric: bool = False, device: int = 0,
-                 check_col: bool = True, hub_sort: bool = False):
+                 check_col: bool = True, hub_sort: bool = False, pack: bool = True):
         lib = load()
         off = np.ascontiguousarray(off)
         if off.dtype not in (np.uint32, np.uint64):
@@ -276,7 +277,7 @@ class Graph:
         self.n = len(off) - 1
         self.m = len(col)
         flags = ((GRAPH_SYMMETRIC if symmetric else 0) | (0 if check_col else GRAPH_SKIP_COL_CHECK)
-                 | (GRAPH_HUB_SORT if hub_sort else 0))
+                 | (GRAPH_HUB_SORT if hub_sort else 0) | (0 if pack else GRAPH_NO_PACK))
         h = ctypes.c_void_p()
         self._keep = [np.zeros(1, np.uint32)]  # stand-in buffer for empty arrays
         colp = _ptr(col) if self.m else _ptr(self._keep[0])
@@ -358,10 +359,14 @@ class Graph:
         _check(load().hytm_staging_bytes(self._h, ALGOS[algo], ctypes.byref(b)))
         return int(b.value)
 
+    def edge_arrays(self, algo: str) -> int:
+        """4-byte words the graph holds per edge for `algo`: 2 for SSSP unless its weights are
+        packed into the neighbour words, else 1."""
+        return 2 if ALGOS[algo] == 1 and not self.info()["packed_weights"] else 1
+
     def set_resident_fraction(self, algo: str, frac: float):
         """Budget = the engines' staging + `frac` of the edge bytes `algo` reads."""
-        arrays = 2 if ALGOS[algo] == 1 else 1
-        self.set_budget(self.staging_bytes(algo) + int(frac * 4 * arrays * self.m))
+        self.set_budget(self.staging_bytes(algo) + int(frac * 4 * self.edge_arrays(algo) * self.m))
 
     def partition_bounds(self) -> np.ndarray:
         npart = self.info()["npart"]

@@ -71,6 +71,14 @@ struct Header {
     uint64_t frontier;       // all active vertices, including those without out-edges
 };
 
+// Edge word layout.  shift < 32: neighbour and weight share one word, neighbour in the low
+// `shift` bits, weight - wmin above them (the weight array is not read); shift = 32: the
+// word is the neighbour and weights, if any, come from their own array.
+struct Pack {
+    uint32_t mask;   // neighbour bits
+    uint32_t shift;  // weight position, 32 = not packed
+    uint32_t wmin;   // smallest weight, added back
+};
 // Vertex state an algorithm's push operator touches.
 struct AlgoState {
     int algo;
@@ -92,6 +100,7 @@ struct AlgoState {
     float* lacc;          // PPR: per-lane accumulators, zero between iterations
     uint32_t lshift;
     const float* inv_n;   // PageRank over a union of graphs: 1 / (vertices of v's graph), else null
+    Pack pk;              // how edge words are laid out
 };
 
 // PageRank keeps one accumulator copy per XCD; the apply step sums them.

@@ -652,6 +652,12 @@ __device__ __forceinline__ void block_prefix_max_u16(uint16_t* a, uint32_t count
 }
 
 // ------------------------------------------------------------- edge push
+// Decode an edge word (see Pack): the neighbour, and the weight from the word or from w.
+__device__ __forceinline__ uint32_t pk_v(uint32_t c, const Pack& pk) { return c & pk.mask; }
+__device__ __forceinline__ uint32_t pk_w(uint32_t c, uint32_t wraw, const Pack& pk) {
+    return pk.shift < 32 ? (c >> pk.shift) + pk.wmin : wraw;
+}
+
 constexpr int EDGE_THREADS = 256;
 constexpr int EDGE_IPB = 1024;  // edge items per workgroup pass
 
@@ -662,7 +668,7 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_push_edges(const uint32_t* __r
                                                              const uint64_t* __restrict__ off,
                                                              const uint32_t* __restrict__ col,
                                                              const uint32_t* __restrict__ w, uint64_t shift,
-                                                             Op op) {
+                                                             Op op, Pack pk) {
     __shared__ uint64_t s_pre[EDGE_IPB];
     __shared__ uint64_t s_st[EDGE_IPB];
     __shared__ uint32_t s_val[EDGE_IPB];
@@ -698,10 +704,10 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_push_edges(const uint32_t* __r
                 const uint32_t k = s_owner[q];
                 const uint64_t e = s_st[k] + (i0 + q - s_pre[k]);
                 v = col[e];
-                if (Op::weighted) wt = w[e];
+                if (Op::weighted && pk.shift == 32) wt = w[e];
                 val = s_val[k];
             }
-            push_if(op, ok, val, v, wt);
+            push_if(op, ok, val, pk_v(v, pk), Op::weighted ? pk_w(v, wt, pk) : 0u);
         }
         __syncthreads();
     }
@@ -720,7 +726,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
                                                              const uint64_t* __restrict__ off,
                                                              const uint32_t* __restrict__ col,
                                                              const uint32_t* __restrict__ w, Op op,
-                                                             unsigned long long* __restrict__ distinct) {
+                                                             unsigned long long* __restrict__ distinct, Pack pk) {
     __shared__ uint64_t s_pre[LINE_IPB];
     __shared__ uint64_t s_s[LINE_IPB];
     __shared__ uint64_t s_e[LINE_IPB];
@@ -778,12 +784,13 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
                     ok[r] = true;
                     kk[r] = lo;
                     cv[r] = col[e];
-                    if (Op::weighted) wv[r] = w[e];
+                    if (Op::weighted && pk.shift == 32) wv[r] = w[e];
                 }
             }
         }
 #pragma unroll
-        for (int r = 0; r < LINE_UNROLL; r++) push_if(op, ok[r], s_val[kk[r]], cv[r], wv[r]);
+        for (int r = 0; r < LINE_UNROLL; r++)
+            push_if(op, ok[r], s_val[kk[r]], pk_v(cv[r], pk), Op::weighted ? pk_w(cv[r], wv[r], pk) : 0u);
         __syncthreads();
     }
     if (distinct) {
@@ -1116,7 +1123,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
                                                                const uint32_t* __restrict__ list,
                                                                const uint64_t* __restrict__ off,
                                                                const uint32_t* __restrict__ col,
-                                                               const uint32_t* __restrict__ w, Op op) {
+                                                               const uint32_t* __restrict__ w, Op op, Pack pk) {
     constexpr uint32_t MAXE = FSTREAM_LINES * 32;  // edges per chunk (2048)
     constexpr int UNROLL = FSTREAM_LINES / LINE_HALVES;
     static_assert(MAXE <= 8 * LINE_THREADS, "owner map prefix covers 8 entries per thread");
@@ -1143,7 +1150,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
             wv[r] = 0;
             if (e >= ce0 && e < ce1) {
                 cv[r] = col[e];
-                if (Op::weighted) wv[r] = w[e];
+                if (Op::weighted && pk.shift == 32) wv[r] = w[e];
             }
         }
         // active vertices whose out-edge ranges meet [ce0, ce1): list entries [j0, j0 + nv)
@@ -1178,7 +1185,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
                     ok = q >= s_s[k] && q < s_e[k];
                     val = s_val[k];
                 }
-                push_if(op, ok, val, cv[r], wv[r]);
+                push_if(op, ok, val, pk_v(cv[r], pk), Op::weighted ? pk_w(cv[r], wv[r], pk) : 0u);
             }
         }
         __syncthreads();
@@ -1361,12 +1368,12 @@ hipError_t launch_build_lists(uint32_t npart, const uint32_t* pv, const uint64_t
 template <class Op>
 static hipError_t push_edges_op(const Op& op, const uint32_t* list, const uint64_t* wpre, uint32_t ja, uint32_t jb,
                                 uint64_t lo, uint64_t hi, const uint64_t* off, const uint32_t* col,
-                                const uint32_t* w, uint64_t shift, bool compacted, hipStream_t st) {
+                                const uint32_t* w, uint64_t shift, bool compacted, const Pack& pk, hipStream_t st) {
     const unsigned g = grid_for(hi - lo, EDGE_IPB, GRID_CAP);
     if (compacted)
-        k_push_edges<Op, true><<<g, EDGE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, shift, op);
+        k_push_edges<Op, true><<<g, EDGE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, shift, op, pk);
     else
-        k_push_edges<Op, false><<<g, EDGE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, shift, op);
+        k_push_edges<Op, false><<<g, EDGE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, shift, op, pk);
     return hipGetLastError();
 }
 
@@ -1378,37 +1385,37 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
     switch (s.algo) {
     case ALGO_BFS:
         return push_edges_op(OpBfs{s.visited, s.next, s.val, s.level_next}, list, wpre, ja, jb, item_lo, item_hi,
-                             off, col, w, shift, compacted, st);
+                             off, col, w, shift, compacted, s.pk, st);
     case ALGO_SSSP:
         return push_edges_op(OpSssp{s.val, s.next, s.overflow}, list, wpre, ja, jb, item_lo, item_hi, off, col, w,
-                             shift, compacted, st);
+                             shift, compacted, s.pk, st);
     case ALGO_CC:
         return push_edges_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
-                             compacted, st);
+                             compacted, s.pk, st);
     case ALGO_BFS_RELAX:
         return push_edges_op(OpBfsRelax{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
-                             compacted, st);
+                             compacted, s.pk, st);
     case ALGO_MBFS:
         return push_edges_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next, s.lshift}, list, wpre, ja, jb,
-                             item_lo, item_hi, off, col, w, shift, compacted, st);
+                             item_lo, item_hi, off, col, w, shift, compacted, s.pk, st);
     case ALGO_MSSSP:
         return push_edges_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow, s.lshift}, list, wpre, ja, jb, item_lo,
-                             item_hi, off, col, w, shift, compacted, st);
+                             item_hi, off, col, w, shift, compacted, s.pk, st);
     case ALGO_MPPR:
         return push_edges_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
-                             item_hi, off, col, w, shift, compacted, st);
+                             item_hi, off, col, w, shift, compacted, s.pk, st);
     default:
         return push_edges_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
-                             compacted, st);
+                             compacted, s.pk, st);
     }
 }
 
 template <class Op>
 static hipError_t push_lines_op(const Op& op, const uint32_t* list, const uint64_t* wpre, uint32_t ja, uint32_t jb,
                                 uint64_t lo, uint64_t hi, const uint64_t* off, const uint32_t* col,
-                                const uint32_t* w, unsigned long long* distinct, hipStream_t st) {
+                                const uint32_t* w, unsigned long long* distinct, const Pack& pk, hipStream_t st) {
     const unsigned g = grid_for(hi - lo, LINE_IPB, GRID_CAP);
-    k_push_lines<Op><<<g, LINE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, op, distinct);
+    k_push_lines<Op><<<g, LINE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, op, distinct, pk);
     return hipGetLastError();
 }
 
@@ -1419,24 +1426,24 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
     switch (s.algo) {
     case ALGO_BFS:
         return push_lines_op(OpBfs{s.visited, s.next, s.val, s.level_next}, list, wpre, ja, jb, item_lo, item_hi,
-                             off, col, w, distinct, st);
+                             off, col, w, distinct, s.pk, st);
     case ALGO_SSSP:
-        return push_lines_op(OpSssp{s.val, s.next, s.overflow}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, st);
+        return push_lines_op(OpSssp{s.val, s.next, s.overflow}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, s.pk, st);
     case ALGO_CC:
-        return push_lines_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, st);
+        return push_lines_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, s.pk, st);
     case ALGO_BFS_RELAX:
-        return push_lines_op(OpBfsRelax{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, st);
+        return push_lines_op(OpBfsRelax{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, s.pk, st);
     case ALGO_MBFS:
         return push_lines_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next, s.lshift}, list, wpre, ja, jb,
-                             item_lo, item_hi, off, col, w, distinct, st);
+                             item_lo, item_hi, off, col, w, distinct, s.pk, st);
     case ALGO_MSSSP:
         return push_lines_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow, s.lshift}, list, wpre, ja, jb, item_lo,
-                             item_hi, off, col, w, distinct, st);
+                             item_hi, off, col, w, distinct, s.pk, st);
     case ALGO_MPPR:
         return push_lines_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
-                             item_hi, off, col, w, distinct, st);
+                             item_hi, off, col, w, distinct, s.pk, st);
     default:
-        return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, st);
+        return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, s.pk, st);
     }
 }
 
@@ -1450,9 +1457,9 @@ hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, fl
 template <class Op>
 static hipError_t push_fstream_op(const Op& op, const FTask* tasks, uint32_t ntasks, uint64_t chunks,
                                   const uint32_t* list, const uint64_t* off, const uint32_t* col, const uint32_t* w,
-                                  hipStream_t st) {
+                                  const Pack& pk, hipStream_t st) {
     const unsigned g = (unsigned)(chunks < GRID_CAP ? chunks : GRID_CAP);
-    k_push_fstream<Op><<<g, LINE_THREADS, 0, st>>>(tasks, ntasks, chunks, list, off, col, w, op);
+    k_push_fstream<Op><<<g, LINE_THREADS, 0, st>>>(tasks, ntasks, chunks, list, off, col, w, op, pk);
     return hipGetLastError();
 }
 
@@ -1463,24 +1470,24 @@ hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t 
     switch (s.algo) {
     case ALGO_BFS:
         return push_fstream_op(OpBfs{s.visited, s.next, s.val, s.level_next}, tasks, ntasks, total_chunks, list,
-                               off, col, w, st);
+                               off, col, w, s.pk, st);
     case ALGO_SSSP:
-        return push_fstream_op(OpSssp{s.val, s.next, s.overflow}, tasks, ntasks, total_chunks, list, off, col, w, st);
+        return push_fstream_op(OpSssp{s.val, s.next, s.overflow}, tasks, ntasks, total_chunks, list, off, col, w, s.pk, st);
     case ALGO_CC:
-        return push_fstream_op(OpCc{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, st);
+        return push_fstream_op(OpCc{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, s.pk, st);
     case ALGO_BFS_RELAX:
-        return push_fstream_op(OpBfsRelax{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, st);
+        return push_fstream_op(OpBfsRelax{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, s.pk, st);
     case ALGO_MBFS:
         return push_fstream_op(OpMBfs{s.mcur, s.mnext, s.mvisited, s.lval, s.next, s.level_next, s.lshift}, tasks, ntasks,
-                               total_chunks, list, off, col, w, st);
+                               total_chunks, list, off, col, w, s.pk, st);
     case ALGO_MSSSP:
         return push_fstream_op(OpMSssp{s.mcur, s.mnext, s.lval, s.next, s.overflow, s.lshift}, tasks, ntasks, total_chunks,
-                               list, off, col, w, st);
+                               list, off, col, w, s.pk, st);
     case ALGO_MPPR:
         return push_fstream_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, tasks, ntasks, total_chunks,
-                               list, off, col, w, st);
+                               list, off, col, w, s.pk, st);
     default:
-        return push_fstream_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, tasks, ntasks, total_chunks, list, off, col, w, st);
+        return push_fstream_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, tasks, ntasks, total_chunks, list, off, col, w, s.pk, st);
     }
 }
 

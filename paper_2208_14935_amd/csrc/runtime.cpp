@@ -179,7 +179,9 @@ struct hytm_graph {
     // host side
     std::vector<uint64_t> h_off;      // n + 1
     uint32_t* h_col = nullptr;        // pinned, device-mapped
-    uint32_t* h_w = nullptr;          // pinned, device-mapped, or null
+    uint32_t* h_w = nullptr;          // pinned, device-mapped, or null (also when packed)
+    bool weighted = false;            // the graph has edge weights
+    Pack pk{0xFFFFFFFFu, 32, 0};      // edge word layout: weights packed into h_col when shift < 32
     uint32_t* d_col_map = nullptr;    // device addresses of the mapped arrays
     uint32_t* d_w_map = nullptr;
 
@@ -312,6 +314,10 @@ void partition_graph(hytm_graph* g) {
     HIP_CHECK(hipMemcpy(g->d_pv.p, g->pv.data(), g->pv.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     g->res_valid = false;
 }
+
+// Edge arrays an algorithm reads per edge: SSSP reads neighbours and weights, unless the
+// weights are packed into the neighbour words.
+uint32_t edge_arrays(const hytm_graph* g, int algo) { return algo == HYTM_SSSP && g->pk.shift == 32 ? 2 : 1; }
 
 SelParams make_sel(const hytm_graph* g, uint32_t arrays) {
     const hytm_params& p = g->params;
@@ -711,7 +717,7 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
 void init_ctx(RunCtx& rc, hytm_graph* g, int algo, bool batched, const Plan& pl, hytm_run_stats* stats) {
     rc.g = g;
     rc.algo = algo;
-    rc.arrays = algo == HYTM_SSSP ? 2 : 1;
+    rc.arrays = edge_arrays(g, algo);
     rc.batched = batched;
     rc.plan = pl;
     rc.stats = stats;
@@ -722,6 +728,7 @@ void init_ctx(RunCtx& rc, hytm_graph* g, int algo, bool batched, const Plan& pl,
     rc.nwords = (uint32_t)((g->n + 31) / 32);
     rc.as.n = g->n;
     rc.as.overflow = g->d_overflow.p;
+    rc.as.pk = g->pk;
 }
 
 // One engine pass over the frontier `cur` (Algorithm 1 plus the engines of Sec. 6.2),
@@ -1093,7 +1100,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     HIP_CHECK(hipSetDevice(g->device));
     ensure_streams(g);
     const double t_begin = now_ms();
-    const uint32_t arrays = algo == HYTM_SSSP ? 2 : 1;
+    const uint32_t arrays = edge_arrays(g, algo);
     const bool batched = lanes > 0;
     const uint32_t source = sources ? g->inner(sources[0]) : 0;
     hipStream_t main = hip_stream ? (hipStream_t)hip_stream : g->s_main;
@@ -1510,7 +1517,7 @@ hytm_status server_setup(hytm_server* s) {
     const uint32_t nwords = (uint32_t)((n + 31) / 32);
     Plan pl;
     Totals tot;
-    const uint32_t plan_arrays = s->cfg.lanes[1] ? 2 : 1;
+    const uint32_t plan_arrays = s->cfg.lanes[1] ? edge_arrays(g, HYTM_SSSP) : 1;
     hytm_status ps = prepare_graph(g, plan_arrays, main, &pl, &tot);
     if (ps != HYTM_OK) return ps;
     static const int algos[3] = {HYTM_BFS, HYTM_SSSP, HYTM_PPR};
@@ -1606,7 +1613,8 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
     if (n == 0) return fail(HYTM_E_INVAL, "graph has no vertices");
     if (n >= 0xFFFFFFFFull) return fail(HYTM_E_RANGE, "n = %llu: vertex ids must fit below 2^32-1", (unsigned long long)n);
     if (offset_bytes == 4 && m > 0xFFFFFFFFull) return fail(HYTM_E_INVAL, "m does not fit 4-byte offsets");
-    if (flags & ~(uint32_t)(HYTM_GRAPH_SYMMETRIC | HYTM_GRAPH_SKIP_COL_CHECK | HYTM_GRAPH_HUB_SORT))
+    if (flags & ~(uint32_t)(HYTM_GRAPH_SYMMETRIC | HYTM_GRAPH_SKIP_COL_CHECK | HYTM_GRAPH_HUB_SORT |
+                            HYTM_GRAPH_NO_PACK))
         return fail(HYTM_E_INVAL, "unknown flag bits 0x%x", flags);
     const bool hub_sort = flags & HYTM_GRAPH_HUB_SORT;
     hytm_graph* g = nullptr;
@@ -1653,23 +1661,46 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
         if (hip_device < 0 || hip_device >= count)
             return fail(HYTM_E_DEVICE, "HIP device %d does not exist (%d visible)", hip_device, count);
         HIP_CHECK(hipSetDevice(hip_device));
-        // edge arrays: pinned host memory mapped into the device address space
+        // edge arrays: pinned host memory mapped into the device address space.  When the
+        // neighbour ids and the weight range fit one 32-bit word together, the weights
+        // travel inside the neighbour words and SSSP moves 4 bytes per edge instead of 8.
+        g->weighted = weights != nullptr;
+        const unsigned threads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        if (weights && m && !(flags & HYTM_GRAPH_NO_PACK)) {
+            uint32_t wmin = UINT32_MAX, wmax = 0;
+            for (uint64_t e = 0; e < m; e++) {
+                wmin = std::min(wmin, weights[e]);
+                wmax = std::max(wmax, weights[e]);
+            }
+            uint32_t vbits = 1, wbits = 0;
+            while (vbits < 32 && (n - 1) >> vbits) vbits++;
+            while (wbits < 32 && ((uint64_t)(wmax - wmin) >> wbits)) wbits++;
+            if (vbits + wbits <= 32 && vbits < 32) g->pk = Pack{(1u << vbits) - 1, vbits, wmin};
+        }
+        const bool packed = g->pk.shift < 32;
         const size_t eb = std::max<uint64_t>(m, 1) * sizeof(uint32_t);
         HIP_CHECK(hipHostMalloc((void**)&g->h_col, eb, hipHostMallocMapped));
         HIP_CHECK(hipHostGetDevicePointer((void**)&g->d_col_map, g->h_col, 0));
-        if (weights) {
+        if (weights && !packed) {
             HIP_CHECK(hipHostMalloc((void**)&g->h_w, eb, hipHostMallocMapped));
             HIP_CHECK(hipHostGetDevicePointer((void**)&g->d_w_map, g->h_w, 0));
         }
+        std::vector<uint32_t> wtmp;  // relabelled weights on their way into the packed words
+        const uint32_t* wsrc = weights;
         if (hub_sort) {
             // relabel once, straight into the pinned arrays (Sec. 6.1)
-            const unsigned threads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
             std::vector<uint32_t> order(n);
             g->h_rank.resize(n);
             g->hubs = hub_order(n, g->h_off.data(), col, 8, 100, threads, order.data(), g->h_rank.data());
             std::vector<uint64_t> off2(n + 1);
+            uint32_t* w2 = g->h_w;
+            if (weights && packed) {
+                wtmp.resize(m);
+                w2 = wtmp.data();
+                wsrc = wtmp.data();
+            }
             hub_relabel(n, g->h_off.data(), col, weights, order.data(), g->h_rank.data(), threads, off2.data(),
-                        g->h_col, g->h_w);
+                        g->h_col, w2);
             g->h_off.swap(off2);
             g->d_rank.ensure(n);
             g->d_order.ensure(n);
@@ -1677,7 +1708,20 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
             HIP_CHECK(hipMemcpy(g->d_order.p, order.data(), n * 4, hipMemcpyHostToDevice));
         } else if (m) {
             parallel_copy(g->h_col, col, m * sizeof(uint32_t));
-            if (weights) parallel_copy(g->h_w, weights, m * sizeof(uint32_t));
+            if (weights && !packed) parallel_copy(g->h_w, weights, m * sizeof(uint32_t));
+        }
+        if (packed) {
+            const Pack pk = g->pk;
+            uint32_t* hc = g->h_col;
+            const uint64_t step = (m + threads - 1) / threads;
+            std::vector<std::thread> th;
+            for (unsigned t = 0; t < threads; t++) {
+                const uint64_t a = std::min<uint64_t>(m, t * step), b = std::min<uint64_t>(m, a + step);
+                th.emplace_back([=] {
+                    for (uint64_t e = a; e < b; e++) hc[e] |= (wsrc[e] - pk.wmin) << pk.shift;
+                });
+            }
+            for (auto& x : th) x.join();
         }
         g->d_off.ensure(n + 1);
         HIP_CHECK(hipMemcpy(g->d_off.p, g->h_off.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
@@ -1748,7 +1792,7 @@ hytm_status hytm_graph_set_parts(hytm_graph* g, uint32_t count, const uint64_t* 
             const uint32_t gi = graph_of(cv);
             inv[v] = (float)(1.0 / (double)(vertex_bounds[gi + 1] - vertex_bounds[gi]));
             for (uint64_t e = g->h_off[v]; e < g->h_off[v + 1]; e++) {
-                const uint64_t cu = caller(g->h_col[e]);
+                const uint64_t cu = caller(g->h_col[e] & g->pk.mask);
                 if (cu < vertex_bounds[gi] || cu >= vertex_bounds[gi + 1])
                     return fail(HYTM_E_INVAL, "edge %llu -> %llu leaves graph %u", (unsigned long long)cv,
                                 (unsigned long long)cu, gi);
@@ -1809,7 +1853,7 @@ hytm_status hytm_staging_bytes(const hytm_graph* g, hytm_algo algo, uint64_t* by
     if (!g || !bytes) return fail(HYTM_E_INVAL, "NULL argument");
     if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
     if (algo < HYTM_BFS || algo > HYTM_PAGERANK_DELTA) return fail(HYTM_E_INVAL, "unknown algorithm %d", (int)algo);
-    const Staging s = staging_of(g, algo == HYTM_SSSP ? 2 : 1);
+    const Staging s = staging_of(g, edge_arrays(g, algo));
     switch (g->params.mode) {
     case HYTM_MODE_FILTER: *bytes = s.f_bytes; break;
     case HYTM_MODE_COMPACT: *bytes = s.c_bytes; break;
@@ -1829,6 +1873,7 @@ hytm_status hytm_graph_info_get(const hytm_graph* g, hytm_graph_info* info) {
     info->hip_device = g->device;
     info->flags = g->flags;
     info->hubs = g->hubs;
+    info->packed_weights = g->pk.shift < 32 ? 1u : 0u;
     return HYTM_OK;
 }
 
@@ -1853,7 +1898,7 @@ hytm_status hytm_run(hytm_graph* g, hytm_algo algo, uint32_t source, void* value
         return fail(HYTM_E_INVAL, "stats.struct_size mismatch");
     if ((algo == HYTM_BFS || algo == HYTM_SSSP || algo == HYTM_PPR) && source >= g->n)
         return fail(HYTM_E_RANGE, "source %u >= n = %llu", source, (unsigned long long)g->n);
-    if (algo == HYTM_SSSP && !g->h_w) return fail(HYTM_E_INVAL, "SSSP needs edge weights");
+    if (algo == HYTM_SSSP && !g->weighted) return fail(HYTM_E_INVAL, "SSSP needs edge weights");
     if (algo == HYTM_CC && !(g->flags & HYTM_GRAPH_SYMMETRIC))
         return fail(HYTM_E_INVAL, "CC needs a graph created with HYTM_GRAPH_SYMMETRIC");
     if (algo == HYTM_PAGERANK && g->params.pr_iterations == 0)
@@ -1877,7 +1922,7 @@ hytm_status hytm_run_batch(hytm_graph* g, hytm_algo algo, const uint32_t* source
     for (uint32_t l = 0; l < nsources; l++)
         if (sources[l] >= g->n)
             return fail(HYTM_E_RANGE, "sources[%u] = %u >= n = %llu", l, sources[l], (unsigned long long)g->n);
-    if (algo == HYTM_SSSP && !g->h_w) return fail(HYTM_E_INVAL, "SSSP needs edge weights");
+    if (algo == HYTM_SSSP && !g->weighted) return fail(HYTM_E_INVAL, "SSSP needs edge weights");
     return guarded(
         [&] { return run_impl(g, algo, sources, nsources, values_out, iterations_out, stats, hip_stream); });
 }
@@ -2043,7 +2088,7 @@ hytm_status hytm_server_open(hytm_graph* g, const hytm_server_config* cfg, hytm_
         need += group_state_bytes(g->n, algos[k], cfg->lanes[k]);
     }
     if (!groups) return fail(HYTM_E_INVAL, "no lane group: every lanes[] entry is 0");
-    if (cfg->lanes[1] && !g->h_w) return fail(HYTM_E_INVAL, "an SSSP group needs edge weights");
+    if (cfg->lanes[1] && !g->weighted) return fail(HYTM_E_INVAL, "an SSSP group needs edge weights");
     if (cfg->state_budget && need > cfg->state_budget)
         return fail(HYTM_E_BUDGET, "lane state needs %llu bytes, state_budget is %llu", (unsigned long long)need,
                     (unsigned long long)cfg->state_budget);

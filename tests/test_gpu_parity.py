@@ -353,3 +353,35 @@ def test_zero_copy_counts_each_line_once(rmat16):
     assert st["zc_lines_distinct"] == want
     assert st["zc_lines_distinct"] <= st["zc_lines"]
     assert st["bytes_zerocopy"] == want * 128
+
+
+@pytest.mark.parametrize("mode", ["hybrid", "filter", "compact", "zerocopy"])
+@pytest.mark.parametrize("fe", ["stream", "copy"])
+def test_packed_and_separate_weights_agree(rmat16, mode, fe):
+    """Weights packed into the neighbour words (the default when they fit) and weights in
+    their own array give the oracle's distances under every engine, batched too."""
+    off, col, w = rmat16.off, rmat16.col, rmat16.w
+    want = rmat16.want("sssp", 0)[0]
+    srcs = np.array([0, 3, 77], dtype=np.uint32)
+    for pack in (True, False):
+        with hy.Graph(off, col, weights=w, pack=pack) as g:
+            assert g.info()["packed_weights"] == int(pack)
+            assert g.edge_arrays("sssp") == (1 if pack else 2)
+            g.set_params(mode=mode, filter_engine=fe, partition_edges=4096, compact_chunk_edges=1 << 16)
+            g.set_resident_fraction("sssp", 0.1 if mode in ("compact", "hybrid") else 0.0)
+            np.testing.assert_array_equal(g.run("sssp", 0).values, want)
+            vals, _, _ = g.run_batch("sssp", srcs)
+            for i, s in enumerate(srcs):
+                np.testing.assert_array_equal(vals[i], oracle.sssp(off, col, w, int(s)))
+
+
+def test_weights_too_wide_to_pack_stay_separate():
+    off, col = gen.rmat(10, 8, seed=3)
+    w = gen.weights(off, col, 5, maxw=(1 << 23))  # 10 id bits + 23 weight bits > 32
+    with hy.Graph(off, col, weights=w) as g:
+        assert g.info()["packed_weights"] == 0
+        np.testing.assert_array_equal(g.run("sssp", 1).values, oracle.sssp(off, col, w, 1))
+    w2 = np.full(len(col), 7, dtype=np.uint32)  # one weight: no weight bits at all
+    with hy.Graph(off, col, weights=w2) as g:
+        assert g.info()["packed_weights"] == 1
+        np.testing.assert_array_equal(g.run("sssp", 1).values, oracle.sssp(off, col, w2, 1))
