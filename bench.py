@@ -31,9 +31,9 @@ HBM_PEAK_GBPS = 8000.0
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the factors read off the probe's device copy of
 # known size), mean per launch of the timed step.  It holds only for the kernel source and
 # workload it was measured on; otherwise the roofline reports traffic null.
-PMC_TRAFFIC = {"kernel": "push_filter", "workload": "rmat24-ef16-budget0.25-hybrid",
-               "kernels_sha256": "25cc50230ef3d240e97667df86712d988b8577d02ff0f10a8036adfc93de8fbf",
-               "bytes_per_launch": (2 * 1167379 + 1201606) * 1024.0,
+PMC_TRAFFIC = {"kernel": "push_filter", "workload": "rmat24-ef16-budget0.25-hybrid-rqdistinct",
+               "kernels_sha256": "2a15512200553956306880cd3d594a96720007427f73e221a8a6c034e1427b86",
+               "bytes_per_launch": (2 * 1046351 + 1159771) * 1024.0,
                "summary": "profiles/pmc_traffic_rmat24_budget25_hybrid.md"}
 PCIE_GEN5_X16_GBPS = 63.0
 
