@@ -238,7 +238,7 @@ struct hytm_graph {
     // streams / events
     hipStream_t s_main = nullptr, s_copy = nullptr, s_fk = nullptr, s_zc = nullptr, s_c = nullptr;
     hipEvent_t ev_copied[kMaxSlots] = {}, ev_free[kMaxSlots] = {};
-    hipEvent_t ev_cdone[2] = {}, ev_join[4] = {}, ev_start = nullptr, ev_clist = nullptr;
+    hipEvent_t ev_cdone[2] = {}, ev_join[4] = {}, ev_start = nullptr, ev_clist = nullptr, ev_go = nullptr;
 
     Pool* pool = nullptr;
     KTimer timer;
@@ -447,6 +447,7 @@ void ensure_streams(hytm_graph* g) {
     for (auto& e : g->ev_join) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIP_CHECK(hipEventCreateWithFlags(&g->ev_start, hipEventDisableTiming));
     HIP_CHECK(hipEventCreateWithFlags(&g->ev_clist, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&g->ev_go, hipEventDisableTiming));
 }
 
 void release_all(hytm_graph* g) {
@@ -509,6 +510,7 @@ void release_all(hytm_graph* g) {
         if (e) (void)hipEventDestroy(e);
     if (g->ev_start) (void)hipEventDestroy(g->ev_start);
     if (g->ev_clist) (void)hipEventDestroy(g->ev_clist);
+    if (g->ev_go) (void)hipEventDestroy(g->ev_go);
     delete g->pool;
     g->pool = nullptr;
     g->timer.destroy();
@@ -558,6 +560,16 @@ struct RunCtx {
     uint64_t *mcur = nullptr, *mnxt = nullptr; // lane masks
     LaneSet ppr{};                             // PPR lanes stepping, restarted at their sources
     bool reprocess = false;                    // second pass over loaded partitions (Sec. 6.1)
+    // PageRank's frontier is every vertex in every iteration, so the first iteration's
+    // selection, lists and filter tasks hold for all of them: later iterations replay them
+    struct {
+        bool ok = false;
+        Header h{};
+        uint32_t ftasks = 0;
+        uint64_t fchunks = 0, fbytes = 0;
+    } replay;
+    uint32_t last_ftasks = 0;                  // streaming filter tasks of the last pass
+    uint64_t last_fchunks = 0;
     uint32_t t = 0;                            // iterations taken
     Totals tot;
 };
@@ -882,6 +894,8 @@ hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Heade
                 gidx++;
                 i = j;
             }
+            rc.last_ftasks = fstream ? gidx : 0;
+            rc.last_fchunks = fstream ? chunks : 0;
             if (fstream && gidx) {
                 // one launch streams every filter task of the pass
                 HIP_CHECK(hipMemcpyAsync(g->d_tasks.p, g->h_tasks.p, gidx * sizeof(FTask), hipMemcpyHostToDevice,
@@ -932,6 +946,58 @@ void record_iteration(RunCtx& rc, hytm_iter_stats& rec, uint32_t t, double t_it)
     }
 }
 
+// PageRank iterations after the first: the same pushes over the same lists and filter
+// tasks, ordered after the main stream's prepare by an event instead of a host round trip.
+hytm_status replay_pass(RunCtx& rc, hipStream_t main, hytm_iter_stats* rec, int64_t trace_t) {
+    hytm_graph* g = rc.g;
+    KTimer& kt = g->timer;
+    AlgoState& as = rc.as;
+    const uint32_t npart = g->npart;
+    const Header& h = rc.replay.h;
+    uint32_t scheduled = 0;
+    for (int s = 0; s < NSEG; s++) {
+        rec->parts[s + 1] += h.seg_parts[s];
+        scheduled += h.seg_parts[s];
+    }
+    rec->parts[0] += npart - scheduled;
+    rec->active_vertices += h.total_active;
+    for (int s = 0; s < NSEG; s++) rec->active_edges += h.seg_edges[s];
+    hytm_run_stats* stats = rc.stats;
+    if (trace_t >= 0 && stats && stats->mode_trace && (uint64_t)(trace_t + 1) * npart <= stats->mode_trace_cap)
+        memcpy(stats->mode_trace + (uint64_t)trace_t * npart, g->h_mode.p, npart);
+    HIP_CHECK(hipEventRecord(g->ev_go, main));
+    if (h.seg_list_count[SEG_R])
+        HIP_CHECK(kt.run(HYTM_K_PUSH_RES, h.seg_work_total[SEG_R], main, [&] {
+            return launch_push_edges(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_R],
+                                     h.seg_list_start[SEG_R] + h.seg_list_count[SEG_R], h.seg_work_start[SEG_R],
+                                     h.seg_work_start[SEG_R] + h.seg_work_total[SEG_R], g->d_off.p, g->d_res_col.p,
+                                     g->d_res_w.p, 0, false, main);
+        }));
+    if (h.seg_list_count[SEG_Z]) {
+        HIP_CHECK(hipStreamWaitEvent(g->s_zc, g->ev_go, 0));
+        HIP_CHECK(kt.run(HYTM_K_PUSH_ZC, h.seg_work_total[SEG_Z], g->s_zc, [&] {
+            return launch_push_lines(as, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_Z],
+                                     h.seg_list_start[SEG_Z] + h.seg_list_count[SEG_Z], h.seg_work_start[SEG_Z],
+                                     h.seg_work_start[SEG_Z] + h.seg_work_total[SEG_Z], g->d_off.p, g->d_col_map,
+                                     g->d_w_map, (unsigned long long*)g->d_zcl.p, g->s_zc);
+        }));
+        rec->zc_lines += h.seg_work_total[SEG_Z];
+    }
+    if (rc.replay.ftasks) {
+        HIP_CHECK(hipStreamWaitEvent(g->s_fk, g->ev_go, 0));
+        HIP_CHECK(kt.run(HYTM_K_PUSH_F, rc.replay.fbytes / (4ull * rc.arrays), g->s_fk, [&] {
+            return launch_push_fstream(as, g->d_tasks.p, rc.replay.ftasks, rc.replay.fchunks, g->d_list.p,
+                                       g->d_off.p, g->d_col_map, g->d_w_map, g->s_fk);
+        }));
+        rec->filter_tasks += rc.replay.ftasks;
+        rec->bytes_filter += rc.replay.fbytes;
+    }
+    HIP_CHECK(hipEventRecord(g->ev_join[0], g->s_fk));
+    HIP_CHECK(hipEventRecord(g->ev_join[1], g->s_zc));
+    for (int q = 0; q < 2; q++) HIP_CHECK(hipStreamWaitEvent(main, g->ev_join[q], 0));
+    return HYTM_OK;
+}
+
 // One iteration of a traversal.  *lanes_out: batched runs: the lanes with a non-empty
 // frontier at the start of the iteration.  *empty_out: BFS/SSSP/CC only: the frontier was
 // empty, nothing was pushed and the traversal is over.
@@ -954,7 +1020,24 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
     Header h;
     *lanes_out = 0;
     *empty_out = false;
-    hytm_status st = engine_pass(rc, rc.cur, main, &h, rc.batched ? lanes_out : nullptr, !fixed_steps, &rec, t);
+    hytm_status st;
+    if (rc.replay.ok) {
+        st = replay_pass(rc, main, &rec, t);
+        h = rc.replay.h;
+    } else {
+        st = engine_pass(rc, rc.cur, main, &h, rc.batched ? lanes_out : nullptr, !fixed_steps, &rec, t);
+        // PageRank with every engine but compaction (whose host gather needs the host each
+        // iteration), or with the copy-form filter (its per-task copies are host calls),
+        // replays this selection from now on
+        if (st == HYTM_OK && rc.algo == HYTM_PAGERANK && h.seg_list_count[SEG_C] == 0 &&
+            (h.seg_list_count[SEG_F] == 0 || g->params.filter_engine == HYTM_FILTER_STREAM)) {
+            rc.replay.ok = true;
+            rc.replay.h = h;
+            rc.replay.ftasks = rc.last_ftasks;
+            rc.replay.fchunks = rc.last_fchunks;
+            rc.replay.fbytes = rec.bytes_filter;
+        }
+    }
     if (st != HYTM_OK) return st;
     if (!fixed_steps && h.frontier == 0) {
         *empty_out = true;
