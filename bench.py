@@ -536,8 +536,10 @@ def serve_workload(args, g, off, gamma, probe):
     # result buffers per kind: enough for every query of the kind in flight or queued, up to
     # 2 x lanes; latency counts from the scheduled arrival, so a submit held back by a
     # missing buffer is charged to the server
+    # (pinned result memory is capped at about 16 GB in all)
+    per_kind = max(4, int(16e9 // (3 * 4 * max(n, 1))))
     bufs = {k: [hy.pinned_empty(n, np.float32 if k == "ppr" else np.uint32)
-                for _ in range(min(2 * lanes, int((kinds == k).sum()) or 1))] for k in ("bfs", "sssp", "ppr")}
+                for _ in range(min(2 * lanes, per_kind, int((kinds == k).sum()) or 1))] for k in ("bfs", "sssp", "ppr")}
     with hy.Server(g, bfs=lanes, sssp=lanes, ppr=lanes) as srv:
         warm = [srv.submit(k, int(srcs[0])) for k in ("bfs", "sssp", "ppr")]
         for q in warm:

@@ -1405,6 +1405,8 @@ struct LaneGroup {
     DevBuf<float> lx, lacc;
     uint64_t occupied = 0;  // lanes holding a query (changed by the worker only, under the lock)
     uint64_t fresh = 0;     // lanes admitted since the last step
+    double vtime = 0;       // worker time spent on this group (fair sharing between groups)
+    bool was_busy = false;
     std::shared_ptr<Query> q[MAX_LANES];
     uint32_t src[MAX_LANES] = {}, base[MAX_LANES] = {}, iters[MAX_LANES] = {}, left[MAX_LANES] = {};
 
@@ -1522,8 +1524,30 @@ void serve_loop(hytm_server* s) {
                     it = s->pending.erase(it);
                 }
             }
+            // Fair sharing: step only the busy group that has used the least worker time, so
+            // short BFS/SSSP steps interleave with long dense PPR steps instead of waiting
+            // behind them; a group that turns busy starts at the current minimum.
+            double base = 1e300;
+            for (const LaneGroup& gr : s->grp)
+                if (gr.was_busy && gr.occupied) base = std::min(base, gr.vtime);
+            LaneGroup* pick = nullptr;
             for (LaneGroup& gr : s->grp) {
-                if (!gr.occupied) continue;
+                if (!gr.occupied) {
+                    gr.was_busy = false;
+                    continue;
+                }
+                if (!gr.was_busy && base < 1e300) gr.vtime = std::max(gr.vtime, base);
+                gr.was_busy = true;
+                if (!pick || gr.vtime < pick->vtime) pick = &gr;
+            }
+            for (LaneGroup* pg : {pick}) {
+                if (!pg) continue;
+                LaneGroup& gr = *pg;
+                struct Clock {
+                    double& acc;
+                    double t0 = now_ms();
+                    ~Clock() { acc += now_ms() - t0; }
+                } clock{gr.vtime};
                 if (gr.fresh) {
                     LaneSet set{};
                     set.mask = gr.fresh;
