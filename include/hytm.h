@@ -406,7 +406,9 @@ hytm_status hytm_server_wait(hytm_server *s, uint64_t ticket, double timeout_ms,
 
 /* Finish every queued query, stop the worker, free the lane state and release the graph.
    Tickets not waited for are dropped.  Returns the error that stopped the worker, if a
-   step failed (every query then failed with it).  NULL is accepted. */
+   step failed (every query then failed with it).  NULL is accepted.  The handle is freed:
+   no other thread may be inside, or later enter, hytm_server_submit / hytm_server_wait on
+   it (submit and wait from several threads are otherwise safe). */
 hytm_status hytm_server_close(hytm_server *s);
 
 /* Free everything the handle owns.  NULL is accepted; E_STATE while a query server is
