@@ -34,7 +34,7 @@ def build() -> str:
 class _CostParams(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint32) for k in (
         "line_bytes", "max_outstanding", "d1", "d2", "alpha_num", "alpha_den",
-        "beta_num", "beta_den", "gamma_num", "gamma_den", "gather_num", "gather_den")]
+        "beta_num", "beta_den", "gamma_num", "gamma_den", "gather_num", "gather_den", "zc_tie")]
 
 
 @dataclass
@@ -49,11 +49,12 @@ class CostParams:
     beta: tuple = (2, 5)
     gamma: tuple = (5, 8)
     gather: tuple = (0, 1)  # link rate / host gather rate; (0, 1) = the paper's transfer-only Tec
+    zc_tie: int = 0  # 1: a Tiz = Tef tie goes to zero-copy instead of filter
 
     def _c(self):
         return _CostParams(self.line_bytes, self.max_outstanding, self.d1, self.d2,
                            self.alpha[0], self.alpha[1], self.beta[0], self.beta[1],
-                           self.gamma[0], self.gamma[1], self.gather[0], self.gather[1])
+                           self.gamma[0], self.gamma[1], self.gather[0], self.gather[1], self.zc_tie)
 
 
 def _load():

@@ -412,6 +412,7 @@ typedef struct {
     uint32_t beta_num, beta_den;    /* 2/5 */
     uint32_t gamma_num, gamma_den;  /* 5/8 */
     uint32_t gather_num, gather_den; /* 0/1: link rate / host gather rate (extension, see below) */
+    uint32_t zc_tie;                /* 0: a Tiz = Tef tie goes to filter (the prose); 1: to zero-copy */
 } orc_cost_params;
 
 /* Engine selection for every partition (Sec. 5.1, Algorithm 1 cost analysis), with
@@ -430,7 +431,9 @@ typedef struct {
    with gather = link rate / host gather rate > 0, the host gather of the active edges is
    priced in the same units, Tgc = ceil(Ea_i * d1 * gather / m / MR), and since gathering
    and copying run as a pipeline, compaction costs max(Tec, Tgc).  gather = 0 is the
-   paper's rule. */
+   paper's rule.
+   zc_tie = 1 hands a Tiz = Tef tie to zero-copy, for hosts whose full-line zero-copy reads
+   are as fast as explicit copies (the tie then means equal bytes at an equal rate). */
 void orc_select(uint64_t npart, const uint64_t *E, const uint64_t *nA, const uint64_t *Ea, const uint64_t *Rq,
                 uint64_t nres, const orc_cost_params *cp, int force, unsigned char *p) {
     const u128 L = (u128)cp->line_bytes * cp->max_outstanding;
@@ -452,7 +455,7 @@ void orc_select(uint64_t npart, const uint64_t *E, const uint64_t *nA, const uin
         rat Tiz = rat_mul(rat_make(ceil_div(Rq[i], cp->max_outstanding), 1), RTTzc);
         if (rat_lt(Tec, rat_mul(alpha, Tef)) && rat_lt(Tec, rat_mul(beta, Tiz)))
             p[i] = ORC_COMPACT;
-        else if (rat_lt(Tiz, Tef))
+        else if (rat_lt(Tiz, Tef) || (cp->zc_tie && !rat_lt(Tef, Tiz)))
             p[i] = ORC_ZEROCOPY;
         else
             p[i] = ORC_FILTER;

@@ -254,3 +254,12 @@ def test_distinct_lines_match_a_set_of_touched_lines(deg, target, data):
                     lines.update(range(int(off[v]) * 4 // 128, (int(off[v + 1]) * 4 - 1) // 128 + 1))
             assert rq[i] == arrays * len(lines)
             assert rq[i] <= rq_pv[i]  # never more than one request per vertex line
+
+
+def test_select_tie_rule_parameter():
+    # the w1 tie (Tiz = Tef = 4) goes to zero-copy with zc_tie; a strict Tef < Tiz stays filter
+    E, nA, Ea, Rq = one_partition([32] * 1024, [1] * 1024)
+    assert oracle.select(E, nA, Ea, Rq, params=CostParams(zc_tie=1))[0] == ZEROCOPY
+    E2, nA2, Ea2, Rq2 = one_partition([33] * 1024, [1] * 1024)  # misaligned lists: Rq > lines
+    assert int(Rq2[0]) > (int(Ea2[0]) * 4 + 127) // 128
+    assert oracle.select(E2, nA2, Ea2, Rq2, params=CostParams(zc_tie=1))[0] == FILTER
