@@ -96,6 +96,9 @@ def main():
                     help="zero-copy requests of the cost model as Eq. 3's per-vertex lines (default: the distinct "
                          "lines the zero-copy kernel actually reads)")
     ap.add_argument("--rq-distinct", dest="rq_distinct", action="store_true")
+    ap.add_argument("--zc-tie", default="probe",
+                    help="where a Tiz = Tef tie goes: 'probe' (zero-copy when full-line zero-copy reads reach the "
+                         "measured copy rate), 'filter' (the paper) or 'zerocopy'")
     ap.add_argument("--compact-gather", default="off",
                     help="host-gather term of the compaction cost: 'off' (the paper's rule), 'probe' (link rate / "
                          "measured gather rate) or num/den")
@@ -146,17 +149,20 @@ def main():
         a, b_ = args.compact_gather.split("/")
         cgather = (int(a), int(b_))
     log(f"compaction gather cost = {cgather[0]}/{cgather[1]}")
+    zc_tie = {"filter": 0, "zerocopy": 1}.get(args.zc_tie,
+                                              int(probe["zc_read_gbps"]["128B"] >= probe["h2d_copy_gbps"]))
+    log(f"tie to zero-copy = {zc_tie}")
     for h in (g, gs):
         if h is not None:
             h.set_params(mode=args.mode, partition_edges=args.partition_edges, combine_k=args.combine_k,
                          filter_engine=args.filter_engine, gamma=gamma, reprocess=int(args.reprocess),
-                         compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct))
+                         compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct), zc_tie=zc_tie)
     if args.workload == "batch":
         return batch_workload(args, g, off, col, deg, gamma, probe)
     if args.workload == "serve":
         return serve_workload(args, g, off, gamma, probe)
     if args.workload == "modes":
-        return modes_workload(args, gname, g, (soff, scol), deg, srcs[:1], algos, gamma, probe, cgather)
+        return modes_workload(args, gname, g, (soff, scol), deg, srcs[:1], algos, gamma, probe, cgather, zc_tie)
 
     def budget(h, algo):
         # a fraction of the edge bytes the graph holds for the algorithm (SSSP: neighbours and
@@ -246,7 +252,8 @@ def main():
                 + f"-budget{args.budget_frac:g}-{args.mode}"
                 + (f"-reprocess{args.reprocess}" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
                 + ("" if g.info()["packed_weights"] else "-unpacked")
-                + ("" if cgather[0] == 0 else "-gathercost") + ("-rqdistinct" if args.rq_distinct else ""))
+                + ("" if cgather[0] == 0 else "-gathercost") + ("-rqdistinct" if args.rq_distinct else "")
+                + ("-zctie" if zc_tie else ""))
     roofline = None
     kernels = {}
     if kt:
@@ -254,6 +261,7 @@ def main():
         launches = np.zeros(8, dtype=np.int64)
         items = np.zeros(8, dtype=np.int64)
         arrays_items = np.zeros(8)  # items weighted by edge arrays read
+        zc_bytes = 0  # lines the zero-copy kernel really read (a line two lists share counts once)
         for name, r, _ in all_runs:
             a = (gs if name == "cc" else g).edge_arrays(name)
             ms += np.array(r.stats["kernel_ms"])
@@ -261,6 +269,7 @@ def main():
             it = np.array(r.stats["kernel_items"], dtype=np.int64)
             items += it
             arrays_items += it * a
+            zc_bytes += r.stats["zc_lines_distinct"] * 128 * a
         for c, nm in enumerate(hy.KERNEL_CLASSES):
             kernels[nm] = {"ms": ms[c] / args.steps, "launches": int(launches[c]) // args.steps,
                            "items": int(items[c]) // args.steps}
@@ -268,12 +277,12 @@ def main():
         avg_ms = ms[dom] / max(launches[dom], 1)
         name = hy.KERNEL_CLASSES[dom]
         # algorithmic bytes per launch.  Kernels reading the mapped host arrays are priced
-        # against the host link: the zero-copy kernel moves 128 B per line item per edge
-        # array, the streaming filter kernel 4 B per edge of its tasks per edge array.
+        # against the host link: the zero-copy kernel moves 128 B per distinct line it reads
+        # per edge array, the streaming filter kernel 4 B per edge of its tasks per edge array.
         # Kernels reading device memory are priced against HBM: 4 B per edge per array
         # plus one 4-byte vertex value touched per edge.
         if name == "push_zerocopy":
-            per_launch = arrays_items[dom] * 128 / max(launches[dom], 1)
+            per_launch = zc_bytes / max(launches[dom], 1)
             bound, peak = "pcie", PCIE_GEN5_X16_GBPS
         elif name == "push_filter" and args.filter_engine == "stream":
             per_launch = arrays_items[dom] * 4 / max(launches[dom], 1)
@@ -381,7 +390,7 @@ def batch_workload(args, g, off, col, deg, gamma, probe):
     print(json.dumps(out), flush=True)
 
 
-def modes_workload(args, gname, g, sym, deg, srcs, algos, gamma, probe, cgather):
+def modes_workload(args, gname, g, sym, deg, srcs, algos, gamma, probe, cgather, zc_tie):
     """Every algorithm under each transfer mode at one device budget (one warm-up run, then
     one timed run that reuses the resident prefix; absolute
     --budget-bytes, else --budget-frac of the algorithm's edge bytes): GTEPS and the host
@@ -401,7 +410,7 @@ def modes_workload(args, gname, g, sym, deg, srcs, algos, gamma, probe, cgather)
             gs = hy.Graph(sym[0], sym[1], symmetric=True, check_col=False, hub_sort=args.hub_sort)
             gs.set_params(partition_edges=args.partition_edges, combine_k=args.combine_k,
                           filter_engine=args.filter_engine, gamma=gamma, reprocess=int(args.reprocess),
-                          compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct))
+                          compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct), zc_tie=zc_tie)
         for mode in args.modes.split(","):
             h = gs if a == "cc" else g
             arrays = h.edge_arrays(a)

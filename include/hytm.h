@@ -141,6 +141,10 @@ typedef struct {
                                    per-vertex requests).  1: Rq counts the different m-byte lines the
                                    active lists of a partition touch -- what the zero-copy kernel
                                    reads, since it loads a line two consecutive lists share once. */
+    uint32_t zc_tie;            /* 0: a Tiz = Tef tie selects filter, as the paper's prose says.  1: it
+                                   selects zero-copy -- for hosts where full-line zero-copy reads run
+                                   at the copy engine's rate (hytm_link_probe), so equal bytes cost
+                                   equal time and zero-copy skips the whole-partition pass. */
 } hytm_params;
 
 /* How a FILTER task moves its whole partition range to the GPU.  Both transfer every

@@ -52,7 +52,7 @@ class Params(ctypes.Structure):
         ("ppr_iterations", ctypes.c_uint32), ("reprocess", ctypes.c_uint32),
         ("dpr_max_iterations", ctypes.c_uint32), ("dpr_epsilon", ctypes.c_double),
         ("compact_gather_num", ctypes.c_uint32), ("compact_gather_den", ctypes.c_uint32),
-        ("rq_distinct_lines", ctypes.c_uint32),
+        ("rq_distinct_lines", ctypes.c_uint32), ("zc_tie", ctypes.c_uint32),
     ]
 
 

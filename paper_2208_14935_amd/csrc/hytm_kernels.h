@@ -56,6 +56,7 @@ struct SelParams {
     uint32_t allow_filter, allow_compact; // engines whose staging fits the budget
     uint32_t gn_c, gd_c;  // host gather cost: link rate / gather rate = gn_c / gd_c (0 = off)
     uint32_t rq_distinct; // zero-copy requests: 0 = per vertex (Eq. 3), 1 = distinct lines touched
+    uint32_t zc_tie;      // 1: a Tiz = Tef tie selects zero-copy instead of filter
 };
 
 // Written by the scan kernel, copied to the host every iteration.

@@ -138,7 +138,8 @@ __device__ __forceinline__ uint8_t select_engine(uint64_t E, uint64_t nA, uint64
     const bool c1 = (u128)sp.ad * tec < (u128)sp.an * tef;
     const bool c2 = (u128)sp.bd * sp.gd * E * tec < (u128)sp.bn * q * zfac;
     if (c1 && c2 && sp.allow_compact) return P_COMPACT;
-    if ((u128)q * zfac < (u128)sp.gd * E * tef) return P_ZC;
+    const u128 zl = (u128)q * zfac, zr = (u128)sp.gd * E * tef;
+    if (zl < zr || (sp.zc_tie && zl == zr)) return P_ZC;
     return sp.allow_filter ? P_FILTER : P_ZC;
 }
 

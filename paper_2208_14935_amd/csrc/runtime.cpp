@@ -277,6 +277,7 @@ bool params_valid(const hytm_params& p, std::string* why) {
     if (!(p.pr_damping >= 0.0 && p.pr_damping <= 1.0)) return bad("pr_damping must be in [0, 1]");
     if (p.reprocess > 2) return bad("reprocess must be 0, 1 or 2");
     if (p.rq_distinct_lines > 1) return bad("rq_distinct_lines must be 0 or 1");
+    if (p.zc_tie > 1) return bad("zc_tie must be 0 or 1");
     if (!frac_ok(p.compact_gather_num, p.compact_gather_den, false))
         return bad("compact_gather must be num/den with den in 1..65536");
     if (!(p.dpr_epsilon >= 0.0)) return bad("dpr_epsilon must be >= 0");
@@ -345,6 +346,7 @@ SelParams make_sel(const hytm_graph* g, uint32_t arrays) {
     sp.gn_c = p.compact_gather_num;
     sp.gd_c = p.compact_gather_den;
     sp.rq_distinct = p.rq_distinct_lines;
+    sp.zc_tie = p.zc_tie;
     return sp;
 }
 
@@ -1703,6 +1705,7 @@ void hytm_default_params(hytm_params* p) {
     p->compact_gather_num = 0;
     p->compact_gather_den = 1;
     p->rq_distinct_lines = 0;
+    p->zc_tie = 0;
     p->streams = 4;
     p->gather_threads = 0;
     p->compact_chunk_edges = 0;

@@ -165,16 +165,17 @@ def test_hybrid_uses_several_engines_and_moves_fewer_bytes_than_filter(rmat16):
 
 
 # --------------------------------------------------- selection parity
-@pytest.mark.parametrize("pe,distinct,gamma", [(4096, False, (5, 8)), (4096, True, (5, 8)),
-                                              (1 << 18, True, (1, 1)), (1 << 18, False, (1, 1))])
-def test_bfs_engine_trace_matches_oracle_selection(rmat16, pe, distinct, gamma):
+@pytest.mark.parametrize("pe,distinct,gamma,tie", [(4096, False, (5, 8), 0), (4096, True, (5, 8), 0),
+                                                  (1 << 18, True, (1, 1), 0), (1 << 18, False, (1, 1), 0),
+                                                  (4096, True, (1, 1), 1), (1 << 18, True, (1, 1), 1)])
+def test_bfs_engine_trace_matches_oracle_selection(rmat16, pe, distinct, gamma, tie):
     """BFS frontiers are unique (level t), so the per-iteration engine vector is pinned --
     with Eq. 3's per-vertex requests or with distinct lines (partitions of 2^18 edges span
     more than one 256-word pass of the statistics kernel)."""
     note(f"rmat16 bfs engine trace pe={pe} distinct={distinct}")
     lvl, it = rmat16.want("bfs", 0)
     with rmat16.graph("bfs") as g:
-        g.set_params(partition_edges=pe, rq_distinct_lines=int(distinct), gamma=gamma)
+        g.set_params(partition_edges=pe, rq_distinct_lines=int(distinct), gamma=gamma, zc_tie=tie)
         g.set_resident_fraction("bfs", 0.25)
         res = g.run("bfs", 0, trace=True, stats=True)
         check(rmat16, "bfs", res)
@@ -185,7 +186,7 @@ def test_bfs_engine_trace_matches_oracle_selection(rmat16, pe, distinct, gamma):
     assert res.mode_trace.shape == (it, len(E))
     for t in range(it):
         nA, Ea, Rq = oracle.partition_stats(bounds, rmat16.off, lvl == t, arrays=1, distinct=distinct)
-        want = oracle.select(E, nA, Ea, Rq, nres=nres, params=oracle.CostParams(gamma=gamma))
+        want = oracle.select(E, nA, Ea, Rq, nres=nres, params=oracle.CostParams(gamma=gamma, zc_tie=tie))
         np.testing.assert_array_equal(res.mode_trace[t], want, err_msg=f"iteration {t}")
 
 
