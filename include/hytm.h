@@ -145,6 +145,20 @@ typedef struct {
                                    selects zero-copy -- for hosts where full-line zero-copy reads run
                                    at the copy engine's rate (hytm_link_probe), so equal bytes cost
                                    equal time and zero-copy skips the whole-partition pass. */
+    uint32_t pr_blocking;       /* 1: HYTM_PAGERANK's pushes emit one (destination, contribution) pair per
+                                   edge, and each run of partitions with at most max(n / 2, 2^20) edges
+                                   has its pairs bucketed by destination on the GPU and summed in LDS
+                                   (propagation blocking) instead of adding with random float atomics,
+                                   whose fixed rate falls below what the host link feeds a fully active
+                                   iteration.  Applies to single PageRank runs with n <= 2^28 in the
+                                   hybrid, filter (streaming engine) or zero-copy modes; the result is
+                                   the same sum in another order.  Needs 5 x 8 bytes per pair of a piece
+                                   of device memory outside the edge budget (20 bytes per vertex at
+                                   the automatic piece size).
+                                   0: atomic adds into per-XCD accumulator copies. */
+    uint64_t pr_block_pairs;    /* 0 = automatic (max(n / 2, 2^20), at most m): pairs per piece of
+                                   pr_blocking; a smaller value (never below the largest partition)
+                                   cuts more pieces, e.g. to exercise the piece pipeline on small graphs. */
 } hytm_params;
 
 /* How a FILTER task moves its whole partition range to the GPU.  Both transfer every
@@ -201,9 +215,9 @@ typedef struct {
        the edge kernels, 128-byte lines for the zero-copy kernel, vertices otherwise). */
     uint32_t time_kernels;
     uint32_t reserved0;
-    double kernel_ms[8];
-    uint64_t kernel_launches[8];
-    uint64_t kernel_items[8];
+    double kernel_ms[9];
+    uint64_t kernel_launches[9];
+    uint64_t kernel_items[9];
     double residual;            /* PAGERANK_DELTA: total pending delta at the end (else 0) */
     uint64_t zc_lines_distinct; /* different lines among zc_lines: a line shared by two consecutive
                                    active vertices counts once */
@@ -218,7 +232,8 @@ enum {
     HYTM_K_PUSH_F = 4,   /* push over a filter task's staging slot */
     HYTM_K_PUSH_ZC = 5,  /* zero-copy push (mapped host reads) */
     HYTM_K_PUSH_C = 6,   /* push over a compaction chunk */
-    HYTM_K_OTHER = 7     /* init, frontier clear, PageRank prepare/apply */
+    HYTM_K_OTHER = 7,    /* init, frontier clear, PageRank prepare/apply */
+    HYTM_K_PR_BLOCK = 8  /* PageRank pair bucketing and summing, per piece (items = pairs) */
 };
 
 /* Host-link and HBM probe (calibration of the cost constants, Sec. 3.2 / Sec. 5.1). */

@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
         ("ppr_iterations", ctypes.c_uint32), ("reprocess", ctypes.c_uint32),
         ("dpr_max_iterations", ctypes.c_uint32), ("dpr_epsilon", ctypes.c_double),
         ("compact_gather_num", ctypes.c_uint32), ("compact_gather_den", ctypes.c_uint32),
-        ("rq_distinct_lines", ctypes.c_uint32), ("zc_tie", ctypes.c_uint32),
+        ("rq_distinct_lines", ctypes.c_uint32), ("zc_tie", ctypes.c_uint32), ("pr_blocking", ctypes.c_uint32),
+        ("pr_block_pairs", ctypes.c_uint64),
     ]
 
 
@@ -78,14 +79,14 @@ class RunStats(ctypes.Structure):
         ("ms_select", ctypes.c_double), ("iters", ctypes.POINTER(IterStats)), ("iters_cap", ctypes.c_uint32),
         ("iters_written", ctypes.c_uint32), ("mode_trace", ctypes.POINTER(ctypes.c_uint8)),
         ("mode_trace_cap", ctypes.c_uint64), ("time_kernels", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
-        ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_uint64 * 8),
-        ("kernel_items", ctypes.c_uint64 * 8), ("residual", ctypes.c_double),
+        ("kernel_ms", ctypes.c_double * 9), ("kernel_launches", ctypes.c_uint64 * 9),
+        ("kernel_items", ctypes.c_uint64 * 9), ("residual", ctypes.c_double),
         ("zc_lines_distinct", ctypes.c_uint64),
     ]
 
 
 KERNEL_CLASSES = ["stats", "scan", "lists", "push_resident", "push_filter", "push_zerocopy", "push_compact",
-                  "other"]
+                  "other", "pr_blocking"]
 
 
 class LinkProbe(ctypes.Structure):

@@ -20,9 +20,11 @@ constexpr int SEG_R = 0, SEG_F = 1, SEG_Z = 2, SEG_C = 3;
 // ALGO_MPPR: personalized PageRank, one value lane per source.
 // ALGO_BFS_RELAX: BFS by level relaxation (lvl[v] = min(lvl[v], lvl[u] + 1)), exact under
 // the asynchronous reprocessing that first-visit marking would get wrong.
+// ALGO_PR_PB: PageRank's push writes (destination, contribution) pairs into a piece buffer
+// instead of adding into the accumulators (propagation blocking, see launch_pb_*).
 enum Algo : int {
     ALGO_BFS = 0, ALGO_SSSP = 1, ALGO_CC = 2, ALGO_PR = 3, ALGO_MBFS = 4, ALGO_MSSSP = 5, ALGO_MPPR = 6,
-    ALGO_BFS_RELAX = 7
+    ALGO_BFS_RELAX = 7, ALGO_PR_PB = 8
 };
 constexpr uint32_t MAX_LANES = 64;
 
@@ -102,10 +104,64 @@ struct AlgoState {
     uint32_t lshift;
     const float* inv_n;   // PageRank over a union of graphs: 1 / (vertices of v's graph), else null
     Pack pk;              // how edge words are laid out
+    // ALGO_PR_PB: edge e of the current piece writes its pair to slot e - pb_e0
+    uint32_t* pb_v;
+    float* pb_c;
+    uint64_t pb_e0;
+    uint64_t pb_cap;      // slots of the piece buffer: a pair outside them is dropped
 };
 
 // PageRank keeps one accumulator copy per XCD; the apply step sums them.
 constexpr uint32_t ACC_COPIES = 8;
+
+// Propagation blocking of PageRank's adds.  Random float atomics into HBM run at a fixed
+// rate (about 20 G/s on MI355X whatever the footprint), below what the host link feeds a
+// fully active iteration, so the pushes instead write one (destination, contribution)
+// pair per edge into a piece buffer, a piece being a run of partitions with at most a
+// buffer's worth of edges.  The pairs of a piece are bucketed by destination in two
+// counting-sort passes (coarse bins of PB_FINE_PER_COARSE fine bins, then fine bins of
+// PB_FINE accumulator slots), and each fine bin is summed in LDS and added to the single
+// accumulator copy with coalesced read-modify-writes.  Bucket sizes of a piece are the
+// same in every PageRank iteration (every vertex is active), so they are counted once.
+constexpr uint32_t PB_FINE_SHIFT = 14;
+constexpr uint32_t PB_FINE = 1u << PB_FINE_SHIFT;   // accumulator slots per fine bin (64 KB of LDS)
+constexpr uint32_t PB_MAX_FINE = 16384;             // fine bins (LDS histogram): n <= 2^28
+constexpr uint32_t PB_FINE_PER_COARSE = 32;
+constexpr uint32_t PB_SEG = 65536;                  // pairs per accumulation segment
+// Fine bins of n vertices, and the bound on accumulation segments of a piece of `pairs`.
+__host__ __device__ inline uint32_t pb_fine_bins(uint64_t n) { return (uint32_t)((n + PB_FINE - 1) >> PB_FINE_SHIFT); }
+__host__ __device__ inline uint32_t pb_coarse_bins(uint32_t nfine) {
+    return (nfine + PB_FINE_PER_COARSE - 1) / PB_FINE_PER_COARSE;
+}
+__host__ __device__ inline uint32_t pb_max_segs(uint32_t nfine, uint64_t pairs) {
+    return nfine + (uint32_t)((pairs + PB_SEG - 1) / PB_SEG);
+}
+// hist[f] += pairs of pv[0, cnt) whose destination lies in fine bin f (hist zeroed by the
+// caller).  A destination outside [0, nfine * PB_FINE) sets *err.
+hipError_t launch_pb_hist(const uint32_t* pv, uint64_t cnt, uint32_t nfine, uint32_t* hist, uint32_t* err,
+                          hipStream_t st);
+// From a piece's fine histogram: foff[0..nfine] = its exclusive prefix sum (bin starts in
+// the bucketed buffer), segs = the accumulation segments, two words each (fine bin,
+// segment index within the bin), *nsegs = their count (<= pb_max_segs).
+hipError_t launch_pb_plan(const uint32_t* hist, uint32_t nfine, uint32_t* foff, uint32_t* segs, uint32_t* nsegs,
+                          hipStream_t st);
+// Scatter cursors of a piece: fcur[f] = foff[f]; ccur[c] = foff[c * PB_FINE_PER_COARSE].
+hipError_t launch_pb_cursors(const uint32_t* foff, uint32_t nfine, uint32_t* fcur, uint32_t* ccur, hipStream_t st);
+// One counting-sort pass: pair i of (in_v, in_c)[0, cnt) goes to the bin of key
+// in_v[i] >> kshift, at the position its cursor hands out.  Bins are fine bins
+// (kshift = PB_FINE_SHIFT, stride 1) or coarse bins (kshift = PB_FINE_SHIFT + 5, stride
+// PB_FINE_PER_COARSE); bin k ends at foff[min((k + 1) * stride, nfine)], and a pair that
+// would pass its bin's end is dropped and sets *err (counts that do not match the pairs).
+hipError_t launch_pb_scatter(const uint32_t* in_v, const float* in_c, uint64_t cnt, uint32_t kshift, uint32_t stride,
+                             uint32_t nfine, const uint32_t* foff, uint32_t* cursor, uint32_t* out_v, float* out_c,
+                             uint32_t* err, hipStream_t st);
+// Sum each segment's pairs (bucketed by fine bin) in LDS and add the bin's slots into
+// acc (slot order, acc_slot): plain read-modify-write when the bin is one segment,
+// atomic adds of the non-zero slots when it spans several.  Launched with max_segs
+// workgroups; those past *nsegs exit.
+hipError_t launch_pb_accum(const uint32_t* pv, const float* pc, const uint32_t* foff, const uint32_t* segs,
+                           const uint32_t* nsegs, uint32_t max_segs, uint64_t n, float* acc, uint32_t* err,
+                           hipStream_t st);
 
 hipError_t launch_init(const AlgoState& s, uint64_t n, uint32_t source, float pr_x0, float* pr_x, uint32_t* cur,
                        uint32_t nwords, hipStream_t st);
@@ -200,12 +256,13 @@ __host__ __device__ inline uint32_t acc_slot(uint32_t v) {
 }
 __host__ __device__ inline uint64_t acc_slots(uint64_t n) { return (n + 4095) & ~uint64_t(4095); }
 
+// contrib = x / D_o and the first `copies` accumulator copies zeroed.
 hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
-                             hipStream_t st);
-// x = base + damping * (sum of the accumulator copies); with inv_n, the base of v is
-// restart * inv_n[v] (graph-wise normalization of a union of graphs).
-hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, const float* inv_n,
-                           float restart, hipStream_t st);
+                             uint32_t copies, hipStream_t st);
+// x = base + damping * (sum of the first `copies` accumulator copies); with inv_n, the
+// base of v is restart * inv_n[v] (graph-wise normalization of a union of graphs).
+hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, uint32_t copies, float base, float damping,
+                           const float* inv_n, float restart, hipStream_t st);
 // delta[v] = restart * (inv_n ? inv_n[v] : 1 / n): the initial pending mass of delta PageRank.
 hipError_t launch_dpr_init(uint64_t n, float* delta, const float* inv_n, float restart, hipStream_t st);
 

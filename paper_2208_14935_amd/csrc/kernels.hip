@@ -19,6 +19,8 @@
 // PageRank (FP32 atomic add), and a bitmap-directed next frontier (Sec. 6.3).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "hytm_kernels.h"
 
 namespace hytm {
@@ -463,6 +465,26 @@ struct OpPr {
     }
 };
 
+// PageRank with propagation blocking: the push of edge e stores (v, contribution) in slot
+// e - e0 of the piece buffer; the adds happen when the piece's pairs are bucketed.
+struct OpPrPb {
+    static constexpr bool wave = false;
+    static constexpr bool weighted = false;
+    static constexpr bool slotted = true;
+    const float* contrib;
+    uint32_t* pv;
+    float* pc;
+    uint64_t e0, cap;
+    __device__ __forceinline__ uint32_t src(uint32_t u) const { return __float_as_uint(contrib[u]); }
+    __device__ __forceinline__ void push_at(uint32_t c, uint32_t v, uint64_t e) const {
+        const uint64_t slot = e - e0;
+        if (slot < cap) {
+            pv[slot] = v;
+            pc[slot] = __uint_as_float(c);
+        }
+    }
+};
+
 // Batched BFS: lanes of u's mask that have not reached v yet reach it now (one 64-bit
 // atomicOr decides, per lane, which edge discovers v first).  The staged value is u.
 struct OpMBfs {
@@ -586,13 +608,25 @@ struct OpMPpr {
     }
 };
 
-// push(val, v, w) where ok holds, called by every thread of the wave together: operators
-// with a wave form (Op::wave) share the work across the wave.
+template <class Op, class = void>
+struct IsSlotted {
+    static constexpr bool value = false;
+};
 template <class Op>
-__device__ __forceinline__ void push_if(const Op& op, bool ok, uint32_t val, uint32_t v, uint32_t w) {
+struct IsSlotted<Op, std::void_t<decltype(Op::slotted)>> {
+    static constexpr bool value = Op::slotted;
+};
+
+// push(val, v, w) where ok holds, called by every thread of the wave together: operators
+// with a wave form (Op::wave) share the work across the wave; slotted operators take the
+// edge's index e in the CSR instead of its weight.
+template <class Op>
+__device__ __forceinline__ void push_if(const Op& op, bool ok, uint32_t val, uint32_t v, uint32_t w, uint64_t e) {
     if constexpr (Op::wave)
         op.push_wave(ok, val, v);
-    else if (ok)
+    else if constexpr (IsSlotted<Op>::value) {
+        if (ok) op.push_at(val, v, e);
+    } else if (ok)
         op.push(val, v, w);
 }
 
@@ -701,14 +735,16 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_push_edges(const uint32_t* __r
             const uint32_t q = q0 + threadIdx.x;
             const bool ok = q < cnt;
             uint32_t val = 0, v = 0, wt = 0;
+            uint64_t eg = 0;  // the edge's index in the CSR (not known for compacted lists)
             if (ok) {
                 const uint32_t k = s_owner[q];
                 const uint64_t e = s_st[k] + (i0 + q - s_pre[k]);
                 v = col[e];
                 if (Op::weighted && pk.shift == 32) wt = w[e];
                 val = s_val[k];
+                eg = COMPACTED ? 0 : e + shift;
             }
-            push_if(op, ok, val, pk_v(v, pk), Op::weighted ? pk_w(v, wt, pk) : 0u);
+            push_if(op, ok, val, pk_v(v, pk), Op::weighted ? pk_w(v, wt, pk) : 0u, eg);
         }
         __syncthreads();
     }
@@ -754,6 +790,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
         if (distinct && threadIdx.x == 0) s_prev_end = j0 > ja ? off[list[j0 - 1] + 1] : UINT64_MAX;
         __syncthreads();
         uint32_t cv[LINE_UNROLL], wv[LINE_UNROLL], kk[LINE_UNROLL];
+        uint64_t ev[LINE_UNROLL];
         bool ok[LINE_UNROLL];
 #pragma unroll
         for (int r = 0; r < LINE_UNROLL; r++) {
@@ -762,6 +799,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
             kk[r] = 0;
             cv[r] = 0;
             wv[r] = 0;
+            ev[r] = 0;
             if (i < i1) {
                 uint32_t lo = 0, hi = nv;
                 while (hi - lo > 1) {
@@ -784,6 +822,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
                 if (e >= s && e < s_e[lo]) {
                     ok[r] = true;
                     kk[r] = lo;
+                    ev[r] = e;
                     cv[r] = col[e];
                     if (Op::weighted && pk.shift == 32) wv[r] = w[e];
                 }
@@ -791,7 +830,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
         }
 #pragma unroll
         for (int r = 0; r < LINE_UNROLL; r++)
-            push_if(op, ok[r], s_val[kk[r]], pk_v(cv[r], pk), Op::weighted ? pk_w(cv[r], wv[r], pk) : 0u);
+            push_if(op, ok[r], s_val[kk[r]], pk_v(cv[r], pk), Op::weighted ? pk_w(cv[r], wv[r], pk) : 0u, ev[r]);
         __syncthreads();
     }
     if (distinct) {
@@ -1084,7 +1123,7 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t va
 }
 
 __global__ void k_pr_prepare(uint64_t n, const uint64_t* __restrict__ off, const float* __restrict__ x,
-                             float* __restrict__ contrib, float* __restrict__ acc) {
+                             float* __restrict__ contrib, float* __restrict__ acc, uint32_t copies) {
     const uint64_t slots = acc_slots(n);
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < slots;
          v += (uint64_t)gridDim.x * blockDim.x) {
@@ -1092,21 +1131,286 @@ __global__ void k_pr_prepare(uint64_t n, const uint64_t* __restrict__ off, const
             const uint64_t d = off[v + 1] - off[v];
             contrib[v] = d ? x[v] / (float)d : 0.0f;
         }
-#pragma unroll
-        for (uint32_t c = 0; c < ACC_COPIES; c++) acc[c * slots + v] = 0.0f;
+        for (uint32_t c = 0; c < copies; c++) acc[c * slots + v] = 0.0f;
     }
 }
 
-__global__ void k_pr_apply(uint64_t n, float* __restrict__ x, const float* __restrict__ acc, float base,
-                           float damping, const float* __restrict__ inv_n, float restart) {
+__global__ void k_pr_apply(uint64_t n, float* __restrict__ x, const float* __restrict__ acc, uint32_t copies,
+                           float base, float damping, const float* __restrict__ inv_n, float restart) {
     const uint64_t slots = acc_slots(n);
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
          v += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t s = acc_slot((uint32_t)v);
         float sum = 0.0f;
-#pragma unroll
-        for (uint32_t c = 0; c < ACC_COPIES; c++) sum += acc[c * slots + s];
+        for (uint32_t c = 0; c < copies; c++) sum += acc[c * slots + s];
         x[v] = (inv_n ? restart * inv_n[v] : base) + damping * sum;
+    }
+}
+
+// ---------------------------------------------------- propagation blocking
+constexpr int PB_THREADS = 256;
+constexpr int PB_PLAN_THREADS = 1024;
+constexpr uint32_t PB_TILE = 2048;   // pairs per scatter tile, 8 per thread
+constexpr uint32_t PB_LOCAL = 1024;  // bins one tile sorts in LDS
+
+// Exclusive sum of one value per thread over the workgroup (a multiple of 64 threads);
+// *total = the sum of all.  s_w holds blockDim.x / 64 + 1 entries.  Every thread calls it.
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t x, uint32_t* s_w, uint32_t* total) {
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += y;
+    }
+    if (lane == 63) s_w[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0;
+        for (uint32_t w = 0; w < nw; w++) {
+            const uint32_t t = s_w[w];
+            s_w[w] = a;
+            a += t;
+        }
+        s_w[nw] = a;
+    }
+    __syncthreads();
+    const uint32_t r = s_w[wid] + inc - x;
+    *total = s_w[nw];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(PB_THREADS) void k_pb_hist(const uint32_t* __restrict__ pv, uint64_t cnt, uint32_t nfine,
+                                                        uint32_t* __restrict__ hist, uint32_t* __restrict__ err) {
+    __shared__ uint32_t s_h[PB_MAX_FINE];
+    for (uint32_t f = threadIdx.x; f < nfine; f += PB_THREADS) s_h[f] = 0;
+    __syncthreads();
+    bool bad = false;
+    for (uint64_t i = blockIdx.x * (uint64_t)PB_THREADS + threadIdx.x; i < cnt;
+         i += (uint64_t)gridDim.x * PB_THREADS) {
+        const uint32_t f = pv[i] >> PB_FINE_SHIFT;
+        if (f < nfine)
+            atomicAdd(&s_h[f], 1u);
+        else
+            bad = true;
+    }
+    if (bad) atomicOr(err, 1u);
+    __syncthreads();
+    for (uint32_t f = threadIdx.x; f < nfine; f += PB_THREADS)
+        if (s_h[f]) atomicAdd(hist + f, s_h[f]);
+}
+
+// One workgroup: bin starts and the accumulation segments of every non-empty bin.
+__global__ __launch_bounds__(PB_PLAN_THREADS) void k_pb_plan(const uint32_t* __restrict__ hist, uint32_t nfine,
+                                                             uint32_t* __restrict__ foff, uint32_t* __restrict__ segs,
+                                                             uint32_t* __restrict__ nsegs) {
+    constexpr uint32_t PER = PB_MAX_FINE / PB_PLAN_THREADS;
+    __shared__ uint32_t s_w[PB_PLAN_THREADS / 64 + 1];
+    const uint32_t f0 = threadIdx.x * PER;
+    uint32_t c[PER], sum = 0, ns = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < PER; q++) {
+        c[q] = f0 + q < nfine ? hist[f0 + q] : 0u;
+        sum += c[q];
+        ns += (c[q] + PB_SEG - 1) / PB_SEG;
+    }
+    uint32_t total, stotal;
+    uint32_t base = block_excl_sum(sum, s_w, &total);
+    uint32_t sb = block_excl_sum(ns, s_w, &stotal);
+    for (uint32_t q = 0; q < PER; q++) {
+        const uint32_t f = f0 + q;
+        if (f >= nfine) break;
+        foff[f] = base;
+        base += c[q];
+        for (uint32_t j = 0; j * PB_SEG < c[q]; j++, sb++) {
+            segs[2 * sb] = f;
+            segs[2 * sb + 1] = j;
+        }
+    }
+    if (threadIdx.x == 0) {
+        foff[nfine] = total;
+        *nsegs = stotal;
+    }
+}
+
+__global__ void k_pb_cursors(const uint32_t* __restrict__ foff, uint32_t nfine, uint32_t* __restrict__ fcur,
+                             uint32_t* __restrict__ ccur) {
+    for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < nfine; f += gridDim.x * blockDim.x) {
+        fcur[f] = foff[f];
+        if (f % PB_FINE_PER_COARSE == 0) ccur[f / PB_FINE_PER_COARSE] = foff[f];
+    }
+}
+
+// A tile whose keys span fewer than PB_LOCAL bins is counting-sorted in LDS: one cursor
+// reservation per bin present, then the tile's pairs leave bin by bin in runs.  A tile
+// spanning more (a stretch of nearly empty bins) reserves a position per pair.
+__global__ __launch_bounds__(PB_THREADS) void k_pb_scatter(const uint32_t* __restrict__ in_v,
+                                                           const float* __restrict__ in_c, uint64_t cnt,
+                                                           uint32_t kshift, uint32_t stride, uint32_t nfine,
+                                                           const uint32_t* __restrict__ foff,
+                                                           uint32_t* __restrict__ cursor, uint32_t* __restrict__ out_v,
+                                                           float* __restrict__ out_c, uint32_t* __restrict__ err) {
+    constexpr uint32_t PER = PB_TILE / PB_THREADS;
+    constexpr uint32_t LPER = PB_LOCAL / PB_THREADS;
+    __shared__ uint32_t s_v[PB_TILE];
+    __shared__ float s_c[PB_TILE];
+    __shared__ uint16_t s_k[PB_TILE];
+    __shared__ uint32_t s_cnt[PB_LOCAL], s_ofs[PB_LOCAL], s_g[PB_LOCAL], s_end[PB_LOCAL];
+    __shared__ uint32_t s_kmin, s_kmax, s_w[PB_THREADS / 64 + 1];
+    const uint32_t nkeys = (nfine + stride - 1) / stride;
+    const uint32_t lane = threadIdx.x & 63;
+    bool bad = false;
+    for (uint64_t t0 = blockIdx.x * (uint64_t)PB_TILE; t0 < cnt; t0 += (uint64_t)gridDim.x * PB_TILE) {
+        const uint32_t tc = (uint32_t)min((uint64_t)PB_TILE, cnt - t0);
+        uint32_t v[PER], key[PER], rank[PER];
+        float c[PER];
+        uint32_t kmin = UINT32_MAX, kmax = 0;
+        if (threadIdx.x == 0) {
+            s_kmin = UINT32_MAX;
+            s_kmax = 0;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < PER; r++) {
+            const uint32_t i = r * PB_THREADS + threadIdx.x;
+            v[r] = 0;
+            c[r] = 0.0f;
+            key[r] = 0;
+            rank[r] = 0;
+            if (i < tc) {
+                v[r] = in_v[t0 + i];
+                c[r] = in_c[t0 + i];
+                key[r] = v[r] >> kshift;
+                kmin = min(kmin, key[r]);
+                kmax = max(kmax, key[r]);
+            }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            kmin = min(kmin, (uint32_t)__shfl_xor(kmin, d, 64));
+            kmax = max(kmax, (uint32_t)__shfl_xor(kmax, d, 64));
+        }
+        __syncthreads();
+        if (lane == 0) {
+            atomicMin(&s_kmin, kmin);
+            atomicMax(&s_kmax, kmax);
+        }
+        __syncthreads();
+        const uint32_t k0 = s_kmin, k1 = s_kmax;
+        if (k1 < nkeys && k1 - k0 < PB_LOCAL) {  // uniform across the workgroup
+#pragma unroll
+            for (uint32_t q = 0; q < LPER; q++) s_cnt[LPER * threadIdx.x + q] = 0;
+            __syncthreads();
+#pragma unroll
+            for (uint32_t r = 0; r < PER; r++)
+                if (r * PB_THREADS + threadIdx.x < tc) rank[r] = atomicAdd(&s_cnt[key[r] - k0], 1u);
+            __syncthreads();
+            uint32_t loc[LPER], sum = 0, tot;
+#pragma unroll
+            for (uint32_t q = 0; q < LPER; q++) {
+                loc[q] = s_cnt[LPER * threadIdx.x + q];
+                sum += loc[q];
+            }
+            uint32_t base = block_excl_sum(sum, s_w, &tot);
+#pragma unroll
+            for (uint32_t q = 0; q < LPER; q++) {
+                const uint32_t b = LPER * threadIdx.x + q;
+                s_ofs[b] = base;
+                base += loc[q];
+                if (loc[q]) {
+                    const uint32_t k = k0 + b;
+                    s_g[b] = atomicAdd(cursor + k, loc[q]);
+                    s_end[b] = foff[min((k + 1) * stride, nfine)];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (uint32_t r = 0; r < PER; r++)
+                if (r * PB_THREADS + threadIdx.x < tc) {
+                    const uint32_t lk = key[r] - k0;
+                    const uint32_t p = s_ofs[lk] + rank[r];
+                    s_v[p] = v[r];
+                    s_c[p] = c[r];
+                    s_k[p] = (uint16_t)lk;
+                }
+            __syncthreads();
+            for (uint32_t p = threadIdx.x; p < tc; p += PB_THREADS) {
+                const uint32_t lk = s_k[p];
+                const uint32_t gpos = s_g[lk] + (p - s_ofs[lk]);
+                if (gpos < s_end[lk]) {
+                    out_v[gpos] = s_v[p];
+                    out_c[gpos] = s_c[p];
+                } else {
+                    bad = true;
+                }
+            }
+        } else {
+#pragma unroll
+            for (uint32_t r = 0; r < PER; r++)
+                if (r * PB_THREADS + threadIdx.x < tc) {
+                    const uint32_t k = key[r];
+                    if (k >= nkeys) {
+                        bad = true;
+                        continue;
+                    }
+                    const uint32_t gpos = atomicAdd(cursor + k, 1u);
+                    if (gpos < foff[min((k + 1) * stride, nfine)]) {
+                        out_v[gpos] = v[r];
+                        out_c[gpos] = c[r];
+                    } else {
+                        bad = true;
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    if (bad) atomicOr(err, 1u);
+}
+
+__global__ __launch_bounds__(PB_THREADS) void k_pb_accum(const uint32_t* __restrict__ pv,
+                                                         const float* __restrict__ pc,
+                                                         const uint32_t* __restrict__ foff,
+                                                         const uint32_t* __restrict__ segs,
+                                                         const uint32_t* __restrict__ nsegs, uint64_t n,
+                                                         float* __restrict__ acc, uint32_t* __restrict__ err) {
+    __shared__ float4 s_a4[PB_FINE / 4];
+    float* s_a = (float*)s_a4;
+    const uint32_t s = blockIdx.x;
+    if (s >= *nsegs) return;  // the same for every thread of the workgroup
+    const uint32_t f = segs[2 * s], j = segs[2 * s + 1];
+    const uint32_t b0 = foff[f], b1 = foff[f + 1];
+    const uint32_t start = b0 + j * PB_SEG;
+    const uint32_t end = min(b1, start + PB_SEG);
+    const bool multi = b1 - b0 > PB_SEG;
+    for (uint32_t q = threadIdx.x; q < PB_FINE / 4; q += PB_THREADS) s_a4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    bool bad = false;
+    for (uint32_t i = start + threadIdx.x; i < end; i += PB_THREADS) {
+        const uint32_t v = pv[i];
+        if ((v >> PB_FINE_SHIFT) == f && v < n)
+            atomicAdd(&s_a[acc_slot(v) & (PB_FINE - 1)], pc[i]);
+        else
+            bad = true;
+    }
+    if (bad) atomicOr(err, 1u);
+    __syncthreads();
+    // the bin's accumulator slots: [base, base + lim), lim a multiple of 4096
+    const uint64_t base = (uint64_t)f << PB_FINE_SHIFT;
+    const uint32_t lim = (uint32_t)min((uint64_t)PB_FINE, acc_slots(n) - base);
+    if (!multi) {
+        float4* a4 = (float4*)(acc + base);
+        for (uint32_t q = threadIdx.x; q < lim / 4; q += PB_THREADS) {
+            float4 x = a4[q];
+            const float4 y = s_a4[q];
+            x.x += y.x;
+            x.y += y.y;
+            x.z += y.z;
+            x.w += y.w;
+            a4[q] = x;
+        }
+    } else {
+        for (uint32_t q = threadIdx.x; q < lim; q += PB_THREADS)
+            if (s_a[q] != 0.0f) unsafeAtomicAdd(acc + base + q, s_a[q]);
     }
 }
 
@@ -1186,7 +1490,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
                     ok = q >= s_s[k] && q < s_e[k];
                     val = s_val[k];
                 }
-                push_if(op, ok, val, pk_v(cv[r], pk), Op::weighted ? pk_w(cv[r], wv[r], pk) : 0u);
+                push_if(op, ok, val, pk_v(cv[r], pk), Op::weighted ? pk_w(cv[r], wv[r], pk) : 0u, e);
             }
         }
         __syncthreads();
@@ -1405,6 +1709,10 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
     case ALGO_MPPR:
         return push_edges_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
                              item_hi, off, col, w, shift, compacted, s.pk, st);
+    case ALGO_PR_PB:
+        if (compacted) return hipErrorInvalidValue;  // pairs are slotted by CSR edge index
+        return push_edges_op(OpPrPb{s.contrib, s.pb_v, s.pb_c, s.pb_e0, s.pb_cap}, list, wpre, ja, jb, item_lo, item_hi,
+                             off, col, w, shift, compacted, s.pk, st);
     default:
         return push_edges_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
                              compacted, s.pk, st);
@@ -1443,15 +1751,61 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
     case ALGO_MPPR:
         return push_lines_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
                              item_hi, off, col, w, distinct, s.pk, st);
+    case ALGO_PR_PB:
+        return push_lines_op(OpPrPb{s.contrib, s.pb_v, s.pb_c, s.pb_e0, s.pb_cap}, list, wpre, ja, jb, item_lo, item_hi, off,
+                             col, w, distinct, s.pk, st);
     default:
         return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, s.pk, st);
     }
 }
 
 hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
-                             hipStream_t st) {
+                             uint32_t copies, hipStream_t st) {
     if (!n) return hipSuccess;
-    k_pr_prepare<<<grid_for(acc_slots(n), 256, 8192), 256, 0, st>>>(n, off, x, contrib, acc);
+    if (copies < 1 || copies > ACC_COPIES) return hipErrorInvalidValue;
+    k_pr_prepare<<<grid_for(acc_slots(n), 256, 8192), 256, 0, st>>>(n, off, x, contrib, acc, copies);
+    return hipGetLastError();
+}
+
+hipError_t launch_pb_hist(const uint32_t* pv, uint64_t cnt, uint32_t nfine, uint32_t* hist, uint32_t* err,
+                          hipStream_t st) {
+    if (!cnt) return hipSuccess;
+    if (nfine == 0 || nfine > PB_MAX_FINE) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)std::min<uint64_t>(256, (cnt + 4095) / 4096);
+    k_pb_hist<<<g, PB_THREADS, 0, st>>>(pv, cnt, nfine, hist, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_pb_plan(const uint32_t* hist, uint32_t nfine, uint32_t* foff, uint32_t* segs, uint32_t* nsegs,
+                          hipStream_t st) {
+    if (nfine == 0 || nfine > PB_MAX_FINE) return hipErrorInvalidValue;
+    k_pb_plan<<<1, PB_PLAN_THREADS, 0, st>>>(hist, nfine, foff, segs, nsegs);
+    return hipGetLastError();
+}
+
+hipError_t launch_pb_cursors(const uint32_t* foff, uint32_t nfine, uint32_t* fcur, uint32_t* ccur, hipStream_t st) {
+    if (nfine == 0 || nfine > PB_MAX_FINE) return hipErrorInvalidValue;
+    k_pb_cursors<<<grid_for(nfine, 256, 64), 256, 0, st>>>(foff, nfine, fcur, ccur);
+    return hipGetLastError();
+}
+
+hipError_t launch_pb_scatter(const uint32_t* in_v, const float* in_c, uint64_t cnt, uint32_t kshift, uint32_t stride,
+                             uint32_t nfine, const uint32_t* foff, uint32_t* cursor, uint32_t* out_v, float* out_c,
+                             uint32_t* err, hipStream_t st) {
+    if (!cnt) return hipSuccess;
+    if (nfine == 0 || nfine > PB_MAX_FINE || (stride != 1 && stride != PB_FINE_PER_COARSE) ||
+        (1u << kshift) != stride * PB_FINE)
+        return hipErrorInvalidValue;
+    k_pb_scatter<<<grid_for(cnt, PB_TILE, 4096), PB_THREADS, 0, st>>>(in_v, in_c, cnt, kshift, stride, nfine, foff,
+                                                                      cursor, out_v, out_c, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_pb_accum(const uint32_t* pv, const float* pc, const uint32_t* foff, const uint32_t* segs,
+                           const uint32_t* nsegs, uint32_t max_segs, uint64_t n, float* acc, uint32_t* err,
+                           hipStream_t st) {
+    if (!max_segs || !n) return hipSuccess;
+    k_pb_accum<<<max_segs, PB_THREADS, 0, st>>>(pv, pc, foff, segs, nsegs, n, acc, err);
     return hipGetLastError();
 }
 
@@ -1487,15 +1841,19 @@ hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t 
     case ALGO_MPPR:
         return push_fstream_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, tasks, ntasks, total_chunks,
                                list, off, col, w, s.pk, st);
+    case ALGO_PR_PB:
+        return push_fstream_op(OpPrPb{s.contrib, s.pb_v, s.pb_c, s.pb_e0, s.pb_cap}, tasks, ntasks, total_chunks, list, off,
+                               col, w, s.pk, st);
     default:
         return push_fstream_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, tasks, ntasks, total_chunks, list, off, col, w, s.pk, st);
     }
 }
 
-hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, float base, float damping, const float* inv_n,
-                           float restart, hipStream_t st) {
+hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, uint32_t copies, float base, float damping,
+                           const float* inv_n, float restart, hipStream_t st) {
     if (!n) return hipSuccess;
-    k_pr_apply<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, x, acc, base, damping, inv_n, restart);
+    if (copies < 1 || copies > ACC_COPIES) return hipErrorInvalidValue;
+    k_pr_apply<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, x, acc, copies, base, damping, inv_n, restart);
     return hipGetLastError();
 }
 

@@ -110,7 +110,7 @@ struct HostBuf {  // pinned host memory
 };
 
 constexpr uint32_t kMaxSlots = 16;
-constexpr int kClasses = 8;
+constexpr int kClasses = 9;
 
 // Optional per-launch HIP-event timing, by kernel class (HYTM_K_*).  Launches may come
 // from the main thread and the compaction thread, hence the lock.
@@ -217,6 +217,11 @@ struct hytm_graph {
     DevBuf<uint8_t> d_sched;      // ... partitions scheduled this iteration
     HostBuf<uint8_t> h_sched;
     HostBuf<uint64_t> h_lanes;
+    // PageRank propagation blocking: pair buffers [lane * 2 + b] of the resident (lane 0) and
+    // streamed (lane 1) pieces, [4] = the first sort pass's target; bucket plans per piece
+    DevBuf<uint32_t> d_pb_v[5];
+    DevBuf<float> d_pb_c[5];
+    DevBuf<uint32_t> d_pb_hist, d_pb_foff, d_pb_segs, d_pb_nsegs, d_pb_fcur, d_pb_ccur, d_pb_err;
 
     // host mirrors of the per-iteration selection
     HostBuf<Header> h_hdr;
@@ -236,8 +241,9 @@ struct hytm_graph {
     HostBuf<uint32_t> h_cbuf_col[2], h_cbuf_w[2];
 
     // streams / events
-    hipStream_t s_main = nullptr, s_copy = nullptr, s_fk = nullptr, s_zc = nullptr, s_c = nullptr;
+    hipStream_t s_main = nullptr, s_copy = nullptr, s_fk = nullptr, s_zc = nullptr, s_c = nullptr, s_pb = nullptr;
     hipEvent_t ev_copied[kMaxSlots] = {}, ev_free[kMaxSlots] = {};
+    hipEvent_t ev_pbpush[3] = {}, ev_pbfree[4] = {};
     hipEvent_t ev_cdone[2] = {}, ev_join[4] = {}, ev_start = nullptr, ev_clist = nullptr, ev_go = nullptr;
 
     Pool* pool = nullptr;
@@ -278,6 +284,8 @@ bool params_valid(const hytm_params& p, std::string* why) {
     if (p.reprocess > 2) return bad("reprocess must be 0, 1 or 2");
     if (p.rq_distinct_lines > 1) return bad("rq_distinct_lines must be 0 or 1");
     if (p.zc_tie > 1) return bad("zc_tie must be 0 or 1");
+    if (p.pr_blocking > 1) return bad("pr_blocking must be 0 or 1");
+    if (p.pr_block_pairs >= (1ull << 31)) return bad("pr_block_pairs must be below 2^31");
     if (!frac_ok(p.compact_gather_num, p.compact_gather_den, false))
         return bad("compact_gather must be num/den with den in 1..65536");
     if (!(p.dpr_epsilon >= 0.0)) return bad("dpr_epsilon must be >= 0");
@@ -441,6 +449,9 @@ void ensure_streams(hytm_graph* g) {
     HIP_CHECK(hipStreamCreateWithFlags(&g->s_fk, hipStreamNonBlocking));
     HIP_CHECK(hipStreamCreateWithFlags(&g->s_zc, hipStreamNonBlocking));
     HIP_CHECK(hipStreamCreateWithFlags(&g->s_c, hipStreamNonBlocking));
+    HIP_CHECK(hipStreamCreateWithFlags(&g->s_pb, hipStreamNonBlocking));
+    for (auto& e : g->ev_pbpush) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& e : g->ev_pbfree) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (uint32_t i = 0; i < kMaxSlots; i++) {
         HIP_CHECK(hipEventCreateWithFlags(&g->ev_copied[i], hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&g->ev_free[i], hipEventDisableTiming));
@@ -481,6 +492,13 @@ void release_all(hytm_graph* g) {
     g->d_inv_n.release();
     g->h_lanes.release();
     g->d_hdr.release();
+    for (int i = 0; i < 5; i++) {
+        g->d_pb_v[i].release();
+        g->d_pb_c[i].release();
+    }
+    for (auto* b : {&g->d_pb_hist, &g->d_pb_foff, &g->d_pb_segs, &g->d_pb_nsegs, &g->d_pb_fcur, &g->d_pb_ccur,
+                    &g->d_pb_err})
+        b->release();
     for (uint32_t i = 0; i < kMaxSlots; i++) {
         g->d_slot_col[i].release();
         g->d_slot_w[i].release();
@@ -500,8 +518,12 @@ void release_all(hytm_graph* g) {
     if (g->h_col) (void)hipHostFree(g->h_col);
     if (g->h_w) (void)hipHostFree(g->h_w);
     g->h_col = g->h_w = nullptr;
-    for (hipStream_t s : {g->s_main, g->s_copy, g->s_fk, g->s_zc, g->s_c})
+    for (hipStream_t s : {g->s_main, g->s_copy, g->s_fk, g->s_zc, g->s_c, g->s_pb})
         if (s) (void)hipStreamDestroy(s);
+    for (auto e : g->ev_pbpush)
+        if (e) (void)hipEventDestroy(e);
+    for (auto e : g->ev_pbfree)
+        if (e) (void)hipEventDestroy(e);
     for (uint32_t i = 0; i < kMaxSlots; i++) {
         if (g->ev_copied[i]) (void)hipEventDestroy(g->ev_copied[i]);
         if (g->ev_free[i]) (void)hipEventDestroy(g->ev_free[i]);
@@ -545,6 +567,18 @@ struct Totals {
     uint64_t av = 0, ae = 0, bf = 0, bc = 0, zcl = 0, d2h = 0, ftasks = 0, cchunks = 0;
 };
 
+// A run of consecutive partitions whose pairs fit one piece buffer (PageRank with
+// propagation blocking), with the parts of the selection's lists and filter tasks that
+// cover it.
+struct PbPiece {
+    int lane = 0;                    // 0: resident partitions, 1: streamed partitions
+    uint64_t e0 = 0, cnt = 0;        // CSR edge range [e0, e0 + cnt): pair slot = edge - e0
+    uint32_t rja = 0, rjb = 0, zja = 0, zjb = 0;  // resident / zero-copy list ranges
+    uint64_t rwa = 0, rwb = 0, zwa = 0, zwb = 0;  // ... and their work ranges
+    uint32_t ta = 0, tb = 0;         // streaming filter tasks (chunk0 counted from task ta)
+    uint64_t fchunks = 0, fedges = 0;
+};
+
 // One traversal: a single-source or whole-graph run, or one group of lanes (a batched
 // run or a lane group of the query server).  The per-graph scratch it steps through
 // (lists, selection, staging) is shared; the frontier and value state is its own.
@@ -572,6 +606,17 @@ struct RunCtx {
     } replay;
     uint32_t last_ftasks = 0;                  // streaming filter tasks of the last pass
     uint64_t last_fchunks = 0;
+    // PageRank with propagation blocking: the first iteration's selection cut into pieces
+    bool pb_on = false;
+    struct {
+        bool ok = false;
+        Header h{};
+        std::vector<PbPiece> pieces;
+        std::vector<uint32_t> lane[2];  // piece indices per lane, in partition order
+        uint64_t cap = 0;               // pairs per piece buffer
+        uint32_t nfine = 0, max_segs = 0, ftasks = 0;
+        uint64_t fedges = 0;
+    } pb;
     uint32_t t = 0;                            // iterations taken
     Totals tot;
 };
@@ -751,7 +796,7 @@ void init_ctx(RunCtx& rc, hytm_graph* g, int algo, bool batched, const Plan& pl,
 // is pushed.  Transfer and activity counts are added to *rec; trace_t >= 0 records the
 // engine choice in the caller's mode trace.
 hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Header* hout, uint64_t* lanes,
-                        bool stop_if_empty, hytm_iter_stats* rec, int64_t trace_t) {
+                        bool stop_if_empty, hytm_iter_stats* rec, int64_t trace_t, bool select_only = false) {
     hytm_graph* g = rc.g;
     KTimer& kt = g->timer;
     AlgoState& as = rc.as;
@@ -806,6 +851,7 @@ hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Heade
     hytm_run_stats* stats = rc.stats;
     if (trace_t >= 0 && stats && stats->mode_trace && (uint64_t)(trace_t + 1) * npart <= stats->mode_trace_cap)
         memcpy(stats->mode_trace + (uint64_t)trace_t * npart, g->h_mode.p, npart);
+    if (select_only) return HYTM_OK;
 
     // resident partitions: no transfer
     if (h.seg_list_count[SEG_R])
@@ -1000,6 +1046,268 @@ hytm_status replay_pass(RunCtx& rc, hipStream_t main, hytm_iter_stats* rec, int6
     return HYTM_OK;
 }
 
+// ------------------------------------------------------ propagation blocking
+// PageRank's adds go through pair buckets (see PB_* in the kernel header) when it runs
+// alone, the selection can contain no compaction partitions (their pushes do not know the
+// CSR index of an edge), filter partitions use the streaming engine, and the fine bins
+// fit the LDS histogram.
+bool pb_eligible(const RunCtx& rc) {
+    const hytm_graph* g = rc.g;
+    return rc.algo == HYTM_PAGERANK && !rc.batched && g->params.pr_blocking && g->m > 0 &&
+           pb_fine_bins(g->n) <= PB_MAX_FINE && g->max_part_edges < (1ull << 31) && g->n / 2 < (1ull << 31) &&
+           g->params.mode != HYTM_MODE_COMPACT && g->params.filter_engine == HYTM_FILTER_STREAM;
+}
+
+// Pairs per piece buffer: by default half a pair per vertex, so that a piece's bucket
+// flushes (one read-modify-write of every accumulator slot) cost at most 16 bytes per
+// pair; never less than the largest partition, never more than the edges.
+uint64_t pb_capacity(const hytm_graph* g) {
+    const uint64_t want = g->params.pr_block_pairs ? g->params.pr_block_pairs : std::max<uint64_t>(g->n / 2, 1ull << 20);
+    return std::min<uint64_t>(std::max<uint64_t>(want, g->max_part_edges), g->m);
+}
+
+// List and work range of segment `seg` over partitions [pa, pb): its entries run from the
+// first such partition's bases to those of the next one at or after pb (or the segment's end).
+void seg_range(const hytm_graph* g, const Header& h, int seg, uint32_t pa, uint32_t pb, uint32_t* ja, uint32_t* jb,
+               uint64_t* wa, uint64_t* wb) {
+    const uint8_t code = (uint8_t)(seg + 1);
+    const uint8_t* md = g->h_mode.p;
+    uint32_t p = pa;
+    while (p < pb && md[p] != code) p++;
+    *ja = *jb = 0;
+    *wa = *wb = 0;
+    if (p == pb) return;
+    *ja = g->h_lbase.p[p];
+    *wa = g->h_wbase.p[p];
+    uint32_t q = pb;
+    while (q < g->npart && md[q] != code) q++;
+    if (q < g->npart) {
+        *jb = g->h_lbase.p[q];
+        *wb = g->h_wbase.p[q];
+    } else {
+        *jb = h.seg_list_start[seg] + h.seg_list_count[seg];
+        *wb = h.seg_work_start[seg] + h.seg_work_total[seg];
+    }
+}
+
+// Cut the first iteration's selection into pieces, build each piece's filter tasks, and
+// put the pair buffers and bucket plans in place.
+hytm_status pb_plan(RunCtx& rc, const Header& h, hipStream_t main) {
+    hytm_graph* g = rc.g;
+    auto& pb = rc.pb;
+    const uint32_t npart = g->npart;
+    const uint8_t* md = g->h_mode.p;
+    pb.h = h;
+    pb.cap = pb_capacity(g);
+    pb.nfine = pb_fine_bins(g->n);
+    pb.max_segs = pb_max_segs(pb.nfine, pb.cap);
+    pb.pieces.clear();
+    pb.lane[0].clear();
+    pb.lane[1].clear();
+    pb.ftasks = 0;
+    pb.fedges = 0;
+    for (uint32_t p = 0; p < npart; p++)
+        if (md[p] == P_COMPACT) return fail(HYTM_E_STATE, "internal: compaction partition under PageRank blocking");
+    const uint32_t k = g->params.combine_k;
+    const uint64_t fend_list = h.seg_list_start[SEG_F] + h.seg_list_count[SEG_F];
+    g->h_tasks.ensure(npart);
+    auto add = [&](uint32_t pa, uint32_t pb_, int lane) {
+        PbPiece pc;
+        pc.lane = lane;
+        pc.e0 = g->h_off[g->pv[pa]];
+        pc.cnt = g->h_off[g->pv[pb_]] - pc.e0;
+        if (pc.cnt == 0) return;
+        seg_range(g, h, SEG_R, pa, pb_, &pc.rja, &pc.rjb, &pc.rwa, &pc.rwb);
+        seg_range(g, h, SEG_Z, pa, pb_, &pc.zja, &pc.zjb, &pc.zwa, &pc.zwb);
+        // filter tasks: runs of <= k adjacent filter partitions, cut at the piece's end
+        pc.ta = pb.ftasks;
+        uint32_t i = pa;
+        while (i < pb_) {
+            if (md[i] != P_FILTER) {
+                i++;
+                continue;
+            }
+            uint32_t j = i + 1;
+            uint64_t edges = g->pE[i];
+            while (j < pb_ && j - i < k && md[j] == P_FILTER) edges += g->pE[j++];
+            uint32_t nx = j;
+            while (nx < npart && md[nx] != P_FILTER) nx++;
+            FTask& ft = g->h_tasks.p[pb.ftasks++];
+            ft.e0 = g->h_off[g->pv[i]];
+            ft.e1 = ft.e0 + edges;
+            ft.ja = g->h_lbase.p[i];
+            ft.jb = nx < npart ? g->h_lbase.p[nx] : (uint32_t)fend_list;
+            ft.chunk0 = pc.fchunks;
+            pc.fchunks += fstream_chunks(ft.e0, ft.e1);
+            pc.fedges += edges;
+            i = j;
+        }
+        pc.tb = pb.ftasks;
+        pb.fedges += pc.fedges;
+        pb.lane[lane].push_back((uint32_t)pb.pieces.size());
+        pb.pieces.push_back(pc);
+    };
+    auto cut = [&](uint32_t a, uint32_t b, int lane) {
+        uint32_t pa = a;
+        while (pa < b) {
+            uint32_t pb_ = pa;
+            uint64_t e = 0;
+            while (pb_ < b && (pb_ == pa || e + g->pE[pb_] <= pb.cap)) e += g->pE[pb_++];
+            add(pa, pb_, lane);
+            pa = pb_;
+        }
+    };
+    const uint32_t nres = std::min(rc.plan.nres, npart);
+    cut(0, nres, 0);
+    cut(nres, npart, 1);
+    if (pb.ftasks) {
+        g->d_tasks.ensure(pb.ftasks);
+        HIP_CHECK(hipMemcpyAsync(g->d_tasks.p, g->h_tasks.p, pb.ftasks * sizeof(FTask), hipMemcpyHostToDevice, main));
+    }
+    const uint32_t np = (uint32_t)pb.pieces.size();
+    for (int lane = 0; lane < 2; lane++)
+        for (uint32_t b = 0; b < std::min<size_t>(2, pb.lane[lane].size()); b++) {
+            g->d_pb_v[lane * 2 + b].ensure(pb.cap);
+            g->d_pb_c[lane * 2 + b].ensure(pb.cap);
+        }
+    g->d_pb_v[4].ensure(pb.cap);
+    g->d_pb_c[4].ensure(pb.cap);
+    g->d_pb_hist.ensure(pb.nfine);
+    g->d_pb_foff.ensure((uint64_t)np * (pb.nfine + 1));
+    g->d_pb_segs.ensure((uint64_t)np * 2 * pb.max_segs);
+    g->d_pb_nsegs.ensure(np);
+    g->d_pb_fcur.ensure(pb.nfine);
+    g->d_pb_ccur.ensure(pb_coarse_bins(pb.nfine));
+    g->d_pb_err.ensure(1);
+    HIP_CHECK(launch_fill_u32(g->d_pb_err.p, 1, 0u, main));
+    return HYTM_OK;
+}
+
+// One PageRank push pass with propagation blocking.  Pieces of the two lanes are issued in
+// turn, in proportion to their edges: a piece's pushes (resident, zero-copy and filter
+// parts on their engines' streams) write its pair buffer, then the bucketing stream sorts
+// and sums the pairs into the accumulators and frees the buffer for the lane's piece after
+// next.  `first`: the bucket plans are counted (the same pairs recur every iteration).
+hytm_status pb_pass(RunCtx& rc, hipStream_t main, hytm_iter_stats* rec, int64_t trace_t, bool first) {
+    hytm_graph* g = rc.g;
+    KTimer& kt = g->timer;
+    const auto& pb = rc.pb;
+    const uint32_t npart = g->npart;
+    if (!first) {
+        const Header& h = pb.h;
+        uint32_t scheduled = 0;
+        for (int s = 0; s < NSEG; s++) {
+            rec->parts[s + 1] += h.seg_parts[s];
+            scheduled += h.seg_parts[s];
+        }
+        rec->parts[0] += npart - scheduled;
+        rec->active_vertices += h.total_active;
+        for (int s = 0; s < NSEG; s++) rec->active_edges += h.seg_edges[s];
+        hytm_run_stats* stats = rc.stats;
+        if (trace_t >= 0 && stats && stats->mode_trace && (uint64_t)(trace_t + 1) * npart <= stats->mode_trace_cap)
+            memcpy(stats->mode_trace + (uint64_t)trace_t * npart, g->h_mode.p, npart);
+    }
+    HIP_CHECK(hipEventRecord(g->ev_go, main));
+    for (hipStream_t s : {g->s_c, g->s_zc, g->s_fk, g->s_pb}) HIP_CHECK(hipStreamWaitEvent(s, g->ev_go, 0));
+    AlgoState as = rc.as;
+    as.algo = ALGO_PR_PB;
+    as.pb_cap = pb.cap;
+    const uint32_t nfine = pb.nfine, ncoarse = pb_coarse_bins(nfine);
+    uint64_t lane_total[2] = {0, 0}, lane_done[2] = {0, 0};
+    for (int l = 0; l < 2; l++)
+        for (uint32_t i : pb.lane[l]) lane_total[l] += pb.pieces[i].cnt;
+    uint32_t next[2] = {0, 0};
+    while (next[0] < pb.lane[0].size() || next[1] < pb.lane[1].size()) {
+        // the lane that has issued the smaller share of its edges goes next
+        int lane;
+        if (next[0] == pb.lane[0].size())
+            lane = 1;
+        else if (next[1] == pb.lane[1].size())
+            lane = 0;
+        else
+            lane = (double)lane_done[0] * lane_total[1] <= (double)lane_done[1] * lane_total[0] ? 0 : 1;
+        const uint32_t kk = next[lane]++;
+        const uint32_t pi = pb.lane[lane][kk];
+        const PbPiece& pc = pb.pieces[pi];
+        lane_done[lane] += pc.cnt;
+        const int buf = lane * 2 + (int)(kk & 1);
+        as.pb_v = g->d_pb_v[buf].p;
+        as.pb_c = g->d_pb_c[buf].p;
+        as.pb_e0 = pc.e0;
+        const bool hasR = pc.rjb > pc.rja && pc.rwb > pc.rwa;
+        const bool hasZ = pc.zjb > pc.zja && pc.zwb > pc.zwa;
+        const bool hasF = pc.tb > pc.ta;
+        if (kk >= 2) {  // the buffer's previous piece has been summed
+            if (hasR) HIP_CHECK(hipStreamWaitEvent(g->s_c, g->ev_pbfree[buf], 0));
+            if (hasZ) HIP_CHECK(hipStreamWaitEvent(g->s_zc, g->ev_pbfree[buf], 0));
+            if (hasF) HIP_CHECK(hipStreamWaitEvent(g->s_fk, g->ev_pbfree[buf], 0));
+        }
+        if (hasR) {
+            HIP_CHECK(kt.run(HYTM_K_PUSH_RES, pc.rwb - pc.rwa, g->s_c, [&] {
+                return launch_push_edges(as, g->d_list.p, g->d_wpre.p, pc.rja, pc.rjb, pc.rwa, pc.rwb, g->d_off.p,
+                                         g->d_res_col.p, g->d_res_w.p, 0, false, g->s_c);
+            }));
+            HIP_CHECK(hipEventRecord(g->ev_pbpush[0], g->s_c));
+            HIP_CHECK(hipStreamWaitEvent(g->s_pb, g->ev_pbpush[0], 0));
+        }
+        if (hasZ) {
+            HIP_CHECK(kt.run(HYTM_K_PUSH_ZC, pc.zwb - pc.zwa, g->s_zc, [&] {
+                return launch_push_lines(as, g->d_list.p, g->d_wpre.p, pc.zja, pc.zjb, pc.zwa, pc.zwb, g->d_off.p,
+                                         g->d_col_map, g->d_w_map, (unsigned long long*)g->d_zcl.p, g->s_zc);
+            }));
+            HIP_CHECK(hipEventRecord(g->ev_pbpush[1], g->s_zc));
+            HIP_CHECK(hipStreamWaitEvent(g->s_pb, g->ev_pbpush[1], 0));
+            rec->zc_lines += pc.zwb - pc.zwa;
+        }
+        if (hasF) {
+            HIP_CHECK(kt.run(HYTM_K_PUSH_F, pc.fedges, g->s_fk, [&] {
+                return launch_push_fstream(as, g->d_tasks.p + pc.ta, pc.tb - pc.ta, pc.fchunks, g->d_list.p,
+                                           g->d_off.p, g->d_col_map, g->d_w_map, g->s_fk);
+            }));
+            HIP_CHECK(hipEventRecord(g->ev_pbpush[2], g->s_fk));
+            HIP_CHECK(hipStreamWaitEvent(g->s_pb, g->ev_pbpush[2], 0));
+        }
+        uint32_t* foff = g->d_pb_foff.p + (uint64_t)pi * (nfine + 1);
+        uint32_t* segs = g->d_pb_segs.p + (uint64_t)pi * 2 * pb.max_segs;
+        uint32_t* nsegs = g->d_pb_nsegs.p + pi;
+        uint32_t* pv = g->d_pb_v[buf].p;
+        float* pcv = g->d_pb_c[buf].p;
+        uint32_t* err = g->d_pb_err.p;
+        hipStream_t sp = g->s_pb;
+        HIP_CHECK(kt.run(HYTM_K_PR_BLOCK, pc.cnt, sp, [&]() -> hipError_t {
+            hipError_t e;
+            if (first) {
+                if ((e = launch_fill_u32(g->d_pb_hist.p, nfine, 0u, sp)) != hipSuccess) return e;
+                if ((e = launch_pb_hist(pv, pc.cnt, nfine, g->d_pb_hist.p, err, sp)) != hipSuccess) return e;
+                if ((e = launch_pb_plan(g->d_pb_hist.p, nfine, foff, segs, nsegs, sp)) != hipSuccess) return e;
+            }
+            if ((e = launch_pb_cursors(foff, nfine, g->d_pb_fcur.p, g->d_pb_ccur.p, sp)) != hipSuccess) return e;
+            uint32_t* sv = g->d_pb_v[4].p;
+            float* sc = g->d_pb_c[4].p;
+            if (ncoarse > 1) {
+                // coarse pass into the sort buffer, fine pass back into the piece buffer
+                if ((e = launch_pb_scatter(pv, pcv, pc.cnt, PB_FINE_SHIFT + 5, PB_FINE_PER_COARSE, nfine, foff,
+                                           g->d_pb_ccur.p, sv, sc, err, sp)) != hipSuccess)
+                    return e;
+                if ((e = launch_pb_scatter(sv, sc, pc.cnt, PB_FINE_SHIFT, 1, nfine, foff, g->d_pb_fcur.p, pv, pcv,
+                                           err, sp)) != hipSuccess)
+                    return e;
+                return launch_pb_accum(pv, pcv, foff, segs, nsegs, pb.max_segs, g->n, rc.as.acc, err, sp);
+            }
+            if ((e = launch_pb_scatter(pv, pcv, pc.cnt, PB_FINE_SHIFT, 1, nfine, foff, g->d_pb_fcur.p, sv, sc, err,
+                                       sp)) != hipSuccess)
+                return e;
+            return launch_pb_accum(sv, sc, foff, segs, nsegs, pb.max_segs, g->n, rc.as.acc, err, sp);
+        }));
+        HIP_CHECK(hipEventRecord(g->ev_pbfree[buf], sp));
+    }
+    HIP_CHECK(hipEventRecord(g->ev_join[3], g->s_pb));
+    HIP_CHECK(hipStreamWaitEvent(main, g->ev_join[3], 0));
+    rec->filter_tasks += pb.ftasks;
+    rec->bytes_filter += pb.fedges * 4;
+    return HYTM_OK;
+}
+
 // One iteration of a traversal.  *lanes_out: batched runs: the lanes with a non-empty
 // frontier at the start of the iteration.  *empty_out: BFS/SSSP/CC only: the frontier was
 // empty, nothing was pushed and the traversal is over.
@@ -1011,9 +1319,10 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
     const uint32_t t = rc.t;
     const bool fixed_steps = rc.algo == HYTM_PAGERANK || rc.algo == HYTM_PPR;
     const double t_it = now_ms();
+    const uint32_t copies = rc.pb_on ? 1u : ACC_COPIES;  // blocked adds need no per-XCD copies
     if (rc.algo == HYTM_PAGERANK)
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
-            return launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, main);
+            return launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, copies, main);
         }));
     if (rc.algo == HYTM_PPR)
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] { return launch_ppr_prepare(as, g->d_off.p, main); }));
@@ -1023,7 +1332,17 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
     *lanes_out = 0;
     *empty_out = false;
     hytm_status st;
-    if (rc.replay.ok) {
+    if (rc.pb.ok) {
+        st = pb_pass(rc, main, &rec, t, false);
+        h = rc.pb.h;
+    } else if (rc.pb_on) {
+        st = engine_pass(rc, rc.cur, main, &h, nullptr, false, &rec, t, true);
+        if (st == HYTM_OK) st = pb_plan(rc, h, main);
+        if (st == HYTM_OK) {
+            rc.pb.ok = true;
+            st = pb_pass(rc, main, &rec, t, true);
+        }
+    } else if (rc.replay.ok) {
         st = replay_pass(rc, main, &rec, t);
         h = rc.replay.h;
     } else {
@@ -1067,7 +1386,7 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
         const float d = (float)g->params.pr_damping;
         const float restart = (float)(1.0 - g->params.pr_damping);
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
-            return launch_pr_apply(n, g->d_x.p, g->d_acc.p, base, d, as.inv_n, restart, main);
+            return launch_pr_apply(n, g->d_x.p, g->d_acc.p, copies, base, d, as.inv_n, restart, main);
         }));
     } else {
         if (rc.algo == HYTM_PPR) {
@@ -1201,6 +1520,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     HIP_CHECK(hipEventRecord(g->ev_start, main));
     HIP_CHECK(launch_fill_u32((uint32_t*)g->d_zcl.p, 2, 0u, main));
     init_ctx(rc, g, algo, batched, pl, stats);
+    rc.pb_on = pb_eligible(rc);
 
     const uint64_t n = g->n;
     const uint32_t nwords = rc.nwords;
@@ -1295,6 +1615,11 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         for (uint32_t l = 0; l < lanes; l++) lane_iters[l] += (uint32_t)((active >> l) & 1);
     }
     HIP_CHECK(hipStreamSynchronize(main));
+    if (rc.pb.ok) {
+        uint32_t perr = 0;
+        HIP_CHECK(hipMemcpy(&perr, g->d_pb_err.p, sizeof(perr), hipMemcpyDeviceToHost));
+        if (perr) return fail(HYTM_E_DEVICE, "internal: PageRank pair buckets did not match the pushed pairs");
+    }
     if (algo == HYTM_SSSP) {
         uint32_t of[2] = {0, 0};
         HIP_CHECK(hipMemcpy(of, g->d_overflow.p, sizeof(of), hipMemcpyDeviceToHost));
@@ -1706,6 +2031,8 @@ void hytm_default_params(hytm_params* p) {
     p->compact_gather_den = 1;
     p->rq_distinct_lines = 0;
     p->zc_tie = 0;
+    p->pr_blocking = 1;
+    p->pr_block_pairs = 0;
     p->streams = 4;
     p->gather_threads = 0;
     p->compact_chunk_edges = 0;
