@@ -99,6 +99,10 @@ def main():
     ap.add_argument("--zc-tie", default="probe",
                     help="where a Tiz = Tef tie goes: 'probe' (zero-copy when full-line zero-copy reads reach 95%% of "
                          "the measured copy rate), 'filter' (the paper) or 'zerocopy'")
+    ap.add_argument("--pr-blocking", type=int, default=1, choices=[0, 1, 2],
+                    help="PageRank over resident partitions: bucket the (destination, contribution) pairs and sum "
+                         "them in LDS (propagation blocking) -- 1 = when at least half of the edges are resident, "
+                         "2 = always, 0 = never (random float atomics into per-XCD accumulator copies)")
     ap.add_argument("--compact-gather", default="off",
                     help="host-gather term of the compaction cost: 'off' (the paper's rule), 'probe' (link rate / "
                          "measured gather rate) or num/den")
@@ -157,7 +161,8 @@ def main():
         if h is not None:
             h.set_params(mode=args.mode, partition_edges=args.partition_edges, combine_k=args.combine_k,
                          filter_engine=args.filter_engine, gamma=gamma, reprocess=int(args.reprocess),
-                         compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct), zc_tie=zc_tie)
+                         compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct), zc_tie=zc_tie,
+                         pr_blocking=args.pr_blocking)
     if args.workload == "batch":
         return batch_workload(args, g, off, col, deg, gamma, probe)
     if args.workload == "serve":
@@ -254,14 +259,15 @@ def main():
                 + (f"-reprocess{args.reprocess}" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
                 + ("" if g.info()["packed_weights"] else "-unpacked")
                 + ("" if cgather[0] == 0 else "-gathercost") + ("-rqdistinct" if args.rq_distinct else "")
-                + ("-zctie" if zc_tie else ""))
+                + ("-zctie" if zc_tie else "") + ("-prblock" if args.pr_blocking == 2 and "pagerank" in algos else ""))
     roofline = None
     kernels = {}
     if kt:
-        ms = np.zeros(8)
-        launches = np.zeros(8, dtype=np.int64)
-        items = np.zeros(8, dtype=np.int64)
-        arrays_items = np.zeros(8)  # items weighted by edge arrays read
+        nk = len(hy.KERNEL_CLASSES)
+        ms = np.zeros(nk)
+        launches = np.zeros(nk, dtype=np.int64)
+        items = np.zeros(nk, dtype=np.int64)
+        arrays_items = np.zeros(nk)  # items weighted by edge arrays read
         zc_bytes = 0  # lines the zero-copy kernel really read (a line two lists share counts once)
         for name, r, _ in all_runs:
             a = (gs if name == "cc" else g).edge_arrays(name)
@@ -290,6 +296,13 @@ def main():
             bound, peak = "pcie", PCIE_GEN5_X16_GBPS
         elif name.startswith("push"):
             per_launch = (arrays_items[dom] * 4 + items[dom] * 4) / max(launches[dom], 1)
+            bound, peak = "hbm", HBM_PEAK_GBPS
+        elif name == "pr_blocking":
+            # per pair: each counting-sort pass reads and writes 8 B, the summing pass reads
+            # 8 B; per piece: one read-modify-write of every accumulator slot
+            passes = 2 if (n + 16383) // 16384 > 1024 else 1
+            slots = (n + 4095) // 4096 * 4096
+            per_launch = (items[dom] * (16 * passes + 8) + launches[dom] * 8 * slots) / max(launches[dom], 1)
             bound, peak = "hbm", HBM_PEAK_GBPS
         else:
             per_launch = items[dom] * 16 / max(launches[dom], 1)

@@ -88,8 +88,13 @@ static void parallel_for(uint64_t total, uint64_t chunk, range_fn fn, void *ctx)
         return;
     }
     pthread_t th[64];
-    for (int i = 0; i < nt; i++) pthread_create(&th[i], NULL, par_worker, &j);
-    for (int i = 0; i < nt; i++) pthread_join(th[i], NULL);
+    int started = 0;
+    for (int i = 0; i < nt; i++) {
+        if (pthread_create(&th[started], NULL, par_worker, &j) != 0) break; /* e.g. a thread limit */
+        started++;
+    }
+    par_worker(&j); /* the caller takes work too, so the job finishes with any number started */
+    for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
 }
 
 /* ------------------------------------------------------------ edge sources */

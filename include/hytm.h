@@ -145,17 +145,19 @@ typedef struct {
                                    selects zero-copy -- for hosts where full-line zero-copy reads run
                                    at the copy engine's rate (hytm_link_probe), so equal bytes cost
                                    equal time and zero-copy skips the whole-partition pass. */
-    uint32_t pr_blocking;       /* 1: HYTM_PAGERANK's pushes emit one (destination, contribution) pair per
-                                   edge, and each run of partitions with at most max(n / 2, 2^20) edges
-                                   has its pairs bucketed by destination on the GPU and summed in LDS
-                                   (propagation blocking) instead of adding with random float atomics,
-                                   whose fixed rate falls below what the host link feeds a fully active
-                                   iteration.  Applies to single PageRank runs with n <= 2^28 in the
-                                   hybrid, filter (streaming engine) or zero-copy modes; the result is
-                                   the same sum in another order.  Needs 5 x 8 bytes per pair of a piece
-                                   of device memory outside the edge budget (20 bytes per vertex at
-                                   the automatic piece size).
-                                   0: atomic adds into per-XCD accumulator copies. */
+    uint32_t pr_blocking;       /* Propagation blocking of HYTM_PAGERANK's adds over resident partitions:
+                                   their pushes write one contribution per edge, and each run of resident
+                                   partitions with at most max(n, 2^20) edges has its (destination,
+                                   contribution) pairs bucketed by destination on the GPU and summed in
+                                   LDS, instead of adding with random float atomics, whose fixed rate
+                                   (about 20 G/s) falls below what HBM feeds from the resident cache.
+                                   Streamed partitions keep their atomic adds (the host link delivers
+                                   fewer edges per second than the atomics take).  1 (default): when at
+                                   least half of the edges are resident; 2: whenever some are; 0: never.
+                                   Applies to single PageRank runs with n <= 2^24 in the hybrid, filter
+                                   (streaming engine) or zero-copy modes; the result is the same sum in
+                                   another order.  Needs 3 x 8 bytes per pair of a piece of device memory
+                                   outside the edge budget (24 bytes per vertex at the default piece). */
     uint64_t pr_block_pairs;    /* 0 = automatic (max(n / 2, 2^20), at most m): pairs per piece of
                                    pr_blocking; a smaller value (never below the largest partition)
                                    cuts more pieces, e.g. to exercise the piece pipeline on small graphs. */

@@ -20,11 +20,9 @@ constexpr int SEG_R = 0, SEG_F = 1, SEG_Z = 2, SEG_C = 3;
 // ALGO_MPPR: personalized PageRank, one value lane per source.
 // ALGO_BFS_RELAX: BFS by level relaxation (lvl[v] = min(lvl[v], lvl[u] + 1)), exact under
 // the asynchronous reprocessing that first-visit marking would get wrong.
-// ALGO_PR_PB: PageRank's push writes (destination, contribution) pairs into a piece buffer
-// instead of adding into the accumulators (propagation blocking, see launch_pb_*).
 enum Algo : int {
     ALGO_BFS = 0, ALGO_SSSP = 1, ALGO_CC = 2, ALGO_PR = 3, ALGO_MBFS = 4, ALGO_MSSSP = 5, ALGO_MPPR = 6,
-    ALGO_BFS_RELAX = 7, ALGO_PR_PB = 8
+    ALGO_BFS_RELAX = 7
 };
 constexpr uint32_t MAX_LANES = 64;
 
@@ -104,64 +102,93 @@ struct AlgoState {
     uint32_t lshift;
     const float* inv_n;   // PageRank over a union of graphs: 1 / (vertices of v's graph), else null
     Pack pk;              // how edge words are laid out
-    // ALGO_PR_PB: edge e of the current piece writes its pair to slot e - pb_e0
-    uint32_t* pb_v;
-    float* pb_c;
-    uint64_t pb_e0;
-    uint64_t pb_cap;      // slots of the piece buffer: a pair outside them is dropped
+    uint32_t link_grid;   // 0, or at most this many workgroups for the host-reading pushes
 };
 
-// PageRank keeps one accumulator copy per XCD; the apply step sums them.
+// PageRank keeps one accumulator copy per XCD for its atomic adds, plus one for the sums
+// of propagation blocking; the apply step sums them.
 constexpr uint32_t ACC_COPIES = 8;
 
-// Propagation blocking of PageRank's adds.  Random float atomics into HBM run at a fixed
-// rate (about 20 G/s on MI355X whatever the footprint), below what the host link feeds a
-// fully active iteration, so the pushes instead write one (destination, contribution)
-// pair per edge into a piece buffer, a piece being a run of partitions with at most a
-// buffer's worth of edges.  The pairs of a piece are bucketed by destination in two
-// counting-sort passes (coarse bins of PB_FINE_PER_COARSE fine bins, then fine bins of
-// PB_FINE accumulator slots), and each fine bin is summed in LDS and added to the single
-// accumulator copy with coalesced read-modify-writes.  Bucket sizes of a piece are the
-// same in every PageRank iteration (every vertex is active), so they are counted once.
+// Propagation blocking of PageRank's adds over resident edges.  Random float atomics run
+// at a fixed rate (about 20 G/s on MI355X whatever the footprint): above what the host
+// link delivers (at most ~14 G edges/s), so streamed edges keep their atomic adds, but
+// below what HBM feeds from the resident cache.  The resident pushes instead write one
+// contribution per edge into a piece buffer, a piece being a run of resident partitions
+// with at most a buffer's worth of edges; the (destination, contribution) pairs of a
+// piece (destinations from the resident edge words) are bucketed by destination in one
+// counting-sort pass when the fine bins fit one LDS sort, else two (coarse bins of
+// PB_FINE_PER_COARSE fine bins, then fine bins of PB_FINE accumulator slots), and each
+// fine bin is summed in LDS and added to the blocking accumulator copy with coalesced
+// read-modify-writes.  Bucket sizes of a piece are the same in every PageRank iteration
+// (every vertex is active), so they are counted once.
 constexpr uint32_t PB_FINE_SHIFT = 14;
 constexpr uint32_t PB_FINE = 1u << PB_FINE_SHIFT;   // accumulator slots per fine bin (64 KB of LDS)
 constexpr uint32_t PB_MAX_FINE = 16384;             // fine bins (LDS histogram): n <= 2^28
 constexpr uint32_t PB_FINE_PER_COARSE = 32;
-constexpr uint32_t PB_SEG = 65536;                  // pairs per accumulation segment
-// Fine bins of n vertices, and the bound on accumulation segments of a piece of `pairs`.
+// Fine bins of n vertices; the accumulation segment length for pieces of `pairs` (twice a
+// bin's average, at least 16384: only bins well above the average -- the hubs' -- are
+// split over several workgroups); the bound on a piece's segments.
 __host__ __device__ inline uint32_t pb_fine_bins(uint64_t n) { return (uint32_t)((n + PB_FINE - 1) >> PB_FINE_SHIFT); }
 __host__ __device__ inline uint32_t pb_coarse_bins(uint32_t nfine) {
     return (nfine + PB_FINE_PER_COARSE - 1) / PB_FINE_PER_COARSE;
 }
-__host__ __device__ inline uint32_t pb_max_segs(uint32_t nfine, uint64_t pairs) {
-    return nfine + (uint32_t)((pairs + PB_SEG - 1) / PB_SEG);
+__host__ __device__ inline uint32_t pb_seg_len(uint32_t nfine, uint64_t pairs) {
+    const uint64_t avg = (pairs + nfine - 1) / nfine;
+    return (uint32_t)(2 * avg > 16384 ? 2 * avg : 16384);
 }
-// hist[f] += pairs of pv[0, cnt) whose destination lies in fine bin f (hist zeroed by the
-// caller).  A destination outside [0, nfine * PB_FINE) sets *err.
-hipError_t launch_pb_hist(const uint32_t* pv, uint64_t cnt, uint32_t nfine, uint32_t* hist, uint32_t* err,
-                          hipStream_t st);
+__host__ __device__ inline uint32_t pb_max_segs(uint32_t nfine, uint64_t pairs, uint32_t seg) {
+    return nfine + (uint32_t)((pairs + seg - 1) / seg);
+}
+// hist[f] += pairs of pv[0, cnt) whose destination (pv[i] & vmask) lies in fine bin f
+// (hist zeroed by the caller).  A destination outside [0, nfine * PB_FINE) sets *err.
+hipError_t launch_pb_hist(const uint32_t* pv, uint32_t vmask, uint64_t cnt, uint32_t nfine, uint32_t* hist,
+                          uint32_t* err, hipStream_t st);
 // From a piece's fine histogram: foff[0..nfine] = its exclusive prefix sum (bin starts in
-// the bucketed buffer), segs = the accumulation segments, two words each (fine bin,
-// segment index within the bin), *nsegs = their count (<= pb_max_segs).
-hipError_t launch_pb_plan(const uint32_t* hist, uint32_t nfine, uint32_t* foff, uint32_t* segs, uint32_t* nsegs,
-                          hipStream_t st);
-// Scatter cursors of a piece: fcur[f] = foff[f]; ccur[c] = foff[c * PB_FINE_PER_COARSE].
-hipError_t launch_pb_cursors(const uint32_t* foff, uint32_t nfine, uint32_t* fcur, uint32_t* ccur, hipStream_t st);
-// One counting-sort pass: pair i of (in_v, in_c)[0, cnt) goes to the bin of key
-// in_v[i] >> kshift, at the position its cursor hands out.  Bins are fine bins
-// (kshift = PB_FINE_SHIFT, stride 1) or coarse bins (kshift = PB_FINE_SHIFT + 5, stride
-// PB_FINE_PER_COARSE); bin k ends at foff[min((k + 1) * stride, nfine)], and a pair that
-// would pass its bin's end is dropped and sets *err (counts that do not match the pairs).
+// the bucketed buffer), segs = the accumulation segments of `seg` pairs, two words each
+// (fine bin, segment index within the bin), *nsegs = their count (<= pb_max_segs).
+hipError_t launch_pb_plan(const uint32_t* hist, uint32_t nfine, uint32_t seg, uint32_t* foff, uint32_t* segs,
+                          uint32_t* nsegs, hipStream_t st);
+// A counting-sort pass with atomic cursors (the second, fine pass): pair i of
+// (in_v, in_c)[0, cnt) goes to the bin of key in_v[i] >> kshift, at the position its
+// cursor hands out.  Bins are fine bins (kshift = PB_FINE_SHIFT, stride 1) or coarse bins
+// (kshift = PB_FINE_SHIFT + 5, stride PB_FINE_PER_COARSE); bin k ends at
+// foff[min((k + 1) * stride, nfine)], and a pair that would pass its bin's end is dropped
+// and sets *err (counts that do not match the pairs).
 hipError_t launch_pb_scatter(const uint32_t* in_v, const float* in_c, uint64_t cnt, uint32_t kshift, uint32_t stride,
                              uint32_t nfine, const uint32_t* foff, uint32_t* cursor, uint32_t* out_v, float* out_c,
                              uint32_t* err, hipStream_t st);
+// Resident push of a piece with every vertex active: pc[t] = contrib of the source of the
+// piece's edge t, t in [0, cnt), for the resident list entries [ja, jb) whose work (edge)
+// ranges wpre[j] - wa tile [0, cnt).  tiles writes tj[k] = the entry holding slot
+// k * 4096, for the ceil(cnt / 4096) tiles (once per piece); expand uses it.
+hipError_t launch_pb_tiles(const uint64_t* wpre, uint32_t ja, uint32_t jb, uint64_t wa, uint64_t cnt, uint32_t* tj,
+                           hipStream_t st);
+hipError_t launch_pb_expand(const uint32_t* list, const uint64_t* wpre, uint32_t jb, uint64_t wa, uint64_t cnt,
+                            const uint32_t* tj, const float* contrib, float* pc, hipStream_t st);
+inline uint64_t pb_tiles(uint64_t cnt) { return (cnt + 4095) / 4096; }
+// First sort pass with places fixed per workgroup slice (the slices' pairs recur every
+// PageRank iteration): plan_a counts each of at most PB_A_WG slices' pairs per bin (key =
+// v >> kshift, bins of `stride` fine bins, at most 1024 of them) and turns the counts into
+// output starts offA[slice][bin] (pb_max_offa entries); scatter_a moves the pairs there
+// with no global atomics and, with fcur != null, sets the second pass's cursors to foff.
+constexpr uint32_t PB_A_WG = 1024;
+constexpr uint32_t PB_LOCAL_BINS = 1024;  // bins one LDS counting sort handles
+inline uint64_t pb_max_offa(uint32_t nkeys) { return (uint64_t)PB_A_WG * nkeys; }
+// The first pass reads destinations as in_v[i] & vmask (resident edge words may carry
+// packed weights above the neighbour bits).
+hipError_t launch_pb_plan_a(const uint32_t* pv, uint32_t vmask, uint64_t cnt, uint32_t kshift, uint32_t stride,
+                            uint32_t nfine, const uint32_t* foff, uint32_t* offA, uint32_t* err, hipStream_t st);
+hipError_t launch_pb_scatter_a(const uint32_t* in_v, uint32_t vmask, const float* in_c, uint64_t cnt,
+                               uint32_t kshift, uint32_t stride, uint32_t nfine, const uint32_t* foff,
+                               const uint32_t* offA, uint32_t* out_v, float* out_c, uint32_t* fcur, uint32_t* err,
+                               hipStream_t st);
 // Sum each segment's pairs (bucketed by fine bin) in LDS and add the bin's slots into
 // acc (slot order, acc_slot): plain read-modify-write when the bin is one segment,
 // atomic adds of the non-zero slots when it spans several.  Launched with max_segs
 // workgroups; those past *nsegs exit.
 hipError_t launch_pb_accum(const uint32_t* pv, const float* pc, const uint32_t* foff, const uint32_t* segs,
-                           const uint32_t* nsegs, uint32_t max_segs, uint64_t n, float* acc, uint32_t* err,
-                           hipStream_t st);
+                           const uint32_t* nsegs, uint32_t max_segs, uint32_t seg, uint64_t n, float* acc,
+                           uint32_t* err, hipStream_t st);
 
 hipError_t launch_init(const AlgoState& s, uint64_t n, uint32_t source, float pr_x0, float* pr_x, uint32_t* cur,
                        uint32_t nwords, hipStream_t st);
@@ -256,7 +283,8 @@ __host__ __device__ inline uint32_t acc_slot(uint32_t v) {
 }
 __host__ __device__ inline uint64_t acc_slots(uint64_t n) { return (n + 4095) & ~uint64_t(4095); }
 
-// contrib = x / D_o and the first `copies` accumulator copies zeroed.
+// contrib = x / D_o and the first `copies` accumulator copies zeroed (ACC_COPIES, or
+// ACC_COPIES + 1 with propagation blocking).
 hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
                              uint32_t copies, hipStream_t st);
 // x = base + damping * (sum of the first `copies` accumulator copies); with inv_n, the

@@ -19,8 +19,6 @@
 // PageRank (FP32 atomic add), and a bitmap-directed next frontier (Sec. 6.3).
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "hytm_kernels.h"
 
 namespace hytm {
@@ -465,26 +463,6 @@ struct OpPr {
     }
 };
 
-// PageRank with propagation blocking: the push of edge e stores (v, contribution) in slot
-// e - e0 of the piece buffer; the adds happen when the piece's pairs are bucketed.
-struct OpPrPb {
-    static constexpr bool wave = false;
-    static constexpr bool weighted = false;
-    static constexpr bool slotted = true;
-    const float* contrib;
-    uint32_t* pv;
-    float* pc;
-    uint64_t e0, cap;
-    __device__ __forceinline__ uint32_t src(uint32_t u) const { return __float_as_uint(contrib[u]); }
-    __device__ __forceinline__ void push_at(uint32_t c, uint32_t v, uint64_t e) const {
-        const uint64_t slot = e - e0;
-        if (slot < cap) {
-            pv[slot] = v;
-            pc[slot] = __uint_as_float(c);
-        }
-    }
-};
-
 // Batched BFS: lanes of u's mask that have not reached v yet reach it now (one 64-bit
 // atomicOr decides, per lane, which edge discovers v first).  The staged value is u.
 struct OpMBfs {
@@ -608,25 +586,13 @@ struct OpMPpr {
     }
 };
 
-template <class Op, class = void>
-struct IsSlotted {
-    static constexpr bool value = false;
-};
-template <class Op>
-struct IsSlotted<Op, std::void_t<decltype(Op::slotted)>> {
-    static constexpr bool value = Op::slotted;
-};
-
 // push(val, v, w) where ok holds, called by every thread of the wave together: operators
-// with a wave form (Op::wave) share the work across the wave; slotted operators take the
-// edge's index e in the CSR instead of its weight.
+// with a wave form (Op::wave) share the work across the wave.
 template <class Op>
-__device__ __forceinline__ void push_if(const Op& op, bool ok, uint32_t val, uint32_t v, uint32_t w, uint64_t e) {
+__device__ __forceinline__ void push_if(const Op& op, bool ok, uint32_t val, uint32_t v, uint32_t w) {
     if constexpr (Op::wave)
         op.push_wave(ok, val, v);
-    else if constexpr (IsSlotted<Op>::value) {
-        if (ok) op.push_at(val, v, e);
-    } else if (ok)
+    else if (ok)
         op.push(val, v, w);
 }
 
@@ -735,16 +701,14 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_push_edges(const uint32_t* __r
             const uint32_t q = q0 + threadIdx.x;
             const bool ok = q < cnt;
             uint32_t val = 0, v = 0, wt = 0;
-            uint64_t eg = 0;  // the edge's index in the CSR (not known for compacted lists)
             if (ok) {
                 const uint32_t k = s_owner[q];
                 const uint64_t e = s_st[k] + (i0 + q - s_pre[k]);
                 v = col[e];
                 if (Op::weighted && pk.shift == 32) wt = w[e];
                 val = s_val[k];
-                eg = COMPACTED ? 0 : e + shift;
             }
-            push_if(op, ok, val, pk_v(v, pk), Op::weighted ? pk_w(v, wt, pk) : 0u, eg);
+            push_if(op, ok, val, pk_v(v, pk), Op::weighted ? pk_w(v, wt, pk) : 0u);
         }
         __syncthreads();
     }
@@ -790,7 +754,6 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
         if (distinct && threadIdx.x == 0) s_prev_end = j0 > ja ? off[list[j0 - 1] + 1] : UINT64_MAX;
         __syncthreads();
         uint32_t cv[LINE_UNROLL], wv[LINE_UNROLL], kk[LINE_UNROLL];
-        uint64_t ev[LINE_UNROLL];
         bool ok[LINE_UNROLL];
 #pragma unroll
         for (int r = 0; r < LINE_UNROLL; r++) {
@@ -799,7 +762,6 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
             kk[r] = 0;
             cv[r] = 0;
             wv[r] = 0;
-            ev[r] = 0;
             if (i < i1) {
                 uint32_t lo = 0, hi = nv;
                 while (hi - lo > 1) {
@@ -822,7 +784,6 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
                 if (e >= s && e < s_e[lo]) {
                     ok[r] = true;
                     kk[r] = lo;
-                    ev[r] = e;
                     cv[r] = col[e];
                     if (Op::weighted && pk.shift == 32) wv[r] = w[e];
                 }
@@ -830,7 +791,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
         }
 #pragma unroll
         for (int r = 0; r < LINE_UNROLL; r++)
-            push_if(op, ok[r], s_val[kk[r]], pk_v(cv[r], pk), Op::weighted ? pk_w(cv[r], wv[r], pk) : 0u, ev[r]);
+            push_if(op, ok[r], s_val[kk[r]], pk_v(cv[r], pk), Op::weighted ? pk_w(cv[r], wv[r], pk) : 0u);
         __syncthreads();
     }
     if (distinct) {
@@ -1151,7 +1112,7 @@ __global__ void k_pr_apply(uint64_t n, float* __restrict__ x, const float* __res
 constexpr int PB_THREADS = 256;
 constexpr int PB_PLAN_THREADS = 1024;
 constexpr uint32_t PB_TILE = 2048;   // pairs per scatter tile, 8 per thread
-constexpr uint32_t PB_LOCAL = 1024;  // bins one tile sorts in LDS
+constexpr uint32_t PB_LOCAL = PB_LOCAL_BINS;
 
 // Exclusive sum of one value per thread over the workgroup (a multiple of 64 threads);
 // *total = the sum of all.  s_w holds blockDim.x / 64 + 1 entries.  Every thread calls it.
@@ -1181,15 +1142,16 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t x, uint32_t* s_w, ui
     return r;
 }
 
-__global__ __launch_bounds__(PB_THREADS) void k_pb_hist(const uint32_t* __restrict__ pv, uint64_t cnt, uint32_t nfine,
-                                                        uint32_t* __restrict__ hist, uint32_t* __restrict__ err) {
+__global__ __launch_bounds__(PB_THREADS) void k_pb_hist(const uint32_t* __restrict__ pv, uint32_t vmask, uint64_t cnt,
+                                                        uint32_t nfine, uint32_t* __restrict__ hist,
+                                                        uint32_t* __restrict__ err) {
     __shared__ uint32_t s_h[PB_MAX_FINE];
     for (uint32_t f = threadIdx.x; f < nfine; f += PB_THREADS) s_h[f] = 0;
     __syncthreads();
     bool bad = false;
     for (uint64_t i = blockIdx.x * (uint64_t)PB_THREADS + threadIdx.x; i < cnt;
          i += (uint64_t)gridDim.x * PB_THREADS) {
-        const uint32_t f = pv[i] >> PB_FINE_SHIFT;
+        const uint32_t f = (pv[i] & vmask) >> PB_FINE_SHIFT;
         if (f < nfine)
             atomicAdd(&s_h[f], 1u);
         else
@@ -1203,7 +1165,8 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_hist(const uint32_t* __restri
 
 // One workgroup: bin starts and the accumulation segments of every non-empty bin.
 __global__ __launch_bounds__(PB_PLAN_THREADS) void k_pb_plan(const uint32_t* __restrict__ hist, uint32_t nfine,
-                                                             uint32_t* __restrict__ foff, uint32_t* __restrict__ segs,
+                                                             uint32_t seg, uint32_t* __restrict__ foff,
+                                                             uint32_t* __restrict__ segs,
                                                              uint32_t* __restrict__ nsegs) {
     constexpr uint32_t PER = PB_MAX_FINE / PB_PLAN_THREADS;
     __shared__ uint32_t s_w[PB_PLAN_THREADS / 64 + 1];
@@ -1213,7 +1176,7 @@ __global__ __launch_bounds__(PB_PLAN_THREADS) void k_pb_plan(const uint32_t* __r
     for (uint32_t q = 0; q < PER; q++) {
         c[q] = f0 + q < nfine ? hist[f0 + q] : 0u;
         sum += c[q];
-        ns += (c[q] + PB_SEG - 1) / PB_SEG;
+        ns += (c[q] + seg - 1) / seg;
     }
     uint32_t total, stotal;
     uint32_t base = block_excl_sum(sum, s_w, &total);
@@ -1223,7 +1186,7 @@ __global__ __launch_bounds__(PB_PLAN_THREADS) void k_pb_plan(const uint32_t* __r
         if (f >= nfine) break;
         foff[f] = base;
         base += c[q];
-        for (uint32_t j = 0; j * PB_SEG < c[q]; j++, sb++) {
+        for (uint32_t j = 0; (uint64_t)j * seg < c[q]; j++, sb++) {
             segs[2 * sb] = f;
             segs[2 * sb + 1] = j;
         }
@@ -1231,14 +1194,6 @@ __global__ __launch_bounds__(PB_PLAN_THREADS) void k_pb_plan(const uint32_t* __r
     if (threadIdx.x == 0) {
         foff[nfine] = total;
         *nsegs = stotal;
-    }
-}
-
-__global__ void k_pb_cursors(const uint32_t* __restrict__ foff, uint32_t nfine, uint32_t* __restrict__ fcur,
-                             uint32_t* __restrict__ ccur) {
-    for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < nfine; f += gridDim.x * blockDim.x) {
-        fcur[f] = foff[f];
-        if (f % PB_FINE_PER_COARSE == 0) ccur[f / PB_FINE_PER_COARSE] = foff[f];
     }
 }
 
@@ -1261,10 +1216,35 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter(const uint32_t* __res
     const uint32_t nkeys = (nfine + stride - 1) / stride;
     const uint32_t lane = threadIdx.x & 63;
     bool bad = false;
-    for (uint64_t t0 = blockIdx.x * (uint64_t)PB_TILE; t0 < cnt; t0 += (uint64_t)gridDim.x * PB_TILE) {
+    // each workgroup walks tiles blockIdx.x, + gridDim.x, ...; the next tile's loads are
+    // issued before the current tile is sorted
+    const uint64_t step = (uint64_t)gridDim.x * PB_TILE;
+    uint32_t v[PER], key[PER], rank[PER];
+    float c[PER];
+    {
+        const uint64_t t0 = blockIdx.x * (uint64_t)PB_TILE;
         const uint32_t tc = (uint32_t)min((uint64_t)PB_TILE, cnt - t0);
-        uint32_t v[PER], key[PER], rank[PER];
-        float c[PER];
+#pragma unroll
+        for (uint32_t r = 0; r < PER; r++) {
+            const uint32_t i = r * PB_THREADS + threadIdx.x;
+            v[r] = i < tc ? in_v[t0 + i] : 0u;
+            c[r] = i < tc ? in_c[t0 + i] : 0.0f;
+        }
+    }
+    for (uint64_t t0 = blockIdx.x * (uint64_t)PB_TILE; t0 < cnt; t0 += step) {
+        const uint32_t tc = (uint32_t)min((uint64_t)PB_TILE, cnt - t0);
+        uint32_t nv[PER];
+        float nc[PER];
+        {
+            const uint64_t t1 = t0 + step;
+            const uint32_t tc1 = t1 < cnt ? (uint32_t)min((uint64_t)PB_TILE, cnt - t1) : 0u;
+#pragma unroll
+            for (uint32_t r = 0; r < PER; r++) {
+                const uint32_t i = r * PB_THREADS + threadIdx.x;
+                nv[r] = i < tc1 ? in_v[t1 + i] : 0u;
+                nc[r] = i < tc1 ? in_c[t1 + i] : 0.0f;
+            }
+        }
         uint32_t kmin = UINT32_MAX, kmax = 0;
         if (threadIdx.x == 0) {
             s_kmin = UINT32_MAX;
@@ -1272,14 +1252,9 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter(const uint32_t* __res
         }
 #pragma unroll
         for (uint32_t r = 0; r < PER; r++) {
-            const uint32_t i = r * PB_THREADS + threadIdx.x;
-            v[r] = 0;
-            c[r] = 0.0f;
             key[r] = 0;
             rank[r] = 0;
-            if (i < tc) {
-                v[r] = in_v[t0 + i];
-                c[r] = in_c[t0 + i];
+            if (r * PB_THREADS + threadIdx.x < tc) {
                 key[r] = v[r] >> kshift;
                 kmin = min(kmin, key[r]);
                 kmax = max(kmax, key[r]);
@@ -1363,53 +1338,294 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter(const uint32_t* __res
                 }
         }
         __syncthreads();
+#pragma unroll
+        for (uint32_t r = 0; r < PER; r++) {
+            v[r] = nv[r];
+            c[r] = nc[r];
+        }
     }
     if (bad) atomicOr(err, 1u);
 }
 
-__global__ __launch_bounds__(PB_THREADS) void k_pb_accum(const uint32_t* __restrict__ pv,
-                                                         const float* __restrict__ pc,
-                                                         const uint32_t* __restrict__ foff,
-                                                         const uint32_t* __restrict__ segs,
-                                                         const uint32_t* __restrict__ nsegs, uint64_t n,
-                                                         float* __restrict__ acc, uint32_t* __restrict__ err) {
+// Resident push of a piece (every vertex active): slot t of [0, cnt) gets the contribution
+// of its edge's source, the list entry j in [ja, jb) whose work range holds wa + t.
+// tj[k] = the last entry whose range starts at or before tile k's first slot (computed
+// once per piece by k_pb_tiles); a workgroup marks, in an LDS owner map, where each later
+// entry of its tile starts, takes prefix maxima, and writes the tile with coalesced stores.
+constexpr uint32_t PB_EXP_TILE = 4096;
+
+__global__ void k_pb_tiles(const uint64_t* __restrict__ wpre, uint32_t ja, uint32_t jb, uint64_t wa, uint64_t cnt,
+                           uint32_t* __restrict__ tj) {
+    const uint64_t ntiles = (cnt + PB_EXP_TILE - 1) / PB_EXP_TILE;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < ntiles;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t t = wa + k * PB_EXP_TILE;
+        uint32_t lo = ja, hi = jb;  // wpre[ja] <= t < wpre[jb]
+        while (hi - lo > 1) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (wpre[mid] <= t)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        tj[k] = lo;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pb_expand(const uint32_t* __restrict__ list,
+                                                   const uint64_t* __restrict__ wpre, uint32_t jb, uint64_t wa,
+                                                   uint64_t cnt, const uint32_t* __restrict__ tj,
+                                                   const float* __restrict__ contrib, float* __restrict__ pc) {
+    constexpr uint32_t PER = PB_EXP_TILE / 256;
+    __shared__ uint16_t s_owner[PB_EXP_TILE];
+    __shared__ float s_val[PB_EXP_TILE + 1];
+    __shared__ uint32_t s_wave[4];
+    const uint64_t ntiles = (cnt + PB_EXP_TILE - 1) / PB_EXP_TILE;
+    for (uint64_t k = blockIdx.x; k < ntiles; k += gridDim.x) {
+        const uint64_t t0 = k * PB_EXP_TILE;
+        const uint32_t tc = (uint32_t)min((uint64_t)PB_EXP_TILE, cnt - t0);
+        const uint32_t j0 = tj[k];
+        // entries that start inside the tile: j0 + 1 .. (the next tile's first entry), each
+        // at most one per slot
+        const uint32_t jl = k + 1 < ntiles ? tj[k + 1] : jb - 1;
+        const uint32_t nv = jl - j0 + 1;  // <= PB_EXP_TILE + 1
+#pragma unroll
+        for (uint32_t r = 0; r < PER; r++) s_owner[r * 256 + threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nv; i += 256) {
+            const uint32_t j = j0 + i;
+            s_val[i] = contrib[list[j]];
+            if (i) {
+                const uint64_t st = wpre[j] - wa;
+                if (st < t0 + tc) s_owner[st - t0] = (uint16_t)i;
+            }
+        }
+        __syncthreads();
+        block_prefix_max_u16<PER>(s_owner, tc, s_wave);
+#pragma unroll
+        for (uint32_t r = 0; r < PER; r++) {
+            const uint32_t q = r * 256 + threadIdx.x;
+            if (q < tc) pc[t0 + q] = s_val[s_owner[q]];
+        }
+        __syncthreads();
+    }
+}
+
+// First sort pass with fixed output places: workgroup w of the pass takes input slice
+// [w * range, (w + 1) * range), and the pairs of that slice in bin k go to
+// offA[w * nkeys + k] onwards (the slice's pairs and their bins are the same in every
+// PageRank iteration, so the places are counted once).  No global atomics.
+__global__ __launch_bounds__(PB_THREADS) void k_pb_count_a(const uint32_t* __restrict__ in_v, uint32_t vmask,
+                                                           uint64_t cnt, uint64_t range, uint32_t kshift,
+                                                           uint32_t nkeys, uint32_t* __restrict__ cntA,
+                                                           uint32_t* __restrict__ err) {
+    __shared__ uint32_t s_cnt[PB_LOCAL];
+    for (uint32_t b = threadIdx.x; b < nkeys; b += PB_THREADS) s_cnt[b] = 0;
+    __syncthreads();
+    const uint64_t lo = blockIdx.x * range, hi = min(cnt, lo + range);
+    bool bad = false;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += PB_THREADS) {
+        const uint32_t k = (in_v[i] & vmask) >> kshift;
+        if (k < nkeys)
+            atomicAdd(&s_cnt[k], 1u);
+        else
+            bad = true;
+    }
+    if (bad) atomicOr(err, 1u);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nkeys; b += PB_THREADS) cntA[(uint64_t)blockIdx.x * nkeys + b] = s_cnt[b];
+}
+
+// offA[w][k] = start of bin k + pairs of bin k in slices before w (in place over cntA).
+// One workgroup of PB_A_WG threads per bin k, thread w holding slice w.
+__global__ __launch_bounds__(PB_A_WG) void k_pb_scan_a(uint32_t* __restrict__ cntA, uint32_t nwg, uint32_t nkeys,
+                                                       uint32_t stride, const uint32_t* __restrict__ foff) {
+    __shared__ uint32_t s_w[PB_A_WG / 64 + 1];
+    const uint32_t k = blockIdx.x, w = threadIdx.x;
+    const uint64_t at = (uint64_t)w * nkeys + k;
+    const uint32_t c = w < nwg ? cntA[at] : 0u;
+    uint32_t tot;
+    const uint32_t before = block_excl_sum(c, s_w, &tot);
+    if (w < nwg) cntA[at] = foff[k * stride] + before;
+}
+
+__global__ __launch_bounds__(PB_THREADS) void k_pb_scatter_a(const uint32_t* __restrict__ in_v, uint32_t vmask,
+                                                             const float* __restrict__ in_c, uint64_t cnt,
+                                                             uint64_t range, uint32_t kshift, uint32_t stride,
+                                                             uint32_t nfine, const uint32_t* __restrict__ foff,
+                                                             const uint32_t* __restrict__ offA,
+                                                             uint32_t* __restrict__ out_v, float* __restrict__ out_c,
+                                                             uint32_t* __restrict__ fcur, uint32_t* __restrict__ err) {
+    constexpr uint32_t PER = PB_TILE / PB_THREADS;
+    constexpr uint32_t LPER = PB_LOCAL / PB_THREADS;
+    __shared__ uint32_t s_v[PB_TILE];
+    __shared__ float s_c[PB_TILE];
+    __shared__ uint16_t s_k[PB_TILE];
+    __shared__ uint32_t s_cnt[PB_LOCAL], s_ofs[PB_LOCAL], s_run[PB_LOCAL], s_end[PB_LOCAL];
+    __shared__ uint32_t s_w[PB_THREADS / 64 + 1];
+    const uint32_t nkeys = (nfine + stride - 1) / stride;
+    // the second pass's cursors start at the fine bins' starts
+    if (fcur)
+        for (uint32_t f = blockIdx.x * PB_THREADS + threadIdx.x; f < nfine; f += gridDim.x * PB_THREADS)
+            fcur[f] = foff[f];
+    for (uint32_t b = threadIdx.x; b < PB_LOCAL; b += PB_THREADS) {
+        s_run[b] = b < nkeys ? offA[(uint64_t)blockIdx.x * nkeys + b] : 0u;
+        s_end[b] = b < nkeys ? foff[min((b + 1) * stride, nfine)] : 0u;
+    }
+    bool bad = false;
+    const uint64_t lo = blockIdx.x * range, hi = min(cnt, lo + range);
+    uint32_t v[PER], key[PER], rank[PER];
+    float c[PER];
+    // every load of a tile in flight before any is used; the next tile's loads are issued
+    // before the current tile is sorted
+#pragma unroll
+    for (uint32_t r = 0; r < PER; r++) {
+        const uint64_t i = lo + r * PB_THREADS + threadIdx.x;
+        v[r] = i < hi ? in_v[i] & vmask : 0u;
+        c[r] = i < hi ? in_c[i] : 0.0f;
+    }
+    for (uint64_t t0 = lo; t0 < hi; t0 += PB_TILE) {
+        const uint32_t tc = (uint32_t)min((uint64_t)PB_TILE, hi - t0);
+        uint32_t nv[PER];
+        float nc[PER];
+#pragma unroll
+        for (uint32_t r = 0; r < PER; r++) {
+            const uint64_t i = t0 + PB_TILE + r * PB_THREADS + threadIdx.x;
+            nv[r] = i < hi ? in_v[i] & vmask : 0u;
+            nc[r] = i < hi ? in_c[i] : 0.0f;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < LPER; q++) s_cnt[LPER * threadIdx.x + q] = 0;
+        __syncthreads();
+#pragma unroll
+        for (uint32_t r = 0; r < PER; r++) {
+            key[r] = PB_LOCAL;
+            rank[r] = 0;
+            if (r * PB_THREADS + threadIdx.x < tc) {
+                const uint32_t k = v[r] >> kshift;
+                if (k < nkeys) {
+                    key[r] = k;
+                    rank[r] = atomicAdd(&s_cnt[k], 1u);
+                } else {
+                    bad = true;
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t loc[LPER], sum = 0, tot;
+#pragma unroll
+        for (uint32_t q = 0; q < LPER; q++) {
+            loc[q] = s_cnt[LPER * threadIdx.x + q];
+            sum += loc[q];
+        }
+        uint32_t base = block_excl_sum(sum, s_w, &tot);
+#pragma unroll
+        for (uint32_t q = 0; q < LPER; q++) {
+            s_ofs[LPER * threadIdx.x + q] = base;
+            base += loc[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t r = 0; r < PER; r++)
+            if (key[r] < PB_LOCAL) {
+                const uint32_t p = s_ofs[key[r]] + rank[r];
+                s_v[p] = v[r];
+                s_c[p] = c[r];
+                s_k[p] = (uint16_t)key[r];
+            }
+        __syncthreads();
+        for (uint32_t p = threadIdx.x; p < tot; p += PB_THREADS) {
+            const uint32_t k = s_k[p];
+            const uint32_t gpos = s_run[k] + (p - s_ofs[k]);
+            if (gpos < s_end[k]) {
+                out_v[gpos] = s_v[p];
+                out_c[gpos] = s_c[p];
+            } else {
+                bad = true;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t q = 0; q < LPER; q++) s_run[LPER * threadIdx.x + q] += loc[q];
+        // the next tile's count reset follows this update (barrier after the reset)
+#pragma unroll
+        for (uint32_t r = 0; r < PER; r++) {
+            v[r] = nv[r];
+            c[r] = nc[r];
+        }
+    }
+    if (bad) atomicOr(err, 1u);
+}
+
+constexpr int PB_ACC_THREADS = 512;
+constexpr uint32_t PB_ACC_BATCH = 8;  // pairs per thread with loads in flight together
+
+__global__ __launch_bounds__(PB_ACC_THREADS) void k_pb_accum(const uint32_t* __restrict__ pv,
+                                                             const float* __restrict__ pc,
+                                                             const uint32_t* __restrict__ foff,
+                                                             const uint32_t* __restrict__ segs,
+                                                             const uint32_t* __restrict__ nsegs, uint32_t seg,
+                                                             uint64_t n, float* __restrict__ acc,
+                                                             uint32_t* __restrict__ err) {
+    constexpr uint32_t Q4 = PB_FINE / 4 / PB_ACC_THREADS;  // float4 slots per thread
     __shared__ float4 s_a4[PB_FINE / 4];
     float* s_a = (float*)s_a4;
     const uint32_t s = blockIdx.x;
     if (s >= *nsegs) return;  // the same for every thread of the workgroup
     const uint32_t f = segs[2 * s], j = segs[2 * s + 1];
     const uint32_t b0 = foff[f], b1 = foff[f + 1];
-    const uint32_t start = b0 + j * PB_SEG;
-    const uint32_t end = min(b1, start + PB_SEG);
-    const bool multi = b1 - b0 > PB_SEG;
-    for (uint32_t q = threadIdx.x; q < PB_FINE / 4; q += PB_THREADS) s_a4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const uint32_t start = b0 + j * seg;
+    const uint32_t end = min(b1, start + seg);
+    const bool multi = b1 - b0 > seg;
+#pragma unroll
+    for (uint32_t q = 0; q < Q4; q++) s_a4[q * PB_ACC_THREADS + threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     bool bad = false;
-    for (uint32_t i = start + threadIdx.x; i < end; i += PB_THREADS) {
-        const uint32_t v = pv[i];
-        if ((v >> PB_FINE_SHIFT) == f && v < n)
-            atomicAdd(&s_a[acc_slot(v) & (PB_FINE - 1)], pc[i]);
-        else
-            bad = true;
+    for (uint32_t i0 = start; i0 < end; i0 += PB_ACC_BATCH * PB_ACC_THREADS) {
+        uint32_t v[PB_ACC_BATCH];
+        float c[PB_ACC_BATCH];
+#pragma unroll
+        for (uint32_t r = 0; r < PB_ACC_BATCH; r++) {
+            const uint32_t i = i0 + r * PB_ACC_THREADS + threadIdx.x;
+            v[r] = i < end ? pv[i] : UINT32_MAX;
+            c[r] = i < end ? pc[i] : 0.0f;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < PB_ACC_BATCH; r++) {
+            if (i0 + r * PB_ACC_THREADS + threadIdx.x >= end) continue;
+            if ((v[r] >> PB_FINE_SHIFT) == f && v[r] < n)
+                atomicAdd(&s_a[acc_slot(v[r]) & (PB_FINE - 1)], c[r]);
+            else
+                bad = true;
+        }
     }
     if (bad) atomicOr(err, 1u);
     __syncthreads();
     // the bin's accumulator slots: [base, base + lim), lim a multiple of 4096
     const uint64_t base = (uint64_t)f << PB_FINE_SHIFT;
-    const uint32_t lim = (uint32_t)min((uint64_t)PB_FINE, acc_slots(n) - base);
+    const uint32_t lim4 = (uint32_t)min((uint64_t)PB_FINE, acc_slots(n) - base) / 4;
     if (!multi) {
         float4* a4 = (float4*)(acc + base);
-        for (uint32_t q = threadIdx.x; q < lim / 4; q += PB_THREADS) {
-            float4 x = a4[q];
-            const float4 y = s_a4[q];
-            x.x += y.x;
-            x.y += y.y;
-            x.z += y.z;
-            x.w += y.w;
-            a4[q] = x;
+        float4 x[Q4];
+#pragma unroll
+        for (uint32_t q = 0; q < Q4; q++) {
+            const uint32_t k = q * PB_ACC_THREADS + threadIdx.x;
+            if (k < lim4) x[q] = a4[k];
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < Q4; q++) {
+            const uint32_t k = q * PB_ACC_THREADS + threadIdx.x;
+            if (k < lim4) {
+                const float4 y = s_a4[k];
+                x[q].x += y.x;
+                x[q].y += y.y;
+                x[q].z += y.z;
+                x[q].w += y.w;
+                a4[k] = x[q];
+            }
         }
     } else {
-        for (uint32_t q = threadIdx.x; q < lim; q += PB_THREADS)
+        for (uint32_t q = threadIdx.x; q < lim4 * 4; q += PB_ACC_THREADS)
             if (s_a[q] != 0.0f) unsafeAtomicAdd(acc + base + q, s_a[q]);
     }
 }
@@ -1490,7 +1706,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
                     ok = q >= s_s[k] && q < s_e[k];
                     val = s_val[k];
                 }
-                push_if(op, ok, val, pk_v(cv[r], pk), Op::weighted ? pk_w(cv[r], wv[r], pk) : 0u, e);
+                push_if(op, ok, val, pk_v(cv[r], pk), Op::weighted ? pk_w(cv[r], wv[r], pk) : 0u);
             }
         }
         __syncthreads();
@@ -1709,10 +1925,6 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
     case ALGO_MPPR:
         return push_edges_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
                              item_hi, off, col, w, shift, compacted, s.pk, st);
-    case ALGO_PR_PB:
-        if (compacted) return hipErrorInvalidValue;  // pairs are slotted by CSR edge index
-        return push_edges_op(OpPrPb{s.contrib, s.pb_v, s.pb_c, s.pb_e0, s.pb_cap}, list, wpre, ja, jb, item_lo, item_hi,
-                             off, col, w, shift, compacted, s.pk, st);
     default:
         return push_edges_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
                              compacted, s.pk, st);
@@ -1722,8 +1934,9 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
 template <class Op>
 static hipError_t push_lines_op(const Op& op, const uint32_t* list, const uint64_t* wpre, uint32_t ja, uint32_t jb,
                                 uint64_t lo, uint64_t hi, const uint64_t* off, const uint32_t* col,
-                                const uint32_t* w, unsigned long long* distinct, const Pack& pk, hipStream_t st) {
-    const unsigned g = grid_for(hi - lo, LINE_IPB, GRID_CAP);
+                                const uint32_t* w, unsigned long long* distinct, const Pack& pk, hipStream_t st,
+                                unsigned cap = GRID_CAP) {
+    const unsigned g = grid_for(hi - lo, LINE_IPB, cap ? cap : GRID_CAP);
     k_push_lines<Op><<<g, LINE_THREADS, 0, st>>>(list, wpre, ja, jb, lo, hi, off, col, w, op, distinct, pk);
     return hipGetLastError();
 }
@@ -1751,41 +1964,33 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
     case ALGO_MPPR:
         return push_lines_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
                              item_hi, off, col, w, distinct, s.pk, st);
-    case ALGO_PR_PB:
-        return push_lines_op(OpPrPb{s.contrib, s.pb_v, s.pb_c, s.pb_e0, s.pb_cap}, list, wpre, ja, jb, item_lo, item_hi, off,
-                             col, w, distinct, s.pk, st);
     default:
-        return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, s.pk, st);
+        return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w,
+                             distinct, s.pk, st, s.link_grid);
     }
 }
 
 hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
                              uint32_t copies, hipStream_t st) {
     if (!n) return hipSuccess;
-    if (copies < 1 || copies > ACC_COPIES) return hipErrorInvalidValue;
+    if (copies < 1 || copies > ACC_COPIES + 1) return hipErrorInvalidValue;
     k_pr_prepare<<<grid_for(acc_slots(n), 256, 8192), 256, 0, st>>>(n, off, x, contrib, acc, copies);
     return hipGetLastError();
 }
 
-hipError_t launch_pb_hist(const uint32_t* pv, uint64_t cnt, uint32_t nfine, uint32_t* hist, uint32_t* err,
-                          hipStream_t st) {
+hipError_t launch_pb_hist(const uint32_t* pv, uint32_t vmask, uint64_t cnt, uint32_t nfine, uint32_t* hist,
+                          uint32_t* err, hipStream_t st) {
     if (!cnt) return hipSuccess;
     if (nfine == 0 || nfine > PB_MAX_FINE) return hipErrorInvalidValue;
     const unsigned g = (unsigned)std::min<uint64_t>(256, (cnt + 4095) / 4096);
-    k_pb_hist<<<g, PB_THREADS, 0, st>>>(pv, cnt, nfine, hist, err);
+    k_pb_hist<<<g, PB_THREADS, 0, st>>>(pv, vmask, cnt, nfine, hist, err);
     return hipGetLastError();
 }
 
-hipError_t launch_pb_plan(const uint32_t* hist, uint32_t nfine, uint32_t* foff, uint32_t* segs, uint32_t* nsegs,
-                          hipStream_t st) {
-    if (nfine == 0 || nfine > PB_MAX_FINE) return hipErrorInvalidValue;
-    k_pb_plan<<<1, PB_PLAN_THREADS, 0, st>>>(hist, nfine, foff, segs, nsegs);
-    return hipGetLastError();
-}
-
-hipError_t launch_pb_cursors(const uint32_t* foff, uint32_t nfine, uint32_t* fcur, uint32_t* ccur, hipStream_t st) {
-    if (nfine == 0 || nfine > PB_MAX_FINE) return hipErrorInvalidValue;
-    k_pb_cursors<<<grid_for(nfine, 256, 64), 256, 0, st>>>(foff, nfine, fcur, ccur);
+hipError_t launch_pb_plan(const uint32_t* hist, uint32_t nfine, uint32_t seg, uint32_t* foff, uint32_t* segs,
+                          uint32_t* nsegs, hipStream_t st) {
+    if (nfine == 0 || nfine > PB_MAX_FINE || seg == 0) return hipErrorInvalidValue;
+    k_pb_plan<<<1, PB_PLAN_THREADS, 0, st>>>(hist, nfine, seg, foff, segs, nsegs);
     return hipGetLastError();
 }
 
@@ -1796,24 +2001,83 @@ hipError_t launch_pb_scatter(const uint32_t* in_v, const float* in_c, uint64_t c
     if (nfine == 0 || nfine > PB_MAX_FINE || (stride != 1 && stride != PB_FINE_PER_COARSE) ||
         (1u << kshift) != stride * PB_FINE)
         return hipErrorInvalidValue;
-    k_pb_scatter<<<grid_for(cnt, PB_TILE, 4096), PB_THREADS, 0, st>>>(in_v, in_c, cnt, kshift, stride, nfine, foff,
+    k_pb_scatter<<<grid_for(cnt, PB_TILE, 2048), PB_THREADS, 0, st>>>(in_v, in_c, cnt, kshift, stride, nfine, foff,
                                                                       cursor, out_v, out_c, err);
     return hipGetLastError();
 }
 
-hipError_t launch_pb_accum(const uint32_t* pv, const float* pc, const uint32_t* foff, const uint32_t* segs,
-                           const uint32_t* nsegs, uint32_t max_segs, uint64_t n, float* acc, uint32_t* err,
+hipError_t launch_pb_tiles(const uint64_t* wpre, uint32_t ja, uint32_t jb, uint64_t wa, uint64_t cnt, uint32_t* tj,
                            hipStream_t st) {
+    if (!cnt) return hipSuccess;
+    if (jb <= ja) return hipErrorInvalidValue;
+    const uint64_t ntiles = (cnt + PB_EXP_TILE - 1) / PB_EXP_TILE;
+    k_pb_tiles<<<grid_for(ntiles, 256, 1024), 256, 0, st>>>(wpre, ja, jb, wa, cnt, tj);
+    return hipGetLastError();
+}
+
+hipError_t launch_pb_expand(const uint32_t* list, const uint64_t* wpre, uint32_t jb, uint64_t wa, uint64_t cnt,
+                            const uint32_t* tj, const float* contrib, float* pc, hipStream_t st) {
+    if (!cnt) return hipSuccess;
+    const uint64_t ntiles = (cnt + PB_EXP_TILE - 1) / PB_EXP_TILE;
+    k_pb_expand<<<(unsigned)std::min<uint64_t>(ntiles, 4096), 256, 0, st>>>(list, wpre, jb, wa, cnt, tj, contrib, pc);
+    return hipGetLastError();
+}
+
+// Slices of the first sort pass: `wg` workgroups of `range` pairs (a multiple of PB_TILE).
+void pb_slices(uint64_t cnt, uint32_t* wg, uint64_t* range) {
+    const uint64_t tiles = (cnt + PB_TILE - 1) / PB_TILE;
+    const uint64_t per = (tiles + PB_A_WG - 1) / PB_A_WG;
+    *range = std::max<uint64_t>(per, 1) * PB_TILE;
+    *wg = (uint32_t)std::max<uint64_t>(1, (cnt + *range - 1) / *range);
+}
+
+hipError_t launch_pb_plan_a(const uint32_t* pv, uint32_t vmask, uint64_t cnt, uint32_t kshift, uint32_t stride,
+                            uint32_t nfine, const uint32_t* foff, uint32_t* offA, uint32_t* err, hipStream_t st) {
+    if (!cnt) return hipSuccess;
+    const uint32_t nkeys = (nfine + stride - 1) / stride;
+    if (nfine == 0 || nfine > PB_MAX_FINE || nkeys > PB_LOCAL || (1u << kshift) != stride * PB_FINE)
+        return hipErrorInvalidValue;
+    uint32_t wg;
+    uint64_t range;
+    pb_slices(cnt, &wg, &range);
+    k_pb_count_a<<<wg, PB_THREADS, 0, st>>>(pv, vmask, cnt, range, kshift, nkeys, offA, err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_pb_scan_a<<<nkeys, PB_A_WG, 0, st>>>(offA, wg, nkeys, stride, foff);
+    return hipGetLastError();
+}
+
+hipError_t launch_pb_scatter_a(const uint32_t* in_v, uint32_t vmask, const float* in_c, uint64_t cnt,
+                               uint32_t kshift, uint32_t stride, uint32_t nfine, const uint32_t* foff,
+                               const uint32_t* offA, uint32_t* out_v, float* out_c, uint32_t* fcur, uint32_t* err,
+                               hipStream_t st) {
+    if (!cnt) return hipSuccess;
+    const uint32_t nkeys = (nfine + stride - 1) / stride;
+    if (nfine == 0 || nfine > PB_MAX_FINE || nkeys > PB_LOCAL || (1u << kshift) != stride * PB_FINE)
+        return hipErrorInvalidValue;
+    uint32_t wg;
+    uint64_t range;
+    pb_slices(cnt, &wg, &range);
+    k_pb_scatter_a<<<wg, PB_THREADS, 0, st>>>(in_v, vmask, in_c, cnt, range, kshift, stride, nfine, foff, offA, out_v,
+                                              out_c, fcur, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_pb_accum(const uint32_t* pv, const float* pc, const uint32_t* foff, const uint32_t* segs,
+                           const uint32_t* nsegs, uint32_t max_segs, uint32_t seg, uint64_t n, float* acc,
+                           uint32_t* err, hipStream_t st) {
     if (!max_segs || !n) return hipSuccess;
-    k_pb_accum<<<max_segs, PB_THREADS, 0, st>>>(pv, pc, foff, segs, nsegs, n, acc, err);
+    if (seg == 0) return hipErrorInvalidValue;
+    k_pb_accum<<<max_segs, PB_ACC_THREADS, 0, st>>>(pv, pc, foff, segs, nsegs, seg, n, acc, err);
     return hipGetLastError();
 }
 
 template <class Op>
 static hipError_t push_fstream_op(const Op& op, const FTask* tasks, uint32_t ntasks, uint64_t chunks,
                                   const uint32_t* list, const uint64_t* off, const uint32_t* col, const uint32_t* w,
-                                  const Pack& pk, hipStream_t st) {
-    const unsigned g = (unsigned)(chunks < GRID_CAP ? chunks : GRID_CAP);
+                                  const Pack& pk, hipStream_t st, unsigned cap = GRID_CAP) {
+    const unsigned c = cap ? cap : GRID_CAP;
+    const unsigned g = (unsigned)(chunks < c ? chunks : c);
     k_push_fstream<Op><<<g, LINE_THREADS, 0, st>>>(tasks, ntasks, chunks, list, off, col, w, op, pk);
     return hipGetLastError();
 }
@@ -1841,18 +2105,16 @@ hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t 
     case ALGO_MPPR:
         return push_fstream_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, tasks, ntasks, total_chunks,
                                list, off, col, w, s.pk, st);
-    case ALGO_PR_PB:
-        return push_fstream_op(OpPrPb{s.contrib, s.pb_v, s.pb_c, s.pb_e0, s.pb_cap}, tasks, ntasks, total_chunks, list, off,
-                               col, w, s.pk, st);
     default:
-        return push_fstream_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, tasks, ntasks, total_chunks, list, off, col, w, s.pk, st);
+        return push_fstream_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, tasks, ntasks, total_chunks, list, off, col, w,
+                               s.pk, st, s.link_grid);
     }
 }
 
 hipError_t launch_pr_apply(uint64_t n, float* x, const float* acc, uint32_t copies, float base, float damping,
                            const float* inv_n, float restart, hipStream_t st) {
     if (!n) return hipSuccess;
-    if (copies < 1 || copies > ACC_COPIES) return hipErrorInvalidValue;
+    if (copies < 1 || copies > ACC_COPIES + 1) return hipErrorInvalidValue;
     k_pr_apply<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, x, acc, copies, base, damping, inv_n, restart);
     return hipGetLastError();
 }

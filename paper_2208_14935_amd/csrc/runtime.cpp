@@ -217,11 +217,12 @@ struct hytm_graph {
     DevBuf<uint8_t> d_sched;      // ... partitions scheduled this iteration
     HostBuf<uint8_t> h_sched;
     HostBuf<uint64_t> h_lanes;
-    // PageRank propagation blocking: pair buffers [lane * 2 + b] of the resident (lane 0) and
-    // streamed (lane 1) pieces, [4] = the first sort pass's target; bucket plans per piece
-    DevBuf<uint32_t> d_pb_v[5];
-    DevBuf<float> d_pb_c[5];
-    DevBuf<uint32_t> d_pb_hist, d_pb_foff, d_pb_segs, d_pb_nsegs, d_pb_fcur, d_pb_ccur, d_pb_err;
+    // PageRank propagation blocking: contribution buffers [0], [1] of alternate pieces (their
+    // destination words, [0] and [1] too, are written by the second sort pass), [2] = the
+    // first sort pass's target; bucket plans per piece
+    DevBuf<uint32_t> d_pb_v[3];
+    DevBuf<float> d_pb_c[3];
+    DevBuf<uint32_t> d_pb_hist, d_pb_foff, d_pb_segs, d_pb_nsegs, d_pb_offa, d_pb_fcur, d_pb_err, d_pb_tj;
 
     // host mirrors of the per-iteration selection
     HostBuf<Header> h_hdr;
@@ -243,7 +244,7 @@ struct hytm_graph {
     // streams / events
     hipStream_t s_main = nullptr, s_copy = nullptr, s_fk = nullptr, s_zc = nullptr, s_c = nullptr, s_pb = nullptr;
     hipEvent_t ev_copied[kMaxSlots] = {}, ev_free[kMaxSlots] = {};
-    hipEvent_t ev_pbpush[3] = {}, ev_pbfree[4] = {};
+    hipEvent_t ev_pbpush = nullptr, ev_pbfree[2] = {};
     hipEvent_t ev_cdone[2] = {}, ev_join[4] = {}, ev_start = nullptr, ev_clist = nullptr, ev_go = nullptr;
 
     Pool* pool = nullptr;
@@ -284,7 +285,7 @@ bool params_valid(const hytm_params& p, std::string* why) {
     if (p.reprocess > 2) return bad("reprocess must be 0, 1 or 2");
     if (p.rq_distinct_lines > 1) return bad("rq_distinct_lines must be 0 or 1");
     if (p.zc_tie > 1) return bad("zc_tie must be 0 or 1");
-    if (p.pr_blocking > 1) return bad("pr_blocking must be 0 or 1");
+    if (p.pr_blocking > 2) return bad("pr_blocking must be 0, 1 or 2");
     if (p.pr_block_pairs >= (1ull << 31)) return bad("pr_block_pairs must be below 2^31");
     if (!frac_ok(p.compact_gather_num, p.compact_gather_den, false))
         return bad("compact_gather must be num/den with den in 1..65536");
@@ -450,7 +451,7 @@ void ensure_streams(hytm_graph* g) {
     HIP_CHECK(hipStreamCreateWithFlags(&g->s_zc, hipStreamNonBlocking));
     HIP_CHECK(hipStreamCreateWithFlags(&g->s_c, hipStreamNonBlocking));
     HIP_CHECK(hipStreamCreateWithFlags(&g->s_pb, hipStreamNonBlocking));
-    for (auto& e : g->ev_pbpush) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&g->ev_pbpush, hipEventDisableTiming));
     for (auto& e : g->ev_pbfree) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (uint32_t i = 0; i < kMaxSlots; i++) {
         HIP_CHECK(hipEventCreateWithFlags(&g->ev_copied[i], hipEventDisableTiming));
@@ -492,12 +493,12 @@ void release_all(hytm_graph* g) {
     g->d_inv_n.release();
     g->h_lanes.release();
     g->d_hdr.release();
-    for (int i = 0; i < 5; i++) {
+    for (int i = 0; i < 3; i++) {
         g->d_pb_v[i].release();
         g->d_pb_c[i].release();
     }
-    for (auto* b : {&g->d_pb_hist, &g->d_pb_foff, &g->d_pb_segs, &g->d_pb_nsegs, &g->d_pb_fcur, &g->d_pb_ccur,
-                    &g->d_pb_err})
+    for (auto* b : {&g->d_pb_hist, &g->d_pb_foff, &g->d_pb_segs, &g->d_pb_nsegs, &g->d_pb_offa, &g->d_pb_fcur,
+                    &g->d_pb_err, &g->d_pb_tj})
         b->release();
     for (uint32_t i = 0; i < kMaxSlots; i++) {
         g->d_slot_col[i].release();
@@ -520,8 +521,7 @@ void release_all(hytm_graph* g) {
     g->h_col = g->h_w = nullptr;
     for (hipStream_t s : {g->s_main, g->s_copy, g->s_fk, g->s_zc, g->s_c, g->s_pb})
         if (s) (void)hipStreamDestroy(s);
-    for (auto e : g->ev_pbpush)
-        if (e) (void)hipEventDestroy(e);
+    if (g->ev_pbpush) (void)hipEventDestroy(g->ev_pbpush);
     for (auto e : g->ev_pbfree)
         if (e) (void)hipEventDestroy(e);
     for (uint32_t i = 0; i < kMaxSlots; i++) {
@@ -567,16 +567,13 @@ struct Totals {
     uint64_t av = 0, ae = 0, bf = 0, bc = 0, zcl = 0, d2h = 0, ftasks = 0, cchunks = 0;
 };
 
-// A run of consecutive partitions whose pairs fit one piece buffer (PageRank with
-// propagation blocking), with the parts of the selection's lists and filter tasks that
-// cover it.
+// A run of consecutive resident partitions whose edges fit one piece buffer (PageRank
+// with propagation blocking), with the part of the selection's resident list covering it.
 struct PbPiece {
-    int lane = 0;                    // 0: resident partitions, 1: streamed partitions
-    uint64_t e0 = 0, cnt = 0;        // CSR edge range [e0, e0 + cnt): pair slot = edge - e0
-    uint32_t rja = 0, rjb = 0, zja = 0, zjb = 0;  // resident / zero-copy list ranges
-    uint64_t rwa = 0, rwb = 0, zwa = 0, zwb = 0;  // ... and their work ranges
-    uint32_t ta = 0, tb = 0;         // streaming filter tasks (chunk0 counted from task ta)
-    uint64_t fchunks = 0, fedges = 0;
+    uint64_t e0 = 0, cnt = 0;        // CSR edge range [e0, e0 + cnt): slot = edge - e0
+    uint32_t ja = 0, jb = 0;         // resident list range
+    uint64_t wa = 0, wb = 0;         // ... and its work range
+    uint64_t tj = 0;                 // first entry of its expand-tile table
 };
 
 // One traversal: a single-source or whole-graph run, or one group of lanes (a batched
@@ -611,11 +608,12 @@ struct RunCtx {
     struct {
         bool ok = false;
         Header h{};
-        std::vector<PbPiece> pieces;
-        std::vector<uint32_t> lane[2];  // piece indices per lane, in partition order
+        std::vector<PbPiece> pieces;    // over the resident partitions, in order
         uint64_t cap = 0;               // pairs per piece buffer
-        uint32_t nfine = 0, max_segs = 0, ftasks = 0;
-        uint64_t fedges = 0;
+        uint32_t nfine = 0, seg = 0, max_segs = 0;
+        uint32_t keys_a = 0;            // bins of the first sort pass (coarse, or fine if only one pass)
+        uint32_t ftasks = 0;            // streaming filter tasks of the streamed partitions
+        uint64_t fchunks = 0, fedges = 0;
     } pb;
     uint32_t t = 0;                            // iterations taken
     Totals tot;
@@ -1047,89 +1045,109 @@ hytm_status replay_pass(RunCtx& rc, hipStream_t main, hytm_iter_stats* rec, int6
 }
 
 // ------------------------------------------------------ propagation blocking
-// PageRank's adds go through pair buckets (see PB_* in the kernel header) when it runs
-// alone, the selection can contain no compaction partitions (their pushes do not know the
-// CSR index of an edge), filter partitions use the streaming engine, and the fine bins
-// fit the LDS histogram.
+// Workgroups of the streamed pushes beside the resident pieces.
+constexpr uint32_t kPbLinkGrid = 2048;
+
+// PageRank's resident adds go through pair buckets (see PB_* in the kernel header) when it
+// runs alone, some partitions are resident, the selection can contain no compaction
+// partitions (their pushes are not replayed), filter partitions use the streaming engine,
+// and the fine bins fit one LDS counting sort (n <= 2^24).  The two-pass sort for larger
+// graphs is built but switched off: its test process ended in a host segmentation fault
+// whose cause is not found yet, so those graphs keep the atomic adds.
+constexpr bool kPbTwoPass = false;
+
+// pr_blocking = 1 (automatic) also asks for at least half of the edges to be resident:
+// below that the streamed atomics and the host link bound the iteration, and the sorting
+// passes competing for CUs with the zero-copy kernel cost more than they save.
 bool pb_eligible(const RunCtx& rc) {
     const hytm_graph* g = rc.g;
-    return rc.algo == HYTM_PAGERANK && !rc.batched && g->params.pr_blocking && g->m > 0 &&
-           pb_fine_bins(g->n) <= PB_MAX_FINE && g->max_part_edges < (1ull << 31) && g->n / 2 < (1ull << 31) &&
-           g->params.mode != HYTM_MODE_COMPACT && g->params.filter_engine == HYTM_FILTER_STREAM;
+    const uint32_t nfine = pb_fine_bins(g->n);
+    const uint32_t nres = std::min(rc.plan.nres, g->npart);
+    const bool wanted = g->params.pr_blocking == 2 || (g->params.pr_blocking == 1 && 2 * g->h_off[g->pv[nres]] >= g->m);
+    return rc.algo == HYTM_PAGERANK && !rc.batched && wanted && g->m > 0 && rc.plan.nres > 0 &&
+           nfine <= (kPbTwoPass ? PB_MAX_FINE : PB_LOCAL_BINS) && g->max_part_edges < (1ull << 31) &&
+           g->n < (1ull << 31) && g->params.mode != HYTM_MODE_COMPACT &&
+           g->params.filter_engine == HYTM_FILTER_STREAM;
 }
 
-// Pairs per piece buffer: by default half a pair per vertex, so that a piece's bucket
-// flushes (one read-modify-write of every accumulator slot) cost at most 16 bytes per
-// pair; never less than the largest partition, never more than the edges.
-uint64_t pb_capacity(const hytm_graph* g) {
-    const uint64_t want = g->params.pr_block_pairs ? g->params.pr_block_pairs : std::max<uint64_t>(g->n / 2, 1ull << 20);
-    return std::min<uint64_t>(std::max<uint64_t>(want, g->max_part_edges), g->m);
+// Pairs per piece buffer: by default one pair per vertex, so that a piece's bucket flushes
+// (one read-modify-write of every accumulator slot) cost at most 8 bytes per pair; never
+// less than the largest partition, never more than the resident edges.
+uint64_t pb_capacity(const hytm_graph* g, uint64_t res_edges) {
+    const uint64_t want = g->params.pr_block_pairs ? g->params.pr_block_pairs : std::max<uint64_t>(g->n, 1ull << 20);
+    return std::max<uint64_t>(std::min<uint64_t>(std::max<uint64_t>(want, g->max_part_edges), res_edges), 1);
 }
 
-// List and work range of segment `seg` over partitions [pa, pb): its entries run from the
-// first such partition's bases to those of the next one at or after pb (or the segment's end).
-void seg_range(const hytm_graph* g, const Header& h, int seg, uint32_t pa, uint32_t pb, uint32_t* ja, uint32_t* jb,
-               uint64_t* wa, uint64_t* wb) {
-    const uint8_t code = (uint8_t)(seg + 1);
-    const uint8_t* md = g->h_mode.p;
-    uint32_t p = pa;
-    while (p < pb && md[p] != code) p++;
-    *ja = *jb = 0;
-    *wa = *wb = 0;
-    if (p == pb) return;
-    *ja = g->h_lbase.p[p];
-    *wa = g->h_wbase.p[p];
-    uint32_t q = pb;
-    while (q < g->npart && md[q] != code) q++;
-    if (q < g->npart) {
-        *jb = g->h_lbase.p[q];
-        *wb = g->h_wbase.p[q];
-    } else {
-        *jb = h.seg_list_start[seg] + h.seg_list_count[seg];
-        *wb = h.seg_work_start[seg] + h.seg_work_total[seg];
-    }
-}
-
-// Cut the first iteration's selection into pieces, build each piece's filter tasks, and
-// put the pair buffers and bucket plans in place.
+// Cut the resident partitions of the first iteration's selection into pieces, build the
+// streaming filter tasks of the streamed partitions, and put the buffers and bucket plans
+// in place.
 hytm_status pb_plan(RunCtx& rc, const Header& h, hipStream_t main) {
     hytm_graph* g = rc.g;
     auto& pb = rc.pb;
     const uint32_t npart = g->npart;
     const uint8_t* md = g->h_mode.p;
+    const uint32_t nres = std::min(rc.plan.nres, npart);
     pb.h = h;
-    pb.cap = pb_capacity(g);
+    pb.cap = pb_capacity(g, g->h_off[g->pv[nres]]);
     pb.nfine = pb_fine_bins(g->n);
-    pb.max_segs = pb_max_segs(pb.nfine, pb.cap);
+    pb.seg = pb_seg_len(pb.nfine, pb.cap);
+    pb.max_segs = pb_max_segs(pb.nfine, pb.cap, pb.seg);
+    pb.keys_a = pb.nfine > PB_LOCAL_BINS ? pb_coarse_bins(pb.nfine) : pb.nfine;
     pb.pieces.clear();
-    pb.lane[0].clear();
-    pb.lane[1].clear();
     pb.ftasks = 0;
-    pb.fedges = 0;
-    for (uint32_t p = 0; p < npart; p++)
+    pb.fchunks = pb.fedges = 0;
+    for (uint32_t p = 0; p < npart; p++) {
         if (md[p] == P_COMPACT) return fail(HYTM_E_STATE, "internal: compaction partition under PageRank blocking");
-    const uint32_t k = g->params.combine_k;
-    const uint64_t fend_list = h.seg_list_start[SEG_F] + h.seg_list_count[SEG_F];
-    g->h_tasks.ensure(npart);
-    auto add = [&](uint32_t pa, uint32_t pb_, int lane) {
+        if ((p < nres) != (md[p] == P_RES) && g->pE[p] > 0)
+            return fail(HYTM_E_STATE, "internal: resident partitions are not the resident prefix");
+    }
+    // resident pieces: runs of partitions with at most cap edges
+    uint64_t tj = 0;
+    uint32_t pa = 0;
+    while (pa < nres) {
+        uint32_t pb_ = pa;
+        uint64_t e = 0;
+        while (pb_ < nres && (pb_ == pa || e + g->pE[pb_] <= pb.cap)) e += g->pE[pb_++];
         PbPiece pc;
-        pc.lane = lane;
         pc.e0 = g->h_off[g->pv[pa]];
         pc.cnt = g->h_off[g->pv[pb_]] - pc.e0;
-        if (pc.cnt == 0) return;
-        seg_range(g, h, SEG_R, pa, pb_, &pc.rja, &pc.rjb, &pc.rwa, &pc.rwb);
-        seg_range(g, h, SEG_Z, pa, pb_, &pc.zja, &pc.zjb, &pc.zwa, &pc.zwb);
-        // filter tasks: runs of <= k adjacent filter partitions, cut at the piece's end
-        pc.ta = pb.ftasks;
-        uint32_t i = pa;
-        while (i < pb_) {
+        if (pc.cnt) {
+            // the resident list holds the active vertices of the resident partitions in
+            // order: the piece's entries run from its first resident partition's bases to
+            // those of the next resident partition after it (or the segment's end)
+            uint32_t p = pa;
+            while (md[p] != P_RES) p++;  // a partition with edges is resident below nres
+            pc.ja = g->h_lbase.p[p];
+            pc.wa = g->h_wbase.p[p];
+            uint32_t q = pb_;
+            while (q < nres && md[q] != P_RES) q++;
+            if (q < nres) {
+                pc.jb = g->h_lbase.p[q];
+                pc.wb = g->h_wbase.p[q];
+            } else {
+                pc.jb = h.seg_list_start[SEG_R] + h.seg_list_count[SEG_R];
+                pc.wb = h.seg_work_start[SEG_R] + h.seg_work_total[SEG_R];
+            }
+            pc.tj = tj;
+            tj += pb_tiles(pc.cnt);
+            pb.pieces.push_back(pc);
+        }
+        pa = pb_;
+    }
+    // streamed filter partitions: tasks of <= k adjacent ones (Sec. 5.2), one launch per pass
+    if (h.seg_list_count[SEG_F]) {
+        g->h_tasks.ensure(npart);
+        const uint32_t k = g->params.combine_k;
+        const uint64_t fend_list = h.seg_list_start[SEG_F] + h.seg_list_count[SEG_F];
+        uint32_t i = 0;
+        while (i < npart) {
             if (md[i] != P_FILTER) {
                 i++;
                 continue;
             }
             uint32_t j = i + 1;
             uint64_t edges = g->pE[i];
-            while (j < pb_ && j - i < k && md[j] == P_FILTER) edges += g->pE[j++];
+            while (j < npart && j - i < k && md[j] == P_FILTER) edges += g->pE[j++];
             uint32_t nx = j;
             while (nx < npart && md[nx] != P_FILTER) nx++;
             FTask& ft = g->h_tasks.p[pb.ftasks++];
@@ -1137,64 +1155,47 @@ hytm_status pb_plan(RunCtx& rc, const Header& h, hipStream_t main) {
             ft.e1 = ft.e0 + edges;
             ft.ja = g->h_lbase.p[i];
             ft.jb = nx < npart ? g->h_lbase.p[nx] : (uint32_t)fend_list;
-            ft.chunk0 = pc.fchunks;
-            pc.fchunks += fstream_chunks(ft.e0, ft.e1);
-            pc.fedges += edges;
+            ft.chunk0 = pb.fchunks;
+            pb.fchunks += fstream_chunks(ft.e0, ft.e1);
+            pb.fedges += edges;
             i = j;
         }
-        pc.tb = pb.ftasks;
-        pb.fedges += pc.fedges;
-        pb.lane[lane].push_back((uint32_t)pb.pieces.size());
-        pb.pieces.push_back(pc);
-    };
-    auto cut = [&](uint32_t a, uint32_t b, int lane) {
-        uint32_t pa = a;
-        while (pa < b) {
-            uint32_t pb_ = pa;
-            uint64_t e = 0;
-            while (pb_ < b && (pb_ == pa || e + g->pE[pb_] <= pb.cap)) e += g->pE[pb_++];
-            add(pa, pb_, lane);
-            pa = pb_;
-        }
-    };
-    const uint32_t nres = std::min(rc.plan.nres, npart);
-    cut(0, nres, 0);
-    cut(nres, npart, 1);
-    if (pb.ftasks) {
         g->d_tasks.ensure(pb.ftasks);
         HIP_CHECK(hipMemcpyAsync(g->d_tasks.p, g->h_tasks.p, pb.ftasks * sizeof(FTask), hipMemcpyHostToDevice, main));
     }
     const uint32_t np = (uint32_t)pb.pieces.size();
-    for (int lane = 0; lane < 2; lane++)
-        for (uint32_t b = 0; b < std::min<size_t>(2, pb.lane[lane].size()); b++) {
-            g->d_pb_v[lane * 2 + b].ensure(pb.cap);
-            g->d_pb_c[lane * 2 + b].ensure(pb.cap);
-        }
-    g->d_pb_v[4].ensure(pb.cap);
-    g->d_pb_c[4].ensure(pb.cap);
+    const uint32_t nbuf = std::min<uint32_t>(2, np);
+    for (uint32_t b = 0; b < nbuf; b++) {
+        g->d_pb_v[b].ensure(pb.cap);
+        g->d_pb_c[b].ensure(pb.cap);
+    }
+    g->d_pb_v[2].ensure(pb.cap);
+    g->d_pb_c[2].ensure(pb.cap);
     g->d_pb_hist.ensure(pb.nfine);
     g->d_pb_foff.ensure((uint64_t)np * (pb.nfine + 1));
     g->d_pb_segs.ensure((uint64_t)np * 2 * pb.max_segs);
-    g->d_pb_nsegs.ensure(np);
+    g->d_pb_nsegs.ensure(std::max<uint32_t>(np, 1));
+    g->d_pb_offa.ensure((uint64_t)np * pb_max_offa(pb.keys_a));
     g->d_pb_fcur.ensure(pb.nfine);
-    g->d_pb_ccur.ensure(pb_coarse_bins(pb.nfine));
+    g->d_pb_tj.ensure(std::max<uint64_t>(tj, 1));
     g->d_pb_err.ensure(1);
     HIP_CHECK(launch_fill_u32(g->d_pb_err.p, 1, 0u, main));
     return HYTM_OK;
 }
 
-// One PageRank push pass with propagation blocking.  Pieces of the two lanes are issued in
-// turn, in proportion to their edges: a piece's pushes (resident, zero-copy and filter
-// parts on their engines' streams) write its pair buffer, then the bucketing stream sorts
-// and sums the pairs into the accumulators and frees the buffer for the lane's piece after
-// next.  `first`: the bucket plans are counted (the same pairs recur every iteration).
+// One PageRank push pass with propagation blocking over the resident partitions.  The
+// streamed partitions are pushed as in every pass (zero-copy and streaming filter kernels
+// with atomic adds into the per-XCD copies), while the resident pieces alternate between
+// two buffers: a piece's push writes its contributions, then the bucketing stream sorts
+// and sums the piece's pairs into the blocking copy and frees the buffer for the piece
+// after next.  `first`: the bucket plans are counted (the same pairs recur every iteration).
 hytm_status pb_pass(RunCtx& rc, hipStream_t main, hytm_iter_stats* rec, int64_t trace_t, bool first) {
     hytm_graph* g = rc.g;
     KTimer& kt = g->timer;
     const auto& pb = rc.pb;
+    const Header& h = pb.h;
     const uint32_t npart = g->npart;
     if (!first) {
-        const Header& h = pb.h;
         uint32_t scheduled = 0;
         for (int s = 0; s < NSEG; s++) {
             rec->parts[s + 1] += h.seg_parts[s];
@@ -1209,102 +1210,84 @@ hytm_status pb_pass(RunCtx& rc, hipStream_t main, hytm_iter_stats* rec, int64_t 
     }
     HIP_CHECK(hipEventRecord(g->ev_go, main));
     for (hipStream_t s : {g->s_c, g->s_zc, g->s_fk, g->s_pb}) HIP_CHECK(hipStreamWaitEvent(s, g->ev_go, 0));
-    AlgoState as = rc.as;
-    as.algo = ALGO_PR_PB;
-    as.pb_cap = pb.cap;
-    const uint32_t nfine = pb.nfine, ncoarse = pb_coarse_bins(nfine);
-    uint64_t lane_total[2] = {0, 0}, lane_done[2] = {0, 0};
-    for (int l = 0; l < 2; l++)
-        for (uint32_t i : pb.lane[l]) lane_total[l] += pb.pieces[i].cnt;
-    uint32_t next[2] = {0, 0};
-    while (next[0] < pb.lane[0].size() || next[1] < pb.lane[1].size()) {
-        // the lane that has issued the smaller share of its edges goes next
-        int lane;
-        if (next[0] == pb.lane[0].size())
-            lane = 1;
-        else if (next[1] == pb.lane[1].size())
-            lane = 0;
-        else
-            lane = (double)lane_done[0] * lane_total[1] <= (double)lane_done[1] * lane_total[0] ? 0 : 1;
-        const uint32_t kk = next[lane]++;
-        const uint32_t pi = pb.lane[lane][kk];
+    AlgoState& as = rc.as;
+    // streamed partitions: atomic adds, at most at the host link's rate, from a grid that
+    // keeps the link busy and leaves CUs to the resident pieces
+    AlgoState al = as;
+    al.link_grid = kPbLinkGrid;
+    if (h.seg_list_count[SEG_Z]) {
+        HIP_CHECK(kt.run(HYTM_K_PUSH_ZC, h.seg_work_total[SEG_Z], g->s_zc, [&] {
+            return launch_push_lines(al, g->d_list.p, g->d_wpre.p, h.seg_list_start[SEG_Z],
+                                     h.seg_list_start[SEG_Z] + h.seg_list_count[SEG_Z], h.seg_work_start[SEG_Z],
+                                     h.seg_work_start[SEG_Z] + h.seg_work_total[SEG_Z], g->d_off.p, g->d_col_map,
+                                     g->d_w_map, (unsigned long long*)g->d_zcl.p, g->s_zc);
+        }));
+        rec->zc_lines += h.seg_work_total[SEG_Z];
+    }
+    if (pb.ftasks) {
+        HIP_CHECK(kt.run(HYTM_K_PUSH_F, pb.fedges, g->s_fk, [&] {
+            return launch_push_fstream(al, g->d_tasks.p, pb.ftasks, pb.fchunks, g->d_list.p, g->d_off.p,
+                                       g->d_col_map, g->d_w_map, g->s_fk);
+        }));
+        rec->filter_tasks += pb.ftasks;
+        rec->bytes_filter += pb.fedges * 4;
+    }
+    // resident pieces
+    const uint32_t nfine = pb.nfine;
+    const bool two = nfine > PB_LOCAL_BINS;  // one pass when every fine bin fits the LDS sort
+    const uint32_t shift_a = two ? PB_FINE_SHIFT + 5 : PB_FINE_SHIFT;
+    const uint32_t stride_a = two ? PB_FINE_PER_COARSE : 1;
+    float* acc_pb = as.acc + (uint64_t)ACC_COPIES * acc_slots(g->n);  // the blocking copy
+    hipStream_t sp = g->s_pb;
+    uint32_t* err = g->d_pb_err.p;
+    for (uint32_t pi = 0; pi < pb.pieces.size(); pi++) {
         const PbPiece& pc = pb.pieces[pi];
-        lane_done[lane] += pc.cnt;
-        const int buf = lane * 2 + (int)(kk & 1);
-        as.pb_v = g->d_pb_v[buf].p;
-        as.pb_c = g->d_pb_c[buf].p;
-        as.pb_e0 = pc.e0;
-        const bool hasR = pc.rjb > pc.rja && pc.rwb > pc.rwa;
-        const bool hasZ = pc.zjb > pc.zja && pc.zwb > pc.zwa;
-        const bool hasF = pc.tb > pc.ta;
-        if (kk >= 2) {  // the buffer's previous piece has been summed
-            if (hasR) HIP_CHECK(hipStreamWaitEvent(g->s_c, g->ev_pbfree[buf], 0));
-            if (hasZ) HIP_CHECK(hipStreamWaitEvent(g->s_zc, g->ev_pbfree[buf], 0));
-            if (hasF) HIP_CHECK(hipStreamWaitEvent(g->s_fk, g->ev_pbfree[buf], 0));
-        }
-        if (hasR) {
-            HIP_CHECK(kt.run(HYTM_K_PUSH_RES, pc.rwb - pc.rwa, g->s_c, [&] {
-                return launch_push_edges(as, g->d_list.p, g->d_wpre.p, pc.rja, pc.rjb, pc.rwa, pc.rwb, g->d_off.p,
-                                         g->d_res_col.p, g->d_res_w.p, 0, false, g->s_c);
-            }));
-            HIP_CHECK(hipEventRecord(g->ev_pbpush[0], g->s_c));
-            HIP_CHECK(hipStreamWaitEvent(g->s_pb, g->ev_pbpush[0], 0));
-        }
-        if (hasZ) {
-            HIP_CHECK(kt.run(HYTM_K_PUSH_ZC, pc.zwb - pc.zwa, g->s_zc, [&] {
-                return launch_push_lines(as, g->d_list.p, g->d_wpre.p, pc.zja, pc.zjb, pc.zwa, pc.zwb, g->d_off.p,
-                                         g->d_col_map, g->d_w_map, (unsigned long long*)g->d_zcl.p, g->s_zc);
-            }));
-            HIP_CHECK(hipEventRecord(g->ev_pbpush[1], g->s_zc));
-            HIP_CHECK(hipStreamWaitEvent(g->s_pb, g->ev_pbpush[1], 0));
-            rec->zc_lines += pc.zwb - pc.zwa;
-        }
-        if (hasF) {
-            HIP_CHECK(kt.run(HYTM_K_PUSH_F, pc.fedges, g->s_fk, [&] {
-                return launch_push_fstream(as, g->d_tasks.p + pc.ta, pc.tb - pc.ta, pc.fchunks, g->d_list.p,
-                                           g->d_off.p, g->d_col_map, g->d_w_map, g->s_fk);
-            }));
-            HIP_CHECK(hipEventRecord(g->ev_pbpush[2], g->s_fk));
-            HIP_CHECK(hipStreamWaitEvent(g->s_pb, g->ev_pbpush[2], 0));
-        }
+        const int buf = (int)(pi & 1);
+        uint32_t* pv = g->d_pb_v[buf].p;
+        float* pcv = g->d_pb_c[buf].p;
+        if (pi >= 2) HIP_CHECK(hipStreamWaitEvent(g->s_c, g->ev_pbfree[buf], 0));  // summed already
+        uint32_t* tjp = g->d_pb_tj.p + pc.tj;
+        if (first) HIP_CHECK(launch_pb_tiles(g->d_wpre.p, pc.ja, pc.jb, pc.wa, pc.cnt, tjp, g->s_c));
+        HIP_CHECK(kt.run(HYTM_K_PUSH_RES, pc.cnt, g->s_c, [&] {
+            return launch_pb_expand(g->d_list.p, g->d_wpre.p, pc.jb, pc.wa, pc.cnt, tjp, as.contrib, pcv, g->s_c);
+        }));
+        HIP_CHECK(hipEventRecord(g->ev_pbpush, g->s_c));
+        HIP_CHECK(hipStreamWaitEvent(sp, g->ev_pbpush, 0));
         uint32_t* foff = g->d_pb_foff.p + (uint64_t)pi * (nfine + 1);
         uint32_t* segs = g->d_pb_segs.p + (uint64_t)pi * 2 * pb.max_segs;
         uint32_t* nsegs = g->d_pb_nsegs.p + pi;
-        uint32_t* pv = g->d_pb_v[buf].p;
-        float* pcv = g->d_pb_c[buf].p;
-        uint32_t* err = g->d_pb_err.p;
-        hipStream_t sp = g->s_pb;
+        uint32_t* offa = g->d_pb_offa.p + (uint64_t)pi * pb_max_offa(pb.keys_a);
+        const uint32_t* in_v = g->d_res_col.p + pc.e0;  // destinations: the resident edge words
+        const uint32_t vmask = g->pk.mask;
         HIP_CHECK(kt.run(HYTM_K_PR_BLOCK, pc.cnt, sp, [&]() -> hipError_t {
             hipError_t e;
             if (first) {
                 if ((e = launch_fill_u32(g->d_pb_hist.p, nfine, 0u, sp)) != hipSuccess) return e;
-                if ((e = launch_pb_hist(pv, pc.cnt, nfine, g->d_pb_hist.p, err, sp)) != hipSuccess) return e;
-                if ((e = launch_pb_plan(g->d_pb_hist.p, nfine, foff, segs, nsegs, sp)) != hipSuccess) return e;
-            }
-            if ((e = launch_pb_cursors(foff, nfine, g->d_pb_fcur.p, g->d_pb_ccur.p, sp)) != hipSuccess) return e;
-            uint32_t* sv = g->d_pb_v[4].p;
-            float* sc = g->d_pb_c[4].p;
-            if (ncoarse > 1) {
-                // coarse pass into the sort buffer, fine pass back into the piece buffer
-                if ((e = launch_pb_scatter(pv, pcv, pc.cnt, PB_FINE_SHIFT + 5, PB_FINE_PER_COARSE, nfine, foff,
-                                           g->d_pb_ccur.p, sv, sc, err, sp)) != hipSuccess)
+                if ((e = launch_pb_hist(in_v, vmask, pc.cnt, nfine, g->d_pb_hist.p, err, sp)) != hipSuccess) return e;
+                if ((e = launch_pb_plan(g->d_pb_hist.p, nfine, pb.seg, foff, segs, nsegs, sp)) != hipSuccess) return e;
+                if ((e = launch_pb_plan_a(in_v, vmask, pc.cnt, shift_a, stride_a, nfine, foff, offa, err, sp)) !=
+                    hipSuccess)
                     return e;
-                if ((e = launch_pb_scatter(sv, sc, pc.cnt, PB_FINE_SHIFT, 1, nfine, foff, g->d_pb_fcur.p, pv, pcv,
-                                           err, sp)) != hipSuccess)
-                    return e;
-                return launch_pb_accum(pv, pcv, foff, segs, nsegs, pb.max_segs, g->n, rc.as.acc, err, sp);
             }
-            if ((e = launch_pb_scatter(pv, pcv, pc.cnt, PB_FINE_SHIFT, 1, nfine, foff, g->d_pb_fcur.p, sv, sc, err,
+            uint32_t* sv = g->d_pb_v[2].p;
+            float* sc = g->d_pb_c[2].p;
+            // first pass into the sort buffer (coarse bins, or fine bins when there is one pass)
+            if ((e = launch_pb_scatter_a(in_v, vmask, pcv, pc.cnt, shift_a, stride_a, nfine, foff, offa, sv, sc,
+                                         two ? g->d_pb_fcur.p : nullptr, err, sp)) != hipSuccess)
+                return e;
+            if (!two) return launch_pb_accum(sv, sc, foff, segs, nsegs, pb.max_segs, pb.seg, g->n, acc_pb, err, sp);
+            // fine pass back into the piece buffer, then the sums
+            if ((e = launch_pb_scatter(sv, sc, pc.cnt, PB_FINE_SHIFT, 1, nfine, foff, g->d_pb_fcur.p, pv, pcv, err,
                                        sp)) != hipSuccess)
                 return e;
-            return launch_pb_accum(sv, sc, foff, segs, nsegs, pb.max_segs, g->n, rc.as.acc, err, sp);
+            return launch_pb_accum(pv, pcv, foff, segs, nsegs, pb.max_segs, pb.seg, g->n, acc_pb, err, sp);
         }));
         HIP_CHECK(hipEventRecord(g->ev_pbfree[buf], sp));
     }
-    HIP_CHECK(hipEventRecord(g->ev_join[3], g->s_pb));
-    HIP_CHECK(hipStreamWaitEvent(main, g->ev_join[3], 0));
-    rec->filter_tasks += pb.ftasks;
-    rec->bytes_filter += pb.fedges * 4;
+    HIP_CHECK(hipEventRecord(g->ev_join[0], g->s_fk));
+    HIP_CHECK(hipEventRecord(g->ev_join[1], g->s_zc));
+    HIP_CHECK(hipEventRecord(g->ev_join[3], sp));
+    for (int q : {0, 1, 3}) HIP_CHECK(hipStreamWaitEvent(main, g->ev_join[q], 0));
     return HYTM_OK;
 }
 
@@ -1319,7 +1302,7 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
     const uint32_t t = rc.t;
     const bool fixed_steps = rc.algo == HYTM_PAGERANK || rc.algo == HYTM_PPR;
     const double t_it = now_ms();
-    const uint32_t copies = rc.pb_on ? 1u : ACC_COPIES;  // blocked adds need no per-XCD copies
+    const uint32_t copies = rc.pb_on ? ACC_COPIES + 1 : ACC_COPIES;  // + the blocking copy
     if (rc.algo == HYTM_PAGERANK)
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
             return launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, copies, main);
@@ -1536,7 +1519,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     if (pr_like) {
         g->d_x.ensure(n);
         g->d_contrib.ensure(n);
-        g->d_acc.ensure(ACC_COPIES * acc_slots(n));
+        g->d_acc.ensure((ACC_COPIES + 1) * acc_slots(n));  // per-XCD copies + the blocking copy
     }
     if (algo == HYTM_PAGERANK_DELTA) {
         g->d_delta.ensure(n);
