@@ -235,85 +235,114 @@ __global__ void k_select_only(uint64_t npart, const uint64_t* __restrict__ E, co
 }
 
 // -------------------------------------------------------------------- scan
-__global__ __launch_bounds__(1024) void k_scan(uint32_t npart, const uint8_t* __restrict__ mode,
+constexpr int SCAN_THREADS = 512;  // 2 waves per SIMD: room for the 21 running sums per thread
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan(uint32_t npart, const uint8_t* __restrict__ mode,
                                                const uint32_t* __restrict__ nA, const uint32_t* __restrict__ nF,
                                                const uint64_t* __restrict__ Ea, const uint64_t* __restrict__ Rq,
                                                const uint64_t* __restrict__ K, uint32_t* __restrict__ lbase,
                                                uint64_t* __restrict__ wbase, Header* __restrict__ hdr,
                                                uint64_t* __restrict__ wpre) {
-    __shared__ uint64_t lds[16];
-    const uint32_t per = (npart + 1023) / 1024;
+    // per thread: a contiguous run of partitions; per segment the list entries (nA) and work
+    // items to scan, and the partitions, edges and cost lines to total, plus the frontier
+    constexpr int NV = 5 * NSEG + 1;  // cnt[4], work[4], parts[4], edges[4], lines[4], frontier
+    constexpr int NW = SCAN_THREADS / 64;
+    __shared__ uint64_t s_tot[NW][NV];
+    const uint32_t per = (npart + SCAN_THREADS - 1) / SCAN_THREADS;
     const uint32_t i0 = min(threadIdx.x * per, npart), i1 = min(i0 + per, npart);
-    uint64_t cnt[NSEG] = {0, 0, 0, 0}, work[NSEG] = {0, 0, 0, 0}, parts[NSEG] = {0, 0, 0, 0};
-    uint64_t edges[NSEG] = {0, 0, 0, 0}, cl[NSEG] = {0, 0, 0, 0}, fr = 0;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t val[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) val[k] = 0;
     for (uint32_t i = i0; i < i1; i++) {
-        fr += nF[i];
+        val[NV - 1] += nF[i];
         const uint8_t m = mode[i];
         if (m == P_NONE) continue;
+        const uint64_t ea = Ea[i], w = (m == P_ZC) ? K[i] : ea, na = nA[i], rq = Rq[i];
 #pragma unroll
-        for (int s = 0; s < NSEG; s++) {
-            if (m != s + 1) continue;
-            parts[s] += 1;
-            cnt[s] += nA[i];
-            work[s] += (m == P_ZC) ? K[i] : Ea[i];
-            edges[s] += Ea[i];
-            cl[s] += Rq[i];
+        for (int sg = 0; sg < NSEG; sg++) {
+            if (m != sg + 1) continue;
+            val[sg] += na;
+            val[NSEG + sg] += w;
+            val[2 * NSEG + sg] += 1;
+            val[3 * NSEG + sg] += ea;
+            val[4 * NSEG + sg] += rq;
         }
     }
-    uint64_t ex_cnt[NSEG], ex_work[NSEG], tot_cnt[NSEG], tot_work[NSEG], tot_parts[NSEG], tot_edges[NSEG],
-        tot_cl[NSEG];
+    // wave scans for the scanned values (kept as wave-exclusive prefixes), wave sums for
+    // the rest; the per-wave totals go to LDS
+    uint64_t ex[2 * NSEG];
 #pragma unroll
-    for (int s = 0; s < NSEG; s++) {
-        ex_cnt[s] = block_exclusive_scan<1024>(cnt[s], lds, &tot_cnt[s]);
-        ex_work[s] = block_exclusive_scan<1024>(work[s], lds, &tot_work[s]);
-        tot_parts[s] = block_sum<1024>(parts[s], lds);
-        tot_edges[s] = block_sum<1024>(edges[s], lds);
-        tot_cl[s] = block_sum<1024>(cl[s], lds);
+    for (int k = 0; k < 2 * NSEG; k++) {
+        uint64_t v = val[k];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = __shfl_up(v, d, 64);
+            if (lane >= d) v += y;
+        }
+        ex[k] = v - val[k];
+        if (lane == 63) s_tot[wid][k] = v;
     }
-    const uint64_t tot_fr = block_sum<1024>(fr, lds);
-    uint64_t lstart[NSEG], wstart[NSEG];
+#pragma unroll
+    for (int k = 2 * NSEG; k < NV; k++) {
+        const uint64_t v = wave_sum(val[k]);
+        if (lane == 0) s_tot[wid][k] = v;
+    }
+    __syncthreads();
+    // segments lie one after another: RESIDENT, FILTER, ZEROCOPY, COMPACT
+    uint64_t lstart[NSEG], wstart[NSEG], runc[NSEG], runw[NSEG];
     uint64_t la = 0, wa = 0;
 #pragma unroll
-    for (int s = 0; s < NSEG; s++) {
-        lstart[s] = la;
-        wstart[s] = wa;
-        la += tot_cnt[s];
-        wa += tot_work[s];
-    }
-    uint64_t runc[NSEG], runw[NSEG];
-#pragma unroll
-    for (int s = 0; s < NSEG; s++) {
-        runc[s] = lstart[s] + ex_cnt[s];
-        runw[s] = wstart[s] + ex_work[s];
+    for (int sg = 0; sg < NSEG; sg++) {
+        uint64_t bc = 0, tc = 0, bw = 0, tw = 0;
+        for (int w = 0; w < NW; w++) {
+            const uint64_t xc = s_tot[w][sg], xw = s_tot[w][NSEG + sg];
+            bc += w < wid ? xc : 0;
+            bw += w < wid ? xw : 0;
+            tc += xc;
+            tw += xw;
+        }
+        lstart[sg] = la;
+        wstart[sg] = wa;
+        runc[sg] = la + bc + ex[sg];
+        runw[sg] = wa + bw + ex[NSEG + sg];
+        la += tc;
+        wa += tw;
     }
     for (uint32_t i = i0; i < i1; i++) {
         const uint8_t m = mode[i];
         uint32_t lb = 0xFFFFFFFFu;
         uint64_t wb = ~0ull;
 #pragma unroll
-        for (int s = 0; s < NSEG; s++) {
-            if (m != s + 1) continue;
-            lb = (uint32_t)runc[s];
-            wb = runw[s];
-            runc[s] += nA[i];
-            runw[s] += (m == P_ZC) ? K[i] : Ea[i];
+        for (int sg = 0; sg < NSEG; sg++) {
+            if (m != sg + 1) continue;
+            lb = (uint32_t)runc[sg];
+            wb = runw[sg];
+            runc[sg] += nA[i];
+            runw[sg] += (m == P_ZC) ? K[i] : Ea[i];
         }
         lbase[i] = lb;
         wbase[i] = wb;
     }
     if (threadIdx.x == 0) {
+        uint64_t tot[NV];
 #pragma unroll
-        for (int s = 0; s < NSEG; s++) {
-            hdr->seg_parts[s] = (uint32_t)tot_parts[s];
-            hdr->seg_list_start[s] = (uint32_t)lstart[s];
-            hdr->seg_list_count[s] = (uint32_t)tot_cnt[s];
-            hdr->seg_work_start[s] = wstart[s];
-            hdr->seg_work_total[s] = tot_work[s];
-            hdr->seg_edges[s] = tot_edges[s];
-            hdr->seg_cost_lines[s] = tot_cl[s];
+        for (int k = 0; k < NV; k++) {
+            tot[k] = 0;
+            for (int w = 0; w < NW; w++) tot[k] += s_tot[w][k];
+        }
+#pragma unroll
+        for (int sg = 0; sg < NSEG; sg++) {
+            hdr->seg_parts[sg] = (uint32_t)tot[2 * NSEG + sg];
+            hdr->seg_list_start[sg] = (uint32_t)lstart[sg];
+            hdr->seg_list_count[sg] = (uint32_t)tot[sg];
+            hdr->seg_work_start[sg] = wstart[sg];
+            hdr->seg_work_total[sg] = tot[NSEG + sg];
+            hdr->seg_edges[sg] = tot[3 * NSEG + sg];
+            hdr->seg_cost_lines[sg] = tot[4 * NSEG + sg];
         }
         hdr->total_active = la;
-        hdr->frontier = tot_fr;
+        hdr->frontier = tot[NV - 1];
         wpre[la] = wa;
     }
 }
@@ -1873,7 +1902,7 @@ hipError_t launch_stats_select(uint32_t npart, const uint32_t* pv, const uint64_
 hipError_t launch_scan(uint32_t npart, const uint8_t* mode, const uint32_t* nA, const uint32_t* nF,
                        const uint64_t* Ea, const uint64_t* Rq, const uint64_t* K, uint32_t* lbase, uint64_t* wbase,
                        Header* hdr, uint64_t* wpre, hipStream_t st) {
-    k_scan<<<1, 1024, 0, st>>>(npart, mode, nA, nF, Ea, Rq, K, lbase, wbase, hdr, wpre);
+    k_scan<<<1, SCAN_THREADS, 0, st>>>(npart, mode, nA, nF, Ea, Rq, K, lbase, wbase, hdr, wpre);
     return hipGetLastError();
 }
 

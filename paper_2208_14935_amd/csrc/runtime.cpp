@@ -75,20 +75,30 @@ double now_ms() {
 }
 
 // ------------------------------------------------------------ device buffer
+// Owns its allocation, or (view) points into another buffer's.
 template <class T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    bool owns = true;
     void ensure(size_t count) {
-        if (count <= n && p) return;
+        if (count <= n && p && owns) return;
         release();
         HIP_CHECK(hipMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T)));
         n = count;
+        owns = true;
+    }
+    void view(void* at, size_t count) {
+        release();
+        p = (T*)at;
+        n = count;
+        owns = false;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && owns) (void)hipFree(p);
         p = nullptr;
         n = 0;
+        owns = true;
     }
 };
 
@@ -96,16 +106,25 @@ template <class T>
 struct HostBuf {  // pinned host memory
     T* p = nullptr;
     size_t n = 0;
+    bool owns = true;
     void ensure(size_t count) {
-        if (count <= n && p) return;
+        if (count <= n && p && owns) return;
         release();
         HIP_CHECK(hipHostMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
         n = count;
+        owns = true;
+    }
+    void view(void* at, size_t count) {
+        release();
+        p = (T*)at;
+        n = count;
+        owns = false;
     }
     void release() {
-        if (p) (void)hipHostFree(p);
+        if (p && owns) (void)hipHostFree(p);
         p = nullptr;
         n = 0;
+        owns = true;
     }
 };
 
@@ -224,7 +243,10 @@ struct hytm_graph {
     DevBuf<float> d_pb_c[3];
     DevBuf<uint32_t> d_pb_hist, d_pb_foff, d_pb_segs, d_pb_nsegs, d_pb_offa, d_pb_fcur, d_pb_err, d_pb_tj;
 
-    // host mirrors of the per-iteration selection
+    // host mirrors of the per-iteration selection (views into h_sel, as the device arrays
+    // d_hdr, d_wbase, d_lbase, d_mode are views into d_sel)
+    DevBuf<uint8_t> d_sel;
+    HostBuf<uint8_t> h_sel;
     HostBuf<Header> h_hdr;
     HostBuf<uint8_t> h_mode;
     HostBuf<uint32_t> h_lbase;
@@ -361,6 +383,21 @@ SelParams make_sel(const hytm_graph* g, uint32_t arrays) {
 
 // Split of the edge budget (reading of the paper's placement: the budget covers only
 // edge-associated device memory).
+// Byte layout of the selection block: header, work bases (8 B), list bases (4 B), engine
+// codes (1 B) per partition.
+struct SelLayout {
+    size_t wbase, lbase, mode, bytes;
+};
+SelLayout sel_layout(uint32_t npart) {
+    SelLayout L;
+    L.wbase = (sizeof(Header) + 15) & ~size_t(15);
+    L.lbase = L.wbase + 8 * (size_t)npart;
+    L.mode = L.lbase + 4 * (size_t)npart;
+    L.bytes = L.mode + npart;
+    return L;
+}
+size_t sel_block_bytes(uint32_t npart) { return sel_layout(npart).bytes; }
+
 struct Plan {
     uint32_t nres = 0;
     uint64_t res_edges = 0;
@@ -512,6 +549,8 @@ void release_all(hytm_graph* g) {
     }
     g->h_hdr.release();
     g->h_mode.release();
+    g->d_sel.release();  // after its views
+    g->h_sel.release();
     g->h_lbase.release();
     g->h_wbase.release();
     g->h_clist.release();
@@ -706,19 +745,29 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
     g->d_zcl.ensure(1);
     g->d_lanes.ensure(1);
     g->h_lanes.ensure(1);
-    g->d_mode.ensure(npart);
+
     g->d_nA.ensure(npart);
     g->d_nF.ensure(npart);
-    g->d_lbase.ensure(npart);
+
     g->d_Ea.ensure(npart);
     g->d_Rq.ensure(npart);
     g->d_K.ensure(npart);
-    g->d_wbase.ensure(npart);
-    g->d_hdr.ensure(1);
-    g->h_hdr.ensure(1);
-    g->h_mode.ensure(npart);
-    g->h_lbase.ensure(npart);
-    g->h_wbase.ensure(npart);
+    // the selection that crosses to the host every iteration -- header, list and work bases,
+    // engine codes -- is one block on each side, moved by one copy
+    const size_t sel_bytes = sel_block_bytes(npart);
+    if (g->d_sel.n < sel_bytes || g->h_sel.n < sel_bytes || g->d_hdr.p != (Header*)g->d_sel.p) {
+        g->d_sel.ensure(sel_bytes);
+        g->h_sel.ensure(sel_bytes);
+        const SelLayout L = sel_layout(npart);
+        g->d_hdr.view(g->d_sel.p, 1);
+        g->d_wbase.view(g->d_sel.p + L.wbase, npart);
+        g->d_lbase.view(g->d_sel.p + L.lbase, npart);
+        g->d_mode.view(g->d_sel.p + L.mode, npart);
+        g->h_hdr.view(g->h_sel.p, 1);
+        g->h_wbase.view(g->h_sel.p + L.wbase, npart);
+        g->h_lbase.view(g->h_sel.p + L.lbase, npart);
+        g->h_mode.view(g->h_sel.p + L.mode, npart);
+    }
 
     // edge-budget buffers
     const bool fstream = g->params.filter_engine == HYTM_FILTER_STREAM;
@@ -818,10 +867,7 @@ hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Heade
                                   g->d_list.p, g->d_wpre.p, main);
     }));
     // 2. selection back to the host (Algorithm 1: copy Vc, p and A to host)
-    HIP_CHECK(hipMemcpyAsync(g->h_hdr.p, g->d_hdr.p, sizeof(Header), hipMemcpyDeviceToHost, main));
-    HIP_CHECK(hipMemcpyAsync(g->h_mode.p, g->d_mode.p, npart, hipMemcpyDeviceToHost, main));
-    HIP_CHECK(hipMemcpyAsync(g->h_lbase.p, g->d_lbase.p, npart * sizeof(uint32_t), hipMemcpyDeviceToHost, main));
-    HIP_CHECK(hipMemcpyAsync(g->h_wbase.p, g->d_wbase.p, npart * sizeof(uint64_t), hipMemcpyDeviceToHost, main));
+    HIP_CHECK(hipMemcpyAsync(g->h_sel.p, g->d_sel.p, sel_block_bytes(npart), hipMemcpyDeviceToHost, main));
     if (lanes) {
         // which lanes have a non-empty frontier this iteration
         HIP_CHECK(launch_fill_u32((uint32_t*)g->d_lanes.p, 2, 0u, main));
