@@ -531,13 +531,16 @@ def serve_workload(args, g, off, gamma, probe):
     each query at its arrival time and measures submit-to-result latency inside the
     library.  The one-at-a-time reference runs the same queries back to back through
     hytm_run and replays the trace through a single FIFO server with those service times.
-    --budget-frac < 0 keeps the graph device-resident."""
+    --budget-bytes sets the edge budget, else --budget-frac of SSSP's edge bytes; --budget-frac < 0
+    keeps the graph device-resident."""
     n = len(off) - 1
     rng = np.random.default_rng(6000 + args.scale)
     kinds = rng.choice(["bfs", "sssp", "ppr"], size=args.queries, p=[0.5, 0.3, 0.2])
     srcs = gen.sources(off, args.queries, 6100 + args.scale)
     arrivals = np.cumsum(rng.exponential(1.0 / args.qps, size=args.queries))
-    if args.budget_frac >= 0:
+    if args.budget_bytes:
+        g.set_budget(int(args.budget_bytes))
+    elif args.budget_frac >= 0:
         g.set_budget(int(args.budget_frac * 4 * g.edge_arrays("sssp") * g.m))  # planned for SSSP's edge words
     outs = {k: hy.pinned_empty(n, np.float32 if k == "ppr" else np.uint32) for k in ("bfs", "sssp", "ppr")}
     for k in ("bfs", "sssp", "ppr"):
@@ -603,8 +606,10 @@ def serve_workload(args, g, off, gamma, probe):
         "value": res["server"]["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.queries, "warmup": 3,
         "ms_per_step": span * 1e3 / args.queries, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32+f32", "data": "synthetic R-MAT, seeded arrivals",
-        "config": {"workload": f"rmat{args.scale}-serve-{args.qps:g}qps", "n": n, "m": int(g.m), "lanes": lanes,
-                   "budget_frac": args.budget_frac, "gamma": list(gamma)},
+        "config": {"workload": f"rmat{args.scale}-serve-{args.qps:g}qps"
+                               + (f"-budget{args.budget_bytes / 1e9:g}GB" if args.budget_bytes else ""),
+                   "n": n, "m": int(g.m), "lanes": lanes, "budget_frac": args.budget_frac,
+                   "budget_bytes": args.budget_bytes, "gamma": list(gamma)},
         "serve": res, "probe": probe,
     }
     print(json.dumps(out), flush=True)
