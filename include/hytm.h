@@ -156,11 +156,12 @@ typedef struct {
                                    least half of the edges are resident; 2: whenever some are; 0: never.
                                    Applies to single PageRank runs with n <= 2^24 in the hybrid, filter
                                    (streaming engine) or zero-copy modes; the result is the same sum in
-                                   another order.  Needs 3 x 8 bytes per pair of a piece of device memory
-                                   outside the edge budget (24 bytes per vertex at the default piece). */
-    uint64_t pr_block_pairs;    /* 0 = automatic (max(n / 2, 2^20), at most m): pairs per piece of
-                                   pr_blocking; a smaller value (never below the largest partition)
-                                   cuts more pieces, e.g. to exercise the piece pipeline on small graphs. */
+                                   another order.  Needs 16 bytes per pair of a piece of device memory
+                                   outside the edge budget (16 bytes per vertex at the default piece). */
+    uint64_t pr_block_pairs;    /* 0 = automatic (max(n, 2^20), at most the resident edges): pairs per
+                                   piece of pr_blocking; a smaller value (never below the largest
+                                   partition) cuts more pieces, e.g. to exercise the piece pipeline on
+                                   small graphs. */
 } hytm_params;
 
 /* How a FILTER task moves its whole partition range to the GPU.  Both transfer every

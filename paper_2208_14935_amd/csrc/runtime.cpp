@@ -236,9 +236,9 @@ struct hytm_graph {
     DevBuf<uint8_t> d_sched;      // ... partitions scheduled this iteration
     HostBuf<uint8_t> h_sched;
     HostBuf<uint64_t> h_lanes;
-    // PageRank propagation blocking: contribution buffers [0], [1] of alternate pieces (their
-    // destination words, [0] and [1] too, are written by the second sort pass), [2] = the
-    // first sort pass's target; bucket plans per piece
+    // PageRank propagation blocking: contribution buffers [0], [1] of alternate pieces
+    // (destination words [0], [1] only for the second sort pass, which writes them), [2] =
+    // the first sort pass's target; bucket plans per piece
     DevBuf<uint32_t> d_pb_v[3];
     DevBuf<float> d_pb_c[3];
     DevBuf<uint32_t> d_pb_hist, d_pb_foff, d_pb_segs, d_pb_nsegs, d_pb_offa, d_pb_fcur, d_pb_err, d_pb_tj;
@@ -1211,8 +1211,9 @@ hytm_status pb_plan(RunCtx& rc, const Header& h, hipStream_t main) {
     }
     const uint32_t np = (uint32_t)pb.pieces.size();
     const uint32_t nbuf = std::min<uint32_t>(2, np);
+    const bool two = pb.nfine > PB_LOCAL_BINS;  // the second pass writes destinations back
     for (uint32_t b = 0; b < nbuf; b++) {
-        g->d_pb_v[b].ensure(pb.cap);
+        if (two) g->d_pb_v[b].ensure(pb.cap);
         g->d_pb_c[b].ensure(pb.cap);
     }
     g->d_pb_v[2].ensure(pb.cap);
