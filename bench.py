@@ -32,8 +32,8 @@ HBM_PEAK_GBPS = 8000.0
 # known size), mean per launch of the timed step.  It holds only for the kernel source and
 # workload it was measured on; otherwise the roofline reports traffic null.
 PMC_TRAFFIC = {"kernel": "push_zerocopy", "workload": "rmat24-ef16-budget0.25-hybrid-rqdistinct-zctie",
-               "kernels_sha256": "31adec1d655a5efd158268dc0129e66d955cc01fb06574846915fd8c7a5660b7",
-               "bytes_per_launch": (2 * 1425366 + 661381) * 1024.0,
+               "kernels_sha256": "398840e0620a7023d502744bbe37493d9e790c82a1692f11c8ad176798ecff52",
+               "bytes_per_launch": (2 * 1425308 + 661392) * 1024.0,
                "summary": "profiles/pmc_traffic_rmat24_budget25_hybrid.md"}
 PCIE_GEN5_X16_GBPS = 63.0
 
