@@ -523,7 +523,7 @@ struct OpMBfs {
 
 // Batched SSSP: every lane active at u relaxes (u, v) in its own distance row.
 struct OpMSssp {
-    static constexpr bool wave = false;
+    static constexpr bool wave = true;
     static constexpr bool weighted = true;
     const uint64_t* mcur;
     uint64_t* mnext;
@@ -552,6 +552,44 @@ struct OpMSssp {
         if (gained) {
             atomicOr((unsigned long long*)(mnext + v), (unsigned long long)gained);
             atomicOr(next + (v >> 5), 1u << (v & 31));
+        }
+    }
+    // Wave form (see OpMPpr::push_wave): each pass gives 64 >> lshift of the wave's edges one
+    // thread per lane, so an edge's relaxations are one atomicMin instruction over its
+    // contiguous distance row; the lanes that improved are collected by ballot and one
+    // thread per edge marks them.  Called by every thread of the wave.
+    __device__ __forceinline__ void push_wave(bool ok, uint32_t u, uint32_t v, uint32_t w) const {
+        if (lshift < 3) {  // rows of 1..4 lanes: one thread per edge
+            if (ok) push(u, v, w);
+            return;
+        }
+        const uint32_t me = __lane_id();
+        const uint32_t slot = me >> lshift, ln = me & ((1u << lshift) - 1);
+        const uint32_t per = 64u >> lshift;
+        const uint64_t rowmask = lshift >= 6 ? ~0ull : ((1ull << (1u << lshift)) - 1);
+        uint64_t act = __ballot(ok);
+        while (act) {
+            uint64_t a = act;
+            for (uint32_t k = 0; k < slot; k++) a &= a - 1;
+            const int from = a ? (int)__ffsll((unsigned long long)a) - 1 : 0;
+            const uint32_t uu = __shfl(u, from, 64), vv = __shfl(v, from, 64), ww = __shfl(w, from, 64);
+            bool gained = false;
+            if (a && ((mcur[uu] >> ln) & 1)) {
+                const uint64_t nd = (uint64_t)dist[((uint64_t)uu << lshift) + ln] + ww;
+                uint32_t* dv = dist + ((uint64_t)vv << lshift) + ln;
+                if (nd >= UNREACHED) {
+                    atomicOr(overflow + (ln >> 5), 1u << (ln & 31));
+                } else if ((uint32_t)nd < *dv) {
+                    const uint32_t old = atomicMin(dv, (uint32_t)nd);
+                    gained = (uint32_t)nd < old;
+                }
+            }
+            const uint64_t g = (__ballot(gained) >> (slot << lshift)) & rowmask;
+            if (a && ln == 0 && g) {
+                atomicOr((unsigned long long*)(mnext + vv), (unsigned long long)g);
+                atomicOr(next + (vv >> 5), 1u << (vv & 31));
+            }
+            for (uint32_t k = 0; k < per && act; k++) act &= act - 1;
         }
     }
 };
@@ -590,7 +628,7 @@ struct OpMPpr {
     // edges one thread per lane, so the adds of one edge are one instruction over a
     // contiguous accumulator row instead of one instruction per lane.  Called by every
     // thread of the wave.
-    __device__ __forceinline__ void push_wave(bool ok, uint32_t u, uint32_t v) const {
+    __device__ __forceinline__ void push_wave(bool ok, uint32_t u, uint32_t v, uint32_t) const {
         if (lshift < 3) {  // rows of 1..4 lanes: one thread per edge
             if (ok) push(u, v, 0);
             return;
@@ -620,7 +658,7 @@ struct OpMPpr {
 template <class Op>
 __device__ __forceinline__ void push_if(const Op& op, bool ok, uint32_t val, uint32_t v, uint32_t w) {
     if constexpr (Op::wave)
-        op.push_wave(ok, val, v);
+        op.push_wave(ok, val, v, w);
     else if (ok)
         op.push(val, v, w);
 }

@@ -247,6 +247,7 @@ struct hytm_graph {
     // d_hdr, d_wbase, d_lbase, d_mode are views into d_sel)
     DevBuf<uint8_t> d_sel;
     HostBuf<uint8_t> h_sel;
+    uint32_t sel_npart = UINT32_MAX;  // partitions the views were laid out for
     HostBuf<Header> h_hdr;
     HostBuf<uint8_t> h_mode;
     HostBuf<uint32_t> h_lbase;
@@ -551,6 +552,7 @@ void release_all(hytm_graph* g) {
     g->h_mode.release();
     g->d_sel.release();  // after its views
     g->h_sel.release();
+    g->sel_npart = UINT32_MAX;
     g->h_lbase.release();
     g->h_wbase.release();
     g->h_clist.release();
@@ -755,7 +757,8 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
     // the selection that crosses to the host every iteration -- header, list and work bases,
     // engine codes -- is one block on each side, moved by one copy
     const size_t sel_bytes = sel_block_bytes(npart);
-    if (g->d_sel.n < sel_bytes || g->h_sel.n < sel_bytes || g->d_hdr.p != (Header*)g->d_sel.p) {
+    // the views depend on npart (repartitioning changes it): re-derive them whenever it differs
+    if (g->sel_npart != npart || g->d_sel.n < sel_bytes || g->h_sel.n < sel_bytes) {
         g->d_sel.ensure(sel_bytes);
         g->h_sel.ensure(sel_bytes);
         const SelLayout L = sel_layout(npart);
@@ -767,6 +770,7 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
         g->h_wbase.view(g->h_sel.p + L.wbase, npart);
         g->h_lbase.view(g->h_sel.p + L.lbase, npart);
         g->h_mode.view(g->h_sel.p + L.mode, npart);
+        g->sel_npart = npart;
     }
 
     // edge-budget buffers

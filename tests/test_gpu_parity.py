@@ -386,3 +386,15 @@ def test_weights_too_wide_to_pack_stay_separate():
     with hy.Graph(off, col, weights=w2) as g:
         assert g.info()["packed_weights"] == 1
         np.testing.assert_array_equal(g.run("sssp", 1).values, oracle.sssp(off, col, w2, 1))
+
+
+@pytest.mark.parametrize("algo", ["bfs", "sssp"])
+def test_repartitioning_the_same_graph_stays_exact(rmat16, algo):
+    """The per-iteration selection block is laid out per partition count: shrinking and
+    growing the partitions of one graph between runs must re-lay it out."""
+    note(f"rmat16 {algo} repartitioned 2048 -> 32768 -> 4096 -> 2048 edges")
+    with rmat16.graph(algo) as g:
+        for pe in (2048, 32768, 4096, 2048):
+            g.set_params(partition_edges=pe)
+            g.set_resident_fraction(algo, 0.25)
+            check(rmat16, algo, g.run(algo, 0))
