@@ -557,9 +557,14 @@ struct OpMSssp {
     // Wave form (see OpMPpr::push_wave): each pass gives 64 >> lshift of the wave's edges one
     // thread per lane, so an edge's relaxations are one atomicMin instruction over its
     // contiguous distance row; the lanes that improved are collected by ballot and one
-    // thread per edge marks them.  Called by every thread of the wave.
+    // thread per edge marks them.  It pays when the rows are dense (a batch started
+    // together); when the wave's edges carry fewer than a quarter row of active lanes on
+    // average (queries at different stages) each thread relaxes its own edge's lanes.
+    // Called by every thread of the wave.
     __device__ __forceinline__ void push_wave(bool ok, uint32_t u, uint32_t v, uint32_t w) const {
-        if (lshift < 3) {  // rows of 1..4 lanes: one thread per edge
+        const uint64_t active = wave_sum(ok ? (uint64_t)__popcll(mcur[u]) : 0ull);
+        const uint64_t edges = (uint64_t)__popcll(__ballot(ok));
+        if (lshift < 3 || active * 4 < (edges << lshift)) {
             if (ok) push(u, v, w);
             return;
         }
