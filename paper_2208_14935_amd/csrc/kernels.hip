@@ -1060,10 +1060,27 @@ __global__ void k_gather_u32(const uint32_t* __restrict__ src, const uint32_t* _
         dst[v] = src[rank[v]];
 }
 
+// minold[label] = the smallest original id among the vertices holding that label.  Nearly
+// every vertex of a graph with a giant component holds the same label, so one word would
+// take an atomic per vertex: lanes holding the label of the wave's first lane fold their ids
+// into one atomic, and no atomic is made when the slot already holds a smaller id (slots
+// only decrease, so a stale read can only let an unneeded atomic through).
 __global__ void k_cc_min_old(const uint32_t* __restrict__ lab, const uint32_t* __restrict__ order, uint64_t n,
-                             uint32_t* __restrict__ minold) {
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
-        atomicMin(minold + lab[v], order[v]);
+                             uint32_t* minold) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < n; base += stride) {  // uniform per block
+        const uint64_t v = base + threadIdx.x;
+        const bool ok = v < n;
+        const uint32_t l = ok ? lab[v] : UNREACHED;
+        const uint32_t o = ok ? order[v] : UNREACHED;
+        const uint32_t l0 = __shfl(l, 0, 64);  // lane 0 holds the wave's smallest v
+        const bool same = ok && l == l0;
+        uint32_t m = same ? o : UNREACHED;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) m = min(m, (uint32_t)__shfl_xor(m, d, 64));
+        if (__lane_id() == 0 && m != UNREACHED && m < minold[l0]) atomicMin(minold + l0, m);
+        if (ok && !same && o < minold[l]) atomicMin(minold + l, o);
+    }
 }
 
 __global__ void k_cc_canon(const uint32_t* __restrict__ lab, const uint32_t* __restrict__ minold,
