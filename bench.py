@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--zc-tie", default="probe",
                     help="where a Tiz = Tef tie goes: 'probe' (zero-copy when full-line zero-copy reads reach 95%% of "
                          "the measured copy rate), 'filter' (the paper) or 'zerocopy'")
+    ap.add_argument("--sssp-delta", type=int, default=0,
+                    help="SSSP far set: bound step (0 = the paper's synchronous push)")
     ap.add_argument("--pr-blocking", type=int, default=1, choices=[0, 1, 2],
                     help="PageRank over resident partitions: bucket the (destination, contribution) pairs and sum "
                          "them in LDS (propagation blocking) -- 1 = when at least half of the edges are resident, "
@@ -162,7 +164,7 @@ def main():
             h.set_params(mode=args.mode, partition_edges=args.partition_edges, combine_k=args.combine_k,
                          filter_engine=args.filter_engine, gamma=gamma, reprocess=int(args.reprocess),
                          compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct), zc_tie=zc_tie,
-                         pr_blocking=args.pr_blocking)
+                         pr_blocking=args.pr_blocking, sssp_delta=args.sssp_delta)
     if args.workload == "batch":
         return batch_workload(args, g, off, col, deg, gamma, probe)
     if args.workload == "serve":
@@ -259,7 +261,8 @@ def main():
                 + (f"-reprocess{args.reprocess}" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
                 + ("" if g.info()["packed_weights"] else "-unpacked")
                 + ("" if cgather[0] == 0 else "-gathercost") + ("-rqdistinct" if args.rq_distinct else "")
-                + ("-zctie" if zc_tie else "") + ("-prblock" if args.pr_blocking == 2 and "pagerank" in algos else ""))
+                + ("-zctie" if zc_tie else "") + ("-prblock" if args.pr_blocking == 2 and "pagerank" in algos else "")
+                + (f"-delta{args.sssp_delta}" if args.sssp_delta and "sssp" in algos else ""))
     roofline = None
     kernels = {}
     if kt:

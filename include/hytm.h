@@ -162,6 +162,16 @@ typedef struct {
                                    piece of pr_blocking; a smaller value (never below the largest
                                    partition) cuts more pieces, e.g. to exercise the piece pipeline on
                                    small graphs. */
+    uint32_t sssp_delta;        /* 0 (default): HYTM_SSSP pushes every improved vertex in the next
+                                   iteration (the paper's synchronous push).  Otherwise improved vertices
+                                   whose new distance is at or above a bound wait in a far set; the bound
+                                   starts at sssp_delta and, when the frontier empties, rises to the
+                                   smallest multiple of sssp_delta above the smallest waiting distance,
+                                   whose vertices below it form the next frontier (the buckets of
+                                   delta-stepping, Meyer and Sanders, J. Algorithms 2003).  Distances are
+                                   the same; fewer edges are pushed again, iterations may exceed the
+                                   synchronous count.  Single-source runs only; batched SSSP ignores it.
+                                   Needs n/8 bytes of device memory outside the edge budget. */
 } hytm_params;
 
 /* How a FILTER task moves its whole partition range to the GPU.  Both transfer every

@@ -53,7 +53,7 @@ class Params(ctypes.Structure):
         ("dpr_max_iterations", ctypes.c_uint32), ("dpr_epsilon", ctypes.c_double),
         ("compact_gather_num", ctypes.c_uint32), ("compact_gather_den", ctypes.c_uint32),
         ("rq_distinct_lines", ctypes.c_uint32), ("zc_tie", ctypes.c_uint32), ("pr_blocking", ctypes.c_uint32),
-        ("pr_block_pairs", ctypes.c_uint64),
+        ("pr_block_pairs", ctypes.c_uint64), ("sssp_delta", ctypes.c_uint32),
     ]
 
 

@@ -103,6 +103,8 @@ struct AlgoState {
     const float* inv_n;   // PageRank over a union of graphs: 1 / (vertices of v's graph), else null
     Pack pk;              // how edge words are laid out
     uint32_t link_grid;   // 0, or at most this many workgroups for the host-reading pushes
+    uint32_t* far;        // SSSP with a bound: improved vertices at or above it wait here (bitmap)
+    uint32_t bound;       // SSSP: distances below it join the next frontier; 0xFFFFFFFF = no bound
 };
 
 // PageRank keeps one accumulator copy per XCD for its atomic adds, plus one for the sums
@@ -216,6 +218,11 @@ hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* rank, uint64_t
 // original -> new ids; minold: n words of scratch.
 hipError_t launch_cc_relabel(const uint32_t* lab, const uint32_t* order, const uint32_t* rank, uint64_t n,
                              uint32_t* minold, uint32_t* dst, hipStream_t st);
+// SSSP's far set: *out = min(*out, smallest distance of a far vertex) (the caller sets *out
+// to 0xFFFFFFFF first); then the far vertices with distance below `bound` move into `cur`.
+hipError_t launch_far_min(const uint32_t* far, const uint32_t* dist, uint32_t nwords, uint32_t* out, hipStream_t st);
+hipError_t launch_far_move(uint32_t* far, const uint32_t* dist, uint32_t* cur, uint32_t nwords, uint32_t bound,
+                           hipStream_t st);
 // Start the lanes of `set` at their sources (their columns must hold the reset values):
 // BFS level = base, SSSP distance = 0, PPR x = 1; lane bits at the source in mcur (and
 // mvisited), source bits in the union frontier `cur`.

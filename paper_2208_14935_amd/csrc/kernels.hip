@@ -427,6 +427,8 @@ struct OpSssp {
     uint32_t* dist;
     uint32_t* next;
     uint32_t* overflow;
+    uint32_t* far;   // improved vertices at or above `bound` wait here (bound 0xFFFFFFFF: never)
+    uint32_t bound;
     __device__ __forceinline__ uint32_t src(uint32_t u) const { return dist[u]; }
     __device__ __forceinline__ void push(uint32_t du, uint32_t v, uint32_t w) const {
         const uint64_t nd = (uint64_t)du + w;
@@ -436,7 +438,7 @@ struct OpSssp {
         }
         if ((uint32_t)nd < dist[v]) {
             const uint32_t old = atomicMin(dist + v, (uint32_t)nd);
-            if ((uint32_t)nd < old) atomicOr(next + (v >> 5), 1u << (v & 31));
+            if ((uint32_t)nd < old) atomicOr(((uint32_t)nd < bound ? next : far) + (v >> 5), 1u << (v & 31));
         }
     }
 };
@@ -1087,6 +1089,46 @@ __global__ void k_cc_canon(const uint32_t* __restrict__ lab, const uint32_t* __r
                            const uint32_t* __restrict__ rank, uint64_t n, uint32_t* __restrict__ dst) {
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
         dst[v] = minold[lab[rank[v]]];
+}
+
+// Smallest distance among the far vertices: one word of the far bitmap per thread, a wave
+// minimum, one atomic per wave that holds any.
+__global__ void k_far_min(const uint32_t* __restrict__ far, const uint32_t* __restrict__ dist, uint32_t nwords,
+                          uint32_t* out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < nwords; base += stride) {  // uniform per block
+        const uint64_t wd = base + threadIdx.x;
+        uint32_t bits = wd < nwords ? far[wd] : 0u, m = UNREACHED;
+        while (bits) {
+            const uint32_t b = __ffs(bits) - 1;
+            bits &= bits - 1;
+            m = min(m, dist[wd * 32 + b]);
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) m = min(m, (uint32_t)__shfl_xor(m, d, 64));
+        if (__lane_id() == 0 && m != UNREACHED) atomicMin(out, m);
+    }
+}
+
+// Far vertices with distance below `bound` leave the far set and join the frontier; each
+// thread owns one word of both bitmaps.
+__global__ void k_far_move(uint32_t* __restrict__ far, const uint32_t* __restrict__ dist, uint32_t* __restrict__ cur,
+                           uint32_t nwords, uint32_t bound) {
+    for (uint64_t wd = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; wd < nwords;
+         wd += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t f = far[wd];
+        if (!f) continue;
+        uint32_t bits = f, moved = 0;
+        while (bits) {
+            const uint32_t b = __ffs(bits) - 1;
+            bits &= bits - 1;
+            if (dist[wd * 32 + b] < bound) moved |= 1u << b;
+        }
+        if (moved) {
+            far[wd] = f & ~moved;
+            cur[wd] |= moved;
+        }
+    }
 }
 
 __global__ void k_admit_lanes(AlgoState s, LaneSet set, uint32_t* __restrict__ cur) {
@@ -1914,6 +1956,19 @@ hipError_t launch_cc_relabel(const uint32_t* lab, const uint32_t* order, const u
     return hipGetLastError();
 }
 
+hipError_t launch_far_min(const uint32_t* far, const uint32_t* dist, uint32_t nwords, uint32_t* out, hipStream_t st) {
+    if (!nwords) return hipSuccess;
+    k_far_min<<<grid_for(nwords, 256, 8192), 256, 0, st>>>(far, dist, nwords, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_far_move(uint32_t* far, const uint32_t* dist, uint32_t* cur, uint32_t nwords, uint32_t bound,
+                           hipStream_t st) {
+    if (!nwords) return hipSuccess;
+    k_far_move<<<grid_for(nwords, 256, 8192), 256, 0, st>>>(far, dist, cur, nwords, bound);
+    return hipGetLastError();
+}
+
 hipError_t launch_admit_lanes(const AlgoState& s, const LaneSet& set, uint32_t* cur, hipStream_t st) {
     if (!set.mask) return hipSuccess;
     k_admit_lanes<<<1, MAX_LANES, 0, st>>>(s, set, cur);
@@ -1997,7 +2052,7 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
         return push_edges_op(OpBfs{s.visited, s.next, s.val, s.level_next}, list, wpre, ja, jb, item_lo, item_hi,
                              off, col, w, shift, compacted, s.pk, st);
     case ALGO_SSSP:
-        return push_edges_op(OpSssp{s.val, s.next, s.overflow}, list, wpre, ja, jb, item_lo, item_hi, off, col, w,
+        return push_edges_op(OpSssp{s.val, s.next, s.overflow, s.far, s.bound}, list, wpre, ja, jb, item_lo, item_hi, off, col, w,
                              shift, compacted, s.pk, st);
     case ALGO_CC:
         return push_edges_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
@@ -2039,7 +2094,7 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
         return push_lines_op(OpBfs{s.visited, s.next, s.val, s.level_next}, list, wpre, ja, jb, item_lo, item_hi,
                              off, col, w, distinct, s.pk, st);
     case ALGO_SSSP:
-        return push_lines_op(OpSssp{s.val, s.next, s.overflow}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, s.pk, st);
+        return push_lines_op(OpSssp{s.val, s.next, s.overflow, s.far, s.bound}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, s.pk, st);
     case ALGO_CC:
         return push_lines_op(OpCc{s.val, s.next}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, distinct, s.pk, st);
     case ALGO_BFS_RELAX:
@@ -2180,7 +2235,7 @@ hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t 
         return push_fstream_op(OpBfs{s.visited, s.next, s.val, s.level_next}, tasks, ntasks, total_chunks, list,
                                off, col, w, s.pk, st);
     case ALGO_SSSP:
-        return push_fstream_op(OpSssp{s.val, s.next, s.overflow}, tasks, ntasks, total_chunks, list, off, col, w, s.pk, st);
+        return push_fstream_op(OpSssp{s.val, s.next, s.overflow, s.far, s.bound}, tasks, ntasks, total_chunks, list, off, col, w, s.pk, st);
     case ALGO_CC:
         return push_fstream_op(OpCc{s.val, s.next}, tasks, ntasks, total_chunks, list, off, col, w, s.pk, st);
     case ALGO_BFS_RELAX:

@@ -229,6 +229,9 @@ struct hytm_graph {
     DevBuf<float> d_lx, d_lacc;   // batched PPR: x and accumulator rows
     DevBuf<uint32_t> d_xout;      // lanes extracted for the copy back
     DevBuf<uint32_t> d_cur2;      // frontier of the reprocessing pass
+    DevBuf<uint32_t> d_far;       // SSSP with sssp_delta: improved vertices waiting for a higher bound
+    DevBuf<uint32_t> d_farmin;    // smallest waiting distance
+    HostBuf<uint32_t> h_farmin;
     DevBuf<uint64_t> d_zcl;       // distinct 128-byte lines read by the zero-copy kernel this run
     DevBuf<float> d_delta;        // delta-based PageRank: pending delta per vertex
     DevBuf<double> d_psum;        // ... and per partition
@@ -519,6 +522,9 @@ void release_all(hytm_graph* g) {
     g->d_lacc.release();
     g->d_xout.release();
     g->d_cur2.release();
+    g->d_far.release();
+    g->d_farmin.release();
+    g->h_farmin.release();
     g->d_zcl.release();
     g->d_delta.release();
     g->d_psum.release();
@@ -839,6 +845,8 @@ void init_ctx(RunCtx& rc, hytm_graph* g, int algo, bool batched, const Plan& pl,
     rc.as.n = g->n;
     rc.as.overflow = g->d_overflow.p;
     rc.as.pk = g->pk;
+    rc.as.far = nullptr;
+    rc.as.bound = 0xFFFFFFFFu;  // no far set unless a single-source SSSP run asks for one
 }
 
 // One engine pass over the frontier `cur` (Algorithm 1 plus the engines of Sec. 6.2),
@@ -1533,6 +1541,30 @@ void copy_lanes_out(hytm_graph* g, const uint32_t* vals, uint32_t lshift, const 
 // holds n values, iterations_out one count.  lanes in 1..64: batched BFS/SSSP/PPR from
 // sources[0..lanes), values_out holds lanes rows of n values, iterations_out one count per
 // lane (the non-empty frontiers of that lane; PPR: its steps).
+// SSSP with sssp_delta, once the frontier is empty: the bound rises to the smallest multiple
+// of sssp_delta above the smallest distance waiting in the far set, and the far vertices
+// below it become the frontier.  *more = false when nothing waits (the run is over).
+hytm_status far_advance(RunCtx& rc, hipStream_t main, bool* more) {
+    hytm_graph* g = rc.g;
+    KTimer& kt = g->timer;
+    HIP_CHECK(launch_fill_u32(g->d_farmin.p, 1, 0xFFFFFFFFu, main));
+    HIP_CHECK(kt.run(HYTM_K_OTHER, rc.nwords, main, [&] {
+        return launch_far_min(g->d_far.p, g->d_val.p, rc.nwords, g->d_farmin.p, main);
+    }));
+    HIP_CHECK(hipMemcpyAsync(g->h_farmin.p, g->d_farmin.p, sizeof(uint32_t), hipMemcpyDeviceToHost, main));
+    HIP_CHECK(hipStreamSynchronize(main));
+    rc.tot.d2h += sizeof(uint32_t);
+    const uint32_t lo = *g->h_farmin.p;
+    *more = lo != 0xFFFFFFFFu;
+    if (!*more) return HYTM_OK;
+    const uint64_t delta = g->params.sssp_delta;
+    rc.as.bound = (uint32_t)std::min<uint64_t>((lo / delta + 1) * delta, 0xFFFFFFFFull);
+    HIP_CHECK(kt.run(HYTM_K_OTHER, rc.nwords, main, [&] {
+        return launch_far_move(g->d_far.p, g->d_val.p, rc.cur, rc.nwords, rc.as.bound, main);
+    }));
+    return HYTM_OK;
+}
+
 hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uint32_t lanes, void* values_out,
                      uint32_t* iterations_out, hytm_run_stats* stats, void* hip_stream) {
     HIP_CHECK(hipSetDevice(g->device));
@@ -1580,6 +1612,13 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         g->h_sched.ensure(g->npart);
     }
     if (rc.reprocess) g->d_cur2.ensure(nwords);
+    const bool near_far = algo == HYTM_SSSP && !batched && g->params.sssp_delta > 0;
+    if (near_far) {
+        g->d_far.ensure(nwords);
+        g->d_farmin.ensure(1);
+        g->h_farmin.ensure(1);
+        HIP_CHECK(launch_fill_u32(g->d_far.p, nwords, 0u, main));
+    }
     if (batched) {
         g->d_mcur.ensure(n);
         g->d_mnext.ensure(n);
@@ -1603,6 +1642,10 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     as.acc = g->d_acc.p;
     as.contrib = g->d_contrib.p;
     as.inv_n = g->d_inv_n.p;  // null unless the graph is a union of graphs
+    if (near_far) {
+        as.far = g->d_far.p;
+        as.bound = g->params.sssp_delta;  // the source's distance 0 lies below it
+    }
     rc.cur = g->d_cur.p;
     rc.nxt = g->d_next.p;
     if (batched) {
@@ -1645,6 +1688,11 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         bool empty = false;
         hytm_status st = step_once(rc, main, &active, &empty);
         if (st != HYTM_OK) return st;
+        if (empty && near_far) {
+            bool more = false;
+            if ((st = far_advance(rc, main, &more)) != HYTM_OK) return st;
+            if (more) continue;
+        }
         if (empty) break;
         for (uint32_t l = 0; l < lanes; l++) lane_iters[l] += (uint32_t)((active >> l) & 1);
     }
@@ -2067,6 +2115,7 @@ void hytm_default_params(hytm_params* p) {
     p->zc_tie = 0;
     p->pr_blocking = 1;
     p->pr_block_pairs = 0;
+    p->sssp_delta = 0;
     p->streams = 4;
     p->gather_threads = 0;
     p->compact_chunk_edges = 0;
