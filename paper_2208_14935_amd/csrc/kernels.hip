@@ -155,6 +155,21 @@ __global__ __launch_bounds__(256) void k_stats_select(uint32_t npart, const uint
     for (uint32_t i = blockIdx.x; i < npart; i += gridDim.x) {
         const uint32_t vb = pv[i], ve = pv[i + 1];
         const uint32_t wb = vb >> 5, we = (ve + 31) >> 5;
+        // a partition without active vertices (most of them while the frontier is small)
+        // costs one barrier instead of the reductions below
+        uint32_t any = 0;
+        for (uint32_t wi = wb + threadIdx.x; wi < we; wi += blockDim.x) any |= masked_word(cur, wi, vb, ve);
+        if (!__syncthreads_or(any != 0)) {
+            if (threadIdx.x == 0) {
+                mode[i] = P_NONE;
+                nA[i] = 0;
+                nF[i] = 0;
+                Ea[i] = 0;
+                Rq[i] = 0;
+                K[i] = 0;
+            }
+            continue;
+        }
         uint64_t c = 0, f = 0, ea = 0, rq = 0, kl = 0, rqd = 0;
         // distinct lines: (line + 1) of the last list before the current 256 words, 0 = none
         uint64_t carry = 0;
