@@ -110,7 +110,7 @@ def main():
                          "measured gather rate) or num/den")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the engine runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU sharding is a design only)", file=sys.stderr)
         sys.exit(2)
     algos = args.algos.split(",")

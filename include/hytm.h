@@ -49,7 +49,7 @@ typedef enum {
     HYTM_E_BUDGET = 4,      /* a forced FILTER/COMPACT run whose staging does not fit the budget */
     HYTM_E_DEVICE = 5,      /* a HIP runtime error; the message carries hipGetErrorString */
     HYTM_E_STATE = 6,       /* call not valid in the handle's current state */
-    HYTM_E_UNSUPPORTED = 7  /* request this build does not implement */
+    HYTM_E_UNSUPPORTED = 7  /* request the library does not implement */
 } hytm_status;
 
 /* Algorithms (Sec. 7.1).  Outputs are one 4-byte value per vertex:
