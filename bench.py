@@ -414,6 +414,10 @@ def modes_workload(args, gname, g, sym, deg, srcs, algos, gamma, probe, cgather,
     link's achieved GB/s (explicit + zero-copy + resident-fill bytes over run time) against
     the measured pinned-copy peak."""
     s = int(srcs[0])
+    # results land in pinned buffers, as in the other workloads (a pageable one makes the
+    # final copy of n values go through staging: ~90 ms more at RMAT-28)
+    n_max = max(g.n, len(sym[0]) - 1 if sym[0] is not None else 0)
+    outs = {np.uint32: hy.pinned_empty(n_max, np.uint32), np.float32: hy.pinned_empty(n_max, np.float32)}
     lv = g.run("bfs", s).values  # reach of the source, outside the timed runs
     reach = int(deg[lv != hy.UNREACHED].sum())
     m_directed, m_sym = int(g.m), (len(sym[1]) if sym[1] is not None else 0)
@@ -433,9 +437,10 @@ def modes_workload(args, gname, g, sym, deg, srcs, algos, gamma, probe, cgather,
             arrays = h.edge_arrays(a)
             h.set_params(mode=mode)
             h.set_budget(int(args.budget_bytes) if args.budget_bytes else int(args.budget_frac * 4 * arrays * h.m))
+            out = outs[np.float32 if a == "pagerank" else np.uint32][: h.n]
             try:
-                h.run(a, s)  # warm-up: staging buffers and the resident prefix of this plan
-                r = h.run(a, s, stats=True)
+                h.run(a, s, out=out)  # warm-up: staging buffers and the resident prefix of this plan
+                r = h.run(a, s, stats=True, out=out)
             except hy.HytmError as e:  # a forced engine whose staging does not fit
                 table[f"{mode}/{a}"] = {"error": str(e)}
                 log(f"{mode:9s} {a:9s} {e}")
