@@ -14,6 +14,8 @@ from __future__ import annotations
 
 import time
 
+import numpy as np
+
 DEFAULT_GRID = {
     "partition_edges": [8192, 16384, 32768, 65536, 131072, 262144],
     "combine_k": [1, 4, 16, 64],
@@ -67,14 +69,18 @@ def autotune(graph, algo: str, source: int = 0, budget_frac: float | None = 0.25
         "gamma": (p.gamma_num, p.gamma_den),
         "filter_engine": "stream" if p.filter_engine == 0 else "copy",
     }
-    arrays = 2 if algo == "sssp" else 1
+    arrays = graph.edge_arrays(algo)  # SSSP reads one array when its weights are packed
 
     def timed(g, a, s):
-        g.run(a, s)  # warm caches and allocations
+        # results into a pinned buffer: a pageable one adds the same staged copy to every
+        # candidate and blurs their differences
+        from . import ALGOS, FLOAT_ALGOS, pinned_empty
+        out = pinned_empty(max(g.n, 1), np.float32 if ALGOS[a] in FLOAT_ALGOS else np.uint32)[: g.n]
+        g.run(a, s, out=out)  # warm caches and allocations
         t = float("inf")
         for _ in range(repeats):
             t0 = time.perf_counter()
-            g.run(a, s)
+            g.run(a, s, out=out)
             t = min(t, time.perf_counter() - t0)
         return t
 
