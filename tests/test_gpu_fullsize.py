@@ -79,8 +79,15 @@ def test_sssp_fullsize_certificate(big, setting):
     s = int(srcs[0])
     note(f"sssp from {s}, {setting} cost model")
     r = g.run("sssp", s)
-    dist = r.values
     lvl, it_bfs = cached(("bfs", s), lambda: oracle.bfs(off, col, s))
+    sssp_certificate(off, col, w, r.values, s, lvl)
+    assert r.iterations >= it_bfs
+
+
+def sssp_certificate(off, col, w, dist, s, lvl):
+    """Distance 0 at the source, reachability equal to BFS's, no edge can still relax and
+    every reached vertex but the source has a tight in-edge: together they fix the unique
+    shortest distances (weights >= 1)."""
     n = len(off) - 1
     assert dist[s] == 0
     assert ((dist != hy.UNREACHED) == (lvl != hy.UNREACHED)).all()
@@ -96,7 +103,30 @@ def test_sssp_fullsize_certificate(big, setting):
     need = dist != hy.UNREACHED
     need[s] = False
     assert has_parent[need].all()
-    assert r.iterations >= it_bfs
+
+
+def test_batched_fullsize_lanes(big):
+    """64 BFS and 64 SSSP sources in one traversal each, as the batch benchmark runs them
+    (bench cost-model settings, 25% budget): sampled lanes against the oracle (BFS element by
+    element, SSSP by its certificate)."""
+    off, col, w, srcs, g = big
+    budget(g, 1, "bench")
+    lanes = gen.sources(off, 64, 3000 + SCALE)
+    check = [0, 1, 63]
+    note("batched bfs, 64 sources")
+    vals, its, _ = g.run_batch("bfs", lanes)
+    for i in check:
+        s = int(lanes[i])
+        want, it = cached(("bfs", s), lambda: oracle.bfs(off, col, s))
+        np.testing.assert_array_equal(vals[i], want, err_msg=f"bfs lane {i} source {s}")
+        assert its[i] == it
+    note("batched sssp, 64 sources")
+    vals, its, _ = g.run_batch("sssp", lanes)
+    for i in (0, 63):
+        s = int(lanes[i])
+        lvl, it_bfs = cached(("bfs", s), lambda: oracle.bfs(off, col, s))
+        sssp_certificate(off, col, w, vals[i], s, lvl)
+        assert its[i] >= it_bfs
 
 
 def test_cc_fullsize_exact():
