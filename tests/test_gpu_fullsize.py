@@ -129,6 +129,34 @@ def test_batched_fullsize_lanes(big):
         assert its[i] >= it_bfs
 
 
+def test_server_fullsize_queries(big):
+    """The query server as the serving benchmark runs it (64 lanes per group, budget planned
+    for SSSP's edge words at 25%, bench cost-model settings): BFS queries exact against the
+    oracle, SSSP queries by the certificate, a PPR query within 1e-6 of the FP64 oracle."""
+    off, col, w, srcs, g = big
+    budget(g, g.edge_arrays("sssp"), "bench")
+    queries = [("bfs", int(srcs[0])), ("sssp", int(srcs[0])), ("ppr", int(srcs[0])), ("bfs", int(srcs[1])),
+               ("sssp", int(srcs[1]))]
+    note("server, 5 queries")
+    with hy.Server(g, bfs=64, sssp=64, ppr=64) as srv:
+        subs = [srv.submit(a, s) for a, s in queries]
+        done = [srv.wait(q) for q in subs]
+    for q in done:
+        assert q.result["status"] == hy.OK
+        lvl, it = cached(("bfs", q.source), lambda: oracle.bfs(off, col, q.source))
+        if q.algo == "bfs":
+            np.testing.assert_array_equal(q.values, lvl)
+            assert q.result["iterations"] == it
+        elif q.algo == "sssp":
+            sssp_certificate(off, col, w, q.values, q.source, lvl)
+            assert q.result["iterations"] >= it
+        else:
+            want = oracle.ppr(off, col, q.source, 0.85, 10)
+            err = float(np.abs(q.values.astype(np.float64) - want).max())
+            assert err <= 1e-6, err
+            assert q.result["iterations"] == 10
+
+
 def test_cc_fullsize_exact():
     off, col = gen.rmat(SCALE, 16, seed=SCALE)
     soff, scol = gen.symmetrize(off, col)
