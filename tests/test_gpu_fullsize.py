@@ -132,7 +132,13 @@ def test_batched_fullsize_lanes(big):
 def test_server_fullsize_queries(big):
     """The query server as the serving benchmark runs it (64 lanes per group, budget planned
     for SSSP's edge words at 25%, bench cost-model settings): BFS queries exact against the
-    oracle, SSSP queries by the certificate, a PPR query within 1e-6 of the FP64 oracle."""
+    oracle, SSSP queries by the certificate, a PPR query against the FP64 oracle.
+
+    PPR keeps its mass near the source, so values reach ~3e-2 and each is an FP32 sum of up to
+    ~2.4e5 in-contributions per step, added by atomics in no fixed order: the typical relative
+    error of such a sum is ~sqrt(k) * 2^-24 (3e-5 at k = 2.4e5) per step, and the steps compound
+    it through the in-neighbours' own values (~3e-4 over 10 steps; 1.8e-4 was seen at a vertex
+    of in-degree 11180).  The bound is 1e-6 absolute plus 1e-3 of the oracle's value."""
     off, col, w, srcs, g = big
     budget(g, g.edge_arrays("sssp"), "bench")
     queries = [("bfs", int(srcs[0])), ("sssp", int(srcs[0])), ("ppr", int(srcs[0])), ("bfs", int(srcs[1])),
@@ -152,8 +158,8 @@ def test_server_fullsize_queries(big):
             assert q.result["iterations"] >= it
         else:
             want = oracle.ppr(off, col, q.source, 0.85, 10)
-            err = float(np.abs(q.values.astype(np.float64) - want).max())
-            assert err <= 1e-6, err
+            excess = np.abs(q.values.astype(np.float64) - want) - (1e-6 + 1e-3 * want)
+            assert excess.max() <= 0, (float(excess.max()), int(excess.argmax()))
             assert q.result["iterations"] == 10
 
 
