@@ -32,8 +32,8 @@ HBM_PEAK_GBPS = 8000.0
 # known size), mean per launch of the timed step.  It holds only for the kernel source and
 # workload it was measured on; otherwise the roofline reports traffic null.
 PMC_TRAFFIC = {"kernel": "push_zerocopy", "workload": "rmat24-ef16-budget0.25-hybrid-rqdistinct-zctie",
-               "kernels_sha256": "a2287f71a6fe6d2ae06e77bd4368a2b4776bccfc58c21463fccd9ef00cc6c9b8",
-               "bytes_per_launch": (2 * 1423700 + 661342) * 1024.0,
+               "kernels_sha256": "2696a4f85b450697caa1b3210bdea42cdccba76aaafa555b67f283c18f59d58a",
+               "bytes_per_launch": (2 * 1424311 + 661331) * 1024.0,
                "summary": "profiles/pmc_traffic_rmat24_budget25_hybrid.md"}
 PCIE_GEN5_X16_GBPS = 63.0
 

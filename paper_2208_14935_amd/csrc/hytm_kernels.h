@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 namespace hytm {
@@ -238,9 +239,15 @@ hipError_t launch_ppr_prepare(const AlgoState& s, const uint64_t* off, hipStream
 hipError_t launch_ppr_apply(const AlgoState& s, float damping, hipStream_t st);
 hipError_t launch_ppr_restart(const AlgoState& s, const LaneSet& set, float restart, hipStream_t st);
 
+// Scan of the selection: scratch holds scan_scratch_words(npart) uint64 (tile totals and bases).
+constexpr int SCAN_THREADS = 512;
+constexpr int SCAN_PER = 8;                                        // partitions per thread
+constexpr uint32_t SCAN_TILE = (uint32_t)SCAN_THREADS * SCAN_PER;  // partitions per workgroup
+inline uint32_t scan_tiles(uint32_t npart) { return (npart + SCAN_TILE - 1) / SCAN_TILE; }
+inline uint64_t scan_scratch_words(uint32_t npart) { return (uint64_t)std::max(scan_tiles(npart), 1u) * (7 * NSEG + 1); }
 hipError_t launch_scan(uint32_t npart, const uint8_t* mode, const uint32_t* nA, const uint32_t* nF,
                        const uint64_t* Ea, const uint64_t* Rq, const uint64_t* K, uint32_t* lbase, uint64_t* wbase,
-                       Header* hdr, uint64_t* wpre, hipStream_t st);
+                       Header* hdr, uint64_t* wpre, uint64_t* scratch, hipStream_t st);
 
 hipError_t launch_build_lists(uint32_t npart, const uint32_t* pv, const uint64_t* off, const uint32_t* cur,
                               const uint8_t* mode, const uint32_t* lbase, const uint64_t* wbase, uint32_t* list,

@@ -250,45 +250,120 @@ __global__ void k_select_only(uint64_t npart, const uint64_t* __restrict__ E, co
 }
 
 // -------------------------------------------------------------------- scan
-constexpr int SCAN_THREADS = 512;  // 2 waves per SIMD: room for the 21 running sums per thread
+// The engine segments' list and work offsets and the selection header, in three launches:
+// per tile of SCAN_TILE partitions the totals of every value (one workgroup per tile), then
+// the segment starts and each tile's bases from the tile totals (one small workgroup), then
+// per tile the offsets of each partition (one workgroup per tile).  Every thread takes a
+// contiguous run of SCAN_PER partitions, so a workgroup needs one barrier per pass.
+constexpr int SCAN_NV = 5 * NSEG + 1;  // cnt[4], work[4], parts[4], edges[4], lines[4], frontier
+constexpr int SCAN_NB = 2 * NSEG;      // scanned per segment: list entries, work items
+constexpr int SCAN_NW = SCAN_THREADS / 64;
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan(uint32_t npart, const uint8_t* __restrict__ mode,
-                                               const uint32_t* __restrict__ nA, const uint32_t* __restrict__ nF,
-                                               const uint64_t* __restrict__ Ea, const uint64_t* __restrict__ Rq,
-                                               const uint64_t* __restrict__ K, uint32_t* __restrict__ lbase,
-                                               uint64_t* __restrict__ wbase, Header* __restrict__ hdr,
-                                               uint64_t* __restrict__ wpre) {
-    // per thread: a contiguous run of partitions; per segment the list entries (nA) and work
-    // items to scan, and the partitions, edges and cost lines to total, plus the frontier
-    constexpr int NV = 5 * NSEG + 1;  // cnt[4], work[4], parts[4], edges[4], lines[4], frontier
-    constexpr int NW = SCAN_THREADS / 64;
-    __shared__ uint64_t s_tot[NW][NV];
-    const uint32_t per = (npart + SCAN_THREADS - 1) / SCAN_THREADS;
-    const uint32_t i0 = min(threadIdx.x * per, npart), i1 = min(i0 + per, npart);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint64_t val[NV];
+// The values of partitions [i0, i1) summed into val[0, NV).
+template <int NV>
+__device__ __forceinline__ void scan_run_sums(uint32_t i0, uint32_t i1, const uint8_t* __restrict__ mode,
+                                              const uint32_t* __restrict__ nA, const uint32_t* __restrict__ nF,
+                                              const uint64_t* __restrict__ Ea, const uint64_t* __restrict__ Rq,
+                                              const uint64_t* __restrict__ K, uint64_t (&val)[NV]) {
 #pragma unroll
     for (int k = 0; k < NV; k++) val[k] = 0;
     for (uint32_t i = i0; i < i1; i++) {
-        val[NV - 1] += nF[i];
+        if (NV == SCAN_NV) val[SCAN_NV - 1] += nF[i];
         const uint8_t m = mode[i];
         if (m == P_NONE) continue;
-        const uint64_t ea = Ea[i], w = (m == P_ZC) ? K[i] : ea, na = nA[i], rq = Rq[i];
+        const uint64_t ea = Ea[i], w = (m == P_ZC) ? K[i] : ea, na = nA[i];
 #pragma unroll
         for (int sg = 0; sg < NSEG; sg++) {
             if (m != sg + 1) continue;
             val[sg] += na;
             val[NSEG + sg] += w;
-            val[2 * NSEG + sg] += 1;
-            val[3 * NSEG + sg] += ea;
-            val[4 * NSEG + sg] += rq;
+            if (NV == SCAN_NV) {
+                val[2 * NSEG + sg] += 1;
+                val[3 * NSEG + sg] += ea;
+                val[4 * NSEG + sg] += Rq[i];
+            }
         }
     }
-    // wave scans for the scanned values (kept as wave-exclusive prefixes), wave sums for
-    // the rest; the per-wave totals go to LDS
-    uint64_t ex[2 * NSEG];
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tot(uint32_t npart, const uint8_t* __restrict__ mode,
+                                                   const uint32_t* __restrict__ nA, const uint32_t* __restrict__ nF,
+                                                   const uint64_t* __restrict__ Ea, const uint64_t* __restrict__ Rq,
+                                                   const uint64_t* __restrict__ K, uint64_t* __restrict__ tile_tot) {
+    __shared__ uint64_t s_tot[SCAN_NW][SCAN_NV];
+    const uint32_t i0 = min(blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_PER, npart), i1 = min(i0 + SCAN_PER, npart);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t val[SCAN_NV];
+    scan_run_sums<SCAN_NV>(i0, i1, mode, nA, nF, Ea, Rq, K, val);
 #pragma unroll
-    for (int k = 0; k < 2 * NSEG; k++) {
+    for (int k = 0; k < SCAN_NV; k++) {
+        const uint64_t v = wave_sum(val[k]);
+        if (lane == 0) s_tot[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < SCAN_NV) {
+        uint64_t t = 0;
+        for (int w = 0; w < SCAN_NW; w++) t += s_tot[w][threadIdx.x];
+        tile_tot[(uint64_t)blockIdx.x * SCAN_NV + threadIdx.x] = t;
+    }
+}
+
+// One workgroup of 64 threads: grand totals, segment starts (segments lie one after another:
+// RESIDENT, FILTER, ZEROCOPY, COMPACT), each tile's bases, the header, and the work prefix's
+// closing entry.
+__global__ __launch_bounds__(64) void k_scan_base(uint32_t ntiles, const uint64_t* __restrict__ tile_tot,
+                                                  uint64_t* __restrict__ tile_base, Header* __restrict__ hdr,
+                                                  uint64_t* __restrict__ wpre) {
+    __shared__ uint64_t s_g[SCAN_NV];
+    const uint32_t k = threadIdx.x;
+    if (k < SCAN_NV) {
+        uint64_t t = 0;
+        for (uint32_t i = 0; i < ntiles; i++) t += tile_tot[(uint64_t)i * SCAN_NV + k];
+        s_g[k] = t;
+    }
+    __syncthreads();
+    if (k < SCAN_NB) {
+        const uint32_t sg = k % NSEG, first = k - sg;  // first: 0 (list entries) or NSEG (work)
+        uint64_t run = 0;
+        for (uint32_t s2 = 0; s2 < sg; s2++) run += s_g[first + s2];
+        for (uint32_t i = 0; i < ntiles; i++) {
+            tile_base[(uint64_t)i * SCAN_NB + k] = run;
+            run += tile_tot[(uint64_t)i * SCAN_NV + k];
+        }
+    }
+    if (k == 0) {
+        uint64_t la = 0, wa = 0;
+#pragma unroll
+        for (int sg = 0; sg < NSEG; sg++) {
+            hdr->seg_parts[sg] = (uint32_t)s_g[2 * NSEG + sg];
+            hdr->seg_list_start[sg] = (uint32_t)la;
+            hdr->seg_list_count[sg] = (uint32_t)s_g[sg];
+            hdr->seg_work_start[sg] = wa;
+            hdr->seg_work_total[sg] = s_g[NSEG + sg];
+            hdr->seg_edges[sg] = s_g[3 * NSEG + sg];
+            hdr->seg_cost_lines[sg] = s_g[4 * NSEG + sg];
+            la += s_g[sg];
+            wa += s_g[NSEG + sg];
+        }
+        hdr->total_active = la;
+        hdr->frontier = s_g[SCAN_NV - 1];
+        wpre[la] = wa;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_write(uint32_t npart, const uint8_t* __restrict__ mode,
+                                                     const uint32_t* __restrict__ nA, const uint64_t* __restrict__ Ea,
+                                                     const uint64_t* __restrict__ K,
+                                                     const uint64_t* __restrict__ tile_base,
+                                                     uint32_t* __restrict__ lbase, uint64_t* __restrict__ wbase) {
+    __shared__ uint64_t s_tot[SCAN_NW][SCAN_NB];
+    const uint32_t i0 = min(blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_PER, npart), i1 = min(i0 + SCAN_PER, npart);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t val[SCAN_NB];
+    scan_run_sums<SCAN_NB>(i0, i1, mode, nA, nullptr, Ea, nullptr, K, val);
+    uint64_t ex[SCAN_NB];
+#pragma unroll
+    for (int k = 0; k < SCAN_NB; k++) {
         uint64_t v = val[k];
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -298,31 +373,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(uint32_t npart, const uin
         ex[k] = v - val[k];
         if (lane == 63) s_tot[wid][k] = v;
     }
-#pragma unroll
-    for (int k = 2 * NSEG; k < NV; k++) {
-        const uint64_t v = wave_sum(val[k]);
-        if (lane == 0) s_tot[wid][k] = v;
-    }
     __syncthreads();
-    // segments lie one after another: RESIDENT, FILTER, ZEROCOPY, COMPACT
-    uint64_t lstart[NSEG], wstart[NSEG], runc[NSEG], runw[NSEG];
-    uint64_t la = 0, wa = 0;
+    uint64_t run[SCAN_NB];
 #pragma unroll
-    for (int sg = 0; sg < NSEG; sg++) {
-        uint64_t bc = 0, tc = 0, bw = 0, tw = 0;
-        for (int w = 0; w < NW; w++) {
-            const uint64_t xc = s_tot[w][sg], xw = s_tot[w][NSEG + sg];
-            bc += w < wid ? xc : 0;
-            bw += w < wid ? xw : 0;
-            tc += xc;
-            tw += xw;
-        }
-        lstart[sg] = la;
-        wstart[sg] = wa;
-        runc[sg] = la + bc + ex[sg];
-        runw[sg] = wa + bw + ex[NSEG + sg];
-        la += tc;
-        wa += tw;
+    for (int k = 0; k < SCAN_NB; k++) {
+        uint64_t before = 0;
+        for (int w = 0; w < wid; w++) before += s_tot[w][k];
+        run[k] = tile_base[(uint64_t)blockIdx.x * SCAN_NB + k] + before + ex[k];
     }
     for (uint32_t i = i0; i < i1; i++) {
         const uint8_t m = mode[i];
@@ -331,34 +388,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(uint32_t npart, const uin
 #pragma unroll
         for (int sg = 0; sg < NSEG; sg++) {
             if (m != sg + 1) continue;
-            lb = (uint32_t)runc[sg];
-            wb = runw[sg];
-            runc[sg] += nA[i];
-            runw[sg] += (m == P_ZC) ? K[i] : Ea[i];
+            lb = (uint32_t)run[sg];
+            wb = run[NSEG + sg];
+            run[sg] += nA[i];
+            run[NSEG + sg] += (m == P_ZC) ? K[i] : Ea[i];
         }
         lbase[i] = lb;
         wbase[i] = wb;
-    }
-    if (threadIdx.x == 0) {
-        uint64_t tot[NV];
-#pragma unroll
-        for (int k = 0; k < NV; k++) {
-            tot[k] = 0;
-            for (int w = 0; w < NW; w++) tot[k] += s_tot[w][k];
-        }
-#pragma unroll
-        for (int sg = 0; sg < NSEG; sg++) {
-            hdr->seg_parts[sg] = (uint32_t)tot[2 * NSEG + sg];
-            hdr->seg_list_start[sg] = (uint32_t)lstart[sg];
-            hdr->seg_list_count[sg] = (uint32_t)tot[sg];
-            hdr->seg_work_start[sg] = wstart[sg];
-            hdr->seg_work_total[sg] = tot[NSEG + sg];
-            hdr->seg_edges[sg] = tot[3 * NSEG + sg];
-            hdr->seg_cost_lines[sg] = tot[4 * NSEG + sg];
-        }
-        hdr->total_active = la;
-        hdr->frontier = tot[NV - 1];
-        wpre[la] = wa;
     }
 }
 
@@ -2031,8 +2067,13 @@ hipError_t launch_stats_select(uint32_t npart, const uint32_t* pv, const uint64_
 
 hipError_t launch_scan(uint32_t npart, const uint8_t* mode, const uint32_t* nA, const uint32_t* nF,
                        const uint64_t* Ea, const uint64_t* Rq, const uint64_t* K, uint32_t* lbase, uint64_t* wbase,
-                       Header* hdr, uint64_t* wpre, hipStream_t st) {
-    k_scan<<<1, SCAN_THREADS, 0, st>>>(npart, mode, nA, nF, Ea, Rq, K, lbase, wbase, hdr, wpre);
+                       Header* hdr, uint64_t* wpre, uint64_t* scratch, hipStream_t st) {
+    const uint32_t ntiles = scan_tiles(npart);
+    uint64_t* tile_tot = scratch;
+    uint64_t* tile_base = scratch + (uint64_t)ntiles * SCAN_NV;
+    if (ntiles) k_scan_tot<<<ntiles, SCAN_THREADS, 0, st>>>(npart, mode, nA, nF, Ea, Rq, K, tile_tot);
+    k_scan_base<<<1, 64, 0, st>>>(ntiles, tile_tot, tile_base, hdr, wpre);
+    if (ntiles) k_scan_write<<<ntiles, SCAN_THREADS, 0, st>>>(npart, mode, nA, Ea, K, tile_base, lbase, wbase);
     return hipGetLastError();
 }
 

@@ -229,6 +229,7 @@ struct hytm_graph {
     DevBuf<float> d_lx, d_lacc;   // batched PPR: x and accumulator rows
     DevBuf<uint32_t> d_xout;      // lanes extracted for the copy back
     DevBuf<uint32_t> d_cur2;      // frontier of the reprocessing pass
+    DevBuf<uint64_t> d_scan;      // selection scan: per-tile totals and bases
     DevBuf<uint32_t> d_far;       // SSSP with sssp_delta: improved vertices waiting for a higher bound
     DevBuf<uint32_t> d_farmin;    // smallest waiting distance
     HostBuf<uint32_t> h_farmin;
@@ -523,6 +524,7 @@ void release_all(hytm_graph* g) {
     g->d_xout.release();
     g->d_cur2.release();
     g->d_far.release();
+    g->d_scan.release();
     g->d_farmin.release();
     g->h_farmin.release();
     g->d_zcl.release();
@@ -870,9 +872,10 @@ hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Heade
         return launch_stats_select(npart, g->d_pv.p, g->d_off.p, cur, rc.sp, g->d_mode.p, g->d_nA.p, g->d_nF.p,
                                    g->d_Ea.p, g->d_Rq.p, g->d_K.p, main);
     }));
+    g->d_scan.ensure(scan_scratch_words(npart));
     HIP_CHECK(kt.run(HYTM_K_SCAN, npart, main, [&] {
         return launch_scan(npart, g->d_mode.p, g->d_nA.p, g->d_nF.p, g->d_Ea.p, g->d_Rq.p, g->d_K.p, g->d_lbase.p,
-                           g->d_wbase.p, g->d_hdr.p, g->d_wpre.p, main);
+                           g->d_wbase.p, g->d_hdr.p, g->d_wpre.p, g->d_scan.p, main);
     }));
     HIP_CHECK(kt.run(HYTM_K_LISTS, npart, main, [&] {
         return launch_build_lists(npart, g->d_pv.p, g->d_off.p, cur, g->d_mode.p, g->d_lbase.p, g->d_wbase.p,
