@@ -240,6 +240,9 @@ static void write_rows_fn(void *ctx, uint64_t lo, uint64_t hi, int tid) {
     (void)tid;
     bctx *c = (bctx *)ctx;
     for (uint64_t b = lo; b < hi; b++) {
+        /* buckets cover 2^vbits >= n ids: those starting at or past n hold no keys, and
+           their first id would index past off[n] */
+        if (!c->bkept[b]) continue;
         const uint64_t *k = c->keys + c->bstart[b];
         uint32_t *out = c->col + c->off[b << c->shift];
         for (uint64_t i = 0; i < c->bkept[b]; i++) out[i] = (uint32_t)k[i];
