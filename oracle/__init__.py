@@ -68,6 +68,7 @@ def _load():
     sig = {
         "orc_bfs": (u32, [u64, vp, vp, u32, vp]),
         "orc_sssp": (i32, [u64, vp, vp, vp, u32, vp]),
+        "orc_sssp_check": (i32, [u64, vp, vp, vp, u32, vp, vp]),
         "orc_sync_rounds": (u32, [u64, vp, vp, vp, i32, u32]),
         "orc_cc": (u64, [u64, vp, vp, vp]),
         "orc_pagerank": (None, [u64, vp, vp, dbl, u32, vp]),
@@ -117,6 +118,19 @@ def sssp(off, col, w, source: int):
     if _load().orc_sssp(n, _p(off), _p(col), _p(w), int(source), _p(dist)):
         raise OverflowError("shortest distance does not fit below 2^32-1")
     return dist
+
+
+def sssp_check(off, col, w, source: int, dist) -> tuple[int, int]:
+    """Shortest-path certificate of `dist` (see orc_sssp_check): (0, 0) when it holds, else
+    (condition 1/2/3, vertex)."""
+    off, col, n = _csr(off, col)
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    dist = np.ascontiguousarray(dist, dtype=np.uint32)
+    if len(dist) != n or len(w) != len(col):
+        raise ValueError("dist must have n entries and w one per edge")
+    bad = ctypes.c_uint64(0)
+    code = _load().orc_sssp_check(n, _p(off), _p(col), _p(w), int(source), _p(dist), ctypes.byref(bad))
+    return int(code), int(bad.value)
 
 
 def sync_rounds(off, col, w=None, kind: str = "sssp", source: int = 0) -> int:

@@ -16,6 +16,8 @@
  *                   BFS listed among the algorithms of Sec. 7.1).
  *  - orc_sssp     : Dijkstra with a binary heap and 64-bit sums (Sec. 2.1, Fig. 1's
  *                   SSSP example; Sec. 7.1).
+ *  - orc_sssp_check : the complete shortest-path certificate of a proposed answer, for
+ *                   graphs too large to run Dijkstra on in a test.
  *  - orc_sync_rounds : synchronous Bellman-Ford / label-propagation round count, used
  *                   only as the upper bound of an asynchronous run's iteration count.
  *  - orc_cc       : union-find (union by size, path halving), label = min vertex id
@@ -148,6 +150,48 @@ int orc_sssp(uint64_t n, const uint64_t *off, const uint32_t *col, const uint32_
     free(done);
     free(h);
     return overflow;
+}
+
+/* Shortest-path certificate for weights >= 1, one pass over the edges (Sec. 2.1, Fig. 1:
+   the distances SSSP converges to).  dist is a proposed answer: UNREACHED or a value below
+   it per vertex.  It holds exactly when
+     (a) dist[source] = 0;
+     (b) no edge (u, v) with u reached offers v less: dist[u] + w >= dist[v], where an
+         unreached v counts as 2^32-1 (a sum that fits must have reached it);
+     (c) every reached v other than the source has a tight in-edge, dist[u] + w = dist[v]
+         with u reached.
+   (b) bounds every distance from below by the true one along any path; (c) with positive
+   weights gives each reached vertex a path of exactly its distance.  Returns 0 when all
+   hold, else the violated condition (1, 2, 3) with *bad set to the vertex concerned. */
+int orc_sssp_check(uint64_t n, const uint64_t *off, const uint32_t *col, const uint32_t *w, uint32_t source,
+                   const uint32_t *dist, uint64_t *bad) {
+    if (dist[source] != 0) {
+        *bad = source;
+        return 1;
+    }
+    unsigned char *tight = (unsigned char *)calloc(n ? n : 1, 1);
+    for (uint64_t u = 0; u < n; u++) {
+        if (dist[u] == UNREACHED) continue;
+        for (uint64_t e = off[u]; e < off[u + 1]; e++) {
+            uint32_t v = col[e];
+            uint64_t sum = (uint64_t)dist[u] + w[e];
+            if (sum < dist[v]) {
+                *bad = v;
+                free(tight);
+                return 2;
+            }
+            if (sum == dist[v]) tight[v] = 1;
+        }
+    }
+    for (uint64_t v = 0; v < n; v++) {
+        if (v != source && dist[v] != UNREACHED && !tight[v]) {
+            *bad = v;
+            free(tight);
+            return 3;
+        }
+    }
+    free(tight);
+    return 0;
 }
 
 /* Rounds of a fully synchronous push iteration until nothing changes, counting the

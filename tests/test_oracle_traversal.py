@@ -178,6 +178,41 @@ def test_sssp_rmat16_certificate_scipy_and_unit_weights():
     np.testing.assert_array_equal(oracle.sssp(off, col, np.ones_like(col), 0), lvl)
 
 
+def test_sssp_check_accepts_exactly_the_shortest_distances():
+    """The certificate is complete: on tiny graphs it accepts a proposed answer if and only
+    if it equals Dijkstra's, over every answer with values in 0..6 or unreached."""
+    import itertools
+    rng = np.random.default_rng(5)
+    for _ in range(12):
+        n = 3
+        pairs = [(a, b) for a in range(n) for b in range(n) if a != b and rng.random() < 0.5]
+        off, col = csr_from_edges(n, pairs)
+        w = rng.integers(1, 4, len(col)).astype(np.uint32)
+        want = oracle.sssp(off, col, w, 0)
+        for cand in itertools.product(list(range(7)) + [U], repeat=n):
+            d = np.array(cand, dtype=np.uint32)
+            ok = oracle.sssp_check(off, col, w, 0, d)[0] == 0
+            assert ok == np.array_equal(d, want), (pairs, w, cand)
+
+
+def test_sssp_check_rejects_every_single_change():
+    off, col = gen.rmat(12, 8, seed=12)
+    w = gen.weights(off, col, 1012)
+    for s in (0, 17, 901):
+        dist = oracle.sssp(off, col, w, s)
+        assert oracle.sssp_check(off, col, w, s, dist) == (0, 0)
+        rng = np.random.default_rng(s)
+        for v in rng.integers(0, len(dist), 200):
+            for new in {int(dist[v]) + 1, max(int(dist[v]) - 1, 0), U, 0}:
+                if new == dist[v] or (new == U + 1):
+                    continue
+                bad = dist.copy()
+                bad[v] = new & 0xFFFFFFFF
+                if np.array_equal(bad, dist):
+                    continue
+                assert oracle.sssp_check(off, col, w, s, bad)[0] != 0, (s, v, new)
+
+
 def test_sssp_closed_form_and_overflow():
     n = 20
     off, col = csr_from_edges(n, [(i, i + 1) for i in range(n - 1)])
@@ -189,6 +224,10 @@ def test_sssp_closed_form_and_overflow():
     # 2^32 - 2 is the largest distance that fits
     d = oracle.sssp(off, col, np.array([2**31, 2**31 - 2], dtype=np.uint32), 0)
     assert int(d[2]) == 2**32 - 2
+    # a path whose sum does not fit is no overflow when a shorter one reaches the same vertex
+    off, col = csr_from_edges(5, [(0, 1), (0, 3), (1, 2), (3, 4), (4, 2)])
+    w = np.array([2**31, 1, 2**31, 1, 1], dtype=np.uint32)  # in CSR order of the edges above
+    assert list(oracle.sssp(off, col, w, 0)) == [0, 2**31, 3, 1, 2]
 
 
 def test_sync_rounds_bounds_and_closed_forms():
