@@ -57,7 +57,8 @@ typedef enum {
    of the component; PAGERANK: float rank.  Unreached vertices hold 0xFFFFFFFF.
    PPR: personalized PageRank from a source s, float: the PageRank step with all of the
    restart mass (1 - pr_damping) at s, from x_0 = e_s, ppr_iterations synchronous steps;
-   mass that reaches a vertex without out-edges leaks, as in PAGERANK.
+   mass that reaches a vertex without out-edges leaks, as in PAGERANK.  Values and shares
+   are FP32; each step's sums are accumulated in FP64 and rounded once.
    PAGERANK_DELTA: PageRank to convergence by delta accumulation with delta-driven
    partition priority (Sec. 6.1), float: x = 0 and delta = (1 - d) / n at the start; each
    iteration folds the pushed deltas in, schedules the partitions whose delta sum is at
@@ -216,7 +217,8 @@ typedef struct {
     uint64_t compact_chunks;
     double ms_total;            /* first kernel to values in the caller's buffer */
     double ms_fill;             /* resident-cache fill inside ms_total */
-    double ms_select;           /* stats + selection + active lists + their D2H */
+    double ms_select;           /* device time of stats + selection + active lists + their D2H
+                                   (HIP events around them; excludes waiting for earlier pushes) */
     hytm_iter_stats *iters;     /* caller buffer of iters_cap records, or NULL */
     uint32_t iters_cap;
     uint32_t iters_written;
@@ -342,7 +344,9 @@ hytm_status hytm_graph_info_get(const hytm_graph *g, hytm_graph_info *info);
    info.npart + 1 entries). */
 hytm_status hytm_partition_bounds(const hytm_graph *g, uint64_t *bounds, uint64_t cap);
 
-/* Run one algorithm to convergence (PageRank: pr_iterations synchronous steps).
+/* Run one algorithm to convergence: the push iteration of Sec. 2.1 (Fig. 1), repeated
+   until the frontier is empty, with each iteration's transfers chosen per partition by
+   Sec. 5.1 (PageRank: pr_iterations synchronous steps, Sec. 7.1).
    source     : start vertex for BFS/SSSP (ignored by CC and PageRank); E_RANGE if >= n.
    values_out : host buffer of n 4-byte values (see hytm_algo).
    iterations_out : number of non-empty frontiers processed (NULL ok).
@@ -350,7 +354,8 @@ hytm_status hytm_partition_bounds(const hytm_graph *g, uint64_t *bounds, uint64_
    hip_stream : hipStream_t to order the run after (NULL = the null stream); the call
                 returns only once values_out is written.
    Errors: E_INVAL (SSSP without weights, CC without HYTM_GRAPH_SYMMETRIC), E_RANGE
-   (source, SSSP distance overflow), E_BUDGET, E_NOMEM, E_DEVICE. */
+   (source; SSSP: some shortest distance does not fit below 2^32-1 -- a longer path whose
+   sum would not fit is no error when a shorter one does), E_BUDGET, E_NOMEM, E_DEVICE. */
 hytm_status hytm_run(hytm_graph *g, hytm_algo algo, uint32_t source, void *values_out, uint32_t *iterations_out,
                      hytm_run_stats *stats, void *hip_stream);
 
@@ -364,7 +369,7 @@ hytm_status hytm_run(hytm_graph *g, hytm_algo algo, uint32_t source, void *value
    iterations_out : NULL or nsources counts: the non-empty frontiers of each lane.
    values_out is float for PPR (row l = x from sources[l]).
    Errors as hytm_run; E_INVAL also for CC/PageRank or nsources outside 1..64.  Device
-   memory for the lanes (n x L x 4 bytes of values, twice for PPR, with L the power of two
+   memory for the lanes (n x L x 4 bytes of values, 12 for PPR, with L the power of two
    >= nsources, plus three n x 8-byte masks) is vertex data, outside the edge budget. */
 hytm_status hytm_run_batch(hytm_graph *g, hytm_algo algo, const uint32_t *sources, uint32_t nsources,
                            void *values_out, uint32_t *iterations_out, hytm_run_stats *stats, void *hip_stream);

@@ -87,7 +87,7 @@ struct AlgoState {
     uint32_t* val;        // BFS level / SSSP distance / CC label
     uint32_t* visited;    // BFS: discovered-vertex bitmap
     uint32_t* next;       // next-frontier bitmap
-    uint32_t* overflow;   // SSSP: set when a distance would reach 2^32-1
+    uint32_t* overflow;   // SSSP: lane bits raised when a candidate distance reaches 2^32-1 (it is skipped)
     float* acc;           // PageRank accumulators: ACC_COPIES x acc_slots(n) floats
     const float* contrib; // PageRank x[u] / D_o(u)
     uint32_t level_next;  // BFS: level given to vertices discovered this iteration
@@ -99,7 +99,7 @@ struct AlgoState {
     uint64_t* mvisited;   // BFS: lanes that have reached each vertex
     uint32_t* lval;       // BFS: level (plus the lane's join iteration); SSSP: distance
     float* lx;            // PPR: x of each lane; scaled to x / D_o in place before a push
-    float* lacc;          // PPR: per-lane accumulators, zero between iterations
+    double* lacc;         // PPR: per-lane accumulators (FP64), zero between iterations
     uint32_t lshift;
     const float* inv_n;   // PageRank over a union of graphs: 1 / (vertices of v's graph), else null
     Pack pk;              // how edge words are laid out
@@ -224,6 +224,12 @@ hipError_t launch_cc_relabel(const uint32_t* lab, const uint32_t* order, const u
 hipError_t launch_far_min(const uint32_t* far, const uint32_t* dist, uint32_t nwords, uint32_t* out, hipStream_t st);
 hipError_t launch_far_move(uint32_t* far, const uint32_t* dist, uint32_t* cur, uint32_t nwords, uint32_t bound,
                            hipStream_t st);
+// SSSP overflow after convergence: *out |= the lanes of `mask` for which some edge of the
+// mapped host array col leads from a vertex they reached to one they did not (dist: n rows
+// of 2^lshift lanes; *out zeroed by the caller).  Such a lane's distances do not all fit
+// below 2^32-1.
+hipError_t launch_sssp_ovf_check(const uint64_t* off, const uint32_t* col, const Pack& pk, const uint32_t* dist,
+                                 uint32_t lshift, uint64_t mask, uint64_t n, unsigned long long* out, hipStream_t st);
 // Start the lanes of `set` at their sources (their columns must hold the reset values):
 // BFS level = base, SSSP distance = 0, PPR x = 1; lane bits at the source in mcur (and
 // mvisited), source bits in the union frontier `cur`.

@@ -653,14 +653,16 @@ struct OpMSssp {
 };
 
 // Batched personalized PageRank: every lane active at u adds its share x_u / D_o(u)
-// (prepared in place in u's row) into v's accumulator row.
+// (prepared in place in u's row, FP32) into v's accumulator row (FP64: a hub's value is a
+// sum of up to ~10^5 shares per step, which FP32 adds in atomic order would carry ~1e-4
+// relative error; in FP64 only the FP32 rounding of x and of the shares remains).
 struct OpMPpr {
     static constexpr bool wave = true;
     static constexpr bool weighted = false;
     const uint64_t* mcur;
     uint64_t* mnext;
     const float* share;  // n rows of 2^lshift lanes
-    float* acc;          // n rows of 2^lshift lanes
+    double* acc;         // n rows of 2^lshift lanes
     uint32_t* next;      // union of the next frontier
     uint32_t lshift;
     __device__ __forceinline__ uint32_t src(uint32_t u) const { return u; }
@@ -668,12 +670,12 @@ struct OpMPpr {
         const uint64_t m = mcur[u];
         if (!m) return;
         const float* su = share + ((uint64_t)u << lshift);
-        float* av = acc + ((uint64_t)v << lshift);
+        double* av = acc + ((uint64_t)v << lshift);
         uint64_t b = m;
         while (b) {
             const uint32_t l = __ffsll((unsigned long long)b) - 1;
             b &= b - 1;
-            unsafeAtomicAdd(av + l, su[l]);
+            unsafeAtomicAdd(av + l, (double)su[l]);
         }
         mark(m, v);
     }
@@ -701,7 +703,7 @@ struct OpMPpr {
             const int from = a ? (int)__ffsll((unsigned long long)a) - 1 : 0;
             const uint32_t uu = __shfl(u, from, 64), vv = __shfl(v, from, 64);
             if (a && ((mcur[uu] >> ln) & 1))
-                unsafeAtomicAdd(acc + ((uint64_t)vv << lshift) + ln, share[((uint64_t)uu << lshift) + ln]);
+                unsafeAtomicAdd(acc + ((uint64_t)vv << lshift) + ln, (double)share[((uint64_t)uu << lshift) + ln]);
             for (uint32_t k = 0; k < per && act; k++) act &= act - 1;
         }
         if (ok) {
@@ -966,7 +968,7 @@ __global__ void k_init_lanes(AlgoState s, LaneSources src, uint32_t* __restrict_
         const bool at_src = l < src.count && src.src[l] == v;
         if (s.algo == ALGO_MPPR) {
             s.lx[i] = at_src ? 1.0f : 0.0f;
-            s.lacc[i] = 0.0f;
+            s.lacc[i] = 0.0;
         } else {
             s.lval[i] = at_src ? 0u : UNREACHED;
         }
@@ -1182,6 +1184,37 @@ __global__ void k_far_move(uint32_t* __restrict__ far, const uint32_t* __restric
     }
 }
 
+// SSSP overflow, decided after convergence.  A relaxation whose candidate reaches 2^32-1 is
+// skipped and only raises a lane's flag; whether that lane's shortest distances really
+// overflow is decided here.  After convergence every vertex whose shortest distance fits
+// below 2^32-1 holds it, so a lane overflows exactly when some edge leads from a vertex it
+// reached to one it did not.  One wave per vertex u (grid-stride): the lanes of `mask`
+// that reached u read u's out-edges from the mapped host array `col` and check their
+// targets; lanes that find an unreached target are ORed into *out.  dist: n rows of
+// 2^lshift lanes (lshift 0: one distance per vertex).
+__global__ __launch_bounds__(256) void k_sssp_ovf_check(const uint64_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ col, Pack pk,
+                                                        const uint32_t* __restrict__ dist, uint32_t lshift,
+                                                        uint64_t mask, uint64_t n, unsigned long long* out) {
+    const uint32_t lane = __lane_id();
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
+    uint64_t found = 0;
+    for (uint64_t u = blockIdx.x * (uint64_t)(blockDim.x / 64) + threadIdx.x / 64; u < n; u += waves) {
+        const bool mine = lane < (1u << lshift) && ((mask >> lane) & 1) && dist[(u << lshift) + lane] != UNREACHED;
+        const uint64_t reached = __ballot(mine);
+        if (!reached) continue;
+        const uint64_t e1 = off[u + 1];
+        for (uint64_t e = off[u] + lane; e < e1; e += 64) {
+            const uint32_t* dv = dist + ((uint64_t)pk_v(col[e], pk) << lshift);
+            for (uint64_t r = reached; r; r &= r - 1) {
+                const uint32_t l = __ffsll((unsigned long long)r) - 1;
+                if (dv[l] == UNREACHED) found |= 1ull << l;
+            }
+        }
+    }
+    if (found) atomicOr(out, (unsigned long long)found);
+}
+
 __global__ void k_admit_lanes(AlgoState s, LaneSet set, uint32_t* __restrict__ cur) {
     const uint32_t l = threadIdx.x;
     if (l >= MAX_LANES || !((set.mask >> l) & 1)) return;
@@ -1204,7 +1237,7 @@ __global__ void k_reset_lanes(AlgoState s, uint64_t mask) {
         if (!((mask >> ((uint32_t)i & lmask)) & 1)) continue;
         if (s.algo == ALGO_MPPR) {
             s.lx[i] = 0.0f;
-            s.lacc[i] = 0.0f;
+            s.lacc[i] = 0.0;
         } else {
             s.lval[i] = UNREACHED;
         }
@@ -1240,12 +1273,12 @@ __global__ void k_ppr_apply(AlgoState s, float damping) {
         uint64_t m = s.mcur[v] | s.mnext[v];
         if (!m) continue;
         float* x = s.lx + (v << s.lshift);
-        float* a = s.lacc + (v << s.lshift);
+        double* a = s.lacc + (v << s.lshift);
         while (m) {
             const uint32_t l = __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
-            x[l] = damping * a[l];
-            a[l] = 0.0f;
+            x[l] = (float)((double)damping * a[l]);
+            a[l] = 0.0;
         }
     }
 }
@@ -2017,6 +2050,13 @@ hipError_t launch_far_move(uint32_t* far, const uint32_t* dist, uint32_t* cur, u
                            hipStream_t st) {
     if (!nwords) return hipSuccess;
     k_far_move<<<grid_for(nwords, 256, 8192), 256, 0, st>>>(far, dist, cur, nwords, bound);
+    return hipGetLastError();
+}
+
+hipError_t launch_sssp_ovf_check(const uint64_t* off, const uint32_t* col, const Pack& pk, const uint32_t* dist,
+                                 uint32_t lshift, uint64_t mask, uint64_t n, unsigned long long* out, hipStream_t st) {
+    if (!n || !mask || lshift > 6) return lshift > 6 ? hipErrorInvalidValue : hipSuccess;
+    k_sssp_ovf_check<<<grid_for(n, 4, 16384), 256, 0, st>>>(off, col, pk, dist, lshift, mask, n, out);
     return hipGetLastError();
 }
 

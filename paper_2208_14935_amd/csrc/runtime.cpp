@@ -226,7 +226,8 @@ struct hytm_graph {
     // batched runs (up to 64 lanes): lane masks, lane values, lanes active this iteration
     DevBuf<uint64_t> d_mcur, d_mnext, d_mvis, d_lanes;
     DevBuf<uint32_t> d_lval;
-    DevBuf<float> d_lx, d_lacc;   // batched PPR: x and accumulator rows
+    DevBuf<float> d_lx;           // batched PPR: x rows (FP32)
+    DevBuf<double> d_lacc;        // ... and accumulator rows (FP64)
     DevBuf<uint32_t> d_xout;      // lanes extracted for the copy back
     DevBuf<uint32_t> d_cur2;      // frontier of the reprocessing pass
     DevBuf<uint64_t> d_scan;      // selection scan: per-tile totals and bases
@@ -234,6 +235,7 @@ struct hytm_graph {
     DevBuf<uint32_t> d_farmin;    // smallest waiting distance
     HostBuf<uint32_t> h_farmin;
     DevBuf<uint64_t> d_zcl;       // distinct 128-byte lines read by the zero-copy kernel this run
+    DevBuf<uint64_t> d_ovf;       // SSSP: lanes whose distances overflow (checked after convergence)
     DevBuf<float> d_delta;        // delta-based PageRank: pending delta per vertex
     DevBuf<double> d_psum;        // ... and per partition
     HostBuf<double> h_psum;
@@ -273,6 +275,7 @@ struct hytm_graph {
     hipEvent_t ev_copied[kMaxSlots] = {}, ev_free[kMaxSlots] = {};
     hipEvent_t ev_pbpush = nullptr, ev_pbfree[2] = {};
     hipEvent_t ev_cdone[2] = {}, ev_join[4] = {}, ev_start = nullptr, ev_clist = nullptr, ev_go = nullptr;
+    hipEvent_t ev_sel[2] = {};    // timing events around each pass's selection (statistics to D2H)
 
     Pool* pool = nullptr;
     KTimer timer;
@@ -504,6 +507,7 @@ void ensure_streams(hytm_graph* g) {
     HIP_CHECK(hipEventCreateWithFlags(&g->ev_start, hipEventDisableTiming));
     HIP_CHECK(hipEventCreateWithFlags(&g->ev_clist, hipEventDisableTiming));
     HIP_CHECK(hipEventCreateWithFlags(&g->ev_go, hipEventDisableTiming));
+    for (auto& e : g->ev_sel) HIP_CHECK(hipEventCreate(&e));
 }
 
 void release_all(hytm_graph* g) {
@@ -528,6 +532,7 @@ void release_all(hytm_graph* g) {
     g->d_farmin.release();
     g->h_farmin.release();
     g->d_zcl.release();
+    g->d_ovf.release();
     g->d_delta.release();
     g->d_psum.release();
     g->h_psum.release();
@@ -584,6 +589,8 @@ void release_all(hytm_graph* g) {
     if (g->ev_start) (void)hipEventDestroy(g->ev_start);
     if (g->ev_clist) (void)hipEventDestroy(g->ev_clist);
     if (g->ev_go) (void)hipEventDestroy(g->ev_go);
+    for (auto e : g->ev_sel)
+        if (e) (void)hipEventDestroy(e);
     delete g->pool;
     g->pool = nullptr;
     g->timer.destroy();
@@ -866,8 +873,10 @@ hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Heade
     const Plan& pl = rc.plan;
     const bool fstream = g->params.filter_engine == HYTM_FILTER_STREAM;
     const uint64_t d1b = 4ull * rc.arrays;
-    const double t_sel = now_ms();
-    // 1. statistics, engine selection, active lists (Algorithm 1, GPU part)
+    // 1. statistics, engine selection, active lists (Algorithm 1, GPU part); timed on the
+    // device from the statistics kernel to the end of the D2H copy, so the time the stream
+    // spends finishing the previous iteration's pushes is not counted
+    HIP_CHECK(hipEventRecord(g->ev_sel[0], main));
     HIP_CHECK(kt.run(HYTM_K_STATS, npart, main, [&] {
         return launch_stats_select(npart, g->d_pv.p, g->d_off.p, cur, rc.sp, g->d_mode.p, g->d_nA.p, g->d_nF.p,
                                    g->d_Ea.p, g->d_Rq.p, g->d_K.p, main);
@@ -889,12 +898,15 @@ hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Heade
         HIP_CHECK(launch_lane_union(rc.mcur, n, (unsigned long long*)g->d_lanes.p, main));
         HIP_CHECK(hipMemcpyAsync(g->h_lanes.p, g->d_lanes.p, sizeof(uint64_t), hipMemcpyDeviceToHost, main));
     }
+    HIP_CHECK(hipEventRecord(g->ev_sel[1], main));
     HIP_CHECK(hipStreamSynchronize(main));
     Totals& tt = rc.tot;
     tt.d2h += sizeof(Header) + npart * (1 + 4 + 8);
     const Header h = *g->h_hdr.p;
     *hout = h;
-    tt.select_ms += now_ms() - t_sel;
+    float sel_ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&sel_ms, g->ev_sel[0], g->ev_sel[1]));
+    tt.select_ms += sel_ms;
     if (lanes) *lanes = *g->h_lanes.p;
     if (stop_if_empty && h.frontier == 0) return HYTM_OK;
 
@@ -1112,10 +1124,9 @@ constexpr uint32_t kPbLinkGrid = 2048;
 // PageRank's resident adds go through pair buckets (see PB_* in the kernel header) when it
 // runs alone, some partitions are resident, the selection can contain no compaction
 // partitions (their pushes are not replayed), filter partitions use the streaming engine,
-// and the fine bins fit one LDS counting sort (n <= 2^24).  The two-pass sort for larger
-// graphs is built but switched off: its test process ended in a host segmentation fault
-// whose cause is not found yet, so those graphs keep the atomic adds.
-constexpr bool kPbTwoPass = false;
+// and the fine bins fit one LDS counting sort (n <= 2^24) or two sorting passes do
+// (coarse bins, then fine bins: n <= 2^28).
+constexpr bool kPbTwoPass = true;
 
 // pr_blocking = 1 (automatic) also asks for at least half of the edges to be resident:
 // below that the streamed atomics and the host link bound the iteration, and the sorting
@@ -1568,6 +1579,22 @@ hytm_status far_advance(RunCtx& rc, hipStream_t main, bool* more) {
     return HYTM_OK;
 }
 
+// SSSP overflow.  The push skips a candidate distance of 2^32-1 or more and raises its
+// lane's flag; the flagged lanes whose converged distances leave an unreached vertex next
+// to a reached one are those whose shortest distances do not all fit in uint32 (the
+// oracle's rule: only a final distance decides).  Returns those lanes.
+uint64_t sssp_overflow_lanes(hytm_graph* g, const uint32_t* dist, uint32_t lshift, uint64_t flagged, hipStream_t main) {
+    if (!flagged) return 0;
+    g->d_ovf.ensure(1);
+    HIP_CHECK(launch_fill_u32((uint32_t*)g->d_ovf.p, 2, 0u, main));
+    HIP_CHECK(launch_sssp_ovf_check(g->d_off.p, g->d_col_map, g->pk, dist, lshift, flagged, g->n,
+                                    (unsigned long long*)g->d_ovf.p, main));
+    uint64_t out = 0;
+    HIP_CHECK(hipMemcpyAsync(&out, g->d_ovf.p, sizeof(out), hipMemcpyDeviceToHost, main));
+    HIP_CHECK(hipStreamSynchronize(main));
+    return out;
+}
+
 hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uint32_t lanes, void* values_out,
                      uint32_t* iterations_out, hytm_run_stats* stats, void* hip_stream) {
     HIP_CHECK(hipSetDevice(g->device));
@@ -1708,7 +1735,8 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     if (algo == HYTM_SSSP) {
         uint32_t of[2] = {0, 0};
         HIP_CHECK(hipMemcpy(of, g->d_overflow.p, sizeof(of), hipMemcpyDeviceToHost));
-        if (of[0] | (batched ? of[1] : 0u))
+        const uint64_t flagged = batched ? ((uint64_t)of[0] | ((uint64_t)of[1] << 32)) & rc.ppr.mask : (of[0] ? 1ull : 0ull);
+        if (sssp_overflow_lanes(g, batched ? g->d_lval.p : g->d_val.p, batched ? lsh : 0, flagged, main))
             return fail(HYTM_E_RANGE, "an SSSP distance reaches 2^32-1 and does not fit in uint32");
     }
     if (batched) {
@@ -1814,7 +1842,8 @@ struct LaneGroup {
     RunCtx rc;
     DevBuf<uint32_t> cur, nxt, lval;
     DevBuf<uint64_t> mcur, mnxt, mvis;
-    DevBuf<float> lx, lacc;
+    DevBuf<float> lx;
+    DevBuf<double> lacc;
     uint64_t occupied = 0;  // lanes holding a query (changed by the worker only, under the lock)
     uint64_t fresh = 0;     // lanes admitted since the last step
     double vtime = 0;       // worker time spent on this group (fair sharing between groups)
@@ -1837,7 +1866,7 @@ uint64_t group_state_bytes(uint64_t n, int algo, uint32_t lanes) {
     const uint64_t rows = n << lane_shift(lanes);
     uint64_t b = 2 * ((n + 31) / 32) * 4 + 2 * n * 8;  // union bitmaps, lane masks
     if (algo == HYTM_BFS) b += n * 8;                   // lanes that reached each vertex
-    return b + rows * 4 * (algo == HYTM_PPR ? 2 : 1);
+    return b + rows * (algo == HYTM_PPR ? 4 + 8 : 4);  // PPR: FP32 x and FP64 accumulators
 }
 
 }  // namespace
@@ -1867,7 +1896,7 @@ void retire_lanes(hytm_server* s, LaneGroup& gr, uint64_t mask, hipStream_t main
         HIP_CHECK(hipStreamSynchronize(main));
         uint32_t of[2] = {0, 0};
         HIP_CHECK(hipMemcpy(of, g->d_overflow.p, sizeof(of), hipMemcpyDeviceToHost));
-        over = ((uint64_t)of[0] | ((uint64_t)of[1] << 32)) & mask;
+        over = sssp_overflow_lanes(g, gr.lval.p, gr.lshift, ((uint64_t)of[0] | ((uint64_t)of[1] << 32)) & mask, main);
     }
     LaneSet set{};
     set.mask = mask & ~over;

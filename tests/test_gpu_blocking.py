@@ -134,8 +134,6 @@ def test_automatic_blocking_follows_resident_share(rmat20, resident, blocked):
         assert (res.stats["kernel_launches"][BLOCK] > 0) == blocked
 
 
-@pytest.mark.skip(reason="two-pass bucketing is switched off: this test's process ended in a host segmentation "
-                         "fault (twice, in its first case) and the cause is not found yet")
 @pytest.mark.parametrize("resident", [0.5, None])
 def test_two_pass_buckets_match_oracle(er_big, resident):
     note(f"er 17M pagerank two-pass blocking resident={resident}")
