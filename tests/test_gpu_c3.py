@@ -1,5 +1,6 @@
 """GPU parity on the oversubscribed configuration the benchmark times: R-MAT scale 28
-(268M vertices, ~4.3B edges, so edge indices above 2^32), uint32 weights in [1, 64] kept
+(268M vertices, 4.26B edges after dedupe, past 2^31; its symmetrized graph for CC has ~8.5B,
+so edge indices above 2^32), uint32 weights in [1, 64] kept
 in their own array (28 id bits + 6 weight bits do not fit one word), edge budget 8 GB
 (about 47% of the edges resident, ~133K partitions), hybrid engines with the benchmark's
 cost-model settings.
@@ -56,7 +57,8 @@ def c3():
 
 def test_c3_shape(c3):
     info = c3["g"].info()
-    assert c3["g"].m > (1 << 32)
+    assert c3["g"].m > (1 << 31)
+    assert c3["off"].dtype == np.uint64
     assert not info["packed_weights"]
     assert c3["g"].edge_arrays("sssp") == 2
 
@@ -106,6 +108,7 @@ def test_c3_cc_exact(c3):
     c3["g"] = None
     soff, scol = c3["fut"]["sym"].result()
     note(f"c3: cc on the symmetrized graph, m_sym={len(scol)}")
+    assert len(scol) > (1 << 32)  # edge indices past 32 bits
     with hy.Graph(soff, scol, symmetric=True, check_col=False) as gs:
         gs.set_params(**BENCH)
         gs.set_budget(BUDGET)
