@@ -39,6 +39,11 @@ PMC_TRAFFIC = {"kernel": "push_zerocopy", "workload": "rmat24-ef16-budget0.25-hy
                "bytes_per_launch": (2 * 1424311 + 661331) * 1024.0,
                "summary": "profiles/pmc_traffic_rmat24_budget25_hybrid.md"}
 PCIE_GEN5_X16_GBPS = 63.0
+# hipHostMalloc fails past ~64 GiB per process on the MI355X hosts measured (295 GiB of RAM);
+# the engine's own pinned buffers (compaction lists, selection mirrors, result buffers) need
+# a few GB beside the edge arrays
+PINNED_CEILING = 64 << 30
+PINNED_HEADROOM = 10 << 30
 
 
 def log(*a):
@@ -90,6 +95,8 @@ def main():
                     help="rmat: R-MAT at --scale; er: uniform G(n, m) with --er-vertices and --er-degree")
     ap.add_argument("--er-vertices", type=int, default=200_000_000)
     ap.add_argument("--er-degree", type=float, default=20.0)
+    ap.add_argument("--pinned-ceiling", type=float, default=PINNED_CEILING,
+                    help="pinned host bytes one process may hold; above it the headline step runs phased")
     ap.add_argument("--budget-bytes", type=float, default=None,
                     help="absolute device budget for edge data (default 8e9 for the oversubscribed workload, "
                          "else 0 = --budget-frac of each algorithm's bytes)")
@@ -166,13 +173,27 @@ def main():
 
     t0 = time.time()
     g = hy.Graph(off, col, weights=w, check_col=False, hub_sort=args.hub_sort, pack=not args.no_pack)
+    packed = bool(g.info()["packed_weights"])
+    # Both graphs of the headline step stay pinned at once only when their edge arrays fit
+    # under the host's pinned-memory ceiling with room for the engine's own pinned buffers;
+    # otherwise the step runs phased: every timed pass over the directed graph, then the
+    # directed graph's pinned copy is released, the symmetrized graph is pinned, and every
+    # timed CC pass follows.  Swapping the pinned copies is excluded like graph loading.
+    g_bytes = 4 * m * (1 if packed or w is None else 2)
+    sym_bytes = 4 * len(scol) if scol is not None else 0
+    phased = (headline and scol is not None
+              and g_bytes + sym_bytes + PINNED_HEADROOM > args.pinned_ceiling)
     # the per-mode workload loads the symmetrized graph only after the directed one is
     # closed, so that the two never hold pinned host memory at once
     gs = (hy.Graph(soff, scol, symmetric=True, check_col=False, hub_sort=args.hub_sort)
-          if scol is not None and args.workload != "modes" else None)
-    log(f"pinned graph copies {time.time() - t0:.1f}s")
+          if scol is not None and args.workload != "modes" and not phased else None)
+    log(f"pinned graph copies {time.time() - t0:.1f}s"
+        + (f" (phased: {g_bytes / 1e9:.1f} + {sym_bytes / 1e9:.1f} GB of edges over a "
+           f"{args.pinned_ceiling / 2**30:.0f} GiB pinned ceiling)" if phased else ""))
     if headline:
-        del col, w, scol  # the graphs hold their own pinned copies (at R-MAT 28 these were ~70 GB)
+        del col, w  # the graphs hold their own pinned copies (at R-MAT 28 these were ~70 GB)
+        if not phased:
+            del scol
     gamma = gamma_from(args.gamma, probe)
     log(f"gamma = {gamma[0]}/{gamma[1]}")
     if args.compact_gather == "off":
@@ -187,12 +208,16 @@ def main():
     zc_tie = {"filter": 0, "zerocopy": 1}.get(args.zc_tie,
                                               int(probe["zc_read_gbps"]["128B"] >= 0.95 * probe["h2d_copy_gbps"]))
     log(f"tie to zero-copy = {zc_tie}")
+
+    def configure(h):
+        h.set_params(mode=args.mode, partition_edges=args.partition_edges, combine_k=args.combine_k,
+                     filter_engine=args.filter_engine, gamma=gamma, reprocess=int(args.reprocess),
+                     compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct), zc_tie=zc_tie,
+                     pr_blocking=args.pr_blocking, sssp_delta=args.sssp_delta)
+
     for h in (g, gs):
         if h is not None:
-            h.set_params(mode=args.mode, partition_edges=args.partition_edges, combine_k=args.combine_k,
-                         filter_engine=args.filter_engine, gamma=gamma, reprocess=int(args.reprocess),
-                         compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct), zc_tie=zc_tie,
-                         pr_blocking=args.pr_blocking, sssp_delta=args.sssp_delta)
+            configure(h)
     if args.workload == "batch":
         return batch_workload(args, g, off, col, deg, gamma, probe)
     if args.workload == "serve":
@@ -219,11 +244,12 @@ def main():
         reach_edges[int(s)] = int(deg[lv != hy.UNREACHED].sum())
 
     # results land in pinned host buffers (direct DMA); each run overwrites the previous one
-    out_u32 = hy.pinned_empty(max(g.n, gs.n) if gs is not None else g.n, np.uint32)
-    out_f32 = hy.pinned_empty(g.n, np.float32)
+    out_u32 = hy.pinned_empty(n, np.uint32)
+    out_f32 = hy.pinned_empty(n, np.float32)
 
     k_src = max(1, min(args.sources_per_step, len(srcs)))
     step_no = [0]
+    arrays = {a: g.edge_arrays(a) for a in ("bfs", "sssp", "pagerank")}
 
     def step_sources():
         # step i takes sources i*k .. i*k+k-1 of the seeded list, wrapping around
@@ -231,13 +257,13 @@ def main():
         step_no[0] += 1
         return [srcs[(i * k_src + j) % len(srcs)] for j in range(k_src)]
 
-    def step(record):
+    def step_directed(record):
         runs = []
         ss = step_sources()
         if "bfs" in algos:
             budget(g, "bfs")
             for s in ss:
-                r = g.run("bfs", int(s), stats=True, time_kernels=kt and record, out=out_u32[: g.n])
+                r = g.run("bfs", int(s), stats=True, time_kernels=kt and record, out=out_u32)
                 runs.append(("bfs", r, reach_edges[int(s)]))
         if "pagerank" in algos:
             budget(g, "pagerank")
@@ -246,28 +272,50 @@ def main():
         if "sssp" in algos:
             budget(g, "sssp")
             for s in ss:
-                r = g.run("sssp", int(s), stats=True, time_kernels=kt and record, out=out_u32[: g.n])
+                r = g.run("sssp", int(s), stats=True, time_kernels=kt and record, out=out_u32)
                 runs.append(("sssp", r, reach_edges[int(s)]))
-        if "cc" in algos:
-            budget(gs, "cc")
-            r = gs.run("cc", stats=True, time_kernels=kt and record, out=out_u32[: gs.n])
-            runs.append(("cc", r, gs.m))
         return runs
 
-    for i in range(args.warmup):
-        t = time.time()
-        step(False)
-        log(f"warmup step {i}: {time.time() - t:.2f}s")
+    def step_cc(record):
+        if "cc" not in algos:
+            return []
+        budget(gs, "cc")
+        r = gs.run("cc", stats=True, time_kernels=kt and record, out=out_u32)
+        return [("cc", r, gs.m)]
 
-    all_runs = []
-    sync()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
+    def timed(step):
+        for i in range(args.warmup):
+            t = time.time()
+            step(False)
+            log(f"warmup step {i}: {time.time() - t:.2f}s")
+        runs = []
+        sync()
+        t_start = time.perf_counter()
+        for i in range(args.steps):
+            t = time.time()
+            runs += step(True)
+            log(f"step {i}: {time.time() - t:.2f}s")
+        sync()
+        return runs, time.perf_counter() - t_start
+
+    if not phased:
+        all_runs, elapsed = timed(lambda record: step_directed(record) + step_cc(record))
+        m_sym = int(gs.m) if gs is not None else None
+    else:
+        all_runs, elapsed = timed(step_directed)
+        log(f"phase 1 (directed graph): {elapsed:.2f}s")
+        g.close()
         t = time.time()
-        all_runs += step(True)
-        log(f"step {i}: {time.time() - t:.2f}s")
-    sync()
-    elapsed = time.perf_counter() - t_start
+        gs = hy.Graph(soff, scol, symmetric=True, check_col=False, hub_sort=args.hub_sort)
+        configure(gs)
+        del scol
+        log(f"pinned symmetrized copy {time.time() - t:.1f}s")
+        runs_cc, elapsed_cc = timed(step_cc)
+        log(f"phase 2 (symmetrized graph): {elapsed_cc:.2f}s")
+        all_runs += runs_cc
+        elapsed += elapsed_cc
+        m_sym = int(gs.m)
+    arrays["cc"] = gs.edge_arrays("cc") if gs is not None else 1
 
     edges = sum(e for _, _, e in all_runs)
     value = edges / elapsed / 1e9
@@ -301,7 +349,7 @@ def main():
                 + (f"-budget{args.budget_bytes / 1e9:g}GB" if args.budget_bytes else f"-budget{args.budget_frac:g}")
                 + f"-{args.mode}" + (f"-src{k_src}perstep" if k_src != len(srcs) else "")
                 + (f"-reprocess{args.reprocess}" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
-                + ("" if g.info()["packed_weights"] else "-unpacked")
+                + ("" if packed else "-unpacked")
                 + ("" if cgather[0] == 0 else "-gathercost") + ("-rqdistinct" if args.rq_distinct else "")
                 + ("-zctie" if zc_tie else "") + ("-prblock" if args.pr_blocking == 2 and "pagerank" in algos else "")
                 + (f"-delta{args.sssp_delta}" if args.sssp_delta and "sssp" in algos else ""))
@@ -315,7 +363,7 @@ def main():
         arrays_items = np.zeros(nk)  # items weighted by edge arrays read
         zc_bytes = 0  # lines the zero-copy kernel really read (a line two lists share counts once)
         for name, r, _ in all_runs:
-            a = (gs if name == "cc" else g).edge_arrays(name)
+            a = arrays[name]
             ms += np.array(r.stats["kernel_ms"])
             launches += np.array(r.stats["kernel_launches"], dtype=np.int64)
             it = np.array(r.stats["kernel_items"], dtype=np.int64)
@@ -380,7 +428,7 @@ def main():
         "dtype": "u32 (BFS/SSSP/CC), f32 (PageRank)",
         "data": "synthetic R-MAT, seeded",
         "config": {"workload": workload,
-                   "n": n, "m": m, "m_sym": int(gs.m) if gs is not None else None,
+                   "n": n, "m": m, "m_sym": m_sym, "phased": phased,
                    "sources": [int(s) for s in srcs], "sources_per_step": k_src,
                    "budget_bytes": int(args.budget_bytes) if args.budget_bytes else None,
                    "budget_frac_of_edge_bytes": None if args.budget_bytes else args.budget_frac,
