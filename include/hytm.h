@@ -386,6 +386,19 @@ hytm_status hytm_select_engines(hytm_graph *g, uint64_t npart, const uint64_t *E
                                 const uint64_t *Ea, const uint64_t *Rq, uint64_t nres, uint32_t edge_arrays,
                                 uint8_t *p_out);
 
+/* The same selection as hytm_select_engines, for callers that cannot allocate device
+   memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): the statistics and engine codes pass through a static device array that
+   the library holds on each device for the life of the process, so this call makes no
+   hipMalloc, hipFree or other allocation.  Arguments as hytm_select_engines, plus
+   hip_stream : the HIP stream the copies and the kernel run on (NULL = the null stream);
+                the call returns after that stream has finished them.
+   Limit: npart <= 262144 (HYTM_E_RANGE above it); the array takes 8.65 MB per device.
+   Calls that overlap on one device share that array and race: callers serialize them. */
+hytm_status hytm_select_engines_static(hytm_graph *g, uint64_t npart, const uint64_t *E, const uint64_t *nA,
+                                       const uint64_t *Ea, const uint64_t *Rq, uint64_t nres, uint32_t edge_arrays,
+                                       uint8_t *p_out, void *hip_stream);
+
 /* Pinned host memory for result buffers: a values_out buffer from here is written by DMA
    directly, without the staging copy an ordinary (pageable) buffer needs.  hip_device
    selects the device the allocation is registered with.  hytm_host_free(NULL) is a no-op. */

@@ -31,6 +31,7 @@ GRAPH_HUB_SORT = 1 << 3
 GRAPH_NO_PACK = 1 << 4
 UNCAPPED = (1 << 64) - 1
 UNREACHED = 0xFFFFFFFF
+STATIC_SELECT_MAX_PARTS = 1 << 18  # hytm_select_engines_static's limit
 
 
 class HytmError(RuntimeError):
@@ -133,6 +134,10 @@ _SIGNATURES = {
     "hytm_select_engines": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
                                            ctypes.c_void_p]),
+    "hytm_select_engines_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                                  ctypes.c_void_p]),
     "hytm_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "hytm_last_error": (ctypes.c_char_p, []),
     "hytm_link_probe": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(LinkProbe)]),
@@ -457,6 +462,17 @@ class Graph:
         p = np.zeros(max(npart, 1), dtype=np.uint8)
         _check(load().hytm_select_engines(self._h, npart, *(_ptr(x) for x in arrs), int(nres), int(edge_arrays),
                                           _ptr(p)))
+        return p[:npart]
+
+    def select_engines_static(self, E, nA, Ea, Rq, nres: int = 0, edge_arrays: int = 1, stream=None) -> np.ndarray:
+        """select_engines through the library's static device scratch (no device
+        allocation; at most STATIC_SELECT_MAX_PARTS partitions)."""
+        arrs = [np.ascontiguousarray(x, dtype=np.uint64) for x in (E, nA, Ea, Rq)]
+        npart = len(arrs[0])
+        p = np.zeros(max(npart, 1), dtype=np.uint8)
+        _check(load().hytm_select_engines_static(self._h, npart, *(_ptr(x) for x in arrs), int(nres),
+                                                 int(edge_arrays), _ptr(p),
+                                                 stream if stream is not None else _current_stream()))
         return p[:npart]
 
 

@@ -340,4 +340,13 @@ hipError_t launch_copy_probe(void* dst, const void* src, uint64_t bytes, hipStre
 hipError_t launch_select_only(uint64_t npart, const uint64_t* E, const uint64_t* nA, const uint64_t* Ea,
                               const uint64_t* Rq, const SelParams& sp, uint8_t* p, hipStream_t st);
 
+// Allocation-free selection: a static device array of STATIC_SEL_WORDS words per device
+// holds the statistics (4 x npart uint64) and then the engine codes (npart bytes) for at
+// most STATIC_SEL_MAX_PARTS partitions.  static_select_scratch gives its address on
+// `device`, which must be the current device (resolved on the first call per device).
+constexpr uint64_t STATIC_SEL_MAX_PARTS = 1ull << 18;
+constexpr uint64_t STATIC_SEL_WORDS = 4 * STATIC_SEL_MAX_PARTS + STATIC_SEL_MAX_PARTS / 8;
+constexpr int STATIC_SCRATCH_DEVICES = 64;
+hipError_t static_select_scratch(int device, uint64_t** out);
+
 }  // namespace hytm

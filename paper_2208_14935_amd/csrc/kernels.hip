@@ -19,6 +19,8 @@
 // PageRank (FP32 atomic add), and a bitmap-directed next frontier (Sec. 6.3).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "hytm_kernels.h"
 
 namespace hytm {
@@ -2384,6 +2386,32 @@ hipError_t launch_select_only(uint64_t npart, const uint64_t* E, const uint64_t*
     if (!npart) return hipSuccess;
     k_select_only<<<grid_for(npart, 256, 4096), 256, 0, st>>>(npart, E, nA, Ea, Rq, sp, p);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free selection: the four statistics arrays (uint64 x npart
+// each) followed by the engine codes (npart bytes), for at most STATIC_SEL_MAX_PARTS
+// partitions.  Each device holds its own copy for the life of the process.  In host code
+// the array's name stands for no device address; its address on the current device comes
+// from hipGetSymbolAddress, once per device, below.
+static __device__ __align__(256) uint64_t scratch[STATIC_SEL_WORDS];
+
+hipError_t static_select_scratch(int device, uint64_t** out) {
+    static std::mutex mu;
+    static uint64_t* ptr[STATIC_SCRATCH_DEVICES] = {};
+    if (device < 0 || device >= STATIC_SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current
+        void* at = nullptr;
+        e = hipGetSymbolAddress(&at, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[device] = (uint64_t*)at;
+    }
+    *out = ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace hytm

@@ -2509,6 +2509,41 @@ hytm_status hytm_select_engines(hytm_graph* g, uint64_t npart, const uint64_t* E
     });
 }
 
+hytm_status hytm_select_engines_static(hytm_graph* g, uint64_t npart, const uint64_t* E, const uint64_t* nA,
+                                       const uint64_t* Ea, const uint64_t* Rq, uint64_t nres, uint32_t edge_arrays,
+                                       uint8_t* p_out, void* hip_stream) {
+    g_err.clear();
+    if (!g || (npart && (!E || !nA || !Ea || !Rq || !p_out))) return fail(HYTM_E_INVAL, "NULL argument");
+    if (g->server) return fail(HYTM_E_STATE, "a query server is open on this graph");
+    if (edge_arrays != 1 && edge_arrays != 2) return fail(HYTM_E_INVAL, "edge_arrays must be 1 or 2");
+    if (npart > STATIC_SEL_MAX_PARTS)
+        return fail(HYTM_E_RANGE, "%llu partitions exceed the static scratch (at most %llu)",
+                    (unsigned long long)npart, (unsigned long long)STATIC_SEL_MAX_PARTS);
+    for (uint64_t i = 0; i < npart; i++)
+        if (E[i] >= (1ull << 40) || Ea[i] > E[i] || nA[i] > Ea[i] || Rq[i] >= (1ull << 44) ||
+            (Ea[i] > 0 && nA[i] == 0))
+            return fail(HYTM_E_INVAL, "partition %llu: statistics out of range", (unsigned long long)i);
+    if (npart == 0) return HYTM_OK;
+    return guarded([&]() -> hytm_status {
+        HIP_CHECK(hipSetDevice(g->device));
+        uint64_t* scr = nullptr;  // this device's copy of the static array
+        HIP_CHECK(static_select_scratch(g->device, &scr));
+        hipStream_t st = (hipStream_t)hip_stream;
+        SelParams sp = make_sel(g, edge_arrays);
+        sp.nres = (uint32_t)std::min<uint64_t>(nres, 0xFFFFFFFFull);
+        // every word the selection reads is written first, and every code it returns is
+        // written by it, so nothing left by an earlier call is seen
+        const uint64_t* src[4] = {E, nA, Ea, Rq};
+        for (int a = 0; a < 4; a++)
+            HIP_CHECK(hipMemcpyAsync(scr + a * npart, src[a], npart * 8, hipMemcpyHostToDevice, st));
+        uint8_t* codes = (uint8_t*)(scr + 4 * npart);
+        HIP_CHECK(launch_select_only(npart, scr, scr + npart, scr + 2 * npart, scr + 3 * npart, sp, codes, st));
+        HIP_CHECK(hipMemcpyAsync(p_out, codes, npart, hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        return HYTM_OK;
+    });
+}
+
 hytm_status hytm_link_probe(int hip_device, uint64_t bytes, hytm_link_probe_result* out) {
     g_err.clear();
     if (!out) return fail(HYTM_E_INVAL, "out is NULL");
