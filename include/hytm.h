@@ -154,8 +154,8 @@ typedef struct {
                                    (about 20 G/s) falls below what HBM feeds from the resident cache.
                                    Streamed partitions keep their atomic adds (the host link delivers
                                    fewer edges per second than the atomics take).  1 (default): when at
-                                   least half of the edges are resident; 2: whenever some are; 0: never.
-                                   Applies to single PageRank runs with n <= 2^24 in the hybrid, filter
+                                   least 3/8 of the edges are resident; 2: whenever some are; 0: never.
+                                   Applies to single PageRank runs with n <= 2^28 in the hybrid, filter
                                    (streaming engine) or zero-copy modes; the result is the same sum in
                                    another order.  Needs 16 bytes per pair of a piece of device memory
                                    outside the edge budget (16 bytes per vertex at the default piece). */

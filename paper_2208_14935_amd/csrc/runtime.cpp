@@ -1118,8 +1118,12 @@ hytm_status replay_pass(RunCtx& rc, hipStream_t main, hytm_iter_stats* rec, int6
 }
 
 // ------------------------------------------------------ propagation blocking
-// Workgroups of the streamed pushes beside the resident pieces.
-constexpr uint32_t kPbLinkGrid = 2048;
+// Workgroups of the streamed pushes beside the resident pieces.  Zero-copy line reads alone
+// saturate the link from 128 workgroups of 256 threads up; the streamed PageRank pushes also
+// wait on their atomic adds and need more, and every workgroup they hold is one the sorting
+// passes lack.  Measured on MI355X, R-MAT 28 under an 8 GB budget, 20 steps: 384 -> 4.74 s,
+// 512 -> 4.25-4.41 s, 640 -> 4.45-4.56 s, 1024 -> 4.48 s, 2048 -> 4.58 s, 4096 -> 4.58 s.
+constexpr uint32_t kPbLinkGrid = 512;
 
 // PageRank's resident adds go through pair buckets (see PB_* in the kernel header) when it
 // runs alone, some partitions are resident, the selection can contain no compaction
@@ -1128,14 +1132,16 @@ constexpr uint32_t kPbLinkGrid = 2048;
 // (coarse bins, then fine bins: n <= 2^28).
 constexpr bool kPbTwoPass = true;
 
-// pr_blocking = 1 (automatic) also asks for at least half of the edges to be resident:
+// pr_blocking = 1 (automatic) also asks for at least 3/8 of the edges to be resident:
 // below that the streamed atomics and the host link bound the iteration, and the sorting
-// passes competing for CUs with the zero-copy kernel cost more than they save.
+// passes competing for CUs with the zero-copy kernel cost more than they save (measured on
+// MI355X: a loss at 25% resident on R-MAT 24, 358 against 315 ms for 20 steps; a gain at
+// 47% on R-MAT 28 under an 8 GB budget, 4.58 against 5.14 s).
 bool pb_eligible(const RunCtx& rc) {
     const hytm_graph* g = rc.g;
     const uint32_t nfine = pb_fine_bins(g->n);
     const uint32_t nres = std::min(rc.plan.nres, g->npart);
-    const bool wanted = g->params.pr_blocking == 2 || (g->params.pr_blocking == 1 && 2 * g->h_off[g->pv[nres]] >= g->m);
+    const bool wanted = g->params.pr_blocking == 2 || (g->params.pr_blocking == 1 && 8 * g->h_off[g->pv[nres]] >= 3 * g->m);
     return rc.algo == HYTM_PAGERANK && !rc.batched && wanted && g->m > 0 && rc.plan.nres > 0 &&
            nfine <= (kPbTwoPass ? PB_MAX_FINE : PB_LOCAL_BINS) && g->max_part_edges < (1ull << 31) &&
            g->n < (1ull << 31) && g->params.mode != HYTM_MODE_COMPACT &&

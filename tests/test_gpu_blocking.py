@@ -123,7 +123,7 @@ def test_many_pieces_match_oracle(rmat20, mode, resident):
 
 @pytest.mark.parametrize("resident,blocked", [(0.25, False), (0.6, True), (None, True)])
 def test_automatic_blocking_follows_resident_share(rmat20, resident, blocked):
-    """Default piece size and pr_blocking = 1: blocking only with at least half of the
+    """Default piece size and pr_blocking = 1: blocking only with at least 3/8 of the
     edges resident."""
     note(f"rmat20 pagerank automatic blocking resident={resident}")
     with hy.Graph(rmat20.off, rmat20.col) as g:
