@@ -328,7 +328,11 @@ hytm_status hytm_set_device_budget(hytm_graph *g, uint64_t edge_bytes);
    (max(combine_k * partition_edges, largest partition) edges); compaction = two chunk
    buffers of compact_chunk_edges edges (default max(slot, 2^22)); times 4 bytes per edge
    array read (two arrays for SSSP).  Hybrid needs both; a forced mode needs its own;
-   zero-copy needs none.  The rest of the budget holds resident partitions.  In hybrid
+   zero-copy needs none.  The rest of the budget holds resident partitions; on a graph with
+   separate weights the rest is taken after the larger of the one- and two-array needs, so
+   that one device region holds either layout (neighbours only; a shorter neighbour prefix
+   and its weights) and a switch between BFS/CC/PageRank and SSSP copies only the part of
+   the region that differs.  In hybrid
    mode an engine whose buffers do not fit is left out of the choice; a forced
    FILTER/COMPACT run whose buffers do not fit fails with E_BUDGET. */
 hytm_status hytm_staging_bytes(const hytm_graph *g, hytm_algo algo, uint64_t *bytes);

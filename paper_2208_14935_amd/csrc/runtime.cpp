@@ -264,7 +264,13 @@ struct hytm_graph {
     // edge-budget buffers
     uint32_t res_parts = 0, res_arrays = 0;
     uint64_t res_edges = 0;
-    bool res_valid = false;
+    bool res_valid = false;            // false: nothing in d_res is known to hold edge data
+    // One region holds the resident cache: the neighbour prefix col[0, res_col) from word 0,
+    // and the weight prefix w[0, res_w) from word res_w_at.  A one-array run keeps col[0, E1)
+    // there; a two-array run col[0, E2) followed by w[0, E2) at word E2, so a switch between
+    // the two copies only the part that differs.  d_res_col / d_res_w are views into it.
+    DevBuf<uint32_t> d_res;
+    uint64_t res_col = 0, res_w = 0, res_w_at = 0;
     DevBuf<uint32_t> d_res_col, d_res_w;
     DevBuf<uint32_t> d_slot_col[kMaxSlots], d_slot_w[kMaxSlots];
     DevBuf<uint32_t> d_cbuf_col[2], d_cbuf_w[2];
@@ -409,6 +415,7 @@ size_t sel_block_bytes(uint32_t npart) { return sel_layout(npart).bytes; }
 struct Plan {
     uint32_t nres = 0;
     uint64_t res_edges = 0;
+    uint64_t res_words = 0;  // words of the resident region under this budget
     uint64_t slot_edges = 0;
     uint32_t nslots = 0;
     uint64_t cchunk = 0;
@@ -432,6 +439,24 @@ Staging staging_of(const hytm_graph* g, uint32_t arrays) {
     return s;
 }
 
+// Edge-budget bytes the engines' buffers take under the handle's mode for staging `sg`
+// (hybrid leaves out an engine whose staging does not fit, as make_plan does).
+uint64_t engine_bytes(const hytm_graph* g, const Staging& sg, uint64_t B) {
+    switch (g->params.mode) {
+    case HYTM_MODE_FILTER:
+        return sg.f_bytes;
+    case HYTM_MODE_COMPACT:
+        return sg.c_bytes;
+    case HYTM_MODE_ZEROCOPY:
+        return 0;
+    default:
+        if (sg.f_bytes + sg.c_bytes <= B) return sg.f_bytes + sg.c_bytes;
+        if (sg.f_bytes <= B) return sg.f_bytes;
+        if (sg.c_bytes <= B) return sg.c_bytes;
+        return 0;
+    }
+}
+
 hytm_status make_plan(const hytm_graph* g, uint32_t arrays, Plan* out) {
     const hytm_params& p = g->params;
     const uint64_t d1 = 4ull * arrays;
@@ -439,6 +464,7 @@ hytm_status make_plan(const hytm_graph* g, uint32_t arrays, Plan* out) {
     if (g->budget == UINT64_MAX) {
         pl.nres = g->npart;
         pl.res_edges = g->m;
+        pl.res_words = arrays * g->m;
         *out = pl;
         return HYTM_OK;
     }
@@ -478,12 +504,21 @@ hytm_status make_plan(const hytm_graph* g, uint32_t arrays, Plan* out) {
             used = sg.c_bytes;
         }
     }
-    const uint64_t res_bytes = B - used;
+    // The resident share is the same for both edge-array counts a graph with separate
+    // weights runs with (the budget less the larger of their staging needs), so that one
+    // region holds either layout and the budget covers both.
+    uint64_t used_res = used;
+    if (g->h_w && g->pk.shift == 32) {
+        const uint64_t u = engine_bytes(g, staging_of(g, 3 - arrays), B);
+        if (u <= B) used_res = std::max(used_res, u);
+    }
+    const uint64_t res_bytes = B - used_res;
     uint32_t nres = 0;
     uint64_t edges = 0;
     while (nres < g->npart && (edges + g->pE[nres]) * d1 <= res_bytes) edges += g->pE[nres++];
     pl.nres = nres;
     pl.res_edges = edges;
+    pl.res_words = res_bytes / 4;
     *out = pl;
     return HYTM_OK;
 }
@@ -513,7 +548,7 @@ void ensure_streams(hytm_graph* g) {
 void release_all(hytm_graph* g) {
     if (g->s_copy) (void)hipDeviceSynchronize();
     for (auto* b : {&g->d_val, &g->d_cur, &g->d_next, &g->d_visited, &g->d_list, &g->d_overflow, &g->d_nA, &g->d_nF,
-                    &g->d_lbase, &g->d_pv, &g->d_res_col, &g->d_res_w})
+                    &g->d_lbase, &g->d_pv, &g->d_res_col, &g->d_res_w, &g->d_res})
         b->release();
     for (auto* b : {&g->d_x, &g->d_contrib, &g->d_acc}) b->release();
     for (auto* b : {&g->d_wpre, &g->d_Ea, &g->d_Rq, &g->d_K, &g->d_wbase, &g->d_off, &g->d_sel_in}) b->release();
@@ -817,23 +852,52 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
         }
     }
 
-    // resident cache: partitions [0, nres) copied once and kept while nres/arrays hold
-    if (pl.nres > 0 && !(g->res_valid && g->res_parts == pl.nres && g->res_arrays >= plan_arrays)) {
-        const double t0 = now_ms();
-        g->d_res_col.ensure(pl.res_edges);
-        HIP_CHECK(hipMemcpyAsync(g->d_res_col.p, g->h_col, pl.res_edges * 4, hipMemcpyHostToDevice, main));
-        tot->fill_bytes += pl.res_edges * 4;
-        if (plan_arrays == 2) {
-            g->d_res_w.ensure(pl.res_edges);
-            HIP_CHECK(hipMemcpyAsync(g->d_res_w.p, g->h_w, pl.res_edges * 4, hipMemcpyHostToDevice, main));
-            tot->fill_bytes += pl.res_edges * 4;
+    // resident cache: partitions [0, nres) in the region, copying only what it lacks
+    if (pl.nres > 0) {
+        const uint64_t E = pl.res_edges;
+        const uint64_t need = plan_arrays == 2 ? 2 * E : E;
+        const uint64_t cap = std::max(need, pl.res_words);
+        if (g->d_res.n < need || g->d_res.n > cap) {  // sized to this budget's region
+            g->d_res_col.release();
+            g->d_res_w.release();
+            g->d_res.release();
+            g->d_res.ensure(cap);
+            g->res_valid = false;
         }
-        HIP_CHECK(hipStreamSynchronize(main));
+        if (!g->res_valid) {
+            g->res_col = g->res_w = g->res_w_at = 0;
+            g->res_valid = true;
+        }
+        const double t0 = now_ms();
+        bool filled = false;
+        if (g->res_col < E) {
+            HIP_CHECK(hipMemcpyAsync(g->d_res.p + g->res_col, g->h_col + g->res_col, (E - g->res_col) * 4,
+                                     hipMemcpyHostToDevice, main));
+            tot->fill_bytes += (E - g->res_col) * 4;
+            if (g->res_w && g->res_w_at < E && g->res_w_at + g->res_w > g->res_col) g->res_w = 0;
+            g->res_col = E;
+            filled = true;
+        }
+        if (plan_arrays == 2 && !(g->res_w >= E && g->res_w_at == E)) {
+            HIP_CHECK(hipMemcpyAsync(g->d_res.p + E, g->h_w, E * 4, hipMemcpyHostToDevice, main));
+            tot->fill_bytes += E * 4;
+            g->res_w = E;
+            g->res_w_at = E;
+            g->res_col = std::min(g->res_col, E);  // the weights took the words past E
+            filled = true;
+        }
+        if (filled) {
+            HIP_CHECK(hipStreamSynchronize(main));
+            tot->fill_ms += now_ms() - t0;
+        }
+        g->d_res_col.view(g->d_res.p, E);
+        if (plan_arrays == 2)
+            g->d_res_w.view(g->d_res.p + E, E);
+        else
+            g->d_res_w.release();
         g->res_parts = pl.nres;
-        g->res_edges = pl.res_edges;
+        g->res_edges = E;
         g->res_arrays = plan_arrays;
-        g->res_valid = true;
-        tot->fill_ms += now_ms() - t0;
     }
     return HYTM_OK;
 }
