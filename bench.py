@@ -356,62 +356,69 @@ def main():
     roofline = None
     kernels = {}
     if kt:
-        nk = len(hy.KERNEL_CLASSES)
-        ms = np.zeros(nk)
-        launches = np.zeros(nk, dtype=np.int64)
-        items = np.zeros(nk, dtype=np.int64)
-        arrays_items = np.zeros(nk)  # items weighted by edge arrays read
-        zc_bytes = 0  # lines the zero-copy kernel really read (a line two lists share counts once)
+        # per (algorithm, kernel class): event ms, launches, items, items x edge arrays, and
+        # the distinct lines the zero-copy kernel read (a line two lists share counts once)
+        per = {}
         for name, r, _ in all_runs:
             a = arrays[name]
-            ms += np.array(r.stats["kernel_ms"])
-            launches += np.array(r.stats["kernel_launches"], dtype=np.int64)
-            it = np.array(r.stats["kernel_items"], dtype=np.int64)
-            items += it
-            arrays_items += it * a
-            zc_bytes += r.stats["zc_lines_distinct"] * 128 * a
-        for c, nm in enumerate(hy.KERNEL_CLASSES):
-            kernels[nm] = {"ms": ms[c] / args.steps, "launches": int(launches[c]) // args.steps,
-                           "items": int(items[c]) // args.steps}
-        dom = int(np.argmax(ms))
-        avg_ms = ms[dom] / max(launches[dom], 1)
-        name = hy.KERNEL_CLASSES[dom]
+            for c, cls in enumerate(hy.KERNEL_CLASSES):
+                nl = r.stats["kernel_launches"][c]
+                if not nl:
+                    continue
+                e = per.setdefault((name, cls), [0.0, 0, 0, 0, 0])
+                e[0] += r.stats["kernel_ms"][c]
+                e[1] += nl
+                e[2] += r.stats["kernel_items"][c]
+                e[3] += r.stats["kernel_items"][c] * a
+                if cls == "push_zerocopy":
+                    e[4] += r.stats["zc_lines_distinct"] * 128 * a
+        for cls in hy.KERNEL_CLASSES:
+            es = [v for (al, c), v in per.items() if c == cls]
+            kernels[cls] = {"ms": sum(v[0] for v in es) / args.steps,
+                            "launches": sum(v[1] for v in es) // args.steps,
+                            "items": sum(v[2] for v in es) // args.steps}
+        (dalgo, name), (d_ms, d_launches, d_items, d_aitems, d_zc) = max(per.items(), key=lambda kv: kv[1][0])
+        avg_ms = d_ms / max(d_launches, 1)
         # algorithmic bytes per launch.  Kernels reading the mapped host arrays are priced
         # against the host link: the zero-copy kernel moves 128 B per distinct line it reads
         # per edge array, the streaming filter kernel 4 B per edge of its tasks per edge array.
         # Kernels reading device memory are priced against HBM: 4 B per edge per array
         # plus one 4-byte vertex value touched per edge.
         if name == "push_zerocopy":
-            per_launch = zc_bytes / max(launches[dom], 1)
+            per_launch = d_zc / max(d_launches, 1)
             bound, peak = "pcie", PCIE_GEN5_X16_GBPS
         elif name == "push_filter" and args.filter_engine == "stream":
-            per_launch = arrays_items[dom] * 4 / max(launches[dom], 1)
+            per_launch = d_aitems * 4 / max(d_launches, 1)
             bound, peak = "pcie", PCIE_GEN5_X16_GBPS
         elif name.startswith("push"):
-            per_launch = (arrays_items[dom] * 4 + items[dom] * 4) / max(launches[dom], 1)
+            per_launch = (d_aitems * 4 + d_items * 4) / max(d_launches, 1)
             bound, peak = "hbm", HBM_PEAK_GBPS
         elif name == "pr_blocking":
             # per pair: each counting-sort pass reads and writes 8 B, the summing pass reads
             # 8 B; per piece: one read-modify-write of every accumulator slot
             passes = 2 if (n + 16383) // 16384 > 1024 else 1
             slots = (n + 4095) // 4096 * 4096
-            per_launch = (items[dom] * (16 * passes + 8) + launches[dom] * 8 * slots) / max(launches[dom], 1)
+            per_launch = (d_items * (16 * passes + 8) + d_launches * 8 * slots) / max(d_launches, 1)
             bound, peak = "hbm", HBM_PEAK_GBPS
         else:
-            per_launch = items[dom] * 16 / max(launches[dom], 1)
+            per_launch = d_items * 16 / max(d_launches, 1)
             bound, peak = "hbm", HBM_PEAK_GBPS
         achieved = per_launch / (avg_ms / 1e3) / 1e9
+        op = {"bfs": "OpBfs", "sssp": "OpSssp", "cc": "OpCc", "pagerank": "OpPr"}[dalgo]
+        symbol = {"push_zerocopy": f"k_push_lines<{op}>", "push_filter": f"k_push_fstream<{op}>",
+                  "push_resident": f"k_push_edges<{op}, false>", "push_compact": f"k_push_edges<{op}, true>",
+                  "stats": "k_stats_select", "lists": "k_build_lists"}.get(name, name)
         traffic = None
         src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2208_14935_amd", "csrc", "kernels.hip")
         with open(src, "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
-        if (name == PMC_TRAFFIC["kernel"] and sha == PMC_TRAFFIC["kernels_sha256"]
+        if (symbol == PMC_TRAFFIC["kernel"] and sha == PMC_TRAFFIC["kernels_sha256"]
                 and workload == PMC_TRAFFIC["workload"]):
             traffic = PMC_TRAFFIC["bytes_per_launch"]
-        roofline = {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak,
-                    "unit": "GB/s", "frac": achieved / peak, "traffic": traffic,
+        roofline = {"kernel": symbol, "algorithm": dalgo, "class": name, "bound": bound, "achieved": achieved,
+                    "peak": peak, "unit": "GB/s", "frac": achieved / peak, "traffic": traffic,
                     "traffic_unit": "bytes per launch (HBM, PMC)", "algorithmic_bytes_per_launch": per_launch,
-                    "avg_launch_ms": avg_ms, "launches_per_step": int(launches[dom]) // args.steps,
+                    "avg_launch_ms": avg_ms, "launches_per_step": d_launches // args.steps,
                     "measured_link_peak_gbps": probe["h2d_copy_gbps"]}
 
     out = {

@@ -1,13 +1,14 @@
 // Device side of the hybrid-transfer traversal, written for gfx950 (wave64).
 //
 // Per iteration (Sec. 4 overview, Algorithm 1):
-//   k_stats_select  one workgroup per partition: active vertices, active edges and
+//   k_stats_select  one wave per partition: active vertices, active edges and
 //                   request lines from the frontier bitmap, then the engine choice of
 //                   Sec. 5.1 (Eq. 1-3, alpha/beta rule) in exact integer arithmetic;
-//   k_scan          one workgroup: per-engine prefix sums over partitions, which place
-//                   every partition's active vertices in one list ordered by engine
-//                   segment and partition ("pre-combine" of Vc and Vz, Algorithm 1);
-//   k_build_lists   one workgroup per scheduled partition: ordered compaction of its
+//   k_scan_*        per-engine prefix sums over partitions (tile totals, tile bases,
+//                   offsets), which place every partition's active vertices in one list
+//                   ordered by engine segment and partition ("pre-combine" of Vc and Vz,
+//                   Algorithm 1);
+//   k_build_lists   one wave per scheduled partition: ordered compaction of its
 //                   active vertices into the list plus the work prefix (edges, or
 //                   128-byte lines for zero-copy) used for load balancing;
 //   k_push_edges    edge-balanced push over a list slice reading device memory
@@ -146,73 +147,90 @@ __device__ __forceinline__ uint8_t select_engine(uint64_t E, uint64_t nA, uint64
 }
 
 // ------------------------------------------------------------------- stats
+// One wave per partition (four per workgroup): lane l takes bitmap words wb + l, wb + l + 64,
+// ... of the partition and its own active vertices in them; wave reductions and a wave
+// prefix maximum (distinct lines) replace the workgroup's barriers, so the many partitions
+// of a large graph (133K at R-MAT 28, ~63 bitmap words each) cost one pass of a wave each,
+// and a 64-word chunk without active vertices costs one ballot.
+constexpr uint32_t SEL_WAVES = 4;  // waves (partitions in flight) per 256-thread workgroup
+
+__device__ __forceinline__ uint64_t wave_max_exclusive(uint64_t x, uint64_t* total) {
+    const uint32_t lane = __lane_id();
+    uint64_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v = v > y ? v : y;
+    }
+    *total = __shfl(v, 63, 64);
+    const uint64_t ex = __shfl_up(v, 1, 64);
+    return lane ? ex : 0;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_exclusive(uint64_t x, uint64_t* total) {
+    const uint32_t lane = __lane_id();
+    uint64_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += y;
+    }
+    *total = __shfl(v, 63, 64);
+    return v - x;
+}
+
 __global__ __launch_bounds__(256) void k_stats_select(uint32_t npart, const uint32_t* __restrict__ pv,
                                                       const uint64_t* __restrict__ off,
                                                       const uint32_t* __restrict__ cur, SelParams sp,
                                                       uint8_t* __restrict__ mode, uint32_t* __restrict__ nA,
                                                       uint32_t* __restrict__ nF, uint64_t* __restrict__ Ea,
                                                       uint64_t* __restrict__ Rq, uint64_t* __restrict__ K) {
-    __shared__ uint64_t red[4], red2[4];
     const uint32_t sh = sp.cost_shift;
-    for (uint32_t i = blockIdx.x; i < npart; i += gridDim.x) {
+    const uint32_t lane = __lane_id();
+    const uint32_t nwaves = gridDim.x * SEL_WAVES;
+    for (uint32_t i = blockIdx.x * SEL_WAVES + (threadIdx.x >> 6); i < npart; i += nwaves) {
         const uint32_t vb = pv[i], ve = pv[i + 1];
         const uint32_t wb = vb >> 5, we = (ve + 31) >> 5;
-        // a partition without active vertices (most of them while the frontier is small)
-        // costs one barrier instead of the reductions below
-        uint32_t any = 0;
-        for (uint32_t wi = wb + threadIdx.x; wi < we; wi += blockDim.x) any |= masked_word(cur, wi, vb, ve);
-        if (!__syncthreads_or(any != 0)) {
-            if (threadIdx.x == 0) {
-                mode[i] = P_NONE;
-                nA[i] = 0;
-                nF[i] = 0;
-                Ea[i] = 0;
-                Rq[i] = 0;
-                K[i] = 0;
-            }
-            continue;
-        }
         uint64_t c = 0, f = 0, ea = 0, rq = 0, kl = 0, rqd = 0;
-        // distinct lines: (line + 1) of the last list before the current 256 words, 0 = none
+        // distinct lines: (line + 1) of the last list before the current 64 words, 0 = none
         uint64_t carry = 0;
-        for (uint32_t base = wb; base < we; base += blockDim.x) {  // uniform across the block
-            const uint32_t wi = base + threadIdx.x;
+        for (uint32_t base = wb; base < we; base += 64) {  // uniform across the wave
+            const uint32_t wi = base + lane;
+            uint32_t bits = wi < we ? masked_word(cur, wi, vb, ve) : 0u;
+            if (__ballot(bits != 0) == 0) continue;
+            f += __popc(bits);
             uint64_t first1 = 0, last1 = 0, dl = 0;  // (line + 1) of the word's first / last list
-            if (wi < we) {
-                uint32_t bits = masked_word(cur, wi, vb, ve);
-                f += __popc(bits);
-                while (bits) {
-                    const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
-                    bits &= bits - 1;
-                    const uint64_t s = off[v], e = off[v + 1];
-                    if (e > s) {
-                        c += 1;
-                        ea += e - s;
-                        rq += lines_of(s, e, sh);
-                        kl += lines_of(s, e, ZC_LINE_SHIFT);
-                        const uint64_t fl = (s >> sh) + 1, ll = ((e - 1) >> sh) + 1;
-                        dl += ll - fl + 1 - (last1 == fl ? 1 : 0);
-                        if (!first1) first1 = fl;
-                        last1 = ll;
-                    }
+            while (bits) {
+                const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
+                bits &= bits - 1;
+                const uint64_t s0 = off[v], e0 = off[v + 1];
+                if (e0 > s0) {
+                    c += 1;
+                    ea += e0 - s0;
+                    rq += lines_of(s0, e0, sh);
+                    kl += lines_of(s0, e0, ZC_LINE_SHIFT);
+                    const uint64_t fl = (s0 >> sh) + 1, ll = ((e0 - 1) >> sh) + 1;
+                    dl += ll - fl + 1 - (last1 == fl ? 1 : 0);
+                    if (!first1) first1 = fl;
+                    last1 = ll;
                 }
             }
             if (sp.rq_distinct) {
                 // a word's first line repeats the last line of the latest earlier list
                 uint64_t tot;
-                const uint64_t ex = block_exclusive_max<256>(last1, red2, &tot);
+                const uint64_t ex = wave_max_exclusive(last1, &tot);
                 const uint64_t prev = carry > ex ? carry : ex;
                 if (first1 && prev == first1) dl -= 1;
                 rqd += dl;
                 carry = carry > tot ? carry : tot;
             }
         }
-        c = block_sum<256>(c, red);
-        f = block_sum<256>(f, red);
-        ea = block_sum<256>(ea, red);
-        rq = block_sum<256>(sp.rq_distinct ? rqd : rq, red) * sp.arrays;
-        kl = block_sum<256>(kl, red);
-        if (threadIdx.x == 0) {
+        c = wave_sum(c);
+        f = wave_sum(f);
+        ea = wave_sum(ea);
+        rq = wave_sum(sp.rq_distinct ? rqd : rq) * sp.arrays;
+        kl = wave_sum(kl);
+        if (lane == 0) {
             const uint64_t E = off[ve] - off[vb];
             uint8_t p;
             if (ea == 0)
@@ -408,44 +426,47 @@ __global__ __launch_bounds__(256) void k_build_lists(uint32_t npart, const uint3
                                                      const uint32_t* __restrict__ lbase,
                                                      const uint64_t* __restrict__ wbase,
                                                      uint32_t* __restrict__ list, uint64_t* __restrict__ wpre) {
-    __shared__ uint64_t lds[4];
-    for (uint32_t i = blockIdx.x; i < npart; i += gridDim.x) {
+    // one wave per scheduled partition; lane l takes bitmap words base + l of each 64-word
+    // chunk, so list order (chunks in order, lanes in order, bits in order) is vertex order
+    const uint32_t lane = __lane_id();
+    const uint32_t nwaves = gridDim.x * SEL_WAVES;
+    for (uint32_t i = blockIdx.x * SEL_WAVES + (threadIdx.x >> 6); i < npart; i += nwaves) {
         const uint8_t m = mode[i];
         if (m == P_NONE) continue;
         const bool by_lines = m == P_ZC;
         const uint32_t vb = pv[i], ve = pv[i + 1];
         const uint32_t wb = vb >> 5, we = (ve + 31) >> 5;
-        const uint32_t per = (we - wb + blockDim.x - 1) / blockDim.x;
-        const uint32_t w0 = min(wb + threadIdx.x * per, we), w1 = min(w0 + per, we);
-        uint64_t c = 0, wk = 0;
-        for (uint32_t wi = w0; wi < w1; wi++) {
-            uint32_t bits = masked_word(cur, wi, vb, ve);
-            while (bits) {
+        uint64_t pos = lbase[i], wp = wbase[i];  // the chunk's first list entry and work item
+        for (uint32_t base = wb; base < we; base += 64) {  // uniform across the wave
+            const uint32_t wi = base + lane;
+            const uint32_t word = wi < we ? masked_word(cur, wi, vb, ve) : 0u;
+            if (__ballot(word != 0) == 0) continue;
+            uint64_t c = 0, wk = 0;
+            for (uint32_t bits = word; bits;) {
                 const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
                 bits &= bits - 1;
-                const uint64_t s = off[v], e = off[v + 1];
-                if (e > s) {
+                const uint64_t s0 = off[v], e0 = off[v + 1];
+                if (e0 > s0) {
                     c += 1;
-                    wk += by_lines ? lines_of(s, e, ZC_LINE_SHIFT) : e - s;
+                    wk += by_lines ? lines_of(s0, e0, ZC_LINE_SHIFT) : e0 - s0;
                 }
             }
-        }
-        uint64_t tc, tw;
-        uint64_t pos = lbase[i] + block_exclusive_scan<256>(c, lds, &tc);
-        uint64_t wp = wbase[i] + block_exclusive_scan<256>(wk, lds, &tw);
-        for (uint32_t wi = w0; wi < w1; wi++) {
-            uint32_t bits = masked_word(cur, wi, vb, ve);
-            while (bits) {
+            uint64_t tc, tw;
+            uint64_t p = pos + wave_sum_exclusive(c, &tc);
+            uint64_t w = wp + wave_sum_exclusive(wk, &tw);
+            for (uint32_t bits = word; bits;) {
                 const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
                 bits &= bits - 1;
-                const uint64_t s = off[v], e = off[v + 1];
-                if (e > s) {
-                    list[pos] = v;
-                    wpre[pos] = wp;
-                    pos++;
-                    wp += by_lines ? lines_of(s, e, ZC_LINE_SHIFT) : e - s;
+                const uint64_t s0 = off[v], e0 = off[v + 1];
+                if (e0 > s0) {
+                    list[p] = v;
+                    wpre[p] = w;
+                    p++;
+                    w += by_lines ? lines_of(s0, e0, ZC_LINE_SHIFT) : e0 - s0;
                 }
             }
+            pos += tc;
+            wp += tw;
         }
     }
 }
@@ -2102,8 +2123,9 @@ hipError_t launch_stats_select(uint32_t npart, const uint32_t* pv, const uint64_
                                const SelParams& sp, uint8_t* mode, uint32_t* nA, uint32_t* nF, uint64_t* Ea,
                                uint64_t* Rq, uint64_t* K, hipStream_t st) {
     if (!npart) return hipSuccess;
-    k_stats_select<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, sp, mode, nA, nF, Ea,
-                                                                         Rq, K);
+    const uint32_t wgs = (npart + SEL_WAVES - 1) / SEL_WAVES;
+    k_stats_select<<<wgs < GRID_CAP ? wgs : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, sp, mode, nA, nF, Ea, Rq,
+                                                                     K);
     return hipGetLastError();
 }
 
@@ -2123,8 +2145,9 @@ hipError_t launch_build_lists(uint32_t npart, const uint32_t* pv, const uint64_t
                               const uint8_t* mode, const uint32_t* lbase, const uint64_t* wbase, uint32_t* list,
                               uint64_t* wpre, hipStream_t st) {
     if (!npart) return hipSuccess;
-    k_build_lists<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, mode, lbase, wbase,
-                                                                        list, wpre);
+    const uint32_t wgs = (npart + SEL_WAVES - 1) / SEL_WAVES;
+    k_build_lists<<<wgs < GRID_CAP ? wgs : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, mode, lbase, wbase, list,
+                                                                    wpre);
     return hipGetLastError();
 }
 
