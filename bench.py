@@ -14,14 +14,23 @@ dominant kernel's roofline from live HIP-event timings, and the single-threaded 
 oracle's rate on a bounded sample of the same workload (run before any GPU call, on one
 core the process pins its thread to).
 """
-import argparse
-import hashlib
-import json
 import os
-import sys
-import time
 
-import numpy as np
+# The engine issues each pass's work on six HIP streams (selection, resident pushes, zero-copy,
+# streaming filter, compaction copies, PageRank pair sorting).  HIP maps streams onto
+# GPU_MAX_HW_QUEUES hardware queues (4 by default), and two streams that share a queue run
+# their kernels one after the other.  The benchmark gives each stream its own queue (at least
+# 8 queues, also where the environment sets fewer); it must be set before the process makes
+# its first HIP call.
+os.environ["GPU_MAX_HW_QUEUES"] = str(max(8, int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4)))
+
+import argparse  # noqa: E402
+import hashlib  # noqa: E402
+import json  # noqa: E402
+import sys  # noqa: E402
+import time  # noqa: E402
+
+import numpy as np  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -117,9 +126,10 @@ def main():
                     help="zero-copy requests of the cost model as Eq. 3's per-vertex lines (default: the distinct "
                          "lines the zero-copy kernel actually reads)")
     ap.add_argument("--rq-distinct", dest="rq_distinct", action="store_true")
-    ap.add_argument("--zc-tie", default="probe",
-                    help="where a Tiz = Tef tie goes: 'probe' (zero-copy when full-line zero-copy reads reach 95%% of "
-                         "the measured copy rate), 'filter' (the paper) or 'zerocopy'")
+    ap.add_argument("--zc-tie", default="auto",
+                    help="where a Tiz = Tef tie goes: 'auto' (zero-copy for PageRank without propagation blocking, "
+                         "filter otherwise), 'filter' (the paper), 'zerocopy', or 'probe' (zero-copy when full-line "
+                         "zero-copy reads reach 95%% of the measured copy rate)")
     ap.add_argument("--sssp-delta", type=int, default=0,
                     help="SSSP far set: bound step (0 = the paper's synchronous push)")
     ap.add_argument("--pr-blocking", type=int, default=1, choices=[0, 1, 2],
@@ -205,7 +215,7 @@ def main():
         cgather = (int(a), int(b_))
     log(f"compaction gather cost = {cgather[0]}/{cgather[1]}")
     # a tie means equal bytes by either engine; rates within 5% of each other count as equal
-    zc_tie = {"filter": 0, "zerocopy": 1}.get(args.zc_tie,
+    zc_tie = {"filter": 0, "zerocopy": 1, "auto": 2}.get(args.zc_tie,
                                               int(probe["zc_read_gbps"]["128B"] >= 0.95 * probe["h2d_copy_gbps"]))
     log(f"tie to zero-copy = {zc_tie}")
 
@@ -351,7 +361,7 @@ def main():
                 + (f"-reprocess{args.reprocess}" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
                 + ("" if packed else "-unpacked")
                 + ("" if cgather[0] == 0 else "-gathercost") + ("-rqdistinct" if args.rq_distinct else "")
-                + ("-zctie" if zc_tie else "") + ("-prblock" if args.pr_blocking == 2 and "pagerank" in algos else "")
+                + {0: "", 1: "-zctie", 2: "-autotie"}[zc_tie] + ("-prblock" if args.pr_blocking == 2 and "pagerank" in algos else "")
                 + (f"-delta{args.sssp_delta}" if args.sssp_delta and "sssp" in algos else ""))
     roofline = None
     kernels = {}
@@ -441,7 +451,8 @@ def main():
                    "budget_frac_of_edge_bytes": None if args.budget_bytes else args.budget_frac,
                    "partition_edges": args.partition_edges, "combine_k": args.combine_k, "mode": args.mode,
                    "filter_engine": args.filter_engine, "gamma": list(gamma), "algos": algos,
-                   "compact_gather": list(cgather)},
+                   "compact_gather": list(cgather), "zc_tie": zc_tie,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "host_link": host_link,

@@ -145,7 +145,13 @@ typedef struct {
     uint32_t zc_tie;            /* 0: a Tiz = Tef tie selects filter, as the paper's prose says.  1: it
                                    selects zero-copy -- for hosts where full-line zero-copy reads run
                                    at the copy engine's rate (hytm_link_probe), so equal bytes cost
-                                   equal time and zero-copy skips the whole-partition pass. */
+                                   equal time and zero-copy skips the whole-partition pass.  2:
+                                   automatic -- zero-copy for HYTM_PAGERANK runs without propagation
+                                   blocking (their pushes fill the GPU, where zero-copy's passes are
+                                   the faster), filter otherwise (a blocked run's streamed pushes get a
+                                   limited grid, in which the streaming filter reads faster; for BFS,
+                                   SSSP and CC ties to filter measured as fast or faster).
+                                   hytm_select_engines treats 2 as 0. */
     uint32_t pr_blocking;       /* Propagation blocking of HYTM_PAGERANK's adds over resident partitions:
                                    their pushes write one contribution per edge, and each run of resident
                                    partitions with at most max(n, 2^20) edges has its (destination,
@@ -326,7 +332,7 @@ hytm_status hytm_set_device_budget(hytm_graph *g, uint64_t edge_bytes);
 /* Bytes of the budget that the engines' buffers take for `algo` under the current
    parameters: filter = `streams` staging slots, each holding the largest combined task
    (max(combine_k * partition_edges, largest partition) edges); compaction = two chunk
-   buffers of compact_chunk_edges edges (default max(slot, 2^22)); times 4 bytes per edge
+   buffers of compact_chunk_edges edges (default max(slot, 2^20)); times 4 bytes per edge
    array read (two arrays for SSSP).  Hybrid needs both; a forced mode needs its own;
    zero-copy needs none.  The rest of the budget holds resident partitions; on a graph with
    separate weights the rest is taken after the larger of the one- and two-array needs, so

@@ -283,7 +283,9 @@ struct FTask {
     uint32_t ja, jb;
     uint64_t chunk0;
 };
-constexpr uint32_t FSTREAM_LINES = 64;
+// 48 lines keep a chunk's staging at ~15 KB of LDS, so LDS does not cap the kernel below
+// 8 workgroups of 256 threads per CU (64 lines needed 20 KB: 7 workgroups)
+constexpr uint32_t FSTREAM_LINES = 48;
 inline uint64_t fstream_chunks(uint64_t e0, uint64_t e1) {
     const uint64_t lines = ((e1 - 1) >> ZC_LINE_SHIFT) - (e0 >> ZC_LINE_SHIFT) + 1;
     return (lines + FSTREAM_LINES - 1) / FSTREAM_LINES;

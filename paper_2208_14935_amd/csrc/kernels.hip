@@ -1883,9 +1883,10 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
                                                                const uint64_t* __restrict__ off,
                                                                const uint32_t* __restrict__ col,
                                                                const uint32_t* __restrict__ w, Op op, Pack pk) {
-    constexpr uint32_t MAXE = FSTREAM_LINES * 32;  // edges per chunk (2048)
+    constexpr uint32_t MAXE = FSTREAM_LINES * 32;  // edges per chunk (1536)
     constexpr int UNROLL = FSTREAM_LINES / LINE_HALVES;
     static_assert(MAXE <= 8 * LINE_THREADS, "owner map prefix covers 8 entries per thread");
+    static_assert(FSTREAM_LINES % LINE_HALVES == 0, "whole lines per half wave");
     __shared__ uint16_t s_owner[MAXE];  // chunk position -> staged vertex
     __shared__ uint16_t s_s[MAXE];      // staged vertex range, relative to the chunk start
     __shared__ uint16_t s_e[MAXE];

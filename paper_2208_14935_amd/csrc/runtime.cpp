@@ -320,7 +320,7 @@ bool params_valid(const hytm_params& p, std::string* why) {
     if (!(p.pr_damping >= 0.0 && p.pr_damping <= 1.0)) return bad("pr_damping must be in [0, 1]");
     if (p.reprocess > 2) return bad("reprocess must be 0, 1 or 2");
     if (p.rq_distinct_lines > 1) return bad("rq_distinct_lines must be 0 or 1");
-    if (p.zc_tie > 1) return bad("zc_tie must be 0 or 1");
+    if (p.zc_tie > 2) return bad("zc_tie must be 0, 1 or 2");
     if (p.pr_blocking > 2) return bad("pr_blocking must be 0, 1 or 2");
     if (p.pr_block_pairs >= (1ull << 31)) return bad("pr_block_pairs must be below 2^31");
     if (!frac_ok(p.compact_gather_num, p.compact_gather_den, false))
@@ -391,7 +391,7 @@ SelParams make_sel(const hytm_graph* g, uint32_t arrays) {
     sp.gn_c = p.compact_gather_num;
     sp.gd_c = p.compact_gather_den;
     sp.rq_distinct = p.rq_distinct_lines;
-    sp.zc_tie = p.zc_tie;
+    sp.zc_tie = p.zc_tie == 1 ? 1u : 0u;  // 2 (automatic) is resolved per run, see resolve_tie
     return sp;
 }
 
@@ -432,7 +432,9 @@ Staging staging_of(const hytm_graph* g, uint32_t arrays) {
     const uint64_t d1 = 4ull * arrays;
     Staging s;
     s.slot_edges = std::max<uint64_t>((uint64_t)p.combine_k * p.partition_edges, g->max_part_edges);
-    s.cchunk = p.compact_chunk_edges ? p.compact_chunk_edges : std::max<uint64_t>(s.slot_edges, 1ull << 22);
+    // two chunk buffers of 2^20 edges: 8 MB per edge array, which a 263 MB budget (R-MAT 24 at
+    // 25%) would otherwise hold as resident edges (4x that cost 2% of the budget's edges)
+    s.cchunk = p.compact_chunk_edges ? p.compact_chunk_edges : std::max<uint64_t>(s.slot_edges, 1ull << 20);
     // the streaming filter engine reads host memory directly and stages nothing
     s.f_bytes = p.filter_engine == HYTM_FILTER_COPY ? s.slot_edges * p.streams * d1 : 0;
     s.c_bytes = 2 * s.cchunk * d1;
@@ -900,6 +902,20 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
         g->res_arrays = plan_arrays;
     }
     return HYTM_OK;
+}
+
+// The Tiz = Tef tie rule of a run.  zc_tie = 2 (automatic): zero-copy for PageRank without
+// propagation blocking, filter otherwise.  Measured on MI355X, where a tie means that the
+// two engines read the same lines: blocked PageRank's streamed pushes run from a 512-workgroup
+// grid, in which the streaming filter (a chunk's loads issued before its vertices are
+// located, each line read once) moves them faster than zero-copy's per-list passes (R-MAT 28
+// at 8 GB: 3.82 s against 4.21 s); without blocking PageRank's pushes fill the GPU and zero-copy
+// is the faster (R-MAT 24 at 25%: 313 against 340 ms).  Ties to filter are as fast or faster
+// for BFS, SSSP and CC on both graphs.
+uint32_t resolve_tie(const hytm_graph* g, int algo, bool pb_on) {
+    const uint32_t t = g->params.zc_tie;
+    if (t != 2) return t;
+    return algo == HYTM_PAGERANK && !pb_on ? 1u : 0u;
 }
 
 // Engine choice inputs of a traversal under a plan made by prepare_graph.
@@ -1687,6 +1703,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     HIP_CHECK(launch_fill_u32((uint32_t*)g->d_zcl.p, 2, 0u, main));
     init_ctx(rc, g, algo, batched, pl, stats);
     rc.pb_on = pb_eligible(rc);
+    rc.sp.zc_tie = resolve_tie(g, algo, rc.pb_on);
 
     const uint64_t n = g->n;
     const uint32_t nwords = rc.nwords;

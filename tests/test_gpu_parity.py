@@ -167,7 +167,8 @@ def test_hybrid_uses_several_engines_and_moves_fewer_bytes_than_filter(rmat16):
 # --------------------------------------------------- selection parity
 @pytest.mark.parametrize("pe,distinct,gamma,tie", [(4096, False, (5, 8), 0), (4096, True, (5, 8), 0),
                                                   (1 << 18, True, (1, 1), 0), (1 << 18, False, (1, 1), 0),
-                                                  (4096, True, (1, 1), 1), (1 << 18, True, (1, 1), 1)])
+                                                  (4096, True, (1, 1), 1), (1 << 18, True, (1, 1), 1),
+                                                  (4096, True, (1, 1), 2)])
 def test_bfs_engine_trace_matches_oracle_selection(rmat16, pe, distinct, gamma, tie):
     """BFS frontiers are unique (level t), so the per-iteration engine vector is pinned --
     with Eq. 3's per-vertex requests or with distinct lines (partitions of 2^18 edges span
@@ -186,8 +187,34 @@ def test_bfs_engine_trace_matches_oracle_selection(rmat16, pe, distinct, gamma, 
     assert res.mode_trace.shape == (it, len(E))
     for t in range(it):
         nA, Ea, Rq = oracle.partition_stats(bounds, rmat16.off, lvl == t, arrays=1, distinct=distinct)
-        want = oracle.select(E, nA, Ea, Rq, nres=nres, params=oracle.CostParams(gamma=gamma, zc_tie=tie))
+        # the automatic tie rule (2) gives ties to filter outside unblocked PageRank
+        want = oracle.select(E, nA, Ea, Rq, nres=nres, params=oracle.CostParams(gamma=gamma, zc_tie=tie % 2))
         np.testing.assert_array_equal(res.mode_trace[t], want, err_msg=f"iteration {t}")
+
+
+@pytest.mark.parametrize("blocking,tie", [(0, 2), (2, 2), (0, 0), (2, 1)])
+def test_pagerank_engine_trace_follows_the_tie_rule(rmat16, blocking, tie):
+    """PageRank's partitions are all active, so with 4096-edge partitions (16 KB, one
+    32 KB unit) Tef = Tiz for most of them and the tie rule decides: the automatic rule (2)
+    sends ties to zero-copy without propagation blocking and to filter with it."""
+    note(f"rmat16 pagerank engine trace blocking={blocking} tie={tie}")
+    with rmat16.graph("pagerank") as g:
+        g.set_params(partition_edges=4096, rq_distinct_lines=1, gamma=(1, 1), zc_tie=tie, pr_blocking=blocking)
+        g.set_resident_fraction("pagerank", 0.5)
+        res = g.run("pagerank", trace=True, stats=True, time_kernels=True)
+        check(rmat16, "pagerank", res)
+        bounds = g.partition_bounds()
+        nres = res.stats["nres"]
+    blocked = res.stats["kernel_launches"][hy.KERNEL_CLASSES.index("pr_blocking")] > 0
+    assert blocked == (blocking == 2)
+    eff = {0: 0, 1: 1, 2: 0 if blocked else 1}[tie]
+    E = np.diff(rmat16.off[bounds.astype(np.int64)])
+    nA, Ea, Rq = oracle.partition_stats(bounds, rmat16.off, np.ones(len(rmat16.off) - 1, bool), arrays=1,
+                                        distinct=True)
+    want = oracle.select(E, nA, Ea, Rq, nres=nres, params=oracle.CostParams(gamma=(1, 1), zc_tie=eff))
+    other = oracle.select(E, nA, Ea, Rq, nres=nres, params=oracle.CostParams(gamma=(1, 1), zc_tie=1 - eff))
+    assert (want != other).sum() > 10  # the case really has ties
+    np.testing.assert_array_equal(res.mode_trace[0], want)
 
 
 @settings(max_examples=30, deadline=None, suppress_health_check=list(HealthCheck))
