@@ -88,7 +88,8 @@ struct AlgoState {
     uint32_t* visited;    // BFS: discovered-vertex bitmap
     uint32_t* next;       // next-frontier bitmap
     uint32_t* overflow;   // SSSP: lane bits raised when a candidate distance reaches 2^32-1 (it is skipped)
-    float* acc;           // PageRank accumulators: ACC_COPIES x acc_slots(n) floats
+    float* acc;           // PageRank accumulators: acc_copies (+ 1 with blocking) x acc_slots(n) floats
+    uint32_t acc_copies;  // PageRank: copies the atomic adds spread over (a power of two, <= ACC_COPIES)
     const float* contrib; // PageRank x[u] / D_o(u)
     uint32_t level_next;  // BFS: level given to vertices discovered this iteration
     uint64_t n;           // vertices
@@ -108,9 +109,15 @@ struct AlgoState {
     uint32_t bound;       // SSSP: distances below it join the next frontier; 0xFFFFFFFF = no bound
 };
 
-// PageRank keeps one accumulator copy per XCD for its atomic adds, plus one for the sums
-// of propagation blocking; the apply step sums them.
+// PageRank spreads its atomic adds over up to one accumulator copy per XCD (the die id,
+// masked to the copies in use), plus one copy after them for the sums of propagation
+// blocking; the apply step sums them.  Copies relieve contention on hub slots, which only
+// adds at HBM speed create: a run with blocking (whose atomic adds come from the host link)
+// uses one, other runs four.  Measured on MI355X: R-MAT 28 at 8 GB with blocking, 20 steps:
+// 3.72 s with one copy, 3.77-3.79 s with eight; R-MAT 24 at 25% without blocking: 410 ms with
+// one, 311 ms with two, four or eight.
 constexpr uint32_t ACC_COPIES = 8;
+inline uint32_t pr_acc_copies(bool blocked) { return blocked ? 1u : 4u; }
 
 // Propagation blocking of PageRank's adds over resident edges.  Random float atomics run
 // at a fixed rate (about 20 G/s on MI355X whatever the footprint): above what the host
@@ -305,8 +312,8 @@ __host__ __device__ inline uint32_t acc_slot(uint32_t v) {
 }
 __host__ __device__ inline uint64_t acc_slots(uint64_t n) { return (n + 4095) & ~uint64_t(4095); }
 
-// contrib = x / D_o and the first `copies` accumulator copies zeroed (ACC_COPIES, or
-// ACC_COPIES + 1 with propagation blocking).
+// contrib = x / D_o and the first `copies` accumulator copies zeroed (acc_copies, or
+// acc_copies + 1 with propagation blocking).
 hipError_t launch_pr_prepare(uint64_t n, const uint64_t* off, const float* x, float* contrib, float* acc,
                              uint32_t copies, hipStream_t st);
 // x = base + damping * (sum of the first `copies` accumulator copies); with inv_n, the
@@ -324,8 +331,8 @@ hipError_t launch_loaded_frontier(uint32_t npart, const uint32_t* pv, const uint
 // psum[p] = the partition's delta sum (FP64).  activate: in every partition with
 // sched[p] != 0, each vertex with delta > 0 moves delta into x, shares damping * delta /
 // D_o(v) as its contribution and joins the frontier cur (cleared first).
-hipError_t launch_dpr_fold(uint32_t npart, const uint32_t* pv, uint64_t n, float* acc, float* delta, double* psum,
-                           hipStream_t st);
+hipError_t launch_dpr_fold(uint32_t npart, const uint32_t* pv, uint64_t n, float* acc, uint32_t copies, float* delta,
+                           double* psum, hipStream_t st);
 hipError_t launch_dpr_activate(uint32_t npart, const uint32_t* pv, const uint64_t* off, const uint8_t* sched,
                                float* delta, float* x, float* contrib, uint32_t* cur, uint32_t nwords, float damping,
                                hipStream_t st);

@@ -1,14 +1,14 @@
 // Device side of the hybrid-transfer traversal, written for gfx950 (wave64).
 //
 // Per iteration (Sec. 4 overview, Algorithm 1):
-//   k_stats_select  one wave per partition: active vertices, active edges and
+//   k_stats_select  one workgroup per partition: active vertices, active edges and
 //                   request lines from the frontier bitmap, then the engine choice of
 //                   Sec. 5.1 (Eq. 1-3, alpha/beta rule) in exact integer arithmetic;
 //   k_scan_*        per-engine prefix sums over partitions (tile totals, tile bases,
 //                   offsets), which place every partition's active vertices in one list
 //                   ordered by engine segment and partition ("pre-combine" of Vc and Vz,
 //                   Algorithm 1);
-//   k_build_lists   one wave per scheduled partition: ordered compaction of its
+//   k_build_lists   one workgroup per scheduled partition: ordered compaction of its
 //                   active vertices into the list plus the work prefix (edges, or
 //                   128-byte lines for zero-copy) used for load balancing;
 //   k_push_edges    edge-balanced push over a list slice reading device memory
@@ -147,90 +147,88 @@ __device__ __forceinline__ uint8_t select_engine(uint64_t E, uint64_t nA, uint64
 }
 
 // ------------------------------------------------------------------- stats
-// One wave per partition (four per workgroup): lane l takes bitmap words wb + l, wb + l + 64,
-// ... of the partition and its own active vertices in them; wave reductions and a wave
-// prefix maximum (distinct lines) replace the workgroup's barriers, so the many partitions
-// of a large graph (133K at R-MAT 28, ~63 bitmap words each) cost one pass of a wave each,
-// and a 64-word chunk without active vertices costs one ballot.
-constexpr uint32_t SEL_WAVES = 4;  // waves (partitions in flight) per 256-thread workgroup
-
-__device__ __forceinline__ uint64_t wave_max_exclusive(uint64_t x, uint64_t* total) {
-    const uint32_t lane = __lane_id();
-    uint64_t v = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t y = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v = v > y ? v : y;
-    }
-    *total = __shfl(v, 63, 64);
-    const uint64_t ex = __shfl_up(v, 1, 64);
-    return lane ? ex : 0;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_exclusive(uint64_t x, uint64_t* total) {
-    const uint32_t lane = __lane_id();
-    uint64_t v = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t y = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += y;
-    }
-    *total = __shfl(v, 63, 64);
-    return v - x;
-}
-
 __global__ __launch_bounds__(256) void k_stats_select(uint32_t npart, const uint32_t* __restrict__ pv,
                                                       const uint64_t* __restrict__ off,
                                                       const uint32_t* __restrict__ cur, SelParams sp,
                                                       uint8_t* __restrict__ mode, uint32_t* __restrict__ nA,
                                                       uint32_t* __restrict__ nF, uint64_t* __restrict__ Ea,
                                                       uint64_t* __restrict__ Rq, uint64_t* __restrict__ K) {
+    __shared__ uint64_t red[4], red2[4];
     const uint32_t sh = sp.cost_shift;
-    const uint32_t lane = __lane_id();
-    const uint32_t nwaves = gridDim.x * SEL_WAVES;
-    for (uint32_t i = blockIdx.x * SEL_WAVES + (threadIdx.x >> 6); i < npart; i += nwaves) {
+    for (uint32_t i = blockIdx.x; i < npart; i += gridDim.x) {
         const uint32_t vb = pv[i], ve = pv[i + 1];
         const uint32_t wb = vb >> 5, we = (ve + 31) >> 5;
+        // a partition without active vertices (most of them while the frontier is small)
+        // costs one barrier instead of the reductions below
+        uint32_t any = 0;
+        for (uint32_t wi = wb + threadIdx.x; wi < we; wi += blockDim.x) any |= masked_word(cur, wi, vb, ve);
+        if (!__syncthreads_or(any != 0)) {
+            if (threadIdx.x == 0) {
+                mode[i] = P_NONE;
+                nA[i] = 0;
+                nF[i] = 0;
+                Ea[i] = 0;
+                Rq[i] = 0;
+                K[i] = 0;
+            }
+            continue;
+        }
         uint64_t c = 0, f = 0, ea = 0, rq = 0, kl = 0, rqd = 0;
-        // distinct lines: (line + 1) of the last list before the current 64 words, 0 = none
+        // distinct lines: (line + 1) of the last list before the current 256 words, 0 = none
         uint64_t carry = 0;
-        for (uint32_t base = wb; base < we; base += 64) {  // uniform across the wave
-            const uint32_t wi = base + lane;
-            uint32_t bits = wi < we ? masked_word(cur, wi, vb, ve) : 0u;
-            if (__ballot(bits != 0) == 0) continue;
-            f += __popc(bits);
+        for (uint32_t base = wb; base < we; base += blockDim.x) {  // uniform across the block
+            const uint32_t wi = base + threadIdx.x;
             uint64_t first1 = 0, last1 = 0, dl = 0;  // (line + 1) of the word's first / last list
-            while (bits) {
-                const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
-                bits &= bits - 1;
-                const uint64_t s0 = off[v], e0 = off[v + 1];
-                if (e0 > s0) {
-                    c += 1;
-                    ea += e0 - s0;
-                    rq += lines_of(s0, e0, sh);
-                    kl += lines_of(s0, e0, ZC_LINE_SHIFT);
-                    const uint64_t fl = (s0 >> sh) + 1, ll = ((e0 - 1) >> sh) + 1;
-                    dl += ll - fl + 1 - (last1 == fl ? 1 : 0);
-                    if (!first1) first1 = fl;
-                    last1 = ll;
+            if (wi < we) {
+                uint32_t bits = masked_word(cur, wi, vb, ve);
+                f += __popc(bits);
+                // the offsets of up to four active vertices are loaded together, so a dense
+                // word waits for 8 rounds of gathers instead of 32
+                while (bits) {
+                    uint64_t ss[4], ee[4];
+                    uint32_t nb = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        if (bits) {
+                            const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
+                            bits &= bits - 1;
+                            ss[q] = off[v];
+                            ee[q] = off[v + 1];
+                            nb = q + 1;
+                        }
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        if (q >= (int)nb) break;
+                        const uint64_t s = ss[q], e = ee[q];
+                        if (e > s) {
+                            c += 1;
+                            ea += e - s;
+                            rq += lines_of(s, e, sh);
+                            kl += lines_of(s, e, ZC_LINE_SHIFT);
+                            const uint64_t fl = (s >> sh) + 1, ll = ((e - 1) >> sh) + 1;
+                            dl += ll - fl + 1 - (last1 == fl ? 1 : 0);
+                            if (!first1) first1 = fl;
+                            last1 = ll;
+                        }
+                    }
                 }
             }
             if (sp.rq_distinct) {
                 // a word's first line repeats the last line of the latest earlier list
                 uint64_t tot;
-                const uint64_t ex = wave_max_exclusive(last1, &tot);
+                const uint64_t ex = block_exclusive_max<256>(last1, red2, &tot);
                 const uint64_t prev = carry > ex ? carry : ex;
                 if (first1 && prev == first1) dl -= 1;
                 rqd += dl;
                 carry = carry > tot ? carry : tot;
             }
         }
-        c = wave_sum(c);
-        f = wave_sum(f);
-        ea = wave_sum(ea);
-        rq = wave_sum(sp.rq_distinct ? rqd : rq) * sp.arrays;
-        kl = wave_sum(kl);
-        if (lane == 0) {
+        c = block_sum<256>(c, red);
+        f = block_sum<256>(f, red);
+        ea = block_sum<256>(ea, red);
+        rq = block_sum<256>(sp.rq_distinct ? rqd : rq, red) * sp.arrays;
+        kl = block_sum<256>(kl, red);
+        if (threadIdx.x == 0) {
             const uint64_t E = off[ve] - off[vb];
             uint8_t p;
             if (ea == 0)
@@ -288,7 +286,7 @@ __device__ __forceinline__ void scan_run_sums(uint32_t i0, uint32_t i1, const ui
 #pragma unroll
     for (int k = 0; k < NV; k++) val[k] = 0;
     for (uint32_t i = i0; i < i1; i++) {
-        if (NV == SCAN_NV) val[SCAN_NV - 1] += nF[i];
+        if constexpr (NV == SCAN_NV) val[SCAN_NV - 1] += nF[i];
         const uint8_t m = mode[i];
         if (m == P_NONE) continue;
         const uint64_t ea = Ea[i], w = (m == P_ZC) ? K[i] : ea, na = nA[i];
@@ -426,47 +424,65 @@ __global__ __launch_bounds__(256) void k_build_lists(uint32_t npart, const uint3
                                                      const uint32_t* __restrict__ lbase,
                                                      const uint64_t* __restrict__ wbase,
                                                      uint32_t* __restrict__ list, uint64_t* __restrict__ wpre) {
-    // one wave per scheduled partition; lane l takes bitmap words base + l of each 64-word
-    // chunk, so list order (chunks in order, lanes in order, bits in order) is vertex order
-    const uint32_t lane = __lane_id();
-    const uint32_t nwaves = gridDim.x * SEL_WAVES;
-    for (uint32_t i = blockIdx.x * SEL_WAVES + (threadIdx.x >> 6); i < npart; i += nwaves) {
+    __shared__ uint64_t lds[4];
+    for (uint32_t i = blockIdx.x; i < npart; i += gridDim.x) {
         const uint8_t m = mode[i];
         if (m == P_NONE) continue;
         const bool by_lines = m == P_ZC;
         const uint32_t vb = pv[i], ve = pv[i + 1];
         const uint32_t wb = vb >> 5, we = (ve + 31) >> 5;
-        uint64_t pos = lbase[i], wp = wbase[i];  // the chunk's first list entry and work item
-        for (uint32_t base = wb; base < we; base += 64) {  // uniform across the wave
-            const uint32_t wi = base + lane;
-            const uint32_t word = wi < we ? masked_word(cur, wi, vb, ve) : 0u;
-            if (__ballot(word != 0) == 0) continue;
-            uint64_t c = 0, wk = 0;
-            for (uint32_t bits = word; bits;) {
-                const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
-                bits &= bits - 1;
-                const uint64_t s0 = off[v], e0 = off[v + 1];
-                if (e0 > s0) {
-                    c += 1;
-                    wk += by_lines ? lines_of(s0, e0, ZC_LINE_SHIFT) : e0 - s0;
-                }
+        const uint32_t per = (we - wb + blockDim.x - 1) / blockDim.x;
+        const uint32_t w0 = min(wb + threadIdx.x * per, we), w1 = min(w0 + per, we);
+        uint64_t c = 0, wk = 0;
+        for (uint32_t wi = w0; wi < w1; wi++) {
+            uint32_t bits = masked_word(cur, wi, vb, ve);
+            while (bits) {
+                uint64_t ss[4], ee[4];
+                uint32_t nb = 0;
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    if (bits) {
+                        const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
+                        bits &= bits - 1;
+                        ss[q] = off[v];
+                        ee[q] = off[v + 1];
+                        nb = q + 1;
+                    }
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    if (q < (int)nb && ee[q] > ss[q]) {
+                        c += 1;
+                        wk += by_lines ? lines_of(ss[q], ee[q], ZC_LINE_SHIFT) : ee[q] - ss[q];
+                    }
             }
-            uint64_t tc, tw;
-            uint64_t p = pos + wave_sum_exclusive(c, &tc);
-            uint64_t w = wp + wave_sum_exclusive(wk, &tw);
-            for (uint32_t bits = word; bits;) {
-                const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
-                bits &= bits - 1;
-                const uint64_t s0 = off[v], e0 = off[v + 1];
-                if (e0 > s0) {
-                    list[p] = v;
-                    wpre[p] = w;
-                    p++;
-                    w += by_lines ? lines_of(s0, e0, ZC_LINE_SHIFT) : e0 - s0;
-                }
+        }
+        uint64_t tc, tw;
+        uint64_t pos = lbase[i] + block_exclusive_scan<256>(c, lds, &tc);
+        uint64_t wp = wbase[i] + block_exclusive_scan<256>(wk, lds, &tw);
+        for (uint32_t wi = w0; wi < w1; wi++) {
+            uint32_t bits = masked_word(cur, wi, vb, ve);
+            while (bits) {
+                uint64_t ss[4], ee[4];
+                uint32_t vv[4];
+                uint32_t nb = 0;
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    if (bits) {
+                        vv[q] = (wi << 5) + (__ffs(bits) - 1);
+                        bits &= bits - 1;
+                        ss[q] = off[vv[q]];
+                        ee[q] = off[vv[q] + 1];
+                        nb = q + 1;
+                    }
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    if (q < (int)nb && ee[q] > ss[q]) {
+                        list[pos] = vv[q];
+                        wpre[pos] = wp;
+                        pos++;
+                        wp += by_lines ? lines_of(ss[q], ee[q], ZC_LINE_SHIFT) : ee[q] - ss[q];
+                    }
             }
-            pos += tc;
-            wp += tw;
         }
     }
 }
@@ -546,14 +562,14 @@ struct OpCc {
     }
 };
 
-// Accumulator copy of the XCD (accelerator complex die) the wave runs on.  Any value in
-// [0, ACC_COPIES) would be correct -- the adds are device-scope atomics and the copies are
-// summed afterwards -- the die id just keeps each copy's lines in one die's L2 and splits
-// the adds aimed at one hub vertex eight ways.
-__device__ __forceinline__ uint32_t acc_copy() {
+// Accumulator copy of the XCD (accelerator complex die) the wave runs on, masked to the
+// copies in use.  Any value in [0, copies) would be correct -- the adds are device-scope
+// atomics and the copies are summed afterwards -- the die id just keeps each copy's lines in
+// few dies' L2 and splits the adds aimed at one hub vertex `copies` ways.
+__device__ __forceinline__ uint32_t acc_copy(uint32_t cmask) {
     uint32_t x;
     asm("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(x));
-    return x & (ACC_COPIES - 1);
+    return x & cmask;
 }
 
 struct OpPr {
@@ -562,9 +578,10 @@ struct OpPr {
     float* acc;
     uint64_t stride;  // floats per accumulator copy
     const float* contrib;
+    uint32_t cmask;   // copies in use - 1
     __device__ __forceinline__ uint32_t src(uint32_t u) const { return __float_as_uint(contrib[u]); }
     __device__ __forceinline__ void push(uint32_t c, uint32_t v, uint32_t) const {
-        unsafeAtomicAdd(acc + acc_copy() * stride + acc_slot(v), __uint_as_float(c));
+        unsafeAtomicAdd(acc + acc_copy(cmask) * stride + acc_slot(v), __uint_as_float(c));
     }
 };
 
@@ -1074,8 +1091,8 @@ __global__ __launch_bounds__(256) void k_loaded_frontier(uint32_t npart, const u
 }
 
 __global__ __launch_bounds__(256) void k_dpr_fold(uint32_t npart, const uint32_t* __restrict__ pv, uint64_t n,
-                                                  float* __restrict__ acc, float* __restrict__ delta,
-                                                  double* __restrict__ psum) {
+                                                  float* __restrict__ acc, uint32_t copies,
+                                                  float* __restrict__ delta, double* __restrict__ psum) {
     __shared__ double s_w[4];
     const uint64_t slots = acc_slots(n);
     for (uint32_t p = blockIdx.x; p < npart; p += gridDim.x) {
@@ -1083,8 +1100,7 @@ __global__ __launch_bounds__(256) void k_dpr_fold(uint32_t npart, const uint32_t
         for (uint32_t v = pv[p] + threadIdx.x; v < pv[p + 1]; v += blockDim.x) {
             const uint32_t sl = acc_slot(v);
             float d = delta[v];
-#pragma unroll
-            for (uint32_t c = 0; c < ACC_COPIES; c++) {
+            for (uint32_t c = 0; c < copies; c++) {
                 d += acc[c * slots + sl];
                 acc[c * slots + sl] = 0.0f;
             }
@@ -2025,10 +2041,11 @@ hipError_t launch_loaded_frontier(uint32_t npart, const uint32_t* pv, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_dpr_fold(uint32_t npart, const uint32_t* pv, uint64_t n, float* acc, float* delta, double* psum,
-                           hipStream_t st) {
+hipError_t launch_dpr_fold(uint32_t npart, const uint32_t* pv, uint64_t n, float* acc, uint32_t copies, float* delta,
+                           double* psum, hipStream_t st) {
     if (!npart) return hipSuccess;
-    k_dpr_fold<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, n, acc, delta, psum);
+    if (copies < 1 || copies > ACC_COPIES) return hipErrorInvalidValue;
+    k_dpr_fold<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, n, acc, copies, delta, psum);
     return hipGetLastError();
 }
 
@@ -2124,9 +2141,8 @@ hipError_t launch_stats_select(uint32_t npart, const uint32_t* pv, const uint64_
                                const SelParams& sp, uint8_t* mode, uint32_t* nA, uint32_t* nF, uint64_t* Ea,
                                uint64_t* Rq, uint64_t* K, hipStream_t st) {
     if (!npart) return hipSuccess;
-    const uint32_t wgs = (npart + SEL_WAVES - 1) / SEL_WAVES;
-    k_stats_select<<<wgs < GRID_CAP ? wgs : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, sp, mode, nA, nF, Ea, Rq,
-                                                                     K);
+    k_stats_select<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, sp, mode, nA, nF, Ea,
+                                                                         Rq, K);
     return hipGetLastError();
 }
 
@@ -2146,9 +2162,8 @@ hipError_t launch_build_lists(uint32_t npart, const uint32_t* pv, const uint64_t
                               const uint8_t* mode, const uint32_t* lbase, const uint64_t* wbase, uint32_t* list,
                               uint64_t* wpre, hipStream_t st) {
     if (!npart) return hipSuccess;
-    const uint32_t wgs = (npart + SEL_WAVES - 1) / SEL_WAVES;
-    k_build_lists<<<wgs < GRID_CAP ? wgs : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, mode, lbase, wbase, list,
-                                                                    wpre);
+    k_build_lists<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, mode, lbase, wbase,
+                                                                        list, wpre);
     return hipGetLastError();
 }
 
@@ -2192,7 +2207,7 @@ hipError_t launch_push_edges(const AlgoState& s, const uint32_t* list, const uin
         return push_edges_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
                              item_hi, off, col, w, shift, compacted, s.pk, st);
     default:
-        return push_edges_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
+        return push_edges_op(OpPr{s.acc, acc_slots(s.n), s.contrib, s.acc_copies - 1}, list, wpre, ja, jb, item_lo, item_hi, off, col, w, shift,
                              compacted, s.pk, st);
     }
 }
@@ -2231,7 +2246,7 @@ hipError_t launch_push_lines(const AlgoState& s, const uint32_t* list, const uin
         return push_lines_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, list, wpre, ja, jb, item_lo,
                              item_hi, off, col, w, distinct, s.pk, st);
     default:
-        return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, list, wpre, ja, jb, item_lo, item_hi, off, col, w,
+        return push_lines_op(OpPr{s.acc, acc_slots(s.n), s.contrib, s.acc_copies - 1}, list, wpre, ja, jb, item_lo, item_hi, off, col, w,
                              distinct, s.pk, st, s.link_grid);
     }
 }
@@ -2372,7 +2387,7 @@ hipError_t launch_push_fstream(const AlgoState& s, const FTask* tasks, uint32_t 
         return push_fstream_op(OpMPpr{s.mcur, s.mnext, s.lx, s.lacc, s.next, s.lshift}, tasks, ntasks, total_chunks,
                                list, off, col, w, s.pk, st);
     default:
-        return push_fstream_op(OpPr{s.acc, acc_slots(s.n), s.contrib}, tasks, ntasks, total_chunks, list, off, col, w,
+        return push_fstream_op(OpPr{s.acc, acc_slots(s.n), s.contrib, s.acc_copies - 1}, tasks, ntasks, total_chunks, list, off, col, w,
                                s.pk, st, s.link_grid);
     }
 }

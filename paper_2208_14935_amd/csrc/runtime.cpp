@@ -936,6 +936,7 @@ void init_ctx(RunCtx& rc, hytm_graph* g, int algo, bool batched, const Plan& pl,
     rc.as.pk = g->pk;
     rc.as.far = nullptr;
     rc.as.bound = 0xFFFFFFFFu;  // no far set unless a single-source SSSP run asks for one
+    rc.as.acc_copies = pr_acc_copies(false);  // a run decides once it knows whether it blocks
 }
 
 // One engine pass over the frontier `cur` (Algorithm 1 plus the engines of Sec. 6.2),
@@ -1396,7 +1397,7 @@ hytm_status pb_pass(RunCtx& rc, hipStream_t main, hytm_iter_stats* rec, int64_t 
     const bool two = nfine > PB_LOCAL_BINS;  // one pass when every fine bin fits the LDS sort
     const uint32_t shift_a = two ? PB_FINE_SHIFT + 5 : PB_FINE_SHIFT;
     const uint32_t stride_a = two ? PB_FINE_PER_COARSE : 1;
-    float* acc_pb = as.acc + (uint64_t)ACC_COPIES * acc_slots(g->n);  // the blocking copy
+    float* acc_pb = as.acc + (uint64_t)as.acc_copies * acc_slots(g->n);  // the blocking copy
     hipStream_t sp = g->s_pb;
     uint32_t* err = g->d_pb_err.p;
     for (uint32_t pi = 0; pi < pb.pieces.size(); pi++) {
@@ -1461,7 +1462,7 @@ hytm_status step_once(RunCtx& rc, hipStream_t main, uint64_t* lanes_out, bool* e
     const uint32_t t = rc.t;
     const bool fixed_steps = rc.algo == HYTM_PAGERANK || rc.algo == HYTM_PPR;
     const double t_it = now_ms();
-    const uint32_t copies = rc.pb_on ? ACC_COPIES + 1 : ACC_COPIES;  // + the blocking copy
+    const uint32_t copies = rc.pb_on ? as.acc_copies + 1 : as.acc_copies;  // + the blocking copy
     if (rc.algo == HYTM_PAGERANK)
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
             return launch_pr_prepare(n, g->d_off.p, g->d_x.p, g->d_contrib.p, g->d_acc.p, copies, main);
@@ -1568,7 +1569,7 @@ hytm_status run_delta_pagerank(RunCtx& rc, hipStream_t main, double* residual) {
     for (;;) {
         const double t_it = now_ms();
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
-            return launch_dpr_fold(npart, g->d_pv.p, n, g->d_acc.p, g->d_delta.p, g->d_psum.p, main);
+            return launch_dpr_fold(npart, g->d_pv.p, n, g->d_acc.p, rc.as.acc_copies, g->d_delta.p, g->d_psum.p, main);
         }));
         HIP_CHECK(hipMemcpyAsync(g->h_psum.p, g->d_psum.p, npart * sizeof(double), hipMemcpyDeviceToHost, main));
         HIP_CHECK(hipStreamSynchronize(main));
@@ -1584,7 +1585,7 @@ hytm_status run_delta_pagerank(RunCtx& rc, hipStream_t main, double* residual) {
         for (uint32_t pass = 0; pass < passes; pass++) {
             if (pass)
                 HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
-                    return launch_dpr_fold(npart, g->d_pv.p, n, g->d_acc.p, g->d_delta.p, g->d_psum.p, main);
+                    return launch_dpr_fold(npart, g->d_pv.p, n, g->d_acc.p, rc.as.acc_copies, g->d_delta.p, g->d_psum.p, main);
                 }));
             HIP_CHECK(kt.run(HYTM_K_OTHER, n, main, [&] {
                 return launch_dpr_activate(npart, g->d_pv.p, g->d_off.p, g->d_sched.p, g->d_delta.p, g->d_x.p,
@@ -1704,6 +1705,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     init_ctx(rc, g, algo, batched, pl, stats);
     rc.pb_on = pb_eligible(rc);
     rc.sp.zc_tie = resolve_tie(g, algo, rc.pb_on);
+    rc.as.acc_copies = pr_acc_copies(rc.pb_on);
 
     const uint64_t n = g->n;
     const uint32_t nwords = rc.nwords;
@@ -1719,7 +1721,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
     if (pr_like) {
         g->d_x.ensure(n);
         g->d_contrib.ensure(n);
-        g->d_acc.ensure((ACC_COPIES + 1) * acc_slots(n));  // per-XCD copies + the blocking copy
+        g->d_acc.ensure((rc.as.acc_copies + 1) * acc_slots(n));  // the adds' copies + the blocking copy
     }
     if (algo == HYTM_PAGERANK_DELTA) {
         g->d_delta.ensure(n);
@@ -1785,7 +1787,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         // x = 0, every vertex holds delta = (1 - d) / n (n of its own graph), nothing pushed yet
         HIP_CHECK(launch_fill_u32((uint32_t*)g->d_x.p, n, 0u, main));
         HIP_CHECK(launch_dpr_init(n, g->d_delta.p, as.inv_n, (float)(1.0 - g->params.pr_damping), main));
-        HIP_CHECK(launch_fill_u32((uint32_t*)g->d_acc.p, ACC_COPIES * acc_slots(n), 0u, main));
+        HIP_CHECK(launch_fill_u32((uint32_t*)g->d_acc.p, rc.as.acc_copies * acc_slots(n), 0u, main));
     } else {
         const float x0 = n ? (float)(1.0 / (double)n) : 0.f;
         HIP_CHECK(kt.run(HYTM_K_OTHER, n, main,
