@@ -43,10 +43,11 @@ HBM_PEAK_GBPS = 8000.0
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the factors read off the probe's device copy of
 # known size), mean per launch of the timed step.  It holds only for the kernel source and
 # workload it was measured on; otherwise the roofline reports traffic null.
-PMC_TRAFFIC = {"kernel": "push_zerocopy", "workload": "rmat24-ef16-budget0.25-hybrid-rqdistinct-zctie",
-               "kernels_sha256": "2696a4f85b450697caa1b3210bdea42cdccba76aaafa555b67f283c18f59d58a",
-               "bytes_per_launch": (2 * 1424311 + 661331) * 1024.0,
-               "summary": "profiles/pmc_traffic_rmat24_budget25_hybrid.md"}
+PMC_TRAFFIC = {"kernel": "k_push_fstream<OpPr>",
+               "workload": "rmat28-ef16-budget8GB-hybrid-src1perstep-unpacked-rqdistinct-autotie",
+               "kernels_sha256": "472cb91235db7dafa6f2e70f65e286e6349556de90cf1b220243b39a9c609284",
+               "bytes_per_launch": (2.0 * 16347866.41875 + 1.0 * 70166834.1875) * 1024.0,
+               "summary": "profiles/pmc_traffic_rmat28_budget8GB_hybrid.md"}
 PCIE_GEN5_X16_GBPS = 63.0
 # hipHostMalloc fails past ~64 GiB per process on the MI355X hosts measured (295 GiB of RAM);
 # the engine's own pinned buffers (compaction lists, selection mirrors, result buffers) need
