@@ -1202,9 +1202,11 @@ hytm_status replay_pass(RunCtx& rc, hipStream_t main, hytm_iter_stats* rec, int6
 // Workgroups of the streamed pushes beside the resident pieces.  Zero-copy line reads alone
 // saturate the link from 128 workgroups of 256 threads up; the streamed PageRank pushes also
 // wait on their atomic adds and need more, and every workgroup they hold is one the sorting
-// passes lack.  Measured on MI355X, R-MAT 28 under an 8 GB budget, 20 steps: 384 -> 4.74 s,
-// 512 -> 4.25-4.41 s, 640 -> 4.45-4.56 s, 1024 -> 4.48 s, 2048 -> 4.58 s, 4096 -> 4.58 s.
-constexpr uint32_t kPbLinkGrid = 512;
+// passes lack.  Measured on MI355X, R-MAT 28 under an 8 GB budget, 20 steps, each engine on
+// its own hardware queue and the streamed partitions read by the streaming filter: 192 ->
+// 4.07 s, 256 -> 3.84-3.95 s, 320 -> 3.82-3.85 s, 384 -> 3.62-3.70 s, 448 -> 3.61 s, 512 ->
+// 3.78 s, 768 -> 3.92 s, 1024 -> 4.08 s, 2048 -> 4.26 s.
+constexpr uint32_t kPbLinkGrid = 384;
 
 // PageRank's resident adds go through pair buckets (see PB_* in the kernel header) when it
 // runs alone, some partitions are resident, the selection can contain no compaction
