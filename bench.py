@@ -184,13 +184,14 @@ def main():
 
     t0 = time.time()
     g = hy.Graph(off, col, weights=w, check_col=False, hub_sort=args.hub_sort, pack=not args.no_pack)
-    packed = bool(g.info()["packed_weights"])
+    ginfo = g.info()
+    packed = bool(ginfo["packed_weights"])
     # Both graphs of the headline step stay pinned at once only when their edge arrays fit
     # under the host's pinned-memory ceiling with room for the engine's own pinned buffers;
     # otherwise the step runs phased: every timed pass over the directed graph, then the
     # directed graph's pinned copy is released, the symmetrized graph is pinned, and every
     # timed CC pass follows.  Swapping the pinned copies is excluded like graph loading.
-    g_bytes = 4 * m * (1 if packed or w is None else 2)
+    g_bytes = m * g.edge_bytes("sssp" if w is not None else "bfs")
     sym_bytes = 4 * len(scol) if scol is not None else 0
     phased = (headline and scol is not None
               and g_bytes + sym_bytes + PINNED_HEADROOM > args.pinned_ceiling)
@@ -242,7 +243,7 @@ def main():
         if args.budget_bytes:
             h.set_budget(int(args.budget_bytes))
         else:
-            h.set_budget(int(args.budget_frac * 4 * h.edge_arrays(algo) * h.m))
+            h.set_budget(int(args.budget_frac * h.edge_bytes(algo) * h.m))
 
     kt = not args.no_kernel_timing
 
@@ -260,7 +261,7 @@ def main():
 
     k_src = max(1, min(args.sources_per_step, len(srcs)))
     step_no = [0]
-    arrays = {a: g.edge_arrays(a) for a in ("bfs", "sssp", "pagerank")}
+    ebytes = {a: g.edge_bytes(a) for a in ("bfs", "sssp", "pagerank")}  # bytes per edge read
 
     def step_sources():
         # step i takes sources i*k .. i*k+k-1 of the seeded list, wrapping around
@@ -326,7 +327,7 @@ def main():
         all_runs += runs_cc
         elapsed += elapsed_cc
         m_sym = int(gs.m)
-    arrays["cc"] = gs.edge_arrays("cc") if gs is not None else 1
+    ebytes["cc"] = gs.edge_bytes("cc") if gs is not None else 4
 
     edges = sum(e for _, _, e in all_runs)
     value = edges / elapsed / 1e9
@@ -360,7 +361,7 @@ def main():
                 + (f"-budget{args.budget_bytes / 1e9:g}GB" if args.budget_bytes else f"-budget{args.budget_frac:g}")
                 + f"-{args.mode}" + (f"-src{k_src}perstep" if k_src != len(srcs) else "")
                 + (f"-reprocess{args.reprocess}" if args.reprocess else "") + ("-hubsort" if args.hub_sort else "")
-                + ("" if packed else "-unpacked")
+                + ("" if packed else {1: "-w8", 4: "-unpacked"}.get(ginfo["weight_bytes"], ""))
                 + ("" if cgather[0] == 0 else "-gathercost") + ("-rqdistinct" if args.rq_distinct else "")
                 + {0: "", 1: "-zctie", 2: "-autotie"}[zc_tie] + ("-prblock" if args.pr_blocking == 2 and "pagerank" in algos else "")
                 + (f"-delta{args.sssp_delta}" if args.sssp_delta and "sssp" in algos else ""))
@@ -371,7 +372,7 @@ def main():
         # the distinct lines the zero-copy kernel read (a line two lists share counts once)
         per = {}
         for name, r, _ in all_runs:
-            a = arrays[name]
+            a = ebytes[name]
             for c, cls in enumerate(hy.KERNEL_CLASSES):
                 nl = r.stats["kernel_launches"][c]
                 if not nl:
@@ -380,9 +381,9 @@ def main():
                 e[0] += r.stats["kernel_ms"][c]
                 e[1] += nl
                 e[2] += r.stats["kernel_items"][c]
-                e[3] += r.stats["kernel_items"][c] * a
+                e[3] += r.stats["kernel_items"][c] * a  # bytes of the edge arrays
                 if cls == "push_zerocopy":
-                    e[4] += r.stats["zc_lines_distinct"] * 128 * a
+                    e[4] += r.stats["zc_lines_distinct"] * 32 * a  # a line of each array
         for cls in hy.KERNEL_CLASSES:
             es = [v for (al, c), v in per.items() if c == cls]
             kernels[cls] = {"ms": sum(v[0] for v in es) / args.steps,
@@ -392,17 +393,17 @@ def main():
         avg_ms = d_ms / max(d_launches, 1)
         # algorithmic bytes per launch.  Kernels reading the mapped host arrays are priced
         # against the host link: the zero-copy kernel moves 128 B per distinct line it reads
-        # per edge array, the streaming filter kernel 4 B per edge of its tasks per edge array.
-        # Kernels reading device memory are priced against HBM: 4 B per edge per array
-        # plus one 4-byte vertex value touched per edge.
+        # per edge array, the streaming filter kernel the bytes per edge (4, 5 with byte weights,
+        # 8) of its tasks' edges.  Kernels reading device memory are priced against HBM: the
+        # bytes per edge plus one 4-byte vertex value touched per edge.
         if name == "push_zerocopy":
             per_launch = d_zc / max(d_launches, 1)
             bound, peak = "pcie", PCIE_GEN5_X16_GBPS
         elif name == "push_filter" and args.filter_engine == "stream":
-            per_launch = d_aitems * 4 / max(d_launches, 1)
+            per_launch = d_aitems / max(d_launches, 1)
             bound, peak = "pcie", PCIE_GEN5_X16_GBPS
         elif name.startswith("push"):
-            per_launch = (d_aitems * 4 + d_items * 4) / max(d_launches, 1)
+            per_launch = (d_aitems + d_items * 4) / max(d_launches, 1)
             bound, peak = "hbm", HBM_PEAK_GBPS
         elif name == "pr_blocking":
             # per pair: each counting-sort pass reads and writes 8 B, the summing pass reads
@@ -479,8 +480,8 @@ def batch_workload(args, g, off, col, deg, gamma, probe):
     res = {}
     out_b = hy.pinned_empty((len(srcs), g.n), np.uint32)
     out_1 = hy.pinned_empty(g.n, np.uint32)
-    for algo, arrays in (("bfs", 1), ("sssp", 2)):
-        g.set_budget(int(args.budget_frac * 4 * g.edge_arrays(algo) * g.m))
+    for algo in ("bfs", "sssp"):
+        g.set_budget(int(args.budget_frac * g.edge_bytes(algo) * g.m))
         g.run_batch(algo, srcs, out=out_b)  # warm-up
         times = []
         for _ in range(args.steps):
@@ -543,12 +544,11 @@ def modes_workload(args, gname, g, sym, deg, srcs, algos, gamma, probe, cgather,
                           compact_gather=cgather, rq_distinct_lines=int(args.rq_distinct), zc_tie=zc_tie)
         for mode in args.modes.split(","):
             h = gs if a == "cc" else g
-            arrays = h.edge_arrays(a)
             if mode == "filter-copy":
                 h.set_params(mode="filter", filter_engine="copy", combine_k=args.copy_k)
             else:
                 h.set_params(mode=mode, filter_engine=args.filter_engine, combine_k=args.combine_k)
-            h.set_budget(int(args.budget_bytes) if args.budget_bytes else int(args.budget_frac * 4 * arrays * h.m))
+            h.set_budget(int(args.budget_bytes) if args.budget_bytes else int(args.budget_frac * h.edge_bytes(a) * h.m))
             out = outs[np.float32 if a == "pagerank" else np.uint32][: h.n]
             try:
                 h.run(a, s, out=out)  # warm-up: staging buffers and the resident prefix of this plan
@@ -665,7 +665,7 @@ def serve_workload(args, g, off, gamma, probe):
     if args.budget_bytes:
         g.set_budget(int(args.budget_bytes))
     elif args.budget_frac >= 0:
-        g.set_budget(int(args.budget_frac * 4 * g.edge_arrays("sssp") * g.m))  # planned for SSSP's edge words
+        g.set_budget(int(args.budget_frac * g.edge_bytes("sssp") * g.m))  # planned for SSSP's edge bytes
     outs = {k: hy.pinned_empty(n, np.float32 if k == "ppr" else np.uint32) for k in ("bfs", "sssp", "ppr")}
     for k in ("bfs", "sssp", "ppr"):
         g.run(k, int(srcs[0]), out=outs[k])  # warm-up: buffers and resident cache

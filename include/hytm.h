@@ -98,7 +98,11 @@ enum {
        and the bits of (max weight - min weight) fit one 32-bit word, the library stores
        each edge as one word (neighbour low, weight - min above), so SSSP moves 4 bytes per
        edge instead of 8; results are the same either way. */
-    HYTM_GRAPH_NO_PACK = 1u << 4
+    HYTM_GRAPH_NO_PACK = 1u << 4,
+    /* Weights kept apart from the neighbour words are stored as one byte each (w - min w) when
+       max w - min w <= 255, so SSSP reads 5 bytes per edge instead of 8 (d1 = 5 in Eq. 1-2);
+       this flag keeps them as 4-byte words.  Results are the same either way. */
+    HYTM_GRAPH_WIDE_WEIGHTS = 1u << 5
 };
 
 /* Tunables.  Defaults (hytm_default_params) are the constants the paper states:
@@ -282,7 +286,8 @@ typedef struct {
     uint32_t flags;
     uint64_t hubs;              /* vertices moved to the front by HYTM_GRAPH_HUB_SORT (else 0) */
     uint32_t packed_weights;    /* 1 when weights share the neighbour words (see HYTM_GRAPH_NO_PACK) */
-    uint32_t reserved0;
+    uint32_t weight_bytes;      /* bytes per weight kept apart from the neighbour words: 1 (byte weights,
+                                   see HYTM_GRAPH_WIDE_WEIGHTS), 4, or 0 (no weights, or packed) */
 } hytm_graph_info;
 
 /* Fill *p with the paper's defaults listed above. */
@@ -389,7 +394,8 @@ hytm_status hytm_run_batch(hytm_graph *g, hytm_algo algo, const uint32_t *source
    npart      : partitions; E, nA, Ea, Rq: host arrays of npart uint64 (edges, active
                 vertices, active edges, zero-copy requests at m-byte lines);
    nres       : partitions [0, nres) are resident;
-   edge_arrays: 1 (neighbours only) or 2 (neighbours and weights) -> d1 = 4 or 8;
+   edge_arrays: 1 (neighbours only) or 2 (neighbours and weights) -> d1 = 4, or 4 + the
+                graph's bytes per weight (8, or 5 with byte weights, see HYTM_GRAPH_WIDE_WEIGHTS);
    p_out      : host array of npart engine codes (HYTM_P_*).  Used to test the device
                 selection against a reference on arbitrary inputs. */
 hytm_status hytm_select_engines(hytm_graph *g, uint64_t npart, const uint64_t *E, const uint64_t *nA,

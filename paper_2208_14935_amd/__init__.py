@@ -29,6 +29,7 @@ GRAPH_SYMMETRIC = 1 << 1
 GRAPH_SKIP_COL_CHECK = 1 << 2
 GRAPH_HUB_SORT = 1 << 3
 GRAPH_NO_PACK = 1 << 4
+GRAPH_WIDE_WEIGHTS = 1 << 5
 UNCAPPED = (1 << 64) - 1
 UNREACHED = 0xFFFFFFFF
 STATIC_SELECT_MAX_PARTS = 1 << 18  # hytm_select_engines_static's limit
@@ -109,7 +110,7 @@ class QueryResult(ctypes.Structure):
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("m", ctypes.c_uint64), ("npart", ctypes.c_uint32),
                 ("max_partition_edges", ctypes.c_uint32), ("hip_device", ctypes.c_int), ("flags", ctypes.c_uint32),
-                ("hubs", ctypes.c_uint64), ("packed_weights", ctypes.c_uint32), ("reserved0", ctypes.c_uint32)]
+                ("hubs", ctypes.c_uint64), ("packed_weights", ctypes.c_uint32), ("weight_bytes", ctypes.c_uint32)]
 
 
 # every exported entry point of include/hytm.h with its ctypes signature
@@ -271,7 +272,7 @@ class Graph:
     """A CSR graph whose edge arrays live in pinned host memory (libhytm handle)."""
 
     def __init__(self, off, col, weights=None, symmetric: bool = False, device: int = 0,
-                 check_col: bool = True, hub_sort: bool = False, pack: bool = True):
+                 check_col: bool = True, hub_sort: bool = False, pack: bool = True, narrow: bool = True):
         lib = load()
         off = np.ascontiguousarray(off)
         if off.dtype not in (np.uint32, np.uint64):
@@ -283,7 +284,8 @@ class Graph:
         self.n = len(off) - 1
         self.m = len(col)
         flags = ((GRAPH_SYMMETRIC if symmetric else 0) | (0 if check_col else GRAPH_SKIP_COL_CHECK)
-                 | (GRAPH_HUB_SORT if hub_sort else 0) | (0 if pack else GRAPH_NO_PACK))
+                 | (GRAPH_HUB_SORT if hub_sort else 0) | (0 if pack else GRAPH_NO_PACK)
+                 | (0 if narrow else GRAPH_WIDE_WEIGHTS))
         h = ctypes.c_void_p()
         self._keep = [np.zeros(1, np.uint32)]  # stand-in buffer for empty arrays
         colp = _ptr(col) if self.m else _ptr(self._keep[0])
@@ -369,6 +371,11 @@ class Graph:
         """4-byte words the graph holds per edge for `algo`: 2 for SSSP unless its weights are
         packed into the neighbour words, else 1."""
         return 2 if ALGOS[algo] == 1 and not self.info()["packed_weights"] else 1
+
+    def edge_bytes(self, algo: str) -> int:
+        """Bytes the graph holds per edge for `algo` (d1): 4 per neighbour word, plus the weight
+        kept apart for SSSP (4 bytes, or 1 with byte weights)."""
+        return 4 + (self.info()["weight_bytes"] if ALGOS[algo] == 1 else 0)
 
     def set_resident_fraction(self, algo: str, frac: float):
         """Budget = the engines' staging + `frac` of the edge bytes `algo` reads."""

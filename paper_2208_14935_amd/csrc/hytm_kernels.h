@@ -77,9 +77,10 @@ struct Header {
 // `shift` bits, weight - wmin above them (the weight array is not read); shift = 32: the
 // word is the neighbour and weights, if any, come from their own array.
 struct Pack {
-    uint32_t mask;   // neighbour bits
-    uint32_t shift;  // weight position, 32 = not packed
-    uint32_t wmin;   // smallest weight, added back
+    uint32_t mask;    // neighbour bits
+    uint32_t shift;   // weight position, 32 = not packed
+    uint32_t wmin;    // smallest weight, added back
+    uint32_t wbytes;  // weights kept apart: 4 = one uint32 each, 1 = one byte each holding w - wmin
 };
 // Vertex state an algorithm's push operator touches.
 struct AlgoState {

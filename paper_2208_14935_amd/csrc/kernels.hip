@@ -825,6 +825,10 @@ __device__ __forceinline__ uint32_t pk_v(uint32_t c, const Pack& pk) { return c 
 __device__ __forceinline__ uint32_t pk_w(uint32_t c, uint32_t wraw, const Pack& pk) {
     return pk.shift < 32 ? (c >> pk.shift) + pk.wmin : wraw;
 }
+// A weight kept apart from the neighbour words: a uint32, or one byte holding w - wmin.
+__device__ __forceinline__ uint32_t load_w(const uint32_t* __restrict__ w, uint64_t e, const Pack& pk) {
+    return pk.wbytes == 1 ? (uint32_t)((const uint8_t*)w)[e] + pk.wmin : w[e];
+}
 
 constexpr int EDGE_THREADS = 256;
 constexpr int EDGE_IPB = 1024;  // edge items per workgroup pass
@@ -872,7 +876,7 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_push_edges(const uint32_t* __r
                 const uint32_t k = s_owner[q];
                 const uint64_t e = s_st[k] + (i0 + q - s_pre[k]);
                 v = col[e];
-                if (Op::weighted && pk.shift == 32) wt = w[e];
+                if (Op::weighted && pk.shift == 32) wt = load_w(w, e, pk);
                 val = s_val[k];
             }
             push_if(op, ok, val, pk_v(v, pk), Op::weighted ? pk_w(v, wt, pk) : 0u);
@@ -952,7 +956,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_lines(const uint32_t* __r
                     ok[r] = true;
                     kk[r] = lo;
                     cv[r] = col[e];
-                    if (Op::weighted && pk.shift == 32) wv[r] = w[e];
+                    if (Op::weighted && pk.shift == 32) wv[r] = load_w(w, e, pk);
                 }
             }
         }
@@ -1926,7 +1930,7 @@ __global__ __launch_bounds__(LINE_THREADS) void k_push_fstream(const FTask* __re
             wv[r] = 0;
             if (e >= ce0 && e < ce1) {
                 cv[r] = col[e];
-                if (Op::weighted && pk.shift == 32) wv[r] = w[e];
+                if (Op::weighted && pk.shift == 32) wv[r] = load_w(w, e, pk);
             }
         }
         // active vertices whose out-edge ranges meet [ce0, ce1): list entries [j0, j0 + nv)

@@ -200,7 +200,7 @@ struct hytm_graph {
     uint32_t* h_col = nullptr;        // pinned, device-mapped
     uint32_t* h_w = nullptr;          // pinned, device-mapped, or null (also when packed)
     bool weighted = false;            // the graph has edge weights
-    Pack pk{0xFFFFFFFFu, 32, 0};      // edge word layout: weights packed into h_col when shift < 32
+    Pack pk{0xFFFFFFFFu, 32, 0, 4};      // edge word layout: weights packed into h_col when shift < 32
     uint32_t* d_col_map = nullptr;    // device addresses of the mapped arrays
     uint32_t* d_w_map = nullptr;
 
@@ -365,12 +365,19 @@ void partition_graph(hytm_graph* g) {
 // weights are packed into the neighbour words.
 uint32_t edge_arrays(const hytm_graph* g, int algo) { return algo == HYTM_SSSP && g->pk.shift == 32 ? 2 : 1; }
 
+// Bytes per edge a run reads with `arrays` edge arrays: the neighbour word, plus the weight
+// (4 bytes, or 1 when the weights are kept as bytes).  This is d1 of Eq. 1-2.
+uint32_t edge_bytes(const hytm_graph* g, uint32_t arrays) { return arrays == 2 ? 4 + g->pk.wbytes : 4; }
+
+// 32-bit words that `count` weights take in device buffers.
+uint64_t weight_words(const hytm_graph* g, uint64_t count) { return (count * g->pk.wbytes + 3) / 4; }
+
 SelParams make_sel(const hytm_graph* g, uint32_t arrays) {
     const hytm_params& p = g->params;
     SelParams sp{};
     sp.L = (uint64_t)p.line_bytes * p.max_outstanding;
     sp.MR = p.max_outstanding;
-    sp.d1 = 4 * arrays;
+    sp.d1 = edge_bytes(g, arrays);
     sp.d2 = p.index_bytes;
     sp.an = p.alpha_num;
     sp.ad = p.alpha_den;
@@ -429,7 +436,7 @@ struct Staging {
 };
 Staging staging_of(const hytm_graph* g, uint32_t arrays) {
     const hytm_params& p = g->params;
-    const uint64_t d1 = 4ull * arrays;
+    const uint64_t d1 = edge_bytes(g, arrays);
     Staging s;
     s.slot_edges = std::max<uint64_t>((uint64_t)p.combine_k * p.partition_edges, g->max_part_edges);
     // two chunk buffers of 2^20 edges: 8 MB per edge array, which a 263 MB budget (R-MAT 24 at
@@ -461,7 +468,7 @@ uint64_t engine_bytes(const hytm_graph* g, const Staging& sg, uint64_t B) {
 
 hytm_status make_plan(const hytm_graph* g, uint32_t arrays, Plan* out) {
     const hytm_params& p = g->params;
-    const uint64_t d1 = 4ull * arrays;
+    const uint64_t d1 = edge_bytes(g, arrays);
     Plan pl;
     if (g->budget == UINT64_MAX) {
         pl.nres = g->npart;
@@ -732,7 +739,10 @@ void gather_chunk(hytm_graph* g, uint32_t arrays, const uint32_t* clist, const u
             const uint64_t a = y, b = std::min(end, y1);
             const uint64_t src = g->h_off[v] + (a - pre);
             memcpy(out_col + (a - x0), g->h_col + src, (b - a) * sizeof(uint32_t));
-            if (arrays == 2) memcpy(out_w + (a - x0), g->h_w + src, (b - a) * sizeof(uint32_t));
+            if (arrays == 2) {
+                const uint32_t wb = g->pk.wbytes;
+                memcpy((uint8_t*)out_w + (a - x0) * wb, (const uint8_t*)g->h_w + src * wb, (b - a) * wb);
+            }
             y = b;
             j++;
         }
@@ -763,14 +773,14 @@ void run_compaction(RunCtx* rc, uint32_t cs, uint32_t cc, uint64_t w0, uint64_t 
             HIP_CHECK(hipMemcpyAsync(g->d_cbuf_col[b].p, g->h_cbuf_col[b].p, (x1 - x0) * 4, hipMemcpyHostToDevice,
                                      g->s_c));
             if (rc->arrays == 2)
-                HIP_CHECK(hipMemcpyAsync(g->d_cbuf_w[b].p, g->h_cbuf_w[b].p, (x1 - x0) * 4, hipMemcpyHostToDevice,
-                                         g->s_c));
+                HIP_CHECK(hipMemcpyAsync(g->d_cbuf_w[b].p, g->h_cbuf_w[b].p, (x1 - x0) * g->pk.wbytes,
+                                         hipMemcpyHostToDevice, g->s_c));
             HIP_CHECK(g->timer.run(HYTM_K_PUSH_C, x1 - x0, g->s_c, [&] {
                 return launch_push_edges(rc->as, g->d_list.p, g->d_wpre.p, cs, cs + cc, x0, x1, g->d_off.p,
                                          g->d_cbuf_col[b].p, g->d_cbuf_w[b].p, x0, true, g->s_c);
             }));
             HIP_CHECK(hipEventRecord(g->ev_cdone[b], g->s_c));
-            *bytes += (x1 - x0) * 4 * rc->arrays;
+            *bytes += (x1 - x0) * edge_bytes(g, rc->arrays);
             *chunks += 1;
             issued++;
             b ^= 1;
@@ -830,7 +840,7 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
     if (pl.allow_filter && !fstream)
         for (uint32_t s = 0; s < pl.nslots; s++) {
             g->d_slot_col[s].ensure(pl.slot_edges);
-            if (plan_arrays == 2) g->d_slot_w[s].ensure(pl.slot_edges);
+            if (plan_arrays == 2) g->d_slot_w[s].ensure(weight_words(g, pl.slot_edges));
         }
     if (pl.allow_filter && fstream) {
         g->d_tasks.ensure(npart);
@@ -841,8 +851,8 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
             g->d_cbuf_col[b].ensure(pl.cchunk);
             g->h_cbuf_col[b].ensure(pl.cchunk);
             if (plan_arrays == 2) {
-                g->d_cbuf_w[b].ensure(pl.cchunk);
-                g->h_cbuf_w[b].ensure(pl.cchunk);
+                g->d_cbuf_w[b].ensure(weight_words(g, pl.cchunk));
+                g->h_cbuf_w[b].ensure(weight_words(g, pl.cchunk));
             }
         }
         g->h_clist.ensure(n);
@@ -857,7 +867,7 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
     // resident cache: partitions [0, nres) in the region, copying only what it lacks
     if (pl.nres > 0) {
         const uint64_t E = pl.res_edges;
-        const uint64_t need = plan_arrays == 2 ? 2 * E : E;
+        const uint64_t need = plan_arrays == 2 ? E + weight_words(g, E) : E;
         const uint64_t cap = std::max(need, pl.res_words);
         if (g->d_res.n < need || g->d_res.n > cap) {  // sized to this budget's region
             g->d_res_col.release();
@@ -876,13 +886,13 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
             HIP_CHECK(hipMemcpyAsync(g->d_res.p + g->res_col, g->h_col + g->res_col, (E - g->res_col) * 4,
                                      hipMemcpyHostToDevice, main));
             tot->fill_bytes += (E - g->res_col) * 4;
-            if (g->res_w && g->res_w_at < E && g->res_w_at + g->res_w > g->res_col) g->res_w = 0;
+            if (g->res_w && g->res_w_at < E && g->res_w_at + weight_words(g, g->res_w) > g->res_col) g->res_w = 0;
             g->res_col = E;
             filled = true;
         }
         if (plan_arrays == 2 && !(g->res_w >= E && g->res_w_at == E)) {
-            HIP_CHECK(hipMemcpyAsync(g->d_res.p + E, g->h_w, E * 4, hipMemcpyHostToDevice, main));
-            tot->fill_bytes += E * 4;
+            HIP_CHECK(hipMemcpyAsync(g->d_res.p + E, g->h_w, E * g->pk.wbytes, hipMemcpyHostToDevice, main));
+            tot->fill_bytes += E * g->pk.wbytes;
             g->res_w = E;
             g->res_w_at = E;
             g->res_col = std::min(g->res_col, E);  // the weights took the words past E
@@ -894,7 +904,7 @@ hytm_status prepare_graph(hytm_graph* g, uint32_t plan_arrays, hipStream_t main,
         }
         g->d_res_col.view(g->d_res.p, E);
         if (plan_arrays == 2)
-            g->d_res_w.view(g->d_res.p + E, E);
+            g->d_res_w.view(g->d_res.p + E, weight_words(g, E));
         else
             g->d_res_w.release();
         g->res_parts = pl.nres;
@@ -953,7 +963,7 @@ hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Heade
     const uint32_t npart = g->npart;
     const Plan& pl = rc.plan;
     const bool fstream = g->params.filter_engine == HYTM_FILTER_STREAM;
-    const uint64_t d1b = 4ull * rc.arrays;
+    const uint64_t d1b = edge_bytes(g, rc.arrays);
     // 1. statistics, engine selection, active lists (Algorithm 1, GPU part); timed on the
     // device from the statistics kernel to the end of the D2H copy, so the time the stream
     // spends finishing the previous iteration's pushes is not counted
@@ -1082,7 +1092,8 @@ hytm_status engine_pass(RunCtx& rc, const uint32_t* cur, hipStream_t main, Heade
                 HIP_CHECK(hipMemcpyAsync(g->d_slot_col[s].p, g->h_col + ebeg, edges * 4, hipMemcpyHostToDevice,
                                          g->s_copy));
                 if (rc.arrays == 2)
-                    HIP_CHECK(hipMemcpyAsync(g->d_slot_w[s].p, g->h_w + ebeg, edges * 4, hipMemcpyHostToDevice,
+                    HIP_CHECK(hipMemcpyAsync(g->d_slot_w[s].p, (const uint8_t*)g->h_w + ebeg * g->pk.wbytes,
+                                             edges * g->pk.wbytes, hipMemcpyHostToDevice,
                                              g->s_copy));
                 HIP_CHECK(hipEventRecord(g->ev_copied[s], g->s_copy));
                 HIP_CHECK(hipStreamWaitEvent(g->s_fk, g->ev_copied[s], 0));
@@ -1185,7 +1196,7 @@ hytm_status replay_pass(RunCtx& rc, hipStream_t main, hytm_iter_stats* rec, int6
     }
     if (rc.replay.ftasks) {
         HIP_CHECK(hipStreamWaitEvent(g->s_fk, g->ev_go, 0));
-        HIP_CHECK(kt.run(HYTM_K_PUSH_F, rc.replay.fbytes / (4ull * rc.arrays), g->s_fk, [&] {
+        HIP_CHECK(kt.run(HYTM_K_PUSH_F, rc.replay.fbytes / edge_bytes(g, rc.arrays), g->s_fk, [&] {
             return launch_push_fstream(as, g->d_tasks.p, rc.replay.ftasks, rc.replay.fchunks, g->d_list.p,
                                        g->d_off.p, g->d_col_map, g->d_w_map, g->s_fk);
         }));
@@ -1885,7 +1896,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         HIP_CHECK(hipMemcpy(&zcd, g->d_zcl.p, sizeof(zcd), hipMemcpyDeviceToHost));
         stats->zc_lines = tt.zcl;
         stats->zc_lines_distinct = zcd;
-        stats->bytes_zerocopy = zcd * 128 * arrays;
+        stats->bytes_zerocopy = zcd * 32 * edge_bytes(g, arrays);  // a line of each array per zero-copy line
         stats->bytes_d2h = tt.d2h;
         stats->bytes_resident_fill = tt.fill_bytes;
         stats->filter_tasks = tt.ftasks;
@@ -2257,7 +2268,7 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
     if (n >= 0xFFFFFFFFull) return fail(HYTM_E_RANGE, "n = %llu: vertex ids must fit below 2^32-1", (unsigned long long)n);
     if (offset_bytes == 4 && m > 0xFFFFFFFFull) return fail(HYTM_E_INVAL, "m does not fit 4-byte offsets");
     if (flags & ~(uint32_t)(HYTM_GRAPH_SYMMETRIC | HYTM_GRAPH_SKIP_COL_CHECK | HYTM_GRAPH_HUB_SORT |
-                            HYTM_GRAPH_NO_PACK))
+                            HYTM_GRAPH_NO_PACK | HYTM_GRAPH_WIDE_WEIGHTS))
         return fail(HYTM_E_INVAL, "unknown flag bits 0x%x", flags);
     const bool hub_sort = flags & HYTM_GRAPH_HUB_SORT;
     hytm_graph* g = nullptr;
@@ -2309,26 +2320,35 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
         // travel inside the neighbour words and SSSP moves 4 bytes per edge instead of 8.
         g->weighted = weights != nullptr;
         const unsigned threads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        if (weights && m && !(flags & HYTM_GRAPH_NO_PACK)) {
-            uint32_t wmin = UINT32_MAX, wmax = 0;
+        uint32_t wmin = UINT32_MAX, wmax = 0;
+        if (weights)
             for (uint64_t e = 0; e < m; e++) {
                 wmin = std::min(wmin, weights[e]);
                 wmax = std::max(wmax, weights[e]);
             }
+        if (weights && m && !(flags & HYTM_GRAPH_NO_PACK)) {
             uint32_t vbits = 1, wbits = 0;
             while (vbits < 32 && (n - 1) >> vbits) vbits++;
             while (wbits < 32 && ((uint64_t)(wmax - wmin) >> wbits)) wbits++;
-            if (vbits + wbits <= 32 && vbits < 32) g->pk = Pack{(1u << vbits) - 1, vbits, wmin};
+            if (vbits + wbits <= 32 && vbits < 32) g->pk = Pack{(1u << vbits) - 1, vbits, wmin, 4};
         }
         const bool packed = g->pk.shift < 32;
+        // weights kept apart whose range fits a byte travel as one byte each (w - wmin): SSSP then
+        // reads 5 bytes per edge instead of 8
+        const bool narrow = weights && m && !packed && !(flags & HYTM_GRAPH_WIDE_WEIGHTS) && wmax - wmin <= 255;
+        if (narrow) {
+            g->pk.wmin = wmin;
+            g->pk.wbytes = 1;
+        }
         const size_t eb = std::max<uint64_t>(m, 1) * sizeof(uint32_t);
         HIP_CHECK(hipHostMalloc((void**)&g->h_col, eb, hipHostMallocMapped));
         HIP_CHECK(hipHostGetDevicePointer((void**)&g->d_col_map, g->h_col, 0));
         if (weights && !packed) {
-            HIP_CHECK(hipHostMalloc((void**)&g->h_w, eb, hipHostMallocMapped));
+            // padded to whole words: byte weights are loaded one byte at a time
+            HIP_CHECK(hipHostMalloc((void**)&g->h_w, weight_words(g, std::max<uint64_t>(m, 1)) * 4, hipHostMallocMapped));
             HIP_CHECK(hipHostGetDevicePointer((void**)&g->d_w_map, g->h_w, 0));
         }
-        std::vector<uint32_t> wtmp;  // relabelled weights on their way into the packed words
+        std::vector<uint32_t> wtmp;  // relabelled weights on their way into packed words or bytes
         const uint32_t* wsrc = weights;
         if (hub_sort) {
             // relabel once, straight into the pinned arrays (Sec. 6.1)
@@ -2337,7 +2357,7 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
             g->hubs = hub_order(n, g->h_off.data(), col, 8, 100, threads, order.data(), g->h_rank.data());
             std::vector<uint64_t> off2(n + 1);
             uint32_t* w2 = g->h_w;
-            if (weights && packed) {
+            if (weights && (packed || narrow)) {
                 wtmp.resize(m);
                 w2 = wtmp.data();
                 wsrc = wtmp.data();
@@ -2351,7 +2371,20 @@ hytm_status hytm_graph_create(uint64_t n, uint64_t m, const void* offsets, uint3
             HIP_CHECK(hipMemcpy(g->d_order.p, order.data(), n * 4, hipMemcpyHostToDevice));
         } else if (m) {
             parallel_copy(g->h_col, col, m * sizeof(uint32_t));
-            if (weights && !packed) parallel_copy(g->h_w, weights, m * sizeof(uint32_t));
+            if (weights && !packed && !narrow) parallel_copy(g->h_w, weights, m * sizeof(uint32_t));
+        }
+        if (narrow) {
+            uint8_t* hw = (uint8_t*)g->h_w;
+            const uint32_t base = wmin;
+            const uint64_t step = (m + threads - 1) / threads;
+            std::vector<std::thread> th;
+            for (unsigned t = 0; t < threads; t++) {
+                const uint64_t a = std::min<uint64_t>(m, t * step), b = std::min<uint64_t>(m, a + step);
+                th.emplace_back([=] {
+                    for (uint64_t e = a; e < b; e++) hw[e] = (uint8_t)(wsrc[e] - base);
+                });
+            }
+            for (auto& x : th) x.join();
         }
         if (packed) {
             const Pack pk = g->pk;
@@ -2517,6 +2550,7 @@ hytm_status hytm_graph_info_get(const hytm_graph* g, hytm_graph_info* info) {
     info->flags = g->flags;
     info->hubs = g->hubs;
     info->packed_weights = g->pk.shift < 32 ? 1u : 0u;
+    info->weight_bytes = g->weighted && g->pk.shift == 32 ? g->pk.wbytes : 0u;
     return HYTM_OK;
 }
 

@@ -1,7 +1,7 @@
 """GPU parity on the oversubscribed configuration the benchmark times: R-MAT scale 28
 (268M vertices, 4.26B edges after dedupe, past 2^31; its symmetrized graph for CC has ~8.5B,
-so edge indices above 2^32), uint32 weights in [1, 64] kept
-in their own array (28 id bits + 6 weight bits do not fit one word), edge budget 8 GB
+so edge indices above 2^32), weights in [1, 64] kept in their own array as bytes (28 id bits +
+6 weight bits do not fit one word), edge budget 8 GB
 (about 47% of the edges resident, ~133K partitions), hybrid engines with the benchmark's
 cost-model settings.
 
@@ -60,6 +60,7 @@ def test_c3_shape(c3):
     assert c3["g"].m > (1 << 31)
     assert c3["off"].dtype == np.uint64
     assert not info["packed_weights"]
+    assert info["weight_bytes"] == 1  # weights in [1, 64] kept apart as bytes: 5 bytes per SSSP edge
     assert c3["g"].edge_arrays("sssp") == 2
 
 

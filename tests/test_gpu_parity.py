@@ -386,14 +386,17 @@ def test_zero_copy_counts_each_line_once(rmat16):
 @pytest.mark.parametrize("mode", ["hybrid", "filter", "compact", "zerocopy"])
 @pytest.mark.parametrize("fe", ["stream", "copy"])
 def test_packed_and_separate_weights_agree(rmat16, mode, fe):
-    """Weights packed into the neighbour words (the default when they fit) and weights in
-    their own array give the oracle's distances under every engine, batched too."""
+    """Weights packed into the neighbour words (the default when they fit), weights in their
+    own array as bytes (w - min, the default when they do not pack and span <= 255) and as
+    4-byte words give the oracle's distances under every engine, batched too."""
     off, col, w = rmat16.off, rmat16.col, rmat16.w
     want = rmat16.want("sssp", 0)[0]
     srcs = np.array([0, 3, 77], dtype=np.uint32)
-    for pack in (True, False):
-        with hy.Graph(off, col, weights=w, pack=pack) as g:
+    for pack, narrow, wbytes in ((True, True, 0), (False, True, 1), (False, False, 4)):
+        with hy.Graph(off, col, weights=w, pack=pack, narrow=narrow) as g:
             assert g.info()["packed_weights"] == int(pack)
+            assert g.info()["weight_bytes"] == wbytes
+            assert g.edge_bytes("sssp") == 4 + wbytes
             assert g.edge_arrays("sssp") == (1 if pack else 2)
             g.set_params(mode=mode, filter_engine=fe, partition_edges=4096, compact_chunk_edges=1 << 16)
             g.set_resident_fraction("sssp", 0.1 if mode in ("compact", "hybrid") else 0.0)
@@ -408,11 +411,53 @@ def test_weights_too_wide_to_pack_stay_separate():
     w = gen.weights(off, col, 5, maxw=(1 << 23))  # 10 id bits + 23 weight bits > 32
     with hy.Graph(off, col, weights=w) as g:
         assert g.info()["packed_weights"] == 0
+        assert g.info()["weight_bytes"] == 4  # the range does not fit a byte either
         np.testing.assert_array_equal(g.run("sssp", 1).values, oracle.sssp(off, col, w, 1))
     w2 = np.full(len(col), 7, dtype=np.uint32)  # one weight: no weight bits at all
     with hy.Graph(off, col, weights=w2) as g:
         assert g.info()["packed_weights"] == 1
         np.testing.assert_array_equal(g.run("sssp", 1).values, oracle.sssp(off, col, w2, 1))
+
+
+@pytest.mark.parametrize("span,wbytes", [(255, 1), (256, 4)])
+@pytest.mark.parametrize("hub_sort", [False, True])
+def test_byte_weights_at_the_range_limit(span, wbytes, hub_sort):
+    """Separate weights become bytes (w - min) exactly when max - min <= 255, also through
+    hub sorting; distances equal the oracle's under a budget that streams most partitions."""
+    off, col = gen.rmat(14, 8, seed=9)
+    rng = np.random.default_rng(span)
+    w = (100 + rng.integers(0, span + 1, len(col))).astype(np.uint32)
+    w[0], w[1] = 100, 100 + span  # both ends of the range occur
+    want = [oracle.sssp(off, col, w, s) for s in (0, 5)]
+    with hy.Graph(off, col, weights=w, pack=False, hub_sort=hub_sort) as g:
+        assert g.info()["weight_bytes"] == wbytes
+        g.set_params(partition_edges=2048, compact_chunk_edges=4096)
+        g.set_resident_fraction("sssp", 0.2)
+        for s, wv in zip((0, 5), want):
+            np.testing.assert_array_equal(g.run("sssp", s).values, wv)
+        vals, _, _ = g.run_batch("sssp", np.array([0, 5], dtype=np.uint32))
+        for i, wv in enumerate(want):
+            np.testing.assert_array_equal(vals[i], wv)
+
+
+def test_select_engines_prices_byte_weights(rmat16):
+    """With byte weights a two-array run reads 5 bytes per edge: the device selection on
+    that graph equals the oracle's with d1 = 5 (and with d1 = 8 on a 4-byte-weight graph)."""
+    rng = np.random.default_rng(55)
+    npart = 4000
+    E = rng.integers(1, 1 << 17, npart, dtype=np.uint64)
+    Ea = (E * rng.random(npart)).astype(np.uint64)
+    nA = np.minimum(Ea, rng.integers(1, 1 << 12, npart, dtype=np.uint64))
+    nA[Ea == 0] = 0
+    Rq = (2 * (Ea * 4 // 128 + nA)).astype(np.uint64)
+    for narrow, d1 in ((True, 5), (False, 8)):
+        with hy.Graph(rmat16.off, rmat16.col, weights=rmat16.w, pack=False, narrow=narrow) as g:
+            got = g.select_engines(E, nA, Ea, Rq, nres=7, edge_arrays=2)
+        want = oracle.select(E, nA, Ea, Rq, nres=7, params=oracle.CostParams(d1=d1))
+        np.testing.assert_array_equal(got, want)
+    w5 = oracle.select(E, nA, Ea, Rq, nres=7, params=oracle.CostParams(d1=5))
+    w8 = oracle.select(E, nA, Ea, Rq, nres=7, params=oracle.CostParams(d1=8))
+    assert (w5 != w8).sum() > 0  # the two byte counts price some partitions differently
 
 
 @pytest.mark.parametrize("algo", ["bfs", "sssp"])

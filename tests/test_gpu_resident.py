@@ -30,14 +30,17 @@ def resident_edges(g, off, nres):
     return int(off[int(g.partition_bounds()[nres])])
 
 
+@pytest.mark.parametrize("narrow", [True, False])
 @pytest.mark.parametrize("frac", [0.3, 0.7])
-def test_switching_copies_only_the_difference(case, frac):
+def test_switching_copies_only_the_difference(case, frac, narrow):
     off, col, w = case
-    note(f"rmat14 alternating bfs/sssp, resident share {frac}")
+    note(f"rmat14 alternating bfs/sssp, resident share {frac}, byte weights {narrow}")
     want_bfs = oracle.bfs(off, col, 0)[0]
     want_sssp = oracle.sssp(off, col, w, 0)
-    with hy.Graph(off, col, weights=w, pack=False) as g:
+    with hy.Graph(off, col, weights=w, pack=False, narrow=narrow) as g:
         assert not g.info()["packed_weights"]
+        wb = g.info()["weight_bytes"]
+        assert wb == (1 if narrow else 4)
         g.set_params(partition_edges=2048, compact_chunk_edges=4096)
         stage = max(g.staging_bytes("bfs"), g.staging_bytes("sssp"))
         g.set_budget(stage + int(frac * 4 * g.m))
@@ -53,11 +56,14 @@ def test_switching_copies_only_the_difference(case, frac):
                 e2 = resident_edges(g, off, r.stats["nres"])
             fills.append(r.stats["bytes_resident_fill"])
         assert 0 < e2 < e1
-        # both layouts fit the one region: E1 and 2*E2 are within a partition of its words
-        assert 2 * e2 <= e1 + int(np.diff(off[g.partition_bounds().astype(np.int64)]).max())
-        # bfs: col[0, E1); sssp: w[0, E2) only; bfs: col[E2, E1); sssp: w again; sssp: nothing;
-        # pagerank after sssp: col[E2, E1); bfs after pagerank: nothing
-        assert fills == [4 * e1, 4 * e2, 4 * (e1 - e2), 4 * e2, 0, 4 * (e1 - e2), 0], (fills, e1, e2)
+        # both layouts fit the one region: 4 E1 and (4 + wb) E2 bytes are within a partition
+        maxpart = int(np.diff(off[g.partition_bounds().astype(np.int64)]).max())
+        assert (4 + wb) * e2 <= 4 * e1 + (4 + wb) * maxpart
+        # bfs: col[0, E1); sssp: w[0, E2) only, placed right after col[0, E2); bfs: col[E2, E1)
+        # again (the neighbour prefix kept is col[0, E2)); sssp: w again; sssp: nothing;
+        # pagerank after sssp: as bfs; bfs after pagerank: nothing
+        back = 4 * (e1 - e2)
+        assert fills == [4 * e1, wb * e2, back, wb * e2, 0, back, 0], (fills, e1, e2)
 
 
 def test_budget_change_resizes_the_region(case):
