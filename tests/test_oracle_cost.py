@@ -156,6 +156,21 @@ def test_select_two_edge_arrays():
     assert oracle.select(E, nA, Ea, Rq, params=CostParams(d1=8))[0] == COMPACT
 
 
+def test_select_byte_weights():
+    # SSSP with weights stored as bytes reads d1 = 5 bytes per edge; its zero-copy requests
+    # still count a line of each array per list (a 2-byte weight run costs a line request).
+    # 16384 vertices of degree 2 (E = 32768), half of them active (Ea = 16384, nA = 8192),
+    # 8-byte lists aligned within lines -> Rq = 2 * 8192 = 16384 -> ceil(/256) = 64,
+    # RTTzc = 5/8 + 3/8 * 1/2 = 13/16, Tiz = 52.
+    #   d1 = 8: Tef = 8, Tec = ceil((131072 + 32768)/32768) = 5 < 6.4 and < 20.8 -> compaction.
+    #   d1 = 5: Tef = 5, Tec = ceil((81920 + 32768)/32768) = 4, not < alpha*Tef = 4; Tiz = 52
+    #           is not < 5 either -> filter.  The index term weighs more against fewer bytes.
+    E, nA, Ea, Rq = one_partition([2] * 16384, [1] * 8192 + [0] * 8192, arrays=2)
+    assert (int(E[0]), int(nA[0]), int(Ea[0]), int(Rq[0])) == (32768, 8192, 16384, 16384)
+    assert oracle.select(E, nA, Ea, Rq, params=CostParams(d1=8))[0] == COMPACT
+    assert oracle.select(E, nA, Ea, Rq, params=CostParams(d1=5))[0] == FILTER
+
+
 def test_select_inactive_resident_and_forced():
     E = [100, 100, 100, 100]
     nA, Ea, Rq = [0, 3, 3, 3], [0, 30, 30, 30], [0, 3, 3, 3]
