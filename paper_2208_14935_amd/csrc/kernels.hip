@@ -1,16 +1,16 @@
 // Device side of the hybrid-transfer traversal, written for gfx950 (wave64).
 //
 // Per iteration (Sec. 4 overview, Algorithm 1):
-//   k_stats_select  one workgroup per partition: active vertices, active edges and
-//                   request lines from the frontier bitmap, then the engine choice of
-//                   Sec. 5.1 (Eq. 1-3, alpha/beta rule) in exact integer arithmetic;
+//   k_stats_select  one wave per partition: active vertices, active edges and request
+//                   lines from the frontier bitmap, then the engine choice of Sec. 5.1
+//                   (Eq. 1-3, alpha/beta rule) in exact integer arithmetic;
 //   k_scan_*        per-engine prefix sums over partitions (tile totals, tile bases,
 //                   offsets), which place every partition's active vertices in one list
 //                   ordered by engine segment and partition ("pre-combine" of Vc and Vz,
 //                   Algorithm 1);
-//   k_build_lists   one workgroup per scheduled partition: ordered compaction of its
-//                   active vertices into the list plus the work prefix (edges, or
-//                   128-byte lines for zero-copy) used for load balancing;
+//   k_build_lists   one wave per scheduled partition: ordered compaction of its active
+//                   vertices into the list plus the work prefix (edges, or 128-byte
+//                   lines for zero-copy) used for load balancing;
 //   k_push_edges    edge-balanced push over a list slice reading device memory
 //                   (resident cache, filter staging, or compaction buffer);
 //   k_push_lines    line-balanced push reading mapped pinned host memory: each half
@@ -42,82 +42,31 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
     return x;
 }
 
-// Block-wide exclusive prefix sum of x (blockDim.x = NT, a multiple of 64).
-// lds must hold NT/64 uint64.  Returns the exclusive prefix; *total gets the sum.
-template <int NT>
-__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t x, uint64_t* lds, uint64_t* total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+// Exclusive prefix sum over the wave; *total gets the wave's sum.
+__device__ __forceinline__ uint64_t wave_exclusive_sum(uint64_t x, uint64_t* total) {
+    const int lane = threadIdx.x & 63;
     uint64_t v = x;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        uint64_t y = __shfl_up(v, d, 64);
+        const uint64_t y = __shfl_up(v, d, 64);
         if (lane >= d) v += y;
     }
-    if (lane == 63) lds[wid] = v;
-    __syncthreads();
-    if (wid == 0) {
-        uint64_t u = lane < NT / 64 ? lds[lane] : 0;
-#pragma unroll
-        for (int d = 1; d < NT / 64; d <<= 1) {
-            uint64_t y = __shfl_up(u, d, 64);
-            if (lane >= d) u += y;
-        }
-        if (lane < NT / 64) lds[lane] = u;
-    }
-    __syncthreads();
-    const uint64_t base = wid ? lds[wid - 1] : 0;
-    *total = lds[NT / 64 - 1];
-    __syncthreads();
-    return base + v - x;
+    *total = __shfl(v, 63, 64);
+    return v - x;
 }
 
-// Block-wide exclusive prefix maximum of x (0 for thread 0); *total gets the maximum over
-// the block.  lds must hold NT/64 uint64.
-template <int NT>
-__device__ __forceinline__ uint64_t block_exclusive_max(uint64_t x, uint64_t* lds, uint64_t* total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+// Exclusive prefix maximum over the wave (0 for lane 0); *total gets the wave's maximum.
+__device__ __forceinline__ uint64_t wave_exclusive_max(uint64_t x, uint64_t* total) {
+    const int lane = threadIdx.x & 63;
     uint64_t v = x;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const uint64_t y = __shfl_up(v, d, 64);
         if (lane >= d) v = v > y ? v : y;
     }
-    if (lane == 63) lds[wid] = v;
-    __syncthreads();
-    uint64_t base = 0, t = 0;
-#pragma unroll
-    for (int k = 0; k < NT / 64; k++) {
-        const uint64_t w = lds[k];
-        if (k < wid) base = base > w ? base : w;
-        t = t > w ? t : w;
-    }
-    *total = t;
-    uint64_t ex = __shfl_up(v, 1, 64);
-    if (lane == 0) ex = 0;
-    __syncthreads();
-    return base > ex ? base : ex;
-}
-
-template <int NT>
-__device__ __forceinline__ uint64_t block_sum(uint64_t x, uint64_t* lds) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    x = wave_sum(x);
-    if (lane == 0) lds[wid] = x;
-    __syncthreads();
-    uint64_t t = 0;
-#pragma unroll
-    for (int i = 0; i < NT / 64; i++) t += lds[i];
-    __syncthreads();
-    return t;
-}
-
-// Bits of word wi restricted to vertices [vb, ve).
-__device__ __forceinline__ uint32_t masked_word(const uint32_t* bm, uint32_t wi, uint32_t vb, uint32_t ve) {
-    uint32_t bits = bm[wi];
-    const uint32_t lo = wi << 5;
-    if (lo < vb) bits &= ~0u << (vb - lo);
-    if (ve - lo < 32) bits &= (1u << (ve - lo)) - 1u;
-    return bits;
+    *total = __shfl(v, 63, 64);
+    const uint64_t ex = __shfl_up(v, 1, 64);
+    return lane ? ex : 0;
 }
 
 // ------------------------------------------------------------- engine selection
@@ -147,89 +96,141 @@ __device__ __forceinline__ uint8_t select_engine(uint64_t E, uint64_t nA, uint64
 }
 
 // ------------------------------------------------------------------- stats
+// One wave per partition (four partitions per workgroup, no workgroup barriers).  The
+// partition's vertices are taken in rounds of 64 aligned windows of 64 vertices: lane l loads
+// the active bits of window l, a wave scan counts them, and then the round's active vertices
+// are dealt out in order, one per lane, in batches of 64 (SEL_B batches with their offset
+// loads in flight together).  Lanes are busy whatever the density, and where the frontier
+// is dense consecutive lanes hold consecutive vertices, so the offset loads coalesce.
+constexpr int SEL_B = 4;
+
+// Active bits of window q (vertices 64 q .. 64 q + 63) restricted to [vb, ve).
+__device__ __forceinline__ uint64_t window_bits(const uint32_t* __restrict__ bm, uint32_t q, uint32_t vb,
+                                                uint32_t ve) {
+    const uint32_t lo = q << 6;
+    // word 2q+1 may lie past the bitmap when 64q + 32 >= ve; then its bits are masked off
+    // below, and the load reads the partition's last word instead
+    const uint32_t hi = min(2 * q + 1, (ve - 1) >> 5);
+    uint64_t bits = bm[2 * q] | ((uint64_t)bm[hi] << 32);
+    if (lo < vb) bits &= ~0ull << (vb - lo);
+    if (ve - lo < 64) bits &= (1ull << (ve - lo)) - 1ull;
+    return bits;
+}
+
+// Position of the r-th (from 0) set bit of x; r < popcount(x).
+__device__ __forceinline__ uint32_t select_bit(uint64_t x, uint32_t r) {
+    uint32_t pos = 0, c;
+    c = __popc((uint32_t)x);
+    if (r >= c) { r -= c; x >>= 32; pos += 32; }
+    c = __popc((uint32_t)x & 0xFFFFu);
+    if (r >= c) { r -= c; x >>= 16; pos += 16; }
+    c = __popc((uint32_t)x & 0xFFu);
+    if (r >= c) { r -= c; x >>= 8; pos += 8; }
+    c = __popc((uint32_t)x & 0xFu);
+    if (r >= c) { r -= c; x >>= 4; pos += 4; }
+    c = __popc((uint32_t)x & 0x3u);
+    if (r >= c) { r -= c; x >>= 2; pos += 2; }
+    if (r >= ((uint32_t)x & 1u)) pos += 1;
+    return pos;
+}
+
+// Inclusive prefix sum over the wave.
+__device__ __forceinline__ uint32_t wave_inclusive_sum_u32(uint32_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// The vertex holding the k-th (from 0) active bit of the round: windows q0 + j, with
+// incl the inclusive count of active bits over windows 0..lane; k < the round's total.
+__device__ __forceinline__ uint32_t round_vertex(uint32_t k, uint32_t incl, uint32_t cnt, uint64_t wbits,
+                                                 uint32_t q0) {
+    uint32_t j = 0;
+#pragma unroll
+    for (uint32_t step = 32; step; step >>= 1)
+        if (__shfl(incl, j + step - 1, 64) <= k) j += step;
+    const uint64_t bj = __shfl(wbits, j, 64);
+    const uint32_t before = __shfl(incl - cnt, j, 64);
+    return ((q0 + j) << 6) + select_bit(bj, k - before);
+}
+
+// Batches [b0, b0 + 64 G) of a round's active vertices: every lane loads (a lane past the
+// round's end the round's last vertex), so the loads of all G batches are issued before the
+// first is used.  Adds the vertices' counts; carry is the (line + 1) of the latest list.
+template <int G>
+__device__ __forceinline__ void stats_batches(uint32_t b0, uint32_t T, uint32_t incl, uint32_t cnt, uint64_t wbits,
+                                              uint32_t q0, const uint64_t* __restrict__ off, uint32_t sh,
+                                              uint64_t& c, uint64_t& ea, uint64_t& rq, uint64_t& kl, uint64_t& rqd,
+                                              uint64_t& carry) {
+    const uint32_t lane = threadIdx.x & 63;
+    uint64_t s[G], e[G];
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        const uint32_t k = b0 + 64 * g + lane;
+        const uint32_t v = round_vertex(k < T ? k : T - 1, incl, cnt, wbits, q0);
+        s[g] = off[v];
+        e[g] = off[v + 1];
+    }
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        if (b0 + 64 * g >= T) break;
+        const bool has = b0 + 64 * g + lane < T && e[g] > s[g];
+        uint64_t fl = 0, ll = 0;
+        if (has) {
+            c += 1;
+            ea += e[g] - s[g];
+            rq += lines_of(s[g], e[g], sh);
+            kl += lines_of(s[g], e[g], ZC_LINE_SHIFT);
+            fl = (s[g] >> sh) + 1;
+            ll = ((e[g] - 1) >> sh) + 1;
+        }
+        // the last line of the latest earlier list (lists are in vertex order)
+        uint64_t tot;
+        const uint64_t ex = wave_exclusive_max(ll, &tot);
+        const uint64_t prev = carry > ex ? carry : ex;
+        if (has) rqd += ll - fl + 1 - (prev == fl ? 1 : 0);
+        carry = carry > tot ? carry : tot;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_stats_select(uint32_t npart, const uint32_t* __restrict__ pv,
                                                       const uint64_t* __restrict__ off,
                                                       const uint32_t* __restrict__ cur, SelParams sp,
                                                       uint8_t* __restrict__ mode, uint32_t* __restrict__ nA,
                                                       uint32_t* __restrict__ nF, uint64_t* __restrict__ Ea,
                                                       uint64_t* __restrict__ Rq, uint64_t* __restrict__ K) {
-    __shared__ uint64_t red[4], red2[4];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wpb = blockDim.x >> 6, waves = gridDim.x * wpb;
     const uint32_t sh = sp.cost_shift;
-    for (uint32_t i = blockIdx.x; i < npart; i += gridDim.x) {
+    for (uint32_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < npart; i += waves) {
         const uint32_t vb = pv[i], ve = pv[i + 1];
-        const uint32_t wb = vb >> 5, we = (ve + 31) >> 5;
-        // a partition without active vertices (most of them while the frontier is small)
-        // costs one barrier instead of the reductions below
-        uint32_t any = 0;
-        for (uint32_t wi = wb + threadIdx.x; wi < we; wi += blockDim.x) any |= masked_word(cur, wi, vb, ve);
-        if (!__syncthreads_or(any != 0)) {
-            if (threadIdx.x == 0) {
-                mode[i] = P_NONE;
-                nA[i] = 0;
-                nF[i] = 0;
-                Ea[i] = 0;
-                Rq[i] = 0;
-                K[i] = 0;
-            }
-            continue;
-        }
+        const uint32_t qb = vb >> 6, qe = (ve + 63) >> 6;
         uint64_t c = 0, f = 0, ea = 0, rq = 0, kl = 0, rqd = 0;
-        // distinct lines: (line + 1) of the last list before the current 256 words, 0 = none
-        uint64_t carry = 0;
-        for (uint32_t base = wb; base < we; base += blockDim.x) {  // uniform across the block
-            const uint32_t wi = base + threadIdx.x;
-            uint64_t first1 = 0, last1 = 0, dl = 0;  // (line + 1) of the word's first / last list
-            if (wi < we) {
-                uint32_t bits = masked_word(cur, wi, vb, ve);
-                f += __popc(bits);
-                // the offsets of up to four active vertices are loaded together, so a dense
-                // word waits for 8 rounds of gathers instead of 32
-                while (bits) {
-                    uint64_t ss[4], ee[4];
-                    uint32_t nb = 0;
-#pragma unroll
-                    for (int q = 0; q < 4; q++)
-                        if (bits) {
-                            const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
-                            bits &= bits - 1;
-                            ss[q] = off[v];
-                            ee[q] = off[v + 1];
-                            nb = q + 1;
-                        }
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        if (q >= (int)nb) break;
-                        const uint64_t s = ss[q], e = ee[q];
-                        if (e > s) {
-                            c += 1;
-                            ea += e - s;
-                            rq += lines_of(s, e, sh);
-                            kl += lines_of(s, e, ZC_LINE_SHIFT);
-                            const uint64_t fl = (s >> sh) + 1, ll = ((e - 1) >> sh) + 1;
-                            dl += ll - fl + 1 - (last1 == fl ? 1 : 0);
-                            if (!first1) first1 = fl;
-                            last1 = ll;
-                        }
-                    }
-                }
-            }
-            if (sp.rq_distinct) {
-                // a word's first line repeats the last line of the latest earlier list
-                uint64_t tot;
-                const uint64_t ex = block_exclusive_max<256>(last1, red2, &tot);
-                const uint64_t prev = carry > ex ? carry : ex;
-                if (first1 && prev == first1) dl -= 1;
-                rqd += dl;
-                carry = carry > tot ? carry : tot;
-            }
+        uint64_t carry = 0;  // (line + 1) of the last list so far, 0 = none
+        for (uint32_t q0 = qb; q0 < qe; q0 += 64) {  // uniform across the wave
+            const uint64_t wbits = q0 + lane < qe ? window_bits(cur, q0 + lane, vb, ve) : 0ull;
+            if (!__ballot(wbits != 0)) continue;
+            const uint32_t cnt = __popcll(wbits);
+            const uint32_t incl = wave_inclusive_sum_u32(cnt);
+            const uint32_t T = __shfl(incl, 63, 64);
+            f += cnt;
+            // a round of at most 64 active vertices takes one batch, larger ones SEL_B at a time
+            if (T <= 64)
+                stats_batches<1>(0, T, incl, cnt, wbits, q0, off, sh, c, ea, rq, kl, rqd, carry);
+            else
+                for (uint32_t b0 = 0; b0 < T; b0 += 64 * SEL_B)
+                    stats_batches<SEL_B>(b0, T, incl, cnt, wbits, q0, off, sh, c, ea, rq, kl, rqd, carry);
         }
-        c = block_sum<256>(c, red);
-        f = block_sum<256>(f, red);
-        ea = block_sum<256>(ea, red);
-        rq = block_sum<256>(sp.rq_distinct ? rqd : rq, red) * sp.arrays;
-        kl = block_sum<256>(kl, red);
-        if (threadIdx.x == 0) {
-            const uint64_t E = off[ve] - off[vb];
+        c = wave_sum(c);
+        f = wave_sum(f);
+        ea = wave_sum(ea);
+        rq = wave_sum(sp.rq_distinct ? rqd : rq) * sp.arrays;
+        kl = wave_sum(kl);
+        if (lane == 0) {
             uint8_t p;
             if (ea == 0)
                 p = P_NONE;
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(256) void k_stats_select(uint32_t npart, const uint
             else if (sp.force)
                 p = (uint8_t)sp.force;
             else
-                p = select_engine(E, c, ea, rq, sp);
+                p = select_engine(off[ve] - off[vb], c, ea, rq, sp);
             mode[i] = p;
             nA[i] = (uint32_t)c;
             nF[i] = (uint32_t)f;
@@ -417,6 +418,44 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_write(uint32_t npart, con
 }
 
 // ------------------------------------------------------------------ lists
+// One wave per scheduled partition, dealing out each round's active vertices as in
+// k_stats_select; a batch's entries are written in lane order, so the stores coalesce.
+// Batches [b0, b0 + 64 G) of a round's active vertices, loaded as in stats_batches; the
+// entries of vertices with edges go to list[pos...) in lane order with their work prefix.
+template <int G>
+__device__ __forceinline__ void list_batches(uint32_t b0, uint32_t T, uint32_t incl, uint32_t cnt, uint64_t wbits,
+                                             uint32_t q0, const uint64_t* __restrict__ off, bool by_lines,
+                                             uint32_t* __restrict__ list, uint64_t* __restrict__ wpre, uint64_t& pos,
+                                             uint64_t& wp) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t s[G], e[G];
+    uint32_t vv[G];
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        const uint32_t k = b0 + 64 * g + lane;
+        vv[g] = round_vertex(k < T ? k : T - 1, incl, cnt, wbits, q0);
+        s[g] = off[vv[g]];
+        e[g] = off[vv[g] + 1];
+    }
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        if (b0 + 64 * g >= T) break;
+        const bool has = b0 + 64 * g + lane < T && e[g] > s[g];
+        const uint64_t A = __ballot(has);
+        const uint64_t wk = has ? (by_lines ? lines_of(s[g], e[g], ZC_LINE_SHIFT) : e[g] - s[g]) : 0;
+        uint64_t tw;
+        const uint64_t ew = wave_exclusive_sum(wk, &tw);
+        if (has) {
+            const uint64_t at = pos + __popcll(A & below);
+            list[at] = vv[g];
+            wpre[at] = wp + ew;
+        }
+        pos += __popcll(A);
+        wp += tw;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_build_lists(uint32_t npart, const uint32_t* __restrict__ pv,
                                                      const uint64_t* __restrict__ off,
                                                      const uint32_t* __restrict__ cur,
@@ -424,65 +463,26 @@ __global__ __launch_bounds__(256) void k_build_lists(uint32_t npart, const uint3
                                                      const uint32_t* __restrict__ lbase,
                                                      const uint64_t* __restrict__ wbase,
                                                      uint32_t* __restrict__ list, uint64_t* __restrict__ wpre) {
-    __shared__ uint64_t lds[4];
-    for (uint32_t i = blockIdx.x; i < npart; i += gridDim.x) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wpb = blockDim.x >> 6, waves = gridDim.x * wpb;
+    for (uint32_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < npart; i += waves) {
         const uint8_t m = mode[i];
         if (m == P_NONE) continue;
         const bool by_lines = m == P_ZC;
         const uint32_t vb = pv[i], ve = pv[i + 1];
-        const uint32_t wb = vb >> 5, we = (ve + 31) >> 5;
-        const uint32_t per = (we - wb + blockDim.x - 1) / blockDim.x;
-        const uint32_t w0 = min(wb + threadIdx.x * per, we), w1 = min(w0 + per, we);
-        uint64_t c = 0, wk = 0;
-        for (uint32_t wi = w0; wi < w1; wi++) {
-            uint32_t bits = masked_word(cur, wi, vb, ve);
-            while (bits) {
-                uint64_t ss[4], ee[4];
-                uint32_t nb = 0;
-#pragma unroll
-                for (int q = 0; q < 4; q++)
-                    if (bits) {
-                        const uint32_t v = (wi << 5) + (__ffs(bits) - 1);
-                        bits &= bits - 1;
-                        ss[q] = off[v];
-                        ee[q] = off[v + 1];
-                        nb = q + 1;
-                    }
-#pragma unroll
-                for (int q = 0; q < 4; q++)
-                    if (q < (int)nb && ee[q] > ss[q]) {
-                        c += 1;
-                        wk += by_lines ? lines_of(ss[q], ee[q], ZC_LINE_SHIFT) : ee[q] - ss[q];
-                    }
-            }
-        }
-        uint64_t tc, tw;
-        uint64_t pos = lbase[i] + block_exclusive_scan<256>(c, lds, &tc);
-        uint64_t wp = wbase[i] + block_exclusive_scan<256>(wk, lds, &tw);
-        for (uint32_t wi = w0; wi < w1; wi++) {
-            uint32_t bits = masked_word(cur, wi, vb, ve);
-            while (bits) {
-                uint64_t ss[4], ee[4];
-                uint32_t vv[4];
-                uint32_t nb = 0;
-#pragma unroll
-                for (int q = 0; q < 4; q++)
-                    if (bits) {
-                        vv[q] = (wi << 5) + (__ffs(bits) - 1);
-                        bits &= bits - 1;
-                        ss[q] = off[vv[q]];
-                        ee[q] = off[vv[q] + 1];
-                        nb = q + 1;
-                    }
-#pragma unroll
-                for (int q = 0; q < 4; q++)
-                    if (q < (int)nb && ee[q] > ss[q]) {
-                        list[pos] = vv[q];
-                        wpre[pos] = wp;
-                        pos++;
-                        wp += by_lines ? lines_of(ss[q], ee[q], ZC_LINE_SHIFT) : ee[q] - ss[q];
-                    }
-            }
+        const uint32_t qb = vb >> 6, qe = (ve + 63) >> 6;
+        uint64_t pos = lbase[i], wp = wbase[i];
+        for (uint32_t q0 = qb; q0 < qe; q0 += 64) {  // uniform across the wave
+            const uint64_t wbits = q0 + lane < qe ? window_bits(cur, q0 + lane, vb, ve) : 0ull;
+            if (!__ballot(wbits != 0)) continue;
+            const uint32_t cnt = __popcll(wbits);
+            const uint32_t incl = wave_inclusive_sum_u32(cnt);
+            const uint32_t T = __shfl(incl, 63, 64);
+            if (T <= 64)
+                list_batches<1>(0, T, incl, cnt, wbits, q0, off, by_lines, list, wpre, pos, wp);
+            else
+                for (uint32_t b0 = 0; b0 < T; b0 += 64 * SEL_B)
+                    list_batches<SEL_B>(b0, T, incl, cnt, wbits, q0, off, by_lines, list, wpre, pos, wp);
         }
     }
 }
@@ -2145,7 +2145,7 @@ hipError_t launch_stats_select(uint32_t npart, const uint32_t* pv, const uint64_
                                const SelParams& sp, uint8_t* mode, uint32_t* nA, uint32_t* nF, uint64_t* Ea,
                                uint64_t* Rq, uint64_t* K, hipStream_t st) {
     if (!npart) return hipSuccess;
-    k_stats_select<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, sp, mode, nA, nF, Ea,
+    k_stats_select<<<grid_for(npart, 4, GRID_CAP), 256, 0, st>>>(npart, pv, off, cur, sp, mode, nA, nF, Ea,
                                                                          Rq, K);
     return hipGetLastError();
 }
@@ -2166,7 +2166,7 @@ hipError_t launch_build_lists(uint32_t npart, const uint32_t* pv, const uint64_t
                               const uint8_t* mode, const uint32_t* lbase, const uint64_t* wbase, uint32_t* list,
                               uint64_t* wpre, hipStream_t st) {
     if (!npart) return hipSuccess;
-    k_build_lists<<<npart < GRID_CAP ? npart : GRID_CAP, 256, 0, st>>>(npart, pv, off, cur, mode, lbase, wbase,
+    k_build_lists<<<grid_for(npart, 4, GRID_CAP), 256, 0, st>>>(npart, pv, off, cur, mode, lbase, wbase,
                                                                         list, wpre);
     return hipGetLastError();
 }
