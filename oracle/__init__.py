@@ -186,19 +186,23 @@ def partition(off, target_edges: int):
     return bounds[: k + 1] if n else np.zeros(1, dtype=np.uint64)
 
 
-def partition_stats(bounds, off, active, arrays: int = 1, line_bytes: int = 128, distinct: bool = False):
+def partition_stats(bounds, off, active, arrays: int = 1, line_bytes: int = 128, distinct: bool = False,
+                    weight_bytes: int | None = None):
     """(nA, Ea, Rq) per partition for the boolean frontier `active`; with distinct, Rq counts
-    the different lines the active lists touch instead of Eq. 3's per-vertex requests."""
+    the different lines the active lists touch instead of Eq. 3's per-vertex requests.
+    Rq covers the neighbour array (4-byte entries) and, when a weight array is read beside it
+    (arrays = 2), that array too: weight_bytes bytes per entry (default 4; 1 for byte weights)."""
+    wb = (4 if arrays == 2 else 0) if weight_bytes is None else int(weight_bytes)
+    if (arrays == 2) != (wb > 0) or wb not in (0, 1, 4):
+        raise ValueError("weight_bytes must be 1 or 4 with two arrays and 0 with one")
     bounds = np.ascontiguousarray(bounds, dtype=np.uint64)
     off = np.ascontiguousarray(off, dtype=np.uint64)
     act = np.ascontiguousarray(active, dtype=np.uint8)
     npart = len(bounds) - 1
     nA, Ea, Rq = (np.zeros(max(npart, 1), dtype=np.uint64)[:npart] for _ in range(3))
-    _load().orc_partition_stats(npart, _p(bounds), _p(off), _p(act), int(arrays), int(line_bytes),
-                                _p(nA), _p(Ea), _p(Rq))
+    _load().orc_partition_stats(npart, _p(bounds), _p(off), _p(act), wb, int(line_bytes), _p(nA), _p(Ea), _p(Rq))
     if distinct:
-        _load().orc_partition_lines_distinct(npart, _p(bounds), _p(off), _p(act), int(arrays), int(line_bytes),
-                                             _p(Rq))
+        _load().orc_partition_lines_distinct(npart, _p(bounds), _p(off), _p(act), wb, int(line_bytes), _p(Rq))
     return nA, Ea, Rq
 
 

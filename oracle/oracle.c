@@ -389,51 +389,68 @@ uint64_t orc_partition(uint64_t n, const uint64_t *off, uint64_t target, uint64_
     return count;
 }
 
+/* Transactions of an m-byte-line engine for a list of len bytes at byte offset start of
+   its array (the arrays start on a line boundary): ceil(len/m), plus one when the list's
+   misaligned start makes it cross one more line boundary (the footnote to Eq. 3 computes
+   it from the list's length and physical start). */
+static uint64_t list_tx(uint64_t start, uint64_t len, uint64_t m) {
+    uint64_t base = (len + m - 1) / m;
+    return base + ((start % m) + len > base * m ? 1 : 0);
+}
+
 /* Per-partition activity statistics for one frontier (Sec. 5.1).
    active[v] != 0 marks v active.  A_i is read as the active vertices of P_i that have
    at least one out-edge: an active vertex with no out-edges has nothing to push and
    needs neither an index entry nor a transfer.
      nA[i] = |A_i|
      Ea[i] = sum over A_i of D_o(v)                 (active edges)
-     Rq[i] = sum over A_i, over each edge array read, of ceil(D_o(v)*4/m) + am(v)
-   where m = line_bytes and am(v) is 1 when the list, placed at byte offset off(v)*4 of
-   its array (the arrays start on a line boundary), needs one transaction more than
-   ceil(len/m) -- the footnote to Eq. 3 computes it from the list's length and
-   physical start. */
+     Rq[i] = sum over A_i, over each edge array read, of the list's transactions
+   where the neighbour array has 4-byte entries and, with wbytes > 0, a weight array of
+   wbytes-byte entries is read beside it (wbytes = 4: the same count twice; wbytes = 1: a
+   weight list of D_o(v) bytes at byte offset off(v)).  Eq. 3 counts the requests the
+   zero-copy engine issues for the data it reads; each array is read with its own
+   requests. */
 void orc_partition_stats(uint64_t npart, const uint64_t *bounds, const uint64_t *off, const unsigned char *active,
-                         uint32_t arrays, uint32_t line_bytes, uint64_t *nA, uint64_t *Ea, uint64_t *Rq) {
+                         uint32_t wbytes, uint32_t line_bytes, uint64_t *nA, uint64_t *Ea, uint64_t *Rq) {
     for (uint64_t i = 0; i < npart; i++) {
         nA[i] = Ea[i] = Rq[i] = 0;
         for (uint64_t v = bounds[i]; v < bounds[i + 1]; v++) {
             uint64_t deg = off[v + 1] - off[v];
             if (!active[v] || deg == 0) continue;
-            uint64_t start = off[v] * 4, len = deg * 4;
-            uint64_t base = (len + line_bytes - 1) / line_bytes;                 /* ceil(D_o*d/m) */
-            uint64_t am = (start % line_bytes) + len > base * line_bytes ? 1 : 0; /* misaligned tail */
             nA[i] += 1;
             Ea[i] += deg;
-            Rq[i] += (uint64_t)arrays * (base + am);
+            Rq[i] += list_tx(off[v] * 4, deg * 4, line_bytes);
+            if (wbytes) Rq[i] += list_tx(off[v] * wbytes, deg * wbytes, line_bytes);
         }
     }
 }
 
+/* The m-byte lines of an array of b-byte entries that the lists of A_i touch, each
+   counted once.  The lists lie in vertex order, so a line repeats only as the previous
+   list's last line. */
+static uint64_t lines_distinct(uint64_t lo, uint64_t hi, const uint64_t *off, const unsigned char *active,
+                               uint64_t b, uint64_t m) {
+    uint64_t count = 0, last = UINT64_MAX;
+    for (uint64_t v = lo; v < hi; v++) {
+        if (!active[v] || off[v + 1] == off[v]) continue;
+        for (uint64_t line = off[v] * b / m; line <= (off[v + 1] * b - 1) / m; line++)
+            if (line != last) {
+                count++;
+                last = line;
+            }
+    }
+    return count;
+}
+
 /* Zero-copy requests counted as distinct lines (a reading for kernels that read a line
-   shared by two consecutive active lists once): Rq[i] = arrays x the number of different
-   m-byte lines that the lists of A_i touch.  The lists lie in vertex order, so a line
-   repeats only as the previous list's last line. */
+   shared by two consecutive active lists once): Rq[i] = the different m-byte lines the
+   lists of A_i touch in the neighbour array, plus, with wbytes > 0, those they touch in
+   the weight array of wbytes-byte entries. */
 void orc_partition_lines_distinct(uint64_t npart, const uint64_t *bounds, const uint64_t *off,
-                                  const unsigned char *active, uint32_t arrays, uint32_t line_bytes, uint64_t *Rq) {
+                                  const unsigned char *active, uint32_t wbytes, uint32_t line_bytes, uint64_t *Rq) {
     for (uint64_t i = 0; i < npart; i++) {
-        uint64_t count = 0, last = UINT64_MAX;
-        for (uint64_t v = bounds[i]; v < bounds[i + 1]; v++) {
-            if (!active[v] || off[v + 1] == off[v]) continue;
-            for (uint64_t line = off[v] * 4 / line_bytes; line <= (off[v + 1] * 4 - 1) / line_bytes; line++)
-                if (line != last) {
-                    count++;
-                    last = line;
-                }
-        }
-        Rq[i] = (uint64_t)arrays * count;
+        Rq[i] = lines_distinct(bounds[i], bounds[i + 1], off, active, 4, line_bytes);
+        if (wbytes) Rq[i] += lines_distinct(bounds[i], bounds[i + 1], off, active, wbytes, line_bytes);
     }
 }
 

@@ -69,7 +69,7 @@ def autotune(graph, algo: str, source: int = 0, budget_frac: float | None = 0.25
         "gamma": (p.gamma_num, p.gamma_den),
         "filter_engine": "stream" if p.filter_engine == 0 else "copy",
     }
-    arrays = graph.edge_arrays(algo)  # SSSP reads one array when its weights are packed
+    ebytes = graph.edge_bytes(algo)  # SSSP: 4 when packed, 5 with byte weights, else 8
 
     def timed(g, a, s):
         # results into a pinned buffer: a pageable one adds the same staged copy to every
@@ -89,11 +89,11 @@ def autotune(graph, algo: str, source: int = 0, budget_frac: float | None = 0.25
     def cost(cfg):
         _apply(graph, cfg)
         if budget_frac is not None:
-            graph.set_budget(int(budget_frac * 4 * arrays * graph.m))
+            graph.set_budget(int(budget_frac * ebytes * graph.m))
         return run(graph, algo, source)
 
     best, t, trials = coordinate_descent(start, grid, cost, rounds=rounds)
     _apply(graph, best)
     if budget_frac is not None:
-        graph.set_budget(int(budget_frac * 4 * arrays * graph.m))
+        graph.set_budget(int(budget_frac * ebytes * graph.m))
     return {"best": best, "seconds": t, "trials": trials}

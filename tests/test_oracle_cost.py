@@ -5,6 +5,7 @@ The selection cases below were worked by hand from the equations; the numbers in
 comment are the hand computation, not the oracle's output.
 """
 import numpy as np
+import pytest
 from hypothesis import given, settings, strategies as st
 
 import gen
@@ -16,9 +17,11 @@ def off_from_degrees(deg):
     return np.concatenate([[0], np.cumsum(np.asarray(deg, dtype=np.uint64))]).astype(np.uint64)
 
 
-def lines_brute(start_edge, deg, line_bytes=128):
-    """Distinct `line_bytes` lines touched by 4-byte elements start_edge..start_edge+deg-1."""
-    return len({(4 * e) // line_bytes for e in range(start_edge, start_edge + deg)})
+def lines_brute(start_edge, deg, line_bytes=128, entry_bytes=4):
+    """Distinct `line_bytes` lines touched by entries start_edge..start_edge+deg-1 of an array
+    of `entry_bytes`-byte entries (every byte of each entry)."""
+    return len({(entry_bytes * e + b) // line_bytes for e in range(start_edge, start_edge + deg)
+                for b in range(entry_bytes)})
 
 
 # ------------------------------------------------------------- partition
@@ -62,6 +65,12 @@ def test_stats_match_brute_force_line_count(deg, target, data):
             assert nA[i] == len(vs)
             assert Ea[i] == sum(deg[v] for v in vs)
             assert Rq[i] == arrays * sum(lines_brute(int(off[v]), deg[v]) for v in vs)
+    # byte weights: the weight lists are deg[v] bytes at byte offset off[v]
+    _, _, Rq1 = oracle.partition_stats(b, off, active, arrays=2, weight_bytes=1)
+    for i in range(len(b) - 1):
+        vs = [v for v in range(int(b[i]), int(b[i + 1])) if active[v] and deg[v] > 0]
+        assert Rq1[i] == sum(lines_brute(int(off[v]), deg[v]) + lines_brute(int(off[v]), deg[v], entry_bytes=1)
+                             for v in vs)
 
 
 def test_fig4_toy_graph_request_counts():
@@ -81,12 +90,31 @@ def test_fig4_toy_graph_request_counts():
 
 
 # ---------------------------------------------------------------- select
-def one_partition(deg, active_mask, arrays=1):
+def one_partition(deg, active_mask, arrays=1, weight_bytes=None, distinct=False):
     off = off_from_degrees(deg)
     E = int(off[-1])
     b = np.array([0, len(deg)], dtype=np.uint64)
-    nA, Ea, Rq = oracle.partition_stats(b, off, np.asarray(active_mask, np.uint8), arrays=arrays)
+    nA, Ea, Rq = oracle.partition_stats(b, off, np.asarray(active_mask, np.uint8), arrays=arrays,
+                                        weight_bytes=weight_bytes, distinct=distinct)
     return [E], nA, Ea, Rq
+
+
+def test_requests_count_each_array_with_its_own_entry_size():
+    # Three active lists of 40, 8 and 100 edges at edge offsets 0, 40, 48, 128-byte lines.
+    # Neighbour array (4-byte entries): bytes [0,160) [160,192) [192,592) touch lines
+    # {0,1} {1} {1,2,3,4}: 2 + 1 + 4 = 7 transactions per list, 5 distinct lines.
+    # Byte weights: bytes [0,40) [40,48) [48,148) touch lines {0} {0} {0,1}: 1 + 1 + 2 = 4
+    # transactions, 2 distinct lines.  4-byte weights repeat the neighbour array's counts.
+    deg, act = [40, 8, 100], [1, 1, 1]
+    for distinct, col, wb1 in ((False, 7, 4), (True, 5, 2)):
+        assert one_partition(deg, act, distinct=distinct)[3][0] == col
+        assert one_partition(deg, act, arrays=2, distinct=distinct)[3][0] == 2 * col
+        assert one_partition(deg, act, arrays=2, weight_bytes=4, distinct=distinct)[3][0] == 2 * col
+        assert one_partition(deg, act, arrays=2, weight_bytes=1, distinct=distinct)[3][0] == col + wb1
+    with pytest.raises(ValueError):
+        one_partition(deg, act, arrays=1, weight_bytes=1)
+    with pytest.raises(ValueError):
+        one_partition(deg, act, arrays=2, weight_bytes=2)
 
 
 def test_select_w1_fully_active_goes_filter():
@@ -157,15 +185,15 @@ def test_select_two_edge_arrays():
 
 
 def test_select_byte_weights():
-    # SSSP with weights stored as bytes reads d1 = 5 bytes per edge; its zero-copy requests
-    # still count a line of each array per list (a 2-byte weight run costs a line request).
+    # SSSP with weights stored as bytes reads d1 = 5 bytes per edge; Eq. 3's per-list requests
+    # still count one transaction of each array per list (a 2-byte weight run costs one).
     # 16384 vertices of degree 2 (E = 32768), half of them active (Ea = 16384, nA = 8192),
-    # 8-byte lists aligned within lines -> Rq = 2 * 8192 = 16384 -> ceil(/256) = 64,
+    # 8-byte and 2-byte lists aligned within lines -> Rq = 2 * 8192 = 16384 -> ceil(/256) = 64,
     # RTTzc = 5/8 + 3/8 * 1/2 = 13/16, Tiz = 52.
     #   d1 = 8: Tef = 8, Tec = ceil((131072 + 32768)/32768) = 5 < 6.4 and < 20.8 -> compaction.
     #   d1 = 5: Tef = 5, Tec = ceil((81920 + 32768)/32768) = 4, not < alpha*Tef = 4; Tiz = 52
     #           is not < 5 either -> filter.  The index term weighs more against fewer bytes.
-    E, nA, Ea, Rq = one_partition([2] * 16384, [1] * 8192 + [0] * 8192, arrays=2)
+    E, nA, Ea, Rq = one_partition([2] * 16384, [1] * 8192 + [0] * 8192, arrays=2, weight_bytes=1)
     assert (int(E[0]), int(nA[0]), int(Ea[0]), int(Rq[0])) == (32768, 8192, 16384, 16384)
     assert oracle.select(E, nA, Ea, Rq, params=CostParams(d1=8))[0] == COMPACT
     assert oracle.select(E, nA, Ea, Rq, params=CostParams(d1=5))[0] == FILTER
@@ -269,6 +297,14 @@ def test_distinct_lines_match_a_set_of_touched_lines(deg, target, data):
                     lines.update(range(int(off[v]) * 4 // 128, (int(off[v + 1]) * 4 - 1) // 128 + 1))
             assert rq[i] == arrays * len(lines)
             assert rq[i] <= rq_pv[i]  # never more than one request per vertex line
+    _, _, rq1 = oracle.partition_stats(bounds, off, active, arrays=2, weight_bytes=1, distinct=True)
+    for i in range(len(bounds) - 1):
+        lines, wlines = set(), set()
+        for v in range(int(bounds[i]), int(bounds[i + 1])):
+            if active[v] and deg[v]:
+                lines.update(range(int(off[v]) * 4 // 128, (int(off[v + 1]) * 4 - 1) // 128 + 1))
+                wlines.update(range(int(off[v]) // 128, (int(off[v + 1]) - 1) // 128 + 1))
+        assert rq1[i] == len(lines) + len(wlines)
 
 
 def test_select_tie_rule_parameter():
