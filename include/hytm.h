@@ -145,7 +145,9 @@ typedef struct {
     uint32_t rq_distinct_lines; /* 0: Rq of Eq. 3 counts each active list's lines (its footnote's
                                    per-vertex requests).  1: Rq counts the different m-byte lines the
                                    active lists of a partition touch -- what the zero-copy kernel
-                                   reads, since it loads a line two consecutive lists share once. */
+                                   reads, since it loads a line two consecutive lists share once.
+                                   Either way each edge array read counts its own lines: with byte
+                                   weights a list of D edges spans D bytes of the weight array. */
     uint32_t zc_tie;            /* 0: a Tiz = Tef tie selects filter, as the paper's prose says.  1: it
                                    selects zero-copy -- for hosts where full-line zero-copy reads run
                                    at the copy engine's rate (hytm_link_probe), so equal bytes cost
@@ -220,7 +222,8 @@ typedef struct {
     uint64_t bytes_compact;     /* H2D bytes of compaction copies */
     uint64_t zc_lines;          /* 128-byte line requests of the zero-copy kernel (one per line of each
                                    active vertex's list), per edge array: Rq of Eq. 3 at m = 128 */
-    uint64_t bytes_zerocopy;    /* zc_lines_distinct x 128 B x edge arrays: lines moved over the link */
+    uint64_t bytes_zerocopy;    /* zc_lines_distinct x 32 edges x d1 bytes per edge: what the zero-copy
+                                   kernel moves over the link */
     uint64_t bytes_d2h;         /* device-to-host bytes of selections and active lists */
     uint64_t bytes_resident_fill; /* H2D bytes copied into the resident cache this run */
     uint64_t filter_tasks;

@@ -51,7 +51,7 @@ struct SelParams {
     uint32_t bn, bd;      // beta  = bn / bd
     uint32_t gn, gd;      // gamma = gn / gd
     uint32_t cost_shift;  // log2(m / 4): elements per m-byte request line
-    uint32_t arrays;      // edge arrays read per edge (1 or 2)
+    uint32_t wbytes;      // bytes per entry of the weight array read beside the neighbours (0: none, 1 or 4)
     uint32_t force;       // 0: cost model; else the engine code for every scheduled partition
     uint32_t nres;        // partitions [0, nres) are resident
     uint32_t allow_filter, allow_compact; // engines whose staging fits the budget

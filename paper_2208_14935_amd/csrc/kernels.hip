@@ -158,15 +158,31 @@ __device__ __forceinline__ uint32_t round_vertex(uint32_t k, uint32_t incl, uint
     return ((q0 + j) << 6) + select_bit(bj, k - before);
 }
 
+// Running sums of a partition's statistics in one lane: active lists, their edges, request
+// lines per list and distinct (Eq. 3), kernel lines; with a byte weight array its request
+// lines are counted apart (a list of D edges spans D bytes there).  carry / carry_w: (line + 1)
+// of the latest list's last line in each array, 0 = none.
+struct SelAcc {
+    uint64_t c = 0, ea = 0, rq = 0, kl = 0, rqd = 0, carry = 0;
+    uint64_t rqw = 0, rqdw = 0, carry_w = 0;
+};
+
+// The lines of a list [s, e) in an array whose lines hold 2^sh entries: (first + 1, last + 1).
+__device__ __forceinline__ void list_lines(uint64_t s, uint64_t e, uint32_t sh, uint64_t& fl, uint64_t& ll) {
+    fl = (s >> sh) + 1;
+    ll = ((e - 1) >> sh) + 1;
+}
+
 // Batches [b0, b0 + 64 G) of a round's active vertices: every lane loads (a lane past the
 // round's end the round's last vertex), so the loads of all G batches are issued before the
-// first is used.  Adds the vertices' counts; carry is the (line + 1) of the latest list.
+// first is used.
 template <int G>
 __device__ __forceinline__ void stats_batches(uint32_t b0, uint32_t T, uint32_t incl, uint32_t cnt, uint64_t wbits,
-                                              uint32_t q0, const uint64_t* __restrict__ off, uint32_t sh,
-                                              uint64_t& c, uint64_t& ea, uint64_t& rq, uint64_t& kl, uint64_t& rqd,
-                                              uint64_t& carry) {
+                                              uint32_t q0, const uint64_t* __restrict__ off, const SelParams& sp,
+                                              SelAcc& a) {
     const uint32_t lane = threadIdx.x & 63;
+    const uint32_t sh = sp.cost_shift, shw = sp.cost_shift + 2;  // byte weights: 4x the entries per line
+    const bool bytew = sp.wbytes == 1;
     uint64_t s[G], e[G];
 #pragma unroll
     for (int g = 0; g < G; g++) {
@@ -179,21 +195,30 @@ __device__ __forceinline__ void stats_batches(uint32_t b0, uint32_t T, uint32_t 
     for (int g = 0; g < G; g++) {
         if (b0 + 64 * g >= T) break;
         const bool has = b0 + 64 * g + lane < T && e[g] > s[g];
-        uint64_t fl = 0, ll = 0;
+        uint64_t fl = 0, ll = 0, flw = 0, llw = 0;
         if (has) {
-            c += 1;
-            ea += e[g] - s[g];
-            rq += lines_of(s[g], e[g], sh);
-            kl += lines_of(s[g], e[g], ZC_LINE_SHIFT);
-            fl = (s[g] >> sh) + 1;
-            ll = ((e[g] - 1) >> sh) + 1;
+            a.c += 1;
+            a.ea += e[g] - s[g];
+            a.rq += lines_of(s[g], e[g], sh);
+            a.kl += lines_of(s[g], e[g], ZC_LINE_SHIFT);
+            list_lines(s[g], e[g], sh, fl, ll);
+            if (bytew) {
+                a.rqw += lines_of(s[g], e[g], shw);
+                list_lines(s[g], e[g], shw, flw, llw);
+            }
         }
         // the last line of the latest earlier list (lists are in vertex order)
         uint64_t tot;
         const uint64_t ex = wave_exclusive_max(ll, &tot);
-        const uint64_t prev = carry > ex ? carry : ex;
-        if (has) rqd += ll - fl + 1 - (prev == fl ? 1 : 0);
-        carry = carry > tot ? carry : tot;
+        const uint64_t prev = a.carry > ex ? a.carry : ex;
+        if (has) a.rqd += ll - fl + 1 - (prev == fl ? 1 : 0);
+        a.carry = a.carry > tot ? a.carry : tot;
+        if (bytew) {  // uniform
+            const uint64_t exw = wave_exclusive_max(llw, &tot);
+            const uint64_t prevw = a.carry_w > exw ? a.carry_w : exw;
+            if (has) a.rqdw += llw - flw + 1 - (prevw == flw ? 1 : 0);
+            a.carry_w = a.carry_w > tot ? a.carry_w : tot;
+        }
     }
 }
 
@@ -205,12 +230,11 @@ __global__ __launch_bounds__(256) void k_stats_select(uint32_t npart, const uint
                                                       uint64_t* __restrict__ Rq, uint64_t* __restrict__ K) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wpb = blockDim.x >> 6, waves = gridDim.x * wpb;
-    const uint32_t sh = sp.cost_shift;
     for (uint32_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < npart; i += waves) {
         const uint32_t vb = pv[i], ve = pv[i + 1];
         const uint32_t qb = vb >> 6, qe = (ve + 63) >> 6;
-        uint64_t c = 0, f = 0, ea = 0, rq = 0, kl = 0, rqd = 0;
-        uint64_t carry = 0;  // (line + 1) of the last list so far, 0 = none
+        SelAcc a;
+        uint64_t f = 0;
         for (uint32_t q0 = qb; q0 < qe; q0 += 64) {  // uniform across the wave
             const uint64_t wbits = q0 + lane < qe ? window_bits(cur, q0 + lane, vb, ve) : 0ull;
             if (!__ballot(wbits != 0)) continue;
@@ -220,16 +244,21 @@ __global__ __launch_bounds__(256) void k_stats_select(uint32_t npart, const uint
             f += cnt;
             // a round of at most 64 active vertices takes one batch, larger ones SEL_B at a time
             if (T <= 64)
-                stats_batches<1>(0, T, incl, cnt, wbits, q0, off, sh, c, ea, rq, kl, rqd, carry);
+                stats_batches<1>(0, T, incl, cnt, wbits, q0, off, sp, a);
             else
                 for (uint32_t b0 = 0; b0 < T; b0 += 64 * SEL_B)
-                    stats_batches<SEL_B>(b0, T, incl, cnt, wbits, q0, off, sh, c, ea, rq, kl, rqd, carry);
+                    stats_batches<SEL_B>(b0, T, incl, cnt, wbits, q0, off, sp, a);
         }
-        c = wave_sum(c);
+        const uint64_t c = wave_sum(a.c);
         f = wave_sum(f);
-        ea = wave_sum(ea);
-        rq = wave_sum(sp.rq_distinct ? rqd : rq) * sp.arrays;
-        kl = wave_sum(kl);
+        const uint64_t ea = wave_sum(a.ea);
+        // request lines: the neighbour array, and the weight array beside it (Eq. 3)
+        uint64_t rq = wave_sum(sp.rq_distinct ? a.rqd : a.rq);
+        if (sp.wbytes == 1)
+            rq += wave_sum(sp.rq_distinct ? a.rqdw : a.rqw);
+        else if (sp.wbytes)
+            rq *= 2;  // 4-byte weights: the neighbour array's lines again
+        const uint64_t kl = wave_sum(a.kl);
         if (lane == 0) {
             uint8_t p;
             if (ea == 0)

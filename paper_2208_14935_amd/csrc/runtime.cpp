@@ -388,7 +388,7 @@ SelParams make_sel(const hytm_graph* g, uint32_t arrays) {
     uint32_t sh = 0;
     while ((4u << sh) < p.line_bytes) sh++;
     sp.cost_shift = sh;
-    sp.arrays = arrays;
+    sp.wbytes = arrays == 2 ? g->pk.wbytes : 0u;
     sp.force = p.mode == HYTM_MODE_FILTER ? P_FILTER
                : p.mode == HYTM_MODE_COMPACT ? P_COMPACT
                : p.mode == HYTM_MODE_ZEROCOPY ? P_ZC
@@ -1896,7 +1896,7 @@ hytm_status run_impl(hytm_graph* g, hytm_algo algo, const uint32_t* sources, uin
         HIP_CHECK(hipMemcpy(&zcd, g->d_zcl.p, sizeof(zcd), hipMemcpyDeviceToHost));
         stats->zc_lines = tt.zcl;
         stats->zc_lines_distinct = zcd;
-        stats->bytes_zerocopy = zcd * 32 * edge_bytes(g, arrays);  // a line of each array per zero-copy line
+        stats->bytes_zerocopy = zcd * 32 * edge_bytes(g, arrays);  // 32 edges of d1 bytes per zero-copy line
         stats->bytes_d2h = tt.d2h;
         stats->bytes_resident_fill = tt.fill_bytes;
         stats->filter_tasks = tt.ftasks;

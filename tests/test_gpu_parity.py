@@ -192,6 +192,41 @@ def test_bfs_engine_trace_matches_oracle_selection(rmat16, pe, distinct, gamma, 
         np.testing.assert_array_equal(res.mode_trace[t], want, err_msg=f"iteration {t}")
 
 
+@pytest.mark.parametrize("narrow,distinct", [(True, False), (True, True), (False, False), (False, True)])
+def test_sssp_engine_trace_counts_the_weight_array(rmat16, narrow, distinct):
+    """SSSP's first two frontiers are unique (the source, then its out-neighbours), so the
+    engine vectors of iterations 0 and 1 are pinned on a graph with weights in their own
+    array: Rq counts that array's lines at its entry size (bytes, or 4-byte words) beside the
+    neighbour array's, and d1 = 5 or 8."""
+    note(f"rmat16 sssp engine trace byte weights={narrow} distinct={distinct}")
+    off, col, w = rmat16.off, rmat16.col, rmat16.w
+    with hy.Graph(off, col, weights=w, pack=False, narrow=narrow) as g:
+        wb = g.info()["weight_bytes"]
+        assert wb == (1 if narrow else 4)
+        g.set_params(partition_edges=4096, rq_distinct_lines=int(distinct), gamma=(5, 8), zc_tie=0)
+        g.set_resident_fraction("sssp", 0.25)
+        res = g.run("sssp", 0, trace=True, stats=True)
+        bounds = g.partition_bounds()
+        nres = res.stats["nres"]
+    np.testing.assert_array_equal(res.values, rmat16.want("sssp", 0)[0])
+    E = np.diff(off[bounds.astype(np.int64)])
+    f0 = np.zeros(len(off) - 1, bool)
+    f0[0] = True
+    f1 = np.zeros(len(off) - 1, bool)
+    f1[col[off[0]:off[1]]] = True
+    f1[0] = False
+    params = oracle.CostParams(gamma=(5, 8), d1=4 + wb, zc_tie=0)
+    differs = 0
+    for t, act in enumerate((f0, f1)):
+        nA, Ea, Rq = oracle.partition_stats(bounds, off, act, arrays=2, weight_bytes=wb, distinct=distinct)
+        want = oracle.select(E, nA, Ea, Rq, nres=nres, params=params)
+        np.testing.assert_array_equal(res.mode_trace[t], want, err_msg=f"iteration {t}")
+        _, _, Rq4 = oracle.partition_stats(bounds, off, act, arrays=2, weight_bytes=4, distinct=distinct)
+        differs += int((oracle.select(E, nA, Ea, Rq4, nres=nres, params=params) != want).sum())
+    if narrow and not distinct:
+        assert differs > 0  # counting the byte array as words would choose otherwise here
+
+
 @pytest.mark.parametrize("blocking,tie", [(0, 2), (2, 2), (0, 0), (2, 1)])
 def test_pagerank_engine_trace_follows_the_tie_rule(rmat16, blocking, tie):
     """PageRank's partitions are all active, so with 4096-edge partitions (16 KB, one
