@@ -45,8 +45,8 @@ HBM_PEAK_GBPS = 8000.0
 # workload it was measured on; otherwise the roofline reports traffic null.
 PMC_TRAFFIC = {"kernel": "k_push_fstream<OpPr>",
                "workload": "rmat28-ef16-budget8GB-hybrid-src1perstep-w8-rqdistinct-autotie",
-               "kernels_sha256": "1ff92191cd39d136f3a3c14d5a16c0c5f866da77d12f54ef2b6a44fda8ccd136",
-               "bytes_per_launch": (2.0 * 14204371.68125 + 1.0 * 70101049.3125) * 1024.0,
+               "kernels_sha256": "7fc92fe00bd43dd6d387b06d39c1643cbf3bec19e808d55180efbbe71fa48e7e",
+               "bytes_per_launch": (2.0 * 14162316.25625 + 1.0 * 70101049.3125) * 1024.0,
                "summary": "profiles/pmc_traffic_rmat28_budget8GB_hybrid.md"}
 PCIE_GEN5_X16_GBPS = 63.0
 # hipHostMalloc fails past ~64 GiB per process on the MI355X hosts measured (295 GiB of RAM);
