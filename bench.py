@@ -161,7 +161,7 @@ def main():
     if args.graph == "er":
         off, col = gen.er(args.er_vertices, int(args.er_vertices * args.er_degree), seed=7)
     else:
-        off, col = gen.rmat(args.scale, args.edge_factor, seed=args.scale)
+        off, col = gen.rmat_cached(args.scale, args.edge_factor, seed=args.scale)  # HYTM_GRAPH_CACHE: reuse
     n, m = len(off) - 1, len(col)
     log(f"generated n={n} m={m} in {time.time() - t0:.1f}s")
     w = gen.weights(off, col, 1000 + args.scale)

@@ -9,6 +9,7 @@ gcc into ``libhytmgen.so`` next to it.
 from __future__ import annotations
 
 import ctypes
+import hashlib
 import os
 import subprocess
 
@@ -158,3 +159,73 @@ def sources(off: np.ndarray, k: int, seed: int) -> np.ndarray:
     out = np.empty(max(int(k), 1), dtype=np.uint32)
     got = _load().gen_sources(len(off) - 1, _ptr(off), int(k), int(seed), _ptr(out))
     return out[:got]
+
+
+# ------------------------------------------------------------------ CSR cache
+_CSR_MAGIC = b"HYTMCSR1"
+
+
+def save_csr(path: str, off: np.ndarray, col: np.ndarray) -> None:
+    """Write a CSR (uint64 offsets, uint32 neighbours) to `path` in a raw binary layout:
+    8-byte magic, n and m as little-endian uint64, then off[0..n] and col[0..m).  The file
+    is written under a temporary name and renamed, so a reader never sees half of it."""
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    col = np.ascontiguousarray(col, dtype=np.uint32)
+    n, m = len(off) - 1, len(col)
+    if n < 0 or int(off[-1]) != m:
+        raise ValueError("off[-1] must equal len(col)")
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "wb") as fh:
+        fh.write(_CSR_MAGIC)
+        fh.write(np.array([n, m], dtype="<u8").tobytes())
+        off.tofile(fh)
+        col.tofile(fh)
+    os.replace(tmp, path)
+
+
+def load_csr(path: str, mmap: bool = False):
+    """(off, col) from a file written by save_csr; with mmap the arrays map the file
+    read-only instead of being read into memory."""
+    with open(path, "rb") as fh:
+        head = fh.read(24)
+    if len(head) != 24 or head[:8] != _CSR_MAGIC:
+        raise ValueError(f"{path}: not a CSR cache file")
+    n, m = (int(x) for x in np.frombuffer(head[8:], dtype="<u8"))
+    if os.path.getsize(path) != 24 + 8 * (n + 1) + 4 * m:
+        raise ValueError(f"{path}: truncated CSR cache file")
+    if mmap:
+        off = np.memmap(path, dtype=np.uint64, mode="r", offset=24, shape=(n + 1,))
+        col = np.memmap(path, dtype=np.uint32, mode="r", offset=24 + 8 * (n + 1), shape=(m,))
+    else:
+        with open(path, "rb") as fh:
+            fh.seek(24)
+            off = np.fromfile(fh, dtype=np.uint64, count=n + 1)
+            col = np.fromfile(fh, dtype=np.uint32, count=m)
+    if len(off) != n + 1 or len(col) != m or int(off[-1]) != m:
+        raise ValueError(f"{path}: inconsistent CSR cache file")
+    return off, col
+
+
+def source_tag() -> str:
+    """A short hash of the generator's source: cache keys include it, so a changed generator
+    never reuses a graph (or anything computed from one) made by an older version."""
+    h = hashlib.sha256()
+    for f in (_SRC, os.path.abspath(__file__)):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def rmat_cached(scale: int, edge_factor: float = 16, seed: int = 0, cache_dir: str | None = None):
+    """rmat(scale, edge_factor, seed), read from (or written to) `cache_dir` when one is
+    given (default: the HYTM_GRAPH_CACHE environment variable; none = no cache)."""
+    cache_dir = cache_dir if cache_dir is not None else os.environ.get("HYTM_GRAPH_CACHE")
+    if not cache_dir:
+        return rmat(scale, edge_factor, seed)
+    path = os.path.join(cache_dir, f"rmat{scale}-ef{edge_factor:g}-s{seed}-{source_tag()}.csr")
+    if os.path.exists(path):
+        return load_csr(path)
+    off, col = rmat(scale, edge_factor, seed)
+    os.makedirs(cache_dir, exist_ok=True)
+    save_csr(path, off, col)
+    return off, col

@@ -18,6 +18,7 @@ import pytest
 
 import gen
 import oracle
+import oracle_cache
 import paper_2208_14935_amd as hy
 
 pytestmark = pytest.mark.gpu
@@ -31,7 +32,7 @@ def note(*a):
 @pytest.fixture(scope="module")
 def big():
     gen.set_threads(min(16, os.cpu_count() or 1))
-    off, col = gen.rmat(SCALE, 16, seed=SCALE)
+    off, col = gen.rmat_cached(SCALE, 16, seed=SCALE)
     w = gen.weights(off, col, 1000 + SCALE)
     srcs = gen.sources(off, 8, 2000 + SCALE)
     g = hy.Graph(off, col, weights=w, check_col=False)
@@ -48,8 +49,10 @@ _want = {}
 
 
 def cached(key, fn):
+    """The oracle's answer for key, computed once per process (and kept on disk across
+    processes when HYTM_ORACLE_CACHE names a directory)."""
     if key not in _want:
-        _want[key] = fn()
+        _want[key] = oracle_cache.cached(f"rmat{SCALE}-" + "-".join(str(k) for k in key), fn)
     return _want[key]
 
 
