@@ -190,6 +190,10 @@ def test_bfs_engine_trace_matches_oracle_selection(rmat16, pe, distinct, gamma, 
         # the automatic tie rule (2) gives ties to filter outside unblocked PageRank
         want = oracle.select(E, nA, Ea, Rq, nres=nres, params=oracle.CostParams(gamma=gamma, zc_tie=tie % 2))
         np.testing.assert_array_equal(res.mode_trace[t], want, err_msg=f"iteration {t}")
+        # the filter partitions go out as Algorithm 1's tasks of at most k = 4 adjacent ones,
+        # each moving its partitions' whole edge ranges
+        assert res.iters[t]["filter_tasks"] == len(oracle.combine(want, E, k=4)), f"iteration {t}"
+        assert res.iters[t]["bytes_filter"] == 4 * int(E[want == oracle.FILTER].sum()), f"iteration {t}"
 
 
 @pytest.mark.parametrize("narrow,distinct", [(True, False), (True, True), (False, False), (False, True)])
