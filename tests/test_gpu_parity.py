@@ -172,7 +172,7 @@ def test_hybrid_uses_several_engines_and_moves_fewer_bytes_than_filter(rmat16):
 def test_bfs_engine_trace_matches_oracle_selection(rmat16, pe, distinct, gamma, tie):
     """BFS frontiers are unique (level t), so the per-iteration engine vector is pinned --
     with Eq. 3's per-vertex requests or with distinct lines (partitions of 2^18 edges span
-    more than one 256-word pass of the statistics kernel)."""
+    more than one 4,096-vertex round of the statistics kernel)."""
     note(f"rmat16 bfs engine trace pe={pe} distinct={distinct}")
     lvl, it = rmat16.want("bfs", 0)
     with rmat16.graph("bfs") as g:
