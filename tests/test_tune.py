@@ -24,6 +24,39 @@ def test_coordinate_descent_keeps_start_when_it_is_best():
     assert best == {"a": 2} and c == 0 and len(trials) == 3
 
 
+def test_autotune_budgets_by_the_algorithms_bytes_per_edge():
+    # budget_frac is a share of the bytes per edge the algorithm reads (SSSP with byte
+    # weights: 5), not of 4 bytes per edge array
+    from types import SimpleNamespace
+    from paper_2208_14935_amd.tune import autotune
+
+    class FakeGraph:
+        m = 1000
+
+        def __init__(self):
+            self.budgets, self.applied = [], []
+
+        def params(self):
+            return SimpleNamespace(partition_edges=32768, combine_k=4, alpha_num=4, alpha_den=5, beta_num=2,
+                                   beta_den=5, gamma_num=5, gamma_den=8, filter_engine=0)
+
+        def edge_bytes(self, algo):
+            return 5 if algo == "sssp" else 4
+
+        def set_params(self, **kw):
+            self.applied.append(kw)
+
+        def set_budget(self, b):
+            self.budgets.append(b)
+
+    for algo, per_edge in (("sssp", 5), ("bfs", 4)):
+        g = FakeGraph()
+        res = autotune(g, algo, 0, budget_frac=0.25, grid={"combine_k": [1, 4]}, rounds=1,
+                       runner=lambda gg, a, s: 1.0 + gg.applied[-1]["combine_k"] / 100)
+        assert set(g.budgets) == {int(0.25 * per_edge * g.m)}
+        assert res["best"]["combine_k"] == 1
+
+
 @pytest.mark.gpu
 def test_autotune_on_rmat16_keeps_results_exact():
     import paper_2208_14935_amd as hy
